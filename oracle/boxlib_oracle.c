@@ -1,0 +1,346 @@
+/*
+ * Plain FP64 CPU oracle for the single-level BoxLib hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY: this file is compiled into liboracle.so and is
+ * called by the tests, by the package smoke check and by the CPU-baseline leg
+ * of the benchmark.  The product library never links, loads or calls it.
+ *
+ * Every routine is written as the plain definition of what it computes, with
+ * no tiling, blocking, vectorisation or reordering, in the operand order that
+ * the comments state.  Build with -O2 -ffp-contract=off (no FMA contraction)
+ * so the rounding of every cell update is exactly the one written here.
+ *
+ * Data model (the oracle's own, independent of the product library):
+ *   - a Box is six ints {lo[3], hi[3]}, inclusive cell indices (paper, Sec. 3.1:
+ *     a three-dimensional Box is represented by six integers);
+ *   - a FAB (FArrayBox) holds ncomp components on its box grown by ng ghost
+ *     cells, stored as one contiguous array, x fastest, then y, z, then the
+ *     component (paper, Sec. 3.1: multi-component data in one contiguous 1-D
+ *     array reshaped as a Fortran array);
+ *   - a MultiFab is nbox FABs of one level; here all FABs live in one double
+ *     array and fab_off[b] is the element offset of FAB b.
+ *
+ * Routines:
+ *   orc_fill_boundary  FillBoundary with periodic wrap (Sec. 3.1, Sec. 3.3,
+ *                      Sec. 4.1): every ghost cell takes the valid value at its
+ *                      periodically wrapped index if some box covers it.
+ *   orc_heat_step      forward-Euler step of the heat equation with
+ *                      second-order centred differences (Sec. 4.1), written as
+ *                      the 7-point update.
+ *   orc_heat_flux_step the same step in the paper's own form (Sec. 4.1): three
+ *                      face-flux loops, then a divergence loop.
+ *   orc_gsrb_color     one colour of a red-black Gauss-Seidel sweep for the
+ *                      7-point discrete Poisson problem -L_h phi = f.
+ *   orc_residual       r = f + L_h phi per valid cell (FP64).
+ *   orc_heat_window    n heat steps on a cube window of a fully periodic global
+ *                      array, returning the centre value (used to check single
+ *                      outputs of very large runs one by one).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the box loops may use (OpenMP over boxes only: each box is updated
+ * by one thread in the plain order, so results do not depend on the count). */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+typedef struct {
+  int nx, ny, nz;      /* grown extents */
+  int glo[3];          /* grown lower corner (global index) */
+} fab_geom;
+
+static fab_geom geom_of(const int* box, int ng) {
+  fab_geom g;
+  g.glo[0] = box[0] - ng;
+  g.glo[1] = box[1] - ng;
+  g.glo[2] = box[2] - ng;
+  g.nx = box[3] - box[0] + 1 + 2 * ng;
+  g.ny = box[4] - box[1] + 1 + 2 * ng;
+  g.nz = box[5] - box[2] + 1 + 2 * ng;
+  return g;
+}
+
+/* element index of global cell (i,j,k), component comp, inside a FAB */
+static int64_t fab_index(const fab_geom* g, int comp, int i, int j, int k) {
+  int64_t li = i - g->glo[0], lj = j - g->glo[1], lk = k - g->glo[2];
+  return (((int64_t)comp * g->nz + lk) * g->ny + lj) * g->nx + li;
+}
+
+static int floor_mod(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+/*
+ * Owner map of the level: owner[(k*N1 + j)*N0 + i] = index of the box whose
+ * valid region holds domain cell (i,j,k), or -1.  Returns -1 if two boxes
+ * overlap or a box leaves the domain (the grids of a level are
+ * non-intersecting, Sec. 3).
+ */
+int orc_owner_map(int nbox, const int* boxes, const int* domain, int32_t* owner) {
+  int N0 = domain[3] - domain[0] + 1, N1 = domain[4] - domain[1] + 1, N2 = domain[5] - domain[2] + 1;
+  int64_t ncell = (int64_t)N0 * N1 * N2;
+  for (int64_t q = 0; q < ncell; ++q) owner[q] = -1;
+  for (int b = 0; b < nbox; ++b) {
+    const int* bx = boxes + 6 * b;
+    for (int d = 0; d < 3; ++d)
+      if (bx[d] < domain[d] || bx[3 + d] > domain[3 + d] || bx[d] > bx[3 + d]) return -1;
+    for (int k = bx[2]; k <= bx[5]; ++k)
+      for (int j = bx[1]; j <= bx[4]; ++j)
+        for (int i = bx[0]; i <= bx[3]; ++i) {
+          int64_t q = ((int64_t)(k - domain[2]) * N1 + (j - domain[1])) * N0 + (i - domain[0]);
+          if (owner[q] >= 0) return -1;
+          owner[q] = b;
+        }
+  }
+  return 0;
+}
+
+/*
+ * FillBoundary(mf, scomp, ncomp).  Plain definition: assemble the global array
+ * G of one component from all valid regions; then every ghost cell p of every
+ * FAB takes G(p') where p' is p wrapped modulo the domain extent along each
+ * periodic axis, provided p' lies inside the domain and inside some box.  Ghost
+ * cells that no box covers (outside a non-periodic domain, or in a hole of a
+ * non-covering box list) are left untouched.
+ *   G      : scratch, one domain-sized double array
+ *   owner  : the owner map from orc_owner_map
+ */
+void orc_fill_boundary(int nbox, const int* boxes, const int* domain, const int* periodic,
+                       int ng, int scomp, int ncomp, double* data, const int64_t* fab_off,
+                       double* G, const int32_t* owner) {
+  int N[3], lo[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = domain[d];
+    N[d] = domain[3 + d] - domain[d] + 1;
+  }
+  for (int comp = scomp; comp < scomp + ncomp; ++comp) {
+    /* gather the valid regions into G */
+#pragma omp parallel for schedule(dynamic)
+    for (int b = 0; b < nbox; ++b) {
+      const int* bx = boxes + 6 * b;
+      fab_geom g = geom_of(bx, ng);
+      const double* fab = data + fab_off[b];
+      for (int k = bx[2]; k <= bx[5]; ++k)
+        for (int j = bx[1]; j <= bx[4]; ++j)
+          for (int i = bx[0]; i <= bx[3]; ++i) {
+            int64_t q = ((int64_t)(k - lo[2]) * N[1] + (j - lo[1])) * N[0] + (i - lo[0]);
+            G[q] = fab[fab_index(&g, comp, i, j, k)];
+          }
+    }
+    /* every ghost cell of every FAB */
+#pragma omp parallel for schedule(dynamic)
+    for (int b = 0; b < nbox; ++b) {
+      const int* bx = boxes + 6 * b;
+      fab_geom g = geom_of(bx, ng);
+      double* fab = data + fab_off[b];
+      for (int k = bx[2] - ng; k <= bx[5] + ng; ++k)
+        for (int j = bx[1] - ng; j <= bx[4] + ng; ++j)
+          for (int i = bx[0] - ng; i <= bx[3] + ng; ++i) {
+            int inside = i >= bx[0] && i <= bx[3] && j >= bx[1] && j <= bx[4] && k >= bx[2] && k <= bx[5];
+            if (inside) continue;
+            int p[3] = {i, j, k};
+            int ok = 1;
+            for (int d = 0; d < 3; ++d) {
+              if (periodic[d]) p[d] = lo[d] + floor_mod(p[d] - lo[d], N[d]);
+              if (p[d] < lo[d] || p[d] >= lo[d] + N[d]) ok = 0;
+            }
+            if (!ok) continue;
+            int64_t q = ((int64_t)(p[2] - lo[2]) * N[1] + (p[1] - lo[1])) * N[0] + (p[0] - lo[0]);
+            if (owner[q] < 0) continue;
+            fab[fab_index(&g, comp, i, j, k)] = G[q];
+          }
+    }
+  }
+}
+
+/*
+ * One forward-Euler heat step on the valid cells of every FAB (Sec. 4.1),
+ * reading u_old (whose ghosts must have been filled) and writing u_new:
+ *   s     = ((u[i-1] + u[i+1]) + (u[j-1] + u[j+1])) + (u[k-1] + u[k+1])
+ *   u_new = u + c * (s - 6 u),   c = dt / dx^2
+ * Ghost cells of u_new are not written.
+ */
+void orc_heat_step(int nbox, const int* boxes, int ng, int ncomp, const double* uold,
+                   double* unew, const int64_t* fab_off, double c) {
+#pragma omp parallel for schedule(dynamic)
+  for (int b = 0; b < nbox; ++b) {
+    const int* bx = boxes + 6 * b;
+    fab_geom g = geom_of(bx, ng);
+    const double* u = uold + fab_off[b];
+    double* v = unew + fab_off[b];
+    for (int comp = 0; comp < ncomp; ++comp)
+      for (int k = bx[2]; k <= bx[5]; ++k)
+        for (int j = bx[1]; j <= bx[4]; ++j)
+          for (int i = bx[0]; i <= bx[3]; ++i) {
+            double uc = u[fab_index(&g, comp, i, j, k)];
+            double sx = u[fab_index(&g, comp, i - 1, j, k)] + u[fab_index(&g, comp, i + 1, j, k)];
+            double sy = u[fab_index(&g, comp, i, j - 1, k)] + u[fab_index(&g, comp, i, j + 1, k)];
+            double sz = u[fab_index(&g, comp, i, j, k - 1)] + u[fab_index(&g, comp, i, j, k + 1)];
+            double s = (sx + sy) + sz;
+            v[fab_index(&g, comp, i, j, k)] = uc + c * (s - 6.0 * uc);
+          }
+  }
+}
+
+/*
+ * The same heat step in the paper's own structure (Sec. 4.1): the flux of each
+ * direction is computed on the faces of the box in its own loop,
+ *   F^x(i-1/2) = (u[i] - u[i-1]) / dx   (likewise for y and z),
+ * and a fourth loop forms the divergence and updates
+ *   u_new = u + dt * ( (F^x(i+1/2) - F^x(i-1/2)) / dx + (y) + (z) ).
+ * Algebraically identical to orc_heat_step with c = dt/dx^2; rounding differs.
+ * Returns -1 if the flux scratch cannot be allocated.
+ */
+int orc_heat_flux_step(int nbox, const int* boxes, int ng, int ncomp, const double* uold,
+                       double* unew, const int64_t* fab_off, double dt, double dx) {
+  for (int b = 0; b < nbox; ++b) {
+    const int* bx = boxes + 6 * b;
+    fab_geom g = geom_of(bx, ng);
+    int ex = bx[3] - bx[0] + 1, ey = bx[4] - bx[1] + 1, ez = bx[5] - bx[2] + 1;
+    /* face-centred flux arrays: nodal in their own direction */
+    double* fx = (double*)malloc(sizeof(double) * (size_t)(ex + 1) * ey * ez);
+    double* fy = (double*)malloc(sizeof(double) * (size_t)ex * (ey + 1) * ez);
+    double* fz = (double*)malloc(sizeof(double) * (size_t)ex * ey * (ez + 1));
+    if (!fx || !fy || !fz) {
+      free(fx); free(fy); free(fz);
+      return -1;
+    }
+    const double* u = uold + fab_off[b];
+    double* v = unew + fab_off[b];
+    for (int comp = 0; comp < ncomp; ++comp) {
+      for (int k = 0; k < ez; ++k)
+        for (int j = 0; j < ey; ++j)
+          for (int i = 0; i <= ex; ++i) {
+            int gi = bx[0] + i, gj = bx[1] + j, gk = bx[2] + k;
+            fx[((size_t)k * ey + j) * (ex + 1) + i] =
+                (u[fab_index(&g, comp, gi, gj, gk)] - u[fab_index(&g, comp, gi - 1, gj, gk)]) / dx;
+          }
+      for (int k = 0; k < ez; ++k)
+        for (int j = 0; j <= ey; ++j)
+          for (int i = 0; i < ex; ++i) {
+            int gi = bx[0] + i, gj = bx[1] + j, gk = bx[2] + k;
+            fy[((size_t)k * (ey + 1) + j) * ex + i] =
+                (u[fab_index(&g, comp, gi, gj, gk)] - u[fab_index(&g, comp, gi, gj - 1, gk)]) / dx;
+          }
+      for (int k = 0; k <= ez; ++k)
+        for (int j = 0; j < ey; ++j)
+          for (int i = 0; i < ex; ++i) {
+            int gi = bx[0] + i, gj = bx[1] + j, gk = bx[2] + k;
+            fz[((size_t)k * ey + j) * ex + i] =
+                (u[fab_index(&g, comp, gi, gj, gk)] - u[fab_index(&g, comp, gi, gj, gk - 1)]) / dx;
+          }
+      for (int k = 0; k < ez; ++k)
+        for (int j = 0; j < ey; ++j)
+          for (int i = 0; i < ex; ++i) {
+            int gi = bx[0] + i, gj = bx[1] + j, gk = bx[2] + k;
+            double dfx = (fx[((size_t)k * ey + j) * (ex + 1) + i + 1] - fx[((size_t)k * ey + j) * (ex + 1) + i]) / dx;
+            double dfy = (fy[((size_t)k * (ey + 1) + j + 1) * ex + i] - fy[((size_t)k * (ey + 1) + j) * ex + i]) / dx;
+            double dfz = (fz[((size_t)(k + 1) * ey + j) * ex + i] - fz[((size_t)k * ey + j) * ex + i]) / dx;
+            int64_t q = fab_index(&g, comp, gi, gj, gk);
+            v[q] = u[q] + dt * ((dfx + dfy) + dfz);
+          }
+    }
+    free(fx);
+    free(fy);
+    free(fz);
+  }
+  return 0;
+}
+
+/*
+ * One colour of a red-black Gauss-Seidel sweep for -L_h phi = f with the
+ * 7-point Laplacian L_h phi = (sum of 6 neighbours - 6 phi) / h2.  The colour
+ * of cell (i,j,k) is the parity of i+j+k in global indices (0 = red, 1 =
+ * black).  Each cell of the colour is solved for exactly, in place:
+ *   phi = ((((phi[i-1] + phi[i+1]) + (phi[j-1] + phi[j+1])) + (phi[k-1] + phi[k+1]))
+ *          + h2 * f) * inv6,      inv6 = 1/6 rounded once by the caller.
+ * Cells of one colour only read cells of the other colour (or ghosts), so the
+ * in-place update is independent of the visiting order.
+ */
+void orc_gsrb_color(int nbox, const int* boxes, int ng, double* phi, const double* f,
+                    const int64_t* fab_off, double h2, double inv6, int color) {
+#pragma omp parallel for schedule(dynamic)
+  for (int b = 0; b < nbox; ++b) {
+    const int* bx = boxes + 6 * b;
+    fab_geom g = geom_of(bx, ng);
+    double* p = phi + fab_off[b];
+    const double* fb = f + fab_off[b];
+    for (int k = bx[2]; k <= bx[5]; ++k)
+      for (int j = bx[1]; j <= bx[4]; ++j)
+        for (int i = bx[0]; i <= bx[3]; ++i) {
+          if (floor_mod(i + j + k, 2) != color) continue;
+          double sx = p[fab_index(&g, 0, i - 1, j, k)] + p[fab_index(&g, 0, i + 1, j, k)];
+          double sy = p[fab_index(&g, 0, i, j - 1, k)] + p[fab_index(&g, 0, i, j + 1, k)];
+          double sz = p[fab_index(&g, 0, i, j, k - 1)] + p[fab_index(&g, 0, i, j, k + 1)];
+          int64_t q = fab_index(&g, 0, i, j, k);
+          p[q] = (((sx + sy) + sz) + h2 * fb[q]) * inv6;
+        }
+  }
+}
+
+/*
+ * Residual of -L_h phi = f on the valid cells, in FP64:
+ *   r = f + (s - 6 phi) / h2,  s = ((phi[i-1]+phi[i+1]) + (phi[j-1]+phi[j+1])) + (phi[k-1]+phi[k+1])
+ * written box after box, each box in (k, j, i) order, into r_out.
+ */
+void orc_residual(int nbox, const int* boxes, int ng, const double* phi, const double* f,
+                  const int64_t* fab_off, double h2, double* r_out) {
+  int64_t n = 0;
+  for (int b = 0; b < nbox; ++b) {
+    const int* bx = boxes + 6 * b;
+    fab_geom g = geom_of(bx, ng);
+    const double* p = phi + fab_off[b];
+    const double* fb = f + fab_off[b];
+    for (int k = bx[2]; k <= bx[5]; ++k)
+      for (int j = bx[1]; j <= bx[4]; ++j)
+        for (int i = bx[0]; i <= bx[3]; ++i) {
+          double sx = p[fab_index(&g, 0, i - 1, j, k)] + p[fab_index(&g, 0, i + 1, j, k)];
+          double sy = p[fab_index(&g, 0, i, j - 1, k)] + p[fab_index(&g, 0, i, j + 1, k)];
+          double sz = p[fab_index(&g, 0, i, j, k - 1)] + p[fab_index(&g, 0, i, j, k + 1)];
+          int64_t q = fab_index(&g, 0, i, j, k);
+          r_out[n++] = fb[q] + (((sx + sy) + sz) - 6.0 * p[q]) / h2;
+        }
+  }
+}
+
+/*
+ * n heat steps on a cube window of edge 2n+1 (x fastest) cut from a fully
+ * periodic, fully covered domain around one cell: step s updates the cells at
+ * distance <= n-s-1 from the centre from those at distance <= n-s, with the
+ * same per-cell expression as orc_heat_step.  After n steps only the centre
+ * cell remains; its value is returned.  w is modified (used as the state) and
+ * tmp must hold as many doubles as w.
+ */
+double orc_heat_window(double* w, double* tmp, int n, double c) {
+  int e = 2 * n + 1;
+  double* a = w;
+  double* bb = tmp;
+  for (int s = 0; s < n; ++s) {
+    int lo = s + 1, hi = e - 2 - s; /* cells still computable after this step */
+    for (int k = lo; k <= hi; ++k)
+      for (int j = lo; j <= hi; ++j)
+        for (int i = lo; i <= hi; ++i) {
+          int64_t q = ((int64_t)k * e + j) * e + i;
+          double uc = a[q];
+          double sx = a[q - 1] + a[q + 1];
+          double sy = a[q - e] + a[q + e];
+          double sz = a[q - (int64_t)e * e] + a[q + (int64_t)e * e];
+          double s6 = (sx + sy) + sz;
+          bb[q] = uc + c * (s6 - 6.0 * uc);
+        }
+    double* t = a;
+    a = bb;
+    bb = t;
+  }
+  return a[((int64_t)n * e + n) * e + n];
+}

@@ -1,0 +1,439 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by the mathematics,
+not by the oracle itself (CPU only).
+
+Each pin is chosen so that a plausible mistake in the oracle fails at least one
+of them (``test_planted_mistakes_are_caught`` plants such mistakes in a copy of
+the oracle and checks exactly that):
+  * a periodic sine mode is a discrete eigenfunction of the 7-point Laplacian,
+    so n heat steps multiply it by g^n, g = 1 - 4c sum_d sin^2(pi k_d / N_d);
+  * the domain sum is conserved on periodic domains;
+  * a single-box and a many-box decomposition give bit-identical results;
+  * FillBoundary equals a brute-force search over boxes on tiny grids;
+  * one periodic box equals a numpy.roll 7-point update;
+  * the paper's flux form agrees with the 7-point form;
+  * red-black Gauss-Seidel equals dense Gauss-Seidel in red-then-black order;
+  * residual invariants (zero on the colour just relaxed, sum r = sum f);
+  * reductions against exactly known sums.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1604_03570_amd import inputs as I
+
+
+def _mf(boxes, n, ncomp=1, ng=1, periodic=(1, 1, 1)):
+    return O.OracleMultiFab(boxes, I.domain_box(n), periodic, ncomp, ng)
+
+
+def _uneven_boxes(n, seed):
+    """A seeded uneven decomposition of an (nx, ny, nz) domain (small edges)."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else n
+    return I.random_chop(I.domain_box((nx, ny, nz)), min_edge=2, max_edge=8, align=2, seed=seed)
+
+
+# ---------------------------------------------------------------------------------------------
+# heat step
+# ---------------------------------------------------------------------------------------------
+def _sine_decay_error(shape=(32, 24, 16), steps=20, boxes=None):
+    nx, ny, nz = shape
+    c = 0.1  # modes stay O(1e-2) after 20 steps, far above the rounding noise
+    modes = [(0.7, (1, 2, 3)), (0.3, (5, 1, 2))]
+    u0 = np.zeros((1, nz, ny, nx))
+    exact = np.zeros_like(u0)
+    for amp, k in modes:
+        phi = I.sine_product(shape, k)
+        g = 1.0 - 4.0 * c * sum(math.sin(math.pi * k[d] / shape[d]) ** 2 for d in range(3))
+        u0[0] += amp * phi
+        exact[0] += amp * g ** steps * phi
+    if boxes is None:
+        boxes = I.random_chop(I.domain_box(shape), min_edge=4, max_edge=16, align=4, seed=3)
+    m = _mf(boxes, shape)
+    m.load_global(u0)
+    out = O.heat_advance(m, steps, c).to_global()
+    return np.abs(out - exact).max() / np.abs(exact).max()
+
+
+def test_sine_mode_decay_closed_form():
+    # anisotropic domain and wavenumbers: axis mix-ups change the decay factor
+    assert _sine_decay_error() <= 1e-12
+    assert _sine_decay_error(boxes=I.regular_chop(I.domain_box((32, 24, 16)), 8)) <= 1e-12
+
+
+def test_sine_mode_decay_cfg1_modes():
+    # the 256^3 workload's seeded modes (wavenumbers 1..8), on a 64^3 grid
+    n, steps = 64, 10
+    u0, modes = I.sine_modes(n, seed=1)
+    c = I.heat_c(n)
+    m = _mf(I.regular_chop(I.domain_box(n), 32), n)
+    m.load_global(u0)
+    out = O.heat_advance(m, steps, c).to_global()
+    exact = np.zeros_like(u0)
+    for md in modes:
+        g = 1.0 - 4.0 * c * sum(math.sin(math.pi * kd / n) ** 2 for kd in md.k)
+        exact[0] += md.amp * g ** steps * I.sine_product(n, md.k)
+    assert np.abs(out - exact).max() / np.abs(exact).max() <= 1e-12
+
+
+def test_domain_sum_conserved_periodic():
+    shape = (12, 10, 8)
+    u0 = I.uniform(shape, 2, seed=5)
+    m = _mf(_uneven_boxes(shape, seed=1), shape, ncomp=2)
+    m.load_global(u0)
+    s0 = [O.reduce(m, comp, "sum") for comp in range(2)]
+    out = O.heat_advance(m, 30, 0.15)
+    for comp in range(2):
+        assert abs(O.reduce(out, comp, "sum") - s0[comp]) <= 1e-13 * abs(s0[comp])
+
+
+def test_single_box_equals_many_boxes_bit_identical():
+    n = 32
+    u0 = I.gaussian(n)
+    c = I.heat_c(n)
+    results = []
+    for boxes in (I.regular_chop(I.domain_box(n), n), I.regular_chop(I.domain_box(n), 16),
+                  I.regular_chop(I.domain_box(n), (8, 16, 32)),
+                  I.random_chop(I.domain_box(n), min_edge=4, max_edge=16, align=4, seed=7)):
+        m = _mf(boxes, n)
+        m.load_global(u0)
+        results.append(O.heat_advance(m, 10, c).to_global())
+    for r in results[1:]:
+        assert np.array_equal(r, results[0])
+
+
+def _roll_step(u, c):
+    """Textbook periodic 7-point update with numpy.roll, same operand order."""
+    xm, xp = np.roll(u, 1, axis=2), np.roll(u, -1, axis=2)
+    ym, yp = np.roll(u, 1, axis=1), np.roll(u, -1, axis=1)
+    zm, zp = np.roll(u, 1, axis=0), np.roll(u, -1, axis=0)
+    s = ((xm + xp) + (ym + yp)) + (zm + zp)
+    return u + c * (s - 6.0 * u)
+
+
+def test_single_periodic_box_equals_numpy_roll():
+    shape = (10, 6, 8)
+    u = I.uniform(shape, 1, seed=11)
+    m = _mf(I.regular_chop(I.domain_box(shape), 64), shape)
+    m.load_global(u)
+    ref = u[0]
+    for _ in range(7):
+        ref = _roll_step(ref, 0.15)
+    assert np.array_equal(O.heat_advance(m, 7, 0.15).to_global()[0], ref)
+
+
+def test_many_boxes_equal_numpy_roll():
+    shape = (10, 6, 8)
+    u = I.uniform(shape, 1, seed=12)
+    m = _mf(_uneven_boxes(shape, seed=4), shape)
+    m.load_global(u)
+    ref = u[0]
+    for _ in range(5):
+        ref = _roll_step(ref, 0.15)
+    assert np.array_equal(O.heat_advance(m, 5, 0.15).to_global()[0], ref)
+
+
+def test_flux_form_agrees_with_seven_point():
+    n = 24
+    dx = 1.0 / n
+    dt = 0.9 * dx * dx / 6.0
+    c = dt / (dx * dx)
+    u0 = I.uniform(n, 2, seed=2) + 1.0
+    a = _mf(_uneven_boxes(n, seed=2), n, ncomp=2)
+    a.load_global(u0)
+    b = a.copy()
+    a2, b2 = a.copy(), b.copy()
+    for _ in range(5):
+        O.heat_step(a, a2, c)
+        a, a2 = a2, a
+        O.heat_flux_step(b, b2, dt, dx)
+        b, b2 = b2, b
+    ga, gb = a.to_global(), b.to_global()
+    assert np.abs(ga - gb).max() / np.abs(ga).max() <= 1e-14
+    assert not np.array_equal(ga, gb)  # genuinely a different formulation
+
+
+def test_heat_window_equals_full_run():
+    n, steps = 16, 6
+    u0 = I.uniform(n, 1, seed=3)
+    c = I.heat_c(n)
+    m = _mf(I.regular_chop(I.domain_box(n), 8), n)
+    m.load_global(u0)
+    full = O.heat_advance(m, steps, c).to_global()[0]
+    rng = np.random.default_rng(0)
+    for _ in range(10):
+        i, j, k = (int(v) for v in rng.integers(0, n, 3))
+        assert O.heat_window(u0[0], (i, j, k), steps, c) == full[k, j, i]
+
+
+# ---------------------------------------------------------------------------------------------
+# FillBoundary
+# ---------------------------------------------------------------------------------------------
+POISON = -1.0e300
+
+
+def _brute_fill(boxes, shape, periodic, ng, ncomp, values):
+    """For every ghost cell of every box, search all boxes for the wrapped index."""
+    nx, ny, nz = shape
+    N = (nx, ny, nz)
+    expect = {}
+    for b, bx in enumerate(boxes):
+        for k in range(bx[2] - ng, bx[5] + ng + 1):
+            for j in range(bx[1] - ng, bx[4] + ng + 1):
+                for i in range(bx[0] - ng, bx[3] + ng + 1):
+                    if bx[0] <= i <= bx[3] and bx[1] <= j <= bx[4] and bx[2] <= k <= bx[5]:
+                        continue
+                    p = [i, j, k]
+                    ok = True
+                    for d in range(3):
+                        if periodic[d]:
+                            p[d] %= N[d]
+                        if not 0 <= p[d] < N[d]:
+                            ok = False
+                    owner = None
+                    if ok:
+                        for bb in boxes:
+                            if bb[0] <= p[0] <= bb[3] and bb[1] <= p[1] <= bb[4] and bb[2] <= p[2] <= bb[5]:
+                                owner = bb
+                    for comp in range(ncomp):
+                        v = values[comp, p[2], p[1], p[0]] if owner is not None else POISON
+                        expect[(b, comp, k, j, i)] = v
+    return expect
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_fill_boundary_brute_force(case):
+    rng = np.random.default_rng(100 + case)
+    shape = [(8, 6, 4), (5, 5, 5), (7, 4, 6)][case % 3]
+    ng = 1 + case % 2
+    ncomp = 1 + case % 3
+    periodic = tuple(int(v) for v in rng.integers(0, 2, 3))
+    boxes = I.random_chop(I.domain_box(shape), min_edge=1, max_edge=4, align=1, seed=case)
+    if case % 4 == 3 and len(boxes) > 2:  # non-covering box list: drop some boxes
+        keep = rng.permutation(len(boxes))[: len(boxes) // 2]
+        boxes = boxes[np.sort(keep)]
+    nx, ny, nz = shape
+    # unique value per (comp, cell): any mis-copied ghost is seen
+    values = np.arange(ncomp * nx * ny * nz, dtype=np.float64).reshape(ncomp, nz, ny, nx) + 0.25
+    m = O.OracleMultiFab(boxes, I.domain_box(shape), periodic, ncomp, ng)
+    m.data[...] = POISON
+    m.load_global(values)
+    before = [m.valid(b).copy() for b in range(m.nbox)]
+    m.fill_boundary()
+    expect = _brute_fill(boxes, shape, periodic, ng, ncomp, values)
+    for (b, comp, k, j, i), v in expect.items():
+        bx = boxes[b]
+        got = m.fab(b)[comp, k - bx[2] + ng, j - bx[1] + ng, i - bx[0] + ng]
+        assert got == v, (b, comp, k, j, i)
+    for b in range(m.nbox):
+        assert np.array_equal(m.valid(b), before[b])
+
+
+def test_fill_boundary_partial_components():
+    shape = (6, 6, 6)
+    boxes = I.regular_chop(I.domain_box(shape), 3)
+    vals = I.uniform(shape, 3, seed=9)
+    m = O.OracleMultiFab(boxes, I.domain_box(shape), (1, 1, 1), 3, 1)
+    m.data[...] = POISON
+    m.load_global(vals)
+    m.fill_boundary(scomp=1, ncomp=1)
+    for b in range(m.nbox):
+        f = m.fab(b)
+        assert np.sum(f[0] == POISON) == f[0].size - m.valid(b)[0].size  # comp 0 ghosts untouched
+        assert np.sum(f[2] == POISON) == f[2].size - m.valid(b)[2].size  # comp 2 ghosts untouched
+        assert not np.any(f[1] == POISON)                                   # comp 1 fully filled
+
+
+# ---------------------------------------------------------------------------------------------
+# red-black Gauss-Seidel
+# ---------------------------------------------------------------------------------------------
+def _dense_minus_laplacian(shape, h2):
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    A = np.zeros((n, n))
+    idx = lambda i, j, k: (k % nz) * ny * nx + (j % ny) * nx + (i % nx)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                r = idx(i, j, k)
+                A[r, r] += 6.0 / h2
+                for di, dj, dk in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                    A[r, idx(i + di, j + dj, k + dk)] -= 1.0 / h2
+    return A
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (6, 4, 8)])
+def test_gsrb_equals_dense_gauss_seidel_red_then_black(shape):
+    nx, ny, nz = shape
+    h2 = (1.0 / 8) ** 2
+    f = I.uniform(shape, 1, seed=21)[0] - 0.5
+    phi0 = I.uniform(shape, 1, seed=22)[0]
+    A = _dense_minus_laplacian(shape, h2)
+    kk, jj, ii = np.meshgrid(range(nz), range(ny), range(nx), indexing="ij")
+    color = ((ii + jj + kk) % 2).ravel()
+    order = np.concatenate([np.flatnonzero(color == 0), np.flatnonzero(color == 1)])
+    Ap = A[np.ix_(order, order)]
+    x = phi0.ravel()[order].copy()
+    b = f.ravel()[order]
+    DL = np.tril(Ap)
+    for _ in range(2):  # two sweeps: x <- x + (D+L)^{-1} (b - A x)
+        x = x + np.linalg.solve(DL, b - Ap @ x)
+    expect = np.empty_like(x)
+    expect[order] = x
+    boxes = I.regular_chop(I.domain_box(shape), (nx // 2, ny // 2, nz))  # several boxes
+    phi = _mf(boxes, shape)
+    phi.load_global(phi0[None])
+    fm = _mf(boxes, shape)
+    fm.load_global(f[None])
+    O.gsrb_sweeps(phi, fm, h2, 2, with_norms=False)
+    got = phi.to_global()[0].ravel()
+    assert np.abs(got - expect).max() / np.abs(expect).max() <= 1e-14
+
+
+def test_gsrb_residual_invariants():
+    shape = (8, 8, 6)
+    h2 = (1.0 / 8) ** 2
+    f = I.zero_mean_normal_f32(shape, seed=4)
+    boxes = _uneven_boxes(shape, seed=5)
+    phi = _mf(boxes, shape)
+    fm = _mf(boxes, shape)
+    fm.load_global(f)
+    kk, jj, ii = np.meshgrid(range(shape[2]), range(shape[1]), range(shape[0]), indexing="ij")
+    red = ((ii + jj + kk) % 2) == 0
+    scale = np.abs(f).max()
+
+    def r_global():
+        r = O.residual(phi, fm, h2)
+        g = np.empty(shape[::-1])
+        n = 0
+        for bx in boxes:
+            e = (bx[3] - bx[0] + 1, bx[4] - bx[1] + 1, bx[5] - bx[2] + 1)
+            sz = e[0] * e[1] * e[2]
+            g[bx[2]:bx[5] + 1, bx[1]:bx[4] + 1, bx[0]:bx[3] + 1] = r[n:n + sz].reshape(e[::-1])
+            n += sz
+        return g
+
+    for _ in range(3):
+        O.gsrb_color(phi, fm, h2, 0)
+        r = r_global()
+        assert np.abs(r[red]).max() <= 1e-12 * scale
+        O.gsrb_color(phi, fm, h2, 1)
+        r = r_global()
+        assert np.abs(r[~red]).max() <= 1e-12 * scale
+        # periodic: sum of L_h phi vanishes, so sum r = sum f
+        assert abs(math.fsum(r.ravel().tolist()) - math.fsum(f.ravel().tolist())) <= 1e-10 * scale * r.size
+
+
+def test_gsrb_exact_discrete_solution_is_fixed_point():
+    shape = (8, 8, 8)
+    h2 = (1.0 / 8) ** 2
+    k = (1, 2, 3)
+    phi_exact = I.sine_product(shape, k)
+    lam = 4.0 / h2 * sum(math.sin(math.pi * kd / 8) ** 2 for kd in k)  # -L_h phi = lam phi
+    boxes = I.regular_chop(I.domain_box(shape), 4)
+    phi = _mf(boxes, shape)
+    phi.load_global(phi_exact[None])
+    fm = _mf(boxes, shape)
+    fm.load_global(lam * phi_exact[None])
+    norms = O.gsrb_sweeps(phi, fm, h2, 3)
+    assert np.abs(phi.to_global()[0] - phi_exact).max() <= 1e-13
+    assert max(norms) <= 1e-10 * lam
+
+
+def test_gsrb_decomposition_invariance_and_single_fill_breaks_it():
+    n = 8
+    h2 = (1.0 / n) ** 2
+    f = I.zero_mean_normal_f32(n, seed=6)
+    out = {}
+    for name, boxes in (("one", I.regular_chop(I.domain_box(n), n)),
+                        ("many", I.regular_chop(I.domain_box(n), 4))):
+        for per_color in (True, False):
+            phi = _mf(boxes, n)
+            fm = _mf(boxes, n)
+            fm.load_global(f)
+            O.gsrb_sweeps(phi, fm, h2, 3, with_norms=False, fill_per_color=per_color)
+            out[(name, per_color)] = phi.to_global()
+    assert np.array_equal(out[("one", True)], out[("many", True)])
+    # one fill per sweep: black cells at box faces read stale red ghosts
+    assert not np.array_equal(out[("one", False)], out[("many", False)])
+
+
+def test_gsrb_residual_decreases():
+    n = 16
+    h2 = (1.0 / n) ** 2
+    f = I.zero_mean_normal_f32(n, seed=7)
+    boxes = I.regular_chop(I.domain_box(n), 8)
+    phi, fm = _mf(boxes, n), _mf(boxes, n)
+    fm.load_global(f)
+    r0 = math.sqrt(math.fsum((f.ravel() ** 2).tolist()))
+    norms = O.gsrb_sweeps(phi, fm, h2, 10)
+    assert norms[0] < r0 and all(b < a for a, b in zip(norms, norms[1:]))
+
+
+# ---------------------------------------------------------------------------------------------
+# reductions
+# ---------------------------------------------------------------------------------------------
+def test_reductions_exact_cases():
+    shape = (4, 4, 2)
+    boxes = I.regular_chop(I.domain_box(shape), 2)
+    g = np.zeros((2,) + shape[::-1])
+    flat = g[0].ravel()
+    flat[:] = 1.0
+    flat[3] = 1e16
+    flat[17] = -1e16  # naive left-to-right summation loses the ones next to 1e16
+    g[1] = -np.arange(32, dtype=np.float64).reshape(shape[::-1]) * 0.5
+    m = _mf(boxes, shape, ncomp=2)
+    m.load_global(g)
+    assert O.reduce(m, 0, "sum") == 30.0
+    assert O.reduce(m, 0, "max") == 1e16 and O.reduce(m, 0, "min") == -1e16
+    assert O.reduce(m, 0, "norm0") == 1e16
+    assert O.reduce(m, 0, "norm1") == 2e16 + 30.0
+    assert O.reduce(m, 1, "sum") == -0.5 * 31 * 32 / 2
+    assert O.reduce(m, 1, "norm1") == 0.5 * 31 * 32 / 2
+    assert O.reduce(m, 1, "norm2") == math.sqrt(0.25 * sum(i * i for i in range(32)))
+    assert O.reduce(m, 1, "max") == 0.0 and O.reduce(m, 1, "min") == -15.5
+
+
+# ---------------------------------------------------------------------------------------------
+# planted mistakes: each must make at least one pin fail
+# ---------------------------------------------------------------------------------------------
+MUTATIONS = {
+    "heat_drops_z_pair": ("double s = (sx + sy) + sz;\n            v[", "double s = (sx + sy);\n            v["),
+    "heat_wrong_sign": ("uc + c * (s - 6.0 * uc)", "uc - c * (s - 6.0 * uc)"),
+    "heat_shifted_index": ("u[fab_index(&g, comp, i, j - 1, k)] + u[fab_index(&g, comp, i, j + 1, k)]",
+                           "u[fab_index(&g, comp, i, j - 1, k)] + u[fab_index(&g, comp, i, j + 2, k)]"),
+    "layout_transposed": ("return (((int64_t)comp * g->nz + lk) * g->ny + lj) * g->nx + li;",
+                          "return (((int64_t)comp * g->nz + lk) * g->nx + li) * g->ny + lj;"),
+    "fill_no_wrap": ("if (periodic[d]) p[d] = lo[d] + floor_mod(p[d] - lo[d], N[d]);", ""),
+    "gsrb_black_first": ("if (floor_mod(i + j + k, 2) != color) continue;",
+                         "if (floor_mod(i + j + k + 1, 2) != color) continue;"),
+    "gsrb_drops_rhs": ("p[q] = (((sx + sy) + sz) + h2 * fb[q]) * inv6;", "p[q] = (((sx + sy) + sz)) * inv6;"),
+}
+
+
+def _pins_pass():
+    checks = []
+    try:
+        checks.append(_sine_decay_error() <= 1e-12)
+        test_single_periodic_box_equals_numpy_roll()
+        test_many_boxes_equal_numpy_roll()
+        test_fill_boundary_brute_force(1)
+        test_gsrb_equals_dense_gauss_seidel_red_then_black((4, 4, 4))
+        test_gsrb_exact_discrete_solution_is_fixed_point()
+    except (AssertionError, ValueError, IndexError):
+        return False
+    return all(checks)
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistakes_are_caught(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = O.source()
+    assert src.count(old) >= 1, "mutation anchor not found"
+    with O.variant(src.replace(old, new), str(tmp_path)):
+        assert not _pins_pass(), f"pins did not catch planted mistake {name}"
+
+
+def test_unmodified_oracle_passes_the_mutation_harness():
+    assert _pins_pass()
