@@ -1,0 +1,246 @@
+"""Benchmark of the batched heat step with FillBoundary on one MI355X.
+
+Workload (default): a 512^3 periodic domain cut by the seeded recursive chop into
+~1270 uneven boxes of edge 16..128 (multiples of 8), 5 components, 1 ghost cell,
+U(0,1) initial data per component, FP64.  One step = FillBoundary + heat step
+over every box and component, run as one launch of the fused kernel; K steps are
+one HIP graph.  value = cell updates per second (valid cells x components x K /
+timed seconds), in GCell-updates/s.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f64|f32]
+
+Prints one JSON line.  With --gpus above 1 it exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GCell-updates/s + % HBM roofline (heat_step+FillBoundary); p50/p99 serve latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat_fused_cfg2_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1604_03570_amd", "csrc", "bl_kernels.hip")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(dtype: str):
+    """HBM bytes per launch of the fused kernel from committed rocprofv3 counter runs,
+    or None if none were taken for the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = t.get(dtype)
+    if not entry or t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def cpu_baseline(boxes, dom, u0, c, nthreads_note: str):
+    """The oracle as it stands, one full step (FillBoundary + heat) of the workload."""
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    m = O.OracleMultiFab(boxes, dom, (1, 1, 1), u0.shape[0], 1)
+    m.load_global(u0)
+    w = m.copy()
+    setup = time.perf_counter() - t0
+    nsteps = 1
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        O.heat_step(m, w, c)
+        m, w = w, m
+    dt = time.perf_counter() - t0
+    cells = sum(int(np.prod(b[3:] - b[:3] + 1)) for b in boxes) * u0.shape[0]
+    log(f"cpu baseline: {nsteps} step(s) in {dt:.2f} s (setup {setup:.1f} s), {O.num_threads()} threads")
+    return {
+        "value": round(cells * nsteps / dt / 1e9, 5),
+        "unit": "GCell-updates/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": f"{nsteps} full step (FillBoundary + 7-point update) of the same workload, FP64, "
+                  f"OpenMP over boxes ({nthreads_note})",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--n", type=int, default=512, help="domain edge")
+    ap.add_argument("--ncomp", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--zchunk", type=int, default=None)
+    ap.add_argument("--waves", type=int, default=None)
+    ap.add_argument("--persist", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and unfused measurements")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    import torch
+    from paper_1604_03570_amd import boxtile as bt
+    from paper_1604_03570_amd import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.zchunk or args.waves or args.persist is not None:
+        z, w, p = bt.get_tile_config()
+        bt.set_tile_config(args.zchunk or z, args.waves or w, p if args.persist is None else args.persist)
+    cfg_tile = bt.get_tile_config()
+
+    n, ncomp = args.n, args.ncomp
+    dom = I.domain_box(n)
+    boxes = I.random_chop(dom, 16, 128, 8, seed=args.seed)
+    c = I.heat_c(n)
+    log(f"workload: {n}^3, {len(boxes)} boxes, {ncomp} comps, dtype {args.dtype}, tile cfg {cfg_tile}")
+    t0 = time.perf_counter()
+    u0 = I.uniform(n, ncomp, seed=args.seed)
+    log(f"inputs generated in {time.perf_counter() - t0:.1f} s")
+    cells = int(sum(int(np.prod(b[3:] - b[:3] + 1)) for b in boxes)) * ncomp
+
+    def run(dtype_name: str, steps: int, warmup: int):
+        dt = bt.F64 if dtype_name == "f64" else bt.F32
+        ba = bt.BoxArray.from_boxes(boxes, dom)
+        a, b = bt.MultiFab(ba, ncomp, 1, dt), bt.MultiFab(ba, ncomp, 1, dt)
+        for comp in range(ncomp):  # one component at a time keeps the staging copy small
+            a.from_global(u0[comp:comp + 1], scomp=comp)
+        torch.cuda.synchronize()
+        if warmup:
+            x = bt.heat_advance(a, b, warmup, c)
+        else:
+            x = a
+        y = b if x is a else a
+        torch.cuda.synchronize()
+        s0 = x.sum(0)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        # capture the K-step graph outside the timed region; with K odd run it twice
+        # so that the state is back in x and the timed call reuses the same graph
+        for _ in range(1 if steps % 2 == 0 else 2):
+            bt.heat_advance(x, y, steps, c)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        res = bt.heat_advance(x, y, steps, c)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = e0.elapsed_time(e1)
+        drift = abs(res.sum(0) - s0) / abs(s0)
+        return ms, wall, drift, ba, a, b
+
+    ms, wall, drift, ba, a, b = run(args.dtype, args.steps, args.warmup)
+    esize = 8 if args.dtype == "f64" else 4
+    sec = ms / 1e3
+    value = cells * args.steps / sec / 1e9
+    per_launch_s = sec / args.steps
+    alg_bytes = 2 * esize * cells  # read u once, write u_new once
+    achieved = alg_bytes / per_launch_s / 1e9
+    traffic = measured_traffic(args.dtype)
+    log(f"{args.dtype}: {ms:.3f} ms for {args.steps} steps (wall {wall * 1e3:.3f} ms), "
+        f"{value:.1f} GCell/s, {achieved:.0f} GB/s, sum drift {drift:.2e}")
+
+    extra = {"sum_drift_rel": drift, "wall_ms_timed": round(wall * 1e3, 4), "tile_config": list(cfg_tile),
+             "nboxes": len(boxes)}
+    if not args.no_extra:
+        # unfused form: fill kernel and stencil kernel timed apart (fill fraction)
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        reps = 10
+        for _ in range(2):
+            bt.heat_step_unfused(a, b, c)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(reps):
+            a.fill_boundary()
+        ev[1].record(stream)
+        for _ in range(reps):
+            bt.heat_step_unfused(a, b, c)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        fill_ms = ev[0].elapsed_time(ev[1]) / reps
+        unfused_ms = ev[1].elapsed_time(ev[2]) / reps
+        extra["unfused_ms_per_step"] = round(unfused_ms, 4)
+        extra["unfused_fill_ms"] = round(fill_ms, 4)
+        extra["unfused_fill_fraction"] = round(fill_ms / unfused_ms, 4)
+        extra["unfused_gcell_s"] = round(cells / (unfused_ms / 1e3) / 1e9, 2)
+        log(f"unfused: {unfused_ms:.3f} ms/step, fill {fill_ms:.3f} ms ({fill_ms / unfused_ms:.1%})")
+        del a, b, ba
+        torch.cuda.empty_cache()
+        if args.dtype == "f64":
+            ms32, _, drift32, ba32, a32, b32 = run("f32", args.steps, args.warmup)
+            v32 = cells * args.steps / (ms32 / 1e3) / 1e9
+            extra["f32_gcell_s"] = round(v32, 2)
+            extra["f32_ms_per_step"] = round(ms32 / args.steps, 5)
+            extra["f32_hbm_frac"] = round(v32 * 8 / HBM_PEAK_GBS, 4)
+            extra["f32_sum_drift_rel"] = drift32
+            log(f"f32: {v32:.1f} GCell/s")
+            del a32, b32, ba32
+            torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(boxes, dom, u0, c, f"OMP_NUM_THREADS={os.environ.get('OMP_NUM_THREADS', 'unset')}")
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GCell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched heat step + FillBoundary (fused, one launch per step, HIP graph): {n}^3 periodic "
+                        f"domain, seeded recursive chop into {len(boxes)} boxes of edge 16-128, {ncomp} comps, "
+                        f"1 ghost, U(0,1) initial data, {args.dtype}",
+            "domain": n, "nboxes": len(boxes), "ncomp": ncomp, "nghost": 1, "seed": args.seed,
+            "cell_updates_per_step": cells,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+        },
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

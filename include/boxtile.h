@@ -1,0 +1,333 @@
+/*
+ * boxtile: the single-level hot path of "BoxLib with Tiling: An AMR Software
+ * Framework" on AMD MI355X (gfx950).
+ *
+ * The calls follow the paper's own objects:
+ *   Box          a rectangle in index space held as six integers (Sec. 3.1);
+ *   BoxArray     the non-intersecting grids of one level, a copy of which every
+ *                process holds (Sec. 3, Sec. 3.1);
+ *   DistributionMapping  which process (here: which GPU) owns each grid (Sec. 3.1);
+ *   MultiFab     the FArrayBoxes of one level: per grid, multi-component data on
+ *                the grid grown by ghost cells (Sec. 3.1);
+ *   FillBoundary the ghost-cell fill between the grids of one level, including
+ *                periodic images (Sec. 3.1, Sec. 3.3, Sec. 4.1);
+ *   heat step    forward Euler with second-order centred differences (Sec. 4.1);
+ *   reductions   e.g. the maximum of one component over the level (Sec. 3.1).
+ * The red-black Gauss-Seidel smoother and its residual norm are the textbook
+ * smoother of the multigrid solvers the paper names (Sec. 1, Sec. 3.3); the
+ * paper does not write them out.
+ *
+ * Conventions
+ *   - Every call returns a bl_status: BL_OK (0) or a negative error code; no
+ *     exception crosses this interface.  bl_last_error() returns a message for
+ *     the calling thread's most recent failure.
+ *   - Boxes hold inclusive cell indices.  A domain box is [lo, hi] per axis.
+ *   - Handles (bl_boxarray, bl_distmap, bl_multifab, bl_batch) are created and
+ *     destroyed by the library.  They are not thread-safe; distinct handles
+ *     may be used from distinct threads.
+ *   - Field data lives in device memory owned by the CALLER (for example a
+ *     torch tensor); it must outlive every MultiFab made on it.  The library
+ *     owns only its metadata (host and device).
+ *   - Work is enqueued asynchronously on the hipStream_t passed in (0 is the
+ *     null stream).  Calls that return a scalar to a host pointer synchronise
+ *     that stream before returning.
+ *   - Data layout of a MultiFab (bl_multifab_layout reports it): FAB b is one
+ *     contiguous block holding its grown box for each component, x fastest,
+ *     then y, then z, then the component.  Rows in x may be padded so that the
+ *     first valid cell of every row is 16-byte aligned; strides give the exact
+ *     element distances.
+ */
+#ifndef BOXTILE_H
+#define BOXTILE_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bl_status;
+#define BL_OK 0
+#define BL_EINVAL (-1)   /* an argument is out of range */
+#define BL_EOVERLAP (-2) /* two boxes of a BoxArray intersect */
+#define BL_EDOMAIN (-3)  /* a box leaves the domain */
+#define BL_ESHAPE (-4)   /* MultiFabs disagree in BoxArray, ncomp or nghost */
+#define BL_EDTYPE (-5)   /* MultiFabs disagree in dtype, or the dtype is unknown */
+#define BL_ENOMEM (-6)   /* a buffer is too small, or host/device metadata allocation failed */
+#define BL_EHIP (-7)     /* a HIP runtime call failed; the message names it */
+
+typedef struct {
+  int32_t lo[3], hi[3];
+} bl_box; /* inclusive cell indices (Sec. 3.1: six integers) */
+
+typedef enum { BL_F64 = 0, BL_F32 = 1 } bl_dtype;
+
+typedef enum {
+  BL_SUM = 0,   /* sum of the component over valid cells, FP64 accumulation */
+  BL_MAX = 1,   /* maximum (Sec. 3.1: mf.max(comp)) */
+  BL_MIN = 2,   /* minimum */
+  BL_NORM0 = 3, /* max |u| */
+  BL_NORM1 = 4, /* sum |u|, FP64 accumulation */
+  BL_NORM2 = 5  /* sqrt(sum u^2), FP64 accumulation */
+} bl_reduce_op;
+
+typedef struct bl_boxarray bl_boxarray;
+typedef struct bl_distmap bl_distmap;
+typedef struct bl_multifab bl_multifab;
+typedef struct bl_batch bl_batch;
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char* bl_last_error(void);
+/* Library version string. */
+const char* bl_version(void);
+
+/* ---------------------------------------------------------------- BoxArray */
+
+/*
+ * A level's grids (Sec. 3, Sec. 3.1): nboxes >= 1 boxes that must be non-empty,
+ * pairwise disjoint (else BL_EOVERLAP) and inside `domain` (else BL_EDOMAIN).
+ * They need not cover the domain.  periodic[d] != 0 makes axis d periodic for
+ * FillBoundary.  The boxes are copied; *out is owned by the caller and freed
+ * with bl_boxarray_destroy.
+ */
+bl_status bl_boxarray_create(const bl_box* boxes, int32_t nboxes, const bl_box* domain,
+                             const int32_t periodic[3], bl_boxarray** out);
+
+/*
+ * Regular chop of `domain` into boxes of edge max_edge[d] along axis d, cut
+ * from the low end, the remainder (if any) as the last box of the axis; boxes
+ * listed x fastest, then y, then z.  max_edge[d] >= 1, else BL_EINVAL.
+ */
+bl_status bl_boxarray_chop(const bl_box* domain, const int32_t periodic[3], const int32_t max_edge[3],
+                           bl_boxarray** out);
+
+/*
+ * Seeded recursive chop into uneven boxes.  Depth first, low half first: a box
+ * whose longest edge m is <= max_edge is kept if m < 2*min_edge, or else if a
+ * uniform draw in [0,1) is below 1/2; otherwise its longest axis (lowest on
+ * ties) is cut at offset min_edge + align*(draw mod ((m - 2*min_edge)/align + 1))
+ * from the box's low end.  Draw n of the stream is SplitMix64 (Steele, Lea and
+ * Flood, 2014) of seed + (n+1)*0x9E3779B97F4A7C15; a uniform draw uses its top
+ * 53 bits.  Requires min_edge % align == 0 and max_edge >= 2*min_edge
+ * (else BL_EINVAL).
+ */
+bl_status bl_boxarray_chop_random(const bl_box* domain, const int32_t periodic[3], int32_t min_edge,
+                                  int32_t max_edge, int32_t align, uint64_t seed, bl_boxarray** out);
+
+/* Number of boxes, and (if boxes != NULL) the boxes themselves, in order. */
+bl_status bl_boxarray_get(const bl_boxarray* ba, int32_t* nboxes, bl_box* boxes);
+/* Domain box and periodic flags. */
+bl_status bl_boxarray_domain(const bl_boxarray* ba, bl_box* domain, int32_t periodic[3]);
+void bl_boxarray_destroy(bl_boxarray* ba);
+
+/* ------------------------------------------------------ DistributionMapping */
+
+/*
+ * Owner of each box (Sec. 3.1: the data of a MultiFab are distributed among
+ * processes).  This build runs on one GPU: ndevices must be 1 and owner, if
+ * given, must hold nboxes zeros; other values give BL_EINVAL.
+ */
+bl_status bl_distmap_create(const bl_boxarray* ba, int32_t ndevices, const int32_t* owner,
+                            bl_distmap** out);
+void bl_distmap_destroy(bl_distmap* dm);
+
+/* ----------------------------------------------------------------- MultiFab */
+
+/*
+ * Device bytes a MultiFab of this shape needs (ncomp >= 1, nghost >= 0).
+ */
+bl_status bl_multifab_bytes(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_dtype dtype,
+                            size_t* bytes);
+
+/*
+ * A MultiFab (Sec. 3.1) on caller-owned device memory dev_ptr of `bytes` bytes
+ * (BL_ENOMEM if fewer than bl_multifab_bytes; dev_ptr must be 256-byte
+ * aligned, else BL_EINVAL).  The memory is not initialised.  dm may be NULL
+ * (all boxes on this GPU).  Stencil calls need nghost >= 1.
+ */
+bl_status bl_multifab_create(const bl_boxarray* ba, const bl_distmap* dm, int32_t ncomp, int32_t nghost,
+                             bl_dtype dtype, void* dev_ptr, size_t bytes, bl_multifab** out);
+
+/*
+ * Layout of FAB `box`: its grown box, the element offset (from dev_ptr) of
+ * its first element, the grown box's low corner, component 0, and element
+ * strides {x, y, z, comp}.  The element of global cell (i,j,k), component n,
+ * is at
+ *   offset + (i - grown.lo[0]) + (j - grown.lo[1])*stride[1]
+ *          + (k - grown.lo[2])*stride[2] + n*stride[3]
+ * in elements of the MultiFab's dtype (stride[0] is 1; stride[1] may exceed
+ * the grown x extent when rows are padded).
+ */
+bl_status bl_multifab_layout(const bl_multifab* mf, int32_t box, bl_box* grown, size_t* offset_elems,
+                             int64_t stride[4]);
+/* Shape query: number of boxes, ncomp, nghost, dtype. */
+bl_status bl_multifab_info(const bl_multifab* mf, int32_t* nboxes, int32_t* ncomp, int32_t* nghost,
+                           int32_t* dtype);
+/* Frees the handle and its metadata; does not free dev_ptr. */
+void bl_multifab_destroy(bl_multifab* mf);
+
+/*
+ * Copy between the valid cells of components [scomp, scomp+ncomp) and a dense
+ * device array `global_dev` of shape (ncomp, Nz, Ny, Nx) over the domain, x
+ * fastest, of the MultiFab's dtype.  to_global != 0 copies MultiFab -> array
+ * (cells no box covers are not written); 0 copies array -> MultiFab.  Ghost
+ * cells are not touched.
+ */
+bl_status bl_multifab_copy_global(bl_multifab* mf, int32_t scomp, int32_t ncomp, void* global_dev,
+                                  int32_t to_global, hipStream_t stream);
+
+/* Set components [scomp, scomp+ncomp) to val on valid cells, and on ghost cells too if with_ghosts. */
+bl_status bl_multifab_set_val(bl_multifab* mf, double val, int32_t scomp, int32_t ncomp, int32_t with_ghosts,
+                              hipStream_t stream);
+
+/* ------------------------------------------------------------ FillBoundary */
+
+/*
+ * FillBoundary (Sec. 3.1, Sec. 3.3, Sec. 4.1): for components [scomp,
+ * scomp+ncomp), every ghost cell of every FAB takes the valid value at its
+ * index wrapped along the periodic axes, if that index lies in the domain and
+ * in some box; other ghost cells keep their value.  Valid cells are only read.
+ */
+bl_status bl_fill_boundary(bl_multifab* mf, int32_t scomp, int32_t ncomp, hipStream_t stream);
+
+/* ---------------------------------------------------------------- heat step */
+
+/*
+ * One forward-Euler heat step with second-order centred differences
+ * (Sec. 4.1), the plain per-box form: optionally FillBoundary(u_old) first
+ * (fill_first != 0), then one kernel launch per box:
+ *   u_new = u + c*( ((u[i-1]+u[i+1]) + (u[j-1]+u[j+1])) + (u[k-1]+u[k+1]) - 6u ),
+ *   c = dt/dx^2 (diffusivity 1), for every component, on valid cells.
+ * Ghost cells of u_new are not written.  u_old and u_new must share BoxArray,
+ * ncomp and nghost (BL_ESHAPE) and dtype (BL_EDTYPE); nghost >= 1 (BL_EINVAL).
+ */
+bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t fill_first,
+                       hipStream_t stream);
+
+/*
+ * nsteps heat steps, ping-ponging u[0] -> u[1] -> u[0] ...; the result is in
+ * u[nsteps % 2].  Each step is ONE launch of the fused kernel over the
+ * flattened tile list of all boxes and components: tiles next to a box face
+ * read the neighbouring box's valid cells (or their periodic image) directly,
+ * which is the value FillBoundary would have put in the ghost cell.  The
+ * per-step launches are captured once in a HIP graph and replayed.  Ghost
+ * cells are neither read where a box covers them nor written.  Results are
+ * bit-identical to bl_heat_step with fill_first = 1.
+ */
+bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream_t stream);
+
+/*
+ * One step of the unfused batched form: FillBoundary(u_old) as one copy
+ * kernel, then one stencil kernel over all tiles reading the filled ghosts.
+ * Same result as bl_heat_step; kept to measure the fill fraction.
+ */
+bl_status bl_heat_step_unfused(bl_multifab* u_old, bl_multifab* u_new, double c, hipStream_t stream);
+
+/* ------------------------------------------------------ red-black Gauss-Seidel */
+
+/*
+ * nsweeps red-black Gauss-Seidel sweeps on -L_h phi = f, L_h the 7-point
+ * Laplacian (L_h phi = (sum of 6 neighbours - 6 phi)/h2), in place on phi
+ * (component 0).  Colour = parity of i+j+k in global indices, red (even)
+ * first; FillBoundary(phi) runs before each colour, and each cell of the
+ * colour is solved exactly:
+ *   phi = ((((phi[i-1]+phi[i+1]) + (phi[j-1]+phi[j+1])) + (phi[k-1]+phi[k+1])) + h2*f) * (1/6).
+ * If resnorm_host != NULL, after each sweep the FP64 residual norm
+ * ||f + L_h phi||_2 over valid cells is written to resnorm_host[s] (the stream
+ * is synchronised once at the end).  phi and f share BoxArray, dtype and
+ * nghost >= 1.  Every periodic axis needs an even extent (else BL_EINVAL:
+ * the colouring would not match across the wrap).
+ */
+bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int32_t nsweeps,
+                         double* resnorm_host, hipStream_t stream);
+
+/* ||f + L_h phi||_2 over valid cells in FP64 (fills phi's ghosts first); synchronises. */
+bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, double* out_host,
+                           hipStream_t stream);
+
+/* ---------------------------------------------------------------- reductions */
+
+/* Reduction of component comp over valid cells (Sec. 3.1); result to host; synchronises. */
+bl_status bl_reduce(const bl_multifab* mf, int32_t comp, bl_reduce_op op, double* out_host,
+                    hipStream_t stream);
+/* Same, result written to device memory out_dev (one double); does not synchronise. */
+bl_status bl_reduce_async(const bl_multifab* mf, int32_t comp, bl_reduce_op op, double* out_dev,
+                          hipStream_t stream);
+
+/* ------------------------------------------------------------ launch tuning */
+
+/*
+ * Tile shape of the stencil kernels: zchunk = z planes per tile (1..1024),
+ * waves = 64-lane waves per workgroup (1..16), persist = workgroups per CU for
+ * the persistent grid (0: one workgroup per tile).  Applies to MultiFabs
+ * created afterwards and to bl_batch objects at their next rebuild.
+ */
+bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist);
+bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist);
+
+/* ------------------------------------------------------------------- batching */
+
+/*
+ * A set of independent heat problems advanced together: every bl_batch_step
+ * advances each member by one step with one fused launch per dtype over the
+ * concatenated tile lists.  Members may be added and removed between steps.
+ * u0/u1 are the member's ping-pong pair (same shape and dtype, nghost >= 1);
+ * its current state is u0 after an even number of its steps, u1 after an odd
+ * number (bl_batch_parity).  The MultiFabs must outlive their membership.
+ */
+bl_status bl_batch_create(bl_batch** out);
+bl_status bl_batch_add(bl_batch* b, bl_multifab* u0, bl_multifab* u1, double c, int32_t* member_id);
+bl_status bl_batch_remove(bl_batch* b, int32_t member_id);
+bl_status bl_batch_parity(const bl_batch* b, int32_t member_id, int32_t* steps_done);
+bl_status bl_batch_step(bl_batch* b, hipStream_t stream);
+void bl_batch_destroy(bl_batch* b);
+
+/* ------------------------------------------------------- metadata inspection */
+
+/*
+ * FillBoundary copy plan of a BoxArray for ghost width nghost: number of
+ * records, and if rec != NULL the records as 11 int32 each: {dst box, src box,
+ * lo[3], hi[3] of the destination ghost region (global indices), shift[3]},
+ * the source cell being destination + shift.  Every ghost cell that some box
+ * covers (after periodic wrap) lies in exactly one record.  Host metadata
+ * only (no device work); for tests and inspection.
+ */
+bl_status bl_fill_plan(const bl_boxarray* ba, int32_t nghost, int32_t* nrec, int32_t* rec);
+
+/*
+ * Face-source records of the fused stencil: for each box and face (2*axis +
+ * side, side 1 = high), the one-cell layer just outside the face split into
+ * rectangles, each read from one source box (src) at destination + shift; a
+ * part no box covers has src = the box itself and shift 0 (its own ghost
+ * cells).  12 int32 per record: {box, face, src, lo[3], hi[3], shift[3]}.
+ * Host metadata only.
+ */
+bl_status bl_face_plan(const bl_boxarray* ba, int32_t* nrec, int32_t* rec);
+
+/*
+ * Flattened tile list of the stencil kernels for a MultiFab of this shape
+ * under the current tile configuration: number of tiles and, if tiles != NULL,
+ * 7 int32 per tile {box, comp, plane_lo, plane_hi, z_lo, z_hi, vec}: lanes
+ * plane_lo..plane_hi-1 of the box's x-y plane (lane = x/vec + row*(x extent/vec),
+ * each lane vec consecutive x cells) over box-local z planes z_lo..z_hi-1.
+ * Host metadata only.
+ */
+bl_status bl_tile_list(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_dtype dtype, int32_t* ntiles,
+                       int32_t* tiles);
+
+/*
+ * Static partition of a tile list over nworkers, as the paper's tile-level
+ * threading shares the collapsed (grid, tile) loop (Sec. 3.3): worker w gets
+ * the contiguous range [first[w], first[w+1]) of near-equal length, the
+ * first (ntiles mod nworkers) workers one tile more.  first has nworkers+1
+ * entries.
+ */
+bl_status bl_static_partition(int32_t ntiles, int32_t nworkers, int32_t* first);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BOXTILE_H */

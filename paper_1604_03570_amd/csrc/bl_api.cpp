@@ -1,0 +1,671 @@
+// C interface of libboxtile: MultiFab handles, FillBoundary, heat step
+// (per-box, unfused batched and fused/graph forms), red-black Gauss-Seidel,
+// reductions, batching of independent problems and metadata inspection.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+
+#include "bl_internal.h"
+#include "bl_launch.h"
+
+namespace bl {
+
+bl_status hip_fail(int err, const char* what) {
+  return fail(BL_EHIP, "%s failed: %s", what, hipGetErrorString((hipError_t)err));
+}
+
+Plan::~Plan() {
+  (void)hipFree(dboxes);
+  (void)hipFree(dfacerecs);
+  (void)hipFree(dtiles);
+  (void)hipFree(dfillrecs);
+  (void)hipFree(dfillchunks);
+}
+
+template <typename T>
+static bl_status upload(T** dst, const std::vector<T>& src, const char* what) {
+  if (src.empty()) return BL_OK;
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * src.size());
+  if (e != hipSuccess) return hip_fail(e, what);
+  e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, what);
+  return BL_OK;
+}
+
+bl_status upload_plan(Plan& p) {
+  if (p.uploaded) return BL_OK;
+  bl_status st;
+  if ((st = upload(&p.dboxes, p.hboxes, "hipMalloc/hipMemcpy(boxes)")) != BL_OK) return st;
+  if ((st = upload(&p.dfacerecs, p.hfacerecs, "hipMalloc/hipMemcpy(face records)")) != BL_OK) return st;
+  if ((st = upload(&p.dtiles, p.htiles, "hipMalloc/hipMemcpy(tiles)")) != BL_OK) return st;
+  if ((st = upload(&p.dfillrecs, p.hfillrecs, "hipMalloc/hipMemcpy(fill records)")) != BL_OK) return st;
+  if ((st = upload(&p.dfillchunks, p.hfillchunks, "hipMalloc/hipMemcpy(fill chunks)")) != BL_OK) return st;
+  p.uploaded = true;
+  return BL_OK;
+}
+
+// Plans are shared by every MultiFab of one shape and tile configuration.
+static std::mutex g_plan_mu;
+static std::map<std::tuple<uint64_t, int, int, int, int, int>, std::weak_ptr<Plan>> g_plans;
+
+static bl_status get_plan(const bl_boxarray* ba, int ncomp, int ng, int dtype, bool to_device,
+                          std::shared_ptr<Plan>* out) {
+  const TileConfig cfg = tile_config();
+  auto key = std::make_tuple(ba->uid, ncomp, ng, dtype, cfg.zchunk, cfg.waves);
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  auto it = g_plans.find(key);
+  std::shared_ptr<Plan> p;
+  if (it != g_plans.end()) p = it->second.lock();
+  if (!p) {
+    bl_status st = build_plan(ba, ncomp, ng, dtype, &p);
+    if (st != BL_OK) return st;
+    g_plans[key] = p;
+  }
+  if (to_device) {
+    bl_status st = upload_plan(*p);
+    if (st != BL_OK) return st;
+  }
+  *out = p;
+  return BL_OK;
+}
+
+static int block_of(const Plan& p) { return 64 * p.cfg.waves; }
+
+static int persistent_grid(int persist) { return persist > 0 ? device_cu_count() * persist : 0; }
+
+static bl_status same_shape(const bl_multifab* a, const bl_multifab* b) {
+  if (!a || !b) return fail(BL_EINVAL, "NULL MultiFab");
+  if (a->plan->dtype != b->plan->dtype) return fail(BL_EDTYPE, "MultiFabs differ in dtype");
+  if (a->plan->ba_uid != b->plan->ba_uid || a->plan->ncomp != b->plan->ncomp || a->plan->ng != b->plan->ng)
+    return fail(BL_ESHAPE, "MultiFabs differ in BoxArray, ncomp or nghost");
+  if (a->plan.get() != b->plan.get())
+    return fail(BL_ESHAPE, "MultiFabs were created under different tile configurations");
+  return BL_OK;
+}
+
+static bl_status ensure_scratch(bl_multifab* mf, size_t ndev, size_t nhost) {
+  if (mf->nscratch < ndev) {
+    (void)hipFree(mf->dscratch);
+    mf->dscratch = nullptr;
+    mf->nscratch = 0;
+    BL_HIP(hipMalloc((void**)&mf->dscratch, ndev * sizeof(double)));
+    mf->nscratch = ndev;
+  }
+  if (mf->nhres < nhost) {
+    (void)hipHostFree(mf->hres);
+    mf->hres = nullptr;
+    mf->nhres = 0;
+    BL_HIP(hipHostMalloc((void**)&mf->hres, nhost * sizeof(double), hipHostMallocDefault));
+    mf->nhres = nhost;
+  }
+  return BL_OK;
+}
+
+// Stream used only to capture graphs (default priority, non-blocking).
+static hipStream_t capture_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  streams[dev] = s;
+  return s;
+}
+
+struct GraphKey {
+  const bl_multifab* u0;
+  const bl_multifab* u1;
+  void* d0;
+  void* d1;
+  int nsteps;
+  uint64_t cbits;
+  int persist;
+  int device;
+  bool operator==(const GraphKey& o) const {
+    return u0 == o.u0 && u1 == o.u1 && d0 == o.d0 && d1 == o.d1 && nsteps == o.nsteps && cbits == o.cbits &&
+           persist == o.persist && device == o.device;
+  }
+};
+static std::mutex g_graph_mu;
+static std::vector<std::pair<GraphKey, hipGraphExec_t>> g_graphs;
+
+static void forget_graphs(const bl_multifab* mf) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (size_t i = 0; i < g_graphs.size();) {
+    if (g_graphs[i].first.u0 == mf || g_graphs[i].first.u1 == mf) {
+      (void)hipGraphExecDestroy(g_graphs[i].second);
+      g_graphs.erase(g_graphs.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+}  // namespace bl
+
+using namespace bl;
+
+bl_multifab::~bl_multifab() {
+  forget_graphs(this);
+  (void)hipFree(dscratch);
+  (void)hipHostFree(hres);
+}
+
+extern "C" {
+
+bl_status bl_multifab_create(const bl_boxarray* ba, const bl_distmap* dm, int32_t ncomp, int32_t nghost,
+                             bl_dtype dtype, void* dev_ptr, size_t bytes, bl_multifab** out) {
+  clear_error();
+  if (!ba || !out) return fail(BL_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (dm && dm->ba_uid != ba->uid) return fail(BL_ESHAPE, "DistributionMapping belongs to another BoxArray");
+  if (ncomp < 1 || nghost < 0) return fail(BL_EINVAL, "need ncomp >= 1 and nghost >= 0");
+  if (dtype != BL_F64 && dtype != BL_F32) return fail(BL_EDTYPE, "unknown dtype %d", (int)dtype);
+  for (int d = 0; d < 3; ++d)
+    if (ba->periodic[d] && nghost > ba->domain.len(d))
+      return fail(BL_EINVAL, "nghost %d exceeds the periodic extent %d of axis %d", nghost, ba->domain.len(d), d);
+  size_t need = 0;
+  bl_status st = bl_multifab_bytes(ba, ncomp, nghost, dtype, &need);
+  if (st != BL_OK) return st;
+  if (!dev_ptr) return fail(BL_EINVAL, "NULL device pointer");
+  if (((uintptr_t)dev_ptr) % 256 != 0) return fail(BL_EINVAL, "device pointer is not 256-byte aligned");
+  if (bytes < need) return fail(BL_ENOMEM, "buffer of %zu bytes, MultiFab needs %zu", bytes, need);
+  std::shared_ptr<Plan> plan;
+  if ((st = get_plan(ba, ncomp, nghost, dtype, true, &plan)) != BL_OK) return st;
+  bl_multifab* mf = new (std::nothrow) bl_multifab;
+  if (!mf) return fail(BL_ENOMEM, "host allocation");
+  mf->plan = plan;
+  mf->data = dev_ptr;
+  mf->bytes = bytes;
+  *out = mf;
+  return BL_OK;
+}
+
+bl_status bl_multifab_layout(const bl_multifab* mf, int32_t box, bl_box* grown, size_t* offset_elems,
+                             int64_t stride[4]) {
+  clear_error();
+  if (!mf) return fail(BL_EINVAL, "NULL MultiFab");
+  const Plan& p = *mf->plan;
+  if (box < 0 || box >= (int)p.fabs.size()) return fail(BL_EINVAL, "box %d out of range", box);
+  const FabGeom& f = p.fabs[box];
+  if (grown) *grown = to_c(f.grown);
+  if (offset_elems) *offset_elems = (size_t)f.off_grown;
+  if (stride) {
+    stride[0] = 1;
+    stride[1] = f.sy;
+    stride[2] = f.sz;
+    stride[3] = f.sc;
+  }
+  return BL_OK;
+}
+
+bl_status bl_multifab_info(const bl_multifab* mf, int32_t* nboxes, int32_t* ncomp, int32_t* nghost, int32_t* dtype) {
+  clear_error();
+  if (!mf) return fail(BL_EINVAL, "NULL MultiFab");
+  if (nboxes) *nboxes = (int32_t)mf->plan->fabs.size();
+  if (ncomp) *ncomp = mf->plan->ncomp;
+  if (nghost) *nghost = mf->plan->ng;
+  if (dtype) *dtype = mf->plan->dtype;
+  return BL_OK;
+}
+
+void bl_multifab_destroy(bl_multifab* mf) { delete mf; }
+
+bl_status bl_multifab_copy_global(bl_multifab* mf, int32_t scomp, int32_t ncomp, void* global_dev, int32_t to_global,
+                                  hipStream_t stream) {
+  clear_error();
+  if (!mf || !global_dev) return fail(BL_EINVAL, "NULL argument");
+  const Plan& p = *mf->plan;
+  if (scomp < 0 || ncomp < 1 || scomp + ncomp > p.ncomp) return fail(BL_EINVAL, "component range out of bounds");
+  BL_HIP(launch_copy_global(p, mf->data, global_dev, scomp, ncomp, to_global, block_of(p), stream));
+  return BL_OK;
+}
+
+bl_status bl_multifab_set_val(bl_multifab* mf, double val, int32_t scomp, int32_t ncomp, int32_t with_ghosts,
+                              hipStream_t stream) {
+  clear_error();
+  if (!mf) return fail(BL_EINVAL, "NULL MultiFab");
+  const Plan& p = *mf->plan;
+  if (scomp < 0 || ncomp < 1 || scomp + ncomp > p.ncomp) return fail(BL_EINVAL, "component range out of bounds");
+  BL_HIP(launch_set_val(p, mf->data, val, scomp, ncomp, with_ghosts, block_of(p), stream));
+  return BL_OK;
+}
+
+bl_status bl_fill_boundary(bl_multifab* mf, int32_t scomp, int32_t ncomp, hipStream_t stream) {
+  clear_error();
+  if (!mf) return fail(BL_EINVAL, "NULL MultiFab");
+  const Plan& p = *mf->plan;
+  if (scomp < 0 || ncomp < 1 || scomp + ncomp > p.ncomp) return fail(BL_EINVAL, "component range out of bounds");
+  BL_HIP(launch_fill(p, mf->data, scomp, ncomp, stream));
+  return BL_OK;
+}
+
+static bl_status check_heat(bl_multifab* a, bl_multifab* b) {
+  bl_status st = same_shape(a, b);
+  if (st != BL_OK) return st;
+  if (a->plan->ng < 1) return fail(BL_EINVAL, "the stencil needs nghost >= 1");
+  if (a->data == b->data) return fail(BL_EINVAL, "u_old and u_new share storage");
+  return BL_OK;
+}
+
+static DevMember member_of(bl_multifab* a, bl_multifab* b, double c) {
+  DevMember m;
+  std::memset(&m, 0, sizeof m);
+  m.a = a->data;
+  m.b = b->data;
+  m.c = c;
+  m.flip_offset = 0;
+  return m;
+}
+
+bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t fill_first, hipStream_t stream) {
+  clear_error();
+  bl_status st = check_heat(u_old, u_new);
+  if (st != BL_OK) return st;
+  const Plan& p = *u_old->plan;
+  if (fill_first) BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream));
+  HeatArgs a{};
+  a.boxes = p.dboxes;
+  a.recs = p.dfacerecs;
+  a.m0 = member_of(u_old, u_new, c);
+  a.members = nullptr;
+  a.flip = 0;
+  for (size_t b = 0; b < p.hboxes.size(); ++b) {  // one launch per box
+    a.tiles = p.dtiles + p.box_tile_start[b];
+    a.ntiles = p.box_tile_start[b + 1] - p.box_tile_start[b];
+    BL_HIP(launch_heat(p.dtype, p.vec, false, a, 0, block_of(p), stream));
+  }
+  return BL_OK;
+}
+
+bl_status bl_heat_step_unfused(bl_multifab* u_old, bl_multifab* u_new, double c, hipStream_t stream) {
+  clear_error();
+  bl_status st = check_heat(u_old, u_new);
+  if (st != BL_OK) return st;
+  const Plan& p = *u_old->plan;
+  BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream));
+  HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u_old, u_new, c), nullptr, 0};
+  BL_HIP(launch_heat(p.dtype, p.vec, false, a, persistent_grid(tile_config().persist), block_of(p), stream));
+  return BL_OK;
+}
+
+bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream_t stream) {
+  clear_error();
+  if (!u) return fail(BL_EINVAL, "NULL MultiFab array");
+  bl_status st = check_heat(u[0], u[1]);
+  if (st != BL_OK) return st;
+  if (nsteps < 0) return fail(BL_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return BL_OK;
+  const Plan& p = *u[0]->plan;
+  const int persist = tile_config().persist;
+  int dev = 0;
+  BL_HIP(hipGetDevice(&dev));
+  uint64_t cbits;
+  std::memcpy(&cbits, &c, sizeof cbits);
+  GraphKey key{u[0], u[1], u[0]->data, u[1]->data, nsteps, cbits, persist, dev};
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto& e : g_graphs)
+      if (e.first == key) exec = e.second;
+  }
+  if (!exec) {
+    hipStream_t cs = capture_stream();
+    if (!cs) return fail(BL_EHIP, "could not create the capture stream");
+    HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u[0], u[1], c), nullptr, 0};
+    BL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (int s = 0; s < nsteps && le == hipSuccess; ++s) {
+      a.flip = s & 1;
+      le = launch_heat(p.dtype, p.vec, true, a, persistent_grid(persist), block_of(p), cs);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(le, "kernel launch during graph capture");
+    }
+    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    g_graphs.push_back({key, exec});
+  }
+  BL_HIP(hipGraphLaunch(exec, stream));
+  return BL_OK;
+}
+
+bl_status bl_reduce_async(const bl_multifab* cmf, int32_t comp, bl_reduce_op op, double* out_dev, hipStream_t stream) {
+  clear_error();
+  bl_multifab* mf = const_cast<bl_multifab*>(cmf);
+  if (!mf || !out_dev) return fail(BL_EINVAL, "NULL argument");
+  const Plan& p = *mf->plan;
+  if (comp < 0 || comp >= p.ncomp) return fail(BL_EINVAL, "component %d out of range", comp);
+  if ((int)op < 0 || (int)op > 5) return fail(BL_EINVAL, "unknown reduction %d", (int)op);
+  bl_status st = ensure_scratch(mf, p.htiles.size() + 8, 8);
+  if (st != BL_OK) return st;
+  BL_HIP(launch_reduce(p, mf->data, comp, (int)op, mf->dscratch, out_dev, block_of(p), stream));
+  return BL_OK;
+}
+
+bl_status bl_reduce(const bl_multifab* cmf, int32_t comp, bl_reduce_op op, double* out_host, hipStream_t stream) {
+  clear_error();
+  bl_multifab* mf = const_cast<bl_multifab*>(cmf);
+  if (!mf || !out_host) return fail(BL_EINVAL, "NULL argument");
+  const Plan& p = *mf->plan;
+  bl_status st = ensure_scratch(mf, p.htiles.size() + 8, 8);
+  if (st != BL_OK) return st;
+  double* dout = mf->dscratch + p.htiles.size();
+  if ((st = bl_reduce_async(mf, comp, op, dout, stream)) != BL_OK) return st;
+  BL_HIP(hipMemcpyAsync(mf->hres, dout, sizeof(double), hipMemcpyDeviceToHost, stream));
+  BL_HIP(hipStreamSynchronize(stream));
+  *out_host = mf->hres[0];
+  return BL_OK;
+}
+
+static bl_status check_gsrb(bl_multifab* phi, const bl_multifab* f) {
+  bl_status st = same_shape(phi, f);
+  if (st != BL_OK) return st;
+  const Plan& p = *phi->plan;
+  if (p.ncomp != 1) return fail(BL_EINVAL, "GSRB acts on single-component MultiFabs");
+  if (p.ng < 1) return fail(BL_EINVAL, "the stencil needs nghost >= 1");
+  for (int d = 0; d < 3; ++d)
+    if (p.periodic[d] && p.domain.len(d) % 2)
+      return fail(BL_EINVAL, "periodic axis %d has odd extent %d: red-black colouring breaks across the wrap", d,
+                  p.domain.len(d));
+  if (phi->data == f->data) return fail(BL_EINVAL, "phi and f share storage");
+  return BL_OK;
+}
+
+bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, double* out_host, hipStream_t stream) {
+  clear_error();
+  bl_status st = check_gsrb(phi, f);
+  if (st != BL_OK) return st;
+  if (!out_host) return fail(BL_EINVAL, "NULL output");
+  const Plan& p = *phi->plan;
+  if ((st = ensure_scratch(phi, p.htiles.size() + 8, 8)) != BL_OK) return st;
+  double* dout = phi->dscratch + p.htiles.size();
+  BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
+  BL_HIP(launch_residual(p, phi->data, f->data, h2, phi->dscratch, dout, block_of(p), stream));
+  BL_HIP(hipMemcpyAsync(phi->hres, dout, sizeof(double), hipMemcpyDeviceToHost, stream));
+  BL_HIP(hipStreamSynchronize(stream));
+  *out_host = phi->hres[0];
+  return BL_OK;
+}
+
+bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int32_t nsweeps, double* resnorm_host,
+                         hipStream_t stream) {
+  clear_error();
+  bl_status st = check_gsrb(phi, f);
+  if (st != BL_OK) return st;
+  if (nsweeps < 0) return fail(BL_EINVAL, "nsweeps < 0");
+  const Plan& p = *phi->plan;
+  const size_t nt = p.htiles.size();
+  if (resnorm_host && (st = ensure_scratch(phi, nt + (size_t)nsweeps + 8, (size_t)nsweeps + 8)) != BL_OK) return st;
+  for (int s = 0; s < nsweeps; ++s) {
+    for (int color = 0; color < 2; ++color) {
+      BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
+      BL_HIP(launch_gsrb(p, phi->data, f->data, h2, color, block_of(p), stream));
+    }
+    if (resnorm_host) {
+      BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
+      BL_HIP(launch_residual(p, phi->data, f->data, h2, phi->dscratch, phi->dscratch + nt + s, block_of(p), stream));
+    }
+  }
+  if (resnorm_host && nsweeps > 0) {
+    BL_HIP(hipMemcpyAsync(phi->hres, phi->dscratch + nt, sizeof(double) * nsweeps, hipMemcpyDeviceToHost, stream));
+    BL_HIP(hipStreamSynchronize(stream));
+    std::memcpy(resnorm_host, phi->hres, sizeof(double) * nsweeps);
+  }
+  return BL_OK;
+}
+
+bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist) {
+  clear_error();
+  if (zchunk < 1 || zchunk > 1024 || waves < 1 || waves > 16 || persist < 0 || persist > 64)
+    return fail(BL_EINVAL, "need 1 <= zchunk <= 1024, 1 <= waves <= 16, 0 <= persist <= 64");
+  TileConfig& c = tile_config();
+  c.zchunk = zchunk;
+  c.waves = waves;
+  c.persist = persist;
+  return BL_OK;
+}
+
+bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist) {
+  clear_error();
+  const TileConfig& c = tile_config();
+  if (zchunk) *zchunk = c.zchunk;
+  if (waves) *waves = c.waves;
+  if (persist) *persist = c.persist;
+  return BL_OK;
+}
+
+bl_status bl_fill_plan(const bl_boxarray* cba, int32_t nghost, int32_t* nrec, int32_t* rec) {
+  clear_error();
+  if (!cba || !nrec) return fail(BL_EINVAL, "NULL argument");
+  if (nghost < 0) return fail(BL_EINVAL, "nghost < 0");
+  const auto plan = fill_plan(const_cast<bl_boxarray*>(cba), nghost);
+  const auto& recs = *plan;
+  *nrec = (int32_t)recs.size();
+  if (rec)
+    for (size_t i = 0; i < recs.size(); ++i) {
+      int32_t* r = rec + 11 * i;
+      r[0] = recs[i].dst;
+      r[1] = recs[i].src;
+      for (int d = 0; d < 3; ++d) {
+        r[2 + d] = recs[i].region.lo[d];
+        r[5 + d] = recs[i].region.hi[d];
+        r[8 + d] = recs[i].shift[d];
+      }
+    }
+  return BL_OK;
+}
+
+bl_status bl_face_plan(const bl_boxarray* cba, int32_t* nrec, int32_t* rec) {
+  clear_error();
+  if (!cba || !nrec) return fail(BL_EINVAL, "NULL argument");
+  const auto plan = face_plan(const_cast<bl_boxarray*>(cba), 1);
+  const auto& recs = *plan;
+  *nrec = (int32_t)recs.size();
+  if (rec)
+    for (size_t i = 0; i < recs.size(); ++i) {
+      int32_t* r = rec + 12 * i;
+      r[0] = recs[i].box;
+      r[1] = recs[i].face;
+      r[2] = recs[i].src;
+      for (int d = 0; d < 3; ++d) {
+        r[3 + d] = recs[i].region.lo[d];
+        r[6 + d] = recs[i].region.hi[d];
+        r[9 + d] = recs[i].shift[d];
+      }
+    }
+  return BL_OK;
+}
+
+bl_status bl_tile_list(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_dtype dtype, int32_t* ntiles,
+                       int32_t* tiles) {
+  clear_error();
+  if (!ba || !ntiles) return fail(BL_EINVAL, "NULL argument");
+  if (ncomp < 1 || nghost < 0) return fail(BL_EINVAL, "need ncomp >= 1 and nghost >= 0");
+  if (dtype != BL_F64 && dtype != BL_F32) return fail(BL_EDTYPE, "unknown dtype %d", (int)dtype);
+  std::shared_ptr<Plan> plan;
+  bl_status st = get_plan(ba, ncomp, nghost, dtype, false, &plan);
+  if (st != BL_OK) return st;
+  const auto& t = plan->htiles;
+  *ntiles = (int32_t)t.size();
+  if (tiles)
+    for (size_t i = 0; i < t.size(); ++i) {
+      int32_t* r = tiles + 7 * i;
+      r[0] = t[i].box;
+      r[1] = t[i].comp;
+      r[2] = t[i].l0;
+      r[3] = t[i].l0 + t[i].nl;
+      r[4] = t[i].z0;
+      r[5] = t[i].z1;
+      r[6] = plan->vec;
+    }
+  return BL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batching
+struct bl_batch {
+  struct Member {
+    bl_multifab* u0;
+    bl_multifab* u1;
+    double c;
+    int64_t joined;  // tick of its first step
+    int id;
+  };
+  struct Group {
+    int dtype = 0, vec = 1;
+    std::vector<int> members;  // indices into mems
+    DevBox* dboxes = nullptr;
+    DevFaceRec* drecs = nullptr;
+    DevTile* dtiles = nullptr;
+    DevMember* dmembers = nullptr;
+    int ntiles = 0;
+  };
+  std::vector<Member> mems;
+  std::vector<Group> groups;
+  int next_id = 0;
+  int64_t tick = 0;
+  bool dirty = true;
+  TileConfig cfg;
+
+  void free_groups() {
+    for (auto& g : groups) {
+      (void)hipFree(g.dboxes);
+      (void)hipFree(g.drecs);
+      (void)hipFree(g.dtiles);
+      (void)hipFree(g.dmembers);
+    }
+    groups.clear();
+  }
+  ~bl_batch() { free_groups(); }
+};
+
+static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
+  BL_HIP(hipStreamSynchronize(stream));  // earlier ticks may still read the old tables
+  b->free_groups();
+  b->cfg = tile_config();
+  for (size_t i = 0; i < b->mems.size(); ++i) {
+    const Plan& p = *b->mems[i].u0->plan;
+    bl_batch::Group* g = nullptr;
+    for (auto& x : b->groups)
+      if (x.dtype == p.dtype && x.vec == p.vec) g = &x;
+    if (!g) {
+      b->groups.emplace_back();
+      g = &b->groups.back();
+      g->dtype = p.dtype;
+      g->vec = p.vec;
+    }
+    g->members.push_back((int)i);
+  }
+  for (auto& g : b->groups) {
+    std::vector<DevBox> boxes;
+    std::vector<DevFaceRec> recs;
+    std::vector<DevTile> tiles;
+    std::vector<DevMember> mems;
+    for (size_t k = 0; k < g.members.size(); ++k) {
+      const bl_batch::Member& m = b->mems[g.members[k]];
+      const Plan& p = *m.u0->plan;
+      const int box_base = (int)boxes.size(), rec_base = (int)recs.size();
+      for (DevBox B : p.hboxes) {
+        for (int f = 0; f < 6; ++f) B.face_start[f] += rec_base;
+        boxes.push_back(B);
+      }
+      recs.insert(recs.end(), p.hfacerecs.begin(), p.hfacerecs.end());
+      build_tiles(p, b->cfg, (int)k, box_base, tiles, nullptr);
+      DevMember dm;
+      std::memset(&dm, 0, sizeof dm);
+      dm.a = m.u0->data;
+      dm.b = m.u1->data;
+      dm.c = m.c;
+      dm.flip_offset = (int32_t)(m.joined & 1);
+      mems.push_back(dm);
+    }
+    bl_status st;
+    if ((st = upload(&g.dboxes, boxes, "batch boxes")) != BL_OK) return st;
+    if ((st = upload(&g.drecs, recs, "batch face records")) != BL_OK) return st;
+    if ((st = upload(&g.dtiles, tiles, "batch tiles")) != BL_OK) return st;
+    if ((st = upload(&g.dmembers, mems, "batch members")) != BL_OK) return st;
+    g.ntiles = (int)tiles.size();
+  }
+  b->dirty = false;
+  return BL_OK;
+}
+
+extern "C" {
+
+bl_status bl_batch_create(bl_batch** out) {
+  clear_error();
+  if (!out) return fail(BL_EINVAL, "NULL argument");
+  *out = new (std::nothrow) bl_batch;
+  if (!*out) return fail(BL_ENOMEM, "host allocation");
+  return BL_OK;
+}
+
+bl_status bl_batch_add(bl_batch* b, bl_multifab* u0, bl_multifab* u1, double c, int32_t* member_id) {
+  clear_error();
+  if (!b || !member_id) return fail(BL_EINVAL, "NULL argument");
+  bl_status st = check_heat(u0, u1);
+  if (st != BL_OK) return st;
+  bl_batch::Member m{u0, u1, c, b->tick, b->next_id++};
+  b->mems.push_back(m);
+  b->dirty = true;
+  *member_id = m.id;
+  return BL_OK;
+}
+
+bl_status bl_batch_remove(bl_batch* b, int32_t member_id) {
+  clear_error();
+  if (!b) return fail(BL_EINVAL, "NULL batch");
+  for (size_t i = 0; i < b->mems.size(); ++i)
+    if (b->mems[i].id == member_id) {
+      b->mems.erase(b->mems.begin() + i);
+      b->dirty = true;
+      return BL_OK;
+    }
+  return fail(BL_EINVAL, "no member %d", member_id);
+}
+
+bl_status bl_batch_parity(const bl_batch* b, int32_t member_id, int32_t* steps_done) {
+  clear_error();
+  if (!b || !steps_done) return fail(BL_EINVAL, "NULL argument");
+  for (const auto& m : b->mems)
+    if (m.id == member_id) {
+      *steps_done = (int32_t)(b->tick - m.joined);
+      return BL_OK;
+    }
+  return fail(BL_EINVAL, "no member %d", member_id);
+}
+
+bl_status bl_batch_step(bl_batch* b, hipStream_t stream) {
+  clear_error();
+  if (!b) return fail(BL_EINVAL, "NULL batch");
+  bl_status st;
+  if (b->dirty && (st = batch_rebuild(b, stream)) != BL_OK) return st;
+  for (auto& g : b->groups) {
+    HeatArgs a{g.dtiles, g.ntiles, g.dboxes, g.drecs, DevMember{}, g.dmembers, (int)(b->tick & 1)};
+    BL_HIP(launch_heat(g.dtype, g.vec, true, a, persistent_grid(b->cfg.persist), 64 * b->cfg.waves, stream));
+  }
+  b->tick++;
+  return BL_OK;
+}
+
+void bl_batch_destroy(bl_batch* b) { delete b; }
+
+}  // extern "C"

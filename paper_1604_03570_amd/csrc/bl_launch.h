@@ -1,0 +1,48 @@
+// Host-side launchers of the gfx950 kernels (bl_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bl_internal.h"
+
+namespace bl {
+
+enum ReduceOp { R_SUM = 0, R_MAX = 1, R_MIN = 2, R_NORM0 = 3, R_NORM1 = 4, R_NORM2 = 5 };
+
+struct HeatArgs {
+  const DevTile* tiles;        // first tile of the launch
+  int ntiles;
+  const DevBox* boxes;
+  const DevFaceRec* recs;
+  DevMember m0;                // used when members == nullptr
+  const DevMember* members;
+  int flip;
+};
+
+// Stencil over `ntiles` tiles.  fused: tiles at box faces read neighbour boxes
+// through the face records; otherwise they read the FAB's own (filled) ghosts.
+// grid == 0: one workgroup per tile; else `grid` persistent workgroups each
+// taking a contiguous range of tiles.
+hipError_t launch_heat(int dtype, int vec, bool fused, const HeatArgs& a, int grid, int block, hipStream_t s);
+
+hipError_t launch_fill(const Plan& p, void* data, int scomp, int ncomp, hipStream_t s);
+
+hipError_t launch_copy_global(const Plan& p, void* data, void* global, int scomp, int ncomp, int to_global,
+                              int block, hipStream_t s);
+
+hipError_t launch_set_val(const Plan& p, void* data, double val, int scomp, int ncomp, int with_ghosts, int block,
+                          hipStream_t s);
+
+// partials must hold p.htiles.size() doubles; the result lands in *out (device).
+hipError_t launch_reduce(const Plan& p, const void* data, int comp, int op, double* partials, double* out, int block,
+                         hipStream_t s);
+
+hipError_t launch_gsrb(const Plan& p, void* phi, const void* f, double h2, int color, int block, hipStream_t s);
+
+// ||f + L_h phi||_2 in FP64 into *out (device); reads phi's ghosts (fill first).
+hipError_t launch_residual(const Plan& p, const void* phi, const void* f, double h2, double* partials, double* out,
+                           int block, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace bl

@@ -1,0 +1,206 @@
+"""Host-side logic of the library (CPU only, no kernels run): exported symbols,
+BoxArray validation, box chops against the shared input generators, the
+FillBoundary copy plan against the oracle's fill, the face-source records,
+tile-list coverage and the static tile partition of the paper's worked example."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1604_03570_amd import inputs as I
+
+bt = pytest.importorskip("paper_1604_03570_amd.boxtile", reason="libboxtile.so not built")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_library_exports_every_declared_function():
+    names = bt.header_functions()
+    assert len(names) >= 30
+    missing = [n for n in names if not hasattr(bt.lib(), n)]
+    assert not missing, missing
+
+
+def test_boxarray_validation_errors():
+    dom = (0, 0, 0, 7, 7, 7)
+    with pytest.raises(bt.BoxtileError) as e:
+        bt.BoxArray.from_boxes([(0, 0, 0, 3, 3, 3), (3, 3, 3, 5, 5, 5)], dom)
+    assert e.value.code == bt.BL_EOVERLAP
+    with pytest.raises(bt.BoxtileError) as e:
+        bt.BoxArray.from_boxes([(0, 0, 0, 3, 3, 8)], dom)
+    assert e.value.code == bt.BL_EDOMAIN
+    with pytest.raises(bt.BoxtileError) as e:
+        bt.BoxArray.from_boxes([(2, 0, 0, 1, 3, 3)], dom)
+    assert e.value.code == bt.BL_EINVAL
+    with pytest.raises(bt.BoxtileError) as e:
+        bt.BoxArray.chop_random(dom, min_edge=4, max_edge=6)
+    assert e.value.code == bt.BL_EINVAL
+    with pytest.raises(bt.BoxtileError) as e:
+        bt.DistributionMapping(bt.BoxArray.chop(dom, 4), ndevices=2)
+    assert e.value.code == bt.BL_EINVAL
+    ba = bt.BoxArray.from_boxes([(0, 0, 0, 3, 3, 3), (4, 4, 4, 7, 7, 7)], dom)  # non-covering is fine
+    assert len(ba) == 2
+
+
+@pytest.mark.parametrize("n,edge", [(64, 32), (96, 64), ((40, 24, 16), (16, 8, 16)), (256, 64)])
+def test_regular_chop_matches_generator(n, edge):
+    dom = I.domain_box(n)
+    assert np.array_equal(bt.BoxArray.chop(dom, edge).boxes(), I.regular_chop(dom, edge))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 17])
+def test_random_chop_matches_generator(seed):
+    dom = I.domain_box(512)
+    lib_boxes = bt.BoxArray.chop_random(dom, 16, 128, 8, seed).boxes()
+    assert np.array_equal(lib_boxes, I.random_chop(dom, 16, 128, 8, seed))
+    e = lib_boxes[:, 3:] - lib_boxes[:, :3] + 1
+    assert e.min() >= 16 and e.max() <= 128 and np.all(e % 8 == 0)
+    assert int(np.prod(e, axis=1).sum()) == 512 ** 3
+
+
+def _fabs_from_plan(boxes, shape, periodic, ng, plan):
+    """Per-box grown arrays with unique valid values, ghosts set by applying the plan records."""
+    nx, ny, nz = shape
+    g = np.arange(nx * ny * nz, dtype=np.float64).reshape(nz, ny, nx) + 0.5
+    fabs = []
+    for bx in boxes:
+        a = np.full((bx[5] - bx[2] + 1 + 2 * ng, bx[4] - bx[1] + 1 + 2 * ng, bx[3] - bx[0] + 1 + 2 * ng), -1e300)
+        a[ng:-ng, ng:-ng, ng:-ng] = g[bx[2]:bx[5] + 1, bx[1]:bx[4] + 1, bx[0]:bx[3] + 1]
+        fabs.append(a)
+    hits = [np.zeros(f.shape, dtype=np.int32) for f in fabs]
+    for r in plan:
+        dst, src, lo, hi, sh = r[0], r[1], r[2:5], r[5:8], r[8:11]
+        db, sb = boxes[dst], boxes[src]
+        dsl = tuple(slice(lo[d] - db[d] + ng, hi[d] - db[d] + ng + 1) for d in (2, 1, 0))
+        ssl = tuple(slice(lo[d] + sh[d] - sb[d] + ng, hi[d] + sh[d] - sb[d] + ng + 1) for d in (2, 1, 0))
+        fabs[dst][dsl] = fabs[src][ssl]
+        hits[dst][dsl] += 1
+    return g, fabs, hits
+
+
+@pytest.mark.parametrize("case", range(16))
+def test_fill_plan_matches_oracle_fill(case):
+    rng = np.random.default_rng(500 + case)
+    shape = [(8, 6, 4), (5, 5, 5), (12, 8, 10), (7, 4, 6)][case % 4]
+    ng = 1 + case % 2
+    periodic = tuple(int(v) for v in rng.integers(0, 2, 3))
+    boxes = I.random_chop(I.domain_box(shape), min_edge=1 + case % 2, max_edge=4 + case % 3, align=1, seed=case)
+    if case % 3 == 2 and len(boxes) > 2:  # non-covering
+        boxes = boxes[np.sort(rng.permutation(len(boxes))[: max(1, len(boxes) * 2 // 3)])]
+    if any(periodic[d] and ng > shape[d] for d in range(3)):
+        pytest.skip("ghost width above a periodic extent")
+    ba = bt.BoxArray.from_boxes(boxes, I.domain_box(shape), periodic)
+    g, fabs, hits = _fabs_from_plan(boxes, shape, periodic, ng, ba.fill_plan(ng))
+    m = O.OracleMultiFab(boxes, I.domain_box(shape), periodic, 1, ng)
+    m.data[...] = -1e300
+    m.load_global(g[None])
+    m.fill_boundary()
+    for b in range(len(boxes)):
+        assert np.array_equal(fabs[b], m.fab(b)[0]), b
+        assert hits[b].max() <= 1  # no ghost cell written twice
+        inner = hits[b][ng:-ng, ng:-ng, ng:-ng]
+        assert inner.max() == 0  # valid cells never written
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_face_plan_partitions_every_face_and_matches_wrap(case):
+    rng = np.random.default_rng(900 + case)
+    shape = [(8, 6, 4), (12, 8, 10), (9, 7, 5)][case % 3]
+    periodic = tuple(int(v) for v in rng.integers(0, 2, 3))
+    boxes = I.random_chop(I.domain_box(shape), min_edge=1, max_edge=4, align=1, seed=40 + case)
+    if case % 2 and len(boxes) > 2:
+        boxes = boxes[np.sort(rng.permutation(len(boxes))[: len(boxes) // 2])]
+    ba = bt.BoxArray.from_boxes(boxes, I.domain_box(shape), periodic)
+    recs = ba.face_plan()
+    N = shape
+    owner = {}
+    for b, bx in enumerate(boxes):
+        for k in range(bx[2], bx[5] + 1):
+            for j in range(bx[1], bx[4] + 1):
+                for i in range(bx[0], bx[3] + 1):
+                    owner[(i, j, k)] = b
+    for b, bx in enumerate(boxes):
+        for face in range(6):
+            a, side = divmod(face, 2)
+            layer = list(bx)
+            layer[a] = layer[3 + a] = bx[3 + a] + 1 if side else bx[a] - 1
+            count = {}
+            for r in recs[(recs[:, 0] == b) & (recs[:, 1] == face)]:
+                src, lo, hi, sh = r[2], r[3:6], r[6:9], r[9:12]
+                for k in range(lo[2], hi[2] + 1):
+                    for j in range(lo[1], hi[1] + 1):
+                        for i in range(lo[0], hi[0] + 1):
+                            p = (i, j, k)
+                            count[p] = count.get(p, 0) + 1
+                            q = [p[d] % N[d] if periodic[d] else p[d] for d in range(3)]
+                            inside = all(0 <= q[d] < N[d] for d in range(3))
+                            want = owner.get(tuple(q)) if inside else None
+                            if want is None:
+                                assert src == b and tuple(sh) == (0, 0, 0)
+                            else:
+                                assert src == want
+                                assert tuple(p[d] + sh[d] for d in range(3)) == tuple(q)
+            cells = {(i, j, k) for k in range(layer[2], layer[5] + 1) for j in range(layer[1], layer[4] + 1)
+                     for i in range(layer[0], layer[3] + 1)}
+            assert set(count) == cells and max(count.values()) == 1
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("boxes_kind", ["regular", "uneven", "odd"])
+def test_tile_list_covers_every_cell_once(dtype, boxes_kind):
+    if boxes_kind == "regular":
+        dom, boxes = I.domain_box(64), I.regular_chop(I.domain_box(64), 32)
+    elif boxes_kind == "uneven":
+        dom = I.domain_box(128)
+        boxes = I.random_chop(dom, 16, 64, 8, seed=3)
+    else:
+        dom = I.domain_box((21, 13, 9))
+        boxes = I.random_chop(dom, 3, 8, 1, seed=5)
+    ncomp = 2
+    ba = bt.BoxArray.from_boxes(boxes, dom)
+    tiles = ba.tile_list(ncomp, 1, dtype)
+    for b, bx in enumerate(boxes):
+        ex, ey, ez = bx[3] - bx[0] + 1, bx[4] - bx[1] + 1, bx[5] - bx[2] + 1
+        cover = np.zeros((ncomp, ez, ey, ex), dtype=np.int32)
+        for t in tiles[tiles[:, 0] == b]:
+            comp, l0, l1, z0, z1, vec = t[1:]
+            nvx = ex // vec
+            for l in range(l0, l1):
+                y, xv = divmod(l, nvx)
+                cover[comp, z0:z1, y, xv * vec:(xv + 1) * vec] += 1
+        assert cover.min() == 1 and cover.max() == 1
+
+
+def test_static_partition_reproduces_the_papers_worked_example():
+    path = os.path.join(GOLDEN, "static_schedule_sec3_3.txt")
+    expect = {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        parts = line.split()
+        expect[int(parts[0])] = [tuple(int(v) for v in p.split(",")) for p in parts[1:]]
+    tiles_per_grid = [4, 2, 2, 4]
+    flat = [(g, t) for g, n in enumerate(tiles_per_grid) for t in range(n)]  # collapsed (grid, tile) loop
+    first = bt.static_partition(len(flat), 4)
+    for w in range(4):
+        assert flat[first[w]:first[w + 1]] == expect[w]
+
+
+def test_static_partition_general():
+    for n, w in [(0, 3), (5, 8), (100, 7), (12, 4)]:
+        f = bt.static_partition(n, w)
+        sizes = np.diff(f)
+        assert f[0] == 0 and f[-1] == n and sizes.max() - sizes.min() <= 1
+        assert list(sizes) == sorted(sizes, reverse=True)
+
+
+def test_multifab_bytes_cover_the_grown_boxes():
+    boxes = I.random_chop(I.domain_box(128), 16, 64, 8, seed=1)
+    ba = bt.BoxArray.from_boxes(boxes, I.domain_box(128))
+    e = boxes[:, 3:] - boxes[:, :3] + 3
+    grown = int(np.prod(e, axis=1).sum())
+    for dtype, es in ((bt.F64, 8), (bt.F32, 4)):
+        nb = ba.multifab_bytes(3, 1, dtype)
+        assert 3 * grown * es <= nb <= 3 * grown * es * 1.35
