@@ -31,11 +31,15 @@
  *   - Work is enqueued asynchronously on the hipStream_t passed in (0 is the
  *     null stream).  Calls that return a scalar to a host pointer synchronise
  *     that stream before returning.
- *   - Data layout of a MultiFab (bl_multifab_layout reports it): FAB b is one
- *     contiguous block holding its grown box for each component, x fastest,
- *     then y, then z, then the component.  Rows in x may be padded so that the
- *     first valid cell of every row is 16-byte aligned; strides give the exact
- *     element distances.
+ *   - Data layout of a MultiFab: FAB b is one contiguous block per component:
+ *     its rows (valid x cells of every row of the grown box, x fastest, then
+ *     y, then z; the rows of a plane are contiguous and each plane starts on
+ *     a 128-byte boundary), then an "x
+ *     ghost slab" holding the ghost cells left and right of the rows
+ *     (contiguous along y), then a copy of the box's own first and last valid
+ *     x columns that the fused stencil keeps for its neighbours.
+ *     bl_multifab_layout and bl_multifab_xghost_layout give exact offsets and
+ *     strides; bl_multifab_copy_fab moves a whole FAB to or from a dense array.
  */
 #ifndef BOXTILE_H
 #define BOXTILE_H
@@ -151,17 +155,38 @@ bl_status bl_multifab_create(const bl_boxarray* ba, const bl_distmap* dm, int32_
                              bl_dtype dtype, void* dev_ptr, size_t bytes, bl_multifab** out);
 
 /*
- * Layout of FAB `box`: its grown box, the element offset (from dev_ptr) of
- * its first element, the grown box's low corner, component 0, and element
- * strides {x, y, z, comp}.  The element of global cell (i,j,k), component n,
- * is at
- *   offset + (i - grown.lo[0]) + (j - grown.lo[1])*stride[1]
+ * Layout of the rows of FAB `box`: its grown box, the element offset (from
+ * dev_ptr) of the row cell (valid lo x, grown lo y, grown lo z), component 0,
+ * and element strides {x, y, z, comp}.  Cell (i,j,k), component n, with i in
+ * the box's valid x range and j, k in the grown range, is at
+ *   offset + (i - box.lo[0]) + (j - grown.lo[1])*stride[1]
  *          + (k - grown.lo[2])*stride[2] + n*stride[3]
- * in elements of the MultiFab's dtype (stride[0] is 1; stride[1] may exceed
- * the grown x extent when rows are padded).
+ * in elements of the MultiFab's dtype.  Planes are padded so that each
+ * starts on a 128-byte boundary.  Ghost cells outside the valid x range
+ * live in the x ghost slab (bl_multifab_xghost_layout).
  */
 bl_status bl_multifab_layout(const bl_multifab* mf, int32_t box, bl_box* grown, size_t* offset_elems,
                              int64_t stride[4]);
+
+/*
+ * Layout of the x ghost slab of FAB `box` (nghost >= 1): the element offset of
+ * the ghost cell (box.lo[0]-1, grown lo y, grown lo z), component 0, and
+ * strides {layer, y, z, side, comp}.  Ghost cell (i,j,k), component n, with
+ * i < box.lo[0] (side 0, layer box.lo[0]-1-i) or i > box.hi[0] (side 1, layer
+ * i-box.hi[0]-1), is at offset + layer*stride[0] + (j - grown.lo[1])*stride[1]
+ * + (k - grown.lo[2])*stride[2] + side*stride[3] + n*stride[4].
+ */
+bl_status bl_multifab_xghost_layout(const bl_multifab* mf, int32_t box, size_t* offset_elems, int64_t stride[5]);
+
+/*
+ * Copy FAB `box` (its whole grown box, valid and ghost cells, components
+ * [scomp, scomp+ncomp)) to (to_dense != 0) or from a dense device array of
+ * shape (ncomp, nz, ny, nx) over the grown box, x fastest, of the MultiFab's
+ * dtype.  Bit copies.
+ */
+bl_status bl_multifab_copy_fab(bl_multifab* mf, int32_t box, int32_t scomp, int32_t ncomp, void* dense_dev,
+                               int32_t to_dense, hipStream_t stream);
+
 /* Shape query: number of boxes, ncomp, nghost, dtype. */
 bl_status bl_multifab_info(const bl_multifab* mf, int32_t* nboxes, int32_t* ncomp, int32_t* nghost,
                            int32_t* dtype);
@@ -211,8 +236,10 @@ bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t
  * u[nsteps % 2].  Each step is ONE launch of the fused kernel over the
  * flattened tile list of all boxes and components: tiles next to a box face
  * read the neighbouring box's valid cells (or their periodic image) directly,
- * which is the value FillBoundary would have put in the ghost cell.  The
- * per-step launches are captured once in a HIP graph and replayed.  Ghost
+ * which is the value FillBoundary would have put in the ghost cell; x
+ * neighbours come from the copy of each box's edge columns that every step
+ * writes with the new state (a first kernel makes it for u[0]).  The launches
+ * are captured once in a HIP graph and replayed.  Ghost
  * cells are neither read where a box covers them nor written.  Results are
  * bit-identical to bl_heat_step with fill_first = 1.
  */
@@ -259,10 +286,11 @@ bl_status bl_reduce_async(const bl_multifab* mf, int32_t comp, bl_reduce_op op, 
 /* ------------------------------------------------------------ launch tuning */
 
 /*
- * Tile shape of the stencil kernels: zchunk = z planes per tile (1..1024),
- * waves = 64-lane waves per workgroup (1..16), persist = workgroups per CU for
+ * Tile shape of the stencil kernels: zchunk = most z planes per tile (1..16384),
+ * waves = 64-lane waves per workgroup (1..16), persist = workgroups per CU of
  * the persistent grid (0: one workgroup per tile).  Applies to MultiFabs
- * created afterwards and to bl_batch objects at their next rebuild.
+ * created afterwards and to bl_batch objects at their next rebuild; results do
+ * not depend on it.
  */
 bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist);
 bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist);
@@ -309,10 +337,9 @@ bl_status bl_face_plan(const bl_boxarray* ba, int32_t* nrec, int32_t* rec);
 /*
  * Flattened tile list of the stencil kernels for a MultiFab of this shape
  * under the current tile configuration: number of tiles and, if tiles != NULL,
- * 7 int32 per tile {box, comp, plane_lo, plane_hi, z_lo, z_hi, vec}: lanes
- * plane_lo..plane_hi-1 of the box's x-y plane (lane = x/vec + row*(x extent/vec),
- * each lane vec consecutive x cells) over box-local z planes z_lo..z_hi-1.
- * Host metadata only.
+ * 9 int32 per tile {box, comp, xv0, nvt, y0, rows, z0, z1, vec}: x vectors
+ * xv0..xv0+nvt-1 (each vec consecutive x cells, box-local) of rows
+ * y0..y0+rows-1 over box-local z planes z0..z1-1.  Host metadata only.
  */
 bl_status bl_tile_list(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_dtype dtype, int32_t* ntiles,
                        int32_t* tiles);

@@ -60,6 +60,8 @@ _SIGS = {
     "bl_multifab_bytes": [_vp, _i32, _i32, _i32, _szp],
     "bl_multifab_create": [_vp, _vp, _i32, _i32, _i32, _vp, ctypes.c_size_t, _vpp],
     "bl_multifab_layout": [_vp, _i32, _boxp, _szp, _i64p],
+    "bl_multifab_xghost_layout": [_vp, _i32, _szp, _i64p],
+    "bl_multifab_copy_fab": [_vp, _i32, _i32, _i32, _vp, _i32, _vp],
     "bl_multifab_info": [_vp, _i32p, _i32p, _i32p, _i32p],
     "bl_multifab_copy_global": [_vp, _i32, _i32, _vp, _i32, _vp],
     "bl_multifab_set_val": [_vp, ctypes.c_double, _i32, _i32, _i32, _vp],
@@ -204,7 +206,7 @@ class BoxArray:
     def tile_list(self, ncomp: int, nghost: int, dtype: int = F64) -> np.ndarray:
         n = ctypes.c_int32()
         _check(_L.bl_tile_list(self._h, ncomp, nghost, dtype, ctypes.byref(n), None))
-        out = np.zeros((n.value, 7), dtype=np.int32)
+        out = np.zeros((n.value, 9), dtype=np.int32)
         _check(_L.bl_tile_list(self._h, ncomp, nghost, dtype, ctypes.byref(n), out.ctypes.data_as(_i32p)))
         return out
 
@@ -255,7 +257,7 @@ def static_partition(ntiles: int, nworkers: int) -> list:
     return list(first)
 
 
-def set_tile_config(zchunk: int = 1024, waves: int = 4, persist: int = 0) -> None:
+def set_tile_config(zchunk: int = 8, waves: int = 4, persist: int = 0) -> None:
     _check(_L.bl_set_tile_config(zchunk, waves, persist))
 
 
@@ -312,11 +314,21 @@ class MultiFab:
         _check(_L.bl_multifab_layout(self._h, box, ctypes.byref(g), ctypes.byref(off), st))
         return tuple(g.lo) + tuple(g.hi), off.value, tuple(st)
 
-    def fab(self, box: int) -> torch.Tensor:
-        """Strided view (comp, z, y, x) of FAB `box` over its grown box."""
-        g, off, st = self.layout(box)
+    def fab(self, box: int, stream=None) -> torch.Tensor:
+        """FAB `box` over its grown box, all components, as a dense (comp, z, y, x) device tensor (a copy)."""
+        g, _, _ = self.layout(box)
         shape = (self.ncomp, g[5] - g[2] + 1, g[4] - g[1] + 1, g[3] - g[0] + 1)
-        return self.elements().as_strided(shape, (st[3], st[2], st[1], st[0]), off)
+        t = torch.empty(shape, dtype=_TORCH[self.dtype], device=self.buffer.device)
+        _check(_L.bl_multifab_copy_fab(self._h, box, 0, self.ncomp, ctypes.c_void_p(t.data_ptr()), 1,
+                                       _stream(stream)))
+        return t
+
+    def set_fab(self, box: int, values: torch.Tensor, stream=None) -> None:
+        """Overwrite FAB `box` (grown box, all components) from a dense (comp, z, y, x) tensor."""
+        t = values.to(device=self.buffer.device, dtype=_TORCH[self.dtype]).contiguous()
+        _check(_L.bl_multifab_copy_fab(self._h, box, 0, self.ncomp, ctypes.c_void_p(t.data_ptr()), 0,
+                                       _stream(stream)))
+        self._keep = t
 
     def from_global(self, g, scomp: int = 0, stream=None) -> None:
         """Set valid cells from a dense (ncomp', Nz, Ny, Nx) array (numpy or torch)."""

@@ -199,13 +199,42 @@ bl_status bl_multifab_layout(const bl_multifab* mf, int32_t box, bl_box* grown, 
   if (box < 0 || box >= (int)p.fabs.size()) return fail(BL_EINVAL, "box %d out of range", box);
   const FabGeom& f = p.fabs[box];
   if (grown) *grown = to_c(f.grown);
-  if (offset_elems) *offset_elems = (size_t)f.off_grown;
+  if (offset_elems) *offset_elems = (size_t)f.index(f.valid.lo[0], f.grown.lo[1], f.grown.lo[2]);
   if (stride) {
     stride[0] = 1;
     stride[1] = f.sy;
     stride[2] = f.sz;
     stride[3] = f.sc;
   }
+  return BL_OK;
+}
+
+bl_status bl_multifab_xghost_layout(const bl_multifab* mf, int32_t box, size_t* offset_elems, int64_t stride[5]) {
+  clear_error();
+  if (!mf) return fail(BL_EINVAL, "NULL MultiFab");
+  const Plan& p = *mf->plan;
+  if (box < 0 || box >= (int)p.fabs.size()) return fail(BL_EINVAL, "box %d out of range", box);
+  if (p.ng < 1) return fail(BL_EINVAL, "the MultiFab has no ghost cells");
+  const FabGeom& f = p.fabs[box];
+  if (offset_elems) *offset_elems = (size_t)f.index(f.valid.lo[0] - 1, f.grown.lo[1], f.grown.lo[2]);
+  if (stride) {
+    stride[0] = 1;
+    stride[1] = f.ng;
+    stride[2] = f.xs_z;
+    stride[3] = f.xs_side;
+    stride[4] = f.sc;
+  }
+  return BL_OK;
+}
+
+bl_status bl_multifab_copy_fab(bl_multifab* mf, int32_t box, int32_t scomp, int32_t ncomp, void* dense_dev,
+                               int32_t to_dense, hipStream_t stream) {
+  clear_error();
+  if (!mf || !dense_dev) return fail(BL_EINVAL, "NULL argument");
+  const Plan& p = *mf->plan;
+  if (box < 0 || box >= (int)p.fabs.size()) return fail(BL_EINVAL, "box %d out of range", box);
+  if (scomp < 0 || ncomp < 1 || scomp + ncomp > p.ncomp) return fail(BL_EINVAL, "component range out of bounds");
+  BL_HIP(launch_copy_fab(p, mf->data, dense_dev, box, scomp, ncomp, to_dense, stream));
   return BL_OK;
 }
 
@@ -275,6 +304,7 @@ bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t
   const Plan& p = *u_old->plan;
   if (fill_first) BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream));
   HeatArgs a{};
+  a.fvec = p.fvec;
   a.boxes = p.dboxes;
   a.recs = p.dfacerecs;
   a.m0 = member_of(u_old, u_new, c);
@@ -294,7 +324,8 @@ bl_status bl_heat_step_unfused(bl_multifab* u_old, bl_multifab* u_new, double c,
   if (st != BL_OK) return st;
   const Plan& p = *u_old->plan;
   BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream));
-  HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u_old, u_new, c), nullptr, 0};
+  HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u_old, u_new, c), nullptr, 0,
+             p.fvec};
   BL_HIP(launch_heat(p.dtype, p.vec, false, a, persistent_grid(tile_config().persist), block_of(p), stream));
   return BL_OK;
 }
@@ -322,9 +353,11 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
   if (!exec) {
     hipStream_t cs = capture_stream();
     if (!cs) return fail(BL_EHIP, "could not create the capture stream");
-    HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u[0], u[1], c), nullptr, 0};
+    HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u[0], u[1], c), nullptr, 0,
+               p.fvec};
     BL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t le = hipSuccess;
+    // the edge-column mirror of the starting state, then the fused steps
+    hipError_t le = launch_extract_mirror(p, u[0]->data, cs);
     for (int s = 0; s < nsteps && le == hipSuccess; ++s) {
       a.flip = s & 1;
       le = launch_heat(p.dtype, p.vec, true, a, persistent_grid(persist), block_of(p), cs);
@@ -433,8 +466,8 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
 
 bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist) {
   clear_error();
-  if (zchunk < 1 || zchunk > 1024 || waves < 1 || waves > 16 || persist < 0 || persist > 64)
-    return fail(BL_EINVAL, "need 1 <= zchunk <= 1024, 1 <= waves <= 16, 0 <= persist <= 64");
+  if (zchunk < 1 || zchunk > 16384 || waves < 1 || waves > 16 || persist < 0 || persist > 64)
+    return fail(BL_EINVAL, "need 1 <= zchunk <= 16384, 1 <= waves <= 16, 0 <= persist <= 64");
   TileConfig& c = tile_config();
   c.zchunk = zchunk;
   c.waves = waves;
@@ -506,14 +539,16 @@ bl_status bl_tile_list(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_
   *ntiles = (int32_t)t.size();
   if (tiles)
     for (size_t i = 0; i < t.size(); ++i) {
-      int32_t* r = tiles + 7 * i;
+      int32_t* r = tiles + 9 * i;
       r[0] = t[i].box;
       r[1] = t[i].comp;
-      r[2] = t[i].l0;
-      r[3] = t[i].l0 + t[i].nl;
-      r[4] = t[i].z0;
-      r[5] = t[i].z1;
-      r[6] = plan->vec;
+      r[2] = t[i].xv0;
+      r[3] = t[i].nvt;
+      r[4] = t[i].y0;
+      r[5] = t[i].rows;
+      r[6] = t[i].z0;
+      r[7] = t[i].z1;
+      r[8] = plan->vec;
     }
   return BL_OK;
 }
@@ -530,7 +565,7 @@ struct bl_batch {
     int id;
   };
   struct Group {
-    int dtype = 0, vec = 1;
+    int dtype = 0, vec = 1, fvec = 1;
     std::vector<int> members;  // indices into mems
     DevBox* dboxes = nullptr;
     DevFaceRec* drecs = nullptr;
@@ -573,6 +608,7 @@ static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
       g->vec = p.vec;
     }
     g->members.push_back((int)i);
+    if (!p.fvec) g->fvec = 0;
   }
   for (auto& g : b->groups) {
     std::vector<DevBox> boxes;
@@ -603,6 +639,11 @@ static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
     if ((st = upload(&g.dtiles, tiles, "batch tiles")) != BL_OK) return st;
     if ((st = upload(&g.dmembers, mems, "batch members")) != BL_OK) return st;
     g.ntiles = (int)tiles.size();
+  }
+  // edge-column mirrors of every member's current state
+  for (const auto& m : b->mems) {
+    bl_multifab* cur = ((b->tick - m.joined) & 1) ? m.u1 : m.u0;
+    BL_HIP(launch_extract_mirror(*cur->plan, cur->data, stream));
   }
   b->dirty = false;
   return BL_OK;
@@ -659,7 +700,7 @@ bl_status bl_batch_step(bl_batch* b, hipStream_t stream) {
   bl_status st;
   if (b->dirty && (st = batch_rebuild(b, stream)) != BL_OK) return st;
   for (auto& g : b->groups) {
-    HeatArgs a{g.dtiles, g.ntiles, g.dboxes, g.drecs, DevMember{}, g.dmembers, (int)(b->tick & 1)};
+    HeatArgs a{g.dtiles, g.ntiles, g.dboxes, g.drecs, DevMember{}, g.dmembers, (int)(b->tick & 1), g.fvec};
     BL_HIP(launch_heat(g.dtype, g.vec, true, a, persistent_grid(b->cfg.persist), 64 * b->cfg.waves, stream));
   }
   b->tick++;

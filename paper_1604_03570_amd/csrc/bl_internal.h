@@ -117,18 +117,35 @@ namespace bl {
 
 // ---------------------------------------------------------------- device descriptors
 // Per box of a MultiFab layout.  Offsets and strides are in elements.
+//
+// FAB layout, per component block (comp stride sc):
+//   rows:   the grown box in y and z, valid x only: cell (i, j, k) (box-local,
+//           i in [0, ex), j and k in [-ng, e+ng)) at off + i + j*sy + k*sz;
+//           rows of a plane are contiguous (sy = ex) and every plane starts
+//           on a 128-byte boundary, so whole rows form one contiguous span;
+//   x slab: the x ghost cells, contiguous along y: ghost layer l (0 = next to
+//           the box) of side s (0 = low x, 1 = high x) at
+//           xs + s*xs_side + k*xs_z + j*ng + l  (j, k grown range);
+//   mirror: a copy of the box's own first (s = 0) and last (s = 1) valid x
+//           column, contiguous along y: mir + s*mir_side + k*ey + j.  The fused
+//           stencil writes it with each new state; neighbours read their x
+//           face values from it.
 struct DevBox {
-  int64_t off;       // element offset of valid cell (0,0,0) (box-local), component 0
+  int64_t off;       // row cell (0,0,0), component 0
   int64_t sc;        // component stride
+  int64_t xs;        // x slab cell (side 0, j = 0, k = 0, l = 0), component 0
+  int64_t mir;       // mirror (side 0, j = 0, k = 0), component 0
   int32_t sy, sz;    // row and plane strides
+  int32_t xs_side, xs_z, mir_side;
   int32_t ex, ey, ez;
   int32_t nvx;       // x vectors per row (ex / vec)
+  int32_t ng;
   int32_t glo[3];    // global index of valid cell (0,0,0)
   int32_t face_start[6];
   int16_t face_count[6];
-  int32_t pad_[1];
+  int32_t pad_[2];
 };
-static_assert(sizeof(DevBox) % 8 == 0, "DevBox alignment");
+static_assert(sizeof(DevBox) % 16 == 0, "DevBox alignment");
 
 // Source of the ghost layer next to one face, over a rectangle of the face:
 // the value next to box-local tangential coordinates (t1, t2) of component n is
@@ -142,16 +159,20 @@ struct DevFaceRec {
 };
 static_assert(sizeof(DevFaceRec) == 32, "DevFaceRec size");
 
-// A unit of stencil work: lanes l0..l0+nl-1 of the box's plane (plane index =
-// x-vector + row * vectors-per-row), z planes z0..z1-1, one component.
+// A unit of stencil work: x vectors xv0..xv0+nvt-1 (each vec cells) of rows
+// y0..y0+rows-1 of one box and component, over box-local z planes z0..z1-1.
+// Lane l of the workgroup takes x vector xv0 + l % nvt of row y0 + l / nvt.
+// Tiles never straddle a z boundary of the box's x- or y-face records, so
+// each lane's face sources are fixed for the whole tile.
 struct DevTile {
   int32_t box;
-  int32_t comp;
   int32_t member;
-  int32_t l0;
-  int32_t nl;
-  int32_t z0, z1;
-  int32_t work;      // cells (nl * vec * (z1 - z0)), for static partitions
+  int16_t comp;
+  int16_t xv0, nvt;
+  int16_t y0, rows;
+  int16_t z0, z1;
+  int16_t pad0_;
+  int32_t pad1_[2];
 };
 static_assert(sizeof(DevTile) == 32, "DevTile size");
 
@@ -165,14 +186,17 @@ struct DevMember {
   int32_t pad_;
 };
 
-// FillBoundary copy chunk: up to kFillChunk cells of one record.
+// FillBoundary copy record: a box of destination ghost cells, one class of
+// storage (rows or one side of the x slab), and its source valid cells; both
+// addresses are affine in the cell's offset (x, y, z) from the region's low corner.
 struct DevFillRec {
-  int64_t dst_base;  // element offset of the region's low cell in the destination, comp 0
-  int64_t src_base;  // element offset of its source cell, comp 0
+  int64_t dst_base;  // element index of the region's low cell, comp 0
+  int64_t src_base;  // element index of its source cell, comp 0
   int64_t dsc, ssc;  // component strides
-  int32_t dsy, dsz, ssy, ssz;
+  int32_t dsx, dsy, dsz;
+  int32_t ssx, ssy, ssz;
   int32_t nx, ny, nz;
-  int32_t pad_;
+  int32_t pad_[3];
 };
 struct DevFillChunk {
   int32_t rec;
@@ -182,17 +206,29 @@ constexpr int kFillChunk = 256;
 
 // ---------------------------------------------------------------- layout + plans
 struct TileConfig {
-  int zchunk = 1024;  // z planes per tile
+  int zchunk = 8;     // z planes per tile at most
   int waves = 4;      // 64-lane waves per workgroup
   int persist = 0;    // workgroups per CU for the persistent grid (0: one workgroup per tile)
 };
 TileConfig& tile_config();
 
 struct FabGeom {
-  Box grown;
-  int64_t off_valid;  // element offset of valid cell (0,0,0), comp 0
-  int64_t off_grown;  // element offset of the grown box's low cell, comp 0
+  Box valid, grown;
+  int64_t fab;        // first element of the FAB
+  int64_t off;        // row cell (0,0,0), component 0 (as DevBox::off)
   int64_t sy, sz, sc;
+  int64_t xs, xs_side, xs_z;
+  int64_t mir, mir_side;
+  int ng;
+  // element index (component 0) of any cell of the grown box, global indices
+  int64_t index(int i, int j, int k) const {
+    const int li = i - valid.lo[0], lj = j - valid.lo[1], lk = k - valid.lo[2];
+    const int ex = valid.len(0);
+    if (li >= 0 && li < ex) return off + li + lj * sy + lk * sz;
+    const int side = li < 0 ? 0 : 1;
+    const int layer = li < 0 ? -1 - li : li - ex;
+    return xs + side * xs_side + lk * xs_z + (int64_t)lj * ng + layer;
+  }
 };
 
 // Everything that depends on (BoxArray, ncomp, nghost, dtype) only; shared by
@@ -202,7 +238,8 @@ struct Plan {
   std::vector<Box> boxes;
   Box domain{};
   int periodic[3] = {0, 0, 0};
-  int ncomp = 0, ng = 0, dtype = 0, esize = 8, vec = 1, xlead = 0;
+  int ncomp = 0, ng = 0, dtype = 0, esize = 8, vec = 1;
+  int fvec = 1;  // every y- and z-face record's source rows are vec-aligned (one 16-byte load per lane)
   std::vector<FabGeom> fabs;
   size_t total_elems = 0;
 

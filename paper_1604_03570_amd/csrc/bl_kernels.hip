@@ -3,11 +3,13 @@
 // residual, reductions and data movement between MultiFabs and dense arrays.
 //
 // Thread mapping shared by the stencil kernels: a workgroup takes one tile
-// (box, component, a run of lanes over the box's x-y plane, a z range).  Each
-// lane owns `V` consecutive x cells of one row (V*sizeof(T) = 16 bytes when all
-// x extents allow it, so every row access is one aligned 16-byte load) and
-// marches up the z range keeping the planes z-1, z, z+1 in registers; x and y
-// neighbours come from the neighbouring lanes' rows through the caches.
+// (box, component, whole rows of x vectors, a z range).  Each lane owns `V`
+// consecutive x cells of one row (V*sizeof(T) = 16 bytes when all x extents
+// allow it, so every row access is one aligned 16-byte load) and marches up
+// the tile's z range keeping the planes z-1, z, z+1 in registers, with the
+// next plane already in flight; x and y neighbours inside the tile come from
+// the other lanes through LDS, those outside from the FAB (or, fused, from the
+// neighbouring box).
 //
 // Every cell update is one fixed expression (heat_cell / gsrb_cell), compiled
 // without FMA contraction, so the per-box, fused and batched forms produce
@@ -37,6 +39,32 @@ __device__ __forceinline__ Vec<T, V> ldv(const T* p) {
 template <typename T, int V>
 __device__ __forceinline__ void stv(T* p, const Vec<T, V>& x) {
   *reinterpret_cast<Vec<T, V>*>(p) = x;
+}
+
+// Field pointers reach the stencil through descriptors in memory, so the
+// compiler cannot tell they are global; generic (flat) accesses would count
+// against the scalar-load counter too and serialise every scalar wait with the
+// data loads in flight.  These views pin them to the global address space.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define BL_GLOBAL __attribute__((address_space(1)))
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> ldv(const BL_GLOBAL T* p) {
+  return *reinterpret_cast<const BL_GLOBAL Vec<T, V>*>(p);
+}
+template <typename T, int V>
+__device__ __forceinline__ void stv(BL_GLOBAL T* p, const Vec<T, V>& x) {
+  *reinterpret_cast<BL_GLOBAL Vec<T, V>*>(p) = x;
+}
+#else
+#define BL_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ const BL_GLOBAL T* as_global(const T* p) {
+  return (const BL_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ BL_GLOBAL T* as_global(T* p) {
+  return (BL_GLOBAL T*)p;
 }
 
 // forward Euler, second-order centred differences (Sec. 4.1 of the paper):
@@ -78,99 +106,197 @@ __device__ __forceinline__ void tile_range(int ntiles, int persist, int& first, 
   last = first + q + (w < r ? 1 : 0);
 }
 
-template <typename T>
-__device__ __forceinline__ T qnan() {
-  return std::numeric_limits<T>::quiet_NaN();
+// Position of this lane in a tile.
+struct TileLane {
+  bool active;
+  int lx, ty;  // x vector and row inside the tile
+  int xv, y;   // box-local x vector and row
+  int x0;      // box-local x of the first of the lane's V cells
+};
+
+template <int V>
+__device__ __forceinline__ TileLane tile_lane(const DevTile& tl) {
+  TileLane L;
+  const int lane = (int)threadIdx.x;
+  const int nvt = tl.nvt;
+  L.ty = lane / nvt;
+  L.lx = lane - L.ty * nvt;
+  L.active = L.ty < tl.rows;
+  L.xv = tl.xv0 + L.lx;
+  L.y = tl.y0 + L.ty;
+  L.x0 = L.xv * V;
+  return L;
 }
 
-// Value in the ghost layer next to face `face` at tangential coordinates (t1, t2):
-// the record covering them gives its source (a neighbour's valid cell, its
-// periodic image, or the box's own ghost cell where no box covers the layer).
-template <typename T>
-__device__ __forceinline__ T face_load(const T* __restrict__ u, const DevFaceRec* __restrict__ recs, int start,
-                                       int count, int t1, int t2, int comp) {
+// Face sources.  The records of a face partition the one-cell layer outside it;
+// the record covering tangential coordinates (t1, t2) names the source of that
+// ghost value: a neighbour's valid cell, its periodic image, or the box's own
+// ghost cell where no box covers the layer.  The loops below run in uniform
+// control flow (every lane walks the same records, so the record reads are
+// scalar loads) and select per lane with `want`.
+
+// x and y faces (t2 = z): value at plane z is data[base + z*step] for the whole
+// tile, since tiles never straddle a record's z boundary.
+__device__ __forceinline__ void face_source_z(const DevFaceRec* __restrict__ recs, int start, int count, bool want,
+                                              int t1, int t2, int comp, int64_t& base, int& step) {
   for (int r = start; r < start + count; ++r) {
     const DevFaceRec R = recs[r];
-    if (t1 >= R.t1lo && t1 <= R.t1hi && t2 >= R.t2lo && t2 <= R.t2hi)
-      return u[R.base + (int64_t)t1 * R.s1 + (int64_t)t2 * R.s2 + (int64_t)comp * R.sc];
+    const bool in = want & (t1 >= R.t1lo) & (t1 <= R.t1hi) & (t2 >= R.t2lo) & (t2 <= R.t2hi);
+    const int64_t b = R.base + (int64_t)t1 * R.s1 + (int64_t)comp * R.sc;
+    base = in ? b : base;
+    step = in ? R.s2 : step;
   }
-  return qnan<T>();  // records partition every face; not reached
 }
 
+// z faces: the value next to (t1, t2) = (x, y).
+__device__ __forceinline__ int64_t face_index_xy(const DevFaceRec* __restrict__ recs, int start, int count, int t1,
+                                                 int t2, int comp, int64_t fallback) {
+  int64_t idx = fallback;
+  for (int r = start; r < start + count; ++r) {
+    const DevFaceRec R = recs[r];
+    const bool in = (t1 >= R.t1lo) & (t1 <= R.t1hi) & (t2 >= R.t2lo) & (t2 <= R.t2hi);
+    const int64_t b = R.base + (int64_t)t1 * R.s1 + (int64_t)t2 * R.s2 + (int64_t)comp * R.sc;
+    idx = in ? b : idx;
+  }
+  return idx;
+}
+
+template <typename T, int V>
+struct EdgeVals {
+  T left, right;
+  Vec<T, V> ym, yp;
+};
+
 // ---------------------------------------------------------------- heat step
-template <typename T, int V, bool FUSED>
+// One tile: lanes march z0..z1-1, keeping planes z-1, z, z+1 in registers with
+// plane z+2 and the neighbour values of plane z+1 already in flight.  Every
+// lane issues the same five loads per plane (the next plane of its column, the
+// rows above and below, the x neighbours on either side) and one store; lanes
+// on a box face (FUSED) only point those loads at the neighbouring box through
+// the face records, and prefetches past the tile's end are clamped to a plane
+// that exists.  The steady-state body is therefore straight-line code whose
+// loads stay in flight across planes; it is unrolled four times so that the
+// rotation of the plane registers is a renaming, not a copy of registers with
+// loads pending.  Lanes beyond the tile's rows mirror row y0 and store the
+// same values as its lanes.
+// FVEC: every y- and z-face source row is vec-aligned, so face rows are one
+// 16-byte load per lane; otherwise face cells are loaded one by one.
+template <typename T, int V, bool FUSED, bool FVEC>
 __global__ void __launch_bounds__(1024)
-    k_heat(const DevTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
-           const DevFaceRec* __restrict__ recs, DevMember m0, const DevMember* __restrict__ members, int flip,
-           int persist) {
+    k_heat_rows(const DevTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+                const DevFaceRec* __restrict__ recs, DevMember m0, const DevMember* __restrict__ members, int flip,
+                int persist) {
   int first, last;
   tile_range(ntiles, persist, first, last);
   for (int t = first; t < last; ++t) {
     const DevTile tl = tiles[t];
-    if ((int)threadIdx.x >= tl.nl) continue;
     const DevBox B = boxes[tl.box];
     const DevMember M = members ? members[tl.member] : m0;
     const bool swap = ((flip + M.flip_offset) & 1) != 0;
-    const T* __restrict__ u = static_cast<const T*>(swap ? M.b : M.a);
-    T* __restrict__ w = static_cast<T*>(swap ? M.a : M.b);
+    const BL_GLOBAL T* __restrict__ u = as_global(static_cast<const T*>(swap ? M.b : M.a));
+    BL_GLOBAL T* __restrict__ w = as_global(static_cast<T*>(swap ? M.a : M.b));
     const T c = (T)M.c;
+    const TileLane L = tile_lane<V>(tl);
     const int n = tl.comp;
-    const int l = tl.l0 + (int)threadIdx.x;
-    const int y = l / B.nvx;
-    const int xv = l - y * B.nvx;
-    const int x0 = xv * V;
-    const int64_t cb = B.off + (int64_t)n * B.sc + x0 + (int64_t)y * B.sy;
-    const T* up = u + cb;
-    T* wp = w + cb;
     const int sy = B.sy, sz = B.sz;
-    int z = tl.z0;
-    Vec<T, V> zm, cc, zp, ym, yp, o;
-    if (!FUSED || z > 0) {
-      zm = ldv<T, V>(up + (z - 1) * sz);
-    } else {
-#pragma unroll
-      for (int e = 0; e < V; ++e) zm.v[e] = face_load(u, recs, B.face_start[4], B.face_count[4], x0 + e, y, n);
+    const int z0 = tl.z0, z1 = tl.z1;
+    const int yy = L.active ? L.y : tl.y0;
+    const int64_t cb = B.off + (int64_t)n * B.sc + L.x0 + (int64_t)yy * sy;  // cell (x0, y, z = 0)
+    BL_GLOBAL T* wp = w + cb;
+    BL_GLOBAL T* mir = w + B.mir + (int64_t)n * B.sc + yy;  // mirror column of row y (side 0, z = 0)
+
+    // Neighbour sources as base + z*step: the own FAB (interior cells, ghost
+    // rows, the x ghost slab for the row's first and last lanes), or on a box
+    // face of the fused form the face record's source.
+    const int64_t slab_lo = B.xs + (int64_t)n * B.sc + (int64_t)yy * B.ng;  // ghost x = -1 at z = 0
+    const int64_t slab_hi = slab_lo + B.xs_side;                            // ghost x = ex at z = 0
+    const bool xlo = L.xv == 0, xhi = L.xv == B.nvx - 1;
+    int64_t lb = xlo ? slab_lo : cb - 1, rb = xhi ? slab_hi : cb + V, ymb = cb - sy, ypb = cb + sy;
+    int ls = xlo ? B.xs_z : sz, rs = xhi ? B.xs_z : sz, yms = sz, yps = sz;
+    // z-face planes: fixed sources (z = -1 and z = ez)
+    int64_t zlo = cb - sz, zhi = cb + (int64_t)B.ez * sz;
+    const bool zface_lo = FUSED && z0 == 0;
+    const bool zface_hi = FUSED && z1 == B.ez;
+    if (FUSED) {
+      face_source_z(recs, B.face_start[0], B.face_count[0], xlo, yy, z0, n, lb, ls);
+      face_source_z(recs, B.face_start[1], B.face_count[1], xhi, yy, z0, n, rb, rs);
+      if (FVEC) {
+        if (tl.y0 == 0) face_source_z(recs, B.face_start[2], B.face_count[2], yy == 0, L.x0, z0, n, ymb, yms);
+        if (tl.y0 + tl.rows == B.ey)
+          face_source_z(recs, B.face_start[3], B.face_count[3], yy == B.ey - 1, L.x0, z0, n, ypb, yps);
+        if (zface_lo) zlo = face_index_xy(recs, B.face_start[4], B.face_count[4], L.x0, yy, n, zlo);
+        if (zface_hi) zhi = face_index_xy(recs, B.face_start[5], B.face_count[5], L.x0, yy, n, zhi);
+      }
     }
-    cc = ldv<T, V>(up + z * sz);
-    for (; z < tl.z1; ++z) {
-      const T* pz = up + z * sz;
-      if (!FUSED || z + 1 < B.ez) {
-        zp = ldv<T, V>(pz + sz);
+    // plane z of the lane's column, z in [z0-1, z1]
+    auto plane = [&](int z) -> Vec<T, V> {
+      if (!FUSED || FVEC) {
+        int64_t a = cb + (int64_t)z * sz;
+        if (FUSED) a = z < 0 ? zlo : (z >= B.ez ? zhi : a);
+        return ldv<T, V>(u + a);
+      }
+      Vec<T, V> v;
+      if (z >= 0 && z < B.ez) {
+        v = ldv<T, V>(u + cb + (int64_t)z * sz);
+      } else {
+        const int f = z < 0 ? 4 : 5;
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          v.v[e] = u[face_index_xy(recs, B.face_start[f], B.face_count[f], L.x0 + e, yy, n, cb + z * sz + e)];
+      }
+      return v;
+    };
+    auto edges = [&](int z, EdgeVals<T, V>& E) {
+      E.left = u[lb + (int64_t)z * ls];
+      E.right = u[rb + (int64_t)z * rs];
+      if (!FUSED || FVEC) {
+        E.ym = ldv<T, V>(u + ymb + (int64_t)z * yms);
+        E.yp = ldv<T, V>(u + ypb + (int64_t)z * yps);
       } else {
 #pragma unroll
-        for (int e = 0; e < V; ++e) zp.v[e] = face_load(u, recs, B.face_start[5], B.face_count[5], x0 + e, y, n);
+        for (int e = 0; e < V; ++e) {
+          int64_t bm = ymb + e, bp = ypb + e;
+          int sm = yms, sp = yps;
+          if (tl.y0 == 0)
+            face_source_z(recs, B.face_start[2], B.face_count[2], yy == 0, L.x0 + e, z0, n, bm, sm);
+          if (tl.y0 + tl.rows == B.ey)
+            face_source_z(recs, B.face_start[3], B.face_count[3], yy == B.ey - 1, L.x0 + e, z0, n, bp, sp);
+          E.ym.v[e] = u[bm + (int64_t)z * sm];
+          E.yp.v[e] = u[bp + (int64_t)z * sp];
+        }
       }
-      T left, right;
-      if (!FUSED || xv > 0)
-        left = pz[-1];
-      else
-        left = face_load(u, recs, B.face_start[0], B.face_count[0], y, z, n);
-      if (!FUSED || xv + 1 < B.nvx)
-        right = pz[V];
-      else
-        right = face_load(u, recs, B.face_start[1], B.face_count[1], y, z, n);
-      if (!FUSED || y > 0) {
-        ym = ldv<T, V>(pz - sy);
-      } else {
-#pragma unroll
-        for (int e = 0; e < V; ++e) ym.v[e] = face_load(u, recs, B.face_start[2], B.face_count[2], x0 + e, z, n);
-      }
-      if (!FUSED || y + 1 < B.ey) {
-        yp = ldv<T, V>(pz + sy);
-      } else {
-#pragma unroll
-        for (int e = 0; e < V; ++e) yp.v[e] = face_load(u, recs, B.face_start[3], B.face_count[3], x0 + e, z, n);
-      }
+    };
+    auto step = [&](int z, const Vec<T, V>& zm, const Vec<T, V>& cc, const Vec<T, V>& zp, Vec<T, V>& zq,
+                    const EdgeVals<T, V>& ec, EdgeVals<T, V>& en) {
+      zq = plane(z + 2 < z1 ? z + 2 : z1);        // clamped: always a plane that exists
+      edges(z + 1 < z1 ? z + 1 : z1 - 1, en);
+      Vec<T, V> o;
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        const T xm = e == 0 ? left : cc.v[e - 1];
-        const T xp = e == V - 1 ? right : cc.v[e + 1];
-        o.v[e] = heat_cell(cc.v[e], xm, xp, ym.v[e], yp.v[e], zm.v[e], zp.v[e], c);
+        const T xm = e == 0 ? ec.left : cc.v[e - 1];
+        const T xp = e == V - 1 ? ec.right : cc.v[e + 1];
+        o.v[e] = heat_cell(cc.v[e], xm, xp, ec.ym.v[e], ec.yp.v[e], zm.v[e], zp.v[e], c);
       }
-      stv<T, V>(wp + z * sz, o);
-      zm = cc;
-      cc = zp;
+      stv<T, V>(wp + (int64_t)z * sz, o);
+      if (FUSED) {  // the new state's edge columns, for the neighbours' next step
+        if (xlo) mir[(int64_t)z * B.ey] = o.v[0];
+        if (xhi) mir[B.mir_side + (int64_t)z * B.ey] = o.v[V - 1];
+      }
+    };
+
+    Vec<T, V> pa = plane(z0 - 1), pb = plane(z0), pc = plane(z0 + 1), pd;
+    EdgeVals<T, V> e0, e1;
+    edges(z0, e0);
+    int z = z0;
+    for (; z + 4 <= z1; z += 4) {
+      step(z, pa, pb, pc, pd, e0, e1);
+      step(z + 1, pb, pc, pd, pa, e1, e0);
+      step(z + 2, pc, pd, pa, pb, e0, e1);
+      step(z + 3, pd, pa, pb, pc, e1, e0);
     }
+    if (z < z1) step(z, pa, pb, pc, pd, e0, e1);
+    if (z + 1 < z1) step(z + 1, pb, pc, pd, pa, e1, e0);
+    if (z + 2 < z1) step(z + 2, pc, pd, pa, pb, e0, e1);
   }
 }
 
@@ -188,8 +314,8 @@ __global__ void __launch_bounds__(kFillChunk)
   const int t = cell / R.nx;
   const int y = t % R.ny;
   const int z = t / R.ny;
-  const int64_t d = R.dst_base + x + (int64_t)y * R.dsy + (int64_t)z * R.dsz;
-  const int64_t s = R.src_base + x + (int64_t)y * R.ssy + (int64_t)z * R.ssz;
+  const int64_t d = R.dst_base + (int64_t)x * R.dsx + (int64_t)y * R.dsy + (int64_t)z * R.dsz;
+  const int64_t s = R.src_base + (int64_t)x * R.ssx + (int64_t)y * R.ssy + (int64_t)z * R.ssz;
   for (int n = scomp; n < scomp + ncomp; ++n) data[d + n * R.dsc] = data[s + n * R.ssc];
 }
 
@@ -200,11 +326,10 @@ __global__ void __launch_bounds__(1024)
                   const DevBox* __restrict__ boxes, int scomp, int ncomp, int dlo0, int dlo1, int dlo2, int Nx, int Ny,
                   int Nz, int to_global) {
   const DevTile tl = tiles[blockIdx.x];
-  if (tl.comp < scomp || tl.comp >= scomp + ncomp || (int)threadIdx.x >= tl.nl) return;
+  const TileLane L = tile_lane<V>(tl);
+  if (tl.comp < scomp || tl.comp >= scomp + ncomp || !L.active) return;
   const DevBox B = boxes[tl.box];
-  const int l = tl.l0 + (int)threadIdx.x;
-  const int y = l / B.nvx;
-  const int x0 = (l - y * B.nvx) * V;
+  const int y = L.y, x0 = L.x0;
   const int64_t cb = B.off + (int64_t)tl.comp * B.sc + x0 + (int64_t)y * B.sy;
   for (int z = tl.z0; z < tl.z1; ++z) {
     const int64_t gi = (((int64_t)(tl.comp - scomp) * Nz + (B.glo[2] + z - dlo2)) * Ny + (B.glo[1] + y - dlo1)) * Nx +
@@ -225,26 +350,75 @@ __global__ void __launch_bounds__(1024)
     k_set_valid(T* __restrict__ data, T val, const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes,
                 int scomp, int ncomp) {
   const DevTile tl = tiles[blockIdx.x];
-  if (tl.comp < scomp || tl.comp >= scomp + ncomp || (int)threadIdx.x >= tl.nl) return;
+  const TileLane L = tile_lane<V>(tl);
+  if (tl.comp < scomp || tl.comp >= scomp + ncomp || !L.active) return;
   const DevBox B = boxes[tl.box];
-  const int l = tl.l0 + (int)threadIdx.x;
-  const int y = l / B.nvx;
-  const int x0 = (l - y * B.nvx) * V;
-  const int64_t cb = B.off + (int64_t)tl.comp * B.sc + x0 + (int64_t)y * B.sy;
+  const int64_t cb = B.off + (int64_t)tl.comp * B.sc + L.x0 + (int64_t)L.y * B.sy;
   for (int z = tl.z0; z < tl.z1; ++z)
 #pragma unroll
     for (int e = 0; e < V; ++e) data[cb + (int64_t)z * B.sz + e] = val;
 }
 
-// whole FAB blocks (valid, ghost and row padding) of components [scomp, scomp+ncomp)
+// whole component blocks (rows with ghosts and padding, x slab, mirror) of components [scomp, scomp+ncomp)
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_set_fab(T* __restrict__ data, T val, const DevBox* __restrict__ boxes, int scomp, int ncomp, int xlead, int ng) {
+    k_set_fab(T* __restrict__ data, T val, const DevBox* __restrict__ boxes, int scomp, int ncomp) {
   const DevBox B = boxes[blockIdx.y];
-  const int64_t start = B.off - (xlead + (int64_t)ng * B.sy + (int64_t)ng * B.sz) + (int64_t)scomp * B.sc;
+  const int64_t start = B.off - ((int64_t)B.ng * B.sy + (int64_t)B.ng * B.sz) + (int64_t)scomp * B.sc;
   const int64_t count = B.sc * ncomp;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     data[start + i] = val;
+}
+
+// ---------------------------------------------------------------- mirror and FAB copies
+// The edge-column mirror of every box and component from the state itself
+// (before the first fused step of a run).  One workgroup per (box, component).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_extract_mirror(T* __restrict__ data, const DevBox* __restrict__ boxes, int ncomp) {
+  const DevBox B = boxes[blockIdx.x / ncomp];
+  const int n = blockIdx.x % ncomp;
+  const int64_t cnt = (int64_t)B.ey * B.ez;
+  T* mir = data + B.mir + (int64_t)n * B.sc;
+  const T* rows = data + B.off + (int64_t)n * B.sc;
+  for (int64_t q = threadIdx.x; q < cnt; q += blockDim.x) {
+    const int y = (int)(q % B.ey), z = (int)(q / B.ey);
+    const T* r = rows + (int64_t)y * B.sy + (int64_t)z * B.sz;
+    mir[q] = r[0];
+    mir[B.mir_side + q] = r[B.ex - 1];
+  }
+}
+
+// element index of box-local cell (i, j, k) of the grown box, component 0
+__device__ __forceinline__ int64_t cell_index(const DevBox& B, int i, int j, int k) {
+  if (i >= 0 && i < B.ex) return B.off + i + (int64_t)j * B.sy + (int64_t)k * B.sz;
+  const int side = i < 0 ? 0 : 1;
+  const int layer = i < 0 ? -1 - i : i - B.ex;
+  return B.xs + (int64_t)side * B.xs_side + (int64_t)k * B.xs_z + (int64_t)j * B.ng + layer;
+}
+
+// FAB `box` (grown box, components [scomp, scomp+ncomp)) <-> dense (ncomp, nz, ny, nx) array
+template <typename I>
+__global__ void __launch_bounds__(256)
+    k_copy_fab(I* __restrict__ data, I* __restrict__ dense, const DevBox* __restrict__ boxes, int box, int scomp,
+               int ncomp, int to_dense) {
+  const DevBox B = boxes[box];
+  const int g = B.ng;
+  const int nx = B.ex + 2 * g, ny = B.ey + 2 * g, nz = B.ez + 2 * g;
+  const int64_t total = (int64_t)ncomp * nz * ny * nx;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(q % nx) - g;
+    int64_t r = q / nx;
+    const int j = (int)(r % ny) - g;
+    r /= ny;
+    const int k = (int)(r % nz) - g;
+    const int n = (int)(r / nz) + scomp;
+    const int64_t e = cell_index(B, i, j, k) + (int64_t)n * B.sc;
+    if (to_dense)
+      dense[q] = data[e];
+    else
+      data[e] = dense[q];
+  }
 }
 
 // ---------------------------------------------------------------- reductions
@@ -284,13 +458,11 @@ __global__ void __launch_bounds__(1024)
     k_reduce_tiles(const T* __restrict__ data, const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes,
                    int comp, int op, double* __restrict__ partials) {
   const DevTile tl = tiles[blockIdx.x];
+  const TileLane L = tile_lane<V>(tl);
   double acc = r_identity(op);
-  if (tl.comp == comp && (int)threadIdx.x < tl.nl) {
+  if (tl.comp == comp && L.active) {
     const DevBox B = boxes[tl.box];
-    const int l = tl.l0 + (int)threadIdx.x;
-    const int y = l / B.nvx;
-    const int x0 = (l - y * B.nvx) * V;
-    const T* p = data + B.off + (int64_t)comp * B.sc + x0 + (int64_t)y * B.sy;
+    const T* p = data + B.off + (int64_t)comp * B.sc + L.x0 + (int64_t)L.y * B.sy;
     for (int z = tl.z0; z < tl.z1; ++z) {
       const Vec<T, V> v = ldv<T, V>(p + (int64_t)z * B.sz);
 #pragma unroll
@@ -317,16 +489,18 @@ __global__ void __launch_bounds__(1024)
     k_gsrb(const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes, T* __restrict__ phi,
            const T* __restrict__ f, T h2, T inv6, int color) {
   const DevTile tl = tiles[blockIdx.x];
-  if ((int)threadIdx.x >= tl.nl) return;
+  const TileLane L = tile_lane<V>(tl);
+  if (!L.active) return;
   const DevBox B = boxes[tl.box];
-  const int l = tl.l0 + (int)threadIdx.x;
-  const int y = l / B.nvx;
-  const int x0 = (l - y * B.nvx) * V;
+  const int y = L.y, x0 = L.x0;
   const int64_t cb = B.off + x0 + (int64_t)y * B.sy;
   T* pp = phi + cb;
   const T* fp = f + cb;
   const int sy = B.sy, sz = B.sz;
   const int par0 = (B.glo[0] + x0 + B.glo[1] + y + B.glo[2]) & 1;
+  const int64_t lb = L.xv == 0 ? B.xs + (int64_t)y * B.ng : cb - 1;
+  const int64_t rb = L.xv == B.nvx - 1 ? B.xs + B.xs_side + (int64_t)y * B.ng : cb + V;
+  const int ls = L.xv == 0 ? B.xs_z : sz, rs = L.xv == B.nvx - 1 ? B.xs_z : sz;
   for (int z = tl.z0; z < tl.z1; ++z) {
     T* pz = pp + z * sz;
     const Vec<T, V> cc = ldv<T, V>(pz);
@@ -335,7 +509,7 @@ __global__ void __launch_bounds__(1024)
     const Vec<T, V> ym = ldv<T, V>(pz - sy);
     const Vec<T, V> yp = ldv<T, V>(pz + sy);
     const Vec<T, V> fv = ldv<T, V>(fp + z * sz);
-    const T left = pz[-1], right = pz[V];
+    const T left = phi[lb + (int64_t)z * ls], right = phi[rb + (int64_t)z * rs];
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       if (((par0 + z + e) & 1) != color) continue;
@@ -352,16 +526,17 @@ __global__ void __launch_bounds__(1024)
     k_residual(const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes, const T* __restrict__ phi,
                const T* __restrict__ f, double h2, double* __restrict__ partials) {
   const DevTile tl = tiles[blockIdx.x];
+  const TileLane L = tile_lane<V>(tl);
   double acc = 0.0;
-  if ((int)threadIdx.x < tl.nl) {
+  if (L.active) {
     const DevBox B = boxes[tl.box];
-    const int l = tl.l0 + (int)threadIdx.x;
-    const int y = l / B.nvx;
-    const int x0 = (l - y * B.nvx) * V;
-    const int64_t cb = B.off + x0 + (int64_t)y * B.sy;
+    const int64_t cb = B.off + L.x0 + (int64_t)L.y * B.sy;
     const T* pp = phi + cb;
     const T* fp = f + cb;
     const int sy = B.sy, sz = B.sz;
+    const int64_t lb = L.xv == 0 ? B.xs + (int64_t)L.y * B.ng : cb - 1;
+    const int64_t rb = L.xv == B.nvx - 1 ? B.xs + B.xs_side + (int64_t)L.y * B.ng : cb + V;
+    const int ls = L.xv == 0 ? B.xs_z : sz, rs = L.xv == B.nvx - 1 ? B.xs_z : sz;
     for (int z = tl.z0; z < tl.z1; ++z) {
       const T* pz = pp + z * sz;
       const Vec<T, V> cc = ldv<T, V>(pz);
@@ -370,7 +545,7 @@ __global__ void __launch_bounds__(1024)
       const Vec<T, V> ym = ldv<T, V>(pz - sy);
       const Vec<T, V> yp = ldv<T, V>(pz + sy);
       const Vec<T, V> fv = ldv<T, V>(fp + z * sz);
-      const double left = (double)pz[-1], right = (double)pz[V];
+      const double left = (double)phi[lb + (int64_t)z * ls], right = (double)phi[rb + (int64_t)z * rs];
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         const double xm = e == 0 ? left : (double)cc.v[e - 1];
@@ -389,12 +564,13 @@ template <typename T, int V>
 hipError_t heat_dispatch(bool fused, const HeatArgs& a, int grid, int block, hipStream_t s) {
   const int persist = grid > 0 ? 1 : 0;
   const int g = persist ? (grid < a.ntiles ? grid : a.ntiles) : a.ntiles;
-  if (fused)
-    hipLaunchKernelGGL((k_heat<T, V, true>), dim3(g), dim3(block), 0, s, a.tiles, a.ntiles, a.boxes, a.recs, a.m0,
-                       a.members, a.flip, persist);
-  else
-    hipLaunchKernelGGL((k_heat<T, V, false>), dim3(g), dim3(block), 0, s, a.tiles, a.ntiles, a.boxes, a.recs, a.m0,
-                       a.members, a.flip, persist);
+#define BL_LAUNCH_ROWS(F, Y)                                                                                  \
+  hipLaunchKernelGGL((k_heat_rows<T, V, F, Y>), dim3(g), dim3(block), 0, s, a.tiles, a.ntiles, a.boxes, a.recs, \
+                     a.m0, a.members, a.flip, persist)
+  if (!fused) BL_LAUNCH_ROWS(false, true);
+  else if (a.fvec) BL_LAUNCH_ROWS(true, true);
+  else BL_LAUNCH_ROWS(true, false);
+#undef BL_LAUNCH_ROWS
   return hipGetLastError();
 }
 
@@ -460,11 +636,10 @@ hipError_t launch_set_val(const Plan& p, void* data, double val, int scomp, int 
   const unsigned nb = (unsigned)p.hboxes.size();
   if (with_ghosts) {
     if (p.dtype == BL_F64)
-      hipLaunchKernelGGL(k_set_fab<double>, dim3(64, nb), dim3(256), 0, s, (double*)data, val, p.dboxes, scomp, ncomp,
-                         p.xlead, p.ng);
+      hipLaunchKernelGGL(k_set_fab<double>, dim3(64, nb), dim3(256), 0, s, (double*)data, val, p.dboxes, scomp, ncomp);
     else
       hipLaunchKernelGGL(k_set_fab<float>, dim3(64, nb), dim3(256), 0, s, (float*)data, (float)val, p.dboxes, scomp,
-                         ncomp, p.xlead, p.ng);
+                         ncomp);
   } else if (p.dtype == BL_F64) {
     if (p.vec == 2)
       hipLaunchKernelGGL((k_set_valid<double, 2>), dim3(nt), dim3(block), 0, s, (double*)data, val, p.dtiles, p.dboxes,
@@ -480,6 +655,27 @@ hipError_t launch_set_val(const Plan& p, void* data, double val, int scomp, int 
       hipLaunchKernelGGL((k_set_valid<float, 1>), dim3(nt), dim3(block), 0, s, (float*)data, (float)val, p.dtiles,
                          p.dboxes, scomp, ncomp);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_mirror(const Plan& p, void* data, hipStream_t s) {
+  const unsigned nb = (unsigned)(p.hboxes.size() * p.ncomp);
+  if (!nb) return hipSuccess;
+  if (p.dtype == BL_F64)
+    hipLaunchKernelGGL(k_extract_mirror<double>, dim3(nb), dim3(256), 0, s, (double*)data, p.dboxes, p.ncomp);
+  else
+    hipLaunchKernelGGL(k_extract_mirror<float>, dim3(nb), dim3(256), 0, s, (float*)data, p.dboxes, p.ncomp);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_fab(const Plan& p, void* data, void* dense, int box, int scomp, int ncomp, int to_dense,
+                           hipStream_t s) {
+  if (p.esize == 8)
+    hipLaunchKernelGGL(k_copy_fab<unsigned long long>, dim3(256), dim3(256), 0, s, (unsigned long long*)data,
+                       (unsigned long long*)dense, p.dboxes, box, scomp, ncomp, to_dense);
+  else
+    hipLaunchKernelGGL(k_copy_fab<unsigned int>, dim3(256), dim3(256), 0, s, (unsigned int*)data,
+                       (unsigned int*)dense, p.dboxes, box, scomp, ncomp, to_dense);
   return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ struct HeatArgs {
   DevMember m0;                // used when members == nullptr
   const DevMember* members;
   int flip;
+  int fvec;                    // 1: every y- and z-face source row allows aligned vector loads
 };
 
 // Stencil over `ntiles` tiles.  fused: tiles at box faces read neighbour boxes
@@ -32,6 +33,13 @@ hipError_t launch_copy_global(const Plan& p, void* data, void* global, int scomp
 
 hipError_t launch_set_val(const Plan& p, void* data, double val, int scomp, int ncomp, int with_ghosts, int block,
                           hipStream_t s);
+
+// Fill every box's edge-column mirror from the state in `data` (one launch).
+hipError_t launch_extract_mirror(const Plan& p, void* data, hipStream_t s);
+
+// FAB `box`, grown box, components [scomp, scomp+ncomp) <-> dense (ncomp, nz, ny, nx) device array.
+hipError_t launch_copy_fab(const Plan& p, void* data, void* dense, int box, int scomp, int ncomp, int to_dense,
+                           hipStream_t s);
 
 // partials must hold p.htiles.size() doubles; the result lands in *out (device).
 hipError_t launch_reduce(const Plan& p, const void* data, int comp, int op, double* partials, double* out, int block,

@@ -398,27 +398,73 @@ void build_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base,
                  std::vector<int>* box_tile_start) {
   const int lanes = 64 * cfg.waves;
   if (box_tile_start) box_tile_start->clear();
+  std::vector<int> zc;
   for (int b = 0; b < (int)p.hboxes.size(); ++b) {
     const DevBox& B = p.hboxes[b];
     if (box_tile_start) box_tile_start->push_back((int)tiles.size());
-    int nplane = B.nvx * B.ey;
+    // z cuts: chunk boundaries and every z boundary of the x- and y-face records
+    zc.clear();
+    for (int z = 0; z < B.ez; z += cfg.zchunk) zc.push_back(z);
+    zc.push_back(B.ez);
+    for (int f = 0; f < 4; ++f)
+      for (int r = B.face_start[f]; r < B.face_start[f] + B.face_count[f]; ++r) {
+        zc.push_back(std::max(0, std::min<int>(B.ez, p.hfacerecs[r].t2lo)));
+        zc.push_back(std::max(0, std::min<int>(B.ez, p.hfacerecs[r].t2hi + 1)));
+      }
+    std::sort(zc.begin(), zc.end());
+    zc.erase(std::unique(zc.begin(), zc.end()), zc.end());
+    const int nvt_full = std::min(B.nvx, lanes);
+    const int rows_full = std::max(1, std::min(B.ey, lanes / nvt_full));
     for (int n = 0; n < p.ncomp; ++n)
-      for (int l0 = 0; l0 < nplane; l0 += lanes)
-        for (int z0 = 0; z0 < B.ez; z0 += cfg.zchunk) {
-          DevTile t;
-          t.box = box_base + b;
-          t.comp = n;
-          t.member = member;
-          t.l0 = l0;
-          t.nl = std::min(lanes, nplane - l0);
-          t.z0 = z0;
-          t.z1 = std::min(B.ez, z0 + cfg.zchunk);
-          t.work = t.nl * p.vec * (t.z1 - t.z0);
-          tiles.push_back(t);
-        }
+      for (int xv0 = 0; xv0 < B.nvx; xv0 += nvt_full)
+        for (int y0 = 0; y0 < B.ey; y0 += rows_full)
+          for (size_t k = 0; k + 1 < zc.size(); ++k) {
+            DevTile t;
+            std::memset(&t, 0, sizeof t);
+            t.box = box_base + b;
+            t.member = member;
+            t.comp = (int16_t)n;
+            t.xv0 = (int16_t)xv0;
+            t.nvt = (int16_t)std::min(nvt_full, B.nvx - xv0);
+            t.y0 = (int16_t)y0;
+            t.rows = (int16_t)std::min(rows_full, B.ey - y0);
+            t.z0 = (int16_t)zc[k];
+            t.z1 = (int16_t)zc[k + 1];
+            tiles.push_back(t);
+          }
   }
   if (box_tile_start) box_tile_start->push_back((int)tiles.size());
 }
+
+// Layout of one FAB whose first element is `fab` (a multiple of A elements,
+// A = 128 bytes / element size).  Returns its size in elements.
+static int64_t layout_fab(const Box& b, int ng, int ncomp, int64_t A, int64_t fab, FabGeom& f) {
+  const int64_t ex = b.len(0), ey = b.len(1), ez = b.len(2);
+  const int64_t nyg = ey + 2 * ng, nzg = ez + 2 * ng;
+  // rows of one plane are contiguous (pitch = x extent); planes start on
+  // 128-byte boundaries, so a run of whole rows is one contiguous span
+  const int64_t px = ex;
+  const int64_t plane = round_up(nyg * px, A);
+  const int64_t rows = nzg * plane;
+  const int64_t slab = round_up(2 * nzg * nyg * ng, A);
+  const int64_t mirror = round_up(2 * ez * ey, A);
+  f.valid = b;
+  f.grown = b.grow(ng);
+  f.ng = ng;
+  f.fab = fab;
+  f.sy = px;
+  f.sz = plane;
+  f.sc = rows + slab + mirror;
+  f.off = fab + ng * f.sz + ng * f.sy;
+  f.xs_side = nzg * nyg * ng;
+  f.xs_z = nyg * ng;
+  f.xs = fab + rows + ng * f.xs_z + (int64_t)ng * ng;
+  f.mir_side = ez * ey;
+  f.mir = fab + rows + slab;
+  return f.sc * ncomp;
+}
+
+static int64_t elem_align(int esize) { return 128 / esize; }
 
 bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, std::shared_ptr<Plan>* out) {
   bl_boxarray* ba = const_cast<bl_boxarray*>(cba);
@@ -433,81 +479,108 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, std::
   p->esize = dtype == BL_F64 ? 8 : 4;
   const int v16 = 16 / p->esize;
   bool all_div = true;
-  for (const Box& b : ba->boxes)
+  for (const Box& b : ba->boxes) {
     if (b.len(0) % v16) all_div = false;
+    for (int d = 0; d < 3; ++d)
+      if (b.len(d) > 16384) return fail(BL_EINVAL, "box edge %d above 16384", b.len(d));
+  }
   p->vec = all_div ? v16 : 1;
-  const int xlead = (int)round_up(ng, p->vec);
-  p->xlead = xlead;
-  const int64_t fab_align = 128 / p->esize;
+  const int64_t A = elem_align(p->esize);
   int64_t off = 0;
   p->fabs.resize(ba->boxes.size());
   for (size_t i = 0; i < ba->boxes.size(); ++i) {
-    const Box& b = ba->boxes[i];
-    FabGeom& f = p->fabs[i];
-    f.grown = b.grow(ng);
-    int64_t px = round_up(xlead + b.len(0) + ng, p->vec);
-    f.sy = px;
-    f.sz = px * (b.len(1) + 2 * ng);
-    f.sc = f.sz * (b.len(2) + 2 * ng);
-    if (f.sc * ncomp >= ((int64_t)1 << 31))
-      return fail(BL_EINVAL, "box %zu is too large for one FAB (%lld elements)", i, (long long)(f.sc * ncomp));
-    off = round_up(off, fab_align);
-    f.off_valid = off + xlead + ng * f.sy + ng * f.sz;
-    f.off_grown = off + (xlead - ng);
-    off += f.sc * ncomp;
+    const int64_t size = layout_fab(ba->boxes[i], ng, ncomp, A, off, p->fabs[i]);
+    if (size >= ((int64_t)1 << 31))
+      return fail(BL_EINVAL, "box %zu is too large for one FAB (%lld elements)", i, (long long)size);
+    off = round_up(off + size, A);
   }
-  p->total_elems = (size_t)round_up(off, fab_align);
+  p->total_elems = (size_t)off;
 
-  // per-box descriptors and face records
-  const auto face_ptr = face_plan(ba, ng);
-  const auto& faces = *face_ptr;
+  // per-box descriptors
   p->hboxes.resize(ba->boxes.size());
   for (size_t i = 0; i < ba->boxes.size(); ++i) {
     const Box& b = ba->boxes[i];
     const FabGeom& f = p->fabs[i];
     DevBox& B = p->hboxes[i];
     std::memset(&B, 0, sizeof B);
-    B.off = f.off_valid;
+    B.off = f.off;
     B.sc = f.sc;
+    B.xs = f.xs;
+    B.mir = f.mir;
     B.sy = (int32_t)f.sy;
     B.sz = (int32_t)f.sz;
+    B.xs_side = (int32_t)f.xs_side;
+    B.xs_z = (int32_t)f.xs_z;
+    B.mir_side = (int32_t)f.mir_side;
     B.ex = b.len(0);
     B.ey = b.len(1);
     B.ez = b.len(2);
     B.nvx = B.ex / p->vec;
+    B.ng = ng;
     for (int d = 0; d < 3; ++d) B.glo[d] = b.lo[d];
   }
-  // face records arrive grouped by (box, face) in order
+
+  // Face records (fused stencil), grouped by (box, face) in order.  The value
+  // next to tangential coordinates (t1, t2) of a face is read at
+  // base + t1*s1 + t2*s2 (+ comp*sc): for a covered x face from the source
+  // box's mirror of its edge column, for a covered y or z face from the
+  // source's valid rows, for an uncovered part from the box's own ghost cells.
+  const auto face_ptr = face_plan(ba, ng);
+  const auto& faces = *face_ptr;
   p->hfacerecs.clear();
   size_t k = 0;
   for (size_t i = 0; i < ba->boxes.size(); ++i) {
+    const Box& bx = ba->boxes[i];
     for (int face = 0; face < 6; ++face) {
       DevBox& B = p->hboxes[i];
       B.face_start[face] = (int32_t)p->hfacerecs.size();
       int cnt = 0;
       while (k < faces.size() && faces[k].box == (int)i && faces[k].face == face) {
         const FaceRecord& r = faces[k++];
-        const Box& bx = ba->boxes[i];
-        const Box& sb = ba->boxes[r.src];
+        const int a = face / 2, side = face % 2;
+        const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+        const bool uncovered = r.src == (int)i && r.shift[0] == 0 && r.shift[1] == 0 && r.shift[2] == 0;
         const FabGeom& sf = p->fabs[r.src];
-        int a = face / 2, side = face % 2;
-        int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
-        int64_t sstride[3] = {1, sf.sy, sf.sz};
-        int lfix[3] = {0, 0, 0};
-        lfix[a] = side ? bx.len(a) - 1 : 0;
-        int nrm[3] = {0, 0, 0};
-        nrm[a] = side ? 1 : -1;
-        int64_t base = sf.off_valid;
-        for (int d = 0; d < 3; ++d) base += (int64_t)(bx.lo[d] + lfix[d] + nrm[d] + r.shift[d] - sb.lo[d]) * sstride[d];
+        const Box& sb = ba->boxes[r.src];
+        // ghost-layer cell at the record's low tangential corner
+        int q[3];
+        for (int d = 0; d < 3; ++d) q[d] = r.region.lo[d];
+        const int lo1 = r.region.lo[t1] - bx.lo[t1], lo2 = r.region.lo[t2] - bx.lo[t2];
+        int64_t addr, s1, s2;
+        if (uncovered) {
+          const FabGeom& f = p->fabs[i];
+          addr = f.index(q[0], q[1], q[2]);
+          if (a == 0) {
+            s1 = f.ng;    // along y in the x slab
+            s2 = f.xs_z;  // along z
+          } else {
+            s1 = 1;
+            s2 = a == 1 ? f.sz : f.sy;
+          }
+        } else if (a == 0) {
+          // source cell: the source's last (for our low face) or first x column
+          const int sside = side ? 0 : 1;
+          const int j = q[1] + r.shift[1] - sb.lo[1], kk = q[2] + r.shift[2] - sb.lo[2];
+          addr = sf.mir + sside * sf.mir_side + (int64_t)kk * sb.len(1) + j;
+          s1 = 1;
+          s2 = sb.len(1);
+        } else {
+          addr = sf.index(q[0] + r.shift[0], q[1] + r.shift[1], q[2] + r.shift[2]);
+          s1 = 1;
+          s2 = a == 1 ? sf.sz : sf.sy;
+        }
         DevFaceRec R;
-        R.base = base;
+        R.base = addr - lo1 * s1 - lo2 * s2;
         R.sc = sf.sc;
-        R.s1 = (int32_t)sstride[t1];
-        R.s2 = (int32_t)sstride[t2];
-        R.t1lo = (int16_t)(r.region.lo[t1] - bx.lo[t1]);
+        R.s1 = (int32_t)s1;
+        R.s2 = (int32_t)s2;
+        R.t1lo = (int16_t)lo1;
         R.t1hi = (int16_t)(r.region.hi[t1] - bx.lo[t1]);
-        R.t2lo = (int16_t)(r.region.lo[t2] - bx.lo[t2]);
+        R.t2lo = (int16_t)lo2;
         R.t2hi = (int16_t)(r.region.hi[t2] - bx.lo[t2]);
+        if (a >= 1 && p->vec > 1 &&
+            (((R.base % p->vec) + p->vec) % p->vec != 0 || R.t1lo % p->vec != 0 || (R.t1hi + 1) % p->vec != 0))
+          p->fvec = 0;
         p->hfacerecs.push_back(R);
         ++cnt;
       }
@@ -515,39 +588,45 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, std::
       B.face_count[face] = (int16_t)cnt;
     }
   }
-  for (const Box& b : ba->boxes)
-    for (int d = 0; d < 3; ++d)
-      if (b.len(d) > 32767) return fail(BL_EINVAL, "box edge above 32767");
 
-  // FillBoundary records and chunks
+  // FillBoundary records: each plan region split by the destination's
+  // storage class along x (low x slab, rows, high x slab), chunked.
   p->fill = fill_plan(ba, ng);
-  const auto& fill = *p->fill;
   p->hfillrecs.clear();
   p->hfillchunks.clear();
-  for (const FillRecord& r : fill) {
+  for (const FillRecord& r : *p->fill) {
     const Box& db = ba->boxes[r.dst];
-    const Box& sb = ba->boxes[r.src];
     const FabGeom& df = p->fabs[r.dst];
     const FabGeom& sf = p->fabs[r.src];
-    DevFillRec R;
-    std::memset(&R, 0, sizeof R);
-    R.dst_base = df.off_valid + (r.region.lo[0] - db.lo[0]) + (r.region.lo[1] - db.lo[1]) * df.sy +
-                 (r.region.lo[2] - db.lo[2]) * df.sz;
-    R.src_base = sf.off_valid + (r.region.lo[0] + r.shift[0] - sb.lo[0]) +
-                 (r.region.lo[1] + r.shift[1] - sb.lo[1]) * sf.sy + (r.region.lo[2] + r.shift[2] - sb.lo[2]) * sf.sz;
-    R.dsc = df.sc;
-    R.ssc = sf.sc;
-    R.dsy = (int32_t)df.sy;
-    R.dsz = (int32_t)df.sz;
-    R.ssy = (int32_t)sf.sy;
-    R.ssz = (int32_t)sf.sz;
-    R.nx = r.region.len(0);
-    R.ny = r.region.len(1);
-    R.nz = r.region.len(2);
-    int rid = (int)p->hfillrecs.size();
-    p->hfillrecs.push_back(R);
-    int64_t vol = r.region.volume();
-    for (int64_t s = 0; s < vol; s += kFillChunk) p->hfillchunks.push_back(DevFillChunk{rid, (int32_t)s});
+    const int xs[3][2] = {{r.region.lo[0], std::min(r.region.hi[0], db.lo[0] - 1)},
+                          {std::max(r.region.lo[0], db.lo[0]), std::min(r.region.hi[0], db.hi[0])},
+                          {std::max(r.region.lo[0], db.hi[0] + 1), r.region.hi[0]}};
+    for (int part = 0; part < 3; ++part) {
+      if (xs[part][0] > xs[part][1]) continue;
+      Box R0 = r.region;
+      R0.lo[0] = xs[part][0];
+      R0.hi[0] = xs[part][1];
+      DevFillRec R;
+      std::memset(&R, 0, sizeof R);
+      const int *lo = R0.lo, *sh = r.shift;
+      R.dst_base = df.index(lo[0], lo[1], lo[2]);
+      R.dsx = R0.len(0) > 1 ? (int32_t)(df.index(lo[0] + 1, lo[1], lo[2]) - R.dst_base) : 0;
+      R.dsy = R0.len(1) > 1 ? (int32_t)(df.index(lo[0], lo[1] + 1, lo[2]) - R.dst_base) : 0;
+      R.dsz = R0.len(2) > 1 ? (int32_t)(df.index(lo[0], lo[1], lo[2] + 1) - R.dst_base) : 0;
+      R.src_base = sf.index(lo[0] + sh[0], lo[1] + sh[1], lo[2] + sh[2]);
+      R.ssx = 1;
+      R.ssy = (int32_t)sf.sy;
+      R.ssz = (int32_t)sf.sz;
+      R.dsc = df.sc;
+      R.ssc = sf.sc;
+      R.nx = R0.len(0);
+      R.ny = R0.len(1);
+      R.nz = R0.len(2);
+      const int rid = (int)p->hfillrecs.size();
+      p->hfillrecs.push_back(R);
+      const int64_t vol = R0.volume();
+      for (int64_t c0 = 0; c0 < vol; c0 += kFillChunk) p->hfillchunks.push_back(DevFillChunk{rid, (int32_t)c0});
+    }
   }
 
   p->cfg = tile_config();
@@ -565,20 +644,12 @@ bl_status bl_multifab_bytes(const bl_boxarray* ba, int32_t ncomp, int32_t nghost
   if (!ba || !bytes) return fail(BL_EINVAL, "NULL argument");
   if (ncomp < 1 || nghost < 0) return fail(BL_EINVAL, "need ncomp >= 1 and nghost >= 0");
   if (dtype != BL_F64 && dtype != BL_F32) return fail(BL_EDTYPE, "unknown dtype %d", (int)dtype);
-  int esize = dtype == BL_F64 ? 8 : 4;
-  int v16 = 16 / esize;
-  bool all_div = true;
-  for (const Box& b : ba->boxes)
-    if (b.len(0) % v16) all_div = false;
-  int vec = all_div ? v16 : 1;
-  int64_t xlead = round_up(nghost, vec);
-  int64_t fab_align = 128 / esize, off = 0;
-  for (const Box& b : ba->boxes) {
-    int64_t px = round_up(xlead + b.len(0) + nghost, vec);
-    int64_t sc = px * (b.len(1) + 2 * nghost) * (b.len(2) + 2 * nghost);
-    off = round_up(off, fab_align) + sc * ncomp;
-  }
-  *bytes = (size_t)round_up(off, fab_align) * esize;
+  const int esize = dtype == BL_F64 ? 8 : 4;
+  const int64_t A = elem_align(esize);
+  int64_t off = 0;
+  FabGeom f;
+  for (const Box& b : ba->boxes) off = round_up(off + layout_fab(b, nghost, ncomp, A, off, f), A);
+  *bytes = (size_t)off * esize;
   return BL_OK;
 }
 

@@ -326,3 +326,47 @@ def test_batch_alone_equals_in_the_mix(bt):
                 p["done"] = True
     for i in range(len(probs)):
         assert np.array_equal(results[i], alone[i]), i
+
+
+# ----------------------------------------------------------------------------- tile configurations
+TILE_CONFIGS = [(1, 4, 0), (2, 2, 0), (3, 4, 0), (8, 1, 0), (1024, 4, 0), (5, 8, 0), (4, 4, 2), (1024, 2, 3),
+                (8, 16, 1), (16, 1, 0)]
+
+
+@pytest.mark.parametrize("cfg", TILE_CONFIGS)
+@pytest.mark.parametrize("layout", ["uneven", "odd_noncovering"])
+def test_every_tile_configuration_bit_exact(bt, cfg, layout):
+    """Every stencil kernel variant (z-blocked 1/2/4/8, z march, persistent grid)
+    gives the oracle's FP64 result, fused and per box, on ragged tiles."""
+    rng = np.random.default_rng(31)
+    if layout == "uneven":
+        dom, periodic = I.domain_box((64, 48, 40)), (1, 1, 1)
+        boxes = I.random_chop(dom, 8, 32, 8, seed=6)
+    else:
+        dom, periodic = I.domain_box((35, 22, 27)), (0, 1, 1)
+        boxes = I.random_chop(dom, 3, 13, 1, seed=8)
+        boxes = boxes[np.sort(rng.permutation(len(boxes))[: len(boxes) * 4 // 5])]
+    N = tuple(dom[3 + d] + 1 for d in range(3))
+    ncomp, steps, c = 2, 5, 0.15
+    g = rng.random((ncomp,) + N[::-1]) + 1.0
+    saved = bt.get_tile_config()
+    bt.set_tile_config(*cfg)
+    try:
+        say(f"tile cfg {cfg} layout={layout}")
+        _, a, b, o = make_pair(boxes, dom, periodic, ncomp, 1, bt.F64, g, ghost_value=0.25)
+        fused = gpu_global(bt.heat_advance(a, b, steps, c))
+        _, a2, b2, _ = make_pair(boxes, dom, periodic, ncomp, 1, bt.F64, g, ghost_value=0.25)
+        x, y = a2, b2
+        for s in range(steps):
+            if s % 2:
+                bt.heat_step(x, y, c)
+            else:
+                bt.heat_step_unfused(x, y, c)
+            x, y = y, x
+        other = gpu_global(x)
+    finally:
+        bt.set_tile_config(*saved)
+    ref = O.heat_advance(o, steps, c).to_global()
+    m = np.isfinite(ref)
+    assert np.array_equal(fused[m], ref[m])
+    assert np.array_equal(other[m], ref[m])

@@ -164,12 +164,26 @@ def test_tile_list_covers_every_cell_once(dtype, boxes_kind):
         ex, ey, ez = bx[3] - bx[0] + 1, bx[4] - bx[1] + 1, bx[5] - bx[2] + 1
         cover = np.zeros((ncomp, ez, ey, ex), dtype=np.int32)
         for t in tiles[tiles[:, 0] == b]:
-            comp, l0, l1, z0, z1, vec = t[1:]
-            nvx = ex // vec
-            for l in range(l0, l1):
-                y, xv = divmod(l, nvx)
-                cover[comp, z0:z1, y, xv * vec:(xv + 1) * vec] += 1
+            comp, xv0, nvt, y0, rows, z0, z1, vec = t[1:]
+            assert nvt * rows <= 256  # fits the default workgroup
+            cover[comp, z0:z1, y0:y0 + rows, xv0 * vec:(xv0 + nvt) * vec] += 1
         assert cover.min() == 1 and cover.max() == 1
+
+
+def test_tiles_do_not_straddle_face_record_z_boundaries():
+    dom = I.domain_box(128)
+    boxes = I.random_chop(dom, 16, 64, 8, seed=2)
+    ba = bt.BoxArray.from_boxes(boxes, dom)
+    tiles = ba.tile_list(1, 1, bt.F64)
+    faces = ba.face_plan()
+    for b, bx in enumerate(boxes):
+        cuts = set()
+        for r in faces[(faces[:, 0] == b) & (faces[:, 1] < 4)]:
+            cuts.add(int(r[5] - bx[2]))          # region lo z, box-local
+            cuts.add(int(r[8] - bx[2] + 1))      # region hi z + 1
+        for t in tiles[tiles[:, 0] == b]:
+            z0, z1 = t[6], t[7]
+            assert not any(z0 < c < z1 for c in cuts)
 
 
 def test_static_partition_reproduces_the_papers_worked_example():
