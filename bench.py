@@ -92,6 +92,7 @@ def main() -> int:
     ap.add_argument("--zchunk", type=int, default=None)
     ap.add_argument("--waves", type=int, default=None)
     ap.add_argument("--persist", type=int, default=None)
+    ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and unfused measurements")
     args = ap.parse_args()
@@ -108,9 +109,10 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    if args.zchunk or args.waves or args.persist is not None:
-        z, w, p = bt.get_tile_config()
-        bt.set_tile_config(args.zchunk or z, args.waves or w, p if args.persist is None else args.persist)
+    if args.zchunk or args.waves or args.persist is not None or args.block is not None:
+        z, w, p, b = bt.get_tile_config()
+        bt.set_tile_config(args.zchunk or z, args.waves or w, p if args.persist is None else args.persist,
+                           b if args.block is None else args.block)
     cfg_tile = bt.get_tile_config()
 
     n, ncomp = args.n, args.ncomp

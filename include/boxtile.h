@@ -287,13 +287,15 @@ bl_status bl_reduce_async(const bl_multifab* mf, int32_t comp, bl_reduce_op op, 
 
 /*
  * Tile shape of the stencil kernels: zchunk = most z planes per tile (1..16384),
- * waves = 64-lane waves per workgroup (1..16), persist = workgroups per CU of
- * the persistent grid (0: one workgroup per tile).  Applies to MultiFabs
- * created afterwards and to bl_batch objects at their next rebuild; results do
- * not depend on it.
+ * waves = 64-lane waves per workgroup (1..4), persist = workgroups per CU of
+ * the persistent grid (0: one workgroup per tile), block = 1 for the block
+ * form (each tile issues all of its loads before its updates), 2 for the
+ * block form exchanging in-tile neighbours through LDS (zchunk 2, 4 or 8 for
+ * both), 0 for the z march.  Applies to MultiFabs created afterwards and to
+ * bl_batch objects at their next rebuild; results do not depend on it.
  */
-bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist);
-bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist);
+bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int32_t block);
+bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist, int32_t* block);
 
 /* ------------------------------------------------------------------- batching */
 

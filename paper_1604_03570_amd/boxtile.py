@@ -73,8 +73,8 @@ _SIGS = {
     "bl_residual_norm": [_vp, _vp, ctypes.c_double, _dp, _vp],
     "bl_reduce": [_vp, _i32, _i32, _dp, _vp],
     "bl_reduce_async": [_vp, _i32, _i32, _vp, _vp],
-    "bl_set_tile_config": [_i32, _i32, _i32],
-    "bl_get_tile_config": [_i32p, _i32p, _i32p],
+    "bl_set_tile_config": [_i32, _i32, _i32, _i32],
+    "bl_get_tile_config": [_i32p, _i32p, _i32p, _i32p],
     "bl_batch_create": [_vpp],
     "bl_batch_add": [_vp, _vp, _vp, ctypes.c_double, _i32p],
     "bl_batch_remove": [_vp, _i32],
@@ -257,14 +257,14 @@ def static_partition(ntiles: int, nworkers: int) -> list:
     return list(first)
 
 
-def set_tile_config(zchunk: int = 8, waves: int = 4, persist: int = 0) -> None:
-    _check(_L.bl_set_tile_config(zchunk, waves, persist))
+def set_tile_config(zchunk: int = 8, waves: int = 4, persist: int = 0, block: int = 2) -> None:
+    _check(_L.bl_set_tile_config(zchunk, waves, persist, block))
 
 
 def get_tile_config() -> tuple:
-    z, w, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(_L.bl_get_tile_config(ctypes.byref(z), ctypes.byref(w), ctypes.byref(p)))
-    return z.value, w.value, p.value
+    z, w, p, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_L.bl_get_tile_config(ctypes.byref(z), ctypes.byref(w), ctypes.byref(p), ctypes.byref(b)))
+    return z.value, w.value, p.value, b.value
 
 
 # --------------------------------------------------------------------------- MultiFab

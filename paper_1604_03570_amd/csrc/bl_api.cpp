@@ -52,12 +52,12 @@ bl_status upload_plan(Plan& p) {
 
 // Plans are shared by every MultiFab of one shape and tile configuration.
 static std::mutex g_plan_mu;
-static std::map<std::tuple<uint64_t, int, int, int, int, int>, std::weak_ptr<Plan>> g_plans;
+static std::map<std::tuple<uint64_t, int, int, int, int, int, int>, std::weak_ptr<Plan>> g_plans;
 
 static bl_status get_plan(const bl_boxarray* ba, int ncomp, int ng, int dtype, bool to_device,
                           std::shared_ptr<Plan>* out) {
   const TileConfig cfg = tile_config();
-  auto key = std::make_tuple(ba->uid, ncomp, ng, dtype, cfg.zchunk, cfg.waves);
+  auto key = std::make_tuple(ba->uid, ncomp, ng, dtype, cfg.zchunk, cfg.waves, cfg.block);
   std::lock_guard<std::mutex> lk(g_plan_mu);
   auto it = g_plans.find(key);
   std::shared_ptr<Plan> p;
@@ -305,6 +305,8 @@ bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t
   if (fill_first) BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream));
   HeatArgs a{};
   a.fvec = p.fvec;
+  a.zblock = p.cfg.block ? p.cfg.zchunk : 0;
+  a.lds = p.cfg.block == 2;
   a.boxes = p.dboxes;
   a.recs = p.dfacerecs;
   a.m0 = member_of(u_old, u_new, c);
@@ -325,7 +327,7 @@ bl_status bl_heat_step_unfused(bl_multifab* u_old, bl_multifab* u_new, double c,
   const Plan& p = *u_old->plan;
   BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream));
   HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u_old, u_new, c), nullptr, 0,
-             p.fvec};
+             p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block == 2};
   BL_HIP(launch_heat(p.dtype, p.vec, false, a, persistent_grid(tile_config().persist), block_of(p), stream));
   return BL_OK;
 }
@@ -354,7 +356,7 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
     hipStream_t cs = capture_stream();
     if (!cs) return fail(BL_EHIP, "could not create the capture stream");
     HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u[0], u[1], c), nullptr, 0,
-               p.fvec};
+               p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block == 2};
     BL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     // the edge-column mirror of the starting state, then the fused steps
     hipError_t le = launch_extract_mirror(p, u[0]->data, cs);
@@ -464,23 +466,29 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
   return BL_OK;
 }
 
-bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist) {
+bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int32_t block) {
   clear_error();
-  if (zchunk < 1 || zchunk > 16384 || waves < 1 || waves > 16 || persist < 0 || persist > 64)
-    return fail(BL_EINVAL, "need 1 <= zchunk <= 16384, 1 <= waves <= 16, 0 <= persist <= 64");
+  if (zchunk < 1 || zchunk > 16384 || waves < 1 || waves > kStencilMaxThreads / 64 || persist < 0 ||
+      persist > 64 || block < 0 || block > 2)
+    return fail(BL_EINVAL, "need 1 <= zchunk <= 16384, 1 <= waves <= %d, 0 <= persist <= 64, block in {0, 1, 2}",
+                kStencilMaxThreads / 64);
+  if (block && zchunk != 2 && zchunk != 4 && zchunk != 8)
+    return fail(BL_EINVAL, "the block form needs zchunk 2, 4 or 8");
   TileConfig& c = tile_config();
   c.zchunk = zchunk;
   c.waves = waves;
   c.persist = persist;
+  c.block = block;
   return BL_OK;
 }
 
-bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist) {
+bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist, int32_t* block) {
   clear_error();
   const TileConfig& c = tile_config();
   if (zchunk) *zchunk = c.zchunk;
   if (waves) *waves = c.waves;
   if (persist) *persist = c.persist;
+  if (block) *block = c.block;
   return BL_OK;
 }
 
@@ -700,7 +708,8 @@ bl_status bl_batch_step(bl_batch* b, hipStream_t stream) {
   bl_status st;
   if (b->dirty && (st = batch_rebuild(b, stream)) != BL_OK) return st;
   for (auto& g : b->groups) {
-    HeatArgs a{g.dtiles, g.ntiles, g.dboxes, g.drecs, DevMember{}, g.dmembers, (int)(b->tick & 1), g.fvec};
+    HeatArgs a{g.dtiles, g.ntiles, g.dboxes, g.drecs, DevMember{}, g.dmembers, (int)(b->tick & 1), g.fvec,
+               b->cfg.block ? b->cfg.zchunk : 0, b->cfg.block == 2};
     BL_HIP(launch_heat(g.dtype, g.vec, true, a, persistent_grid(b->cfg.persist), 64 * b->cfg.waves, stream));
   }
   b->tick++;

@@ -203,12 +203,14 @@ struct DevFillChunk {
   int32_t start;     // first cell (linear x-fastest index inside the region)
 };
 constexpr int kFillChunk = 256;
+constexpr int kStencilMaxThreads = 256;  // workgroup size limit of the stencil kernels (waves <= 4)
 
 // ---------------------------------------------------------------- layout + plans
 struct TileConfig {
   int zchunk = 8;     // z planes per tile at most
   int waves = 4;      // 64-lane waves per workgroup
   int persist = 0;    // workgroups per CU for the persistent grid (0: one workgroup per tile)
+  int block = 2;      // 0: z march; 1: block form; 2: block form with LDS neighbours (zchunk 2, 4 or 8)
 };
 TileConfig& tile_config();
 

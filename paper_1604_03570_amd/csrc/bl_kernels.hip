@@ -181,8 +181,10 @@ struct EdgeVals {
 // same values as its lanes.
 // FVEC: every y- and z-face source row is vec-aligned, so face rows are one
 // 16-byte load per lane; otherwise face cells are loaded one by one.
-template <typename T, int V, bool FUSED, bool FVEC>
-__global__ void __launch_bounds__(1024)
+// ZB > 0 selects the block form for tiles of at most ZB planes: all of the
+// tile's loads are issued first, then its updates (short, load-heavy waves).
+template <typename T, int V, bool FUSED, bool FVEC, int ZB>
+__global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_waves_per_eu(ZB == 8 ? 2 : 4)))
     k_heat_rows(const DevTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
                 const DevFaceRec* __restrict__ recs, DevMember m0, const DevMember* __restrict__ members, int flip,
                 int persist) {
@@ -284,19 +286,145 @@ __global__ void __launch_bounds__(1024)
       }
     };
 
-    Vec<T, V> pa = plane(z0 - 1), pb = plane(z0), pc = plane(z0 + 1), pd;
-    EdgeVals<T, V> e0, e1;
-    edges(z0, e0);
-    int z = z0;
-    for (; z + 4 <= z1; z += 4) {
-      step(z, pa, pb, pc, pd, e0, e1);
-      step(z + 1, pb, pc, pd, pa, e1, e0);
-      step(z + 2, pc, pd, pa, pb, e0, e1);
-      step(z + 3, pd, pa, pb, pc, e1, e0);
+    if (ZB == 0) {  // march
+      Vec<T, V> pa = plane(z0 - 1), pb = plane(z0), pc = plane(z0 + 1), pd;
+      EdgeVals<T, V> e0, e1;
+      edges(z0, e0);
+      int z = z0;
+      for (; z + 4 <= z1; z += 4) {
+        step(z, pa, pb, pc, pd, e0, e1);
+        step(z + 1, pb, pc, pd, pa, e1, e0);
+        step(z + 2, pc, pd, pa, pb, e0, e1);
+        step(z + 3, pd, pa, pb, pc, e1, e0);
+      }
+      if (z < z1) step(z, pa, pb, pc, pd, e0, e1);
+      if (z + 1 < z1) step(z + 1, pb, pc, pd, pa, e1, e0);
+      if (z + 2 < z1) step(z + 2, pc, pd, pa, pb, e0, e1);
+    } else {  // block: every load of the tile (at most ZB planes) first, then the updates
+      constexpr int NB = ZB > 0 ? ZB : 1;
+      Vec<T, V> P[NB + 2];
+      EdgeVals<T, V> E[NB];
+#pragma unroll
+      for (int k = 0; k < NB + 2; ++k) P[k] = plane(z0 - 1 + k < z1 ? z0 - 1 + k : z1);
+#pragma unroll
+      for (int k = 0; k < NB; ++k) edges(z0 + k < z1 ? z0 + k : z1 - 1, E[k]);
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        if (z0 + k < z1) {
+          Vec<T, V> o;
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            const T xm = e == 0 ? E[k].left : P[k + 1].v[e - 1];
+            const T xp = e == V - 1 ? E[k].right : P[k + 1].v[e + 1];
+            o.v[e] = heat_cell(P[k + 1].v[e], xm, xp, E[k].ym.v[e], E[k].yp.v[e], P[k].v[e], P[k + 2].v[e], c);
+          }
+          const int z = z0 + k;
+          stv<T, V>(wp + (int64_t)z * sz, o);
+          if (FUSED) {
+            if (xlo) mir[(int64_t)z * B.ey] = o.v[0];
+            if (xhi) mir[B.mir_side + (int64_t)z * B.ey] = o.v[V - 1];
+          }
+        }
+      }
     }
-    if (z < z1) step(z, pa, pb, pc, pd, e0, e1);
-    if (z + 1 < z1) step(z + 1, pb, pc, pd, pa, e1, e0);
-    if (z + 2 < z1) step(z + 2, pc, pd, pa, pb, e0, e1);
+  }
+}
+
+// ---------------------------------------------------------------- heat step, LDS block form
+// Tiles of at most ZB planes.  Every lane loads its own ZB+2 planes; only the
+// lanes on the tile's edges load what lies outside the tile (the rows above
+// and below, the x neighbours at the row ends: from the FAB, or through the
+// face records when FUSED).  The tile's planes then go through LDS, from which
+// every lane takes its in-tile x and y neighbours.  One wait for all loads,
+// one barrier, then the updates.  Needs FVEC when FUSED.
+template <typename T, int V, bool FUSED, int ZB>
+__global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_waves_per_eu(ZB == 8 ? 2 : 4)))
+    k_heat_lds(const DevTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+               const DevFaceRec* __restrict__ recs, DevMember m0, const DevMember* __restrict__ members, int flip,
+               int persist) {
+  extern __shared__ unsigned char smem_raw[];
+  Vec<T, V>* sh = reinterpret_cast<Vec<T, V>*>(smem_raw);  // [ZB][blockDim.x]
+  int first, last;
+  tile_range(ntiles, persist, first, last);
+  for (int t = first; t < last; ++t) {
+    const DevTile tl = tiles[t];
+    const DevBox B = boxes[tl.box];
+    const DevMember M = members ? members[tl.member] : m0;
+    const bool swap = ((flip + M.flip_offset) & 1) != 0;
+    const BL_GLOBAL T* __restrict__ u = as_global(static_cast<const T*>(swap ? M.b : M.a));
+    BL_GLOBAL T* __restrict__ w = as_global(static_cast<T*>(swap ? M.a : M.b));
+    const T c = (T)M.c;
+    const TileLane L = tile_lane<V>(tl);
+    const int n = tl.comp, nvt = tl.nvt, rows = tl.rows;
+    const int sy = B.sy, sz = B.sz;
+    const int z0 = tl.z0, z1 = tl.z1;
+    const int yy = L.active ? L.y : tl.y0;
+    const int64_t cb = B.off + (int64_t)n * B.sc + L.x0 + (int64_t)yy * sy;
+    BL_GLOBAL T* wp = w + cb;
+    BL_GLOBAL T* mir = w + B.mir + (int64_t)n * B.sc + yy;
+
+    const int64_t slab_lo = B.xs + (int64_t)n * B.sc + (int64_t)yy * B.ng;
+    const bool xlo = L.xv == 0, xhi = L.xv == B.nvx - 1;
+    int64_t lb = xlo ? slab_lo : cb - 1, rb = xhi ? slab_lo + B.xs_side : cb + V;
+    int64_t ymb = cb - sy, ypb = cb + sy;
+    int ls = xlo ? B.xs_z : sz, rs = xhi ? B.xs_z : sz, yms = sz, yps = sz;
+    int64_t zlo = cb - sz, zhi = cb + (int64_t)B.ez * sz;
+    if (FUSED) {
+      face_source_z(recs, B.face_start[0], B.face_count[0], xlo, yy, z0, n, lb, ls);
+      face_source_z(recs, B.face_start[1], B.face_count[1], xhi, yy, z0, n, rb, rs);
+      if (tl.y0 == 0) face_source_z(recs, B.face_start[2], B.face_count[2], yy == 0, L.x0, z0, n, ymb, yms);
+      if (tl.y0 + rows == B.ey)
+        face_source_z(recs, B.face_start[3], B.face_count[3], yy == B.ey - 1, L.x0, z0, n, ypb, yps);
+      if (z0 == 0) zlo = face_index_xy(recs, B.face_start[4], B.face_count[4], L.x0, yy, n, zlo);
+      if (z1 == B.ez) zhi = face_index_xy(recs, B.face_start[5], B.face_count[5], L.x0, yy, n, zhi);
+    }
+    const bool eL = L.lx == 0, eR = L.lx == nvt - 1, eM = L.ty == 0, eP = L.ty == rows - 1;
+
+    Vec<T, V> P[ZB + 2];
+#pragma unroll
+    for (int k = 0; k < ZB + 2; ++k) {
+      const int z = z0 - 1 + k < z1 ? z0 - 1 + k : z1;
+      int64_t a = cb + (int64_t)z * sz;
+      if (FUSED) a = z < 0 ? zlo : (z >= B.ez ? zhi : a);
+      P[k] = ldv<T, V>(u + a);
+    }
+    T hl[ZB], hr[ZB];
+    Vec<T, V> hm[ZB], hp[ZB];
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
+      const int z = z0 + k < z1 ? z0 + k : z1 - 1;
+      if (eL) hl[k] = u[lb + (int64_t)z * ls];
+      if (eR) hr[k] = u[rb + (int64_t)z * rs];
+      if (eM) hm[k] = ldv<T, V>(u + ymb + (int64_t)z * yms);
+      if (eP) hp[k] = ldv<T, V>(u + ypb + (int64_t)z * yps);
+    }
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) sh[k * blockDim.x + threadIdx.x] = P[k + 1];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
+      const Vec<T, V>* row = sh + k * blockDim.x + threadIdx.x;
+      const T left = eL ? hl[k] : row[-1].v[V - 1];
+      const T right = eR ? hr[k] : row[1].v[0];
+      const Vec<T, V> ym = eM ? hm[k] : row[-nvt];
+      const Vec<T, V> yp = eP ? hp[k] : row[nvt];
+      Vec<T, V> o;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const T xm = e == 0 ? left : P[k + 1].v[e - 1];
+        const T xp = e == V - 1 ? right : P[k + 1].v[e + 1];
+        o.v[e] = heat_cell(P[k + 1].v[e], xm, xp, ym.v[e], yp.v[e], P[k].v[e], P[k + 2].v[e], c);
+      }
+      const int z = z0 + k;
+      if (z < z1 && L.active) {
+        stv<T, V>(wp + (int64_t)z * sz, o);
+        if (FUSED) {
+          if (xlo) mir[(int64_t)z * B.ey] = o.v[0];
+          if (xhi) mir[B.mir_side + (int64_t)z * B.ey] = o.v[V - 1];
+        }
+      }
+    }
+    if (persist) __syncthreads();  // the next tile reuses the LDS buffers
   }
 }
 
@@ -560,18 +688,48 @@ __global__ void __launch_bounds__(1024)
   if (threadIdx.x == 0) partials[blockIdx.x] = r;
 }
 
-template <typename T, int V>
-hipError_t heat_dispatch(bool fused, const HeatArgs& a, int grid, int block, hipStream_t s) {
-  const int persist = grid > 0 ? 1 : 0;
-  const int g = persist ? (grid < a.ntiles ? grid : a.ntiles) : a.ntiles;
-#define BL_LAUNCH_ROWS(F, Y)                                                                                  \
-  hipLaunchKernelGGL((k_heat_rows<T, V, F, Y>), dim3(g), dim3(block), 0, s, a.tiles, a.ntiles, a.boxes, a.recs, \
+template <typename T, int V, int ZB>
+hipError_t heat_dispatch_zb(bool fused, const HeatArgs& a, int g, int block, int persist, hipStream_t s) {
+#define BL_LAUNCH_ROWS(F, Y)                                                                                     \
+  hipLaunchKernelGGL((k_heat_rows<T, V, F, Y, ZB>), dim3(g), dim3(block), 0, s, a.tiles, a.ntiles, a.boxes, a.recs, \
                      a.m0, a.members, a.flip, persist)
   if (!fused) BL_LAUNCH_ROWS(false, true);
   else if (a.fvec) BL_LAUNCH_ROWS(true, true);
   else BL_LAUNCH_ROWS(true, false);
 #undef BL_LAUNCH_ROWS
   return hipGetLastError();
+}
+
+template <typename T, int V, int ZB>
+hipError_t heat_dispatch_lds(bool fused, const HeatArgs& a, int g, int block, int persist, hipStream_t s) {
+  const size_t lds = (size_t)ZB * block * sizeof(Vec<T, V>);
+  if (fused)
+    hipLaunchKernelGGL((k_heat_lds<T, V, true, ZB>), dim3(g), dim3(block), lds, s, a.tiles, a.ntiles, a.boxes, a.recs,
+                       a.m0, a.members, a.flip, persist);
+  else
+    hipLaunchKernelGGL((k_heat_lds<T, V, false, ZB>), dim3(g), dim3(block), lds, s, a.tiles, a.ntiles, a.boxes,
+                       a.recs, a.m0, a.members, a.flip, persist);
+  return hipGetLastError();
+}
+
+template <typename T, int V>
+hipError_t heat_dispatch(bool fused, const HeatArgs& a, int grid, int block, hipStream_t s) {
+  const int persist = grid > 0 ? 1 : 0;
+  const int g = persist ? (grid < a.ntiles ? grid : a.ntiles) : a.ntiles;
+  if (a.lds && (!fused || a.fvec)) {
+    switch (a.zblock) {
+      case 2: return heat_dispatch_lds<T, V, 2>(fused, a, g, block, persist, s);
+      case 4: return heat_dispatch_lds<T, V, 4>(fused, a, g, block, persist, s);
+      case 8: return heat_dispatch_lds<T, V, 8>(fused, a, g, block, persist, s);
+      default: break;
+    }
+  }
+  switch (a.zblock) {
+    case 2: return heat_dispatch_zb<T, V, 2>(fused, a, g, block, persist, s);
+    case 4: return heat_dispatch_zb<T, V, 4>(fused, a, g, block, persist, s);
+    case 8: return heat_dispatch_zb<T, V, 8>(fused, a, g, block, persist, s);
+    default: return heat_dispatch_zb<T, V, 0>(fused, a, g, block, persist, s);
+  }
 }
 
 }  // namespace

@@ -18,6 +18,8 @@ struct HeatArgs {
   const DevMember* members;
   int flip;
   int fvec;                    // 1: every y- and z-face source row allows aligned vector loads
+  int zblock;                  // 2, 4, 8: block form (tiles of at most that many planes); else the march
+  int lds;                     // block form: in-tile neighbours through LDS
 };
 
 // Stencil over `ntiles` tiles.  fused: tiles at box faces read neighbour boxes

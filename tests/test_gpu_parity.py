@@ -329,8 +329,9 @@ def test_batch_alone_equals_in_the_mix(bt):
 
 
 # ----------------------------------------------------------------------------- tile configurations
-TILE_CONFIGS = [(1, 4, 0), (2, 2, 0), (3, 4, 0), (8, 1, 0), (1024, 4, 0), (5, 8, 0), (4, 4, 2), (1024, 2, 3),
-                (8, 16, 1), (16, 1, 0)]
+TILE_CONFIGS = [(1, 4, 0, 0), (2, 2, 0, 0), (3, 4, 0, 0), (8, 1, 0, 0), (1024, 4, 0, 0), (5, 3, 0, 0), (4, 4, 2, 0),
+                (1024, 2, 3, 0), (8, 4, 1, 0), (16, 1, 0, 0), (2, 4, 0, 1), (4, 4, 0, 1), (8, 2, 0, 1), (8, 4, 2, 1),
+                (2, 4, 0, 2), (4, 4, 0, 2), (8, 3, 0, 2), (4, 4, 2, 2), (4, 1, 0, 2)]
 
 
 @pytest.mark.parametrize("cfg", TILE_CONFIGS)
