@@ -291,7 +291,8 @@ bl_status bl_reduce_async(const bl_multifab* mf, int32_t comp, bl_reduce_op op, 
  * the persistent grid (0: one workgroup per tile), block = 1 for the block
  * form (each tile issues all of its loads before its updates), 2 for the
  * block form exchanging in-tile neighbours through LDS (zchunk 2, 4 or 8 for
- * both), 0 for the z march.  Applies to MultiFabs created afterwards and to
+ * both), 0 for the z march.  Default: zchunk 4, waves 4, persist 0, block 2.
+ * Applies to MultiFabs created afterwards and to
  * bl_batch objects at their next rebuild; results do not depend on it.
  */
 bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int32_t block);

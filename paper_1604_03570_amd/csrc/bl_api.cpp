@@ -307,6 +307,7 @@ bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t
   a.fvec = p.fvec;
   a.zblock = p.cfg.block ? p.cfg.zchunk : 0;
   a.lds = p.cfg.block == 2;
+  a.rmax = p.rmax;
   a.boxes = p.dboxes;
   a.recs = p.dfacerecs;
   a.m0 = member_of(u_old, u_new, c);
@@ -327,7 +328,7 @@ bl_status bl_heat_step_unfused(bl_multifab* u_old, bl_multifab* u_new, double c,
   const Plan& p = *u_old->plan;
   BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream));
   HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u_old, u_new, c), nullptr, 0,
-             p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block == 2};
+             p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block == 2, p.rmax};
   BL_HIP(launch_heat(p.dtype, p.vec, false, a, persistent_grid(tile_config().persist), block_of(p), stream));
   return BL_OK;
 }
@@ -356,7 +357,7 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
     hipStream_t cs = capture_stream();
     if (!cs) return fail(BL_EHIP, "could not create the capture stream");
     HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u[0], u[1], c), nullptr, 0,
-               p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block == 2};
+               p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block == 2, p.rmax};
     BL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     // the edge-column mirror of the starting state, then the fused steps
     hipError_t le = launch_extract_mirror(p, u[0]->data, cs);
@@ -573,7 +574,7 @@ struct bl_batch {
     int id;
   };
   struct Group {
-    int dtype = 0, vec = 1, fvec = 1;
+    int dtype = 0, vec = 1, fvec = 1, rmax = 1;
     std::vector<int> members;  // indices into mems
     DevBox* dboxes = nullptr;
     DevFaceRec* drecs = nullptr;
@@ -632,7 +633,7 @@ static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
         boxes.push_back(B);
       }
       recs.insert(recs.end(), p.hfacerecs.begin(), p.hfacerecs.end());
-      build_tiles(p, b->cfg, (int)k, box_base, tiles, nullptr);
+      build_tiles(p, b->cfg, (int)k, box_base, rec_base, tiles, nullptr);
       DevMember dm;
       std::memset(&dm, 0, sizeof dm);
       dm.a = m.u0->data;
@@ -647,6 +648,7 @@ static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
     if ((st = upload(&g.dtiles, tiles, "batch tiles")) != BL_OK) return st;
     if ((st = upload(&g.dmembers, mems, "batch members")) != BL_OK) return st;
     g.ntiles = (int)tiles.size();
+    for (const DevTile& t : tiles) g.rmax = std::max<int>(g.rmax, t.rows);
   }
   // edge-column mirrors of every member's current state
   for (const auto& m : b->mems) {
@@ -709,7 +711,7 @@ bl_status bl_batch_step(bl_batch* b, hipStream_t stream) {
   if (b->dirty && (st = batch_rebuild(b, stream)) != BL_OK) return st;
   for (auto& g : b->groups) {
     HeatArgs a{g.dtiles, g.ntiles, g.dboxes, g.drecs, DevMember{}, g.dmembers, (int)(b->tick & 1), g.fvec,
-               b->cfg.block ? b->cfg.zchunk : 0, b->cfg.block == 2};
+               b->cfg.block ? b->cfg.zchunk : 0, b->cfg.block == 2, g.rmax};
     BL_HIP(launch_heat(g.dtype, g.vec, true, a, persistent_grid(b->cfg.persist), 64 * b->cfg.waves, stream));
   }
   b->tick++;

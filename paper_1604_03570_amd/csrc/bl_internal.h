@@ -164,6 +164,12 @@ static_assert(sizeof(DevFaceRec) == 32, "DevFaceRec size");
 // Lane l of the workgroup takes x vector xv0 + l % nvt of row y0 + l / nvt.
 // Tiles never straddle a z boundary of the box's x- or y-face records, so
 // each lane's face sources are fixed for the whole tile.
+// frec[f]: for each face f of the box that the tile touches, the index of the
+// one face record that covers the tile's part of that face, kFaceMany if
+// several records do (the kernel then searches), kFaceNone if the tile does
+// not touch face f.
+constexpr int32_t kFaceNone = -1;
+constexpr int32_t kFaceMany = -2;
 struct DevTile {
   int32_t box;
   int32_t member;
@@ -172,9 +178,10 @@ struct DevTile {
   int16_t y0, rows;
   int16_t z0, z1;
   int16_t pad0_;
-  int32_t pad1_[2];
+  int32_t frec[6];
+  int32_t pad1_[4];
 };
-static_assert(sizeof(DevTile) == 32, "DevTile size");
+static_assert(sizeof(DevTile) == 64, "DevTile size");
 
 // One heat problem of a launch: at launch flip f it reads a and writes b when
 // (f + flip_offset) is even, and the reverse when it is odd.
@@ -207,7 +214,7 @@ constexpr int kStencilMaxThreads = 256;  // workgroup size limit of the stencil 
 
 // ---------------------------------------------------------------- layout + plans
 struct TileConfig {
-  int zchunk = 8;     // z planes per tile at most
+  int zchunk = 4;     // z planes per tile at most
   int waves = 4;      // 64-lane waves per workgroup
   int persist = 0;    // workgroups per CU for the persistent grid (0: one workgroup per tile)
   int block = 2;      // 0: z march; 1: block form; 2: block form with LDS neighbours (zchunk 2, 4 or 8)
@@ -250,6 +257,7 @@ struct Plan {
   std::vector<DevFaceRec> hfacerecs;
   std::vector<DevTile> htiles;            // all components
   std::vector<int> box_tile_start;        // tiles of box b = [start[b], start[b+1])
+  int rmax = 1;                           // most rows of any tile
   std::vector<DevFillRec> hfillrecs;
   std::vector<DevFillChunk> hfillchunks;
   std::shared_ptr<const std::vector<FillRecord>> fill;
@@ -270,7 +278,7 @@ bl_status build_plan(const bl_boxarray* ba, int ncomp, int ng, int dtype, std::s
 bl_status upload_plan(Plan& p);  // allocates and copies device metadata (once)
 std::shared_ptr<const std::vector<FillRecord>> fill_plan(bl_boxarray* ba, int ng);
 std::shared_ptr<const std::vector<FaceRecord>> face_plan(bl_boxarray* ba, int ng);
-void build_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base,
+void build_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base, int rec_base,
                  std::vector<DevTile>& tiles, std::vector<int>* box_tile_start);
 
 }  // namespace bl

@@ -331,19 +331,48 @@ __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_wave
 }
 
 // ---------------------------------------------------------------- heat step, LDS block form
+// Source (base + z*step) of face cell (t1, z) of x or y face f for lanes with
+// `want`, from the tile's resolved record fr (one record covers the tile's
+// part of the face: a uniform scalar read) or, for kFaceMany, by search.
+__device__ __forceinline__ void tile_face_source(const DevFaceRec* __restrict__ recs, const DevBox& B, int f,
+                                                 int32_t fr, bool want, int t1, int z0, int comp, int64_t& base,
+                                                 int& step) {
+  if (fr >= 0) {
+    const DevFaceRec R = recs[fr];
+    base = want ? R.base + (int64_t)t1 * R.s1 + (int64_t)comp * R.sc : base;
+    step = want ? R.s2 : step;
+  } else if (fr == kFaceMany) {
+    face_source_z(recs, B.face_start[f], B.face_count[f], want, t1, z0, comp, base, step);
+  }
+}
+
+// Element index of z-face cell (t1, t2) = (x, y) of face f (4 or 5).
+__device__ __forceinline__ int64_t tile_face_index(const DevFaceRec* __restrict__ recs, const DevBox& B, int f,
+                                                   int32_t fr, int t1, int t2, int comp, int64_t fallback) {
+  if (fr >= 0) {
+    const DevFaceRec R = recs[fr];
+    return R.base + (int64_t)t1 * R.s1 + (int64_t)t2 * R.s2 + (int64_t)comp * R.sc;
+  }
+  if (fr == kFaceMany) return face_index_xy(recs, B.face_start[f], B.face_count[f], t1, t2, comp, fallback);
+  return fallback;
+}
+
 // Tiles of at most ZB planes.  Every lane loads its own ZB+2 planes; only the
 // lanes on the tile's edges load what lies outside the tile (the rows above
 // and below, the x neighbours at the row ends: from the FAB, or through the
 // face records when FUSED).  The tile's planes then go through LDS, from which
 // every lane takes its in-tile x and y neighbours.  One wait for all loads,
-// one barrier, then the updates.  Needs FVEC when FUSED.
+// one barrier, then the updates.  FUSED: the new edge columns are gathered in
+// LDS and written to the mirror with one coalesced store.  Needs FVEC when FUSED.
+// LDS: ZB*blockDim vectors of planes, then 2*ZB*rmax mirror values.
 template <typename T, int V, bool FUSED, int ZB>
 __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_waves_per_eu(ZB == 8 ? 2 : 4)))
     k_heat_lds(const DevTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
                const DevFaceRec* __restrict__ recs, DevMember m0, const DevMember* __restrict__ members, int flip,
-               int persist) {
+               int persist, int rmax) {
   extern __shared__ unsigned char smem_raw[];
   Vec<T, V>* sh = reinterpret_cast<Vec<T, V>*>(smem_raw);  // [ZB][blockDim.x]
+  T* shm = reinterpret_cast<T*>(sh + ZB * blockDim.x);     // [2][ZB][rmax]
   int first, last;
   tile_range(ntiles, persist, first, last);
   for (int t = first; t < last; ++t) {
@@ -361,25 +390,13 @@ __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_wave
     const int yy = L.active ? L.y : tl.y0;
     const int64_t cb = B.off + (int64_t)n * B.sc + L.x0 + (int64_t)yy * sy;
     BL_GLOBAL T* wp = w + cb;
-    BL_GLOBAL T* mir = w + B.mir + (int64_t)n * B.sc + yy;
 
-    const int64_t slab_lo = B.xs + (int64_t)n * B.sc + (int64_t)yy * B.ng;
-    const bool xlo = L.xv == 0, xhi = L.xv == B.nvx - 1;
-    int64_t lb = xlo ? slab_lo : cb - 1, rb = xhi ? slab_lo + B.xs_side : cb + V;
-    int64_t ymb = cb - sy, ypb = cb + sy;
-    int ls = xlo ? B.xs_z : sz, rs = xhi ? B.xs_z : sz, yms = sz, yps = sz;
+    // the lane's own planes first (z-face planes through the face records)
     int64_t zlo = cb - sz, zhi = cb + (int64_t)B.ez * sz;
     if (FUSED) {
-      face_source_z(recs, B.face_start[0], B.face_count[0], xlo, yy, z0, n, lb, ls);
-      face_source_z(recs, B.face_start[1], B.face_count[1], xhi, yy, z0, n, rb, rs);
-      if (tl.y0 == 0) face_source_z(recs, B.face_start[2], B.face_count[2], yy == 0, L.x0, z0, n, ymb, yms);
-      if (tl.y0 + rows == B.ey)
-        face_source_z(recs, B.face_start[3], B.face_count[3], yy == B.ey - 1, L.x0, z0, n, ypb, yps);
-      if (z0 == 0) zlo = face_index_xy(recs, B.face_start[4], B.face_count[4], L.x0, yy, n, zlo);
-      if (z1 == B.ez) zhi = face_index_xy(recs, B.face_start[5], B.face_count[5], L.x0, yy, n, zhi);
+      if (z0 == 0) zlo = tile_face_index(recs, B, 4, tl.frec[4], L.x0, yy, n, zlo);
+      if (z1 == B.ez) zhi = tile_face_index(recs, B, 5, tl.frec[5], L.x0, yy, n, zhi);
     }
-    const bool eL = L.lx == 0, eR = L.lx == nvt - 1, eM = L.ty == 0, eP = L.ty == rows - 1;
-
     Vec<T, V> P[ZB + 2];
 #pragma unroll
     for (int k = 0; k < ZB + 2; ++k) {
@@ -388,6 +405,20 @@ __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_wave
       if (FUSED) a = z < 0 ? zlo : (z >= B.ez ? zhi : a);
       P[k] = ldv<T, V>(u + a);
     }
+
+    // sources of what lies outside the tile
+    const int64_t slab_lo = B.xs + (int64_t)n * B.sc + (int64_t)yy * B.ng;
+    const bool xlo = L.xv == 0, xhi = L.xv == B.nvx - 1;
+    int64_t lb = xlo ? slab_lo : cb - 1, rb = xhi ? slab_lo + B.xs_side : cb + V;
+    int64_t ymb = cb - sy, ypb = cb + sy;
+    int ls = xlo ? B.xs_z : sz, rs = xhi ? B.xs_z : sz, yms = sz, yps = sz;
+    if (FUSED) {
+      tile_face_source(recs, B, 0, tl.frec[0], xlo, yy, z0, n, lb, ls);
+      tile_face_source(recs, B, 1, tl.frec[1], xhi, yy, z0, n, rb, rs);
+      tile_face_source(recs, B, 2, tl.frec[2], yy == 0, L.x0, z0, n, ymb, yms);
+      tile_face_source(recs, B, 3, tl.frec[3], yy == B.ey - 1, L.x0, z0, n, ypb, yps);
+    }
+    const bool eL = L.lx == 0, eR = L.lx == nvt - 1, eM = L.ty == 0, eP = L.ty == rows - 1;
     T hl[ZB], hr[ZB];
     Vec<T, V> hm[ZB], hp[ZB];
 #pragma unroll
@@ -416,11 +447,21 @@ __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_wave
         o.v[e] = heat_cell(P[k + 1].v[e], xm, xp, ym.v[e], yp.v[e], P[k].v[e], P[k + 2].v[e], c);
       }
       const int z = z0 + k;
-      if (z < z1 && L.active) {
-        stv<T, V>(wp + (int64_t)z * sz, o);
-        if (FUSED) {
-          if (xlo) mir[(int64_t)z * B.ey] = o.v[0];
-          if (xhi) mir[B.mir_side + (int64_t)z * B.ey] = o.v[V - 1];
+      if (z < z1 && L.active) stv<T, V>(wp + (int64_t)z * sz, o);
+      if (FUSED && L.active) {  // this tile's share of the new edge columns, staged in LDS
+        if (xlo) shm[(0 * ZB + k) * rmax + L.ty] = o.v[0];
+        if (xhi) shm[(1 * ZB + k) * rmax + L.ty] = o.v[V - 1];
+      }
+    }
+    if (FUSED) {
+      const bool has_lo = tl.xv0 == 0, has_hi = tl.xv0 + nvt == B.nvx;
+      if (has_lo || has_hi) {
+        __syncthreads();
+        BL_GLOBAL T* mir = w + B.mir + (int64_t)n * B.sc + tl.y0;
+        for (int q = threadIdx.x; q < 2 * ZB * rows; q += blockDim.x) {
+          const int side = q / (ZB * rows), k = (q / rows) % ZB, r = q % rows;
+          if (z0 + k < z1 && (side ? has_hi : has_lo))
+            mir[side * B.mir_side + (int64_t)(z0 + k) * B.ey + r] = shm[(side * ZB + k) * rmax + r];
         }
       }
     }
@@ -702,13 +743,14 @@ hipError_t heat_dispatch_zb(bool fused, const HeatArgs& a, int g, int block, int
 
 template <typename T, int V, int ZB>
 hipError_t heat_dispatch_lds(bool fused, const HeatArgs& a, int g, int block, int persist, hipStream_t s) {
-  const size_t lds = (size_t)ZB * block * sizeof(Vec<T, V>);
+  const int rmax = a.rmax > 0 ? a.rmax : block;
+  const size_t lds = (size_t)ZB * block * sizeof(Vec<T, V>) + (fused ? (size_t)2 * ZB * rmax * sizeof(T) : 0);
   if (fused)
     hipLaunchKernelGGL((k_heat_lds<T, V, true, ZB>), dim3(g), dim3(block), lds, s, a.tiles, a.ntiles, a.boxes, a.recs,
-                       a.m0, a.members, a.flip, persist);
+                       a.m0, a.members, a.flip, persist, rmax);
   else
     hipLaunchKernelGGL((k_heat_lds<T, V, false, ZB>), dim3(g), dim3(block), lds, s, a.tiles, a.ntiles, a.boxes,
-                       a.recs, a.m0, a.members, a.flip, persist);
+                       a.recs, a.m0, a.members, a.flip, persist, rmax);
   return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ struct HeatArgs {
   int fvec;                    // 1: every y- and z-face source row allows aligned vector loads
   int zblock;                  // 2, 4, 8: block form (tiles of at most that many planes); else the march
   int lds;                     // block form: in-tile neighbours through LDS
+  int rmax;                    // most rows of any tile of the launch (sizes the LDS mirror stage)
 };
 
 // Stencil over `ntiles` tiles.  fused: tiles at box faces read neighbour boxes

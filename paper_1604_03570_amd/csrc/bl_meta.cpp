@@ -394,8 +394,23 @@ std::shared_ptr<const std::vector<FaceRecord>> face_plan(bl_boxarray* ba, int ng
 // ---------------------------------------------------------------- layout, records, tiles
 static int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
 
-void build_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base, std::vector<DevTile>& tiles,
-                 std::vector<int>* box_tile_start) {
+// Index of the face record of box B, face f, covering the tangential
+// rectangle [a1, b1] x [a2, b2] (box-local) entirely, or kFaceMany.
+static int32_t covering_record(const Plan& p, const DevBox& B, int f, int a1, int b1, int a2, int b2) {
+  int32_t found = kFaceMany;
+  for (int r = B.face_start[f]; r < B.face_start[f] + B.face_count[f]; ++r) {
+    const DevFaceRec& R = p.hfacerecs[r];
+    const bool overlap = !(b1 < R.t1lo || a1 > R.t1hi || b2 < R.t2lo || a2 > R.t2hi);
+    if (!overlap) continue;
+    const bool covers = a1 >= R.t1lo && b1 <= R.t1hi && a2 >= R.t2lo && b2 <= R.t2hi;
+    if (!covers) return kFaceMany;
+    found = r;
+  }
+  return found;
+}
+
+void build_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base, int rec_base,
+                 std::vector<DevTile>& tiles, std::vector<int>* box_tile_start) {
   const int lanes = 64 * cfg.waves;
   if (box_tile_start) box_tile_start->clear();
   std::vector<int> zc;
@@ -415,10 +430,12 @@ void build_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base,
     zc.erase(std::unique(zc.begin(), zc.end()), zc.end());
     const int nvt_full = std::min(B.nvx, lanes);
     const int rows_full = std::max(1, std::min(B.ey, lanes / nvt_full));
+    // consecutive tiles cover consecutive memory: the row groups of one z range
+    // come together, then the next z range
     for (int n = 0; n < p.ncomp; ++n)
-      for (int xv0 = 0; xv0 < B.nvx; xv0 += nvt_full)
-        for (int y0 = 0; y0 < B.ey; y0 += rows_full)
-          for (size_t k = 0; k + 1 < zc.size(); ++k) {
+      for (size_t k = 0; k + 1 < zc.size(); ++k)
+        for (int xv0 = 0; xv0 < B.nvx; xv0 += nvt_full)
+          for (int y0 = 0; y0 < B.ey; y0 += rows_full) {
             DevTile t;
             std::memset(&t, 0, sizeof t);
             t.box = box_base + b;
@@ -430,6 +447,18 @@ void build_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base,
             t.rows = (int16_t)std::min(rows_full, B.ey - y0);
             t.z0 = (int16_t)zc[k];
             t.z1 = (int16_t)zc[k + 1];
+            const int x0 = xv0 * p.vec, x1 = (xv0 + t.nvt) * p.vec - 1;
+            const int y1 = y0 + t.rows - 1, z1 = t.z1 - 1;
+            const bool touch[6] = {xv0 == 0, xv0 + t.nvt == B.nvx, y0 == 0, y0 + t.rows == B.ey, t.z0 == 0,
+                                   t.z1 == B.ez};
+            const int rect[6][4] = {{y0, y1, t.z0, z1}, {y0, y1, t.z0, z1}, {x0, x1, t.z0, z1},
+                                    {x0, x1, t.z0, z1}, {x0, x1, y0, y1},   {x0, x1, y0, y1}};
+            for (int f = 0; f < 6; ++f) {
+              t.frec[f] = kFaceNone;
+              if (!touch[f]) continue;
+              const int32_t r = covering_record(p, B, f, rect[f][0], rect[f][1], rect[f][2], rect[f][3]);
+              t.frec[f] = r >= 0 ? r + rec_base : r;
+            }
             tiles.push_back(t);
           }
   }
@@ -630,7 +659,8 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, std::
   }
 
   p->cfg = tile_config();
-  build_tiles(*p, p->cfg, 0, 0, p->htiles, &p->box_tile_start);
+  build_tiles(*p, p->cfg, 0, 0, 0, p->htiles, &p->box_tile_start);
+  for (const DevTile& t : p->htiles) p->rmax = std::max<int>(p->rmax, t.rows);
   *out = p;
   return BL_OK;
 }
