@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GCell-updates/s + % HBM roofline (heat_step+FillBoundary); p50/p99 serve latency"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 2 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat_fused_cfg2_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1604_03570_amd", "csrc", "bl_kernels.hip")
 
@@ -83,8 +84,8 @@ def cpu_baseline(boxes, dom, u0, c, nthreads_note: str):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--n", type=int, default=512, help="domain edge")
     ap.add_argument("--ncomp", type=int, default=5)
@@ -95,6 +96,8 @@ def main() -> int:
     ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and unfused measurements")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with three plain device copies of 2 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -204,6 +207,19 @@ def main() -> int:
             log(f"f32: {v32:.1f} GCell/s")
             del a32, b32, ba32
             torch.cuda.empty_cache()
+
+    if args.calibrate_copy:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
+        # give the scale of those counters on this device
+        torch.cuda.empty_cache()
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {COPY_BYTES} bytes")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -290,8 +290,9 @@ bl_status bl_reduce_async(const bl_multifab* mf, int32_t comp, bl_reduce_op op, 
  * waves = 64-lane waves per workgroup (1..4), persist = workgroups per CU of
  * the persistent grid (0: one workgroup per tile), block = 1 for the block
  * form (each tile issues all of its loads before its updates), 2 for the
- * block form exchanging in-tile neighbours through LDS (zchunk 2, 4 or 8 for
- * both), 0 for the z march.  Default: zchunk 4, waves 4, persist 0, block 2.
+ * block form exchanging in-tile neighbours through LDS, 3 for that form with
+ * the tile's halo loaded from memory straight into LDS (zchunk 2, 4 or 8 for
+ * the block forms), 0 for the z march.  Default: zchunk 4, waves 4, persist 0, block 3.
  * Applies to MultiFabs created afterwards and to
  * bl_batch objects at their next rebuild; results do not depend on it.
  */

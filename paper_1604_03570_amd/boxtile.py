@@ -257,7 +257,7 @@ def static_partition(ntiles: int, nworkers: int) -> list:
     return list(first)
 
 
-def set_tile_config(zchunk: int = 4, waves: int = 4, persist: int = 0, block: int = 2) -> None:
+def set_tile_config(zchunk: int = 4, waves: int = 4, persist: int = 0, block: int = 3) -> None:
     _check(_L.bl_set_tile_config(zchunk, waves, persist, block))
 
 

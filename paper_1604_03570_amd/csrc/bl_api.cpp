@@ -306,8 +306,9 @@ bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t
   HeatArgs a{};
   a.fvec = p.fvec;
   a.zblock = p.cfg.block ? p.cfg.zchunk : 0;
-  a.lds = p.cfg.block == 2;
+  a.form = p.cfg.block;
   a.rmax = p.rmax;
+  a.nvtmax = p.nvtmax;
   a.boxes = p.dboxes;
   a.recs = p.dfacerecs;
   a.m0 = member_of(u_old, u_new, c);
@@ -328,7 +329,7 @@ bl_status bl_heat_step_unfused(bl_multifab* u_old, bl_multifab* u_new, double c,
   const Plan& p = *u_old->plan;
   BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream));
   HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u_old, u_new, c), nullptr, 0,
-             p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block == 2, p.rmax};
+             p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block, p.rmax, p.nvtmax};
   BL_HIP(launch_heat(p.dtype, p.vec, false, a, persistent_grid(tile_config().persist), block_of(p), stream));
   return BL_OK;
 }
@@ -357,7 +358,7 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
     hipStream_t cs = capture_stream();
     if (!cs) return fail(BL_EHIP, "could not create the capture stream");
     HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u[0], u[1], c), nullptr, 0,
-               p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block == 2, p.rmax};
+               p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block, p.rmax, p.nvtmax};
     BL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     // the edge-column mirror of the starting state, then the fused steps
     hipError_t le = launch_extract_mirror(p, u[0]->data, cs);
@@ -470,8 +471,8 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
 bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int32_t block) {
   clear_error();
   if (zchunk < 1 || zchunk > 16384 || waves < 1 || waves > kStencilMaxThreads / 64 || persist < 0 ||
-      persist > 64 || block < 0 || block > 2)
-    return fail(BL_EINVAL, "need 1 <= zchunk <= 16384, 1 <= waves <= %d, 0 <= persist <= 64, block in {0, 1, 2}",
+      persist > 64 || block < 0 || block > 3)
+    return fail(BL_EINVAL, "need 1 <= zchunk <= 16384, 1 <= waves <= %d, 0 <= persist <= 64, block in {0, 1, 2, 3}",
                 kStencilMaxThreads / 64);
   if (block && zchunk != 2 && zchunk != 4 && zchunk != 8)
     return fail(BL_EINVAL, "the block form needs zchunk 2, 4 or 8");
@@ -574,7 +575,7 @@ struct bl_batch {
     int id;
   };
   struct Group {
-    int dtype = 0, vec = 1, fvec = 1, rmax = 1;
+    int dtype = 0, vec = 1, fvec = 1, rmax = 1, nvtmax = 1;
     std::vector<int> members;  // indices into mems
     DevBox* dboxes = nullptr;
     DevFaceRec* drecs = nullptr;
@@ -648,7 +649,10 @@ static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
     if ((st = upload(&g.dtiles, tiles, "batch tiles")) != BL_OK) return st;
     if ((st = upload(&g.dmembers, mems, "batch members")) != BL_OK) return st;
     g.ntiles = (int)tiles.size();
-    for (const DevTile& t : tiles) g.rmax = std::max<int>(g.rmax, t.rows);
+    for (const DevTile& t : tiles) {
+      g.rmax = std::max<int>(g.rmax, t.rows);
+      g.nvtmax = std::max<int>(g.nvtmax, t.nvt);
+    }
   }
   // edge-column mirrors of every member's current state
   for (const auto& m : b->mems) {
@@ -711,7 +715,7 @@ bl_status bl_batch_step(bl_batch* b, hipStream_t stream) {
   if (b->dirty && (st = batch_rebuild(b, stream)) != BL_OK) return st;
   for (auto& g : b->groups) {
     HeatArgs a{g.dtiles, g.ntiles, g.dboxes, g.drecs, DevMember{}, g.dmembers, (int)(b->tick & 1), g.fvec,
-               b->cfg.block ? b->cfg.zchunk : 0, b->cfg.block == 2, g.rmax};
+               b->cfg.block ? b->cfg.zchunk : 0, b->cfg.block, g.rmax, g.nvtmax};
     BL_HIP(launch_heat(g.dtype, g.vec, true, a, persistent_grid(b->cfg.persist), 64 * b->cfg.waves, stream));
   }
   b->tick++;

@@ -170,16 +170,15 @@ static_assert(sizeof(DevFaceRec) == 32, "DevFaceRec size");
 // not touch face f.
 constexpr int32_t kFaceNone = -1;
 constexpr int32_t kFaceMany = -2;
-struct DevTile {
+struct DevTile {    // 32-bit fields only: each one is a plain scalar load
   int32_t box;
   int32_t member;
-  int16_t comp;
-  int16_t xv0, nvt;
-  int16_t y0, rows;
-  int16_t z0, z1;
-  int16_t pad0_;
+  int32_t comp;
+  int32_t xv0, nvt;
+  int32_t y0, rows;
+  int32_t z0, z1;
   int32_t frec[6];
-  int32_t pad1_[4];
+  int32_t pad_;
 };
 static_assert(sizeof(DevTile) == 64, "DevTile size");
 
@@ -211,13 +210,15 @@ struct DevFillChunk {
 };
 constexpr int kFillChunk = 256;
 constexpr int kStencilMaxThreads = 256;  // workgroup size limit of the stencil kernels (waves <= 4)
+constexpr size_t kDmaLdsMax = 65536;     // LDS of one workgroup of the halo-in-LDS stencil form, at most
 
 // ---------------------------------------------------------------- layout + plans
 struct TileConfig {
   int zchunk = 4;     // z planes per tile at most
   int waves = 4;      // 64-lane waves per workgroup
   int persist = 0;    // workgroups per CU for the persistent grid (0: one workgroup per tile)
-  int block = 2;      // 0: z march; 1: block form; 2: block form with LDS neighbours (zchunk 2, 4 or 8)
+  int block = 3;      // 0: z march; 1: block form; 2: block form with LDS neighbours; 3: as 2, halos
+                      // loaded straight into LDS (block forms: zchunk 2, 4 or 8)
 };
 TileConfig& tile_config();
 
@@ -258,6 +259,7 @@ struct Plan {
   std::vector<DevTile> htiles;            // all components
   std::vector<int> box_tile_start;        // tiles of box b = [start[b], start[b+1])
   int rmax = 1;                           // most rows of any tile
+  int nvtmax = 1;                         // most x vectors of any tile
   std::vector<DevFillRec> hfillrecs;
   std::vector<DevFillChunk> hfillchunks;
   std::shared_ptr<const std::vector<FillRecord>> fill;

@@ -67,6 +67,28 @@ __device__ __forceinline__ BL_GLOBAL T* as_global(T* p) {
   return (BL_GLOBAL T*)p;
 }
 
+// Descriptor tables (tiles, boxes, face and fill records, members) are never
+// written by a kernel; reading them through the constant address space lets a
+// workgroup-uniform index become a scalar load.  Otherwise a store or an LDS
+// load elsewhere in the kernel can turn them into vector loads, whose waits
+// then also wait for every data load in flight.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define BL_CONST __attribute__((address_space(4)))
+#else
+#define BL_CONST
+#endif
+template <typename T>
+__device__ __forceinline__ T ldc(const T* p) {
+  return *(const BL_CONST T*)p;
+}
+
+// Workgroup barrier ordering LDS only: waits for this wave's LDS accesses, not
+// for its global stores (__syncthreads also drains those).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt left open
+  __builtin_amdgcn_s_barrier();
+}
+
 // forward Euler, second-order centred differences (Sec. 4.1 of the paper):
 // u + c*(((xm+xp) + (ym+yp)) + (zm+zp) - 6u), c = dt/dx^2
 template <typename T>
@@ -140,7 +162,7 @@ __device__ __forceinline__ TileLane tile_lane(const DevTile& tl) {
 __device__ __forceinline__ void face_source_z(const DevFaceRec* __restrict__ recs, int start, int count, bool want,
                                               int t1, int t2, int comp, int64_t& base, int& step) {
   for (int r = start; r < start + count; ++r) {
-    const DevFaceRec R = recs[r];
+    const DevFaceRec R = ldc(recs + r);
     const bool in = want & (t1 >= R.t1lo) & (t1 <= R.t1hi) & (t2 >= R.t2lo) & (t2 <= R.t2hi);
     const int64_t b = R.base + (int64_t)t1 * R.s1 + (int64_t)comp * R.sc;
     base = in ? b : base;
@@ -153,7 +175,7 @@ __device__ __forceinline__ int64_t face_index_xy(const DevFaceRec* __restrict__ 
                                                  int t2, int comp, int64_t fallback) {
   int64_t idx = fallback;
   for (int r = start; r < start + count; ++r) {
-    const DevFaceRec R = recs[r];
+    const DevFaceRec R = ldc(recs + r);
     const bool in = (t1 >= R.t1lo) & (t1 <= R.t1hi) & (t2 >= R.t2lo) & (t2 <= R.t2hi);
     const int64_t b = R.base + (int64_t)t1 * R.s1 + (int64_t)t2 * R.s2 + (int64_t)comp * R.sc;
     idx = in ? b : idx;
@@ -191,9 +213,9 @@ __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_wave
   int first, last;
   tile_range(ntiles, persist, first, last);
   for (int t = first; t < last; ++t) {
-    const DevTile tl = tiles[t];
-    const DevBox B = boxes[tl.box];
-    const DevMember M = members ? members[tl.member] : m0;
+    const DevTile tl = ldc(tiles + t);
+    const DevBox B = ldc(boxes + tl.box);
+    const DevMember M = members ? ldc(members + tl.member) : m0;
     const bool swap = ((flip + M.flip_offset) & 1) != 0;
     const BL_GLOBAL T* __restrict__ u = as_global(static_cast<const T*>(swap ? M.b : M.a));
     BL_GLOBAL T* __restrict__ w = as_global(static_cast<T*>(swap ? M.a : M.b));
@@ -331,29 +353,32 @@ __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_wave
 }
 
 // ---------------------------------------------------------------- heat step, LDS block form
-// Source (base + z*step) of face cell (t1, z) of x or y face f for lanes with
-// `want`, from the tile's resolved record fr (one record covers the tile's
-// part of the face: a uniform scalar read) or, for kFaceMany, by search.
-__device__ __forceinline__ void tile_face_source(const DevFaceRec* __restrict__ recs, const DevBox& B, int f,
-                                                 int32_t fr, bool want, int t1, int z0, int comp, int64_t& base,
+// Source (base + z*step) of face cell (t1, z) of an x or y face for lanes with
+// `want`, from the tile's resolved record fr of that face (one record covers
+// the tile's part of the face: a uniform scalar read) or, for kFaceMany, by
+// search over the face's records [start, start+count).  Callers pick fr, start
+// and count with constant indices: a variable index into the tile or box
+// descriptor would move the descriptor to scratch memory.
+__device__ __forceinline__ void tile_face_source(const DevFaceRec* __restrict__ recs, int32_t fr, int start,
+                                                 int count, bool want, int t1, int z0, int comp, int64_t& base,
                                                  int& step) {
   if (fr >= 0) {
-    const DevFaceRec R = recs[fr];
+    const DevFaceRec R = ldc(recs + fr);
     base = want ? R.base + (int64_t)t1 * R.s1 + (int64_t)comp * R.sc : base;
     step = want ? R.s2 : step;
   } else if (fr == kFaceMany) {
-    face_source_z(recs, B.face_start[f], B.face_count[f], want, t1, z0, comp, base, step);
+    face_source_z(recs, start, count, want, t1, z0, comp, base, step);
   }
 }
 
-// Element index of z-face cell (t1, t2) = (x, y) of face f (4 or 5).
-__device__ __forceinline__ int64_t tile_face_index(const DevFaceRec* __restrict__ recs, const DevBox& B, int f,
-                                                   int32_t fr, int t1, int t2, int comp, int64_t fallback) {
+// Element index of z-face cell (t1, t2) = (x, y), as above.
+__device__ __forceinline__ int64_t tile_face_index(const DevFaceRec* __restrict__ recs, int32_t fr, int start,
+                                                   int count, int t1, int t2, int comp, int64_t fallback) {
   if (fr >= 0) {
-    const DevFaceRec R = recs[fr];
+    const DevFaceRec R = ldc(recs + fr);
     return R.base + (int64_t)t1 * R.s1 + (int64_t)t2 * R.s2 + (int64_t)comp * R.sc;
   }
-  if (fr == kFaceMany) return face_index_xy(recs, B.face_start[f], B.face_count[f], t1, t2, comp, fallback);
+  if (fr == kFaceMany) return face_index_xy(recs, start, count, t1, t2, comp, fallback);
   return fallback;
 }
 
@@ -376,9 +401,9 @@ __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_wave
   int first, last;
   tile_range(ntiles, persist, first, last);
   for (int t = first; t < last; ++t) {
-    const DevTile tl = tiles[t];
-    const DevBox B = boxes[tl.box];
-    const DevMember M = members ? members[tl.member] : m0;
+    const DevTile tl = ldc(tiles + t);
+    const DevBox B = ldc(boxes + tl.box);
+    const DevMember M = members ? ldc(members + tl.member) : m0;
     const bool swap = ((flip + M.flip_offset) & 1) != 0;
     const BL_GLOBAL T* __restrict__ u = as_global(static_cast<const T*>(swap ? M.b : M.a));
     BL_GLOBAL T* __restrict__ w = as_global(static_cast<T*>(swap ? M.a : M.b));
@@ -394,8 +419,8 @@ __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_wave
     // the lane's own planes first (z-face planes through the face records)
     int64_t zlo = cb - sz, zhi = cb + (int64_t)B.ez * sz;
     if (FUSED) {
-      if (z0 == 0) zlo = tile_face_index(recs, B, 4, tl.frec[4], L.x0, yy, n, zlo);
-      if (z1 == B.ez) zhi = tile_face_index(recs, B, 5, tl.frec[5], L.x0, yy, n, zhi);
+      if (z0 == 0) zlo = tile_face_index(recs, tl.frec[4], B.face_start[4], B.face_count[4], L.x0, yy, n, zlo);
+      if (z1 == B.ez) zhi = tile_face_index(recs, tl.frec[5], B.face_start[5], B.face_count[5], L.x0, yy, n, zhi);
     }
     Vec<T, V> P[ZB + 2];
 #pragma unroll
@@ -413,10 +438,10 @@ __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_wave
     int64_t ymb = cb - sy, ypb = cb + sy;
     int ls = xlo ? B.xs_z : sz, rs = xhi ? B.xs_z : sz, yms = sz, yps = sz;
     if (FUSED) {
-      tile_face_source(recs, B, 0, tl.frec[0], xlo, yy, z0, n, lb, ls);
-      tile_face_source(recs, B, 1, tl.frec[1], xhi, yy, z0, n, rb, rs);
-      tile_face_source(recs, B, 2, tl.frec[2], yy == 0, L.x0, z0, n, ymb, yms);
-      tile_face_source(recs, B, 3, tl.frec[3], yy == B.ey - 1, L.x0, z0, n, ypb, yps);
+      tile_face_source(recs, tl.frec[0], B.face_start[0], B.face_count[0], xlo, yy, z0, n, lb, ls);
+      tile_face_source(recs, tl.frec[1], B.face_start[1], B.face_count[1], xhi, yy, z0, n, rb, rs);
+      tile_face_source(recs, tl.frec[2], B.face_start[2], B.face_count[2], yy == 0, L.x0, z0, n, ymb, yms);
+      tile_face_source(recs, tl.frec[3], B.face_start[3], B.face_count[3], yy == B.ey - 1, L.x0, z0, n, ypb, yps);
     }
     const bool eL = L.lx == 0, eR = L.lx == nvt - 1, eM = L.ty == 0, eP = L.ty == rows - 1;
     T hl[ZB], hr[ZB];
@@ -456,7 +481,7 @@ __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_wave
     if (FUSED) {
       const bool has_lo = tl.xv0 == 0, has_hi = tl.xv0 + nvt == B.nvx;
       if (has_lo || has_hi) {
-        __syncthreads();
+        lds_barrier();
         BL_GLOBAL T* mir = w + B.mir + (int64_t)n * B.sc + tl.y0;
         for (int q = threadIdx.x; q < 2 * ZB * rows; q += blockDim.x) {
           const int side = q / (ZB * rows), k = (q / rows) % ZB, r = q % rows;
@@ -469,14 +494,182 @@ __global__ void __launch_bounds__(kStencilMaxThreads) __attribute__((amdgpu_wave
   }
 }
 
+// ---------------------------------------------------------------- heat step, LDS block form, halos loaded into LDS
+// Bytes from global memory straight into LDS (no registers): lane l's bytes
+// land at dst + l*size; dst is the same for the whole wave.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define BL_LDS __attribute__((address_space(3)))
+__device__ __forceinline__ void lds_load16(const BL_GLOBAL void* src, void* dst) {
+  __builtin_amdgcn_global_load_lds(src, (BL_LDS void*)dst, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_load4(const BL_GLOBAL void* src, void* dst) {
+  __builtin_amdgcn_global_load_lds(src, (BL_LDS void*)dst, 4, 0, 0);
+}
+#else
+__device__ __forceinline__ void lds_load16(const void*, void*) {}
+__device__ __forceinline__ void lds_load4(const void*, void*) {}
+#endif
+
+
+// As k_heat_lds, but what lies outside the tile (the rows above and below, the
+// values beyond the row ends) goes from memory straight into LDS, loaded by
+// all waves in 64-lane pieces, so the registers hold only the tile's own
+// planes.  LDS: ZB*blockDim plane vectors, ZB*2*nvtmax row vectors,
+// ZB*2*rmax values beyond the row ends (FUSED: then the new edge columns).
+template <typename T, int V, bool FUSED, int ZB>
+__global__ void __launch_bounds__(kStencilMaxThreads)
+    __attribute__((amdgpu_waves_per_eu(FUSED ? (ZB == 8 ? 4 : 6) : (ZB == 8 ? 5 : 8))))
+    k_heat_dma(const DevTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+               const DevFaceRec* __restrict__ recs, DevMember m0, const DevMember* __restrict__ members, int flip,
+               int persist, int nvtmax, int rmax) {
+  using VT = Vec<T, V>;
+  constexpr int DPV = (int)sizeof(T) / 4;  // dwords per value
+  extern __shared__ unsigned char smem_raw[];
+  const int nthr = blockDim.x;
+  VT* sh = reinterpret_cast<VT*>(smem_raw);               // [ZB][nthr]
+  VT* shy = sh + ZB * nthr;                               // [ZB][2][nvtmax]
+  // [ZB][2][rmax] values beyond the row ends; FUSED: then the new edge columns,
+  // each written by the one lane that read the value in its slot
+  T* shx = reinterpret_cast<T*>(shy + ZB * 2 * nvtmax);
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int nwaves = nthr >> 6;
+  const int lane = (int)threadIdx.x & 63;
+  int first, last;
+  tile_range(ntiles, persist, first, last);
+  for (int t = first; t < last; ++t) {
+    const DevTile tl = ldc(tiles + t);
+    const DevBox B = ldc(boxes + tl.box);
+    const DevMember M = members ? ldc(members + tl.member) : m0;
+    const bool swap = ((flip + M.flip_offset) & 1) != 0;
+    const BL_GLOBAL T* __restrict__ u = as_global(static_cast<const T*>(swap ? M.b : M.a));
+    BL_GLOBAL T* __restrict__ w = as_global(static_cast<T*>(swap ? M.a : M.b));
+    const T c = (T)M.c;
+    const TileLane L = tile_lane<V>(tl);
+    const int n = tl.comp, nvt = tl.nvt, rows = tl.rows;
+    const int sy = B.sy, sz = B.sz;
+    const int z0 = tl.z0, z1 = tl.z1;
+    const int yy = L.active ? L.y : tl.y0;
+    const int64_t comp0 = B.off + (int64_t)n * B.sc;
+    const int64_t cb = comp0 + L.x0 + (int64_t)yy * sy;
+
+    // rows y0-1 (s = 0) and y0+rows (s = 1) of planes z0.. into LDS: one
+    // 16-byte vector per lane, or one dword per lane for narrower vectors
+    constexpr int YW = sizeof(VT) == 16 ? 16 : 4;
+    constexpr int YPER = (int)sizeof(VT) / YW;  // lanes per vector
+    const int nyi = nvt * YPER, nchy = (nyi + 63) >> 6;
+    for (int q = wave; q < ZB * 2 * nchy; q += nwaves) {
+      const int k = q / (2 * nchy), s = (q / nchy) & 1, ch = q % nchy;
+      const int i = ch * 64 + lane;
+      const int z = z0 + k < z1 ? z0 + k : z1 - 1;
+      if (i < nyi) {
+        const int j = i / YPER, part = i - j * YPER;
+        const int x0 = (tl.xv0 + j) * V;
+        const int y = s ? tl.y0 + rows : tl.y0 - 1;
+        int64_t a = comp0 + x0 + (int64_t)y * sy + (int64_t)z * sz;
+        if (FUSED && (s ? y == B.ey : y < 0)) {
+          int64_t base = a;
+          int step = 0;
+          const int32_t fr = s ? tl.frec[3] : tl.frec[2];
+          const int fs = s ? B.face_start[3] : B.face_start[2], fc = s ? B.face_count[3] : B.face_count[2];
+          tile_face_source(recs, fr, fs, fc, true, x0, z0, n, base, step);
+          a = base + (int64_t)z * step;
+        }
+        if (YW == 16)
+          lds_load16(u + a, shy + (k * 2 + s) * nvtmax + ch * 64);
+        else
+          lds_load4(reinterpret_cast<const BL_GLOBAL unsigned char*>(u + a) + part * 4,
+                    reinterpret_cast<unsigned char*>(shy + (k * 2 + s) * nvtmax) + ch * 256);
+      }
+    }
+    // values left (s = 0) and right (s = 1) of the tile's rows, one dword per lane
+    const int nitems = rows * DPV, nchx = (nitems + 63) >> 6;
+    const bool face_lo = tl.xv0 == 0, face_hi = tl.xv0 + nvt == B.nvx;
+    for (int q = wave; q < ZB * 2 * nchx; q += nwaves) {
+      const int k = q / (2 * nchx), s = (q / nchx) & 1, ch = q % nchx;
+      const int i = ch * 64 + lane;
+      const int z = z0 + k < z1 ? z0 + k : z1 - 1;
+      if (i < nitems) {
+        const int r = i / DPV, part = i - r * DPV;
+        const int y = tl.y0 + r;
+        int64_t a;
+        if (!(s ? face_hi : face_lo)) {
+          a = comp0 + (int64_t)y * sy + (int64_t)z * sz + (s ? (tl.xv0 + nvt) * V : tl.xv0 * V - 1);
+        } else if (!FUSED) {
+          a = B.xs + (int64_t)n * B.sc + (s ? B.xs_side : 0) + (int64_t)z * B.xs_z + (int64_t)y * B.ng;
+        } else {
+          int64_t base = 0;
+          int step = 0;
+          const int32_t fr = s ? tl.frec[1] : tl.frec[0];
+          const int fs = s ? B.face_start[1] : B.face_start[0], fc = s ? B.face_count[1] : B.face_count[0];
+          tile_face_source(recs, fr, fs, fc, true, y, z0, n, base, step);
+          a = base + (int64_t)z * step;
+        }
+        lds_load4(reinterpret_cast<const BL_GLOBAL unsigned char*>(u + a) + part * 4,
+                  reinterpret_cast<unsigned char*>(shx + (k * 2 + s) * rmax) + ch * 256);
+      }
+    }
+
+    // the lane's own planes (z-face planes through the face records)
+    int64_t zlo = cb - sz, zhi = cb + (int64_t)B.ez * sz;
+    if (FUSED) {
+      if (z0 == 0) zlo = tile_face_index(recs, tl.frec[4], B.face_start[4], B.face_count[4], L.x0, yy, n, zlo);
+      if (z1 == B.ez) zhi = tile_face_index(recs, tl.frec[5], B.face_start[5], B.face_count[5], L.x0, yy, n, zhi);
+    }
+    VT P[ZB + 2];
+#pragma unroll
+    for (int k = 0; k < ZB + 2; ++k) {
+      const int z = z0 - 1 + k < z1 ? z0 - 1 + k : z1;
+      int64_t a = cb + (int64_t)z * sz;
+      if (FUSED) a = z < 0 ? zlo : (z >= B.ez ? zhi : a);
+      P[k] = ldv<T, V>(u + a);
+    }
+
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) sh[k * nthr + threadIdx.x] = P[k + 1];
+    __syncthreads();
+    BL_GLOBAL T* wp = w + cb;
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
+      const VT* row = sh + k * nthr + threadIdx.x;
+      const T left = L.lx == 0 ? shx[(k * 2) * rmax + L.ty] : row[-1].v[V - 1];
+      const T right = L.lx == nvt - 1 ? shx[(k * 2 + 1) * rmax + L.ty] : row[1].v[0];
+      const VT ym = L.ty == 0 ? shy[(k * 2) * nvtmax + L.lx] : row[-nvt];
+      const VT yp = L.ty == rows - 1 ? shy[(k * 2 + 1) * nvtmax + L.lx] : row[nvt];
+      VT o;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const T xm = e == 0 ? left : P[k + 1].v[e - 1];
+        const T xp = e == V - 1 ? right : P[k + 1].v[e + 1];
+        o.v[e] = heat_cell(P[k + 1].v[e], xm, xp, ym.v[e], yp.v[e], P[k].v[e], P[k + 2].v[e], c);
+      }
+      const int z = z0 + k;
+      if (z < z1 && L.active) stv<T, V>(wp + (int64_t)z * sz, o);
+      if (FUSED && L.active) {
+        if (L.xv == 0) shx[(k * 2) * rmax + L.ty] = o.v[0];
+        if (L.xv == B.nvx - 1) shx[(k * 2 + 1) * rmax + L.ty] = o.v[V - 1];
+      }
+    }
+    if (FUSED && (face_lo || face_hi)) {
+      lds_barrier();
+      BL_GLOBAL T* mir = w + B.mir + (int64_t)n * B.sc + tl.y0;
+      for (int q = threadIdx.x; q < 2 * ZB * rows; q += nthr) {
+        const int side = q / (ZB * rows), k = (q / rows) % ZB, r = q % rows;
+        if (z0 + k < z1 && (side ? face_hi : face_lo))
+          mir[side * B.mir_side + (int64_t)(z0 + k) * B.ey + r] = shx[(k * 2 + side) * rmax + r];
+      }
+    }
+    if (persist) __syncthreads();  // the next tile reuses the LDS buffers
+  }
+}
+
 // ---------------------------------------------------------------- FillBoundary
 // One workgroup per chunk of a copy-plan record; bit copies (integer type of the element size).
 template <typename I>
 __global__ void __launch_bounds__(kFillChunk)
     k_fill(I* __restrict__ data, const DevFillRec* __restrict__ recs, const DevFillChunk* __restrict__ chunks,
            int scomp, int ncomp) {
-  const DevFillChunk ch = chunks[blockIdx.x];
-  const DevFillRec R = recs[ch.rec];
+  const DevFillChunk ch = ldc(chunks + blockIdx.x);
+  const DevFillRec R = ldc(recs + ch.rec);
   const int cell = ch.start + (int)threadIdx.x;
   if (cell >= R.nx * R.ny * R.nz) return;
   const int x = cell % R.nx;
@@ -494,10 +687,10 @@ __global__ void __launch_bounds__(1024)
     k_copy_global(T* __restrict__ data, T* __restrict__ g, const DevTile* __restrict__ tiles,
                   const DevBox* __restrict__ boxes, int scomp, int ncomp, int dlo0, int dlo1, int dlo2, int Nx, int Ny,
                   int Nz, int to_global) {
-  const DevTile tl = tiles[blockIdx.x];
+  const DevTile tl = ldc(tiles + blockIdx.x);
   const TileLane L = tile_lane<V>(tl);
   if (tl.comp < scomp || tl.comp >= scomp + ncomp || !L.active) return;
-  const DevBox B = boxes[tl.box];
+  const DevBox B = ldc(boxes + tl.box);
   const int y = L.y, x0 = L.x0;
   const int64_t cb = B.off + (int64_t)tl.comp * B.sc + x0 + (int64_t)y * B.sy;
   for (int z = tl.z0; z < tl.z1; ++z) {
@@ -518,10 +711,10 @@ template <typename T, int V>
 __global__ void __launch_bounds__(1024)
     k_set_valid(T* __restrict__ data, T val, const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes,
                 int scomp, int ncomp) {
-  const DevTile tl = tiles[blockIdx.x];
+  const DevTile tl = ldc(tiles + blockIdx.x);
   const TileLane L = tile_lane<V>(tl);
   if (tl.comp < scomp || tl.comp >= scomp + ncomp || !L.active) return;
-  const DevBox B = boxes[tl.box];
+  const DevBox B = ldc(boxes + tl.box);
   const int64_t cb = B.off + (int64_t)tl.comp * B.sc + L.x0 + (int64_t)L.y * B.sy;
   for (int z = tl.z0; z < tl.z1; ++z)
 #pragma unroll
@@ -532,7 +725,7 @@ __global__ void __launch_bounds__(1024)
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_set_fab(T* __restrict__ data, T val, const DevBox* __restrict__ boxes, int scomp, int ncomp) {
-  const DevBox B = boxes[blockIdx.y];
+  const DevBox B = ldc(boxes + blockIdx.y);
   const int64_t start = B.off - ((int64_t)B.ng * B.sy + (int64_t)B.ng * B.sz) + (int64_t)scomp * B.sc;
   const int64_t count = B.sc * ncomp;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
@@ -545,7 +738,7 @@ __global__ void __launch_bounds__(256)
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_extract_mirror(T* __restrict__ data, const DevBox* __restrict__ boxes, int ncomp) {
-  const DevBox B = boxes[blockIdx.x / ncomp];
+  const DevBox B = ldc(boxes + blockIdx.x / ncomp);
   const int n = blockIdx.x % ncomp;
   const int64_t cnt = (int64_t)B.ey * B.ez;
   T* mir = data + B.mir + (int64_t)n * B.sc;
@@ -571,7 +764,7 @@ template <typename I>
 __global__ void __launch_bounds__(256)
     k_copy_fab(I* __restrict__ data, I* __restrict__ dense, const DevBox* __restrict__ boxes, int box, int scomp,
                int ncomp, int to_dense) {
-  const DevBox B = boxes[box];
+  const DevBox B = ldc(boxes + box);
   const int g = B.ng;
   const int nx = B.ex + 2 * g, ny = B.ey + 2 * g, nz = B.ez + 2 * g;
   const int64_t total = (int64_t)ncomp * nz * ny * nx;
@@ -626,11 +819,11 @@ template <typename T, int V>
 __global__ void __launch_bounds__(1024)
     k_reduce_tiles(const T* __restrict__ data, const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes,
                    int comp, int op, double* __restrict__ partials) {
-  const DevTile tl = tiles[blockIdx.x];
+  const DevTile tl = ldc(tiles + blockIdx.x);
   const TileLane L = tile_lane<V>(tl);
   double acc = r_identity(op);
   if (tl.comp == comp && L.active) {
-    const DevBox B = boxes[tl.box];
+    const DevBox B = ldc(boxes + tl.box);
     const T* p = data + B.off + (int64_t)comp * B.sc + L.x0 + (int64_t)L.y * B.sy;
     for (int z = tl.z0; z < tl.z1; ++z) {
       const Vec<T, V> v = ldv<T, V>(p + (int64_t)z * B.sz);
@@ -657,10 +850,10 @@ template <typename T, int V>
 __global__ void __launch_bounds__(1024)
     k_gsrb(const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes, T* __restrict__ phi,
            const T* __restrict__ f, T h2, T inv6, int color) {
-  const DevTile tl = tiles[blockIdx.x];
+  const DevTile tl = ldc(tiles + blockIdx.x);
   const TileLane L = tile_lane<V>(tl);
   if (!L.active) return;
-  const DevBox B = boxes[tl.box];
+  const DevBox B = ldc(boxes + tl.box);
   const int y = L.y, x0 = L.x0;
   const int64_t cb = B.off + x0 + (int64_t)y * B.sy;
   T* pp = phi + cb;
@@ -694,11 +887,11 @@ template <typename T, int V>
 __global__ void __launch_bounds__(1024)
     k_residual(const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes, const T* __restrict__ phi,
                const T* __restrict__ f, double h2, double* __restrict__ partials) {
-  const DevTile tl = tiles[blockIdx.x];
+  const DevTile tl = ldc(tiles + blockIdx.x);
   const TileLane L = tile_lane<V>(tl);
   double acc = 0.0;
   if (L.active) {
-    const DevBox B = boxes[tl.box];
+    const DevBox B = ldc(boxes + tl.box);
     const int64_t cb = B.off + L.x0 + (int64_t)L.y * B.sy;
     const T* pp = phi + cb;
     const T* fp = f + cb;
@@ -754,11 +947,48 @@ hipError_t heat_dispatch_lds(bool fused, const HeatArgs& a, int g, int block, in
   return hipGetLastError();
 }
 
+template <typename T, int V, int ZB>
+size_t dma_lds_bytes(bool fused, const HeatArgs& a, int block) {
+  (void)fused;
+  return (size_t)ZB * block * sizeof(Vec<T, V>) + (size_t)ZB * 2 * a.nvtmax * sizeof(Vec<T, V>) +
+         (size_t)ZB * 2 * a.rmax * sizeof(T);
+}
+
+template <typename T, int V, int ZB>
+hipError_t heat_dispatch_dma(bool fused, const HeatArgs& a, int g, int block, int persist, hipStream_t s) {
+  const size_t lds = dma_lds_bytes<T, V, ZB>(fused, a, block);
+  if (fused)
+    hipLaunchKernelGGL((k_heat_dma<T, V, true, ZB>), dim3(g), dim3(block), lds, s, a.tiles, a.ntiles, a.boxes, a.recs,
+                       a.m0, a.members, a.flip, persist, a.nvtmax, a.rmax);
+  else
+    hipLaunchKernelGGL((k_heat_dma<T, V, false, ZB>), dim3(g), dim3(block), lds, s, a.tiles, a.ntiles, a.boxes,
+                       a.recs, a.m0, a.members, a.flip, persist, a.nvtmax, a.rmax);
+  return hipGetLastError();
+}
+
 template <typename T, int V>
 hipError_t heat_dispatch(bool fused, const HeatArgs& a, int grid, int block, hipStream_t s) {
   const int persist = grid > 0 ? 1 : 0;
   const int g = persist ? (grid < a.ntiles ? grid : a.ntiles) : a.ntiles;
-  if (a.lds && (!fused || a.fvec)) {
+  // the halo-in-LDS form while its LDS fits one workgroup's share
+  if (a.form == 3 && (!fused || a.fvec) && a.nvtmax > 0 && a.rmax > 0) {
+    switch (a.zblock) {
+      case 2:
+        if (dma_lds_bytes<T, V, 2>(fused, a, block) <= kDmaLdsMax)
+          return heat_dispatch_dma<T, V, 2>(fused, a, g, block, persist, s);
+        break;
+      case 4:
+        if (dma_lds_bytes<T, V, 4>(fused, a, block) <= kDmaLdsMax)
+          return heat_dispatch_dma<T, V, 4>(fused, a, g, block, persist, s);
+        break;
+      case 8:
+        if (dma_lds_bytes<T, V, 8>(fused, a, block) <= kDmaLdsMax)
+          return heat_dispatch_dma<T, V, 8>(fused, a, g, block, persist, s);
+        break;
+      default: break;
+    }
+  }
+  if (a.form >= 2 && (!fused || a.fvec)) {
     switch (a.zblock) {
       case 2: return heat_dispatch_lds<T, V, 2>(fused, a, g, block, persist, s);
       case 4: return heat_dispatch_lds<T, V, 4>(fused, a, g, block, persist, s);

@@ -19,8 +19,9 @@ struct HeatArgs {
   int flip;
   int fvec;                    // 1: every y- and z-face source row allows aligned vector loads
   int zblock;                  // 2, 4, 8: block form (tiles of at most that many planes); else the march
-  int lds;                     // block form: in-tile neighbours through LDS
-  int rmax;                    // most rows of any tile of the launch (sizes the LDS mirror stage)
+  int form;                    // 0 march, 1 block, 2 block with LDS neighbours, 3 as 2 with halos loaded into LDS
+  int rmax;                    // most rows of any tile of the launch
+  int nvtmax;                  // most x vectors of any tile of the launch
 };
 
 // Stencil over `ntiles` tiles.  fused: tiles at box faces read neighbour boxes

@@ -440,13 +440,13 @@ void build_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base,
             std::memset(&t, 0, sizeof t);
             t.box = box_base + b;
             t.member = member;
-            t.comp = (int16_t)n;
-            t.xv0 = (int16_t)xv0;
-            t.nvt = (int16_t)std::min(nvt_full, B.nvx - xv0);
-            t.y0 = (int16_t)y0;
-            t.rows = (int16_t)std::min(rows_full, B.ey - y0);
-            t.z0 = (int16_t)zc[k];
-            t.z1 = (int16_t)zc[k + 1];
+            t.comp = n;
+            t.xv0 = xv0;
+            t.nvt = std::min(nvt_full, B.nvx - xv0);
+            t.y0 = y0;
+            t.rows = std::min(rows_full, B.ey - y0);
+            t.z0 = zc[k];
+            t.z1 = zc[k + 1];
             const int x0 = xv0 * p.vec, x1 = (xv0 + t.nvt) * p.vec - 1;
             const int y1 = y0 + t.rows - 1, z1 = t.z1 - 1;
             const bool touch[6] = {xv0 == 0, xv0 + t.nvt == B.nvx, y0 == 0, y0 + t.rows == B.ey, t.z0 == 0,
@@ -660,7 +660,10 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, std::
 
   p->cfg = tile_config();
   build_tiles(*p, p->cfg, 0, 0, 0, p->htiles, &p->box_tile_start);
-  for (const DevTile& t : p->htiles) p->rmax = std::max<int>(p->rmax, t.rows);
+  for (const DevTile& t : p->htiles) {
+    p->rmax = std::max<int>(p->rmax, t.rows);
+    p->nvtmax = std::max<int>(p->nvtmax, t.nvt);
+  }
   *out = p;
   return BL_OK;
 }

@@ -331,14 +331,16 @@ def test_batch_alone_equals_in_the_mix(bt):
 # ----------------------------------------------------------------------------- tile configurations
 TILE_CONFIGS = [(1, 4, 0, 0), (2, 2, 0, 0), (3, 4, 0, 0), (8, 1, 0, 0), (1024, 4, 0, 0), (5, 3, 0, 0), (4, 4, 2, 0),
                 (1024, 2, 3, 0), (8, 4, 1, 0), (16, 1, 0, 0), (2, 4, 0, 1), (4, 4, 0, 1), (8, 2, 0, 1), (8, 4, 2, 1),
-                (2, 4, 0, 2), (4, 4, 0, 2), (8, 3, 0, 2), (4, 4, 2, 2), (4, 1, 0, 2)]
+                (2, 4, 0, 2), (4, 4, 0, 2), (8, 3, 0, 2), (4, 4, 2, 2), (4, 1, 0, 2),
+                (2, 4, 0, 3), (4, 4, 0, 3), (8, 3, 0, 3), (4, 4, 2, 3), (4, 1, 0, 3), (8, 2, 0, 3)]
 
 
 @pytest.mark.parametrize("cfg", TILE_CONFIGS)
 @pytest.mark.parametrize("layout", ["uneven", "odd_noncovering"])
 def test_every_tile_configuration_bit_exact(bt, cfg, layout):
-    """Every stencil kernel variant (z-blocked 1/2/4/8, z march, persistent grid)
-    gives the oracle's FP64 result, fused and per box, on ragged tiles."""
+    """Every stencil kernel variant (z march, block forms of 2/4/8 planes with
+    registers, LDS neighbours or LDS halos, persistent grid) gives the oracle's
+    FP64 result, fused and per box, on ragged tiles."""
     rng = np.random.default_rng(31)
     if layout == "uneven":
         dom, periodic = I.domain_box((64, 48, 40)), (1, 1, 1)
