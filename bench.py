@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GCell-updates/s + % HBM roofline (heat_step+FillBoundary); p50/p99 serve latency"
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 2 << 30
+CPU_SAMPLE_SECONDS = 10.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat_fused_cfg2_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1604_03570_amd", "csrc", "bl_kernels.hip")
 
@@ -63,12 +64,16 @@ def cpu_baseline(boxes, dom, u0, c, nthreads_note: str):
     m.load_global(u0)
     w = m.copy()
     setup = time.perf_counter() - t0
-    nsteps = 1
+    # whole steps until about 10 s of host work (at least one step)
+    nsteps = 0
     t0 = time.perf_counter()
-    for _ in range(nsteps):
+    while True:
         O.heat_step(m, w, c)
         m, w = w, m
-    dt = time.perf_counter() - t0
+        nsteps += 1
+        dt = time.perf_counter() - t0
+        if dt >= CPU_SAMPLE_SECONDS or nsteps >= 200:
+            break
     cells = sum(int(np.prod(b[3:] - b[:3] + 1)) for b in boxes) * u0.shape[0]
     log(f"cpu baseline: {nsteps} step(s) in {dt:.2f} s (setup {setup:.1f} s), {O.num_threads()} threads")
     return {
@@ -76,9 +81,123 @@ def cpu_baseline(boxes, dom, u0, c, nthreads_note: str):
         "unit": "GCell-updates/s",
         "cores": O.num_threads(),
         "kind": "oracle",
-        "sample": f"{nsteps} full step (FillBoundary + 7-point update) of the same workload, FP64, "
+        "sample": f"{nsteps} full steps (FillBoundary + 7-point update each) of the same workload, FP64, "
                   f"OpenMP over boxes ({nthreads_note})",
     }
+
+
+PROFILE_ARGS = "--steps 20 --warmup 2 --no-cpu-baseline --no-extra --calibrate-copy"
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short_kernel(name: str) -> str:
+    import re
+    m = re.search(r"(k_\w+<[^>]*>|k_\w+)", name)
+    if m:
+        return m.group(1)
+    return name.split("(")[0].replace("void ", "")[:60]
+
+
+def summarize_profiles(d: str) -> int:
+    """Summaries of three rocprofv3 runs of this script with PROFILE_ARGS: kernel trace
+    statistics, FETCH_SIZE and WRITE_SIZE per dispatch.  The counters are scaled by
+    what they read for the plain 2 GiB device copy that the same runs end with."""
+    import glob
+    import statistics
+    import re
+
+    def one(pattern):
+        got = sorted(glob.glob(os.path.join(d, pattern)))
+        if not got:
+            raise SystemExit(f"missing {pattern} under {d}")
+        return got[0]
+
+    logs = {k: open(os.path.join(d, f"{k}.log")).read() for k in ("trace", "fetch", "write")}
+    hashes = {k: re.findall(r"kernel source sha256/16: (\w+)", v) for k, v in logs.items()}
+    hs = {h for v in hashes.values() for h in v}
+    if len(hs) != 1:
+        raise SystemExit(f"runs disagree on the kernel source: {hashes}")
+    src_hash = hs.pop()
+    line = None
+    for ln in logs["trace"].splitlines():
+        if ln.startswith("{") and '"metric"' in ln:
+            line = json.loads(ln)
+    if line is None:
+        raise SystemExit("no JSON line in the trace run's log")
+    dtype = line["dtype"]
+    stats = _read_csv(one("trace/*kernel_stats.csv"))
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    heat = [r for r in stats if "k_heat_" in r["Name"] and ", true," in r["Name"]]
+    if not heat:
+        raise SystemExit("no fused heat kernel in the trace")
+    hk = heat[0]["Name"]
+    avg_us = float(heat[0]["AverageNs"]) / 1e3
+
+    def per_dispatch(path, counter):
+        vals = {}
+        for r in _read_csv(path):
+            if r["Counter_Name"] == counter:
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    fetch = per_dispatch(one("fetch/*counter_collection.csv"), "FETCH_SIZE")
+    write = per_dispatch(one("write/*counter_collection.csv"), "WRITE_SIZE")
+    copy_name = next((k for k in fetch if "copyBuffer" in k), None)
+    if copy_name is None:
+        raise SystemExit("no copy kernel in the counter runs")
+    copy_kib = COPY_BYTES / 1024
+    big = lambda v: [x for x in v if x > 0.25 * copy_kib / 2]  # the 2 GiB copies, not small ones
+    fetch_scale = copy_kib / statistics.median(big(fetch[copy_name]))
+    write_scale = copy_kib / statistics.median(big(write[copy_name]))
+    f_kib = statistics.median(fetch[hk])
+    w_kib = statistics.median(write[hk])
+    fetch_b = f_kib * 1024 * fetch_scale
+    write_b = w_kib * 1024 * write_scale
+    cells = line["config"]["cell_updates_per_step"]
+    esize = 8 if dtype == "f64" else 4
+    alg = 2 * esize * cells
+    cmd = f"rocprofv3 {{--kernel-trace --stats | --pmc FETCH_SIZE | --pmc WRITE_SIZE}} --output-format csv -- python3 bench.py {PROFILE_ARGS}"
+    out = os.path.join(ROOT, "profiles", f"heat_fused_cfg2_{dtype}.md")
+    with open(out, "w") as fh:
+        fh.write(f"# Fused heat step + FillBoundary, 512^3 random chop, 5 comps, {dtype}\n\n")
+        fh.write("Commands (three runs, from the repository root, after `cd /tmp && export TMPDIR=/tmp` for the profiler's files):\n\n")
+        for opt in ("--kernel-trace --stats", "--pmc FETCH_SIZE", "--pmc WRITE_SIZE"):
+            fh.write(f"    rocprofv3 {opt} --output-format csv -d <out> -o run -- python3 bench.py {PROFILE_ARGS}\n")
+        fh.write(f"\nSummarised with `python3 bench.py --summarize-profiles <out>`.  Kernel source sha256/16: `{src_hash}`.\n\n")
+        fh.write("## Kernel trace statistics\n\n| kernel | calls | average us | total % |\n|---|---|---|---|\n")
+        for r in stats[:10]:
+            fh.write(f"| `{_short_kernel(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |\n")
+        fh.write("\n## HBM traffic of the fused kernel, per launch (median over dispatches)\n\n")
+        fh.write(f"* kernel: `{_short_kernel(hk)}`, average duration {avg_us:.1f} us\n")
+        fh.write(f"* copy calibration (`{_short_kernel(copy_name)}`, {COPY_BYTES} bytes read and written): "
+                 f"FETCH_SIZE x{fetch_scale:.4f}, WRITE_SIZE x{write_scale:.4f}\n")
+        fh.write(f"* FETCH_SIZE {f_kib:.0f} KiB -> {fetch_b / 1e9:.4f} GB read\n")
+        fh.write(f"* WRITE_SIZE {w_kib:.0f} KiB -> {write_b / 1e9:.4f} GB written\n")
+        fh.write(f"* algorithmic bytes (one read and one write of every cell update): {alg / 1e9:.4f} GB; "
+                 f"measured / algorithmic = {(fetch_b + write_b) / alg:.4f}\n")
+        fh.write(f"* achieved at the traced average: algorithmic {alg / (avg_us * 1e-6) / 1e9:.0f} GB/s, "
+                 f"measured {(fetch_b + write_b) / (avg_us * 1e-6) / 1e9:.0f} GB/s\n")
+        fh.write(f"\nBench line of the trace run: `{json.dumps({k: line[k] for k in ('value', 'ms_per_step', 'roofline')})}`\n")
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        t = {}
+    if t.get("kernel_source_sha256_16") != src_hash:
+        t = {"kernel_source_sha256_16": src_hash}
+    t[dtype] = {"bytes_per_launch": round(fetch_b + write_b), "fetch_bytes": round(fetch_b),
+                "write_bytes": round(write_b), "fetch_scale": round(fetch_scale, 5),
+                "write_scale": round(write_scale, 5), "kernel": _short_kernel(hk), "avg_duration_us": round(avg_us, 2),
+                "summary": os.path.relpath(out, ROOT)}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1)
+    print(f"wrote {out} and {TRAFFIC_FILE}")
+    return 0
 
 
 def main() -> int:
@@ -98,7 +217,13 @@ def main() -> int:
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and unfused measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three plain device copies of 2 GiB (reference for HBM byte counters)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="no GPU: turn rocprofv3 output of this script (DIR/trace, DIR/fetch, DIR/write) into "
+                         "the summary and traffic files under profiles/")
     args = ap.parse_args()
+
+    if args.summarize_profiles:
+        return summarize_profiles(args.summarize_profiles)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -117,6 +242,7 @@ def main() -> int:
         bt.set_tile_config(args.zchunk or z, args.waves or w, p if args.persist is None else args.persist,
                            b if args.block is None else args.block)
     cfg_tile = bt.get_tile_config()
+    log(f"kernel source sha256/16: {kernel_source_hash()}")
 
     n, ncomp = args.n, args.ncomp
     dom = I.domain_box(n)
@@ -157,21 +283,33 @@ def main() -> int:
         wall = time.perf_counter() - w0
         ms = e0.elapsed_time(e1)
         drift = abs(res.sum(0) - s0) / abs(s0)
-        return ms, wall, drift, ba, a, b
+        # per-launch duration of the fused kernel: a 2K-step graph minus the K-step
+        # one (both measured with events on this stream), so the once-per-advance
+        # mirror extraction and the graph launch drop out
+        cur = res
+        oth = a if cur is b else b
+        bt.heat_advance(cur, oth, 2 * steps, c)  # captures the 2K-step graph; 2K even: state back in cur
+        torch.cuda.synchronize()
+        e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e2.record(stream)
+        bt.heat_advance(cur, oth, 2 * steps, c)
+        e3.record(stream)
+        torch.cuda.synchronize()
+        per_launch_ms = (e2.elapsed_time(e3) - ms) / steps
+        return ms, wall, drift, ba, a, b, per_launch_ms
 
-    ms, wall, drift, ba, a, b = run(args.dtype, args.steps, args.warmup)
+    ms, wall, drift, ba, a, b, per_launch_ms = run(args.dtype, args.steps, args.warmup)
     esize = 8 if args.dtype == "f64" else 4
     sec = ms / 1e3
     value = cells * args.steps / sec / 1e9
-    per_launch_s = sec / args.steps
     alg_bytes = 2 * esize * cells  # read u once, write u_new once
-    achieved = alg_bytes / per_launch_s / 1e9
+    achieved = alg_bytes / (per_launch_ms / 1e3) / 1e9
     traffic = measured_traffic(args.dtype)
     log(f"{args.dtype}: {ms:.3f} ms for {args.steps} steps (wall {wall * 1e3:.3f} ms), "
         f"{value:.1f} GCell/s, {achieved:.0f} GB/s, sum drift {drift:.2e}")
 
     extra = {"sum_drift_rel": drift, "wall_ms_timed": round(wall * 1e3, 4), "tile_config": list(cfg_tile),
-             "nboxes": len(boxes)}
+             "nboxes": len(boxes), "fused_kernel_ms_per_launch": round(per_launch_ms, 5)}
     if not args.no_extra:
         # unfused form: fill kernel and stencil kernel timed apart (fill fraction)
         stream = torch.cuda.current_stream()
@@ -198,7 +336,7 @@ def main() -> int:
         del a, b, ba
         torch.cuda.empty_cache()
         if args.dtype == "f64":
-            ms32, _, drift32, ba32, a32, b32 = run("f32", args.steps, args.warmup)
+            ms32, _, drift32, ba32, a32, b32, _ = run("f32", args.steps, args.warmup)
             v32 = cells * args.steps / (ms32 / 1e3) / 1e9
             extra["f32_gcell_s"] = round(v32, 2)
             extra["f32_ms_per_step"] = round(ms32 / args.steps, 5)
