@@ -86,7 +86,7 @@ def cpu_baseline(boxes, dom, u0, c, nthreads_note: str):
     }
 
 
-PROFILE_ARGS = "--steps 20 --warmup 2 --no-cpu-baseline --no-extra --calibrate-copy"
+PROFILE_ARGS = "--steps 20 --warmup 2 --no-cpu-baseline --no-extra --calibrate-copy --zchunk 4 --waves 4 --block 3"
 
 
 def _read_csv(path):
@@ -237,7 +237,8 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    if args.zchunk or args.waves or args.persist is not None or args.block is not None:
+    explicit = bool(args.zchunk or args.waves or args.persist is not None or args.block is not None)
+    if explicit:
         z, w, p, b = bt.get_tile_config()
         bt.set_tile_config(args.zchunk or z, args.waves or w, p if args.persist is None else args.persist,
                            b if args.block is None else args.block)
@@ -248,7 +249,8 @@ def main() -> int:
     dom = I.domain_box(n)
     boxes = I.random_chop(dom, 16, 128, 8, seed=args.seed)
     c = I.heat_c(n)
-    log(f"workload: {n}^3, {len(boxes)} boxes, {ncomp} comps, dtype {args.dtype}, tile cfg {cfg_tile}")
+    log(f"workload: {n}^3, {len(boxes)} boxes, {ncomp} comps, dtype {args.dtype}, "
+        f"tile shape {'fixed ' + str(cfg_tile) if explicit else 'autotuned'}")
     t0 = time.perf_counter()
     u0 = I.uniform(n, ncomp, seed=args.seed)
     log(f"inputs generated in {time.perf_counter() - t0:.1f} s")
@@ -258,6 +260,15 @@ def main() -> int:
         dt = bt.F64 if dtype_name == "f64" else bt.F32
         ba = bt.BoxArray.from_boxes(boxes, dom)
         a, b = bt.MultiFab(ba, ncomp, 1, dt), bt.MultiFab(ba, ncomp, 1, dt)
+        tuned = None
+        if not explicit:  # pick the tile shape on this workload before loading the data
+            t0 = time.perf_counter()
+            a.set_val(0.5)
+            b.set_val(0.5)
+            best, table = bt.autotune(ba, a, b, c, trial_steps=3)
+            tuned = {"best": list(best), "seconds": round(time.perf_counter() - t0, 2),
+                     "table": [[list(k), round(v, 4)] for k, v in table]}
+            log(f"{dtype_name}: autotuned tile shape {best} in {tuned['seconds']} s")
         for comp in range(ncomp):  # one component at a time keeps the staging copy small
             a.from_global(u0[comp:comp + 1], scomp=comp)
         torch.cuda.synchronize()
@@ -296,9 +307,9 @@ def main() -> int:
         e3.record(stream)
         torch.cuda.synchronize()
         per_launch_ms = (e2.elapsed_time(e3) - ms) / steps
-        return ms, wall, drift, ba, a, b, per_launch_ms
+        return ms, wall, drift, ba, a, b, per_launch_ms, tuned
 
-    ms, wall, drift, ba, a, b, per_launch_ms = run(args.dtype, args.steps, args.warmup)
+    ms, wall, drift, ba, a, b, per_launch_ms, tuned = run(args.dtype, args.steps, args.warmup)
     esize = 8 if args.dtype == "f64" else 4
     sec = ms / 1e3
     value = cells * args.steps / sec / 1e9
@@ -308,7 +319,8 @@ def main() -> int:
     log(f"{args.dtype}: {ms:.3f} ms for {args.steps} steps (wall {wall * 1e3:.3f} ms), "
         f"{value:.1f} GCell/s, {achieved:.0f} GB/s, sum drift {drift:.2e}")
 
-    extra = {"sum_drift_rel": drift, "wall_ms_timed": round(wall * 1e3, 4), "tile_config": list(cfg_tile),
+    extra = {"sum_drift_rel": drift, "wall_ms_timed": round(wall * 1e3, 4),
+             "tile_shape": tuned["best"] if tuned else list(cfg_tile), "autotune": tuned,
              "nboxes": len(boxes), "fused_kernel_ms_per_launch": round(per_launch_ms, 5)}
     if not args.no_extra:
         # unfused form: fill kernel and stencil kernel timed apart (fill fraction)
@@ -336,12 +348,13 @@ def main() -> int:
         del a, b, ba
         torch.cuda.empty_cache()
         if args.dtype == "f64":
-            ms32, _, drift32, ba32, a32, b32, _ = run("f32", args.steps, args.warmup)
+            ms32, _, drift32, ba32, a32, b32, _, tuned32 = run("f32", args.steps, args.warmup)
             v32 = cells * args.steps / (ms32 / 1e3) / 1e9
             extra["f32_gcell_s"] = round(v32, 2)
             extra["f32_ms_per_step"] = round(ms32 / args.steps, 5)
             extra["f32_hbm_frac"] = round(v32 * 8 / HBM_PEAK_GBS, 4)
             extra["f32_sum_drift_rel"] = drift32
+            extra["f32_tile_shape"] = tuned32["best"] if tuned32 else list(cfg_tile)
             log(f"f32: {v32:.1f} GCell/s")
             del a32, b32, ba32
             torch.cuda.empty_cache()

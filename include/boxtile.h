@@ -299,6 +299,29 @@ bl_status bl_reduce_async(const bl_multifab* mf, int32_t comp, bl_reduce_op op, 
 bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int32_t block);
 bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist, int32_t* block);
 
+/*
+ * Autotuner of the tile shape (the paper tunes tile sizes per loop and
+ * machine, Sec. 3.2 and Sec. 4.1; here the shape is picked by timing on the
+ * device).  Times the fused heat step (bl_heat_advance's kernel) of u0/u1 on
+ * `stream` for every candidate shape: block forms 3 and 2, zchunk 2, 4 and 8,
+ * waves 2, 3 and 4 (persist as set by bl_set_tile_config), 2 warm-up steps
+ * then 2*trial_steps timed steps each (1 <= trial_steps <= 1000), and keeps
+ * the fastest: MultiFabs of this (BoxArray, ncomp, nghost, dtype) created
+ * afterwards use it, and u0 and u1 are switched to it now.  A later
+ * bl_set_tile_config drops every autotuned choice.
+ *
+ * The contents of u0 and u1 are overwritten (the trial steps advance them):
+ * tune before loading initial data, or on scratch MultiFabs.  Synchronises
+ * `stream`.  Optional outputs: the first max_results candidates' shapes
+ * (configs[4*i .. 4*i+3] = zchunk, waves, persist, block) and their mean
+ * milliseconds per step, their count in *nresults, the chosen shape in best[4].
+ * Errors: ESHAPE/EDTYPE as bl_heat_step, ESHAPE if u0 is not on ba, EINVAL
+ * for trial_steps or max_results out of range, EHIP.
+ */
+bl_status bl_autotune(const bl_boxarray* ba, bl_multifab* u0, bl_multifab* u1, double c, int32_t trial_steps,
+                      int32_t max_results, int32_t* nresults, int32_t* configs, float* ms_per_step,
+                      int32_t best[4], hipStream_t stream);
+
 /* ------------------------------------------------------------------- batching */
 
 /*

@@ -74,6 +74,8 @@ _SIGS = {
     "bl_reduce": [_vp, _i32, _i32, _dp, _vp],
     "bl_reduce_async": [_vp, _i32, _i32, _vp, _vp],
     "bl_set_tile_config": [_i32, _i32, _i32, _i32],
+    "bl_autotune": [_vp, _vp, _vp, ctypes.c_double, _i32, _i32, _i32p, _i32p, ctypes.POINTER(ctypes.c_float), _i32p,
+                    _vp],
     "bl_get_tile_config": [_i32p, _i32p, _i32p, _i32p],
     "bl_batch_create": [_vpp],
     "bl_batch_add": [_vp, _vp, _vp, ctypes.c_double, _i32p],
@@ -265,6 +267,21 @@ def get_tile_config() -> tuple:
     z, w, p, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(_L.bl_get_tile_config(ctypes.byref(z), ctypes.byref(w), ctypes.byref(p), ctypes.byref(b)))
     return z.value, w.value, p.value, b.value
+
+
+def autotune(ba: "BoxArray", u0: "MultiFab", u1: "MultiFab", c: float, trial_steps: int = 4, stream=None):
+    """Time every candidate tile shape of the fused heat step on u0/u1 (their contents are
+    overwritten) and keep the fastest for this (BoxArray, ncomp, nghost, dtype).
+    Returns (best (zchunk, waves, persist, block), [((zchunk, waves, persist, block), ms_per_step), ...])."""
+    nmax = 64
+    cfgs = (ctypes.c_int32 * (4 * nmax))()
+    ms = (ctypes.c_float * nmax)()
+    n = ctypes.c_int32()
+    best = (ctypes.c_int32 * 4)()
+    _check(_L.bl_autotune(ba.handle, u0.handle, u1.handle, float(c), int(trial_steps), nmax, ctypes.byref(n), cfgs, ms,
+                          best, _stream(stream)))
+    table = [(tuple(cfgs[4 * i:4 * i + 4]), float(ms[i])) for i in range(n.value)]
+    return tuple(best), table
 
 
 # --------------------------------------------------------------------------- MultiFab

@@ -54,16 +54,24 @@ bl_status upload_plan(Plan& p) {
 static std::mutex g_plan_mu;
 static std::map<std::tuple<uint64_t, int, int, int, int, int, int>, std::weak_ptr<Plan>> g_plans;
 
-static bl_status get_plan(const bl_boxarray* ba, int ncomp, int ng, int dtype, bool to_device,
-                          std::shared_ptr<Plan>* out) {
-  const TileConfig cfg = tile_config();
+// Tile configurations chosen by bl_autotune, per (BoxArray, ncomp, nghost, dtype);
+// they take precedence over the global configuration until bl_set_tile_config.
+static std::map<std::tuple<uint64_t, int, int, int>, TileConfig> g_tuned;
+
+static TileConfig config_for(const bl_boxarray* ba, int ncomp, int ng, int dtype) {
+  auto it = g_tuned.find(std::make_tuple(ba->uid, ncomp, ng, dtype));
+  return it != g_tuned.end() ? it->second : tile_config();
+}
+
+static bl_status get_plan_cfg(const bl_boxarray* ba, int ncomp, int ng, int dtype, const TileConfig& cfg,
+                              bool to_device, std::shared_ptr<Plan>* out) {
   auto key = std::make_tuple(ba->uid, ncomp, ng, dtype, cfg.zchunk, cfg.waves, cfg.block);
   std::lock_guard<std::mutex> lk(g_plan_mu);
   auto it = g_plans.find(key);
   std::shared_ptr<Plan> p;
   if (it != g_plans.end()) p = it->second.lock();
   if (!p) {
-    bl_status st = build_plan(ba, ncomp, ng, dtype, &p);
+    bl_status st = build_plan(ba, ncomp, ng, dtype, cfg, &p);
     if (st != BL_OK) return st;
     g_plans[key] = p;
   }
@@ -75,6 +83,16 @@ static bl_status get_plan(const bl_boxarray* ba, int ncomp, int ng, int dtype, b
   return BL_OK;
 }
 
+static bl_status get_plan(const bl_boxarray* ba, int ncomp, int ng, int dtype, bool to_device,
+                          std::shared_ptr<Plan>* out) {
+  TileConfig cfg;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    cfg = config_for(ba, ncomp, ng, dtype);
+  }
+  return get_plan_cfg(ba, ncomp, ng, dtype, cfg, to_device, out);
+}
+
 static int block_of(const Plan& p) { return 64 * p.cfg.waves; }
 
 static int persistent_grid(int persist) { return persist > 0 ? device_cu_count() * persist : 0; }
@@ -84,9 +102,7 @@ static bl_status same_shape(const bl_multifab* a, const bl_multifab* b) {
   if (a->plan->dtype != b->plan->dtype) return fail(BL_EDTYPE, "MultiFabs differ in dtype");
   if (a->plan->ba_uid != b->plan->ba_uid || a->plan->ncomp != b->plan->ncomp || a->plan->ng != b->plan->ng)
     return fail(BL_ESHAPE, "MultiFabs differ in BoxArray, ncomp or nghost");
-  if (a->plan.get() != b->plan.get())
-    return fail(BL_ESHAPE, "MultiFabs were created under different tile configurations");
-  return BL_OK;
+  return BL_OK;  // the FAB layout does not depend on the tile configuration
 }
 
 static bl_status ensure_scratch(bl_multifab* mf, size_t ndev, size_t nhost) {
@@ -481,6 +497,99 @@ bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int
   c.waves = waves;
   c.persist = persist;
   c.block = block;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_tuned.clear();  // an explicit choice replaces earlier autotuned ones
+  return BL_OK;
+}
+
+bl_status bl_autotune(const bl_boxarray* ba, bl_multifab* u0, bl_multifab* u1, double c, int32_t trial_steps,
+                      int32_t max_results, int32_t* nresults, int32_t* configs, float* ms_per_step,
+                      int32_t best[4], hipStream_t stream) {
+  clear_error();
+  if (!ba) return fail(BL_EINVAL, "NULL BoxArray");
+  bl_status st = check_heat(u0, u1);
+  if (st != BL_OK) return st;
+  if (u0->plan->ba_uid != ba->uid) return fail(BL_ESHAPE, "the MultiFabs are not on this BoxArray");
+  if (trial_steps < 1 || trial_steps > 1000) return fail(BL_EINVAL, "need 1 <= trial_steps <= 1000");
+  if (max_results < 0) return fail(BL_EINVAL, "max_results < 0");
+  const Plan& p0 = *u0->plan;
+  const int ncomp = p0.ncomp, ng = p0.ng, dtype = p0.dtype;
+  const int persist = tile_config().persist;
+  std::vector<TileConfig> cands;
+  for (int block : {3, 2})
+    for (int z : {2, 4, 8})
+      for (int w : {2, 3, 4}) cands.push_back(TileConfig{z, w, persist, block});
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BL_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(BL_EHIP, "hipEventCreate");
+  }
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } ev{e0, e1};
+  float best_ms = 0.f;
+  int best_i = -1;
+  std::shared_ptr<Plan> best_plan;
+  int nres = 0;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    const TileConfig& cfg = cands[i];
+    std::shared_ptr<Plan> pl;
+    if ((st = get_plan_cfg(ba, ncomp, ng, dtype, cfg, true, &pl)) != BL_OK) return st;
+    HeatArgs a{pl->dtiles, (int)pl->htiles.size(), pl->dboxes, pl->dfacerecs, member_of(u0, u1, c), nullptr, 0,
+               pl->fvec, cfg.zchunk, cfg.block, pl->rmax, pl->nvtmax};
+    const int grid = persistent_grid(cfg.persist), block = 64 * cfg.waves;
+    BL_HIP(launch_extract_mirror(*pl, u0->data, stream));
+    for (int s = 0; s < 2; ++s) {  // warm-up; an even count leaves the state in u0
+      a.flip = s;
+      BL_HIP(launch_heat(dtype, pl->vec, true, a, grid, block, stream));
+    }
+    BL_HIP(hipEventRecord(e0, stream));
+    for (int s = 0; s < 2 * trial_steps; ++s) {
+      a.flip = s & 1;
+      BL_HIP(launch_heat(dtype, pl->vec, true, a, grid, block, stream));
+    }
+    BL_HIP(hipEventRecord(e1, stream));
+    BL_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    BL_HIP(hipEventElapsedTime(&ms, e0, e1));
+    ms /= (float)(2 * trial_steps);
+    if (nres < max_results) {
+      if (configs) {
+        configs[4 * nres + 0] = cfg.zchunk;
+        configs[4 * nres + 1] = cfg.waves;
+        configs[4 * nres + 2] = cfg.persist;
+        configs[4 * nres + 3] = cfg.block;
+      }
+      if (ms_per_step) ms_per_step[nres] = ms;
+      ++nres;
+    }
+    if (best_i < 0 || ms < best_ms) {
+      best_ms = ms;
+      best_i = (int)i;
+      best_plan = pl;
+    }
+  }
+  if (nresults) *nresults = nres;
+  const TileConfig& bc = cands[best_i];
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_tuned[std::make_tuple(ba->uid, ncomp, ng, dtype)] = bc;
+  }
+  forget_graphs(u0);
+  forget_graphs(u1);
+  u0->plan = best_plan;
+  u1->plan = best_plan;
+  if (best) {
+    best[0] = bc.zchunk;
+    best[1] = bc.waves;
+    best[2] = bc.persist;
+    best[3] = bc.block;
+  }
   return BL_OK;
 }
 

@@ -276,7 +276,8 @@ struct Plan {
   ~Plan();
 };
 
-bl_status build_plan(const bl_boxarray* ba, int ncomp, int ng, int dtype, std::shared_ptr<Plan>* out);
+bl_status build_plan(const bl_boxarray* ba, int ncomp, int ng, int dtype, const TileConfig& cfg,
+                     std::shared_ptr<Plan>* out);
 bl_status upload_plan(Plan& p);  // allocates and copies device metadata (once)
 std::shared_ptr<const std::vector<FillRecord>> fill_plan(bl_boxarray* ba, int ng);
 std::shared_ptr<const std::vector<FaceRecord>> face_plan(bl_boxarray* ba, int ng);

@@ -495,7 +495,8 @@ static int64_t layout_fab(const Box& b, int ng, int ncomp, int64_t A, int64_t fa
 
 static int64_t elem_align(int esize) { return 128 / esize; }
 
-bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, std::shared_ptr<Plan>* out) {
+bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const TileConfig& cfg,
+                     std::shared_ptr<Plan>* out) {
   bl_boxarray* ba = const_cast<bl_boxarray*>(cba);
   auto p = std::make_shared<Plan>();
   p->ba_uid = ba->uid;
@@ -658,7 +659,7 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, std::
     }
   }
 
-  p->cfg = tile_config();
+  p->cfg = cfg;
   build_tiles(*p, p->cfg, 0, 0, 0, p->htiles, &p->box_tile_start);
   for (const DevTile& t : p->htiles) {
     p->rmax = std::max<int>(p->rmax, t.rows);

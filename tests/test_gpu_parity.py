@@ -373,3 +373,33 @@ def test_every_tile_configuration_bit_exact(bt, cfg, layout):
     m = np.isfinite(ref)
     assert np.array_equal(fused[m], ref[m])
     assert np.array_equal(other[m], ref[m])
+
+
+# ----------------------------------------------------------------------------- autotuner
+def test_autotune_picks_the_fastest_and_stays_bit_exact(bt):
+    """The autotuner times every candidate shape, keeps the fastest, and the tuned
+    MultiFabs (and ones created afterwards) still give the oracle's FP64 result."""
+    dom = I.domain_box((64, 48, 40))
+    boxes = I.random_chop(dom, 8, 32, 8, seed=21)
+    g = np.random.default_rng(5).random((2, 40, 48, 64)) + 1.0
+    c = 0.15
+    saved = bt.get_tile_config()
+    try:
+        ba = bt.BoxArray.from_boxes(boxes, dom)
+        s0, s1 = bt.MultiFab(ba, 2, 1, bt.F64), bt.MultiFab(ba, 2, 1, bt.F64)
+        s0.set_val(1.0)
+        s1.set_val(1.0)
+        best, table = bt.autotune(ba, s0, s1, c, trial_steps=2)
+        say(f"autotune best {best}, {len(table)} candidates")
+        assert len(table) == 18
+        assert best == min(table, key=lambda t: t[1])[0]
+        assert all(ms > 0 for _, ms in table)
+        # the scratch pair, and a fresh pair of the same shape, now run the tuned shape
+        for a, b in ((s0, s1), (bt.MultiFab(ba, 2, 1, bt.F64), bt.MultiFab(ba, 2, 1, bt.F64))):
+            _, _, _, o = make_pair(boxes, dom, (1, 1, 1), 2, 1, bt.F64, g)
+            a.from_global(g)
+            got = gpu_global(bt.heat_advance(a, b, 5, c))
+            ref = O.heat_advance(o, 5, c).to_global()
+            assert np.array_equal(got, ref)
+    finally:
+        bt.set_tile_config(*saved)
