@@ -215,6 +215,7 @@ def main() -> int:
     ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and unfused measurements")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three plain device copies of 2 GiB (reference for HBM byte counters)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -358,6 +359,21 @@ def main() -> int:
             log(f"f32: {v32:.1f} GCell/s")
             del a32, b32, ba32
             torch.cuda.empty_cache()
+
+    if not args.no_extra and not args.no_serve:
+        # serving: 2000 independent periodic heat problems, Poisson arrivals at 200/s,
+        # edge 32..256, box edge 32 or 64, 10..200 steps, FP32/FP64; continuous batching
+        # with HBM admission at a generous and a tight budget
+        from paper_1604_03570_amd import serve as S
+        reqs = I.request_stream(2000, 200.0, seed=args.seed)
+        sv = {"requests": len(reqs), "rate_per_s": 200.0, "offered_gcell_s": round(S.offered_load(reqs) / 1e9, 3)}
+        for name, budget in (("budget_64GiB", 64 << 30), ("budget_1GiB", 1 << 30)):
+            sv[name] = S.Server(budget, max_slots=64).run(reqs).summary()
+            log(f"serve {name}: p50 {sv[name]['p50_ms']} ms, p99 {sv[name]['p99_ms']} ms, "
+                f"{sv[name]['throughput_gcell_s']} GCell/s")
+        extra["serve"] = sv
+        extra["serve_p50_ms"] = sv["budget_64GiB"]["p50_ms"]
+        extra["serve_p99_ms"] = sv["budget_64GiB"]["p99_ms"]
 
     if args.calibrate_copy:
         # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE per dispatch

@@ -331,6 +331,13 @@ bl_status bl_autotune(const bl_boxarray* ba, bl_multifab* u0, bl_multifab* u1, d
  * u0/u1 are the member's ping-pong pair (same shape and dtype, nghost >= 1);
  * its current state is u0 after an even number of its steps, u1 after an odd
  * number (bl_batch_parity).  The MultiFabs must outlive their membership.
+ * The paper's collapsed (grid, tile) loop (Sec. 3.3) spans every member here.
+ *
+ * Issue every bl_batch_step of one batch on the same stream: after an add or
+ * remove, the next step refills the batch's device tables with copies ordered
+ * on that stream (no device synchronisation), building each member's tile
+ * list once, when it is first stepped.  Only a newly joined member's edge
+ * mirror is extracted; the fused kernel keeps the others current.
  */
 bl_status bl_batch_create(bl_batch** out);
 bl_status bl_batch_add(bl_batch* b, bl_multifab* u0, bl_multifab* u1, double c, int32_t* member_id);

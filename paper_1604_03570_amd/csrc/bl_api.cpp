@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <new>
@@ -53,6 +54,8 @@ bl_status upload_plan(Plan& p) {
 // Plans are shared by every MultiFab of one shape and tile configuration.
 static std::mutex g_plan_mu;
 static std::map<std::tuple<uint64_t, int, int, int, int, int, int>, std::weak_ptr<Plan>> g_plans;
+static constexpr size_t kPlansKept = 16;
+static std::deque<std::shared_ptr<Plan>> g_plan_keep;
 
 // Tile configurations chosen by bl_autotune, per (BoxArray, ncomp, nghost, dtype);
 // they take precedence over the global configuration until bl_set_tile_config.
@@ -74,6 +77,10 @@ static bl_status get_plan_cfg(const bl_boxarray* ba, int ncomp, int ng, int dtyp
     bl_status st = build_plan(ba, ncomp, ng, dtype, cfg, &p);
     if (st != BL_OK) return st;
     g_plans[key] = p;
+    // the most recent plans stay alive after their last MultiFab goes, so a
+    // shape that comes back (a serving loop) reuses its tables
+    g_plan_keep.push_back(p);
+    if (g_plan_keep.size() > kPlansKept) g_plan_keep.pop_front();
   }
   if (to_device) {
     bl_status st = upload_plan(*p);
@@ -680,17 +687,33 @@ struct bl_batch {
     bl_multifab* u0;
     bl_multifab* u1;
     double c;
-    int64_t joined;  // tick of its first step
+    int64_t joined;               // tick of its first step
     int id;
+    bool mirrored = false;        // its current state's edge mirror is valid
+    std::vector<DevTile> tiles;   // member-local numbering (box, face record, member 0)
+  };
+  // Device table of one kind, grown on demand and refilled in stream order from
+  // pinned staging memory, so a rebuild needs no device synchronisation.
+  template <typename T>
+  struct Table {
+    T* dev = nullptr;
+    T* host = nullptr;
+    size_t cap = 0, n = 0;
+    void release() {
+      (void)hipFree(dev);
+      (void)hipHostFree(host);
+      dev = host = nullptr;
+      cap = n = 0;
+    }
   };
   struct Group {
     int dtype = 0, vec = 1, fvec = 1, rmax = 1, nvtmax = 1;
     std::vector<int> members;  // indices into mems
-    DevBox* dboxes = nullptr;
-    DevFaceRec* drecs = nullptr;
-    DevTile* dtiles = nullptr;
-    DevMember* dmembers = nullptr;
-    int ntiles = 0;
+    Table<DevBox> boxes;
+    Table<DevFaceRec> recs;
+    Table<DevTile> tiles;
+    Table<DevMember> dmembers;
+    hipEvent_t staged = nullptr;  // the last upload from the staging buffers
   };
   std::vector<Member> mems;
   std::vector<Group> groups;
@@ -698,23 +721,64 @@ struct bl_batch {
   int64_t tick = 0;
   bool dirty = true;
   TileConfig cfg;
+  bool have_cfg = false;
 
-  void free_groups() {
+  ~bl_batch() {
     for (auto& g : groups) {
-      (void)hipFree(g.dboxes);
-      (void)hipFree(g.drecs);
-      (void)hipFree(g.dtiles);
-      (void)hipFree(g.dmembers);
+      if (g.staged) (void)hipEventSynchronize(g.staged);
+      g.boxes.release();
+      g.recs.release();
+      g.tiles.release();
+      g.dmembers.release();
+      if (g.staged) (void)hipEventDestroy(g.staged);
     }
-    groups.clear();
   }
-  ~bl_batch() { free_groups(); }
 };
 
+namespace bl {
+
+// Make room for n entries; a device buffer that must grow is replaced after the
+// stream has drained (rare: capacities double).
+template <typename T>
+static bl_status table_reserve(bl_batch::Table<T>& t, size_t n, hipStream_t stream) {
+  if (n <= t.cap) return BL_OK;
+  size_t cap = std::max<size_t>(n, 2 * t.cap);
+  BL_HIP(hipStreamSynchronize(stream));
+  (void)hipFree(t.dev);
+  (void)hipHostFree(t.host);
+  t.dev = nullptr;
+  t.host = nullptr;
+  t.cap = 0;
+  BL_HIP(hipMalloc((void**)&t.dev, cap * sizeof(T)));
+  BL_HIP(hipHostMalloc((void**)&t.host, cap * sizeof(T), hipHostMallocDefault));
+  t.cap = cap;
+  return BL_OK;
+}
+
+template <typename T>
+static bl_status table_upload(bl_batch::Table<T>& t, hipStream_t stream) {
+  if (t.n) BL_HIP(hipMemcpyAsync(t.dev, t.host, t.n * sizeof(T), hipMemcpyHostToDevice, stream));
+  return BL_OK;
+}
+
+}  // namespace bl
+
 static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
-  BL_HIP(hipStreamSynchronize(stream));  // earlier ticks may still read the old tables
-  b->free_groups();
-  b->cfg = tile_config();
+  const TileConfig cfg = tile_config();
+  const bool cfg_changed = !b->have_cfg || cfg.zchunk != b->cfg.zchunk || cfg.waves != b->cfg.waves ||
+                           cfg.block != b->cfg.block || cfg.persist != b->cfg.persist;
+  b->cfg = cfg;
+  b->have_cfg = true;
+  for (auto& m : b->mems)
+    if (cfg_changed || m.tiles.empty()) {
+      m.tiles.clear();
+      build_tiles(*m.u0->plan, cfg, 0, 0, 0, m.tiles, nullptr);
+    }
+  // members grouped by (dtype, vector width): one launch per group
+  for (auto& g : b->groups) {
+    g.members.clear();
+    g.fvec = 1;
+  }
   for (size_t i = 0; i < b->mems.size(); ++i) {
     const Plan& p = *b->mems[i].u0->plan;
     bl_batch::Group* g = nullptr;
@@ -730,44 +794,66 @@ static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
     if (!p.fvec) g->fvec = 0;
   }
   for (auto& g : b->groups) {
-    std::vector<DevBox> boxes;
-    std::vector<DevFaceRec> recs;
-    std::vector<DevTile> tiles;
-    std::vector<DevMember> mems;
+    size_t nb = 0, nr = 0, nt = 0;
+    for (int i : g.members) {
+      const Plan& p = *b->mems[i].u0->plan;
+      nb += p.hboxes.size();
+      nr += p.hfacerecs.size();
+      nt += b->mems[i].tiles.size();
+    }
+    if (g.staged) BL_HIP(hipEventSynchronize(g.staged));  // staging buffers free again
+    bl_status st;
+    if ((st = table_reserve(g.boxes, nb, stream)) != BL_OK) return st;
+    if ((st = table_reserve(g.recs, nr, stream)) != BL_OK) return st;
+    if ((st = table_reserve(g.tiles, nt, stream)) != BL_OK) return st;
+    if ((st = table_reserve(g.dmembers, g.members.size(), stream)) != BL_OK) return st;
+    size_t ob = 0, orr = 0, ot = 0;
+    g.rmax = g.nvtmax = 1;
     for (size_t k = 0; k < g.members.size(); ++k) {
       const bl_batch::Member& m = b->mems[g.members[k]];
       const Plan& p = *m.u0->plan;
-      const int box_base = (int)boxes.size(), rec_base = (int)recs.size();
+      const int box_base = (int)ob, rec_base = (int)orr;
       for (DevBox B : p.hboxes) {
         for (int f = 0; f < 6; ++f) B.face_start[f] += rec_base;
-        boxes.push_back(B);
+        g.boxes.host[ob++] = B;
       }
-      recs.insert(recs.end(), p.hfacerecs.begin(), p.hfacerecs.end());
-      build_tiles(p, b->cfg, (int)k, box_base, rec_base, tiles, nullptr);
+      for (const DevFaceRec& R : p.hfacerecs) g.recs.host[orr++] = R;
+      for (DevTile t : m.tiles) {
+        t.box += box_base;
+        t.member = (int32_t)k;
+        for (int f = 0; f < 6; ++f)
+          if (t.frec[f] >= 0) t.frec[f] += rec_base;
+        g.rmax = std::max<int>(g.rmax, t.rows);
+        g.nvtmax = std::max<int>(g.nvtmax, t.nvt);
+        g.tiles.host[ot++] = t;
+      }
       DevMember dm;
       std::memset(&dm, 0, sizeof dm);
       dm.a = m.u0->data;
       dm.b = m.u1->data;
       dm.c = m.c;
       dm.flip_offset = (int32_t)(m.joined & 1);
-      mems.push_back(dm);
+      g.dmembers.host[k] = dm;
     }
-    bl_status st;
-    if ((st = upload(&g.dboxes, boxes, "batch boxes")) != BL_OK) return st;
-    if ((st = upload(&g.drecs, recs, "batch face records")) != BL_OK) return st;
-    if ((st = upload(&g.dtiles, tiles, "batch tiles")) != BL_OK) return st;
-    if ((st = upload(&g.dmembers, mems, "batch members")) != BL_OK) return st;
-    g.ntiles = (int)tiles.size();
-    for (const DevTile& t : tiles) {
-      g.rmax = std::max<int>(g.rmax, t.rows);
-      g.nvtmax = std::max<int>(g.nvtmax, t.nvt);
+    g.boxes.n = nb;
+    g.recs.n = nr;
+    g.tiles.n = nt;
+    g.dmembers.n = g.members.size();
+    if ((st = table_upload(g.boxes, stream)) != BL_OK) return st;
+    if ((st = table_upload(g.recs, stream)) != BL_OK) return st;
+    if ((st = table_upload(g.tiles, stream)) != BL_OK) return st;
+    if ((st = table_upload(g.dmembers, stream)) != BL_OK) return st;
+    if (!g.staged) BL_HIP(hipEventCreateWithFlags(&g.staged, hipEventDisableTiming));
+    BL_HIP(hipEventRecord(g.staged, stream));
+  }
+  // edge-column mirrors of the newly joined members' current states (the fused
+  // kernel keeps every other member's mirror current)
+  for (auto& m : b->mems)
+    if (!m.mirrored) {
+      bl_multifab* cur = ((b->tick - m.joined) & 1) ? m.u1 : m.u0;
+      BL_HIP(launch_extract_mirror(*cur->plan, cur->data, stream));
+      m.mirrored = true;
     }
-  }
-  // edge-column mirrors of every member's current state
-  for (const auto& m : b->mems) {
-    bl_multifab* cur = ((b->tick - m.joined) & 1) ? m.u1 : m.u0;
-    BL_HIP(launch_extract_mirror(*cur->plan, cur->data, stream));
-  }
   b->dirty = false;
   return BL_OK;
 }
@@ -787,10 +873,15 @@ bl_status bl_batch_add(bl_batch* b, bl_multifab* u0, bl_multifab* u1, double c, 
   if (!b || !member_id) return fail(BL_EINVAL, "NULL argument");
   bl_status st = check_heat(u0, u1);
   if (st != BL_OK) return st;
-  bl_batch::Member m{u0, u1, c, b->tick, b->next_id++};
-  b->mems.push_back(m);
+  bl_batch::Member m;
+  m.u0 = u0;
+  m.u1 = u1;
+  m.c = c;
+  m.joined = b->tick;
+  m.id = b->next_id++;
+  b->mems.push_back(std::move(m));
   b->dirty = true;
-  *member_id = m.id;
+  *member_id = b->mems.back().id;
   return BL_OK;
 }
 
@@ -823,8 +914,9 @@ bl_status bl_batch_step(bl_batch* b, hipStream_t stream) {
   bl_status st;
   if (b->dirty && (st = batch_rebuild(b, stream)) != BL_OK) return st;
   for (auto& g : b->groups) {
-    HeatArgs a{g.dtiles, g.ntiles, g.dboxes, g.drecs, DevMember{}, g.dmembers, (int)(b->tick & 1), g.fvec,
-               b->cfg.block ? b->cfg.zchunk : 0, b->cfg.block, g.rmax, g.nvtmax};
+    if (g.members.empty()) continue;
+    HeatArgs a{g.tiles.dev, (int)g.tiles.n, g.boxes.dev, g.recs.dev, DevMember{}, g.dmembers.dev,
+               (int)(b->tick & 1), g.fvec, b->cfg.block ? b->cfg.zchunk : 0, b->cfg.block, g.rmax, g.nvtmax};
     BL_HIP(launch_heat(g.dtype, g.vec, true, a, persistent_grid(b->cfg.persist), 64 * b->cfg.waves, stream));
   }
   b->tick++;

@@ -1,0 +1,68 @@
+"""Serving loop on the GPU: requests that overlap on the device give the same result
+as each one run alone (bit for bit, FP64 and FP32), and FP64 results equal the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1604_03570_amd import inputs as I
+from tests.gpu_helpers import lib, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bt():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return lib()
+
+
+def _stream(seed, nreq, rate):
+    rng = np.random.default_rng(seed)
+    out, t = [], 0.0
+    for i in range(nreq):
+        t += float(rng.exponential(1.0 / rate))
+        n = int(rng.choice([16, 24, 32, 48, 64]))
+        be = int(rng.choice([16, 32]))
+        out.append(I.Request(i, t, n, be, int(rng.integers(3, 25)), "f32" if rng.random() < 0.5 else "f64",
+                             tuple(float(v) for v in rng.uniform(0.25, 0.75, 3))))
+    return out
+
+
+@pytest.mark.parametrize("budget_mb", [4096, 2])
+def test_served_results_equal_alone_runs(bt, budget_mb):
+    from paper_1604_03570_amd import serve as S
+    reqs = _stream(3, 24, 2000.0)
+    got = {}
+    srv = S.Server(budget_mb << 20, max_slots=8, on_complete=lambda r, t: got.__setitem__(r.rid, t.double().cpu().numpy()))
+    st = srv.run(reqs)
+    say(f"budget {budget_mb} MB: {st.summary()}")
+    assert st.completed + st.rejected == len(reqs)
+    assert st.completed == len(got)
+    if budget_mb > 100:
+        assert st.rejected == 0 and st.peak_active > 1  # requests overlapped on the device
+    assert st.peak_bytes <= budget_mb << 20
+    for r in reqs:
+        if r.rid not in got:
+            continue
+        dt = bt.F64 if r.dtype == "f64" else bt.F32
+        ba = bt.BoxArray.chop(I.domain_box(r.n), min(r.box_edge, r.n))
+        a, b = bt.MultiFab(ba, 1, 1, dt), bt.MultiFab(ba, 1, 1, dt)
+        a.from_global(S.initial_field(r, device="cuda"))
+        alone = bt.heat_advance(a, b, r.steps, I.heat_c(r.n)).to_global().double().cpu().numpy()
+        assert np.array_equal(got[r.rid], alone), r
+
+
+def test_served_fp64_equals_oracle(bt):
+    from paper_1604_03570_amd import serve as S
+    reqs = [r for r in _stream(5, 10, 3000.0)]
+    for r in reqs:
+        r.dtype = "f64"
+    got = {}
+    S.Server(1 << 32, max_slots=6, on_complete=lambda r, t: got.__setitem__(r.rid, t.cpu().numpy())).run(reqs)
+    for r in reqs[:4]:
+        boxes = I.regular_chop(I.domain_box(r.n), min(r.box_edge, r.n))
+        o = O.OracleMultiFab(boxes, I.domain_box(r.n), (1, 1, 1), 1, 1)
+        o.load_global(I.gaussian_separable(r.n, r.center))
+        ref = O.heat_advance(o, r.steps, I.heat_c(r.n)).to_global()
+        assert np.array_equal(got[r.rid], ref), r
