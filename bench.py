@@ -200,6 +200,53 @@ def summarize_profiles(d: str) -> int:
     return 0
 
 
+def gsrb_run(bt, I, torch, seed: int, sweeps: int = 20) -> dict:
+    """Red-black Gauss-Seidel for -Lap(phi) = f: 384^3 periodic, 216 boxes of 64^3, f a seeded
+    zero-mean N(0,1) field rounded to FP32, phi0 = 0, FP32 state, 20 sweeps with a FillBoundary
+    before each colour (the fused form reads neighbour boxes directly) and the FP64 residual
+    norm after every sweep.  Also the form with explicit fills, for comparison."""
+    n = 384
+    dom = I.domain_box(n)
+    ba = bt.BoxArray.from_boxes(I.regular_chop(dom, 64), dom)
+    t0 = time.perf_counter()
+    f = I.zero_mean_normal_f32(n, seed=seed)
+    log(f"gsrb: source field in {time.perf_counter() - t0:.1f} s")
+    h2 = (1.0 / n) ** 2
+    out = {"workload": f"{n}^3 periodic, 216 boxes of 64^3, FP32 state, {sweeps} sweeps, FP64 norm each sweep"}
+    saved = bt.get_tile_config()
+    for form, cfg in (("fused", None), ("fill_then_pass", (saved[0], saved[1], saved[2], 2))):
+        if cfg:
+            bt.set_tile_config(*cfg)
+        try:
+            phi, fm = bt.MultiFab(ba, 1, 1, bt.F32), bt.MultiFab(ba, 1, 1, bt.F32)
+            fm.set_val(0.0, with_ghosts=True)
+            fm.from_global(f)
+            phi.set_val(0.0, with_ghosts=True)
+            bt.gsrb_sweeps(phi, fm, h2, 2)  # warm-up
+            phi.set_val(0.0, with_ghosts=True)
+            torch.cuda.synchronize()
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            norms = bt.gsrb_sweeps(phi, fm, h2, sweeps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+        finally:
+            if cfg:
+                bt.set_tile_config(*saved)
+        cs = n ** 3 * sweeps / (ms / 1e3)
+        out[form] = {"ms_per_sweep": round(ms / sweeps, 4), "gcell_sweeps_s": round(cs / 1e9, 2),
+                     "hbm_frac_at_12B": round(cs * 12 / (HBM_PEAK_GBS * 1e9), 4),
+                     "resnorm_first": norms[0], "resnorm_last": norms[-1]}
+        log(f"gsrb {form}: {ms / sweeps:.3f} ms per sweep, {cs / 1e9:.1f} G cell-sweeps/s, "
+            f"norm {norms[0]:.4e} -> {norms[-1]:.4e}")
+        del phi, fm
+    del f
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +263,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and unfused measurements")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
+    ap.add_argument("--no-gsrb", action="store_true", help="skip the GSRB smoother run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three plain device copies of 2 GiB (reference for HBM byte counters)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -359,6 +407,9 @@ def main() -> int:
             log(f"f32: {v32:.1f} GCell/s")
             del a32, b32, ba32
             torch.cuda.empty_cache()
+
+    if not args.no_extra and not args.no_gsrb:
+        extra["gsrb"] = gsrb_run(bt, I, torch, args.seed)
 
     if not args.no_extra and not args.no_serve:
         # serving: 2000 independent periodic heat problems, Poisson arrivals at 200/s,

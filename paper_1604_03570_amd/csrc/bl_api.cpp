@@ -456,8 +456,15 @@ bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, do
   const Plan& p = *phi->plan;
   if ((st = ensure_scratch(phi, p.htiles.size() + 8, 8)) != BL_OK) return st;
   double* dout = phi->dscratch + p.htiles.size();
-  BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
-  BL_HIP(launch_residual(p, phi->data, f->data, h2, phi->dscratch, dout, block_of(p), stream));
+  const int grid = persistent_grid(tile_config().persist);
+  if (gsrb_fused_ok(p, block_of(p))) {  // neighbour values straight from the neighbour boxes
+    BL_HIP(launch_extract_mirror(p, phi->data, stream));
+    BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, -1, 2, phi->dscratch, grid, block_of(p), stream));
+    BL_HIP(launch_reduce_partials(phi->dscratch, gsrb_fused_grid(p, grid), 1, dout, stream));
+  } else {
+    BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
+    BL_HIP(launch_residual(p, phi->data, f->data, h2, phi->dscratch, dout, block_of(p), stream));
+  }
   BL_HIP(hipMemcpyAsync(phi->hres, dout, sizeof(double), hipMemcpyDeviceToHost, stream));
   BL_HIP(hipStreamSynchronize(stream));
   *out_host = phi->hres[0];
@@ -472,6 +479,34 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
   if (nsweeps < 0) return fail(BL_EINVAL, "nsweeps < 0");
   const Plan& p = *phi->plan;
   const size_t nt = p.htiles.size();
+  if (gsrb_fused_ok(p, block_of(p))) {
+    // fused form: no FillBoundary; each colour pass reads the neighbour boxes
+    // through the face records.  The norm after sweep s is the black cells'
+    // part, taken in its black pass, plus the red cells' part, taken in the
+    // red pass of sweep s+1 (after the last sweep: a pass that only reads).
+    const int grid = persistent_grid(tile_config().persist);
+    const size_t g = (size_t)gsrb_fused_grid(p, grid);
+    if (resnorm_host && (st = ensure_scratch(phi, 2 * g + (size_t)nsweeps + 8, (size_t)nsweeps + 8)) != BL_OK)
+      return st;
+    double* red_part = resnorm_host ? phi->dscratch : nullptr;
+    double* black_part = resnorm_host ? phi->dscratch + g : nullptr;
+    double* norms = resnorm_host ? phi->dscratch + 2 * g : nullptr;
+    if (nsweeps > 0) BL_HIP(launch_extract_mirror(p, phi->data, stream));
+    for (int s = 0; s < nsweeps; ++s) {
+      BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, 0, 0, s > 0 ? red_part : nullptr, grid, block_of(p),
+                               stream));
+      if (resnorm_host && s > 0) BL_HIP(launch_reduce_partials(phi->dscratch, (int)(2 * g), 1, norms + s - 1, stream));
+      BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, 1, 1, black_part, grid, block_of(p), stream));
+    }
+    if (resnorm_host && nsweeps > 0) {
+      BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, -1, 0, red_part, grid, block_of(p), stream));
+      BL_HIP(launch_reduce_partials(phi->dscratch, (int)(2 * g), 1, norms + nsweeps - 1, stream));
+      BL_HIP(hipMemcpyAsync(phi->hres, norms, sizeof(double) * nsweeps, hipMemcpyDeviceToHost, stream));
+      BL_HIP(hipStreamSynchronize(stream));
+      std::memcpy(resnorm_host, phi->hres, sizeof(double) * nsweeps);
+    }
+    return BL_OK;
+  }
   if (resnorm_host && (st = ensure_scratch(phi, nt + (size_t)nsweeps + 8, (size_t)nsweeps + 8)) != BL_OK) return st;
   for (int s = 0; s < nsweeps; ++s) {
     for (int color = 0; color < 2; ++color) {

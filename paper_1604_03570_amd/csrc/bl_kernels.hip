@@ -511,11 +511,162 @@ __device__ __forceinline__ void lds_load4(const void*, void*) {}
 #endif
 
 
-// As k_heat_lds, but what lies outside the tile (the rows above and below, the
-// values beyond the row ends) goes from memory straight into LDS, loaded by
-// all waves in 64-lane pieces, so the registers hold only the tile's own
-// planes.  LDS: ZB*blockDim plane vectors, ZB*2*nvtmax row vectors,
-// ZB*2*rmax values beyond the row ends (FUSED: then the new edge columns).
+// Staging of one tile for the block forms with the halo in LDS.  What lies
+// outside the tile (the rows above and below, the values beyond the row ends)
+// goes from memory straight into LDS, loaded by all waves in 64-lane pieces, so
+// the registers hold only the tile's own planes.  LDS layout: ZB*blockDim plane
+// vectors `sh`, ZB*2*nvtmax row vectors `shy`, ZB*2*rmax values beyond the row
+// ends `shx` (FUSED: then the new edge columns, each written by the one lane
+// that read the value in its slot).
+template <typename T, int V>
+struct TileLds {
+  Vec<T, V>* sh;
+  Vec<T, V>* shy;
+  T* shx;
+  int nvtmax, rmax, nthr, wave, nwaves, lane;
+};
+
+template <typename T, int V, int ZB>
+__device__ __forceinline__ TileLds<T, V> tile_lds(unsigned char* smem, int nvtmax, int rmax) {
+  TileLds<T, V> S;
+  S.nthr = blockDim.x;
+  S.sh = reinterpret_cast<Vec<T, V>*>(smem);
+  S.shy = S.sh + ZB * S.nthr;
+  S.shx = reinterpret_cast<T*>(S.shy + ZB * 2 * nvtmax);
+  S.nvtmax = nvtmax;
+  S.rmax = rmax;
+  S.wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  S.nwaves = S.nthr >> 6;
+  S.lane = (int)threadIdx.x & 63;
+  return S;
+}
+
+// Issue the loads of the tile's halo into LDS (no wait).
+template <typename T, int V, bool FUSED, int ZB>
+__device__ __forceinline__ void stage_halo(const TileLds<T, V>& S, const DevTile& tl, const DevBox& B,
+                                           const DevFaceRec* __restrict__ recs, const BL_GLOBAL T* __restrict__ u,
+                                           int64_t comp0) {
+  using VT = Vec<T, V>;
+  constexpr int DPV = (int)sizeof(T) / 4;  // dwords per value
+  const int n = tl.comp, nvt = tl.nvt, rows = tl.rows, z0 = tl.z0, z1 = tl.z1;
+  const int sy = B.sy, sz = B.sz;
+  // rows y0-1 (s = 0) and y0+rows (s = 1) of planes z0..: one 16-byte vector
+  // per lane, or one dword per lane for narrower vectors
+  constexpr int YW = sizeof(VT) == 16 ? 16 : 4;
+  constexpr int YPER = (int)sizeof(VT) / YW;  // lanes per vector
+  const int nyi = nvt * YPER, nchy = (nyi + 63) >> 6;
+  for (int q = S.wave; q < ZB * 2 * nchy; q += S.nwaves) {
+    const int k = q / (2 * nchy), s = (q / nchy) & 1, ch = q % nchy;
+    const int i = ch * 64 + S.lane;
+    const int z = z0 + k < z1 ? z0 + k : z1 - 1;
+    if (i < nyi) {
+      const int j = i / YPER, part = i - j * YPER;
+      const int x0 = (tl.xv0 + j) * V;
+      const int y = s ? tl.y0 + rows : tl.y0 - 1;
+      int64_t a = comp0 + x0 + (int64_t)y * sy + (int64_t)z * sz;
+      if (FUSED && (s ? y == B.ey : y < 0)) {
+        int64_t base = a;
+        int step = 0;
+        const int32_t fr = s ? tl.frec[3] : tl.frec[2];
+        const int fs = s ? B.face_start[3] : B.face_start[2], fc = s ? B.face_count[3] : B.face_count[2];
+        tile_face_source(recs, fr, fs, fc, true, x0, z0, n, base, step);
+        a = base + (int64_t)z * step;
+      }
+      if (YW == 16)
+        lds_load16(u + a, S.shy + (k * 2 + s) * S.nvtmax + ch * 64);
+      else
+        lds_load4(reinterpret_cast<const BL_GLOBAL unsigned char*>(u + a) + part * 4,
+                  reinterpret_cast<unsigned char*>(S.shy + (k * 2 + s) * S.nvtmax) + ch * 256);
+    }
+  }
+  // values left (s = 0) and right (s = 1) of the tile's rows, one dword per lane
+  const int nitems = rows * DPV, nchx = (nitems + 63) >> 6;
+  const bool face_lo = tl.xv0 == 0, face_hi = tl.xv0 + nvt == B.nvx;
+  for (int q = S.wave; q < ZB * 2 * nchx; q += S.nwaves) {
+    const int k = q / (2 * nchx), s = (q / nchx) & 1, ch = q % nchx;
+    const int i = ch * 64 + S.lane;
+    const int z = z0 + k < z1 ? z0 + k : z1 - 1;
+    if (i < nitems) {
+      const int r = i / DPV, part = i - r * DPV;
+      const int y = tl.y0 + r;
+      int64_t a;
+      if (!(s ? face_hi : face_lo)) {
+        a = comp0 + (int64_t)y * sy + (int64_t)z * sz + (s ? (tl.xv0 + nvt) * V : tl.xv0 * V - 1);
+      } else if (!FUSED) {
+        a = B.xs + (int64_t)n * B.sc + (s ? B.xs_side : 0) + (int64_t)z * B.xs_z + (int64_t)y * B.ng;
+      } else {
+        int64_t base = 0;
+        int step = 0;
+        const int32_t fr = s ? tl.frec[1] : tl.frec[0];
+        const int fs = s ? B.face_start[1] : B.face_start[0], fc = s ? B.face_count[1] : B.face_count[0];
+        tile_face_source(recs, fr, fs, fc, true, y, z0, n, base, step);
+        a = base + (int64_t)z * step;
+      }
+      lds_load4(reinterpret_cast<const BL_GLOBAL unsigned char*>(u + a) + part * 4,
+                reinterpret_cast<unsigned char*>(S.shx + (k * 2 + s) * S.rmax) + ch * 256);
+    }
+  }
+}
+
+// The lane's own planes z0-1 .. z0+ZB (clamped to z1; z-face planes through the
+// face records when FUSED) into registers.
+template <typename T, int V, bool FUSED, int ZB>
+__device__ __forceinline__ void load_planes(Vec<T, V> (&P)[ZB + 2], const DevTile& tl, const DevBox& B,
+                                            const DevFaceRec* __restrict__ recs, const BL_GLOBAL T* __restrict__ u,
+                                            int64_t cb, int x0, int yy) {
+  const int n = tl.comp, z0 = tl.z0, z1 = tl.z1, sz = B.sz;
+  int64_t zlo = cb - sz, zhi = cb + (int64_t)B.ez * sz;
+  if (FUSED) {
+    if (z0 == 0) zlo = tile_face_index(recs, tl.frec[4], B.face_start[4], B.face_count[4], x0, yy, n, zlo);
+    if (z1 == B.ez) zhi = tile_face_index(recs, tl.frec[5], B.face_start[5], B.face_count[5], x0, yy, n, zhi);
+  }
+#pragma unroll
+  for (int k = 0; k < ZB + 2; ++k) {
+    const int z = z0 - 1 + k < z1 ? z0 - 1 + k : z1;
+    int64_t a = cb + (int64_t)z * sz;
+    if (FUSED) a = z < 0 ? zlo : (z >= B.ez ? zhi : a);
+    P[k] = ldv<T, V>(u + a);
+  }
+}
+
+// Neighbours of the lane's vector in plane k of the tile (after the barrier that
+// follows the planes' LDS writes): the values left and right of it, the vectors
+// of the rows below and above.
+template <typename T, int V>
+struct Nbr {
+  T left, right;
+  Vec<T, V> ym, yp;
+};
+template <typename T, int V>
+__device__ __forceinline__ Nbr<T, V> tile_neighbours(const TileLds<T, V>& S, const TileLane& L, int k, int nvt,
+                                                     int rows) {
+  const Vec<T, V>* row = S.sh + k * S.nthr + threadIdx.x;
+  Nbr<T, V> N;
+  N.left = L.lx == 0 ? S.shx[(k * 2) * S.rmax + L.ty] : row[-1].v[V - 1];
+  N.right = L.lx == nvt - 1 ? S.shx[(k * 2 + 1) * S.rmax + L.ty] : row[1].v[0];
+  N.ym = L.ty == 0 ? S.shy[(k * 2) * S.nvtmax + L.lx] : row[-nvt];
+  N.yp = L.ty == rows - 1 ? S.shy[(k * 2 + 1) * S.nvtmax + L.lx] : row[nvt];
+  return N;
+}
+
+// The new edge columns staged in shx, stored as contiguous runs into the mirror.
+template <typename T, int V, int ZB>
+__device__ __forceinline__ void store_mirror(const TileLds<T, V>& S, const DevTile& tl, const DevBox& B,
+                                             BL_GLOBAL T* __restrict__ w) {
+  const bool face_lo = tl.xv0 == 0, face_hi = tl.xv0 + tl.nvt == B.nvx;
+  if (!(face_lo || face_hi)) return;
+  lds_barrier();
+  const int rows = tl.rows, z0 = tl.z0, z1 = tl.z1;
+  BL_GLOBAL T* mir = w + B.mir + (int64_t)tl.comp * B.sc + tl.y0;
+  for (int q = threadIdx.x; q < 2 * ZB * rows; q += S.nthr) {
+    const int side = q / (ZB * rows), k = (q / rows) % ZB, r = q % rows;
+    if (z0 + k < z1 && (side ? face_hi : face_lo))
+      mir[side * B.mir_side + (int64_t)(z0 + k) * B.ey + r] = S.shx[(k * 2 + side) * S.rmax + r];
+  }
+}
+
+// Heat step, block form with the halo in LDS: one wait for all loads, the
+// tile's planes into LDS, one barrier, the updates, full-vector stores.
 template <typename T, int V, bool FUSED, int ZB>
 __global__ void __launch_bounds__(kStencilMaxThreads)
     __attribute__((amdgpu_waves_per_eu(FUSED ? (ZB == 8 ? 4 : 6) : (ZB == 8 ? 5 : 8))))
@@ -523,17 +674,8 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
                const DevFaceRec* __restrict__ recs, DevMember m0, const DevMember* __restrict__ members, int flip,
                int persist, int nvtmax, int rmax) {
   using VT = Vec<T, V>;
-  constexpr int DPV = (int)sizeof(T) / 4;  // dwords per value
   extern __shared__ unsigned char smem_raw[];
-  const int nthr = blockDim.x;
-  VT* sh = reinterpret_cast<VT*>(smem_raw);               // [ZB][nthr]
-  VT* shy = sh + ZB * nthr;                               // [ZB][2][nvtmax]
-  // [ZB][2][rmax] values beyond the row ends; FUSED: then the new edge columns,
-  // each written by the one lane that read the value in its slot
-  T* shx = reinterpret_cast<T*>(shy + ZB * 2 * nvtmax);
-  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const int nwaves = nthr >> 6;
-  const int lane = (int)threadIdx.x & 63;
+  const TileLds<T, V> S = tile_lds<T, V, ZB>(smem_raw, nvtmax, rmax);
   int first, last;
   tile_range(ntiles, persist, first, last);
   for (int t = first; t < last; ++t) {
@@ -545,120 +687,134 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
     BL_GLOBAL T* __restrict__ w = as_global(static_cast<T*>(swap ? M.a : M.b));
     const T c = (T)M.c;
     const TileLane L = tile_lane<V>(tl);
-    const int n = tl.comp, nvt = tl.nvt, rows = tl.rows;
-    const int sy = B.sy, sz = B.sz;
-    const int z0 = tl.z0, z1 = tl.z1;
+    const int nvt = tl.nvt, rows = tl.rows;
     const int yy = L.active ? L.y : tl.y0;
-    const int64_t comp0 = B.off + (int64_t)n * B.sc;
-    const int64_t cb = comp0 + L.x0 + (int64_t)yy * sy;
+    const int64_t comp0 = B.off + (int64_t)tl.comp * B.sc;
+    const int64_t cb = comp0 + L.x0 + (int64_t)yy * B.sy;
 
-    // rows y0-1 (s = 0) and y0+rows (s = 1) of planes z0.. into LDS: one
-    // 16-byte vector per lane, or one dword per lane for narrower vectors
-    constexpr int YW = sizeof(VT) == 16 ? 16 : 4;
-    constexpr int YPER = (int)sizeof(VT) / YW;  // lanes per vector
-    const int nyi = nvt * YPER, nchy = (nyi + 63) >> 6;
-    for (int q = wave; q < ZB * 2 * nchy; q += nwaves) {
-      const int k = q / (2 * nchy), s = (q / nchy) & 1, ch = q % nchy;
-      const int i = ch * 64 + lane;
-      const int z = z0 + k < z1 ? z0 + k : z1 - 1;
-      if (i < nyi) {
-        const int j = i / YPER, part = i - j * YPER;
-        const int x0 = (tl.xv0 + j) * V;
-        const int y = s ? tl.y0 + rows : tl.y0 - 1;
-        int64_t a = comp0 + x0 + (int64_t)y * sy + (int64_t)z * sz;
-        if (FUSED && (s ? y == B.ey : y < 0)) {
-          int64_t base = a;
-          int step = 0;
-          const int32_t fr = s ? tl.frec[3] : tl.frec[2];
-          const int fs = s ? B.face_start[3] : B.face_start[2], fc = s ? B.face_count[3] : B.face_count[2];
-          tile_face_source(recs, fr, fs, fc, true, x0, z0, n, base, step);
-          a = base + (int64_t)z * step;
-        }
-        if (YW == 16)
-          lds_load16(u + a, shy + (k * 2 + s) * nvtmax + ch * 64);
-        else
-          lds_load4(reinterpret_cast<const BL_GLOBAL unsigned char*>(u + a) + part * 4,
-                    reinterpret_cast<unsigned char*>(shy + (k * 2 + s) * nvtmax) + ch * 256);
-      }
-    }
-    // values left (s = 0) and right (s = 1) of the tile's rows, one dword per lane
-    const int nitems = rows * DPV, nchx = (nitems + 63) >> 6;
-    const bool face_lo = tl.xv0 == 0, face_hi = tl.xv0 + nvt == B.nvx;
-    for (int q = wave; q < ZB * 2 * nchx; q += nwaves) {
-      const int k = q / (2 * nchx), s = (q / nchx) & 1, ch = q % nchx;
-      const int i = ch * 64 + lane;
-      const int z = z0 + k < z1 ? z0 + k : z1 - 1;
-      if (i < nitems) {
-        const int r = i / DPV, part = i - r * DPV;
-        const int y = tl.y0 + r;
-        int64_t a;
-        if (!(s ? face_hi : face_lo)) {
-          a = comp0 + (int64_t)y * sy + (int64_t)z * sz + (s ? (tl.xv0 + nvt) * V : tl.xv0 * V - 1);
-        } else if (!FUSED) {
-          a = B.xs + (int64_t)n * B.sc + (s ? B.xs_side : 0) + (int64_t)z * B.xs_z + (int64_t)y * B.ng;
-        } else {
-          int64_t base = 0;
-          int step = 0;
-          const int32_t fr = s ? tl.frec[1] : tl.frec[0];
-          const int fs = s ? B.face_start[1] : B.face_start[0], fc = s ? B.face_count[1] : B.face_count[0];
-          tile_face_source(recs, fr, fs, fc, true, y, z0, n, base, step);
-          a = base + (int64_t)z * step;
-        }
-        lds_load4(reinterpret_cast<const BL_GLOBAL unsigned char*>(u + a) + part * 4,
-                  reinterpret_cast<unsigned char*>(shx + (k * 2 + s) * rmax) + ch * 256);
-      }
-    }
-
-    // the lane's own planes (z-face planes through the face records)
-    int64_t zlo = cb - sz, zhi = cb + (int64_t)B.ez * sz;
-    if (FUSED) {
-      if (z0 == 0) zlo = tile_face_index(recs, tl.frec[4], B.face_start[4], B.face_count[4], L.x0, yy, n, zlo);
-      if (z1 == B.ez) zhi = tile_face_index(recs, tl.frec[5], B.face_start[5], B.face_count[5], L.x0, yy, n, zhi);
-    }
+    stage_halo<T, V, FUSED, ZB>(S, tl, B, recs, u, comp0);
     VT P[ZB + 2];
+    load_planes<T, V, FUSED, ZB>(P, tl, B, recs, u, cb, L.x0, yy);
 #pragma unroll
-    for (int k = 0; k < ZB + 2; ++k) {
-      const int z = z0 - 1 + k < z1 ? z0 - 1 + k : z1;
-      int64_t a = cb + (int64_t)z * sz;
-      if (FUSED) a = z < 0 ? zlo : (z >= B.ez ? zhi : a);
-      P[k] = ldv<T, V>(u + a);
-    }
-
-#pragma unroll
-    for (int k = 0; k < ZB; ++k) sh[k * nthr + threadIdx.x] = P[k + 1];
+    for (int k = 0; k < ZB; ++k) S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
     __syncthreads();
     BL_GLOBAL T* wp = w + cb;
 #pragma unroll
     for (int k = 0; k < ZB; ++k) {
-      const VT* row = sh + k * nthr + threadIdx.x;
-      const T left = L.lx == 0 ? shx[(k * 2) * rmax + L.ty] : row[-1].v[V - 1];
-      const T right = L.lx == nvt - 1 ? shx[(k * 2 + 1) * rmax + L.ty] : row[1].v[0];
-      const VT ym = L.ty == 0 ? shy[(k * 2) * nvtmax + L.lx] : row[-nvt];
-      const VT yp = L.ty == rows - 1 ? shy[(k * 2 + 1) * nvtmax + L.lx] : row[nvt];
+      const Nbr<T, V> N = tile_neighbours<T, V>(S, L, k, nvt, rows);
       VT o;
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        const T xm = e == 0 ? left : P[k + 1].v[e - 1];
-        const T xp = e == V - 1 ? right : P[k + 1].v[e + 1];
-        o.v[e] = heat_cell(P[k + 1].v[e], xm, xp, ym.v[e], yp.v[e], P[k].v[e], P[k + 2].v[e], c);
+        const T xm = e == 0 ? N.left : P[k + 1].v[e - 1];
+        const T xp = e == V - 1 ? N.right : P[k + 1].v[e + 1];
+        o.v[e] = heat_cell(P[k + 1].v[e], xm, xp, N.ym.v[e], N.yp.v[e], P[k].v[e], P[k + 2].v[e], c);
       }
-      const int z = z0 + k;
-      if (z < z1 && L.active) stv<T, V>(wp + (int64_t)z * sz, o);
+      const int z = tl.z0 + k;
+      if (z < tl.z1 && L.active) stv<T, V>(wp + (int64_t)z * B.sz, o);
       if (FUSED && L.active) {
-        if (L.xv == 0) shx[(k * 2) * rmax + L.ty] = o.v[0];
-        if (L.xv == B.nvx - 1) shx[(k * 2 + 1) * rmax + L.ty] = o.v[V - 1];
+        if (L.xv == 0) S.shx[(k * 2) * S.rmax + L.ty] = o.v[0];
+        if (L.xv == B.nvx - 1) S.shx[(k * 2 + 1) * S.rmax + L.ty] = o.v[V - 1];
       }
     }
-    if (FUSED && (face_lo || face_hi)) {
-      lds_barrier();
-      BL_GLOBAL T* mir = w + B.mir + (int64_t)n * B.sc + tl.y0;
-      for (int q = threadIdx.x; q < 2 * ZB * rows; q += nthr) {
-        const int side = q / (ZB * rows), k = (q / rows) % ZB, r = q % rows;
-        if (z0 + k < z1 && (side ? face_hi : face_lo))
-          mir[side * B.mir_side + (int64_t)(z0 + k) * B.ey + r] = shx[(k * 2 + side) * rmax + r];
-      }
-    }
+    if (FUSED) store_mirror<T, V, ZB>(S, tl, B, w);
     if (persist) __syncthreads();  // the next tile reuses the LDS buffers
+  }
+}
+
+__device__ double block_reduce(double v, int op);
+
+// GSRB colour pass, fused with the ghost fill (neighbour boxes read through the
+// face records), in place.  color 0 (red: even global i+j+k) or 1 (black)
+// updates that colour's cells; every lane stores its whole vector, the other
+// colour's cells with their unchanged values, so stores are full lines and a
+// concurrent reader sees either value of a cell this pass does not change.
+//
+// RES: also accumulates r^2, r = f + (s - 6 phi)/h2 in FP64 from promoted
+// values, over the valid cells of colour rescolor (2: all) into
+// partials[workgroup].  Race-free pairs only: the black pass (color 1,
+// rescolor 1) takes black cells after their update, whose red neighbours this
+// pass does not change; the red pass (color 0, rescolor 0) takes red cells
+// before their update, whose black neighbours it does not change.  Together
+// they give the residual of the state between a black pass and the next red
+// pass.  color -1 stores nothing and may take any rescolor.
+template <typename T, int V, int ZB, bool RES>
+__global__ void __launch_bounds__(kStencilMaxThreads)
+    __attribute__((amdgpu_waves_per_eu(RES ? (ZB == 8 ? 2 : 4) : (ZB == 8 ? 4 : 6))))
+    k_gsrb_dma(const DevTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+               const DevFaceRec* __restrict__ recs, T* phi_, const T* __restrict__ f_, T h2, T inv6, int color,
+               int rescolor, double h2d, double* __restrict__ partials, int persist, int nvtmax, int rmax) {
+  using VT = Vec<T, V>;
+  extern __shared__ unsigned char smem_raw[];
+  const TileLds<T, V> S = tile_lds<T, V, ZB>(smem_raw, nvtmax, rmax);
+  BL_GLOBAL T* phi = as_global(phi_);
+  const BL_GLOBAL T* __restrict__ fq = as_global(f_);
+  double acc = 0.0;
+  int first, last;
+  tile_range(ntiles, persist, first, last);
+  for (int t = first; t < last; ++t) {
+    const DevTile tl = ldc(tiles + t);
+    const DevBox B = ldc(boxes + tl.box);
+    const TileLane L = tile_lane<V>(tl);
+    const int nvt = tl.nvt, rows = tl.rows;
+    const int yy = L.active ? L.y : tl.y0;
+    const int64_t comp0 = B.off + (int64_t)tl.comp * B.sc;
+    const int64_t cb = comp0 + L.x0 + (int64_t)yy * B.sy;
+    const int par0 = (B.glo[0] + L.x0 + B.glo[1] + yy + B.glo[2]) & 1;  // parity of (x0, y, z = 0)
+
+    stage_halo<T, V, true, ZB>(S, tl, B, recs, phi, comp0);
+    VT P[ZB + 2], F[ZB];
+    load_planes<T, V, true, ZB>(P, tl, B, recs, phi, cb, L.x0, yy);
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
+      const int z = tl.z0 + k < tl.z1 ? tl.z0 + k : tl.z1 - 1;
+      F[k] = ldv<T, V>(fq + cb + (int64_t)z * B.sz);
+    }
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
+    __syncthreads();
+    BL_GLOBAL T* wp = phi + cb;
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
+      const Nbr<T, V> N = tile_neighbours<T, V>(S, L, k, nvt, rows);
+      const int z = tl.z0 + k;
+      const bool valid = z < tl.z1 && L.active;
+      VT o = P[k + 1];
+      if (color >= 0) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const T xm = e == 0 ? N.left : P[k + 1].v[e - 1];
+          const T xp = e == V - 1 ? N.right : P[k + 1].v[e + 1];
+          const T nv = gsrb_cell(xm, xp, N.ym.v[e], N.yp.v[e], P[k].v[e], P[k + 2].v[e], F[k].v[e], h2, inv6);
+          if (((par0 + z + e) & 1) == color) o.v[e] = nv;
+        }
+      }
+      if (RES && valid) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          if (rescolor != 2 && ((par0 + z + e) & 1) != rescolor) continue;
+          const double xm = e == 0 ? (double)N.left : (double)P[k + 1].v[e - 1];
+          const double xp = e == V - 1 ? (double)N.right : (double)P[k + 1].v[e + 1];
+          const double sv = ((xm + xp) + ((double)N.ym.v[e] + (double)N.yp.v[e])) +
+                            ((double)P[k].v[e] + (double)P[k + 2].v[e]);
+          // the cell's own value: after its update in the black pass, before it otherwise
+          const double cv = color == 1 ? (double)o.v[e] : (double)P[k + 1].v[e];
+          const double r = (double)F[k].v[e] + (sv - 6.0 * cv) / h2d;
+          acc += r * r;
+        }
+      }
+      if (color < 0) continue;
+      if (valid) stv<T, V>(wp + (int64_t)z * B.sz, o);
+      if (L.active) {
+        if (L.xv == 0) S.shx[(k * 2) * S.rmax + L.ty] = o.v[0];
+        if (L.xv == B.nvx - 1) S.shx[(k * 2 + 1) * S.rmax + L.ty] = o.v[V - 1];
+      }
+    }
+    if (color >= 0) store_mirror<T, V, ZB>(S, tl, B, phi);
+    if (persist) __syncthreads();  // the next tile reuses the LDS buffers
+  }
+  if (RES) {
+    const double r = block_reduce(acc, R_SUM);
+    if (threadIdx.x == 0) partials[logical_block()] = r;
   }
 }
 
@@ -1173,6 +1329,70 @@ hipError_t launch_residual(const Plan& p, const void* phi, const void* f, double
                          (const float*)f, h2, partials);
   }
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, s, partials, (int)nt, (int)R_SUM, 1, out);
+  return hipGetLastError();
+}
+
+// Fused GSRB colour pass / residual (k_gsrb_dma) over the whole level; the
+// grid is one workgroup per tile or, persistent, `grid` workgroups; with
+// `partials` the per-workgroup sums of r^2 of the cells of colour rescolor.
+template <typename T, int V, int ZB>
+static hipError_t gsrb_dma_zb(const Plan& p, void* phi, const void* f, double h2, int color, int rescolor,
+                              double* partials, int g, int persist, int block, hipStream_t s) {
+  HeatArgs a{};
+  a.rmax = p.rmax;
+  a.nvtmax = p.nvtmax;
+  const size_t lds = dma_lds_bytes<T, V, ZB>(true, a, block);
+  const T h2t = (T)h2, inv6 = (T)(1.0 / 6.0);
+  if (partials)
+    hipLaunchKernelGGL((k_gsrb_dma<T, V, ZB, true>), dim3(g), dim3(block), lds, s, p.dtiles,
+                       (int)p.htiles.size(), p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor,
+                       h2, partials, persist, p.nvtmax, p.rmax);
+  else
+    hipLaunchKernelGGL((k_gsrb_dma<T, V, ZB, false>), dim3(g), dim3(block), lds, s, p.dtiles,
+                       (int)p.htiles.size(), p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor,
+                       h2, partials, persist, p.nvtmax, p.rmax);
+  return hipGetLastError();
+}
+
+template <typename T, int V>
+static hipError_t gsrb_dma_v(const Plan& p, void* phi, const void* f, double h2, int color, int rescolor,
+                             double* partials, int g, int persist, int block, hipStream_t s) {
+  switch (p.cfg.zchunk) {
+    case 2: return gsrb_dma_zb<T, V, 2>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
+    case 8: return gsrb_dma_zb<T, V, 8>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
+    default: return gsrb_dma_zb<T, V, 4>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
+  }
+}
+
+bool gsrb_fused_ok(const Plan& p, int block) {
+  if (p.cfg.block != 3 || !p.fvec || p.htiles.empty()) return false;
+  HeatArgs a{};
+  a.rmax = p.rmax;
+  a.nvtmax = p.nvtmax;
+  const int zb = p.cfg.zchunk == 2 || p.cfg.zchunk == 8 ? p.cfg.zchunk : 4;
+  const size_t elt = p.dtype == BL_F64 ? 8 : 4;
+  const size_t lds = (size_t)zb * block * 16 + (size_t)zb * 2 * a.nvtmax * (elt * p.vec) + (size_t)zb * 2 * a.rmax * elt;
+  return lds <= kDmaLdsMax;
+}
+
+int gsrb_fused_grid(const Plan& p, int grid) {
+  const int nt = (int)p.htiles.size();
+  return grid > 0 ? (grid < nt ? grid : nt) : nt;
+}
+
+hipError_t launch_gsrb_fused(const Plan& p, void* phi, const void* f, double h2, int color, int rescolor,
+                             double* partials, int grid, int block, hipStream_t s) {
+  if (p.htiles.empty()) return hipSuccess;
+  const int g = gsrb_fused_grid(p, grid), persist = grid > 0 ? 1 : 0;
+  if (p.dtype == BL_F64)
+    return p.vec == 2 ? gsrb_dma_v<double, 2>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s)
+                      : gsrb_dma_v<double, 1>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
+  return p.vec == 4 ? gsrb_dma_v<float, 4>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s)
+                    : gsrb_dma_v<float, 1>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
+}
+
+hipError_t launch_reduce_partials(const double* partials, int n, int take_sqrt, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, s, partials, n, (int)R_SUM, take_sqrt, out);
   return hipGetLastError();
 }
 

@@ -55,6 +55,17 @@ hipError_t launch_gsrb(const Plan& p, void* phi, const void* f, double h2, int c
 hipError_t launch_residual(const Plan& p, const void* phi, const void* f, double h2, double* partials, double* out,
                            int block, hipStream_t s);
 
+// Fused GSRB (no fill: neighbour boxes through the face records, edge mirrors
+// current): colour pass color (0 red, 1 black; -1 none) in place; with
+// partials, per-workgroup sums of r^2 over the cells of colour rescolor (2: all)
+// into partials[0 .. gsrb_fused_grid).  Usable when gsrb_fused_ok.
+bool gsrb_fused_ok(const Plan& p, int block);
+int gsrb_fused_grid(const Plan& p, int grid);
+hipError_t launch_gsrb_fused(const Plan& p, void* phi, const void* f, double h2, int color, int rescolor,
+                             double* partials, int grid, int block, hipStream_t s);
+// *out = sum (sqrt of it if take_sqrt) of partials[0..n)
+hipError_t launch_reduce_partials(const double* partials, int n, int take_sqrt, double* out, hipStream_t s);
+
 int device_cu_count();
 
 }  // namespace bl
