@@ -54,7 +54,7 @@ bl_status upload_plan(Plan& p) {
 // Plans are shared by every MultiFab of one shape and tile configuration.
 static std::mutex g_plan_mu;
 static std::map<std::tuple<uint64_t, int, int, int, int, int, int>, std::weak_ptr<Plan>> g_plans;
-static constexpr size_t kPlansKept = 16;
+static constexpr size_t kPlansKept = 64;
 static std::deque<std::shared_ptr<Plan>> g_plan_keep;
 
 // Tile configurations chosen by bl_autotune, per (BoxArray, ncomp, nghost, dtype);

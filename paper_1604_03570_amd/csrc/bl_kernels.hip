@@ -692,9 +692,9 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
     const int64_t comp0 = B.off + (int64_t)tl.comp * B.sc;
     const int64_t cb = comp0 + L.x0 + (int64_t)yy * B.sy;
 
-    stage_halo<T, V, FUSED, ZB>(S, tl, B, recs, u, comp0);
     VT P[ZB + 2];
     load_planes<T, V, FUSED, ZB>(P, tl, B, recs, u, cb, L.x0, yy);
+    stage_halo<T, V, FUSED, ZB>(S, tl, B, recs, u, comp0);
 #pragma unroll
     for (int k = 0; k < ZB; ++k) S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
     __syncthreads();

