@@ -379,6 +379,17 @@ bl_status bl_tile_list(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_
                        int32_t* tiles);
 
 /*
+ * Tiles of the stencil forms with the halo in LDS (block form 3; empty under
+ * other forms) for a MultiFab of this shape under the current tile
+ * configuration: 10 int32 per tile {box, comp, q0, nq, nzs, z0, z1, zchunk,
+ * vec, lanes}: the run of x vectors q0..q0+nq-1 of the box's plane (vector q
+ * is row q / nvx, x vector q % nvx, nvx = x extent / vec) over planes z0..z1-1,
+ * taken by nzs z blocks of zchunk planes; nzs*nq <= lanes.  Host metadata only.
+ */
+bl_status bl_stencil_tiles(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_dtype dtype, int32_t* ntiles,
+                           int32_t* tiles);
+
+/*
  * Static partition of a tile list over nworkers, as the paper's tile-level
  * threading shares the collapsed (grid, tile) loop (Sec. 3.3): worker w gets
  * the contiguous range [first[w], first[w+1]) of near-equal length, the

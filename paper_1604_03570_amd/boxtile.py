@@ -85,6 +85,7 @@ _SIGS = {
     "bl_fill_plan": [_vp, _i32, _i32p, _i32p],
     "bl_face_plan": [_vp, _i32p, _i32p],
     "bl_tile_list": [_vp, _i32, _i32, _i32, _i32p, _i32p],
+    "bl_stencil_tiles": [_vp, _i32, _i32, _i32, _i32p, _i32p],
     "bl_static_partition": [_i32, _i32, _i32p],
 }
 for _name, _args in _SIGS.items():
@@ -210,6 +211,14 @@ class BoxArray:
         _check(_L.bl_tile_list(self._h, ncomp, nghost, dtype, ctypes.byref(n), None))
         out = np.zeros((n.value, 9), dtype=np.int32)
         _check(_L.bl_tile_list(self._h, ncomp, nghost, dtype, ctypes.byref(n), out.ctypes.data_as(_i32p)))
+        return out
+
+    def stencil_tiles(self, ncomp: int, nghost: int, dtype: int = F64) -> np.ndarray:
+        """Linear tiles of the stencil (block form 3): rows of {box, comp, q0, nq, nzs, z0, z1, zchunk, vec, lanes}."""
+        n = ctypes.c_int32()
+        _check(_L.bl_stencil_tiles(self._h, ncomp, nghost, dtype, ctypes.byref(n), None))
+        out = np.zeros((n.value, 10), dtype=np.int32)
+        _check(_L.bl_stencil_tiles(self._h, ncomp, nghost, dtype, ctypes.byref(n), out.ctypes.data_as(_i32p)))
         return out
 
     def multifab_bytes(self, ncomp: int, nghost: int, dtype: int = F64) -> int:

@@ -25,6 +25,7 @@ Plan::~Plan() {
   (void)hipFree(dboxes);
   (void)hipFree(dfacerecs);
   (void)hipFree(dtiles);
+  (void)hipFree(dlin);
   (void)hipFree(dfillrecs);
   (void)hipFree(dfillchunks);
 }
@@ -45,6 +46,7 @@ bl_status upload_plan(Plan& p) {
   if ((st = upload(&p.dboxes, p.hboxes, "hipMalloc/hipMemcpy(boxes)")) != BL_OK) return st;
   if ((st = upload(&p.dfacerecs, p.hfacerecs, "hipMalloc/hipMemcpy(face records)")) != BL_OK) return st;
   if ((st = upload(&p.dtiles, p.htiles, "hipMalloc/hipMemcpy(tiles)")) != BL_OK) return st;
+  if ((st = upload(&p.dlin, p.hlin, "hipMalloc/hipMemcpy(stencil tiles)")) != BL_OK) return st;
   if ((st = upload(&p.dfillrecs, p.hfillrecs, "hipMalloc/hipMemcpy(fill records)")) != BL_OK) return st;
   if ((st = upload(&p.dfillchunks, p.hfillchunks, "hipMalloc/hipMemcpy(fill chunks)")) != BL_OK) return st;
   p.uploaded = true;
@@ -352,7 +354,8 @@ bl_status bl_heat_step_unfused(bl_multifab* u_old, bl_multifab* u_new, double c,
   const Plan& p = *u_old->plan;
   BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream));
   HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u_old, u_new, c), nullptr, 0,
-             p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block, p.rmax, p.nvtmax};
+             p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block, p.rmax, p.nvtmax,
+             p.dlin, (int)p.hlin.size(), p.yhmax, p.xhmax};
   BL_HIP(launch_heat(p.dtype, p.vec, false, a, persistent_grid(tile_config().persist), block_of(p), stream));
   return BL_OK;
 }
@@ -381,7 +384,8 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
     hipStream_t cs = capture_stream();
     if (!cs) return fail(BL_EHIP, "could not create the capture stream");
     HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u[0], u[1], c), nullptr, 0,
-               p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block, p.rmax, p.nvtmax};
+               p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block, p.rmax, p.nvtmax,
+               p.dlin, (int)p.hlin.size(), p.yhmax, p.xhmax};
     BL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     // the edge-column mirror of the starting state, then the fused steps
     hipError_t le = launch_extract_mirror(p, u[0]->data, cs);
@@ -583,7 +587,8 @@ bl_status bl_autotune(const bl_boxarray* ba, bl_multifab* u0, bl_multifab* u1, d
     std::shared_ptr<Plan> pl;
     if ((st = get_plan_cfg(ba, ncomp, ng, dtype, cfg, true, &pl)) != BL_OK) return st;
     HeatArgs a{pl->dtiles, (int)pl->htiles.size(), pl->dboxes, pl->dfacerecs, member_of(u0, u1, c), nullptr, 0,
-               pl->fvec, cfg.zchunk, cfg.block, pl->rmax, pl->nvtmax};
+               pl->fvec, cfg.zchunk, cfg.block, pl->rmax, pl->nvtmax,
+               pl->dlin, (int)pl->hlin.size(), pl->yhmax, pl->xhmax};
     const int grid = persistent_grid(cfg.persist), block = 64 * cfg.waves;
     BL_HIP(launch_extract_mirror(*pl, u0->data, stream));
     for (int s = 0; s < 2; ++s) {  // warm-up; an even count leaves the state in u0
@@ -714,6 +719,34 @@ bl_status bl_tile_list(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_
   return BL_OK;
 }
 
+bl_status bl_stencil_tiles(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_dtype dtype, int32_t* ntiles,
+                           int32_t* tiles) {
+  clear_error();
+  if (!ba || !ntiles) return fail(BL_EINVAL, "NULL argument");
+  if (ncomp < 1 || nghost < 0) return fail(BL_EINVAL, "need ncomp >= 1 and nghost >= 0");
+  if (dtype != BL_F64 && dtype != BL_F32) return fail(BL_EDTYPE, "unknown dtype %d", (int)dtype);
+  std::shared_ptr<Plan> plan;
+  bl_status st = get_plan(ba, ncomp, nghost, dtype, false, &plan);
+  if (st != BL_OK) return st;
+  const auto& t = plan->hlin;
+  *ntiles = (int32_t)t.size();
+  if (tiles)
+    for (size_t i = 0; i < t.size(); ++i) {
+      int32_t* r = tiles + 10 * i;
+      r[0] = t[i].box;
+      r[1] = t[i].comp;
+      r[2] = t[i].q0;
+      r[3] = t[i].nq;
+      r[4] = t[i].nzs;
+      r[5] = t[i].z0;
+      r[6] = t[i].z1;
+      r[7] = plan->cfg.zchunk;
+      r[8] = plan->vec;
+      r[9] = 64 * plan->cfg.waves;
+    }
+  return BL_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- batching
@@ -726,6 +759,8 @@ struct bl_batch {
     int id;
     bool mirrored = false;        // its current state's edge mirror is valid
     std::vector<DevTile> tiles;   // member-local numbering (box, face record, member 0)
+    std::vector<DevLinTile> lin;  // the same for the linear-tile form (block form 3)
+    int yh = 1, xh = 1;
   };
   // Device table of one kind, grown on demand and refilled in stream order from
   // pinned staging memory, so a rebuild needs no device synchronisation.
@@ -747,7 +782,9 @@ struct bl_batch {
     Table<DevBox> boxes;
     Table<DevFaceRec> recs;
     Table<DevTile> tiles;
+    Table<DevLinTile> lin;
     Table<DevMember> dmembers;
+    int yhmax = 1, xhmax = 1;
     hipEvent_t staged = nullptr;  // the last upload from the staging buffers
   };
   std::vector<Member> mems;
@@ -764,6 +801,7 @@ struct bl_batch {
       g.boxes.release();
       g.recs.release();
       g.tiles.release();
+      g.lin.release();
       g.dmembers.release();
       if (g.staged) (void)hipEventDestroy(g.staged);
     }
@@ -807,7 +845,10 @@ static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
   for (auto& m : b->mems)
     if (cfg_changed || m.tiles.empty()) {
       m.tiles.clear();
+      m.lin.clear();
+      m.yh = m.xh = 1;
       build_tiles(*m.u0->plan, cfg, 0, 0, 0, m.tiles, nullptr);
+      if (cfg.block == 3) build_lin_tiles(*m.u0->plan, cfg, 0, 0, 0, m.lin, &m.yh, &m.xh);
     }
   // members grouped by (dtype, vector width): one launch per group
   for (auto& g : b->groups) {
@@ -829,20 +870,30 @@ static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
     if (!p.fvec) g->fvec = 0;
   }
   for (auto& g : b->groups) {
-    size_t nb = 0, nr = 0, nt = 0;
+    size_t nb = 0, nr = 0, nt = 0, nl = 0;
+    g.yhmax = g.xhmax = 1;
+    bool lin_ok = cfg.block == 3;
     for (int i : g.members) {
-      const Plan& p = *b->mems[i].u0->plan;
+      const bl_batch::Member& m = b->mems[i];
+      const Plan& p = *m.u0->plan;
       nb += p.hboxes.size();
       nr += p.hfacerecs.size();
-      nt += b->mems[i].tiles.size();
+      nt += m.tiles.size();
+      nl += m.lin.size();
+      g.yhmax = std::max(g.yhmax, m.yh);
+      g.xhmax = std::max(g.xhmax, m.xh);
+      if (m.lin.empty()) lin_ok = false;
     }
+    if (lin_ok && lin_lds_bytes(cfg, g.dtype == BL_F64 ? 8 : 4, g.vec, g.yhmax, g.xhmax) > kDmaLdsMax) lin_ok = false;
+    if (!lin_ok) nl = 0;
     if (g.staged) BL_HIP(hipEventSynchronize(g.staged));  // staging buffers free again
     bl_status st;
     if ((st = table_reserve(g.boxes, nb, stream)) != BL_OK) return st;
     if ((st = table_reserve(g.recs, nr, stream)) != BL_OK) return st;
     if ((st = table_reserve(g.tiles, nt, stream)) != BL_OK) return st;
+    if ((st = table_reserve(g.lin, nl, stream)) != BL_OK) return st;
     if ((st = table_reserve(g.dmembers, g.members.size(), stream)) != BL_OK) return st;
-    size_t ob = 0, orr = 0, ot = 0;
+    size_t ob = 0, orr = 0, ot = 0, ol = 0;
     g.rmax = g.nvtmax = 1;
     for (size_t k = 0; k < g.members.size(); ++k) {
       const bl_batch::Member& m = b->mems[g.members[k]];
@@ -862,6 +913,14 @@ static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
         g.nvtmax = std::max<int>(g.nvtmax, t.nvt);
         g.tiles.host[ot++] = t;
       }
+      if (nl)
+        for (DevLinTile t : m.lin) {
+          t.box += box_base;
+          t.member = (int32_t)k;
+          for (int f = 0; f < 6; ++f)
+            if (t.frec[f] >= 0) t.frec[f] += rec_base;
+          g.lin.host[ol++] = t;
+        }
       DevMember dm;
       std::memset(&dm, 0, sizeof dm);
       dm.a = m.u0->data;
@@ -873,10 +932,12 @@ static bl_status batch_rebuild(bl_batch* b, hipStream_t stream) {
     g.boxes.n = nb;
     g.recs.n = nr;
     g.tiles.n = nt;
+    g.lin.n = nl;
     g.dmembers.n = g.members.size();
     if ((st = table_upload(g.boxes, stream)) != BL_OK) return st;
     if ((st = table_upload(g.recs, stream)) != BL_OK) return st;
     if ((st = table_upload(g.tiles, stream)) != BL_OK) return st;
+    if ((st = table_upload(g.lin, stream)) != BL_OK) return st;
     if ((st = table_upload(g.dmembers, stream)) != BL_OK) return st;
     if (!g.staged) BL_HIP(hipEventCreateWithFlags(&g.staged, hipEventDisableTiming));
     BL_HIP(hipEventRecord(g.staged, stream));
@@ -951,7 +1012,8 @@ bl_status bl_batch_step(bl_batch* b, hipStream_t stream) {
   for (auto& g : b->groups) {
     if (g.members.empty()) continue;
     HeatArgs a{g.tiles.dev, (int)g.tiles.n, g.boxes.dev, g.recs.dev, DevMember{}, g.dmembers.dev,
-               (int)(b->tick & 1), g.fvec, b->cfg.block ? b->cfg.zchunk : 0, b->cfg.block, g.rmax, g.nvtmax};
+               (int)(b->tick & 1), g.fvec, b->cfg.block ? b->cfg.zchunk : 0, b->cfg.block, g.rmax, g.nvtmax,
+               g.lin.n ? g.lin.dev : nullptr, (int)g.lin.n, g.yhmax, g.xhmax};
     BL_HIP(launch_heat(g.dtype, g.vec, true, a, persistent_grid(b->cfg.persist), 64 * b->cfg.waves, stream));
   }
   b->tick++;

@@ -182,6 +182,23 @@ struct DevTile {    // 32-bit fields only: each one is a plain scalar load
 };
 static_assert(sizeof(DevTile) == 64, "DevTile size");
 
+// A unit of work of the stencil forms with the halo in LDS: a run of nq
+// consecutive x vectors of a plane (the valid rows of a plane are contiguous,
+// so vector q is row q / nvx, x vector q % nvx, and a run may start or end
+// inside a row), over planes z0..z1-1 split into nzs z blocks of zchunk planes.
+// Lane l takes vector q0 + l % nq of block l / nq.  rows spanned: y_first ..
+// y_first + nrows - 1.  frec as for DevTile, over the tile's bounding rows.
+struct DevLinTile {
+  int32_t box;
+  int32_t member;
+  int32_t comp;
+  int32_t q0, nq, nzs;
+  int32_t z0, z1;
+  int32_t y_first, nrows;
+  int32_t frec[6];
+};
+static_assert(sizeof(DevLinTile) == 64, "DevLinTile size");
+
 // One heat problem of a launch: at launch flip f it reads a and writes b when
 // (f + flip_offset) is even, and the reverse when it is odd.
 struct DevMember {
@@ -260,6 +277,9 @@ struct Plan {
   std::vector<int> box_tile_start;        // tiles of box b = [start[b], start[b+1])
   int rmax = 1;                           // most rows of any tile
   int nvtmax = 1;                         // most x vectors of any tile
+  std::vector<DevLinTile> hlin;           // the stencil's tiles (forms with the halo in LDS)
+  int yhmax = 1;                          // most halo row vectors (nzs * min(nvx, nq)) of a linear tile
+  int xhmax = 1;                          // most halo row ends (nzs * nrows) of a linear tile
   std::vector<DevFillRec> hfillrecs;
   std::vector<DevFillChunk> hfillchunks;
   std::shared_ptr<const std::vector<FillRecord>> fill;
@@ -268,6 +288,7 @@ struct Plan {
   DevBox* dboxes = nullptr;
   DevFaceRec* dfacerecs = nullptr;
   DevTile* dtiles = nullptr;
+  DevLinTile* dlin = nullptr;
   DevFillRec* dfillrecs = nullptr;
   DevFillChunk* dfillchunks = nullptr;
   bool uploaded = false;
@@ -283,6 +304,14 @@ std::shared_ptr<const std::vector<FillRecord>> fill_plan(bl_boxarray* ba, int ng
 std::shared_ptr<const std::vector<FaceRecord>> face_plan(bl_boxarray* ba, int ng);
 void build_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base, int rec_base,
                  std::vector<DevTile>& tiles, std::vector<int>* box_tile_start);
+
+// Linear tiles of the stencil for every box and component: runs of at most
+// 64*cfg.waves vectors (plane split evenly), or whole planes stacked in
+// several z blocks when a plane holds fewer vectors than the workgroup.
+void build_lin_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base, int rec_base,
+                     std::vector<DevLinTile>& tiles, int* yhmax, int* xhmax);
+// LDS bytes of one workgroup of the linear-tile stencil forms.
+size_t lin_lds_bytes(const TileConfig& cfg, int esize, int vec, int yhmax, int xhmax);
 
 }  // namespace bl
 

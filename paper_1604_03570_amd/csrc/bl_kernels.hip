@@ -511,189 +511,237 @@ __device__ __forceinline__ void lds_load4(const void*, void*) {}
 #endif
 
 
-// Staging of one tile for the block forms with the halo in LDS.  What lies
-// outside the tile (the rows above and below, the values beyond the row ends)
-// goes from memory straight into LDS, loaded by all waves in 64-lane pieces, so
-// the registers hold only the tile's own planes.  LDS layout: ZB*blockDim plane
-// vectors `sh`, ZB*2*nvtmax row vectors `shy`, ZB*2*rmax values beyond the row
-// ends `shx` (FUSED: then the new edge columns, each written by the one lane
-// that read the value in its slot).
+// The stencil forms with the halo in LDS work on linear tiles (DevLinTile): a
+// run of nq consecutive x vectors of a plane (rows are contiguous, so a run
+// may start and end inside a row), over up to ZB planes per z block and nzs z
+// blocks per workgroup.  What lies outside the run (the nvx vectors before and
+// after it, the values beyond its row ends) goes from memory straight into
+// LDS, loaded by all waves in 64-lane pieces, so the registers hold only the
+// lanes' own planes.  LDS: ZB*blockDim plane vectors `sh`; per z block, plane
+// and side, nh = min(nvx, nq) vectors `shy` and nrows values `shx` (the fused
+// forms then stage the new edge columns there, each slot written by the one
+// lane that read it).
 template <typename T, int V>
 struct TileLds {
   Vec<T, V>* sh;
   Vec<T, V>* shy;
   T* shx;
-  int nvtmax, rmax, nthr, wave, nwaves, lane;
+  int nthr, wave, nwaves, lane;
 };
 
 template <typename T, int V, int ZB>
-__device__ __forceinline__ TileLds<T, V> tile_lds(unsigned char* smem, int nvtmax, int rmax) {
+__device__ __forceinline__ TileLds<T, V> tile_lds(unsigned char* smem, int yhmax) {
   TileLds<T, V> S;
   S.nthr = blockDim.x;
   S.sh = reinterpret_cast<Vec<T, V>*>(smem);
   S.shy = S.sh + ZB * S.nthr;
-  S.shx = reinterpret_cast<T*>(S.shy + ZB * 2 * nvtmax);
-  S.nvtmax = nvtmax;
-  S.rmax = rmax;
+  S.shx = reinterpret_cast<T*>(S.shy + ZB * 2 * yhmax);
   S.wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   S.nwaves = S.nthr >> 6;
   S.lane = (int)threadIdx.x & 63;
   return S;
 }
 
+// Position of this lane in a linear tile.
+struct LinLane {
+  bool active;
+  int s, i;      // z block, index in the run
+  int q, y, xv;  // plane vector, its row and x vector
+  int x0;        // first x cell of the vector
+  int zb0, zb1;  // the lane's planes [zb0, zb1)
+  int nh;        // halo vectors per side: min(nvx, nq)
+};
+
+template <int V, int ZB>
+__device__ __forceinline__ LinLane lin_lane(const DevLinTile& tl, int nvx) {
+  LinLane L;
+  const int l = (int)threadIdx.x;
+  const int s = l / tl.nq;
+  L.active = s < tl.nzs;
+  L.s = L.active ? s : 0;  // idle lanes shadow block 0 so every address stays valid
+  L.i = l - s * tl.nq;
+  L.q = tl.q0 + L.i;
+  L.y = L.q / nvx;
+  L.xv = L.q - L.y * nvx;
+  L.x0 = L.xv * V;
+  L.zb0 = tl.z0 + L.s * ZB;
+  L.zb1 = L.zb0 + ZB < tl.z1 ? L.zb0 + ZB : tl.z1;
+  L.nh = nvx < tl.nq ? nvx : tl.nq;
+  return L;
+}
+
 // Issue the loads of the tile's halo into LDS (no wait).
 template <typename T, int V, bool FUSED, int ZB>
-__device__ __forceinline__ void stage_halo(const TileLds<T, V>& S, const DevTile& tl, const DevBox& B,
+__device__ __forceinline__ void stage_halo(const TileLds<T, V>& S, const DevLinTile& tl, const DevBox& B,
                                            const DevFaceRec* __restrict__ recs, const BL_GLOBAL T* __restrict__ u,
                                            int64_t comp0) {
   using VT = Vec<T, V>;
   constexpr int DPV = (int)sizeof(T) / 4;  // dwords per value
-  const int n = tl.comp, nvt = tl.nvt, rows = tl.rows, z0 = tl.z0, z1 = tl.z1;
-  const int sy = B.sy, sz = B.sz;
-  // rows y0-1 (s = 0) and y0+rows (s = 1) of planes z0..: one 16-byte vector
-  // per lane, or one dword per lane for narrower vectors
+  const int n = tl.comp, nvx = B.nvx, P = B.ey * nvx, sz = B.sz;
+  const int nh = nvx < tl.nq ? nvx : tl.nq, nr = tl.nrows;
+  // the nh vectors before the run (s = 0) and after it (s = 1): one 16-byte
+  // vector per lane, or one dword per lane for narrower vectors
   constexpr int YW = sizeof(VT) == 16 ? 16 : 4;
   constexpr int YPER = (int)sizeof(VT) / YW;  // lanes per vector
-  const int nyi = nvt * YPER, nchy = (nyi + 63) >> 6;
-  for (int q = S.wave; q < ZB * 2 * nchy; q += S.nwaves) {
-    const int k = q / (2 * nchy), s = (q / nchy) & 1, ch = q % nchy;
+  const int nyi = nh * YPER, nchy = (nyi + 63) >> 6;
+  for (int q = S.wave; q < tl.nzs * ZB * 2 * nchy; q += S.nwaves) {
+    const int ch = q % nchy, rest = q / nchy, side = rest & 1, k = (rest >> 1) % ZB, zs = (rest >> 1) / ZB;
     const int i = ch * 64 + S.lane;
-    const int z = z0 + k < z1 ? z0 + k : z1 - 1;
+    const int zz = tl.z0 + zs * ZB + k, z = zz < tl.z1 ? zz : tl.z1 - 1;
     if (i < nyi) {
       const int j = i / YPER, part = i - j * YPER;
-      const int x0 = (tl.xv0 + j) * V;
-      const int y = s ? tl.y0 + rows : tl.y0 - 1;
-      int64_t a = comp0 + x0 + (int64_t)y * sy + (int64_t)z * sz;
-      if (FUSED && (s ? y == B.ey : y < 0)) {
+      const int h = side ? tl.q0 + tl.nq - nh + nvx + j : tl.q0 - nvx + j;
+      int64_t a = comp0 + (int64_t)h * V + (int64_t)z * sz;  // rows y = -1 and y = ey are the ghost rows
+      if (FUSED && (h < 0 || h >= P)) {
+        const int x0 = (h < 0 ? h + nvx : h - P) * V;
         int64_t base = a;
         int step = 0;
-        const int32_t fr = s ? tl.frec[3] : tl.frec[2];
-        const int fs = s ? B.face_start[3] : B.face_start[2], fc = s ? B.face_count[3] : B.face_count[2];
-        tile_face_source(recs, fr, fs, fc, true, x0, z0, n, base, step);
+        const int32_t fr = side ? tl.frec[3] : tl.frec[2];
+        const int fs = side ? B.face_start[3] : B.face_start[2], fc = side ? B.face_count[3] : B.face_count[2];
+        tile_face_source(recs, fr, fs, fc, true, x0, tl.z0, n, base, step);
         a = base + (int64_t)z * step;
       }
+      VT* dst = S.shy + ((zs * ZB + k) * 2 + side) * nh;
       if (YW == 16)
-        lds_load16(u + a, S.shy + (k * 2 + s) * S.nvtmax + ch * 64);
+        lds_load16(u + a, dst + ch * 64);
       else
         lds_load4(reinterpret_cast<const BL_GLOBAL unsigned char*>(u + a) + part * 4,
-                  reinterpret_cast<unsigned char*>(S.shy + (k * 2 + s) * S.nvtmax) + ch * 256);
+                  reinterpret_cast<unsigned char*>(dst) + ch * 256);
     }
   }
-  // values left (s = 0) and right (s = 1) of the tile's rows, one dword per lane
-  const int nitems = rows * DPV, nchx = (nitems + 63) >> 6;
-  const bool face_lo = tl.xv0 == 0, face_hi = tl.xv0 + nvt == B.nvx;
-  for (int q = S.wave; q < ZB * 2 * nchx; q += S.nwaves) {
-    const int k = q / (2 * nchx), s = (q / nchx) & 1, ch = q % nchx;
+  // the values left (side 0) and right (side 1) of each row of the run, one dword
+  // per lane: the box face (x slab or face record) where the row's end lies in
+  // the run, else the element next to the run in the same row
+  const int nitems = nr * DPV, nchx = (nitems + 63) >> 6;
+  const bool lo_inrow = tl.q0 % nvx != 0, hi_inrow = (tl.q0 + tl.nq) % nvx != 0;
+  for (int q = S.wave; q < tl.nzs * ZB * 2 * nchx; q += S.nwaves) {
+    const int ch = q % nchx, rest = q / nchx, side = rest & 1, k = (rest >> 1) % ZB, zs = (rest >> 1) / ZB;
     const int i = ch * 64 + S.lane;
-    const int z = z0 + k < z1 ? z0 + k : z1 - 1;
+    const int zz = tl.z0 + zs * ZB + k, z = zz < tl.z1 ? zz : tl.z1 - 1;
     if (i < nitems) {
       const int r = i / DPV, part = i - r * DPV;
-      const int y = tl.y0 + r;
+      const int y = tl.y_first + r;
       int64_t a;
-      if (!(s ? face_hi : face_lo)) {
-        a = comp0 + (int64_t)y * sy + (int64_t)z * sz + (s ? (tl.xv0 + nvt) * V : tl.xv0 * V - 1);
+      if (side == 0 && r == 0 && lo_inrow) {
+        a = comp0 + (int64_t)tl.q0 * V - 1 + (int64_t)z * sz;
+      } else if (side == 1 && r == nr - 1 && hi_inrow) {
+        a = comp0 + (int64_t)(tl.q0 + tl.nq) * V + (int64_t)z * sz;
       } else if (!FUSED) {
-        a = B.xs + (int64_t)n * B.sc + (s ? B.xs_side : 0) + (int64_t)z * B.xs_z + (int64_t)y * B.ng;
+        a = B.xs + (int64_t)n * B.sc + (side ? B.xs_side : 0) + (int64_t)z * B.xs_z + (int64_t)y * B.ng;
       } else {
         int64_t base = 0;
         int step = 0;
-        const int32_t fr = s ? tl.frec[1] : tl.frec[0];
-        const int fs = s ? B.face_start[1] : B.face_start[0], fc = s ? B.face_count[1] : B.face_count[0];
-        tile_face_source(recs, fr, fs, fc, true, y, z0, n, base, step);
+        const int32_t fr = side ? tl.frec[1] : tl.frec[0];
+        const int fs = side ? B.face_start[1] : B.face_start[0], fc = side ? B.face_count[1] : B.face_count[0];
+        tile_face_source(recs, fr, fs, fc, true, y, tl.z0, n, base, step);
         a = base + (int64_t)z * step;
       }
       lds_load4(reinterpret_cast<const BL_GLOBAL unsigned char*>(u + a) + part * 4,
-                reinterpret_cast<unsigned char*>(S.shx + (k * 2 + s) * S.rmax) + ch * 256);
+                reinterpret_cast<unsigned char*>(S.shx + ((zs * ZB + k) * 2 + side) * nr) + ch * 256);
     }
   }
 }
 
-// The lane's own planes z0-1 .. z0+ZB (clamped to z1; z-face planes through the
+// The lane's planes zb0-1 .. zb0+ZB (clamped to zb1; z-face planes through the
 // face records when FUSED) into registers.
 template <typename T, int V, bool FUSED, int ZB>
-__device__ __forceinline__ void load_planes(Vec<T, V> (&P)[ZB + 2], const DevTile& tl, const DevBox& B,
-                                            const DevFaceRec* __restrict__ recs, const BL_GLOBAL T* __restrict__ u,
-                                            int64_t cb, int x0, int yy) {
-  const int n = tl.comp, z0 = tl.z0, z1 = tl.z1, sz = B.sz;
+__device__ __forceinline__ void load_planes(Vec<T, V> (&P)[ZB + 2], const LinLane& L, const DevLinTile& tl,
+                                            const DevBox& B, const DevFaceRec* __restrict__ recs,
+                                            const BL_GLOBAL T* __restrict__ u, int64_t cb) {
+  const int n = tl.comp, sz = B.sz;
   int64_t zlo = cb - sz, zhi = cb + (int64_t)B.ez * sz;
   if (FUSED) {
-    if (z0 == 0) zlo = tile_face_index(recs, tl.frec[4], B.face_start[4], B.face_count[4], x0, yy, n, zlo);
-    if (z1 == B.ez) zhi = tile_face_index(recs, tl.frec[5], B.face_start[5], B.face_count[5], x0, yy, n, zhi);
+    if (tl.z0 == 0) zlo = tile_face_index(recs, tl.frec[4], B.face_start[4], B.face_count[4], L.x0, L.y, n, zlo);
+    if (tl.z1 == B.ez) zhi = tile_face_index(recs, tl.frec[5], B.face_start[5], B.face_count[5], L.x0, L.y, n, zhi);
   }
 #pragma unroll
   for (int k = 0; k < ZB + 2; ++k) {
-    const int z = z0 - 1 + k < z1 ? z0 - 1 + k : z1;
+    const int z = L.zb0 - 1 + k < L.zb1 ? L.zb0 - 1 + k : L.zb1;
     int64_t a = cb + (int64_t)z * sz;
     if (FUSED) a = z < 0 ? zlo : (z >= B.ez ? zhi : a);
     P[k] = ldv<T, V>(u + a);
   }
 }
 
-// Neighbours of the lane's vector in plane k of the tile (after the barrier that
-// follows the planes' LDS writes): the values left and right of it, the vectors
-// of the rows below and above.
+// Neighbours of the lane's vector in its plane k (after the barrier that follows
+// the planes' LDS writes): the values left and right of it, the vectors of the
+// rows below and above.
 template <typename T, int V>
 struct Nbr {
   T left, right;
   Vec<T, V> ym, yp;
 };
-template <typename T, int V>
-__device__ __forceinline__ Nbr<T, V> tile_neighbours(const TileLds<T, V>& S, const TileLane& L, int k, int nvt,
-                                                     int rows) {
+template <typename T, int V, int ZB>
+__device__ __forceinline__ Nbr<T, V> tile_neighbours(const TileLds<T, V>& S, const LinLane& L, const DevLinTile& tl,
+                                                     int nvx, int k) {
   const Vec<T, V>* row = S.sh + k * S.nthr + threadIdx.x;
+  const int slot = (L.s * ZB + k) * 2;
+  const int r = L.y - tl.y_first;
   Nbr<T, V> N;
-  N.left = L.lx == 0 ? S.shx[(k * 2) * S.rmax + L.ty] : row[-1].v[V - 1];
-  N.right = L.lx == nvt - 1 ? S.shx[(k * 2 + 1) * S.rmax + L.ty] : row[1].v[0];
-  N.ym = L.ty == 0 ? S.shy[(k * 2) * S.nvtmax + L.lx] : row[-nvt];
-  N.yp = L.ty == rows - 1 ? S.shy[(k * 2 + 1) * S.nvtmax + L.lx] : row[nvt];
+  N.left = (L.xv == 0 || L.i == 0) ? S.shx[slot * tl.nrows + r] : row[-1].v[V - 1];
+  N.right = (L.xv == nvx - 1 || L.i == tl.nq - 1) ? S.shx[(slot + 1) * tl.nrows + r] : row[1].v[0];
+  N.ym = L.i < nvx ? S.shy[slot * L.nh + L.i] : row[-nvx];
+  N.yp = L.i + nvx >= tl.nq ? S.shy[(slot + 1) * L.nh + L.i - (tl.nq - L.nh)] : row[nvx];
   return N;
 }
 
-// The new edge columns staged in shx, stored as contiguous runs into the mirror.
+// A lane's new edge values into its own x-halo slots (the mirror staging).
 template <typename T, int V, int ZB>
-__device__ __forceinline__ void store_mirror(const TileLds<T, V>& S, const DevTile& tl, const DevBox& B,
+__device__ __forceinline__ void stage_edges(const TileLds<T, V>& S, const LinLane& L, const DevLinTile& tl, int nvx,
+                                            int k, const Vec<T, V>& o) {
+  const int slot = (L.s * ZB + k) * 2, r = L.y - tl.y_first;
+  if (L.xv == 0) S.shx[slot * tl.nrows + r] = o.v[0];
+  if (L.xv == nvx - 1) S.shx[(slot + 1) * tl.nrows + r] = o.v[V - 1];
+}
+
+// The staged edge columns of the run's rows whose ends lie in the run, stored
+// as contiguous runs into the mirror.
+template <typename T, int V, int ZB>
+__device__ __forceinline__ void store_mirror(const TileLds<T, V>& S, const DevLinTile& tl, const DevBox& B,
                                              BL_GLOBAL T* __restrict__ w) {
-  const bool face_lo = tl.xv0 == 0, face_hi = tl.xv0 + tl.nvt == B.nvx;
-  if (!(face_lo || face_hi)) return;
+  const int nvx = B.nvx, nr = tl.nrows;
+  const bool lo_first = tl.q0 % nvx == 0, hi_last = (tl.q0 + tl.nq) % nvx == 0;
+  if (nr == 1 && !lo_first && !hi_last) return;  // a run inside one row: no box face
   lds_barrier();
-  const int rows = tl.rows, z0 = tl.z0, z1 = tl.z1;
-  BL_GLOBAL T* mir = w + B.mir + (int64_t)tl.comp * B.sc + tl.y0;
-  for (int q = threadIdx.x; q < 2 * ZB * rows; q += S.nthr) {
-    const int side = q / (ZB * rows), k = (q / rows) % ZB, r = q % rows;
-    if (z0 + k < z1 && (side ? face_hi : face_lo))
-      mir[side * B.mir_side + (int64_t)(z0 + k) * B.ey + r] = S.shx[(k * 2 + side) * S.rmax + r];
+  BL_GLOBAL T* mir = w + B.mir + (int64_t)tl.comp * B.sc + tl.y_first;
+  const int per = tl.nzs * ZB * 2 * nr;
+  for (int q = threadIdx.x; q < per; q += S.nthr) {
+    const int r = q % nr, rest = q / nr, side = rest & 1, k = (rest >> 1) % ZB, zs = (rest >> 1) / ZB;
+    const int z = tl.z0 + zs * ZB + k;
+    const bool has = side ? (r < nr - 1 || hi_last) : (r > 0 || lo_first);
+    if (has && k < ZB && z < tl.z1 && z < tl.z0 + (zs + 1) * ZB)
+      mir[side * B.mir_side + (int64_t)z * B.ey + r] = S.shx[((zs * ZB + k) * 2 + side) * nr + r];
   }
 }
 
 // Heat step, block form with the halo in LDS: one wait for all loads, the
-// tile's planes into LDS, one barrier, the updates, full-vector stores.
+// lanes' planes into LDS, one barrier, the updates, full-vector stores.
 template <typename T, int V, bool FUSED, int ZB>
 __global__ void __launch_bounds__(kStencilMaxThreads)
-    __attribute__((amdgpu_waves_per_eu(FUSED ? (ZB == 8 ? 4 : 6) : (ZB == 8 ? 5 : 8))))
-    k_heat_dma(const DevTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+    __attribute__((amdgpu_waves_per_eu(ZB == 8 ? 4 : 6)))
+    k_heat_dma(const DevLinTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
                const DevFaceRec* __restrict__ recs, DevMember m0, const DevMember* __restrict__ members, int flip,
-               int persist, int nvtmax, int rmax) {
+               int persist, int yhmax) {
   using VT = Vec<T, V>;
   extern __shared__ unsigned char smem_raw[];
-  const TileLds<T, V> S = tile_lds<T, V, ZB>(smem_raw, nvtmax, rmax);
+  const TileLds<T, V> S = tile_lds<T, V, ZB>(smem_raw, yhmax);
   int first, last;
   tile_range(ntiles, persist, first, last);
   for (int t = first; t < last; ++t) {
-    const DevTile tl = ldc(tiles + t);
+    const DevLinTile tl = ldc(tiles + t);
     const DevBox B = ldc(boxes + tl.box);
     const DevMember M = members ? ldc(members + tl.member) : m0;
     const bool swap = ((flip + M.flip_offset) & 1) != 0;
     const BL_GLOBAL T* __restrict__ u = as_global(static_cast<const T*>(swap ? M.b : M.a));
     BL_GLOBAL T* __restrict__ w = as_global(static_cast<T*>(swap ? M.a : M.b));
     const T c = (T)M.c;
-    const TileLane L = tile_lane<V>(tl);
-    const int nvt = tl.nvt, rows = tl.rows;
-    const int yy = L.active ? L.y : tl.y0;
+    const int nvx = B.nvx;
+    const LinLane L = lin_lane<V, ZB>(tl, nvx);
     const int64_t comp0 = B.off + (int64_t)tl.comp * B.sc;
-    const int64_t cb = comp0 + L.x0 + (int64_t)yy * B.sy;
+    const int64_t cb = comp0 + (int64_t)L.q * V;
 
     VT P[ZB + 2];
-    load_planes<T, V, FUSED, ZB>(P, tl, B, recs, u, cb, L.x0, yy);
+    load_planes<T, V, FUSED, ZB>(P, L, tl, B, recs, u, cb);
     stage_halo<T, V, FUSED, ZB>(S, tl, B, recs, u, comp0);
 #pragma unroll
     for (int k = 0; k < ZB; ++k) S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
@@ -701,7 +749,7 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
     BL_GLOBAL T* wp = w + cb;
 #pragma unroll
     for (int k = 0; k < ZB; ++k) {
-      const Nbr<T, V> N = tile_neighbours<T, V>(S, L, k, nvt, rows);
+      const Nbr<T, V> N = tile_neighbours<T, V, ZB>(S, L, tl, nvx, k);
       VT o;
 #pragma unroll
       for (int e = 0; e < V; ++e) {
@@ -709,11 +757,10 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
         const T xp = e == V - 1 ? N.right : P[k + 1].v[e + 1];
         o.v[e] = heat_cell(P[k + 1].v[e], xm, xp, N.ym.v[e], N.yp.v[e], P[k].v[e], P[k + 2].v[e], c);
       }
-      const int z = tl.z0 + k;
-      if (z < tl.z1 && L.active) stv<T, V>(wp + (int64_t)z * B.sz, o);
-      if (FUSED && L.active) {
-        if (L.xv == 0) S.shx[(k * 2) * S.rmax + L.ty] = o.v[0];
-        if (L.xv == B.nvx - 1) S.shx[(k * 2 + 1) * S.rmax + L.ty] = o.v[V - 1];
+      const int z = L.zb0 + k;
+      if (z < L.zb1 && L.active) {
+        stv<T, V>(wp + (int64_t)z * B.sz, o);
+        if (FUSED) stage_edges<T, V, ZB>(S, L, tl, nvx, k, o);
       }
     }
     if (FUSED) store_mirror<T, V, ZB>(S, tl, B, w);
@@ -739,45 +786,44 @@ __device__ double block_reduce(double v, int op);
 // pass.  color -1 stores nothing and may take any rescolor.
 template <typename T, int V, int ZB, bool RES>
 __global__ void __launch_bounds__(kStencilMaxThreads)
-    __attribute__((amdgpu_waves_per_eu(RES ? (ZB == 8 ? 2 : 4) : (ZB == 8 ? 4 : 6))))
-    k_gsrb_dma(const DevTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+    __attribute__((amdgpu_waves_per_eu(RES ? (ZB == 8 ? 2 : 4) : (ZB == 8 ? 3 : 6))))
+    k_gsrb_dma(const DevLinTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
                const DevFaceRec* __restrict__ recs, T* phi_, const T* __restrict__ f_, T h2, T inv6, int color,
-               int rescolor, double h2d, double* __restrict__ partials, int persist, int nvtmax, int rmax) {
+               int rescolor, double h2d, double* __restrict__ partials, int persist, int yhmax) {
   using VT = Vec<T, V>;
   extern __shared__ unsigned char smem_raw[];
-  const TileLds<T, V> S = tile_lds<T, V, ZB>(smem_raw, nvtmax, rmax);
+  const TileLds<T, V> S = tile_lds<T, V, ZB>(smem_raw, yhmax);
   BL_GLOBAL T* phi = as_global(phi_);
   const BL_GLOBAL T* __restrict__ fq = as_global(f_);
   double acc = 0.0;
   int first, last;
   tile_range(ntiles, persist, first, last);
   for (int t = first; t < last; ++t) {
-    const DevTile tl = ldc(tiles + t);
+    const DevLinTile tl = ldc(tiles + t);
     const DevBox B = ldc(boxes + tl.box);
-    const TileLane L = tile_lane<V>(tl);
-    const int nvt = tl.nvt, rows = tl.rows;
-    const int yy = L.active ? L.y : tl.y0;
+    const int nvx = B.nvx;
+    const LinLane L = lin_lane<V, ZB>(tl, nvx);
     const int64_t comp0 = B.off + (int64_t)tl.comp * B.sc;
-    const int64_t cb = comp0 + L.x0 + (int64_t)yy * B.sy;
-    const int par0 = (B.glo[0] + L.x0 + B.glo[1] + yy + B.glo[2]) & 1;  // parity of (x0, y, z = 0)
+    const int64_t cb = comp0 + (int64_t)L.q * V;
+    const int par0 = (B.glo[0] + L.x0 + B.glo[1] + L.y + B.glo[2]) & 1;  // parity of (x0, y, z = 0)
 
-    stage_halo<T, V, true, ZB>(S, tl, B, recs, phi, comp0);
     VT P[ZB + 2], F[ZB];
-    load_planes<T, V, true, ZB>(P, tl, B, recs, phi, cb, L.x0, yy);
+    load_planes<T, V, true, ZB>(P, L, tl, B, recs, phi, cb);
 #pragma unroll
     for (int k = 0; k < ZB; ++k) {
-      const int z = tl.z0 + k < tl.z1 ? tl.z0 + k : tl.z1 - 1;
+      const int z = L.zb0 + k < L.zb1 ? L.zb0 + k : L.zb1 - 1;
       F[k] = ldv<T, V>(fq + cb + (int64_t)z * B.sz);
     }
+    stage_halo<T, V, true, ZB>(S, tl, B, recs, phi, comp0);
 #pragma unroll
     for (int k = 0; k < ZB; ++k) S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
     __syncthreads();
     BL_GLOBAL T* wp = phi + cb;
 #pragma unroll
     for (int k = 0; k < ZB; ++k) {
-      const Nbr<T, V> N = tile_neighbours<T, V>(S, L, k, nvt, rows);
-      const int z = tl.z0 + k;
-      const bool valid = z < tl.z1 && L.active;
+      const Nbr<T, V> N = tile_neighbours<T, V, ZB>(S, L, tl, nvx, k);
+      const int z = L.zb0 + k;
+      const bool valid = z < L.zb1 && L.active;
       VT o = P[k + 1];
       if (color >= 0) {
 #pragma unroll
@@ -803,10 +849,9 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
         }
       }
       if (color < 0) continue;
-      if (valid) stv<T, V>(wp + (int64_t)z * B.sz, o);
-      if (L.active) {
-        if (L.xv == 0) S.shx[(k * 2) * S.rmax + L.ty] = o.v[0];
-        if (L.xv == B.nvx - 1) S.shx[(k * 2 + 1) * S.rmax + L.ty] = o.v[V - 1];
+      if (valid) {
+        stv<T, V>(wp + (int64_t)z * B.sz, o);
+        stage_edges<T, V, ZB>(S, L, tl, nvx, k, o);
       }
     }
     if (color >= 0) store_mirror<T, V, ZB>(S, tl, B, phi);
@@ -1104,21 +1149,22 @@ hipError_t heat_dispatch_lds(bool fused, const HeatArgs& a, int g, int block, in
 }
 
 template <typename T, int V, int ZB>
-size_t dma_lds_bytes(bool fused, const HeatArgs& a, int block) {
-  (void)fused;
-  return (size_t)ZB * block * sizeof(Vec<T, V>) + (size_t)ZB * 2 * a.nvtmax * sizeof(Vec<T, V>) +
-         (size_t)ZB * 2 * a.rmax * sizeof(T);
+size_t dma_lds_bytes(int yhmax, int xhmax, int block) {
+  return (size_t)ZB * block * sizeof(Vec<T, V>) + (size_t)ZB * 2 * yhmax * sizeof(Vec<T, V>) +
+         (size_t)ZB * 2 * xhmax * sizeof(T);
 }
 
 template <typename T, int V, int ZB>
-hipError_t heat_dispatch_dma(bool fused, const HeatArgs& a, int g, int block, int persist, hipStream_t s) {
-  const size_t lds = dma_lds_bytes<T, V, ZB>(fused, a, block);
+hipError_t heat_dispatch_dma(bool fused, const HeatArgs& a, int block, int grid, hipStream_t s) {
+  const int persist = grid > 0 ? 1 : 0;
+  const int g = persist ? (grid < a.nlin ? grid : a.nlin) : a.nlin;
+  const size_t lds = dma_lds_bytes<T, V, ZB>(a.yhmax, a.xhmax, block);
   if (fused)
-    hipLaunchKernelGGL((k_heat_dma<T, V, true, ZB>), dim3(g), dim3(block), lds, s, a.tiles, a.ntiles, a.boxes, a.recs,
-                       a.m0, a.members, a.flip, persist, a.nvtmax, a.rmax);
+    hipLaunchKernelGGL((k_heat_dma<T, V, true, ZB>), dim3(g), dim3(block), lds, s, a.lin, a.nlin, a.boxes, a.recs,
+                       a.m0, a.members, a.flip, persist, a.yhmax);
   else
-    hipLaunchKernelGGL((k_heat_dma<T, V, false, ZB>), dim3(g), dim3(block), lds, s, a.tiles, a.ntiles, a.boxes,
-                       a.recs, a.m0, a.members, a.flip, persist, a.nvtmax, a.rmax);
+    hipLaunchKernelGGL((k_heat_dma<T, V, false, ZB>), dim3(g), dim3(block), lds, s, a.lin, a.nlin, a.boxes, a.recs,
+                       a.m0, a.members, a.flip, persist, a.yhmax);
   return hipGetLastError();
 }
 
@@ -1126,22 +1172,12 @@ template <typename T, int V>
 hipError_t heat_dispatch(bool fused, const HeatArgs& a, int grid, int block, hipStream_t s) {
   const int persist = grid > 0 ? 1 : 0;
   const int g = persist ? (grid < a.ntiles ? grid : a.ntiles) : a.ntiles;
-  // the halo-in-LDS form while its LDS fits one workgroup's share
-  if (a.form == 3 && (!fused || a.fvec) && a.nvtmax > 0 && a.rmax > 0) {
+  // the halo-in-LDS form over the linear tiles (its LDS is checked when the plan is made)
+  if (a.form == 3 && a.lin && (!fused || a.fvec)) {
     switch (a.zblock) {
-      case 2:
-        if (dma_lds_bytes<T, V, 2>(fused, a, block) <= kDmaLdsMax)
-          return heat_dispatch_dma<T, V, 2>(fused, a, g, block, persist, s);
-        break;
-      case 4:
-        if (dma_lds_bytes<T, V, 4>(fused, a, block) <= kDmaLdsMax)
-          return heat_dispatch_dma<T, V, 4>(fused, a, g, block, persist, s);
-        break;
-      case 8:
-        if (dma_lds_bytes<T, V, 8>(fused, a, block) <= kDmaLdsMax)
-          return heat_dispatch_dma<T, V, 8>(fused, a, g, block, persist, s);
-        break;
-      default: break;
+      case 2: return heat_dispatch_dma<T, V, 2>(fused, a, block, grid, s);
+      case 8: return heat_dispatch_dma<T, V, 8>(fused, a, block, grid, s);
+      default: return heat_dispatch_dma<T, V, 4>(fused, a, block, grid, s);
     }
   }
   if (a.form >= 2 && (!fused || a.fvec)) {
@@ -1175,7 +1211,7 @@ int device_cu_count() {
 }
 
 hipError_t launch_heat(int dtype, int vec, bool fused, const HeatArgs& a, int grid, int block, hipStream_t s) {
-  if (a.ntiles <= 0) return hipSuccess;
+  if ((a.form == 3 && a.lin ? a.nlin : a.ntiles) <= 0) return hipSuccess;
   if (dtype == BL_F64) return vec == 2 ? heat_dispatch<double, 2>(fused, a, grid, block, s)
                                        : heat_dispatch<double, 1>(fused, a, grid, block, s);
   return vec == 4 ? heat_dispatch<float, 4>(fused, a, grid, block, s) : heat_dispatch<float, 1>(fused, a, grid, block, s);
@@ -1338,19 +1374,16 @@ hipError_t launch_residual(const Plan& p, const void* phi, const void* f, double
 template <typename T, int V, int ZB>
 static hipError_t gsrb_dma_zb(const Plan& p, void* phi, const void* f, double h2, int color, int rescolor,
                               double* partials, int g, int persist, int block, hipStream_t s) {
-  HeatArgs a{};
-  a.rmax = p.rmax;
-  a.nvtmax = p.nvtmax;
-  const size_t lds = dma_lds_bytes<T, V, ZB>(true, a, block);
+  const size_t lds = dma_lds_bytes<T, V, ZB>(p.yhmax, p.xhmax, block);
   const T h2t = (T)h2, inv6 = (T)(1.0 / 6.0);
   if (partials)
-    hipLaunchKernelGGL((k_gsrb_dma<T, V, ZB, true>), dim3(g), dim3(block), lds, s, p.dtiles,
-                       (int)p.htiles.size(), p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor,
-                       h2, partials, persist, p.nvtmax, p.rmax);
+    hipLaunchKernelGGL((k_gsrb_dma<T, V, ZB, true>), dim3(g), dim3(block), lds, s, p.dlin, (int)p.hlin.size(),
+                       p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor, h2, partials, persist,
+                       p.yhmax);
   else
-    hipLaunchKernelGGL((k_gsrb_dma<T, V, ZB, false>), dim3(g), dim3(block), lds, s, p.dtiles,
-                       (int)p.htiles.size(), p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor,
-                       h2, partials, persist, p.nvtmax, p.rmax);
+    hipLaunchKernelGGL((k_gsrb_dma<T, V, ZB, false>), dim3(g), dim3(block), lds, s, p.dlin, (int)p.hlin.size(),
+                       p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor, h2, partials, persist,
+                       p.yhmax);
   return hipGetLastError();
 }
 
@@ -1365,24 +1398,18 @@ static hipError_t gsrb_dma_v(const Plan& p, void* phi, const void* f, double h2,
 }
 
 bool gsrb_fused_ok(const Plan& p, int block) {
-  if (p.cfg.block != 3 || !p.fvec || p.htiles.empty()) return false;
-  HeatArgs a{};
-  a.rmax = p.rmax;
-  a.nvtmax = p.nvtmax;
-  const int zb = p.cfg.zchunk == 2 || p.cfg.zchunk == 8 ? p.cfg.zchunk : 4;
-  const size_t elt = p.dtype == BL_F64 ? 8 : 4;
-  const size_t lds = (size_t)zb * block * 16 + (size_t)zb * 2 * a.nvtmax * (elt * p.vec) + (size_t)zb * 2 * a.rmax * elt;
-  return lds <= kDmaLdsMax;
+  (void)block;
+  return p.cfg.block == 3 && p.fvec && !p.hlin.empty();  // linear tiles exist only where their LDS fits
 }
 
 int gsrb_fused_grid(const Plan& p, int grid) {
-  const int nt = (int)p.htiles.size();
+  const int nt = (int)p.hlin.size();
   return grid > 0 ? (grid < nt ? grid : nt) : nt;
 }
 
 hipError_t launch_gsrb_fused(const Plan& p, void* phi, const void* f, double h2, int color, int rescolor,
                              double* partials, int grid, int block, hipStream_t s) {
-  if (p.htiles.empty()) return hipSuccess;
+  if (p.hlin.empty()) return hipSuccess;
   const int g = gsrb_fused_grid(p, grid), persist = grid > 0 ? 1 : 0;
   if (p.dtype == BL_F64)
     return p.vec == 2 ? gsrb_dma_v<double, 2>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s)

@@ -22,6 +22,10 @@ struct HeatArgs {
   int form;                    // 0 march, 1 block, 2 block with LDS neighbours, 3 as 2 with halos loaded into LDS
   int rmax;                    // most rows of any tile of the launch
   int nvtmax;                  // most x vectors of any tile of the launch
+  // form 3: the linear tiles (when null, form 3 runs as form 2 on `tiles`)
+  const DevLinTile* lin;
+  int nlin;
+  int yhmax, xhmax;            // LDS sizing: most halo vectors / row ends of a linear tile
 };
 
 // Stencil over `ntiles` tiles.  fused: tiles at box faces read neighbour boxes

@@ -465,6 +465,74 @@ void build_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base,
   if (box_tile_start) box_tile_start->push_back((int)tiles.size());
 }
 
+size_t lin_lds_bytes(const TileConfig& cfg, int esize, int vec, int yhmax, int xhmax) {
+  const size_t zb = (size_t)cfg.zchunk, vb = (size_t)esize * vec;
+  return zb * 64 * cfg.waves * vb + zb * 2 * yhmax * vb + zb * 2 * xhmax * esize;
+}
+
+void build_lin_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base, int rec_base,
+                     std::vector<DevLinTile>& tiles, int* yhmax, int* xhmax) {
+  const int lanes = 64 * cfg.waves;
+  const int zb = std::max(1, cfg.zchunk);
+  std::vector<int> zc;
+  for (int b = 0; b < (int)p.hboxes.size(); ++b) {
+    const DevBox& B = p.hboxes[b];
+    const int nvx = B.nvx, P = B.ey * nvx;
+    int nq, nzs, ntq;
+    if (P >= lanes) {  // the plane split into ntq near-equal runs of at most `lanes` vectors
+      ntq = (P + lanes - 1) / lanes;
+      nq = (P + ntq - 1) / ntq;
+      nzs = 1;
+    } else {           // whole planes, as many z blocks as fill the workgroup
+      ntq = 1;
+      nq = P;
+      nzs = std::max(1, std::min(lanes / P, (B.ez + zb - 1) / zb));
+    }
+    const int zlen = zb * nzs;
+    // z cuts: multiples of zlen and every z boundary of the x- and y-face records
+    zc.clear();
+    for (int z = 0; z < B.ez; z += zlen) zc.push_back(z);
+    zc.push_back(B.ez);
+    for (int f = 0; f < 4; ++f)
+      for (int r = B.face_start[f]; r < B.face_start[f] + B.face_count[f]; ++r) {
+        zc.push_back(std::max(0, std::min<int>(B.ez, p.hfacerecs[r].t2lo)));
+        zc.push_back(std::max(0, std::min<int>(B.ez, p.hfacerecs[r].t2hi + 1)));
+      }
+    std::sort(zc.begin(), zc.end());
+    zc.erase(std::unique(zc.begin(), zc.end()), zc.end());
+    for (int n = 0; n < p.ncomp; ++n)
+      for (size_t k = 0; k + 1 < zc.size(); ++k)
+        for (int tq = 0; tq < ntq; ++tq) {
+          DevLinTile t;
+          std::memset(&t, 0, sizeof t);
+          t.box = box_base + b;
+          t.member = member;
+          t.comp = n;
+          t.q0 = tq * nq;
+          t.nq = std::min(nq, P - t.q0);
+          t.z0 = zc[k];
+          t.z1 = zc[k + 1];
+          t.nzs = std::min(nzs, (t.z1 - t.z0 + zb - 1) / zb);
+          t.y_first = t.q0 / nvx;
+          const int y_last = (t.q0 + t.nq - 1) / nvx;
+          t.nrows = y_last - t.y_first + 1;
+          const int x1 = B.ex - 1, z1 = t.z1 - 1;
+          const bool touch[6] = {true, true, t.q0 < nvx, t.q0 + t.nq > P - nvx, t.z0 == 0, t.z1 == B.ez};
+          const int rect[6][4] = {{t.y_first, y_last, t.z0, z1}, {t.y_first, y_last, t.z0, z1}, {0, x1, t.z0, z1},
+                                  {0, x1, t.z0, z1},              {0, x1, t.y_first, y_last},   {0, x1, t.y_first, y_last}};
+          for (int f = 0; f < 6; ++f) {
+            t.frec[f] = kFaceNone;
+            if (!touch[f]) continue;
+            const int32_t r = covering_record(p, B, f, rect[f][0], rect[f][1], rect[f][2], rect[f][3]);
+            t.frec[f] = r >= 0 ? r + rec_base : r;
+          }
+          if (yhmax) *yhmax = std::max(*yhmax, t.nzs * std::min(nvx, t.nq));
+          if (xhmax) *xhmax = std::max(*xhmax, t.nzs * t.nrows);
+          tiles.push_back(t);
+        }
+  }
+}
+
 // Layout of one FAB whose first element is `fab` (a multiple of A elements,
 // A = 128 bytes / element size).  Returns its size in elements.
 static int64_t layout_fab(const Box& b, int ng, int ncomp, int64_t A, int64_t fab, FabGeom& f) {
@@ -664,6 +732,10 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
   for (const DevTile& t : p->htiles) {
     p->rmax = std::max<int>(p->rmax, t.rows);
     p->nvtmax = std::max<int>(p->nvtmax, t.nvt);
+  }
+  if (cfg.block == 3) {
+    build_lin_tiles(*p, cfg, 0, 0, 0, p->hlin, &p->yhmax, &p->xhmax);
+    if (lin_lds_bytes(cfg, p->esize, p->vec, p->yhmax, p->xhmax) > kDmaLdsMax) p->hlin.clear();  // form 2 instead
   }
   *out = p;
   return BL_OK;

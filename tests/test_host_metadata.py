@@ -170,6 +170,47 @@ def test_tile_list_covers_every_cell_once(dtype, boxes_kind):
         assert cover.min() == 1 and cover.max() == 1
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("boxes_kind", ["regular", "uneven", "odd"])
+@pytest.mark.parametrize("shape", [(4, 4), (2, 4), (8, 2), (4, 3)])
+def test_stencil_tiles_cover_every_cell_once(dtype, boxes_kind, shape):
+    """Linear tiles (runs of consecutive vectors of a plane, whole planes stacked in z
+    blocks for small planes) cover every valid cell of every component exactly once,
+    fit the workgroup, and do not straddle a z boundary of an x or y face record."""
+    if boxes_kind == "regular":
+        dom, boxes = I.domain_box(64), I.regular_chop(I.domain_box(64), 32)
+    elif boxes_kind == "uneven":
+        dom = I.domain_box(128)
+        boxes = I.random_chop(dom, 16, 64, 8, seed=3)
+    else:
+        dom = I.domain_box((21, 13, 9))
+        boxes = I.random_chop(dom, 3, 8, 1, seed=5)
+    ncomp = 2
+    saved = bt.get_tile_config()
+    bt.set_tile_config(shape[0], shape[1], 0, 3)
+    try:
+        ba = bt.BoxArray.from_boxes(boxes, dom)
+        tiles = ba.stencil_tiles(ncomp, 1, dtype)
+        faces = ba.face_plan()
+    finally:
+        bt.set_tile_config(*saved)
+    assert len(tiles)
+    for b, bx in enumerate(boxes):
+        ex, ey, ez = bx[3] - bx[0] + 1, bx[4] - bx[1] + 1, bx[5] - bx[2] + 1
+        cover = np.zeros((ncomp, ez, ey * ex), dtype=np.int32)
+        cuts = set()
+        for r in faces[(faces[:, 0] == b) & (faces[:, 1] < 4)]:
+            cuts.add(int(r[5] - bx[2]))
+            cuts.add(int(r[8] - bx[2] + 1))
+        for t in tiles[tiles[:, 0] == b]:
+            comp, q0, nq, nzs, z0, z1, zc, vec, lanes = t[1:]
+            assert vec in (1, 2, 4) and ex % vec == 0 and nzs * nq <= lanes == 64 * shape[1]
+            assert z1 - z0 <= nzs * zc and nzs == -(-(z1 - z0) // zc)
+            assert not any(z0 < c < z1 for c in cuts)
+            cover[comp, z0:z1, q0 * vec:(q0 + nq) * vec] += 1
+        assert cover.min() == 1 and cover.max() == 1
+
+
 def test_tiles_do_not_straddle_face_record_z_boundaries():
     dom = I.domain_box(128)
     boxes = I.random_chop(dom, 16, 64, 8, seed=2)
