@@ -777,7 +777,8 @@ __device__ double block_reduce(double v, int op);
 // concurrent reader sees either value of a cell this pass does not change.
 //
 // RES: also accumulates r^2, r = f + (s - 6 phi)/h2 in FP64 from promoted
-// values, over the valid cells of colour rescolor (2: all) into
+// values (the division taken as a product with 1/h2: the norm is held to
+// 1e-13, not to the bit), over the valid cells of colour rescolor (2: all) into
 // partials[workgroup].  Race-free pairs only: the black pass (color 1,
 // rescolor 1) takes black cells after their update, whose red neighbours this
 // pass does not change; the red pass (color 0, rescolor 0) takes red cells
@@ -789,7 +790,7 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
     __attribute__((amdgpu_waves_per_eu(RES ? (ZB == 8 ? 2 : 4) : (ZB == 8 ? 3 : 6))))
     k_gsrb_dma(const DevLinTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
                const DevFaceRec* __restrict__ recs, T* phi_, const T* __restrict__ f_, T h2, T inv6, int color,
-               int rescolor, double h2d, double* __restrict__ partials, int persist, int yhmax) {
+               int rescolor, double inv_h2d, double* __restrict__ partials, int persist, int yhmax) {
   using VT = Vec<T, V>;
   extern __shared__ unsigned char smem_raw[];
   const TileLds<T, V> S = tile_lds<T, V, ZB>(smem_raw, yhmax);
@@ -844,7 +845,7 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
                             ((double)P[k].v[e] + (double)P[k + 2].v[e]);
           // the cell's own value: after its update in the black pass, before it otherwise
           const double cv = color == 1 ? (double)o.v[e] : (double)P[k + 1].v[e];
-          const double r = (double)F[k].v[e] + (sv - 6.0 * cv) / h2d;
+          const double r = (double)F[k].v[e] + (sv - 6.0 * cv) * inv_h2d;
           acc += r * r;
         }
       }
@@ -1378,12 +1379,12 @@ static hipError_t gsrb_dma_zb(const Plan& p, void* phi, const void* f, double h2
   const T h2t = (T)h2, inv6 = (T)(1.0 / 6.0);
   if (partials)
     hipLaunchKernelGGL((k_gsrb_dma<T, V, ZB, true>), dim3(g), dim3(block), lds, s, p.dlin, (int)p.hlin.size(),
-                       p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor, h2, partials, persist,
-                       p.yhmax);
+                       p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor, 1.0 / h2, partials,
+                       persist, p.yhmax);
   else
     hipLaunchKernelGGL((k_gsrb_dma<T, V, ZB, false>), dim3(g), dim3(block), lds, s, p.dlin, (int)p.hlin.size(),
-                       p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor, h2, partials, persist,
-                       p.yhmax);
+                       p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor, 1.0 / h2, partials,
+                       persist, p.yhmax);
   return hipGetLastError();
 }
 
