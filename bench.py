@@ -9,7 +9,7 @@ timed seconds), in GCell-updates/s.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f64|f32]
 
-Prints one JSON line.  With --gpus above 1 it exits: this build runs on one GPU.
+Prints one JSON line.  With --gpus above 1 it exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -29,7 +29,7 @@ METRIC = "GCell-updates/s + % HBM roofline (heat_step+FillBoundary); p50/p99 ser
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 2 << 30
 CPU_SAMPLE_SECONDS = 10.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat_fused_cfg2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat_fused_512cube_uneven_5comp_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1604_03570_amd", "csrc", "bl_kernels.hip")
 
 
@@ -162,7 +162,7 @@ def summarize_profiles(d: str) -> int:
     esize = 8 if dtype == "f64" else 4
     alg = 2 * esize * cells
     cmd = f"rocprofv3 {{--kernel-trace --stats | --pmc FETCH_SIZE | --pmc WRITE_SIZE}} --output-format csv -- python3 bench.py {PROFILE_ARGS}"
-    out = os.path.join(ROOT, "profiles", f"heat_fused_cfg2_{dtype}.md")
+    out = os.path.join(ROOT, "profiles", f"heat_fused_512cube_uneven_5comp_{dtype}.md")
     with open(out, "w") as fh:
         fh.write(f"# Fused heat step + FillBoundary, 512^3 random chop, 5 comps, {dtype}\n\n")
         fh.write("Commands (three runs, from the repository root, after `cd /tmp && export TMPDIR=/tmp` for the profiler's files):\n\n")
@@ -276,7 +276,7 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         return 2
 

@@ -226,7 +226,7 @@ bl_status bl_distmap_create(const bl_boxarray* ba, int32_t ndevices, const int32
   clear_error();
   if (!ba || !out) return fail(BL_EINVAL, "NULL argument");
   *out = nullptr;
-  if (ndevices != 1) return fail(BL_EINVAL, "this build runs on one GPU: ndevices must be 1, got %d", ndevices);
+  if (ndevices != 1) return fail(BL_EINVAL, "the library runs on one GPU: ndevices must be 1, got %d", ndevices);
   if (owner)
     for (size_t i = 0; i < ba->boxes.size(); ++i)
       if (owner[i] != 0) return fail(BL_EINVAL, "box %zu owned by device %d; only device 0 exists", i, owner[i]);

@@ -35,7 +35,7 @@ def _cell(mf, boxes, comp, cell):
     raise AssertionError(f"no box holds {cell}")
 
 
-def test_cfg1_per_box_launches_follow_the_sine_closed_form(bt):
+def test_256cube_per_box_launches_follow_the_sine_closed_form(bt):
     """256^3 periodic, 64 boxes of 64^3, FP64, 3 seeded sine modes, 100 steps of the
     plain per-box form (FillBoundary, then one launch per box)."""
     n, steps = 256, 100
@@ -55,7 +55,7 @@ def test_cfg1_per_box_launches_follow_the_sine_closed_form(bt):
         g = 1.0 - 4.0 * c * sum(math.sin(math.pi * kd / n) ** 2 for kd in md.k)
         exact += md.amp * g ** steps * I.sine_product(n, md.k)
     err = np.abs(got - exact).max() / np.abs(exact).max()
-    say(f"cfg1: closed-form rel err {err:.3e}")
+    say(f"256^3 per box: closed-form rel err {err:.3e}")
     assert err <= 1e-12
     rng = np.random.default_rng(2)
     for _ in range(2):
@@ -64,7 +64,7 @@ def test_cfg1_per_box_launches_follow_the_sine_closed_form(bt):
 
 
 @pytest.mark.parametrize("dtype_name", ["f64", "f32"])
-def test_cfg2_fused_batched_step_at_full_size(bt, dtype_name):
+def test_512cube_uneven_fused_step_at_full_size(bt, dtype_name):
     """512^3 periodic, seeded chop into ~1270 uneven boxes, 5 comps, 50 fused steps in
     one graph (the benchmark's form): sampled cells equal the oracle's (FP64 bit for bit,
     FP32 storage within 2e-5 of the FP64 oracle) and every component's sum is conserved."""
@@ -97,11 +97,11 @@ def test_cfg2_fused_batched_step_at_full_size(bt, dtype_name):
                 assert got == ref, (comp, cell, got, ref)
             else:
                 worst = max(worst, abs(got - ref) / abs(ref))
-    say(f"cfg2 {dtype_name}: sampled cells ok, worst rel err {worst:.2e}")
+    say(f"512^3 uneven {dtype_name}: sampled cells ok, worst rel err {worst:.2e}")
     assert worst <= 2e-5
 
 
-def test_cfg3_gsrb_at_full_size(bt):
+def test_384cube_gsrb_at_full_size(bt):
     """384^3 periodic, 216 boxes of 64^3, zero-mean f: FP64 state after 2 sweeps equals
     the oracle bit for bit (norms to 1e-13); FP32 state over 20 sweeps stays within 1e-5
     of FP64 in field and norms, and the norms fall every sweep."""
@@ -133,6 +133,6 @@ def test_cfg3_gsrb_at_full_size(bt):
     a32 = phi32.to_global().double().cpu().numpy()
     ferr = np.abs(a32 - a64).max() / np.abs(a64).max()
     nerr = max(abs(x - y) / y for x, y in zip(n32, n64))
-    say(f"cfg3: fp32 field rel err {ferr:.2e}, norm rel err {nerr:.2e}, norms {n64[0]:.4e} -> {n64[-1]:.4e}")
+    say(f"384^3 gsrb: fp32 field rel err {ferr:.2e}, norm rel err {nerr:.2e}, norms {n64[0]:.4e} -> {n64[-1]:.4e}")
     assert ferr <= 1e-5 and nerr <= 1e-5
     assert all(y < x for x, y in zip(n64, n64[1:]))

@@ -28,7 +28,7 @@ def bt():
     return lib()
 
 
-def _cfg0():
+def _gauss64():
     n = 64
     return I.domain_box(n), I.regular_chop(I.domain_box(n), 32), I.gaussian(n), I.heat_c(n)
 
@@ -73,10 +73,10 @@ def test_fill_boundary_partial_components(bt):
 
 # ----------------------------------------------------------------------------- heat step
 @pytest.mark.parametrize("form", ["per_box", "unfused", "fused"])
-def test_heat_cfg0_bit_exact(bt, form):
-    dom, boxes, u0, c = _cfg0()
+def test_heat_64cube_8boxes_bit_exact(bt, form):
+    dom, boxes, u0, c = _gauss64()
     steps = 20
-    say(f"heat cfg0 form={form}")
+    say(f"heat 64^3, 8 boxes, form={form}")
     ba, a, b, o = make_pair(boxes, dom, (1, 1, 1), 1, 1, bt.F64, u0)
     if form == "fused":
         res = bt.heat_advance(a, b, steps, c)
@@ -181,7 +181,7 @@ def test_heat_sine_decay_and_conservation_gpu(bt):
 
 
 def test_heat_advance_graph_replay(bt):
-    dom, boxes, u0, c = _cfg0()
+    dom, boxes, u0, c = _gauss64()
     ba, a, b, o = make_pair(boxes, dom, (1, 1, 1), 1, 1, bt.F64, u0)
     for _ in range(5):  # the captured 2-step graph is replayed five times
         r = bt.heat_advance(a, b, 2, c)

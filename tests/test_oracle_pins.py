@@ -62,7 +62,7 @@ def test_sine_mode_decay_closed_form():
     assert _sine_decay_error(boxes=I.regular_chop(I.domain_box((32, 24, 16)), 8)) <= 1e-12
 
 
-def test_sine_mode_decay_cfg1_modes():
+def test_sine_mode_decay_with_the_256cube_modes():
     # the 256^3 workload's seeded modes (wavenumbers 1..8), on a 64^3 grid
     n, steps = 64, 10
     u0, modes = I.sine_modes(n, seed=1)
