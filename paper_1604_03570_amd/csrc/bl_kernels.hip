@@ -58,6 +58,23 @@ __device__ __forceinline__ void stv(BL_GLOBAL T* p, const Vec<T, V>& x) {
 #else
 #define BL_GLOBAL
 #endif
+#if defined(__HIP_DEVICE_COMPILE__)
+// Store that does not keep the line in the caches (the new state is read back
+// only in the next step, long after).
+template <typename T, int V>
+__device__ __forceinline__ void stv_nt(BL_GLOBAL T* p, const Vec<T, V>& x) {
+  using E = T __attribute__((ext_vector_type(V)));
+  E e;
+#pragma unroll
+  for (int i = 0; i < V; ++i) e[i] = x.v[i];
+  __builtin_nontemporal_store(e, reinterpret_cast<BL_GLOBAL E*>(p));
+}
+#else
+template <typename T, int V>
+__device__ __forceinline__ void stv_nt(T* p, const Vec<T, V>& x) {
+  *reinterpret_cast<Vec<T, V>*>(p) = x;
+}
+#endif
 template <typename T>
 __device__ __forceinline__ const BL_GLOBAL T* as_global(const T* p) {
   return (const BL_GLOBAL T*)p;
@@ -759,7 +776,7 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
       }
       const int z = L.zb0 + k;
       if (z < L.zb1 && L.active) {
-        stv<T, V>(wp + (int64_t)z * B.sz, o);
+        stv_nt<T, V>(wp + (int64_t)z * B.sz, o);
         if (FUSED) stage_edges<T, V, ZB>(S, L, tl, nvx, k, o);
       }
     }
@@ -851,7 +868,7 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
       }
       if (color < 0) continue;
       if (valid) {
-        stv<T, V>(wp + (int64_t)z * B.sz, o);
+        stv_nt<T, V>(wp + (int64_t)z * B.sz, o);
         stage_edges<T, V, ZB>(S, L, tl, nvx, k, o);
       }
     }
