@@ -146,16 +146,27 @@ class Server:
         self.shapes = _Shapes()
 
     def prepare(self, requests) -> None:
-        """Build the device tables of every problem shape in the stream ahead of time
-        (a long-running server has them resident), so no request pays for them."""
+        """Make every problem shape of the stream resident ahead of time, as in a
+        long-running server: its device tables, its kernels loaded and the allocator
+        holding blocks of its size, by one batched step of one problem per shape."""
         seen = set()
+        batch = bt.Batch()
+        keep = []
         for r in requests:
             key = (r.n, r.box_edge, r.dtype)
             if key in seen:
                 continue
             seen.add(key)
             ba = self.shapes.boxarray(r.n, r.box_edge)
-            bt.MultiFab(ba, 1, 1, _DT[r.dtype])  # builds and keeps the shape's plan
+            a, b = bt.MultiFab(ba, 1, 1, _DT[r.dtype]), bt.MultiFab(ba, 1, 1, _DT[r.dtype])
+            a.set_val(1.0)
+            keep.append((a, b, batch.add(a, b, I.heat_c(r.n))))
+        if keep:
+            batch.step()
+            torch.cuda.synchronize()
+            for _, _, mid in keep:
+                batch.remove(mid)
+        del keep, batch
         torch.cuda.synchronize()
 
     def run(self, requests, stream=None, prepare: bool = True) -> ServeStats:
