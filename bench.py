@@ -393,6 +393,20 @@ def main() -> int:
         extra["unfused_fill_ms"] = round(fill_ms, 4)
         extra["unfused_fill_fraction"] = round(fill_ms / unfused_ms, 4)
         extra["unfused_gcell_s"] = round(cells / (unfused_ms / 1e3) / 1e9, 2)
+        # reductions over one component (valid cells; FP64 accumulation)
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+        a.reduce_async(0, "sum", out)
+        torch.cuda.synchronize()
+        ev[2].record(stream)
+        for _ in range(reps):
+            a.reduce_async(0, "sum", out)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        red_ms = ev[2].elapsed_time(ev[3]) / reps
+        comp_bytes = cells // ncomp * esize
+        extra["reduce_sum_ms"] = round(red_ms, 4)
+        extra["reduce_sum_gbs"] = round(comp_bytes / (red_ms / 1e3) / 1e9, 1)
+        log(f"reduce sum (one component): {red_ms:.3f} ms, {comp_bytes / (red_ms / 1e3) / 1e9:.0f} GB/s")
         log(f"unfused: {unfused_ms:.3f} ms/step, fill {fill_ms:.3f} ms ({fill_ms / unfused_ms:.1%})")
         del a, b, ba
         torch.cuda.empty_cache()

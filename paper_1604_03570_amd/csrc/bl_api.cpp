@@ -26,6 +26,7 @@ Plan::~Plan() {
   (void)hipFree(dfacerecs);
   (void)hipFree(dtiles);
   (void)hipFree(dlin);
+  (void)hipFree(dred);
   (void)hipFree(dfillrecs);
   (void)hipFree(dfillchunks);
 }
@@ -47,6 +48,7 @@ bl_status upload_plan(Plan& p) {
   if ((st = upload(&p.dfacerecs, p.hfacerecs, "hipMalloc/hipMemcpy(face records)")) != BL_OK) return st;
   if ((st = upload(&p.dtiles, p.htiles, "hipMalloc/hipMemcpy(tiles)")) != BL_OK) return st;
   if ((st = upload(&p.dlin, p.hlin, "hipMalloc/hipMemcpy(stencil tiles)")) != BL_OK) return st;
+  if ((st = upload(&p.dred, p.hred, "hipMalloc/hipMemcpy(reduction chunks)")) != BL_OK) return st;
   if ((st = upload(&p.dfillrecs, p.hfillrecs, "hipMalloc/hipMemcpy(fill records)")) != BL_OK) return st;
   if ((st = upload(&p.dfillchunks, p.hfillchunks, "hipMalloc/hipMemcpy(fill chunks)")) != BL_OK) return st;
   p.uploaded = true;
@@ -103,6 +105,9 @@ static bl_status get_plan(const bl_boxarray* ba, int ncomp, int ng, int dtype, b
 }
 
 static int block_of(const Plan& p) { return 64 * p.cfg.waves; }
+
+// partial results of a reduction (one per reduction chunk)
+static size_t reduce_slots(const Plan& p) { return std::max(p.hred.size(), p.htiles.size()); }
 
 static int persistent_grid(int persist) { return persist > 0 ? device_cu_count() * persist : 0; }
 
@@ -417,7 +422,7 @@ bl_status bl_reduce_async(const bl_multifab* cmf, int32_t comp, bl_reduce_op op,
   const Plan& p = *mf->plan;
   if (comp < 0 || comp >= p.ncomp) return fail(BL_EINVAL, "component %d out of range", comp);
   if ((int)op < 0 || (int)op > 5) return fail(BL_EINVAL, "unknown reduction %d", (int)op);
-  bl_status st = ensure_scratch(mf, p.htiles.size() + 8, 8);
+  bl_status st = ensure_scratch(mf, reduce_slots(p) + 8, 8);
   if (st != BL_OK) return st;
   BL_HIP(launch_reduce(p, mf->data, comp, (int)op, mf->dscratch, out_dev, block_of(p), stream));
   return BL_OK;
@@ -428,9 +433,9 @@ bl_status bl_reduce(const bl_multifab* cmf, int32_t comp, bl_reduce_op op, doubl
   bl_multifab* mf = const_cast<bl_multifab*>(cmf);
   if (!mf || !out_host) return fail(BL_EINVAL, "NULL argument");
   const Plan& p = *mf->plan;
-  bl_status st = ensure_scratch(mf, p.htiles.size() + 8, 8);
+  bl_status st = ensure_scratch(mf, reduce_slots(p) + 8, 8);
   if (st != BL_OK) return st;
-  double* dout = mf->dscratch + p.htiles.size();
+  double* dout = mf->dscratch + reduce_slots(p);
   if ((st = bl_reduce_async(mf, comp, op, dout, stream)) != BL_OK) return st;
   BL_HIP(hipMemcpyAsync(mf->hres, dout, sizeof(double), hipMemcpyDeviceToHost, stream));
   BL_HIP(hipStreamSynchronize(stream));

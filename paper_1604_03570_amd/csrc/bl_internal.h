@@ -199,6 +199,13 @@ struct DevLinTile {
 };
 static_assert(sizeof(DevLinTile) == 64, "DevLinTile size");
 
+// A reduction chunk: valid planes z0..z1-1 of one box (any one component).  The
+// valid cells of a plane are one contiguous run (rows are contiguous), so a
+// chunk is z1-z0 runs of ex*ey values.
+struct DevRedChunk {
+  int32_t box, z0, z1, pad_;
+};
+
 // One heat problem of a launch: at launch flip f it reads a and writes b when
 // (f + flip_offset) is even, and the reverse when it is odd.
 struct DevMember {
@@ -278,6 +285,7 @@ struct Plan {
   int rmax = 1;                           // most rows of any tile
   int nvtmax = 1;                         // most x vectors of any tile
   std::vector<DevLinTile> hlin;           // the stencil's tiles (forms with the halo in LDS)
+  std::vector<DevRedChunk> hred;          // reduction chunks
   int yhmax = 1;                          // most halo row vectors (nzs * min(nvx, nq)) of a linear tile
   int xhmax = 1;                          // most halo row ends (nzs * nrows) of a linear tile
   std::vector<DevFillRec> hfillrecs;
@@ -289,6 +297,7 @@ struct Plan {
   DevFaceRec* dfacerecs = nullptr;
   DevTile* dtiles = nullptr;
   DevLinTile* dlin = nullptr;
+  DevRedChunk* dred = nullptr;
   DevFillRec* dfillrecs = nullptr;
   DevFillChunk* dfillchunks = nullptr;
   bool uploaded = false;

@@ -1034,6 +1034,39 @@ __device__ double block_reduce(double v, int op) {
   return r;  // valid in thread 0
 }
 
+// Reduction over the valid cells of one component: a workgroup per chunk
+// (planes z0..z1-1 of one box), each plane one contiguous run read with four
+// independent vector loads per lane in flight.
+template <typename T, int V>
+__global__ void __launch_bounds__(256)
+    k_reduce_chunks(const T* __restrict__ data_, const DevRedChunk* __restrict__ chunks,
+                    const DevBox* __restrict__ boxes, int comp, int op, double* __restrict__ partials) {
+  const DevRedChunk ch = ldc(chunks + blockIdx.x);
+  const DevBox B = ldc(boxes + ch.box);
+  const BL_GLOBAL T* data = as_global(data_);
+  const int nv = B.ex * B.ey / V;
+  const int bd = (int)blockDim.x;
+  double acc = r_identity(op);
+  for (int z = ch.z0; z < ch.z1; ++z) {
+    const BL_GLOBAL T* run = data + B.off + (int64_t)comp * B.sc + (int64_t)z * B.sz;
+    for (int i = threadIdx.x; i < nv; i += 4 * bd) {
+      Vec<T, V> v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = i + u * bd < nv ? i + u * bd : i;
+        v[u] = ldv<T, V>(run + (int64_t)j * V);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i + u * bd < nv)
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc = r_combine(acc, r_term((double)v[u].v[e], op), op);
+    }
+  }
+  const double r = block_reduce(acc, op);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
 template <typename T, int V>
 __global__ void __launch_bounds__(1024)
     k_reduce_tiles(const T* __restrict__ data, const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes,
@@ -1321,6 +1354,26 @@ hipError_t launch_copy_fab(const Plan& p, void* data, void* dense, int box, int 
 
 hipError_t launch_reduce(const Plan& p, const void* data, int comp, int op, double* partials, double* out, int block,
                          hipStream_t s) {
+  if (p.dred) {  // chunks of whole planes
+    const unsigned nc = (unsigned)p.hred.size();
+    if (p.dtype == BL_F64) {
+      if (p.vec == 2)
+        hipLaunchKernelGGL((k_reduce_chunks<double, 2>), dim3(nc), dim3(256), 0, s, (const double*)data, p.dred,
+                           p.dboxes, comp, op, partials);
+      else
+        hipLaunchKernelGGL((k_reduce_chunks<double, 1>), dim3(nc), dim3(256), 0, s, (const double*)data, p.dred,
+                           p.dboxes, comp, op, partials);
+    } else {
+      if (p.vec == 4)
+        hipLaunchKernelGGL((k_reduce_chunks<float, 4>), dim3(nc), dim3(256), 0, s, (const float*)data, p.dred,
+                           p.dboxes, comp, op, partials);
+      else
+        hipLaunchKernelGGL((k_reduce_chunks<float, 1>), dim3(nc), dim3(256), 0, s, (const float*)data, p.dred,
+                           p.dboxes, comp, op, partials);
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, s, partials, (int)nc, op, op == R_NORM2 ? 1 : 0, out);
+    return hipGetLastError();
+  }
   const unsigned nt = (unsigned)p.htiles.size();
   if (p.dtype == BL_F64) {
     if (p.vec == 2)

@@ -733,6 +733,13 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
     p->rmax = std::max<int>(p->rmax, t.rows);
     p->nvtmax = std::max<int>(p->nvtmax, t.nvt);
   }
+  // reduction chunks of about 32K values
+  for (int b = 0; b < (int)p->hboxes.size(); ++b) {
+    const DevBox& B = p->hboxes[b];
+    const int64_t P = (int64_t)B.ex * B.ey;
+    const int per = (int)std::max<int64_t>(1, std::min<int64_t>(B.ez, (32768 + P - 1) / P));
+    for (int z = 0; z < B.ez; z += per) p->hred.push_back(DevRedChunk{b, z, std::min(B.ez, z + per), 0});
+  }
   if (cfg.block == 3) {
     build_lin_tiles(*p, cfg, 0, 0, 0, p->hlin, &p->yhmax, &p->xhmax);
     if (lin_lds_bytes(cfg, p->esize, p->vec, p->yhmax, p->xhmax) > kDmaLdsMax) p->hlin.clear();  // form 2 instead
