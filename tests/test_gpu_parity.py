@@ -448,3 +448,29 @@ def test_gsrb_every_form_bit_exact_on_uneven_layouts(bt, cfg, layout):
     for a, b in zip(norms, onorms):
         assert abs(a - b) <= F64_SUM_TOL * b
     assert abs(res - onorms[-1]) <= F64_SUM_TOL * onorms[-1]
+
+
+# ----------------------------------------------------------------------------- degenerate calls
+def test_degenerate_calls(bt):
+    """Zero steps and sweeps are no-ops; empty batches step; bad ids, components and
+    trial counts are rejected with EINVAL."""
+    dom = I.domain_box(32)
+    ba = bt.BoxArray.chop(dom, 16)
+    a, b = bt.MultiFab(ba, 2, 1, bt.F64), bt.MultiFab(ba, 2, 1, bt.F64)
+    g = np.random.default_rng(3).random((2, 32, 32, 32))
+    a.from_global(g)
+    assert bt.heat_advance(a, b, 0, 0.15) is a
+    assert np.array_equal(gpu_global(a), g)
+    phi, f = bt.MultiFab(ba, 1, 1, bt.F64), bt.MultiFab(ba, 1, 1, bt.F64)
+    phi.from_global(g[:1])
+    f.set_val(0.0, with_ghosts=True)
+    assert bt.gsrb_sweeps(phi, f, 1e-3, 0) == []
+    assert np.array_equal(gpu_global(phi), g[:1])
+    batch = bt.Batch()
+    batch.step()  # no members
+    for call in (lambda: batch.remove(12345), lambda: a.reduce(2, "sum"), lambda: a.reduce(-1, "max"),
+                 lambda: bt.autotune(ba, a, b, 0.15, trial_steps=0), lambda: bt.heat_advance(a, b, -1, 0.15)):
+        with pytest.raises(bt.BoxtileError) as e:
+            call()
+        assert e.value.code == bt.BL_EINVAL
+    torch.cuda.synchronize()
