@@ -29,6 +29,8 @@
  *                      the 7-point update.
  *   orc_heat_flux_step the same step in the paper's own form (Sec. 4.1): three
  *                      face-flux loops, then a divergence loop.
+ *   orc_heat_varcoef_step  the flux form with a variable diffusion coefficient:
+ *                      each face's coefficient is the mean of its two cells.
  *   orc_gsrb_color     one colour of a red-black Gauss-Seidel sweep for the
  *                      7-point discrete Poisson problem -L_h phi = f.
  *   orc_residual       r = f + L_h phi per valid cell (FP64).
@@ -255,6 +257,49 @@ int orc_heat_flux_step(int nbox, const int* boxes, int ng, int ncomp, const doub
     free(fz);
   }
   return 0;
+}
+
+/*
+ * Heat step with a variable diffusion coefficient beta, a cell-centred field
+ * with the layout of u whose ghost cells are filled, in the flux form of
+ * Sec. 4.1 extended to du/dt = div(beta grad u): on each face the coefficient
+ * is the mean of the two cells it separates,
+ *   b(i-1/2) = 0.5 * (beta[i-1] + beta[i]),
+ *   F^x(i-1/2) = b(i-1/2) * ((u[i] - u[i-1]) / dx)        (likewise y, z),
+ * then, per cell,
+ *   u_new = u + dt * ((dFx + dFy) + dFz),   dFx = (F^x(i+1/2) - F^x(i-1/2)) / dx.
+ * With beta = 1 every b is exactly 1 and the result is orc_heat_flux_step's.
+ * Written per cell: each face flux is the same expression from either side.
+ */
+static double vflux(const double* u, const double* bt, int64_t lo, int64_t hi, double dx) {
+  const double b = 0.5 * (bt[lo] + bt[hi]);
+  return b * ((u[hi] - u[lo]) / dx);
+}
+
+void orc_heat_varcoef_step(int nbox, const int* boxes, int ng, int ncomp, const double* uold,
+                           const double* beta, double* unew, const int64_t* fab_off, double dt, double dx) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int b = 0; b < nbox; ++b) {
+    const int* bx = boxes + 6 * b;
+    fab_geom g = geom_of(bx, ng);
+    const double* u = uold + fab_off[b];
+    const double* bt = beta + fab_off[b];
+    double* v = unew + fab_off[b];
+    for (int comp = 0; comp < ncomp; ++comp)
+      for (int k = bx[2]; k <= bx[5]; ++k)
+        for (int j = bx[1]; j <= bx[4]; ++j)
+          for (int i = bx[0]; i <= bx[3]; ++i) {
+            const int64_t c = fab_index(&g, comp, i, j, k);
+            const double fxm = vflux(u, bt, fab_index(&g, comp, i - 1, j, k), c, dx);
+            const double fxp = vflux(u, bt, c, fab_index(&g, comp, i + 1, j, k), dx);
+            const double fym = vflux(u, bt, fab_index(&g, comp, i, j - 1, k), c, dx);
+            const double fyp = vflux(u, bt, c, fab_index(&g, comp, i, j + 1, k), dx);
+            const double fzm = vflux(u, bt, fab_index(&g, comp, i, j, k - 1), c, dx);
+            const double fzp = vflux(u, bt, c, fab_index(&g, comp, i, j, k + 1), dx);
+            const double dfx = (fxp - fxm) / dx, dfy = (fyp - fym) / dx, dfz = (fzp - fzm) / dx;
+            v[c] = u[c] + dt * ((dfx + dfy) + dfz);
+          }
+  }
 }
 
 /*

@@ -68,6 +68,9 @@ def _configure(L):
     L.orc_heat_flux_step.argtypes = [ctypes.c_int, _ip, ctypes.c_int, ctypes.c_int, _dp, _dp,
                                      _i64p, ctypes.c_double, ctypes.c_double]
     L.orc_heat_flux_step.restype = ctypes.c_int
+    L.orc_heat_varcoef_step.argtypes = [ctypes.c_int, _ip, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _i64p,
+                                        ctypes.c_double, ctypes.c_double]
+    L.orc_heat_varcoef_step.restype = None
     L.orc_gsrb_color.argtypes = [ctypes.c_int, _ip, ctypes.c_int, _dp, _dp, _i64p,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_int]
     L.orc_gsrb_color.restype = None
@@ -230,6 +233,28 @@ def heat_flux_step(u_old: OracleMultiFab, u_new: OracleMultiFab, dt: float, dx: 
                                   _ptr(u_old.fab_off, _i64p), dt, dx)
     if rc != 0:
         raise MemoryError("flux scratch")
+
+
+def heat_varcoef_step(u_old: OracleMultiFab, u_new: OracleMultiFab, beta: OracleMultiFab, dt: float,
+                      dx: float) -> None:
+    """du/dt = div(beta grad u) in the flux form, face coefficients the mean of the two
+    cells (Sec. 4.1's flux form with a variable coefficient); fills u_old's and beta's
+    ghosts first."""
+    _same_layout(u_old, u_new)
+    _same_layout(u_old, beta)
+    u_old.fill_boundary()
+    beta.fill_boundary()
+    lib().orc_heat_varcoef_step(u_old.nbox, _ptr(u_old.boxes, _ip), u_old.ng, u_old.ncomp, _ptr(u_old.data, _dp),
+                                _ptr(beta.data, _dp), _ptr(u_new.data, _dp), _ptr(u_old.fab_off, _i64p), dt, dx)
+
+
+def heat_varcoef_advance(u: OracleMultiFab, beta: OracleMultiFab, nsteps: int, dt: float,
+                         dx: float) -> OracleMultiFab:
+    a, b = u, u.copy()
+    for _ in range(nsteps):
+        heat_varcoef_step(a, b, beta, dt, dx)
+        a, b = b, a
+    return a
 
 
 def heat_advance(u: OracleMultiFab, nsteps: int, c: float) -> OracleMultiFab:

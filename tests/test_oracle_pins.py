@@ -11,6 +11,8 @@ the oracle and checks exactly that):
   * FillBoundary equals a brute-force search over boxes on tiny grids;
   * one periodic box equals a numpy.roll 7-point update;
   * the paper's flux form agrees with the 7-point form;
+  * the variable-coefficient flux form equals a numpy.roll implementation, reduces
+    to the flux form at unit coefficient, conserves the sum and is self-adjoint;
   * red-black Gauss-Seidel equals dense Gauss-Seidel in red-then-black order;
   * residual invariants (zero on the colour just relaxed, sum r = sum f);
   * reductions against exactly known sums.
@@ -132,6 +134,88 @@ def test_many_boxes_equal_numpy_roll():
     for _ in range(5):
         ref = _roll_step(ref, 0.15)
     assert np.array_equal(O.heat_advance(m, 5, 0.15).to_global()[0], ref)
+
+
+def _roll_varcoef_step(u, beta, dt, dx):
+    """Textbook periodic variable-coefficient flux form with numpy.roll: face coefficient
+    the mean of the two cells, same operand order as the oracle's C loop."""
+    out = []
+    for axis in (2, 1, 0):  # x, y, z
+        um, up = np.roll(u, 1, axis=axis), np.roll(u, -1, axis=axis)
+        bm, bp = np.roll(beta, 1, axis=axis), np.roll(beta, -1, axis=axis)
+        fm = (0.5 * (bm + beta)) * ((u - um) / dx)
+        fp = (0.5 * (beta + bp)) * ((up - u) / dx)
+        out.append((fp - fm) / dx)
+    dfx, dfy, dfz = out
+    return u + dt * ((dfx + dfy) + dfz)
+
+
+def test_varcoef_single_periodic_box_equals_numpy_roll():
+    shape = (10, 6, 8)
+    rng = np.random.default_rng(5)
+    u = rng.random((1,) + shape[::-1])
+    beta = 0.5 + rng.random((1,) + shape[::-1])
+    dx, dt = 0.1, 0.001
+    m, bm = _mf(I.regular_chop(I.domain_box(shape), 64), shape), _mf(I.regular_chop(I.domain_box(shape), 64), shape)
+    m.load_global(u)
+    bm.load_global(beta)
+    ref = u[0]
+    for _ in range(4):
+        ref = _roll_varcoef_step(ref, beta[0], dt, dx)
+    assert np.array_equal(O.heat_varcoef_advance(m, bm, 4, dt, dx).to_global()[0], ref)
+
+
+def test_varcoef_many_boxes_equal_one_box_and_conserve_the_sum():
+    shape = (12, 10, 8)
+    rng = np.random.default_rng(6)
+    u = rng.random((2,) + shape[::-1])
+    beta = 0.5 + rng.random((2,) + shape[::-1])
+    dx, dt = 0.1, 0.0005
+    out = []
+    for boxes in (I.regular_chop(I.domain_box(shape), 64), _uneven_boxes(shape, seed=7)):
+        m, bm = _mf(boxes, shape, ncomp=2), _mf(boxes, shape, ncomp=2)
+        m.load_global(u)
+        bm.load_global(beta)
+        out.append(O.heat_varcoef_advance(m, bm, 6, dt, dx).to_global())
+    assert np.array_equal(out[0], out[1])
+    for comp in range(2):
+        s0, s1 = math.fsum(u[comp].ravel()), math.fsum(out[0][comp].ravel())
+        assert abs(s1 - s0) <= 1e-13 * abs(s0)
+
+
+def test_varcoef_unit_coefficient_is_the_flux_form():
+    shape = (9, 7, 6)
+    u = I.uniform(shape, 1, seed=9)
+    dx, dt = 1.0 / 9, 0.9 * (1.0 / 9) ** 2 / 6
+    boxes = _uneven_boxes(shape, seed=8)
+    a, b, bm = _mf(boxes, shape), _mf(boxes, shape), _mf(boxes, shape)
+    a.load_global(u)
+    bm.load_global(np.ones_like(u))
+    O.heat_varcoef_step(a, b, bm, dt, dx)
+    a2, b2 = _mf(boxes, shape), _mf(boxes, shape)
+    a2.load_global(u)
+    O.heat_flux_step(a2, b2, dt, dx)
+    assert np.array_equal(b.to_global(), b2.to_global())
+
+
+def test_varcoef_operator_is_symmetric():
+    """div(beta grad) is self-adjoint on periodic grids: <v, A u> = <u, A v>."""
+    shape = (8, 8, 6)
+    rng = np.random.default_rng(10)
+    beta = 0.5 + rng.random((1,) + shape[::-1])
+    boxes = _uneven_boxes(shape, seed=11)
+
+    def apply(w):
+        m, out, bm = _mf(boxes, shape), _mf(boxes, shape), _mf(boxes, shape)
+        m.load_global(w)
+        bm.load_global(beta)
+        O.heat_varcoef_step(m, out, bm, 1.0, 1.0)
+        return out.to_global() - w
+
+    u, v = rng.random((1,) + shape[::-1]), rng.random((1,) + shape[::-1])
+    lhs, rhs = float((v * apply(u)).sum()), float((u * apply(v)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs))
+    assert float((u * apply(u)).sum()) < 0  # and negative definite on non-constant fields
 
 
 def test_flux_form_agrees_with_seven_point():
@@ -409,6 +493,8 @@ MUTATIONS = {
     "gsrb_black_first": ("if (floor_mod(i + j + k, 2) != color) continue;",
                          "if (floor_mod(i + j + k + 1, 2) != color) continue;"),
     "gsrb_drops_rhs": ("p[q] = (((sx + sy) + sz) + h2 * fb[q]) * inv6;", "p[q] = (((sx + sy) + sz)) * inv6;"),
+    "varcoef_cell_coefficient": ("const double b = 0.5 * (bt[lo] + bt[hi]);", "const double b = bt[hi];"),
+    "varcoef_flux_sign": ("return b * ((u[hi] - u[lo]) / dx);", "return b * ((u[lo] - u[hi]) / dx);"),
 }
 
 
@@ -421,6 +507,7 @@ def _pins_pass():
         test_fill_boundary_brute_force(1)
         test_gsrb_equals_dense_gauss_seidel_red_then_black((4, 4, 4))
         test_gsrb_exact_discrete_solution_is_fixed_point()
+        test_varcoef_single_periodic_box_equals_numpy_roll()
     except (AssertionError, ValueError, IndexError):
         return False
     return all(checks)
