@@ -197,14 +197,15 @@ void orc_heat_step(int nbox, const int* boxes, int ng, int ncomp, const double* 
 /*
  * The same heat step in the paper's own structure (Sec. 4.1): the flux of each
  * direction is computed on the faces of the box in its own loop,
- *   F^x(i-1/2) = (u[i] - u[i-1]) / dx   (likewise for y and z),
+ *   F^x(i-1/2) = (u[i] - u[i-1]) * inv_dx   (likewise for y and z),
  * and a fourth loop forms the divergence and updates
- *   u_new = u + dt * ( (F^x(i+1/2) - F^x(i-1/2)) / dx + (y) + (z) ).
- * Algebraically identical to orc_heat_step with c = dt/dx^2; rounding differs.
+ *   u_new = u + dt * ( (F^x(i+1/2) - F^x(i-1/2)) * inv_dx + (y) + (z) ).
+ * inv_dx = 1/dx is formed once by the caller, as c = dt/dx^2 is for the
+ * 7-point form.  Algebraically identical to orc_heat_step; rounding differs.
  * Returns -1 if the flux scratch cannot be allocated.
  */
 int orc_heat_flux_step(int nbox, const int* boxes, int ng, int ncomp, const double* uold,
-                       double* unew, const int64_t* fab_off, double dt, double dx) {
+                       double* unew, const int64_t* fab_off, double dt, double inv_dx) {
   for (int b = 0; b < nbox; ++b) {
     const int* bx = boxes + 6 * b;
     fab_geom g = geom_of(bx, ng);
@@ -225,29 +226,29 @@ int orc_heat_flux_step(int nbox, const int* boxes, int ng, int ncomp, const doub
           for (int i = 0; i <= ex; ++i) {
             int gi = bx[0] + i, gj = bx[1] + j, gk = bx[2] + k;
             fx[((size_t)k * ey + j) * (ex + 1) + i] =
-                (u[fab_index(&g, comp, gi, gj, gk)] - u[fab_index(&g, comp, gi - 1, gj, gk)]) / dx;
+                (u[fab_index(&g, comp, gi, gj, gk)] - u[fab_index(&g, comp, gi - 1, gj, gk)]) * inv_dx;
           }
       for (int k = 0; k < ez; ++k)
         for (int j = 0; j <= ey; ++j)
           for (int i = 0; i < ex; ++i) {
             int gi = bx[0] + i, gj = bx[1] + j, gk = bx[2] + k;
             fy[((size_t)k * (ey + 1) + j) * ex + i] =
-                (u[fab_index(&g, comp, gi, gj, gk)] - u[fab_index(&g, comp, gi, gj - 1, gk)]) / dx;
+                (u[fab_index(&g, comp, gi, gj, gk)] - u[fab_index(&g, comp, gi, gj - 1, gk)]) * inv_dx;
           }
       for (int k = 0; k <= ez; ++k)
         for (int j = 0; j < ey; ++j)
           for (int i = 0; i < ex; ++i) {
             int gi = bx[0] + i, gj = bx[1] + j, gk = bx[2] + k;
             fz[((size_t)k * ey + j) * ex + i] =
-                (u[fab_index(&g, comp, gi, gj, gk)] - u[fab_index(&g, comp, gi, gj, gk - 1)]) / dx;
+                (u[fab_index(&g, comp, gi, gj, gk)] - u[fab_index(&g, comp, gi, gj, gk - 1)]) * inv_dx;
           }
       for (int k = 0; k < ez; ++k)
         for (int j = 0; j < ey; ++j)
           for (int i = 0; i < ex; ++i) {
             int gi = bx[0] + i, gj = bx[1] + j, gk = bx[2] + k;
-            double dfx = (fx[((size_t)k * ey + j) * (ex + 1) + i + 1] - fx[((size_t)k * ey + j) * (ex + 1) + i]) / dx;
-            double dfy = (fy[((size_t)k * (ey + 1) + j + 1) * ex + i] - fy[((size_t)k * (ey + 1) + j) * ex + i]) / dx;
-            double dfz = (fz[((size_t)(k + 1) * ey + j) * ex + i] - fz[((size_t)k * ey + j) * ex + i]) / dx;
+            double dfx = (fx[((size_t)k * ey + j) * (ex + 1) + i + 1] - fx[((size_t)k * ey + j) * (ex + 1) + i]) * inv_dx;
+            double dfy = (fy[((size_t)k * (ey + 1) + j + 1) * ex + i] - fy[((size_t)k * (ey + 1) + j) * ex + i]) * inv_dx;
+            double dfz = (fz[((size_t)(k + 1) * ey + j) * ex + i] - fz[((size_t)k * ey + j) * ex + i]) * inv_dx;
             int64_t q = fab_index(&g, comp, gi, gj, gk);
             v[q] = u[q] + dt * ((dfx + dfy) + dfz);
           }
@@ -265,19 +266,20 @@ int orc_heat_flux_step(int nbox, const int* boxes, int ng, int ncomp, const doub
  * Sec. 4.1 extended to du/dt = div(beta grad u): on each face the coefficient
  * is the mean of the two cells it separates,
  *   b(i-1/2) = 0.5 * (beta[i-1] + beta[i]),
- *   F^x(i-1/2) = b(i-1/2) * ((u[i] - u[i-1]) / dx)        (likewise y, z),
+ *   F^x(i-1/2) = b(i-1/2) * ((u[i] - u[i-1]) * inv_dx)     (likewise y, z),
  * then, per cell,
- *   u_new = u + dt * ((dFx + dFy) + dFz),   dFx = (F^x(i+1/2) - F^x(i-1/2)) / dx.
+ *   u_new = u + dt * ((dFx + dFy) + dFz),   dFx = (F^x(i+1/2) - F^x(i-1/2)) * inv_dx,
+ * with inv_dx = 1/dx formed once by the caller.
  * With beta = 1 every b is exactly 1 and the result is orc_heat_flux_step's.
  * Written per cell: each face flux is the same expression from either side.
  */
-static double vflux(const double* u, const double* bt, int64_t lo, int64_t hi, double dx) {
+static double vflux(const double* u, const double* bt, int64_t lo, int64_t hi, double inv_dx) {
   const double b = 0.5 * (bt[lo] + bt[hi]);
-  return b * ((u[hi] - u[lo]) / dx);
+  return b * ((u[hi] - u[lo]) * inv_dx);
 }
 
 void orc_heat_varcoef_step(int nbox, const int* boxes, int ng, int ncomp, const double* uold,
-                           const double* beta, double* unew, const int64_t* fab_off, double dt, double dx) {
+                           const double* beta, double* unew, const int64_t* fab_off, double dt, double inv_dx) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int b = 0; b < nbox; ++b) {
     const int* bx = boxes + 6 * b;
@@ -290,13 +292,13 @@ void orc_heat_varcoef_step(int nbox, const int* boxes, int ng, int ncomp, const 
         for (int j = bx[1]; j <= bx[4]; ++j)
           for (int i = bx[0]; i <= bx[3]; ++i) {
             const int64_t c = fab_index(&g, comp, i, j, k);
-            const double fxm = vflux(u, bt, fab_index(&g, comp, i - 1, j, k), c, dx);
-            const double fxp = vflux(u, bt, c, fab_index(&g, comp, i + 1, j, k), dx);
-            const double fym = vflux(u, bt, fab_index(&g, comp, i, j - 1, k), c, dx);
-            const double fyp = vflux(u, bt, c, fab_index(&g, comp, i, j + 1, k), dx);
-            const double fzm = vflux(u, bt, fab_index(&g, comp, i, j, k - 1), c, dx);
-            const double fzp = vflux(u, bt, c, fab_index(&g, comp, i, j, k + 1), dx);
-            const double dfx = (fxp - fxm) / dx, dfy = (fyp - fym) / dx, dfz = (fzp - fzm) / dx;
+            const double fxm = vflux(u, bt, fab_index(&g, comp, i - 1, j, k), c, inv_dx);
+            const double fxp = vflux(u, bt, c, fab_index(&g, comp, i + 1, j, k), inv_dx);
+            const double fym = vflux(u, bt, fab_index(&g, comp, i, j - 1, k), c, inv_dx);
+            const double fyp = vflux(u, bt, c, fab_index(&g, comp, i, j + 1, k), inv_dx);
+            const double fzm = vflux(u, bt, fab_index(&g, comp, i, j, k - 1), c, inv_dx);
+            const double fzp = vflux(u, bt, c, fab_index(&g, comp, i, j, k + 1), inv_dx);
+            const double dfx = (fxp - fxm) * inv_dx, dfy = (fyp - fym) * inv_dx, dfz = (fzp - fzm) * inv_dx;
             v[c] = u[c] + dt * ((dfx + dfy) + dfz);
           }
   }

@@ -225,12 +225,13 @@ def heat_step(u_old: OracleMultiFab, u_new: OracleMultiFab, c: float, fill_first
 
 
 def heat_flux_step(u_old: OracleMultiFab, u_new: OracleMultiFab, dt: float, dx: float) -> None:
-    """The paper's structure of the same step: face-flux loops, then a divergence loop (Sec. 4.1)."""
+    """The paper's structure of the same step: face-flux loops, then a divergence loop (Sec. 4.1);
+    differences are multiplied by 1/dx, formed once here."""
     _same_layout(u_old, u_new)
     u_old.fill_boundary()
     rc = lib().orc_heat_flux_step(u_old.nbox, _ptr(u_old.boxes, _ip), u_old.ng, u_old.ncomp,
                                   _ptr(u_old.data, _dp), _ptr(u_new.data, _dp),
-                                  _ptr(u_old.fab_off, _i64p), dt, dx)
+                                  _ptr(u_old.fab_off, _i64p), dt, 1.0 / dx)
     if rc != 0:
         raise MemoryError("flux scratch")
 
@@ -238,14 +239,15 @@ def heat_flux_step(u_old: OracleMultiFab, u_new: OracleMultiFab, dt: float, dx: 
 def heat_varcoef_step(u_old: OracleMultiFab, u_new: OracleMultiFab, beta: OracleMultiFab, dt: float,
                       dx: float) -> None:
     """du/dt = div(beta grad u) in the flux form, face coefficients the mean of the two
-    cells (Sec. 4.1's flux form with a variable coefficient); fills u_old's and beta's
-    ghosts first."""
+    cells (Sec. 4.1's flux form with a variable coefficient), differences multiplied by
+    1/dx formed once here; fills u_old's and beta's ghosts first."""
     _same_layout(u_old, u_new)
     _same_layout(u_old, beta)
     u_old.fill_boundary()
     beta.fill_boundary()
     lib().orc_heat_varcoef_step(u_old.nbox, _ptr(u_old.boxes, _ip), u_old.ng, u_old.ncomp, _ptr(u_old.data, _dp),
-                                _ptr(beta.data, _dp), _ptr(u_new.data, _dp), _ptr(u_old.fab_off, _i64p), dt, dx)
+                                _ptr(beta.data, _dp), _ptr(u_new.data, _dp), _ptr(u_old.fab_off, _i64p), dt,
+                                1.0 / dx)
 
 
 def heat_varcoef_advance(u: OracleMultiFab, beta: OracleMultiFab, nsteps: int, dt: float,

@@ -140,12 +140,13 @@ def _roll_varcoef_step(u, beta, dt, dx):
     """Textbook periodic variable-coefficient flux form with numpy.roll: face coefficient
     the mean of the two cells, same operand order as the oracle's C loop."""
     out = []
+    inv_dx = 1.0 / dx
     for axis in (2, 1, 0):  # x, y, z
         um, up = np.roll(u, 1, axis=axis), np.roll(u, -1, axis=axis)
         bm, bp = np.roll(beta, 1, axis=axis), np.roll(beta, -1, axis=axis)
-        fm = (0.5 * (bm + beta)) * ((u - um) / dx)
-        fp = (0.5 * (beta + bp)) * ((up - u) / dx)
-        out.append((fp - fm) / dx)
+        fm = (0.5 * (bm + beta)) * ((u - um) * inv_dx)
+        fp = (0.5 * (beta + bp)) * ((up - u) * inv_dx)
+        out.append((fp - fm) * inv_dx)
     dfx, dfy, dfz = out
     return u + dt * ((dfx + dfy) + dfz)
 
@@ -494,7 +495,7 @@ MUTATIONS = {
                          "if (floor_mod(i + j + k + 1, 2) != color) continue;"),
     "gsrb_drops_rhs": ("p[q] = (((sx + sy) + sz) + h2 * fb[q]) * inv6;", "p[q] = (((sx + sy) + sz)) * inv6;"),
     "varcoef_cell_coefficient": ("const double b = 0.5 * (bt[lo] + bt[hi]);", "const double b = bt[hi];"),
-    "varcoef_flux_sign": ("return b * ((u[hi] - u[lo]) / dx);", "return b * ((u[lo] - u[hi]) / dx);"),
+    "varcoef_flux_sign": ("return b * ((u[hi] - u[lo]) * inv_dx);", "return b * ((u[lo] - u[hi]) * inv_dx);"),
 }
 
 
