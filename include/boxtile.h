@@ -246,6 +246,27 @@ bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t
 bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream_t stream);
 
 /*
+ * nsteps forward-Euler steps of du/dt = div(beta grad u) in the flux form
+ * (Sec. 4.1's face-flux loops, here with a coefficient per cell), ping-ponging
+ * u[0] -> u[1] -> u[0] ...; the result is in u[nsteps % 2].  Per valid cell
+ * and component n, with b the mean of the two cells' beta on each face:
+ *   F(i-1/2) = (0.5*(beta[i-1] + beta[i])) * ((u[i] - u[i-1]) * inv_dx)   (and y, z),
+ *   u_new = u + dt*((dFx + dFy) + dFz),   dFx = (F(i+1/2) - F(i-1/2)) * inv_dx.
+ * inv_dx is 1/dx, formed by the caller.  beta (component n: the coefficient of
+ * u's component n) shares BoxArray, ncomp, nghost and dtype with u (BL_ESHAPE,
+ * BL_EDTYPE) and its own storage (BL_EINVAL); its valid cells are only read.
+ * Neighbour values are those FillBoundary would put in the ghost cells of u
+ * and of beta.  Each step is ONE launch over the flattened tile list: where
+ * every face source allows aligned vector loads, tiles next to a box face read
+ * the neighbouring boxes directly, and a first kernel writes the edge-column
+ * copies of beta and u[0] (beta's ghost cells are not written); otherwise
+ * beta's ghosts are filled once and u's before each step.  The stream is not
+ * synchronised; stability (dt <= dx^2 / (6 max beta)) is the caller's.
+ */
+bl_status bl_heat_varcoef_advance(bl_multifab* u[2], bl_multifab* beta, int32_t nsteps, double dt,
+                                  double inv_dx, hipStream_t stream);
+
+/*
  * One step of the unfused batched form: FillBoundary(u_old) as one copy
  * kernel, then one stencil kernel over all tiles reading the filled ghosts.
  * Same result as bl_heat_step; kept to measure the fill fraction.

@@ -259,6 +259,31 @@ def heat_varcoef_advance(u: OracleMultiFab, beta: OracleMultiFab, nsteps: int, d
     return a
 
 
+def heat_varcoef_window(u0_global: np.ndarray, beta_global: np.ndarray, center, nsteps: int, dt: float,
+                        dx: float) -> float:
+    """Value at global cell ``center`` = (i, j, k) after nsteps heat_varcoef_step steps of a
+    fully periodic, fully covered single component (Nz, Ny, Nx) pair u0, beta.  The cube of
+    half-width nsteps around the cell, cut out with periodic wrap, becomes the one box of a
+    non-periodic domain whose ghost layer holds the wrapped neighbours and stays fixed; a
+    fixed ghost first changes a result in step 2 and then moves in one cell per step, so
+    after nsteps steps the cells within distance 1 of the centre are exact."""
+    i, j, k = center
+    n = int(nsteps)
+    Nz, Ny, Nx = u0_global.shape
+    h = n + 1
+    ix = np.arange(i - h, i + h + 1) % Nx
+    iy = np.arange(j - h, j + h + 1) % Ny
+    iz = np.arange(k - h, k + h + 1) % Nz
+    m = 2 * n + 1
+    box = np.array([[0, 0, 0, m - 1, m - 1, m - 1]], dtype=np.int64)
+    u = OracleMultiFab(box, box[0], (0, 0, 0), 1, 1)
+    beta = OracleMultiFab(box, box[0], (0, 0, 0), 1, 1)
+    u.fab(0)[0] = u0_global[np.ix_(iz, iy, ix)]
+    beta.fab(0)[0] = beta_global[np.ix_(iz, iy, ix)]
+    res = heat_varcoef_advance(u, beta, n, dt, dx)
+    return float(res.fab(0)[0, h, h, h])
+
+
 def heat_advance(u: OracleMultiFab, nsteps: int, c: float) -> OracleMultiFab:
     """nsteps heat steps with ping-pong buffers; returns the MultiFab holding the result."""
     a, b = u, u.copy()

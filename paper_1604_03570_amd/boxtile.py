@@ -68,6 +68,7 @@ _SIGS = {
     "bl_fill_boundary": [_vp, _i32, _i32, _vp],
     "bl_heat_step": [_vp, _vp, ctypes.c_double, _i32, _vp],
     "bl_heat_advance": [_vpp, _i32, ctypes.c_double, _vp],
+    "bl_heat_varcoef_advance": [_vpp, _vp, _i32, ctypes.c_double, ctypes.c_double, _vp],
     "bl_heat_step_unfused": [_vp, _vp, ctypes.c_double, _vp],
     "bl_gsrb_sweeps": [_vp, _vp, ctypes.c_double, _i32, _dp, _vp],
     "bl_residual_norm": [_vp, _vp, ctypes.c_double, _dp, _vp],
@@ -433,6 +434,15 @@ def heat_advance(u0: MultiFab, u1: MultiFab, nsteps: int, c: float, stream=None)
     """nsteps fused steps (one launch per step, captured in a HIP graph); returns the result holder."""
     arr = (ctypes.c_void_p * 2)(u0.handle.value, u1.handle.value)
     _check(_L.bl_heat_advance(arr, int(nsteps), float(c), _stream(stream)))
+    return u0 if nsteps % 2 == 0 else u1
+
+
+def heat_varcoef_advance(u0: MultiFab, u1: MultiFab, beta: MultiFab, nsteps: int, dt: float, dx: float,
+                         stream=None) -> MultiFab:
+    """nsteps steps of du/dt = div(beta grad u) in the flux form (face coefficient: the mean
+    of the two cells'), one launch per step; 1/dx is formed here; returns the result holder."""
+    arr = (ctypes.c_void_p * 2)(u0.handle.value, u1.handle.value)
+    _check(_L.bl_heat_varcoef_advance(arr, beta.handle, int(nsteps), float(dt), 1.0 / float(dx), _stream(stream)))
     return u0 if nsteps % 2 == 0 else u1
 
 

@@ -29,6 +29,7 @@ Plan::~Plan() {
   (void)hipFree(dred);
   (void)hipFree(dfillrecs);
   (void)hipFree(dfillchunks);
+  (void)hipFree(dvlin);
 }
 
 template <typename T>
@@ -412,6 +413,87 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
     g_graphs.push_back({key, exec});
   }
   BL_HIP(hipGraphLaunch(exec, stream));
+  return BL_OK;
+}
+
+// Tiles for the variable-coefficient kernel: the plan's own linear tiles when
+// twice their LDS fits, else tiles with fewer planes per z block (4, then 2),
+// built once per plan.
+static std::mutex g_vc_mu;
+
+static bl_status vc_tiles(Plan& p, VcArgs* a) {
+  a->block = 64 * p.cfg.waves;
+  if (p.cfg.block == 3 && !p.hlin.empty() &&
+      2 * vc_lds_half(p.dtype, p.vec, p.cfg.zchunk, p.yhmax, p.xhmax, a->block) <= kDmaLdsMax) {
+    a->lin = p.dlin;
+    a->nlin = (int)p.hlin.size();
+    a->yhmax = p.yhmax;
+    a->xhmax = p.xhmax;
+    a->zchunk = p.cfg.zchunk;
+    return BL_OK;
+  }
+  std::lock_guard<std::mutex> lk(g_vc_mu);
+  if (!p.vzchunk) {
+    for (int zc : {4, 2}) {
+      TileConfig c = p.cfg;
+      c.block = 3;
+      c.zchunk = zc;
+      c.persist = 0;
+      std::vector<DevLinTile> t;
+      int yh = 1, xh = 1;
+      build_lin_tiles(p, c, 0, 0, 0, t, &yh, &xh);
+      if (2 * vc_lds_half(p.dtype, p.vec, zc, yh, xh, a->block) > kDmaLdsMax) continue;
+      bl_status st = upload(&p.dvlin, t, "hipMalloc/hipMemcpy(flux-form tiles)");
+      if (st != BL_OK) return st;
+      p.hvlin.swap(t);
+      p.vyhmax = yh;
+      p.vxhmax = xh;
+      p.vzchunk = zc;
+      break;
+    }
+    if (!p.vzchunk)
+      return fail(BL_EINVAL, "the boxes' planes are too wide for the flux-form kernel's LDS staging at %d waves",
+                  p.cfg.waves);
+  }
+  a->lin = p.dvlin;
+  a->nlin = (int)p.hvlin.size();
+  a->yhmax = p.vyhmax;
+  a->xhmax = p.vxhmax;
+  a->zchunk = p.vzchunk;
+  return BL_OK;
+}
+
+bl_status bl_heat_varcoef_advance(bl_multifab* u[2], bl_multifab* beta, int32_t nsteps, double dt, double inv_dx,
+                                  hipStream_t stream) {
+  clear_error();
+  if (!u) return fail(BL_EINVAL, "NULL MultiFab array");
+  bl_status st = check_heat(u[0], u[1]);
+  if (st != BL_OK) return st;
+  if ((st = same_shape(u[0], beta)) != BL_OK) return st;
+  if (beta->data == u[0]->data || beta->data == u[1]->data) return fail(BL_EINVAL, "beta shares storage with u");
+  if (nsteps < 0) return fail(BL_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return BL_OK;
+  Plan& p = *u[0]->plan;
+  VcArgs a{};
+  if ((st = vc_tiles(p, &a)) != BL_OK) return st;
+  a.boxes = p.dboxes;
+  a.recs = p.dfacerecs;
+  a.fused = p.fvec;
+  a.beta = beta->data;
+  a.dt = dt;
+  a.inv_dx = inv_dx;
+  if (a.fused) {  // neighbour values from the neighbour boxes' faces and edge mirrors
+    BL_HIP(launch_extract_mirror(p, beta->data, stream));
+    BL_HIP(launch_extract_mirror(p, u[0]->data, stream));
+  } else {
+    BL_HIP(launch_fill(p, beta->data, 0, p.ncomp, stream));
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    a.u = u[s & 1]->data;
+    a.w = u[(s + 1) & 1]->data;
+    if (!a.fused) BL_HIP(launch_fill(p, u[s & 1]->data, 0, p.ncomp, stream));
+    BL_HIP(launch_heat_varcoef(p.dtype, p.vec, a, stream));
+  }
   return BL_OK;
 }
 

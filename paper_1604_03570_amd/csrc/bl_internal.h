@@ -303,6 +303,12 @@ struct Plan {
   bool uploaded = false;
   TileConfig cfg;
 
+  // linear tiles of the variable-coefficient flux-form kernel, which stages two
+  // fields: made on first use when the stencil's own would not fit its LDS
+  std::vector<DevLinTile> hvlin;
+  DevLinTile* dvlin = nullptr;
+  int vyhmax = 1, vxhmax = 1, vzchunk = 0;
+
   ~Plan();
 };
 

@@ -785,6 +785,93 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
   }
 }
 
+// ---------------------------------------------------------------- heat step with a variable coefficient, flux form
+// Flux through the face between cells lo and hi: the mean of the two cells'
+// coefficients times the difference quotient, the difference multiplied by 1/dx.
+template <typename T>
+__device__ __forceinline__ T face_flux(T ulo, T uhi, T blo, T bhi, T inv_dx) {
+  const T b = (T)0.5 * (blo + bhi);
+  return b * ((uhi - ulo) * inv_dx);
+}
+
+// du/dt = div(beta grad u), forward Euler in the flux form of Sec. 4.1: per
+// cell the six face fluxes, their differences per direction times 1/dx, then
+// u + dt*((dFx + dFy) + dFz).  The fluxes stay in registers; a face shared by
+// two cells of one lane (neighbours in its vector, consecutive planes) is
+// computed once.  u and beta are staged alike, each with its own LDS region of
+// lds_half bytes: the lane's planes in registers and LDS, the tile's halo
+// straight into LDS.  FUSED: neighbour boxes through the face records (the
+// edge mirrors of u and beta current), the new u's edge columns into its
+// mirror; otherwise the FABs' own filled ghosts.
+template <typename T, int V, bool FUSED, int ZB>
+__global__ void __launch_bounds__(kStencilMaxThreads)
+    __attribute__((amdgpu_waves_per_eu(ZB == 8 ? 2 : (ZB == 4 ? 3 : 5))))
+    k_heat_vc_dma(const DevLinTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+                  const DevFaceRec* __restrict__ recs, const T* u_, T* w_, const T* beta_, T dt, T inv_dx,
+                  int yhmax, int lds_half) {
+  using VT = Vec<T, V>;
+  extern __shared__ unsigned char smem_raw[];
+  const TileLds<T, V> S = tile_lds<T, V, ZB>(smem_raw, yhmax);
+  const TileLds<T, V> Sb = tile_lds<T, V, ZB>(smem_raw + lds_half, yhmax);
+  const BL_GLOBAL T* __restrict__ u = as_global(u_);
+  const BL_GLOBAL T* __restrict__ bt = as_global(beta_);
+  BL_GLOBAL T* __restrict__ w = as_global(w_);
+  int first, last;
+  tile_range(ntiles, 0, first, last);
+  for (int t = first; t < last; ++t) {
+    const DevLinTile tl = ldc(tiles + t);
+    const DevBox B = ldc(boxes + tl.box);
+    const int nvx = B.nvx;
+    const LinLane L = lin_lane<V, ZB>(tl, nvx);
+    const int64_t comp0 = B.off + (int64_t)tl.comp * B.sc;
+    const int64_t cb = comp0 + (int64_t)L.q * V;
+
+    VT P[ZB + 2], Q[ZB + 2];  // u, beta
+    load_planes<T, V, FUSED, ZB>(P, L, tl, B, recs, u, cb);
+    load_planes<T, V, FUSED, ZB>(Q, L, tl, B, recs, bt, cb);
+    stage_halo<T, V, FUSED, ZB>(S, tl, B, recs, u, comp0);
+    stage_halo<T, V, FUSED, ZB>(Sb, tl, B, recs, bt, comp0);
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
+      S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
+      Sb.sh[k * Sb.nthr + threadIdx.x] = Q[k + 1];
+    }
+    __syncthreads();
+    BL_GLOBAL T* wp = w + cb;
+    T fz[V];  // flux through the lower z face of the current plane
+#pragma unroll
+    for (int e = 0; e < V; ++e) fz[e] = face_flux(P[0].v[e], P[1].v[e], Q[0].v[e], Q[1].v[e], inv_dx);
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
+      const Nbr<T, V> N = tile_neighbours<T, V, ZB>(S, L, tl, nvx, k);
+      const Nbr<T, V> NB = tile_neighbours<T, V, ZB>(Sb, L, tl, nvx, k);
+      const VT& c = P[k + 1];
+      const VT& cbeta = Q[k + 1];
+      T fx = face_flux(N.left, c.v[0], NB.left, cbeta.v[0], inv_dx);  // lower x face of element 0
+      VT o;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const T uxp = e == V - 1 ? N.right : c.v[e + 1];
+        const T bxp = e == V - 1 ? NB.right : cbeta.v[e + 1];
+        const T fxp = face_flux(c.v[e], uxp, cbeta.v[e], bxp, inv_dx);
+        const T fym = face_flux(N.ym.v[e], c.v[e], NB.ym.v[e], cbeta.v[e], inv_dx);
+        const T fyp = face_flux(c.v[e], N.yp.v[e], cbeta.v[e], NB.yp.v[e], inv_dx);
+        const T fzp = face_flux(c.v[e], P[k + 2].v[e], cbeta.v[e], Q[k + 2].v[e], inv_dx);
+        const T dfx = (fxp - fx) * inv_dx, dfy = (fyp - fym) * inv_dx, dfz = (fzp - fz[e]) * inv_dx;
+        o.v[e] = c.v[e] + dt * ((dfx + dfy) + dfz);
+        fx = fxp;
+        fz[e] = fzp;
+      }
+      const int z = L.zb0 + k;
+      if (z < L.zb1 && L.active) {
+        stv_nt<T, V>(wp + (int64_t)z * B.sz, o);
+        if (FUSED) stage_edges<T, V, ZB>(S, L, tl, nvx, k, o);
+      }
+    }
+    if (FUSED) store_mirror<T, V, ZB>(S, tl, B, w);
+  }
+}
+
 __device__ double block_reduce(double v, int op);
 
 // GSRB colour pass, fused with the ghost fill (neighbour boxes read through the
@@ -1487,6 +1574,43 @@ hipError_t launch_gsrb_fused(const Plan& p, void* phi, const void* f, double h2,
                       : gsrb_dma_v<double, 1>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
   return p.vec == 4 ? gsrb_dma_v<float, 4>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s)
                     : gsrb_dma_v<float, 1>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
+}
+
+// Variable-coefficient heat step (k_heat_vc_dma) over the whole level, one
+// workgroup per linear tile.
+size_t vc_lds_half(int dtype, int vec, int zchunk, int yhmax, int xhmax, int block) {
+  const size_t es = dtype == BL_F64 ? 8 : 4, vb = es * (size_t)vec, zb = (size_t)zchunk;
+  const size_t b = zb * block * vb + zb * 2 * yhmax * vb + zb * 2 * xhmax * es;
+  return (b + 15) & ~(size_t)15;
+}
+
+template <typename T, int V, int ZB>
+static hipError_t vc_zb(const VcArgs& a, hipStream_t s) {
+  const size_t half = vc_lds_half(sizeof(T) == 8 ? BL_F64 : BL_F32, V, ZB, a.yhmax, a.xhmax, a.block);
+  if (a.fused)
+    hipLaunchKernelGGL((k_heat_vc_dma<T, V, true, ZB>), dim3(a.nlin), dim3(a.block), 2 * half, s, a.lin, a.nlin,
+                       a.boxes, a.recs, (const T*)a.u, (T*)a.w, (const T*)a.beta, (T)a.dt, (T)a.inv_dx, a.yhmax,
+                       (int)half);
+  else
+    hipLaunchKernelGGL((k_heat_vc_dma<T, V, false, ZB>), dim3(a.nlin), dim3(a.block), 2 * half, s, a.lin, a.nlin,
+                       a.boxes, a.recs, (const T*)a.u, (T*)a.w, (const T*)a.beta, (T)a.dt, (T)a.inv_dx, a.yhmax,
+                       (int)half);
+  return hipGetLastError();
+}
+
+template <typename T, int V>
+static hipError_t vc_v(const VcArgs& a, hipStream_t s) {
+  switch (a.zchunk) {
+    case 2: return vc_zb<T, V, 2>(a, s);
+    case 8: return vc_zb<T, V, 8>(a, s);
+    default: return vc_zb<T, V, 4>(a, s);
+  }
+}
+
+hipError_t launch_heat_varcoef(int dtype, int vec, const VcArgs& a, hipStream_t s) {
+  if (a.nlin <= 0) return hipSuccess;
+  if (dtype == BL_F64) return vec == 2 ? vc_v<double, 2>(a, s) : vc_v<double, 1>(a, s);
+  return vec == 4 ? vc_v<float, 4>(a, s) : vc_v<float, 1>(a, s);
 }
 
 hipError_t launch_reduce_partials(const double* partials, int n, int take_sqrt, double* out, hipStream_t s) {

@@ -70,6 +70,23 @@ hipError_t launch_gsrb_fused(const Plan& p, void* phi, const void* f, double h2,
 // *out = sum (sqrt of it if take_sqrt) of partials[0..n)
 hipError_t launch_reduce_partials(const double* partials, int n, int take_sqrt, double* out, hipStream_t s);
 
+// Variable-coefficient heat step in the flux form, u -> w with coefficient beta
+// (same layout), over linear tiles built for zchunk and block; LDS 2*vc_lds_half.
+struct VcArgs {
+  const DevLinTile* lin;
+  int nlin;
+  const DevBox* boxes;
+  const DevFaceRec* recs;
+  int yhmax, xhmax, zchunk, block;
+  int fused;                   // 1: neighbour boxes through the face records; 0: filled ghosts
+  const void* u;
+  void* w;
+  const void* beta;
+  double dt, inv_dx;
+};
+size_t vc_lds_half(int dtype, int vec, int zchunk, int yhmax, int xhmax, int block);
+hipError_t launch_heat_varcoef(int dtype, int vec, const VcArgs& a, hipStream_t s);
+
 int device_cu_count();
 
 }  // namespace bl

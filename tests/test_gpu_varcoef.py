@@ -1,0 +1,170 @@
+"""Parity of the variable-coefficient flux-form heat step (the HIP kernel, through the
+C-ABI) with the oracle: du/dt = div(beta grad u), face coefficient the mean of the two
+cells, differences multiplied by 1/dx.
+
+FP64 results are bit-identical to the oracle (same operand order, no FMA contraction);
+FP32 storage is held to 2e-5 of the FP64 oracle.  Layouts cover uneven boxes, boxes that
+leave holes next to a non-periodic side (ghosts there keep the caller's value on both
+sides), odd extents (no aligned vector loads on some faces: the form that fills ghosts),
+and every tile shape the library can be set to.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1604_03570_amd import inputs as I
+from tests.gpu_helpers import gpu_global, lib, make_pair, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+F32_TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def bt():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return lib()
+
+
+def _layout(name, rng):
+    if name == "uneven_periodic":
+        dom, periodic = I.domain_box(64), (1, 1, 1)
+        boxes = I.random_chop(dom, 8, 32, 8, seed=4)
+    elif name == "noncovering_mixed":
+        dom, periodic = I.domain_box((48, 32, 40)), (1, 0, 1)
+        boxes = I.random_chop(dom, 8, 24, 8, seed=9)
+        boxes = boxes[np.sort(rng.permutation(len(boxes))[: len(boxes) * 3 // 4])]
+    else:  # odd extents, boxes of any edge
+        dom, periodic = I.domain_box((37, 23, 18)), (1, 1, 1)
+        boxes = I.random_chop(dom, 3, 14, 1, seed=2)
+    return dom, periodic, boxes
+
+
+def _beta_like(bt, ba, boxes, dom, periodic, ncomp, dtype, beta, ghost_value=1.25):
+    """beta on u's BoxArray (ghosts ghost_value, valid = beta) and the oracle's copy."""
+    bg = bt.MultiFab(ba, ncomp, 1, dtype)
+    bg.set_val(ghost_value, with_ghosts=True)
+    bg.from_global(beta)
+    ob = O.OracleMultiFab(boxes, dom, periodic, ncomp, 1)
+    ob.data[...] = ghost_value
+    ob.load_global(np.asarray(beta, dtype=np.float64))
+    torch.cuda.synchronize()
+    return bg, ob
+
+
+def _problem(bt, layout, dtype, ncomp, seed):
+    rng = np.random.default_rng(seed)
+    dom, periodic, boxes = _layout(layout, rng)
+    N = tuple(int(dom[3 + d] + 1) for d in range(3))
+    g = rng.random((ncomp,) + N[::-1]) + 1.0
+    beta = 0.5 + rng.random((ncomp,) + N[::-1])
+    if dtype == bt.F32:
+        g, beta = I.round_f32(g), I.round_f32(beta)
+    dx = 1.0 / max(N)
+    dt = 0.9 * dx * dx / (6.0 * 1.5)
+    ba, a, b, o = make_pair(boxes, dom, periodic, ncomp, 1, dtype, g, ghost_value=0.5)
+    bg, ob = _beta_like(bt, ba, boxes, dom, periodic, ncomp, dtype, beta)
+    return dict(boxes=boxes, a=a, b=b, o=o, beta=bg, obeta=ob, dt=dt, dx=dx)
+
+
+def _check(bt, got, ref, dtype):
+    if dtype == bt.F64:
+        assert np.array_equal(got, ref, equal_nan=True)
+    else:
+        err = rel_err(got, ref)
+        say(f"  fp32 rel err {err:.2e}")
+        assert err <= F32_TOL
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+@pytest.mark.parametrize("layout", ["uneven_periodic", "noncovering_mixed", "odd_extents"])
+def test_varcoef_equals_the_oracle(bt, layout, dtype_name):
+    dtype = bt.F64 if dtype_name == "f64" else bt.F32
+    steps = 9
+    say(f"varcoef layout={layout} dtype={dtype_name}")
+    P = _problem(bt, layout, dtype, 2, seed=21)
+    res = bt.heat_varcoef_advance(P["a"], P["b"], P["beta"], steps, P["dt"], P["dx"])
+    ref = O.heat_varcoef_advance(P["o"], P["obeta"], steps, P["dt"], P["dx"]).to_global()
+    _check(bt, gpu_global(res), ref, dtype)
+
+
+TILE_SHAPES = [(2, 4, 0, 3), (8, 4, 0, 3), (4, 1, 0, 3), (4, 2, 0, 3), (8, 3, 0, 3), (4, 4, 0, 2), (0, 2, 0, 0)]
+
+
+@pytest.mark.parametrize("shape", TILE_SHAPES, ids=lambda s: "z%d_w%d_b%d" % (s[0], s[1], s[3]))
+def test_varcoef_every_tile_shape(bt, shape):
+    """The kernel runs on the plan's own tiles where twice their LDS fits, else on tiles
+    it builds with fewer planes per z block; every choice gives the oracle's bits."""
+    zchunk, waves, persist, block = shape
+    say(f"varcoef tile shape zchunk={zchunk} waves={waves} block={block}")
+    bt.set_tile_config(zchunk if block else 4, waves, persist, block)
+    try:
+        P = _problem(bt, "uneven_periodic", bt.F64, 1, seed=5)
+        res = bt.heat_varcoef_advance(P["a"], P["b"], P["beta"], 6, P["dt"], P["dx"])
+        ref = O.heat_varcoef_advance(P["o"], P["obeta"], 6, P["dt"], P["dx"]).to_global()
+        assert np.array_equal(gpu_global(res), ref)
+    finally:
+        bt.set_tile_config(4, 4, 0, 3)
+
+
+def test_varcoef_large_boxes_take_the_smaller_tiles(bt):
+    """128^3 boxes (planes wider than one workgroup) at 8 planes per z block: twice the
+    stencil's LDS would not fit, so the kernel runs on its own tiles; bits unchanged."""
+    n = 128
+    rng = np.random.default_rng(3)
+    dom = I.domain_box((n, n, 32))
+    boxes = I.regular_chop(dom, (128, 128, 16))
+    g = rng.random((1, 32, n, n)) + 1.0
+    beta = 0.5 + rng.random((1, 32, n, n))
+    dx = 1.0 / n
+    dt = 0.9 * dx * dx / 9.0
+    bt.set_tile_config(8, 4, 0, 3)
+    try:
+        ba, a, b, o = make_pair(boxes, dom, (1, 1, 1), 1, 1, bt.F64, g)
+        bg, ob = _beta_like(bt, ba, boxes, dom, (1, 1, 1), 1, bt.F64, beta)
+        res = bt.heat_varcoef_advance(a, b, bg, 5, dt, dx)
+        ref = O.heat_varcoef_advance(o, ob, 5, dt, dx).to_global()
+        assert np.array_equal(gpu_global(res), ref)
+    finally:
+        bt.set_tile_config(4, 4, 0, 3)
+
+
+def test_varcoef_unit_coefficient_is_the_flux_form(bt):
+    """beta = 1 makes every face coefficient exactly 1: the GPU result equals the oracle's
+    constant-coefficient flux form bit for bit."""
+    dom = I.domain_box(32)
+    boxes = I.random_chop(dom, 8, 16, 8, seed=1)
+    g = np.random.default_rng(8).random((1, 32, 32, 32))
+    dx = 1.0 / 32
+    dt = 0.9 * dx * dx / 6.0
+    ba, a, b, o = make_pair(boxes, dom, (1, 1, 1), 1, 1, bt.F64, g)
+    bg, _ = _beta_like(bt, ba, boxes, dom, (1, 1, 1), 1, bt.F64, np.ones_like(g), ghost_value=1.0)
+    res = bt.heat_varcoef_advance(a, b, bg, 4, dt, dx)
+    x, y = o, o.copy()
+    for _ in range(4):
+        O.heat_flux_step(x, y, dt, dx)
+        x, y = y, x
+    assert np.array_equal(gpu_global(res), x.to_global())
+
+
+def test_varcoef_degenerate_calls(bt):
+    dom = I.domain_box(16)
+    boxes = I.regular_chop(dom, 8)
+    g = np.random.default_rng(2).random((1, 16, 16, 16))
+    ba, a, b, _ = make_pair(boxes, dom, (1, 1, 1), 1, 1, bt.F64, g)
+    beta = bt.MultiFab(ba, 1, 1, bt.F64)
+    beta.set_val(1.0, with_ghosts=True)
+    before = gpu_global(a)
+    assert bt.heat_varcoef_advance(a, b, beta, 0, 1e-5, 1.0 / 16) is a  # no steps: u[0] untouched
+    assert np.array_equal(gpu_global(a), before)
+    with pytest.raises(bt.BoxtileError):  # beta sharing u's storage
+        bt.heat_varcoef_advance(a, b, a, 1, 1e-5, 1.0 / 16)
+    other = bt.MultiFab(ba, 2, 1, bt.F64)
+    with pytest.raises(bt.BoxtileError):  # beta of another shape
+        bt.heat_varcoef_advance(a, b, other, 1, 1e-5, 1.0 / 16)
+    f32 = bt.MultiFab(ba, 1, 1, bt.F32)
+    with pytest.raises(bt.BoxtileError):  # beta of another dtype
+        bt.heat_varcoef_advance(a, b, f32, 1, 1e-5, 1.0 / 16)
+    with pytest.raises(bt.BoxtileError):
+        bt.heat_varcoef_advance(a, b, beta, -1, 1e-5, 1.0 / 16)

@@ -252,6 +252,25 @@ def test_heat_window_equals_full_run():
         assert O.heat_window(u0[0], (i, j, k), steps, c) == full[k, j, i]
 
 
+def test_varcoef_window_equals_full_run():
+    """The dependence-cone window (one box, fixed ghosts) gives the full periodic run's
+    cell bit for bit, also for a window that wraps around the domain."""
+    n, steps = 18, 7
+    rng = np.random.default_rng(11)
+    u0 = rng.random((1, n, n, n))
+    beta = 0.5 + rng.random((1, n, n, n))
+    dx = 1.0 / n
+    dt = 0.9 * dx * dx / (6 * 1.5)
+    boxes = I.random_chop(I.domain_box(n), 3, 9, 1, seed=2)
+    m, bm = _mf(boxes, n), _mf(boxes, n)
+    m.load_global(u0)
+    bm.load_global(beta)
+    full = O.heat_varcoef_advance(m, bm, steps, dt, dx).to_global()[0]
+    for cell in [(0, 0, 0), (17, 9, 3)] + [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(6)]:
+        i, j, k = cell
+        assert O.heat_varcoef_window(u0[0], beta[0], cell, steps, dt, dx) == full[k, j, i]
+
+
 # ---------------------------------------------------------------------------------------------
 # FillBoundary
 # ---------------------------------------------------------------------------------------------
