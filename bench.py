@@ -247,6 +247,52 @@ def gsrb_run(bt, I, torch, seed: int, sweeps: int = 20) -> dict:
     return out
 
 
+def varcoef_run(bt, I, torch, boxes, dom, u0, ncomp: int, seed: int, steps: int) -> dict:
+    """du/dt = div(beta grad u) in the flux form on the same level (FP64, same boxes and
+    u0), beta = 0.5 + U(0,1) per cell and component, dt = 0.9 dx^2 / (6 max beta).  The
+    kernel's duration per launch is the 2K-step run minus the K-step run over K; its
+    algorithmic bytes are u and beta read once and u written once (24 per cell)."""
+    n = int(dom[3]) + 1
+    ba = bt.BoxArray.from_boxes(boxes, dom)
+    a, b, beta = (bt.MultiFab(ba, ncomp, 1, bt.F64) for _ in range(3))
+    t0 = time.perf_counter()
+    bg = I.uniform(n, ncomp, seed=seed + 1)
+    for comp in range(ncomp):
+        a.from_global(u0[comp:comp + 1], scomp=comp)
+        beta.from_global(bg[comp:comp + 1] + 0.5, scomp=comp)
+    del bg
+    log(f"varcoef: inputs in {time.perf_counter() - t0:.1f} s")
+    dx = 1.0 / n
+    dt = 0.9 * dx * dx / (6.0 * 1.5)
+    cells = int(sum(int(np.prod(bx[3:] - bx[:3] + 1)) for bx in boxes)) * ncomp
+    s0 = a.sum(0)
+    bt.heat_varcoef_advance(a, b, beta, 2, dt, dx)  # warm-up, state back in a
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    bt.heat_varcoef_advance(a, b, beta, steps, dt, dx)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ev[2].record(stream)
+    res = bt.heat_varcoef_advance(a, b, beta, 2 * steps, dt, dx)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    per_launch = (ev[2].elapsed_time(ev[3]) - ms) / steps
+    drift = abs(res.sum(0) - s0) / abs(s0)
+    gbs = 24 * cells / (per_launch / 1e3) / 1e9
+    out = {"workload": f"{n}^3 periodic, {len(boxes)} uneven boxes, {ncomp} comps, FP64, beta U(0.5, 1.5)",
+           "ms_per_step": round(ms / steps, 5), "kernel_ms_per_launch": round(per_launch, 5),
+           "gcell_s": round(cells * steps / (ms / 1e3) / 1e9, 2), "kernel_gbs_at_24B": round(gbs, 1),
+           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "sum_drift_rel": drift}
+    log(f"varcoef: {ms / steps:.3f} ms/step, kernel {per_launch:.3f} ms, {gbs:.0f} GB/s at 24 B/cell, "
+        f"drift {drift:.2e}")
+    del a, b, beta, ba, res
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +310,7 @@ def main() -> int:
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and unfused measurements")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
     ap.add_argument("--no-gsrb", action="store_true", help="skip the GSRB smoother run")
+    ap.add_argument("--no-varcoef", action="store_true", help="skip the variable-coefficient flux-form run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three plain device copies of 2 GiB (reference for HBM byte counters)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -421,6 +468,9 @@ def main() -> int:
             log(f"f32: {v32:.1f} GCell/s")
             del a32, b32, ba32
             torch.cuda.empty_cache()
+
+    if not args.no_extra and not args.no_varcoef and args.dtype == "f64":
+        extra["varcoef"] = varcoef_run(bt, I, torch, boxes, dom, u0, ncomp, args.seed, 20)
 
     if not args.no_extra and not args.no_gsrb:
         extra["gsrb"] = gsrb_run(bt, I, torch, args.seed)

@@ -380,6 +380,24 @@ void bl_batch_destroy(bl_batch* b);
 bl_status bl_fill_plan(const bl_boxarray* ba, int32_t nghost, int32_t* nrec, int32_t* rec);
 
 /*
+ * Logical tiles of every box (Sec. 3.2's tiling of a box for one loop): along
+ * each axis, tiles of tile_size[d] cells from the box's low corner, the last
+ * one taking what remains; listed box by box, then by z, y and x (x fastest).
+ * 7 int32 per tile {box, lo[3], hi[3]} (inclusive, global index space):
+ *   BL_TILE_CELL   the tile's cells (arg ignored); the tiles of a box partition it;
+ *   BL_TILE_NODAL  faces normal to axis arg (face i lies between cells i-1 and i):
+ *                  the tile's lower faces, plus face hi+1 where the tile ends at the
+ *                  box's high side, so the face tiles of a box partition its faces;
+ *   BL_TILE_GROWN  the tile grown by arg cells on the sides where it meets the box
+ *                  boundary only, so grown tiles still do not overlap.
+ * With out == NULL only *ntiles is set.  tile_size[d] >= 1, 0 <= arg <= 2 for
+ * NODAL, arg >= 0 for GROWN (else BL_EINVAL).  Host metadata only.
+ */
+typedef enum { BL_TILE_CELL = 0, BL_TILE_NODAL = 1, BL_TILE_GROWN = 2 } bl_tile_kind;
+bl_status bl_tile_boxes(const bl_boxarray* ba, const int32_t tile_size[3], bl_tile_kind kind, int32_t arg,
+                        int32_t* ntiles, int32_t* out);
+
+/*
  * Face-source records of the fused stencil: for each box and face (2*axis +
  * side, side 1 = high), the one-cell layer just outside the face split into
  * rectangles, each read from one source box (src) at destination + shift; a

@@ -87,6 +87,7 @@ _SIGS = {
     "bl_face_plan": [_vp, _i32p, _i32p],
     "bl_tile_list": [_vp, _i32, _i32, _i32, _i32p, _i32p],
     "bl_stencil_tiles": [_vp, _i32, _i32, _i32, _i32p, _i32p],
+    "bl_tile_boxes": [_vp, _i32p, _i32, _i32, _i32p, _i32p],
     "bl_static_partition": [_i32, _i32, _i32p],
 }
 for _name, _args in _SIGS.items():
@@ -220,6 +221,21 @@ class BoxArray:
         _check(_L.bl_stencil_tiles(self._h, ncomp, nghost, dtype, ctypes.byref(n), None))
         out = np.zeros((n.value, 10), dtype=np.int32)
         _check(_L.bl_stencil_tiles(self._h, ncomp, nghost, dtype, ctypes.byref(n), out.ctypes.data_as(_i32p)))
+        return out
+
+    TILE_KINDS = {"cell": 0, "nodal": 1, "grown": 2}
+
+    def tile_boxes(self, tile_size, kind: str = "cell", arg: int = 0) -> np.ndarray:
+        """Logical tiles of every box: rows of {box, lo[3], hi[3]}.  kind "cell" (tilebox),
+        "nodal" with arg = the face direction (nodaltilebox), "grown" with arg = ghost width
+        (growntilebox)."""
+        ts = np.ascontiguousarray(np.broadcast_to(np.asarray(tile_size, dtype=np.int32), (3,)))
+        k = self.TILE_KINDS[kind]
+        n = ctypes.c_int32()
+        _check(_L.bl_tile_boxes(self._h, ts.ctypes.data_as(_i32p), k, int(arg), ctypes.byref(n), None))
+        out = np.zeros((n.value, 7), dtype=np.int32)
+        _check(_L.bl_tile_boxes(self._h, ts.ctypes.data_as(_i32p), k, int(arg), ctypes.byref(n),
+                                out.ctypes.data_as(_i32p)))
         return out
 
     def multifab_bytes(self, ncomp: int, nghost: int, dtype: int = F64) -> int:

@@ -752,6 +752,46 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
 
 extern "C" {
 
+bl_status bl_tile_boxes(const bl_boxarray* ba, const int32_t tile_size[3], bl_tile_kind kind, int32_t arg,
+                        int32_t* ntiles, int32_t* out) {
+  clear_error();
+  if (!ba || !tile_size || !ntiles) return fail(BL_EINVAL, "NULL argument");
+  for (int d = 0; d < 3; ++d)
+    if (tile_size[d] < 1) return fail(BL_EINVAL, "tile_size[%d] = %d < 1", d, tile_size[d]);
+  if (kind == BL_TILE_NODAL && (arg < 0 || arg > 2)) return fail(BL_EINVAL, "nodal direction %d not in 0..2", arg);
+  if (kind == BL_TILE_GROWN && arg < 0) return fail(BL_EINVAL, "grow width %d < 0", arg);
+  if (kind != BL_TILE_CELL && kind != BL_TILE_NODAL && kind != BL_TILE_GROWN)
+    return fail(BL_EINVAL, "unknown tile kind %d", (int)kind);
+  int64_t n = 0;
+  for (size_t b = 0; b < ba->boxes.size(); ++b) {
+    const Box& B = ba->boxes[b];
+    int cnt[3];
+    for (int d = 0; d < 3; ++d) cnt[d] = (B.len(d) + tile_size[d] - 1) / tile_size[d];
+    for (int tz = 0; tz < cnt[2]; ++tz)
+      for (int ty = 0; ty < cnt[1]; ++ty)
+        for (int tx = 0; tx < cnt[0]; ++tx, ++n) {
+          if (!out) continue;
+          const int t[3] = {tx, ty, tz};
+          int32_t* r = out + 7 * n;
+          r[0] = (int32_t)b;
+          for (int d = 0; d < 3; ++d) {
+            int lo = B.lo[d] + t[d] * tile_size[d];
+            int hi = std::min(B.hi[d], lo + tile_size[d] - 1);
+            if (kind == BL_TILE_NODAL && d == arg && hi == B.hi[d]) hi += 1;  // the box's last face
+            if (kind == BL_TILE_GROWN) {
+              if (lo == B.lo[d]) lo -= arg;
+              if (hi == B.hi[d]) hi += arg;
+            }
+            r[1 + d] = lo;
+            r[4 + d] = hi;
+          }
+        }
+  }
+  if (n > INT32_MAX) return fail(BL_EINVAL, "more than 2^31 tiles");
+  *ntiles = (int32_t)n;
+  return BL_OK;
+}
+
 bl_status bl_multifab_bytes(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_dtype dtype, size_t* bytes) {
   clear_error();
   if (!ba || !bytes) return fail(BL_EINVAL, "NULL argument");

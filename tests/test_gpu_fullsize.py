@@ -101,6 +101,37 @@ def test_512cube_uneven_fused_step_at_full_size(bt, dtype_name):
     assert worst <= 2e-5
 
 
+def test_512cube_uneven_varcoef_at_full_size(bt):
+    """512^3 periodic, the seeded uneven chop, 5 comps, FP64, beta = 0.5 + U(0,1): 10
+    flux-form steps in the benchmark's launch configuration; sampled cells equal the
+    oracle's dependence-cone window bit for bit and every component's sum is conserved."""
+    n, ncomp, steps = 512, 5, 10
+    dom = I.domain_box(n)
+    boxes = I.random_chop(dom, 16, 128, 8, seed=0)
+    ba = bt.BoxArray.from_boxes(boxes, dom)
+    u0 = I.uniform(n, ncomp, seed=0)
+    beta = I.uniform(n, ncomp, seed=1) + 0.5
+    dx = 1.0 / n
+    dt = 0.9 * dx * dx / (6.0 * 1.5)
+    a, b, bm = (bt.MultiFab(ba, ncomp, 1, bt.F64) for _ in range(3))
+    for comp in range(ncomp):
+        a.from_global(u0[comp:comp + 1], scomp=comp)
+        bm.from_global(beta[comp:comp + 1], scomp=comp)
+    s0 = [a.sum(comp) for comp in range(ncomp)]
+    res = bt.heat_varcoef_advance(a, b, bm, steps, dt, dx)
+    torch.cuda.synchronize()
+    for comp in range(ncomp):
+        drift = abs(res.sum(comp) - s0[comp]) / abs(s0[comp])
+        assert drift <= 1e-13, (comp, drift)
+    rng = np.random.default_rng(9)
+    for comp in (0, 2, 4):
+        for _ in range(3):
+            cell = tuple(int(v) for v in rng.integers(0, n, 3))
+            ref = O.heat_varcoef_window(u0[comp], beta[comp], cell, steps, dt, dx)
+            assert _cell(res, boxes, comp, cell) == ref, (comp, cell)
+    say("512^3 uneven varcoef: sampled cells bit-exact, sums conserved")
+
+
 def test_384cube_gsrb_at_full_size(bt):
     """384^3 periodic, 216 boxes of 64^3, zero-mean f: FP64 state after 2 sweeps equals
     the oracle bit for bit (norms to 1e-13); FP32 state over 20 sweeps stays within 1e-5
