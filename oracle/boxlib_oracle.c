@@ -34,6 +34,10 @@
  *   orc_gsrb_color     one colour of a red-black Gauss-Seidel sweep for the
  *                      7-point discrete Poisson problem -L_h phi = f.
  *   orc_residual       r = f + L_h phi per valid cell (FP64).
+ *   orc_restrict_residual  multigrid restriction: each cell of the coarsened
+ *                      level takes the mean of the residuals of its 8 cells.
+ *   orc_prolong_add    multigrid prolongation: each fine cell adds the value of
+ *                      the coarse cell that contains it.
  *   orc_heat_window    n heat steps on a cube window of a fully periodic global
  *                      array, returning the centre value (used to check single
  *                      outputs of very large runs one by one).
@@ -81,6 +85,8 @@ static int floor_mod(int a, int n) {
   int r = a % n;
   return r < 0 ? r + n : r;
 }
+
+static int floor_half(int a) { return (a - floor_mod(a, 2)) / 2; }
 
 /*
  * Owner map of the level: owner[(k*N1 + j)*N0 + i] = index of the box whose
@@ -340,6 +346,14 @@ void orc_gsrb_color(int nbox, const int* boxes, int ng, double* phi, const doubl
  *   r = f + (s - 6 phi) / h2,  s = ((phi[i-1]+phi[i+1]) + (phi[j-1]+phi[j+1])) + (phi[k-1]+phi[k+1])
  * written box after box, each box in (k, j, i) order, into r_out.
  */
+static double residual_at(const double* p, const double* fb, const fab_geom* g, int i, int j, int k, double h2) {
+  double sx = p[fab_index(g, 0, i - 1, j, k)] + p[fab_index(g, 0, i + 1, j, k)];
+  double sy = p[fab_index(g, 0, i, j - 1, k)] + p[fab_index(g, 0, i, j + 1, k)];
+  double sz = p[fab_index(g, 0, i, j, k - 1)] + p[fab_index(g, 0, i, j, k + 1)];
+  int64_t q = fab_index(g, 0, i, j, k);
+  return fb[q] + (((sx + sy) + sz) - 6.0 * p[q]) / h2;
+}
+
 void orc_residual(int nbox, const int* boxes, int ng, const double* phi, const double* f,
                   const int64_t* fab_off, double h2, double* r_out) {
   int64_t n = 0;
@@ -350,13 +364,65 @@ void orc_residual(int nbox, const int* boxes, int ng, const double* phi, const d
     const double* fb = f + fab_off[b];
     for (int k = bx[2]; k <= bx[5]; ++k)
       for (int j = bx[1]; j <= bx[4]; ++j)
-        for (int i = bx[0]; i <= bx[3]; ++i) {
-          double sx = p[fab_index(&g, 0, i - 1, j, k)] + p[fab_index(&g, 0, i + 1, j, k)];
-          double sy = p[fab_index(&g, 0, i, j - 1, k)] + p[fab_index(&g, 0, i, j + 1, k)];
-          double sz = p[fab_index(&g, 0, i, j, k - 1)] + p[fab_index(&g, 0, i, j, k + 1)];
-          int64_t q = fab_index(&g, 0, i, j, k);
-          r_out[n++] = fb[q] + (((sx + sy) + sz) - 6.0 * p[q]) / h2;
+        for (int i = bx[0]; i <= bx[3]; ++i) r_out[n++] = residual_at(p, fb, &g, i, j, k, h2);
+  }
+}
+
+/*
+ * Multigrid restriction of the residual, cell-centred, refinement ratio 2.
+ * Coarse box b is fine box b coarsened: lo/2 .. (hi+1)/2 - 1, every fine lo
+ * and extent even.  Coarse cell (I,J,K) covers fine cells (2I+a, 2J+b, 2K+c),
+ * a, b, c in {0, 1}; it takes
+ *   fc = (sum of their residuals r = f + L_h phi) * 0.125,
+ * the sum taken in the order c, then b, then a (lower child first), starting
+ * from the first child's residual.  phi's ghost cells must be filled.
+ */
+void orc_restrict_residual(int nbox, const int* fboxes, const int* cboxes, int ng, const double* phi,
+                           const double* f, const int64_t* ffab_off, double* fc, const int64_t* cfab_off,
+                           double h2) {
+#pragma omp parallel for schedule(dynamic)
+  for (int b = 0; b < nbox; ++b) {
+    const int* fbx = fboxes + 6 * b;
+    const int* cbx = cboxes + 6 * b;
+    fab_geom gf = geom_of(fbx, ng), gc = geom_of(cbx, ng);
+    const double* p = phi + ffab_off[b];
+    const double* fb = f + ffab_off[b];
+    double* out = fc + cfab_off[b];
+    for (int K = cbx[2]; K <= cbx[5]; ++K)
+      for (int J = cbx[1]; J <= cbx[4]; ++J)
+        for (int I = cbx[0]; I <= cbx[3]; ++I) {
+          double acc = 0.0;
+          int first = 1;
+          for (int c = 0; c < 2; ++c)
+            for (int bb = 0; bb < 2; ++bb)
+              for (int a = 0; a < 2; ++a) {
+                double r = residual_at(p, fb, &gf, 2 * I + a, 2 * J + bb, 2 * K + c, h2);
+                acc = first ? r : acc + r;
+                first = 0;
+              }
+          out[fab_index(&gc, 0, I, J, K)] = acc * 0.125;
         }
+  }
+}
+
+/*
+ * Multigrid prolongation, piecewise constant: every valid cell (i,j,k) of fine
+ * box b adds the value of cell (floor(i/2), floor(j/2), floor(k/2)) of coarse
+ * box b (the fine box coarsened, as for the restriction).
+ */
+void orc_prolong_add(int nbox, const int* fboxes, const int* cboxes, int ng, double* phi,
+                     const int64_t* ffab_off, const double* pc, const int64_t* cfab_off) {
+#pragma omp parallel for schedule(dynamic)
+  for (int b = 0; b < nbox; ++b) {
+    const int* fbx = fboxes + 6 * b;
+    const int* cbx = cboxes + 6 * b;
+    fab_geom gf = geom_of(fbx, ng), gc = geom_of(cbx, ng);
+    double* p = phi + ffab_off[b];
+    const double* c = pc + cfab_off[b];
+    for (int k = fbx[2]; k <= fbx[5]; ++k)
+      for (int j = fbx[1]; j <= fbx[4]; ++j)
+        for (int i = fbx[0]; i <= fbx[3]; ++i)
+          p[fab_index(&gf, 0, i, j, k)] += c[fab_index(&gc, 0, floor_half(i), floor_half(j), floor_half(k))];
   }
 }
 

@@ -77,6 +77,11 @@ def _configure(L):
     L.orc_residual.argtypes = [ctypes.c_int, _ip, ctypes.c_int, _dp, _dp, _i64p,
                                ctypes.c_double, _dp]
     L.orc_residual.restype = None
+    L.orc_restrict_residual.argtypes = [ctypes.c_int, _ip, _ip, ctypes.c_int, _dp, _dp, _i64p, _dp, _i64p,
+                                        ctypes.c_double]
+    L.orc_restrict_residual.restype = None
+    L.orc_prolong_add.argtypes = [ctypes.c_int, _ip, _ip, ctypes.c_int, _dp, _i64p, _dp, _i64p]
+    L.orc_prolong_add.restype = None
     L.orc_heat_window.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_double]
     L.orc_heat_window.restype = ctypes.c_double
     return L
@@ -338,6 +343,91 @@ def residual_norm(phi: OracleMultiFab, f: OracleMultiFab, h2: float) -> float:
     """||r||_2 = sqrt(sum r^2) with the sum exactly rounded."""
     r = residual(phi, f, h2)
     return math.sqrt(math.fsum((r * r).tolist()))
+
+
+# -- multigrid V-cycle for -L_h phi = f (textbook geometric multigrid; the paper names
+#    multigrid solvers and their coarse levels of small grids, Sec. 1 and Sec. 3.3) ------
+def coarsen_boxes(boxes) -> np.ndarray:
+    """Boxes coarsened by 2: lo/2 .. (hi+1)/2 - 1 (every lo and extent must be even)."""
+    b = np.asarray(boxes, dtype=np.int64).reshape(-1, 6)
+    return np.concatenate([b[:, :3] // 2, (b[:, 3:] + 1) // 2 - 1], axis=1)
+
+
+def mg_level_boxes(boxes, domain, periodic, max_levels: int):
+    """The levels of the hierarchy: level 0 is (boxes, domain); level l+1 is level l
+    coarsened by 2, made while every box and the domain have even lo and even extents
+    and every periodic axis of the coarse domain keeps an even extent (red-black
+    colouring across the wrap), up to max_levels levels."""
+    levels = [(np.asarray(boxes, dtype=np.int64).reshape(-1, 6), np.asarray(domain, dtype=np.int64).reshape(6))]
+    while len(levels) < max_levels:
+        b, d = levels[-1]
+        allb = np.concatenate([b, d[None]], axis=0)
+        if np.any(allb[:, :3] % 2) or np.any((allb[:, 3:] - allb[:, :3] + 1) % 2):
+            break
+        cd = coarsen_boxes(d)[0]
+        if any(periodic[a] and (cd[3 + a] - cd[a] + 1) % 2 for a in range(3)):
+            break
+        levels.append((coarsen_boxes(b), cd))
+    return levels
+
+
+def restrict_residual(phi: OracleMultiFab, f: OracleMultiFab, h2: float, fc: OracleMultiFab) -> None:
+    """fc (on the coarsened boxes) = mean of the 8 fine residuals of each coarse cell; fills
+    phi's ghosts first."""
+    _same_layout(phi, f)
+    if fc.nbox != phi.nbox or not np.array_equal(fc.boxes, coarsen_boxes(phi.boxes)) or fc.ng != phi.ng:
+        raise ValueError("fc must live on the coarsened boxes with the same ghost width")
+    phi.fill_boundary()
+    lib().orc_restrict_residual(phi.nbox, _ptr(phi.boxes, _ip), _ptr(fc.boxes, _ip), phi.ng, _ptr(phi.data, _dp),
+                                _ptr(f.data, _dp), _ptr(phi.fab_off, _i64p), _ptr(fc.data, _dp),
+                                _ptr(fc.fab_off, _i64p), h2)
+
+
+def prolong_add(phi: OracleMultiFab, pc: OracleMultiFab) -> None:
+    """phi (valid cells) += the value of the coarse cell containing each cell."""
+    if pc.nbox != phi.nbox or not np.array_equal(pc.boxes, coarsen_boxes(phi.boxes)) or pc.ng != phi.ng:
+        raise ValueError("pc must live on the coarsened boxes with the same ghost width")
+    lib().orc_prolong_add(phi.nbox, _ptr(phi.boxes, _ip), _ptr(pc.boxes, _ip), phi.ng, _ptr(phi.data, _dp),
+                          _ptr(phi.fab_off, _i64p), _ptr(pc.data, _dp), _ptr(pc.fab_off, _i64p))
+
+
+def _smooth(phi: OracleMultiFab, f: OracleMultiFab, h2: float, nsweeps: int) -> None:
+    for _ in range(nsweeps):
+        gsrb_color(phi, f, h2, 0)
+        gsrb_color(phi, f, h2, 1)
+
+
+def mg_vcycles(phi: OracleMultiFab, f: OracleMultiFab, h2: float, ncycles: int, nu1: int = 2, nu2: int = 2,
+               nu_bottom: int = 8, max_levels: int = 32):
+    """ncycles V-cycles on -L_h phi = f, phi updated in place; returns the residual norm
+    after each cycle.  On level l (h^2 = 4^l h2): nu1 GSRB sweeps, the residual
+    restricted to level l+1 as its f, phi there set to zero (ghosts too), the cycle on
+    level l+1, the coarse phi added back by prolongation, nu2 sweeps.  The coarsest level
+    takes nu_bottom sweeps.  Ghosts no box covers keep their value on level 0 and are 0
+    on the coarse levels (the correction vanishes there)."""
+    _same_layout(phi, f)
+    if phi.ncomp != 1:
+        raise ValueError("multigrid acts on one component")
+    levels = mg_level_boxes(phi.boxes, phi.domain, phi.periodic, max_levels)
+    P = [phi] + [OracleMultiFab(b, d, phi.periodic, 1, phi.ng) for b, d in levels[1:]]
+    F = [f] + [OracleMultiFab(b, d, phi.periodic, 1, phi.ng) for b, d in levels[1:]]
+
+    def cycle(l, h2l):
+        if l == len(levels) - 1:
+            _smooth(P[l], F[l], h2l, nu_bottom)
+            return
+        _smooth(P[l], F[l], h2l, nu1)
+        restrict_residual(P[l], F[l], h2l, F[l + 1])
+        P[l + 1].data[...] = 0.0
+        cycle(l + 1, 4.0 * h2l)
+        prolong_add(P[l], P[l + 1])
+        _smooth(P[l], F[l], h2l, nu2)
+
+    norms = []
+    for _ in range(ncycles):
+        cycle(0, h2)
+        norms.append(residual_norm(phi, f, h2))
+    return norms
 
 
 def gsrb_sweeps(phi: OracleMultiFab, f: OracleMultiFab, h2: float, nsweeps: int,
