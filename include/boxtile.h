@@ -120,6 +120,14 @@ bl_status bl_boxarray_chop(const bl_box* domain, const int32_t periodic[3], cons
 bl_status bl_boxarray_chop_random(const bl_box* domain, const int32_t periodic[3], int32_t min_edge,
                                   int32_t max_edge, int32_t align, uint64_t seed, bl_boxarray** out);
 
+/*
+ * The BoxArray coarsened by `ratio` (Sec. 1's multigrid levels): box i becomes
+ * lo/ratio .. (hi+1)/ratio - 1, the domain likewise, same periodic flags, same
+ * box order.  Every box corner and extent, and the domain's, must be divisible
+ * by ratio (else BL_EINVAL).  The result is a new BoxArray owned by the caller.
+ */
+bl_status bl_boxarray_coarsen(const bl_boxarray* ba, int32_t ratio, bl_boxarray** out);
+
 /* Number of boxes, and (if boxes != NULL) the boxes themselves, in order. */
 bl_status bl_boxarray_get(const bl_boxarray* ba, int32_t* nboxes, bl_box* boxes);
 /* Domain box and periodic flags. */
@@ -294,6 +302,64 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
 /* ||f + L_h phi||_2 over valid cells in FP64 (fills phi's ghosts first); synchronises. */
 bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, double* out_host,
                            hipStream_t stream);
+
+/* ---------------------------------------------------------------- multigrid */
+
+/*
+ * Geometric multigrid for -L_h phi = f (Sec. 1 names the multilevel multigrid
+ * solvers; Sec. 3.3 their coarse levels of small grids), cell-centred,
+ * refinement ratio 2, single-component MultiFabs.  Box b of a coarse level is
+ * box b of the level above coarsened (bl_boxarray_coarsen with ratio 2).
+ *
+ * Restriction of the residual: FillBoundary(phi), then every valid cell
+ * (I,J,K) of fc takes the mean of the residuals r = f + (s - 6 phi)/h2 of its
+ * 8 cells (2I+a, 2J+b, 2K+c) on phi's level (s as in the GSRB residual),
+ * computed in FP64 from promoted values, summed in the order c, b, a (lower
+ * child first), times 0.125, stored in fc's dtype.  phi and f share a shape;
+ * fc lives on the coarsened BoxArray (BL_ESHAPE otherwise), same dtype
+ * (BL_EDTYPE), its own storage.  fc's ghost cells are not written.
+ */
+bl_status bl_mg_restrict_residual(bl_multifab* phi, const bl_multifab* f, double h2, bl_multifab* fc,
+                                  hipStream_t stream);
+
+/*
+ * Prolongation, piecewise constant: every valid cell (i,j,k) of phi adds the
+ * value of cell (floor(i/2), floor(j/2), floor(k/2)) of pc (on the coarsened
+ * BoxArray).  Ghost cells of phi are not written.
+ */
+bl_status bl_mg_prolong_add(bl_multifab* phi, const bl_multifab* pc, hipStream_t stream);
+
+/*
+ * The hierarchy.  Level 0 is `ba`; level l+1 is level l coarsened by 2, made
+ * while every box and the domain have even corners and extents and every
+ * periodic axis of the coarse domain keeps an even extent (red-black colouring
+ * across the wrap), up to max_levels levels in all (>= 1).  Coarse levels hold
+ * phi and f with one ghost layer in a caller-owned, 256-byte aligned device
+ * workspace of bl_mg_workspace_bytes bytes (0 for a single level), which must
+ * outlive the hierarchy.  nlevels (may be NULL) receives the level count.
+ */
+typedef struct bl_mg bl_mg;
+bl_status bl_mg_workspace_bytes(const bl_boxarray* ba, bl_dtype dtype, int32_t max_levels, size_t* bytes,
+                                int32_t* nlevels);
+bl_status bl_mg_create(const bl_boxarray* ba, bl_dtype dtype, int32_t max_levels, void* work_dev, size_t bytes,
+                       bl_mg** out);
+bl_status bl_mg_levels(const bl_mg* mg, int32_t* nlevels);
+void bl_mg_destroy(bl_mg* mg);
+
+/*
+ * ncycles V-cycles on -L_h phi = f, phi (on the hierarchy's level-0 BoxArray,
+ * its dtype, nghost 1) updated in place.  On level l, with h^2 = 4^l h2:
+ * nu1 GSRB sweeps (as bl_gsrb_sweeps), the residual restricted into level
+ * l+1's f, level l+1's phi set to 0 (ghost cells too), the cycle on level
+ * l+1, its phi added back by prolongation, nu2 sweeps; the coarsest level takes
+ * nu_bottom sweeps.  Ghost cells that no box covers keep the caller's values
+ * on level 0 and are 0 on coarse levels.  If resnorm_host != NULL,
+ * resnorm_host[c] = ||f + L_h phi||_2 over level 0's valid cells after cycle c
+ * (FP64; the stream is synchronised once at the end).  Every periodic axis of
+ * level 0 needs an even extent.
+ */
+bl_status bl_mg_vcycles(bl_mg* mg, bl_multifab* phi, const bl_multifab* f, double h2, int32_t ncycles,
+                        int32_t nu1, int32_t nu2, int32_t nu_bottom, double* resnorm_host, hipStream_t stream);
 
 /* ---------------------------------------------------------------- reductions */
 

@@ -88,13 +88,21 @@ _SIGS = {
     "bl_tile_list": [_vp, _i32, _i32, _i32, _i32p, _i32p],
     "bl_stencil_tiles": [_vp, _i32, _i32, _i32, _i32p, _i32p],
     "bl_tile_boxes": [_vp, _i32p, _i32, _i32, _i32p, _i32p],
+    "bl_boxarray_coarsen": [_vp, _i32, _vpp],
+    "bl_mg_restrict_residual": [_vp, _vp, ctypes.c_double, _vp, _vp],
+    "bl_mg_prolong_add": [_vp, _vp, _vp],
+    "bl_mg_workspace_bytes": [_vp, _i32, _i32, _szp, _i32p],
+    "bl_mg_create": [_vp, _i32, _i32, _vp, ctypes.c_size_t, _vpp],
+    "bl_mg_levels": [_vp, _i32p],
+    "bl_mg_vcycles": [_vp, _vp, _vp, ctypes.c_double, _i32, _i32, _i32, _i32, _dp, _vp],
     "bl_static_partition": [_i32, _i32, _i32p],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_L, _name)
     _f.argtypes = _args
     _f.restype = ctypes.c_int32
-for _name in ("bl_boxarray_destroy", "bl_distmap_destroy", "bl_multifab_destroy", "bl_batch_destroy"):
+for _name in ("bl_boxarray_destroy", "bl_distmap_destroy", "bl_multifab_destroy", "bl_batch_destroy",
+              "bl_mg_destroy"):
     getattr(_L, _name).argtypes = [_vp]
     getattr(_L, _name).restype = None
 _L.bl_last_error.restype = ctypes.c_char_p
@@ -164,6 +172,12 @@ class BoxArray:
         _check(_L.bl_boxarray_chop(ctypes.byref(_box(domain)), _per(periodic), (ctypes.c_int32 * 3)(*me),
                                    ctypes.byref(h)))
         return cls(h.value)
+
+    def coarsen(self, ratio: int = 2) -> "BoxArray":
+        """Every box and the domain coarsened by ratio (same box order and periodic flags)."""
+        h = ctypes.c_void_p()
+        _check(_L.bl_boxarray_coarsen(self._h, int(ratio), ctypes.byref(h)))
+        return BoxArray(h.value)
 
     @classmethod
     def chop_random(cls, domain, min_edge=16, max_edge=128, align=8, seed=0, periodic=(1, 1, 1)) -> "BoxArray":
@@ -460,6 +474,53 @@ def heat_varcoef_advance(u0: MultiFab, u1: MultiFab, beta: MultiFab, nsteps: int
     arr = (ctypes.c_void_p * 2)(u0.handle.value, u1.handle.value)
     _check(_L.bl_heat_varcoef_advance(arr, beta.handle, int(nsteps), float(dt), 1.0 / float(dx), _stream(stream)))
     return u0 if nsteps % 2 == 0 else u1
+
+
+def restrict_residual(phi: MultiFab, f: MultiFab, h2: float, fc: MultiFab, stream=None) -> None:
+    """fc (on phi's BoxArray coarsened by 2) = mean of the 8 fine residuals f + L_h phi of each
+    coarse cell; fills phi's ghosts first."""
+    _check(_L.bl_mg_restrict_residual(phi.handle, f.handle, float(h2), fc.handle, _stream(stream)))
+
+
+def prolong_add(phi: MultiFab, pc: MultiFab, stream=None) -> None:
+    """phi (valid cells) += the value of the coarse cell containing each cell."""
+    _check(_L.bl_mg_prolong_add(phi.handle, pc.handle, _stream(stream)))
+
+
+class Multigrid:
+    """V-cycle hierarchy for -L_h phi = f over ba; coarse levels in a device workspace held
+    by a torch uint8 tensor."""
+
+    def __init__(self, ba: BoxArray, dtype: int = F64, max_levels: int = 32, device: str = "cuda"):
+        nb = ctypes.c_size_t()
+        nl = ctypes.c_int32()
+        _check(_L.bl_mg_workspace_bytes(ba.handle, dtype, int(max_levels), ctypes.byref(nb), ctypes.byref(nl)))
+        self.ba, self.dtype = ba, dtype
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=device)
+        ptr = self.workspace.data_ptr()
+        pad = (-ptr) % 256
+        h = ctypes.c_void_p()
+        _check(_L.bl_mg_create(ba.handle, dtype, int(max_levels), ctypes.c_void_p(ptr + pad),
+                               self.workspace.numel() - pad, ctypes.byref(h)))
+        self._h = h
+        self.nlevels = nl.value
+
+    def vcycles(self, phi: MultiFab, f: MultiFab, h2: float, ncycles: int, nu1: int = 2, nu2: int = 2,
+                nu_bottom: int = 8, with_norms: bool = True, stream=None):
+        """ncycles V-cycles, phi updated in place; the level-0 residual norm after each (or None)."""
+        norms = (ctypes.c_double * max(1, ncycles))() if with_norms else None
+        _check(_L.bl_mg_vcycles(self._h, phi.handle, f.handle, float(h2), int(ncycles), int(nu1), int(nu2),
+                                int(nu_bottom), norms, _stream(stream)))
+        return list(norms)[:ncycles] if with_norms else None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _L is not None:
+            try:
+                _L.bl_mg_destroy(h)
+            except Exception:
+                pass
+            self._h = ctypes.c_void_p()
 
 
 def gsrb_sweeps(phi: MultiFab, f: MultiFab, h2: float, nsweeps: int, with_norms: bool = True, stream=None):

@@ -30,6 +30,8 @@ Plan::~Plan() {
   (void)hipFree(dfillrecs);
   (void)hipFree(dfillchunks);
   (void)hipFree(dvlin);
+  (void)hipFree(dcellpre);
+  (void)hipFree(dpairpre);
 }
 
 template <typename T>
@@ -52,6 +54,8 @@ bl_status upload_plan(Plan& p) {
   if ((st = upload(&p.dred, p.hred, "hipMalloc/hipMemcpy(reduction chunks)")) != BL_OK) return st;
   if ((st = upload(&p.dfillrecs, p.hfillrecs, "hipMalloc/hipMemcpy(fill records)")) != BL_OK) return st;
   if ((st = upload(&p.dfillchunks, p.hfillchunks, "hipMalloc/hipMemcpy(fill chunks)")) != BL_OK) return st;
+  if ((st = upload(&p.dcellpre, p.hcellpre, "hipMalloc/hipMemcpy(cell counts)")) != BL_OK) return st;
+  if ((st = upload(&p.dpairpre, p.hpairpre, "hipMalloc/hipMemcpy(pair counts)")) != BL_OK) return st;
   p.uploaded = true;
   return BL_OK;
 }
@@ -107,8 +111,9 @@ static bl_status get_plan(const bl_boxarray* ba, int ncomp, int ng, int dtype, b
 
 static int block_of(const Plan& p) { return 64 * p.cfg.waves; }
 
-// partial results of a reduction (one per reduction chunk)
-static size_t reduce_slots(const Plan& p) { return std::max(p.hred.size(), p.htiles.size()); }
+// partial results of a reduction or residual norm: one per reduction chunk,
+// tile or linear tile, whichever launch writes them
+static size_t reduce_slots(const Plan& p) { return std::max({p.hred.size(), p.htiles.size(), p.hlin.size()}); }
 
 static int persistent_grid(int persist) { return persist > 0 ? device_cu_count() * persist : 0; }
 
@@ -545,8 +550,8 @@ bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, do
   if (st != BL_OK) return st;
   if (!out_host) return fail(BL_EINVAL, "NULL output");
   const Plan& p = *phi->plan;
-  if ((st = ensure_scratch(phi, p.htiles.size() + 8, 8)) != BL_OK) return st;
-  double* dout = phi->dscratch + p.htiles.size();
+  if ((st = ensure_scratch(phi, reduce_slots(p) + 8, 8)) != BL_OK) return st;
+  double* dout = phi->dscratch + reduce_slots(p);
   const int grid = persistent_grid(tile_config().persist);
   if (gsrb_fused_ok(p, block_of(p))) {  // neighbour values straight from the neighbour boxes
     BL_HIP(launch_extract_mirror(p, phi->data, stream));
@@ -560,6 +565,43 @@ bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, do
   BL_HIP(hipStreamSynchronize(stream));
   *out_host = phi->hres[0];
   return BL_OK;
+}
+
+// nsweeps red-black sweeps of phi in place, no norms: the fused passes where the
+// plan allows them (edge mirror extracted first), else a fill before each colour.
+static hipError_t gsrb_smooth(const Plan& p, void* phi, const void* f, double h2, int nsweeps, hipStream_t stream) {
+  if (nsweeps <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+  if (gsrb_fused_ok(p, block_of(p))) {
+    const int grid = persistent_grid(tile_config().persist);
+    e = launch_extract_mirror(p, phi, stream);
+    for (int s = 0; s < nsweeps && e == hipSuccess; ++s) {
+      e = launch_gsrb_fused(p, phi, f, h2, 0, 0, nullptr, grid, block_of(p), stream);
+      if (e == hipSuccess) e = launch_gsrb_fused(p, phi, f, h2, 1, 1, nullptr, grid, block_of(p), stream);
+    }
+    return e;
+  }
+  for (int s = 0; s < nsweeps && e == hipSuccess; ++s)
+    for (int color = 0; color < 2 && e == hipSuccess; ++color) {
+      e = launch_fill(p, phi, 0, 1, stream);
+      if (e == hipSuccess) e = launch_gsrb(p, phi, f, h2, color, block_of(p), stream);
+    }
+  return e;
+}
+
+// ||f + L_h phi||_2 of the level into *out (device); partials needs
+// max(#linear tiles, #tiles) doubles.
+static hipError_t residual_norm_dev(const Plan& p, void* phi, const void* f, double h2, double* partials,
+                                    double* out, hipStream_t stream) {
+  hipError_t e;
+  if (gsrb_fused_ok(p, block_of(p))) {
+    const int grid = persistent_grid(tile_config().persist);
+    if ((e = launch_extract_mirror(p, phi, stream)) != hipSuccess) return e;
+    if ((e = launch_gsrb_fused(p, phi, f, h2, -1, 2, partials, grid, block_of(p), stream)) != hipSuccess) return e;
+    return launch_reduce_partials(partials, gsrb_fused_grid(p, grid), 1, out, stream);
+  }
+  if ((e = launch_fill(p, phi, 0, 1, stream)) != hipSuccess) return e;
+  return launch_residual(p, phi, f, h2, partials, out, block_of(p), stream);
 }
 
 bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int32_t nsweeps, double* resnorm_host,
@@ -613,6 +655,220 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
     BL_HIP(hipMemcpyAsync(phi->hres, phi->dscratch + nt, sizeof(double) * nsweeps, hipMemcpyDeviceToHost, stream));
     BL_HIP(hipStreamSynchronize(stream));
     std::memcpy(resnorm_host, phi->hres, sizeof(double) * nsweeps);
+  }
+  return BL_OK;
+}
+
+// ---------------------------------------------------------------- multigrid
+// fine and coarse: single-component MultiFabs of one dtype, coarse on the fine
+// BoxArray coarsened by 2 (box by box)
+static bl_status check_transfer(const bl_multifab* fine, const bl_multifab* coarse) {
+  if (!fine || !coarse) return fail(BL_EINVAL, "NULL MultiFab");
+  const Plan& F = *fine->plan;
+  const Plan& C = *coarse->plan;
+  if (F.dtype != C.dtype) return fail(BL_EDTYPE, "fine and coarse MultiFabs differ in dtype");
+  if (F.ncomp != 1 || C.ncomp != 1) return fail(BL_EINVAL, "the grid transfers act on single-component MultiFabs");
+  if (F.boxes.size() != C.boxes.size()) return fail(BL_ESHAPE, "coarse BoxArray has another number of boxes");
+  for (size_t b = 0; b < F.boxes.size(); ++b)
+    for (int d = 0; d < 3; ++d) {
+      const Box& fb = F.boxes[b];
+      const Box& cb = C.boxes[b];
+      if (fb.lo[d] % 2 || fb.len(d) % 2 || cb.lo[d] * 2 != fb.lo[d] || (cb.hi[d] + 1) * 2 != fb.hi[d] + 1)
+        return fail(BL_ESHAPE, "box %zu of the coarse BoxArray is not box %zu of the fine one coarsened by 2", b, b);
+    }
+  if (F.hpairpre.empty() || C.hcellpre.empty()) return fail(BL_EINVAL, "too many cells for the grid transfers");
+  return BL_OK;
+}
+
+bl_status bl_mg_restrict_residual(bl_multifab* phi, const bl_multifab* f, double h2, bl_multifab* fc,
+                                  hipStream_t stream) {
+  clear_error();
+  bl_status st = same_shape(phi, f);
+  if (st != BL_OK) return st;
+  if ((st = check_transfer(phi, fc)) != BL_OK) return st;
+  if (phi->plan->ng < 1) return fail(BL_EINVAL, "the residual needs nghost >= 1");
+  if (fc->data == phi->data || fc->data == f->data) return fail(BL_EINVAL, "fc shares storage with phi or f");
+  BL_HIP(launch_fill(*phi->plan, phi->data, 0, 1, stream));
+  BL_HIP(launch_restrict_residual(*phi->plan, *fc->plan, phi->data, f->data, fc->data, h2, stream));
+  return BL_OK;
+}
+
+bl_status bl_mg_prolong_add(bl_multifab* phi, const bl_multifab* pc, hipStream_t stream) {
+  clear_error();
+  bl_status st = check_transfer(phi, pc);
+  if (st != BL_OK) return st;
+  if (pc->data == phi->data) return fail(BL_EINVAL, "pc shares storage with phi");
+  BL_HIP(launch_prolong_add(*phi->plan, *pc->plan, phi->data, pc->data, stream));
+  return BL_OK;
+}
+
+}  // extern "C"
+
+struct bl_mg {
+  uint64_t ba_uid = 0;
+  int dtype = 0;
+  std::vector<bl_boxarray*> ba;     // levels 1..: owned coarse BoxArrays (ba[0] unused)
+  std::vector<bl_multifab*> phi, f; // levels 1..: in the caller's workspace (index 0 unused)
+  ~bl_mg() {
+    for (bl_multifab* m : phi) bl_multifab_destroy(m);
+    for (bl_multifab* m : f) bl_multifab_destroy(m);
+    for (bl_boxarray* b : ba) bl_boxarray_destroy(b);
+  }
+};
+
+namespace bl {
+// The coarse levels of ba: coarsened by 2 while every box and the domain have
+// even corners and extents and every periodic axis keeps an even extent, up to
+// max_levels levels in all.  levels[0] is left null (the caller's BoxArray).
+static bl_status mg_levels(const bl_boxarray* ba, int max_levels, std::vector<bl_boxarray*>* levels) {
+  levels->assign(1, nullptr);
+  const bl_boxarray* cur = ba;
+  while ((int)levels->size() < max_levels) {
+    bool ok = true;
+    auto even = [](const Box& b) {
+      for (int d = 0; d < 3; ++d)
+        if (b.lo[d] % 2 || b.len(d) % 2) return false;
+      return true;
+    };
+    ok = even(cur->domain);
+    for (size_t i = 0; ok && i < cur->boxes.size(); ++i) ok = even(cur->boxes[i]);
+    for (int d = 0; ok && d < 3; ++d)
+      if (cur->periodic[d] && (cur->domain.len(d) / 2) % 2) ok = false;
+    if (!ok) break;
+    bl_boxarray* c = nullptr;
+    bl_status st = bl_boxarray_coarsen(cur, 2, &c);
+    if (st != BL_OK) {
+      for (bl_boxarray* b : *levels) bl_boxarray_destroy(b);
+      levels->clear();
+      return st;
+    }
+    levels->push_back(c);
+    cur = c;
+  }
+  return BL_OK;
+}
+
+static size_t mg_round(size_t n) { return (n + 255) & ~(size_t)255; }
+}  // namespace bl
+
+extern "C" {
+
+bl_status bl_mg_workspace_bytes(const bl_boxarray* ba, bl_dtype dtype, int32_t max_levels, size_t* bytes,
+                                int32_t* nlevels) {
+  clear_error();
+  if (!ba || !bytes) return fail(BL_EINVAL, "NULL argument");
+  if (max_levels < 1) return fail(BL_EINVAL, "max_levels %d < 1", max_levels);
+  if (dtype != BL_F64 && dtype != BL_F32) return fail(BL_EDTYPE, "unknown dtype %d", (int)dtype);
+  std::vector<bl_boxarray*> lv;
+  bl_status st = mg_levels(ba, max_levels, &lv);
+  if (st != BL_OK) return st;
+  size_t total = 0;
+  for (size_t l = 1; l < lv.size() && st == BL_OK; ++l) {
+    size_t b = 0;
+    st = bl_multifab_bytes(lv[l], 1, 1, dtype, &b);
+    total += 2 * mg_round(b);
+  }
+  for (bl_boxarray* b : lv) bl_boxarray_destroy(b);
+  if (st != BL_OK) return st;
+  *bytes = total;
+  if (nlevels) *nlevels = (int32_t)lv.size();
+  return BL_OK;
+}
+
+bl_status bl_mg_create(const bl_boxarray* ba, bl_dtype dtype, int32_t max_levels, void* work_dev, size_t bytes,
+                       bl_mg** out) {
+  clear_error();
+  if (!ba || !out) return fail(BL_EINVAL, "NULL argument");
+  *out = nullptr;
+  size_t need = 0;
+  int32_t nl = 0;
+  bl_status st = bl_mg_workspace_bytes(ba, dtype, max_levels, &need, &nl);
+  if (st != BL_OK) return st;
+  if (need > 0 && !work_dev) return fail(BL_EINVAL, "NULL workspace");
+  if (((uintptr_t)work_dev) % 256 != 0) return fail(BL_EINVAL, "workspace is not 256-byte aligned");
+  if (bytes < need) return fail(BL_ENOMEM, "workspace of %zu bytes, the hierarchy needs %zu", bytes, need);
+  std::unique_ptr<bl_mg> mg(new (std::nothrow) bl_mg);
+  if (!mg) return fail(BL_ENOMEM, "host allocation");
+  mg->ba_uid = ba->uid;
+  mg->dtype = dtype;
+  if ((st = mg_levels(ba, max_levels, &mg->ba)) != BL_OK) return st;
+  mg->phi.assign(1, nullptr);
+  mg->f.assign(1, nullptr);
+  char* w = static_cast<char*>(work_dev);
+  for (size_t l = 1; l < mg->ba.size(); ++l) {
+    size_t b = 0;
+    if ((st = bl_multifab_bytes(mg->ba[l], 1, 1, dtype, &b)) != BL_OK) return st;
+    b = mg_round(b);
+    bl_multifab* p = nullptr;
+    bl_multifab* q = nullptr;
+    if ((st = bl_multifab_create(mg->ba[l], nullptr, 1, 1, dtype, w, b, &p)) != BL_OK) return st;
+    mg->phi.push_back(p);
+    if ((st = bl_multifab_create(mg->ba[l], nullptr, 1, 1, dtype, w + b, b, &q)) != BL_OK) return st;
+    mg->f.push_back(q);
+    w += 2 * b;
+  }
+  *out = mg.release();
+  return BL_OK;
+}
+
+bl_status bl_mg_levels(const bl_mg* mg, int32_t* nlevels) {
+  clear_error();
+  if (!mg || !nlevels) return fail(BL_EINVAL, "NULL argument");
+  *nlevels = (int32_t)mg->ba.size();
+  return BL_OK;
+}
+
+void bl_mg_destroy(bl_mg* mg) { delete mg; }
+
+}  // extern "C"
+
+namespace bl {
+// One V-cycle from level l (phi, f the level's MultiFabs, h2 its spacing squared).
+static bl_status vcycle(bl_mg* mg, size_t l, bl_multifab* phi, const bl_multifab* f, double h2, int nu1, int nu2,
+                        int nu_bottom, hipStream_t stream) {
+  const Plan& p = *phi->plan;
+  if (l + 1 == mg->ba.size()) {
+    BL_HIP(gsrb_smooth(p, phi->data, f->data, h2, nu_bottom, stream));
+    return BL_OK;
+  }
+  BL_HIP(gsrb_smooth(p, phi->data, f->data, h2, nu1, stream));
+  bl_multifab* pc = mg->phi[l + 1];
+  bl_multifab* fc = mg->f[l + 1];
+  BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
+  BL_HIP(launch_restrict_residual(p, *fc->plan, phi->data, f->data, fc->data, h2, stream));
+  BL_HIP(launch_set_val(*pc->plan, pc->data, 0.0, 0, 1, 1, 256, stream));
+  bl_status st = vcycle(mg, l + 1, pc, fc, 4.0 * h2, nu1, nu2, nu_bottom, stream);
+  if (st != BL_OK) return st;
+  BL_HIP(launch_prolong_add(p, *pc->plan, phi->data, pc->data, stream));
+  BL_HIP(gsrb_smooth(p, phi->data, f->data, h2, nu2, stream));
+  return BL_OK;
+}
+}  // namespace bl
+
+extern "C" {
+
+bl_status bl_mg_vcycles(bl_mg* mg, bl_multifab* phi, const bl_multifab* f, double h2, int32_t ncycles, int32_t nu1,
+                        int32_t nu2, int32_t nu_bottom, double* resnorm_host, hipStream_t stream) {
+  clear_error();
+  if (!mg) return fail(BL_EINVAL, "NULL hierarchy");
+  bl_status st = check_gsrb(phi, f);
+  if (st != BL_OK) return st;
+  if (phi->plan->ba_uid != mg->ba_uid) return fail(BL_ESHAPE, "phi lives on another BoxArray than the hierarchy");
+  if (phi->plan->dtype != mg->dtype) return fail(BL_EDTYPE, "phi's dtype differs from the hierarchy's");
+  if (phi->plan->ng != 1) return fail(BL_EINVAL, "the hierarchy's levels have one ghost layer; phi needs nghost 1");
+  if (ncycles < 0 || nu1 < 0 || nu2 < 0 || nu_bottom < 0) return fail(BL_EINVAL, "negative count");
+  const Plan& p = *phi->plan;
+  const size_t slots = reduce_slots(p) + 8;
+  if (resnorm_host && (st = ensure_scratch(phi, slots + (size_t)ncycles, (size_t)ncycles + 8)) != BL_OK) return st;
+  for (int c = 0; c < ncycles; ++c) {
+    if ((st = vcycle(mg, 0, phi, f, h2, nu1, nu2, nu_bottom, stream)) != BL_OK) return st;
+    if (resnorm_host)
+      BL_HIP(residual_norm_dev(p, phi->data, f->data, h2, phi->dscratch, phi->dscratch + slots + c, stream));
+  }
+  if (resnorm_host && ncycles > 0) {
+    BL_HIP(hipMemcpyAsync(phi->hres, phi->dscratch + slots, sizeof(double) * ncycles, hipMemcpyDeviceToHost, stream));
+    BL_HIP(hipStreamSynchronize(stream));
+    std::memcpy(resnorm_host, phi->hres, sizeof(double) * ncycles);
   }
   return BL_OK;
 }

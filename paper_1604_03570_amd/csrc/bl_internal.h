@@ -288,6 +288,8 @@ struct Plan {
   std::vector<DevRedChunk> hred;          // reduction chunks
   int yhmax = 1;                          // most halo row vectors (nzs * min(nvx, nq)) of a linear tile
   int xhmax = 1;                          // most halo row ends (nzs * nrows) of a linear tile
+  std::vector<int32_t> hcellpre;         // flattened valid cells: box b holds [hcellpre[b], hcellpre[b+1])
+  std::vector<int32_t> hpairpre;         // the same in pairs of x cells (boxes of even x extent)
   std::vector<DevFillRec> hfillrecs;
   std::vector<DevFillChunk> hfillchunks;
   std::shared_ptr<const std::vector<FillRecord>> fill;
@@ -300,6 +302,8 @@ struct Plan {
   DevRedChunk* dred = nullptr;
   DevFillRec* dfillrecs = nullptr;
   DevFillChunk* dfillchunks = nullptr;
+  int32_t* dcellpre = nullptr;
+  int32_t* dpairpre = nullptr;
   bool uploaded = false;
   TileConfig cfg;
 

@@ -872,6 +872,95 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
   }
 }
 
+// ---------------------------------------------------------------- multigrid grid transfers
+// Both kernels run over the flattened cells of a level: item g belongs to the
+// box b with pre[b] <= g < pre[b+1], so a workgroup spans as many boxes as it
+// needs and a level of many tiny boxes still fills whole workgroups.
+__device__ __forceinline__ int box_of_item(const int32_t* __restrict__ pre, int nbox, int g) {
+  int lo = 0, hi = nbox - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Restriction of the residual (refinement ratio 2): one thread per coarse cell
+// (I, J, K) of coarse box b (fine box b coarsened).  Its 8 fine cells are the
+// x pair 2I, 2I+1 of rows 2J+b', planes 2K+c; each one's residual
+// r = f + (s - 6 phi) / h2 is taken in FP64 from promoted values, summed in the
+// order c, b', then x (lower first), and the sum times 1/8 is stored.  phi's
+// ghosts must be filled (x neighbours at box faces come from the x ghost slab).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_restrict_residual(const int32_t* __restrict__ cpre, int nbox, int total, const DevBox* __restrict__ fboxes,
+                        const DevBox* __restrict__ cboxes, const T* phi_, const T* f_, T* fc_, double h2) {
+  const int g = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (g >= total) return;
+  const int b = box_of_item(cpre, nbox, g);
+  const DevBox F = fboxes[b];
+  const DevBox C = cboxes[b];
+  int q = g - cpre[b];
+  const int I = q % C.ex;
+  q /= C.ex;
+  const int J = q % C.ey, K = q / C.ey;
+  const BL_GLOBAL T* __restrict__ phi = as_global(phi_);
+  const BL_GLOBAL T* __restrict__ f = as_global(f_);
+  const int x0 = 2 * I;
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      const int y = 2 * J + bb, z = 2 * K + c;
+      const int64_t row = F.off + (int64_t)y * F.sy + (int64_t)z * F.sz;
+      const Vec<T, 2> ctr = ldv<T, 2>(phi + row + x0);
+      const Vec<T, 2> ym = ldv<T, 2>(phi + row - F.sy + x0);
+      const Vec<T, 2> yp = ldv<T, 2>(phi + row + F.sy + x0);
+      const Vec<T, 2> zm = ldv<T, 2>(phi + row - F.sz + x0);
+      const Vec<T, 2> zp = ldv<T, 2>(phi + row + F.sz + x0);
+      const Vec<T, 2> fv = ldv<T, 2>(f + row + x0);
+      const int64_t slab = F.xs + (int64_t)z * F.xs_z + (int64_t)y * F.ng;
+      const double left = (double)(x0 == 0 ? phi[slab] : phi[row + x0 - 1]);
+      const double right = (double)(x0 + 2 == F.ex ? phi[slab + F.xs_side] : phi[row + x0 + 2]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const double xm = a == 0 ? left : (double)ctr.v[0];
+        const double xp = a == 0 ? (double)ctr.v[1] : right;
+        const double sv = ((xm + xp) + ((double)ym.v[a] + (double)yp.v[a])) + ((double)zm.v[a] + (double)zp.v[a]);
+        const double r = (double)fv.v[a] + (sv - 6.0 * (double)ctr.v[a]) / h2;
+        acc = (c == 0 && bb == 0 && a == 0) ? r : acc + r;
+      }
+    }
+  }
+  as_global(fc_)[C.off + I + (int64_t)J * C.sy + (int64_t)K * C.sz] = (T)(acc * 0.125);
+}
+
+// Prolongation, piecewise constant: one thread per x pair (2i', 2i'+1) of a fine
+// row; both cells add the value of their coarse cell (i', y/2, z/2) of box b.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_prolong_add(const int32_t* __restrict__ ppre, int nbox, int total, const DevBox* __restrict__ fboxes,
+                  const DevBox* __restrict__ cboxes, T* phi_, const T* pc_) {
+  const int g = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (g >= total) return;
+  const int b = box_of_item(ppre, nbox, g);
+  const DevBox F = fboxes[b];
+  const DevBox C = cboxes[b];
+  int q = g - ppre[b];
+  const int npx = F.ex >> 1;
+  const int ip = q % npx;
+  q /= npx;
+  const int y = q % F.ey, z = q / F.ey;
+  const T v = as_global(pc_)[C.off + ip + (int64_t)(y >> 1) * C.sy + (int64_t)(z >> 1) * C.sz];
+  BL_GLOBAL T* p = as_global(phi_) + F.off + 2 * ip + (int64_t)y * F.sy + (int64_t)z * F.sz;
+  Vec<T, 2> w = ldv<T, 2>(p);
+  w.v[0] = w.v[0] + v;
+  w.v[1] = w.v[1] + v;
+  stv<T, 2>(p, w);
+}
+
 __device__ double block_reduce(double v, int op);
 
 // GSRB colour pass, fused with the ghost fill (neighbour boxes read through the
@@ -1611,6 +1700,33 @@ hipError_t launch_heat_varcoef(int dtype, int vec, const VcArgs& a, hipStream_t 
   if (a.nlin <= 0) return hipSuccess;
   if (dtype == BL_F64) return vec == 2 ? vc_v<double, 2>(a, s) : vc_v<double, 1>(a, s);
   return vec == 4 ? vc_v<float, 4>(a, s) : vc_v<float, 1>(a, s);
+}
+
+hipError_t launch_restrict_residual(const Plan& fine, const Plan& coarse, const void* phi, const void* f, void* fc,
+                                    double h2, hipStream_t s) {
+  const int total = coarse.hcellpre.empty() ? 0 : coarse.hcellpre.back();
+  if (total <= 0) return hipSuccess;
+  const int nb = (int)coarse.hboxes.size(), g = (total + 255) / 256;
+  if (fine.dtype == BL_F64)
+    hipLaunchKernelGGL(k_restrict_residual<double>, dim3(g), dim3(256), 0, s, coarse.dcellpre, nb, total, fine.dboxes,
+                       coarse.dboxes, (const double*)phi, (const double*)f, (double*)fc, h2);
+  else
+    hipLaunchKernelGGL(k_restrict_residual<float>, dim3(g), dim3(256), 0, s, coarse.dcellpre, nb, total, fine.dboxes,
+                       coarse.dboxes, (const float*)phi, (const float*)f, (float*)fc, h2);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong_add(const Plan& fine, const Plan& coarse, void* phi, const void* pc, hipStream_t s) {
+  const int total = fine.hpairpre.empty() ? 0 : fine.hpairpre.back();
+  if (total <= 0) return hipSuccess;
+  const int nb = (int)fine.hboxes.size(), g = (total + 255) / 256;
+  if (fine.dtype == BL_F64)
+    hipLaunchKernelGGL(k_prolong_add<double>, dim3(g), dim3(256), 0, s, fine.dpairpre, nb, total, fine.dboxes,
+                       coarse.dboxes, (double*)phi, (const double*)pc);
+  else
+    hipLaunchKernelGGL(k_prolong_add<float>, dim3(g), dim3(256), 0, s, fine.dpairpre, nb, total, fine.dboxes,
+                       coarse.dboxes, (float*)phi, (const float*)pc);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(const double* partials, int n, int take_sqrt, double* out, hipStream_t s) {

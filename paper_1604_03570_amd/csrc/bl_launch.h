@@ -87,6 +87,14 @@ struct VcArgs {
 size_t vc_lds_half(int dtype, int vec, int zchunk, int yhmax, int xhmax, int block);
 hipError_t launch_heat_varcoef(int dtype, int vec, const VcArgs& a, hipStream_t s);
 
+// Multigrid transfers between a level and its coarsening by 2 (box b of
+// `coarse` is box b of `fine` coarsened; every fine box has even lo and
+// extents).  Restriction: fc = mean of the 8 fine residuals f + L_h phi of each
+// coarse cell (phi's ghosts filled).  Prolongation: phi += parent value.
+hipError_t launch_restrict_residual(const Plan& fine, const Plan& coarse, const void* phi, const void* f, void* fc,
+                                    double h2, hipStream_t s);
+hipError_t launch_prolong_add(const Plan& fine, const Plan& coarse, void* phi, const void* pc, hipStream_t s);
+
 int device_cu_count();
 
 }  // namespace bl

@@ -146,6 +146,26 @@ bl_status bl_boxarray_create(const bl_box* boxes, int32_t nboxes, const bl_box* 
   return make_boxarray(std::move(v), from_c(*domain), periodic, out);
 }
 
+bl_status bl_boxarray_coarsen(const bl_boxarray* ba, int32_t ratio, bl_boxarray** out) {
+  clear_error();
+  if (!ba || !out) return fail(BL_EINVAL, "NULL argument");
+  if (ratio < 1) return fail(BL_EINVAL, "ratio %d < 1", ratio);
+  auto coarsen = [ratio](const Box& b, Box& c) {
+    for (int d = 0; d < 3; ++d) {
+      if (b.lo[d] % ratio != 0 || b.len(d) % ratio != 0) return false;
+      c.lo[d] = b.lo[d] / ratio;
+      c.hi[d] = (b.hi[d] + 1) / ratio - 1;
+    }
+    return true;
+  };
+  Box dom{};
+  if (!coarsen(ba->domain, dom)) return fail(BL_EINVAL, "the domain's corner or extent is not divisible by %d", ratio);
+  std::vector<Box> v(ba->boxes.size());
+  for (size_t i = 0; i < v.size(); ++i)
+    if (!coarsen(ba->boxes[i], v[i])) return fail(BL_EINVAL, "box %zu's corner or extent is not divisible by %d", i, ratio);
+  return make_boxarray(std::move(v), dom, ba->periodic, out);
+}
+
 bl_status bl_boxarray_chop(const bl_box* domain, const int32_t periodic[3], const int32_t max_edge[3],
                            bl_boxarray** out) {
   clear_error();
@@ -732,6 +752,23 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
   for (const DevTile& t : p->htiles) {
     p->rmax = std::max<int>(p->rmax, t.rows);
     p->nvtmax = std::max<int>(p->nvtmax, t.nvt);
+  }
+  // flattened cell and x-pair counts (grid transfers between multigrid levels)
+  {
+    int64_t nc = 0, np2 = 0;
+    p->hcellpre.assign(1, 0);
+    p->hpairpre.assign(1, 0);
+    for (const DevBox& B : p->hboxes) {
+      nc += (int64_t)B.ex * B.ey * B.ez;
+      np2 += (int64_t)(B.ex / 2) * B.ey * B.ez;
+      if (nc > INT32_MAX) {  // too large for the grid transfers, which then refuse this shape
+        p->hcellpre.clear();
+        p->hpairpre.clear();
+        break;
+      }
+      p->hcellpre.push_back((int32_t)nc);
+      p->hpairpre.push_back((int32_t)np2);
+    }
   }
   // reduction chunks of about 32K values
   for (int b = 0; b < (int)p->hboxes.size(); ++b) {

@@ -167,3 +167,31 @@ def test_384cube_gsrb_at_full_size(bt):
     say(f"384^3 gsrb: fp32 field rel err {ferr:.2e}, norm rel err {nerr:.2e}, norms {n64[0]:.4e} -> {n64[-1]:.4e}")
     assert ferr <= 1e-5 and nerr <= 1e-5
     assert all(y < x for x, y in zip(n64, n64[1:]))
+
+
+def test_256cube_vcycles_at_full_size(bt):
+    """256^3 periodic, 64 boxes of 64^3, FP64, zero-mean f: 7 levels down to 64 boxes of
+    one cell; after one V(2,2) cycle the field equals the oracle's bit for bit; four
+    more cycles cut the residual by 10^4."""
+    n = 256
+    dom = I.domain_box(n)
+    boxes = I.regular_chop(dom, 64)
+    ba = bt.BoxArray.from_boxes(boxes, dom)
+    f = I.zero_mean_normal_f32(n, seed=0)
+    h2 = (1.0 / n) ** 2
+    phi, fm = bt.MultiFab(ba, 1, 1, bt.F64), bt.MultiFab(ba, 1, 1, bt.F64)
+    phi.set_val(0.0, with_ghosts=True)
+    fm.set_val(0.0, with_ghosts=True)
+    fm.from_global(f)
+    mg = bt.Multigrid(ba, bt.F64)
+    assert mg.nlevels == 7
+    n1 = mg.vcycles(phi, fm, h2, 1)
+    ophi, ofm = O.OracleMultiFab(boxes, dom, (1, 1, 1), 1, 1), O.OracleMultiFab(boxes, dom, (1, 1, 1), 1, 1)
+    ofm.load_global(f)
+    on = O.mg_vcycles(ophi, ofm, h2, 1)
+    assert np.array_equal(phi.to_global().cpu().numpy(), ophi.to_global())
+    assert abs(n1[0] - on[0]) <= 1e-13 * on[0]
+    del ophi, ofm
+    more = mg.vcycles(phi, fm, h2, 4)
+    say(f"256^3 vcycles: norms {n1[0]:.4e} then {[f'{x:.3e}' for x in more]}")
+    assert more[-1] <= 1e-4 * n1[0]
