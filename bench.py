@@ -293,6 +293,43 @@ def varcoef_run(bt, I, torch, boxes, dom, u0, ncomp: int, seed: int, steps: int)
     return out
 
 
+def mg_run(bt, I, torch, seed: int, cycles: int = 5) -> dict:
+    """Multigrid V(2,2) cycles for -Lap(phi) = f on GSRB's level (384^3 periodic, 216 boxes
+    of 64^3, f as there): 7 levels down to 216 boxes of one cell, 8 bottom sweeps.  FP64 and
+    FP32 state; time per cycle and the residual's mean reduction per cycle."""
+    n = 384
+    dom = I.domain_box(n)
+    ba = bt.BoxArray.from_boxes(I.regular_chop(dom, 64), dom)
+    f = I.zero_mean_normal_f32(n, seed=seed)
+    h2 = (1.0 / n) ** 2
+    out = {"workload": f"{n}^3 periodic, 216 boxes of 64^3, V(2,2), 8 bottom sweeps, {cycles} cycles"}
+    for name, dt in (("f64", bt.F64), ("f32", bt.F32)):
+        phi, fm = bt.MultiFab(ba, 1, 1, dt), bt.MultiFab(ba, 1, 1, dt)
+        fm.set_val(0.0, with_ghosts=True)
+        fm.from_global(f)
+        mg = bt.Multigrid(ba, dt)
+        phi.set_val(0.0, with_ghosts=True)
+        r0 = bt.residual_norm(phi, fm, h2)
+        mg.vcycles(phi, fm, h2, 1, with_norms=False)  # warm-up
+        phi.set_val(0.0, with_ghosts=True)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        mg.vcycles(phi, fm, h2, cycles, with_norms=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / cycles
+        rn = bt.residual_norm(phi, fm, h2)
+        out[name] = {"levels": mg.nlevels, "ms_per_vcycle": round(ms, 4), "resnorm_0": r0,
+                     f"resnorm_after_{cycles}": rn, "mean_reduction_per_cycle": (rn / r0) ** (1.0 / cycles)}
+        log(f"mg {name}: {mg.nlevels} levels, {ms:.3f} ms per V-cycle, residual {r0:.3e} -> {rn:.3e}")
+        del phi, fm, mg
+    del f
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,6 +348,7 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
     ap.add_argument("--no-gsrb", action="store_true", help="skip the GSRB smoother run")
     ap.add_argument("--no-varcoef", action="store_true", help="skip the variable-coefficient flux-form run")
+    ap.add_argument("--no-mg", action="store_true", help="skip the multigrid V-cycle run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three plain device copies of 2 GiB (reference for HBM byte counters)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -474,6 +512,9 @@ def main() -> int:
 
     if not args.no_extra and not args.no_gsrb:
         extra["gsrb"] = gsrb_run(bt, I, torch, args.seed)
+
+    if not args.no_extra and not args.no_mg:
+        extra["mg"] = mg_run(bt, I, torch, args.seed)
 
     if not args.no_extra and not args.no_serve:
         # serving: 2000 independent periodic heat problems, Poisson arrivals at 200/s,

@@ -32,6 +32,8 @@ Plan::~Plan() {
   (void)hipFree(dvlin);
   (void)hipFree(dcellpre);
   (void)hipFree(dpairpre);
+  (void)hipFree(dcellwg);
+  (void)hipFree(dpairwg);
 }
 
 template <typename T>
@@ -56,6 +58,8 @@ bl_status upload_plan(Plan& p) {
   if ((st = upload(&p.dfillchunks, p.hfillchunks, "hipMalloc/hipMemcpy(fill chunks)")) != BL_OK) return st;
   if ((st = upload(&p.dcellpre, p.hcellpre, "hipMalloc/hipMemcpy(cell counts)")) != BL_OK) return st;
   if ((st = upload(&p.dpairpre, p.hpairpre, "hipMalloc/hipMemcpy(pair counts)")) != BL_OK) return st;
+  if ((st = upload(&p.dcellwg, p.hcellwg, "hipMalloc/hipMemcpy(cell workgroups)")) != BL_OK) return st;
+  if ((st = upload(&p.dpairwg, p.hpairwg, "hipMalloc/hipMemcpy(pair workgroups)")) != BL_OK) return st;
   p.uploaded = true;
   return BL_OK;
 }

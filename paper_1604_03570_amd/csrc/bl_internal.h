@@ -234,6 +234,8 @@ struct DevFillChunk {
 };
 constexpr int kFillChunk = 256;
 constexpr int kStencilMaxThreads = 256;  // workgroup size limit of the stencil kernels (waves <= 4)
+constexpr int kRestrictPerWG = 256;     // coarse cells per workgroup of the restriction (one per lane)
+constexpr int kProlongPerWG = 1024;     // x pairs per workgroup of the prolongation (four per lane)
 constexpr size_t kDmaLdsMax = 65536;     // LDS of one workgroup of the halo-in-LDS stencil form, at most
 
 // ---------------------------------------------------------------- layout + plans
@@ -290,6 +292,8 @@ struct Plan {
   int xhmax = 1;                          // most halo row ends (nzs * nrows) of a linear tile
   std::vector<int32_t> hcellpre;         // flattened valid cells: box b holds [hcellpre[b], hcellpre[b+1])
   std::vector<int32_t> hpairpre;         // the same in pairs of x cells (boxes of even x extent)
+  std::vector<int32_t> hcellwg;          // first box of each workgroup of kRestrictPerWG cells
+  std::vector<int32_t> hpairwg;          // first box of each workgroup of kProlongPerWG pairs
   std::vector<DevFillRec> hfillrecs;
   std::vector<DevFillChunk> hfillchunks;
   std::shared_ptr<const std::vector<FillRecord>> fill;
@@ -304,6 +308,8 @@ struct Plan {
   DevFillChunk* dfillchunks = nullptr;
   int32_t* dcellpre = nullptr;
   int32_t* dpairpre = nullptr;
+  int32_t* dcellwg = nullptr;
+  int32_t* dpairwg = nullptr;
   bool uploaded = false;
   TileConfig cfg;
 

@@ -873,11 +873,14 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
 }
 
 // ---------------------------------------------------------------- multigrid grid transfers
-// Both kernels run over the flattened cells of a level: item g belongs to the
-// box b with pre[b] <= g < pre[b+1], so a workgroup spans as many boxes as it
-// needs and a level of many tiny boxes still fills whole workgroups.
-__device__ __forceinline__ int box_of_item(const int32_t* __restrict__ pre, int nbox, int g) {
-  int lo = 0, hi = nbox - 1;
+// Both kernels run over the flattened items of a level (coarse cells, or x
+// pairs of fine cells): item g belongs to the box b with pre[b] <= g <
+// pre[b+1].  Workgroup w takes items [w*per, (w+1)*per) and wgbox[w] is the box
+// of its first item.  A workgroup inside one box (every workgroup of a level of
+// large boxes) reads that box's descriptors as scalars; one that spans boxes
+// (tiny boxes near the bottom of a V-cycle) finds each item's box by bisection
+// from wgbox[w], so a level of many tiny boxes still fills whole workgroups.
+__device__ __forceinline__ int box_of_item(const int32_t* __restrict__ pre, int lo, int hi, int g) {
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (pre[mid] <= g) lo = mid;
@@ -886,27 +889,19 @@ __device__ __forceinline__ int box_of_item(const int32_t* __restrict__ pre, int 
   return lo;
 }
 
-// Restriction of the residual (refinement ratio 2): one thread per coarse cell
-// (I, J, K) of coarse box b (fine box b coarsened).  Its 8 fine cells are the
-// x pair 2I, 2I+1 of rows 2J+b', planes 2K+c; each one's residual
-// r = f + (s - 6 phi) / h2 is taken in FP64 from promoted values, summed in the
-// order c, b', then x (lower first), and the sum times 1/8 is stored.  phi's
-// ghosts must be filled (x neighbours at box faces come from the x ghost slab).
+// Restriction of the residual of one coarse cell (I, J, K) (refinement ratio 2):
+// its 8 fine cells are the x pair 2I, 2I+1 of rows 2J+b', planes 2K+c; each one's
+// residual r = f + (s - 6 phi) / h2 is taken in FP64 from promoted values,
+// summed in the order c, b', then x (lower first), and the sum times 1/8 is
+// stored.  phi's ghosts must be filled (x neighbours at box faces come from the
+// x ghost slab).
 template <typename T>
-__global__ void __launch_bounds__(256)
-    k_restrict_residual(const int32_t* __restrict__ cpre, int nbox, int total, const DevBox* __restrict__ fboxes,
-                        const DevBox* __restrict__ cboxes, const T* phi_, const T* f_, T* fc_, double h2) {
-  const int g = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (g >= total) return;
-  const int b = box_of_item(cpre, nbox, g);
-  const DevBox F = fboxes[b];
-  const DevBox C = cboxes[b];
-  int q = g - cpre[b];
+__device__ __forceinline__ void restrict_cell(const DevBox& F, const DevBox& C, int q,
+                                              const BL_GLOBAL T* __restrict__ phi, const BL_GLOBAL T* __restrict__ f,
+                                              BL_GLOBAL T* __restrict__ fc, double h2) {
   const int I = q % C.ex;
   q /= C.ex;
   const int J = q % C.ey, K = q / C.ey;
-  const BL_GLOBAL T* __restrict__ phi = as_global(phi_);
-  const BL_GLOBAL T* __restrict__ f = as_global(f_);
   const int x0 = 2 * I;
   double acc = 0.0;
 #pragma unroll
@@ -934,31 +929,73 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  as_global(fc_)[C.off + I + (int64_t)J * C.sy + (int64_t)K * C.sz] = (T)(acc * 0.125);
+  fc[C.off + I + (int64_t)J * C.sy + (int64_t)K * C.sz] = (T)(acc * 0.125);
 }
 
-// Prolongation, piecewise constant: one thread per x pair (2i', 2i'+1) of a fine
-// row; both cells add the value of their coarse cell (i', y/2, z/2) of box b.
+// One lane per coarse cell, kRestrictPerWG cells per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(kRestrictPerWG)
+    k_restrict_residual(const int32_t* __restrict__ cpre, const int32_t* __restrict__ wgbox, int nbox, int total,
+                        const DevBox* __restrict__ fboxes, const DevBox* __restrict__ cboxes, const T* phi_,
+                        const T* f_, T* fc_, double h2) {
+  const BL_GLOBAL T* __restrict__ phi = as_global(phi_);
+  const BL_GLOBAL T* __restrict__ f = as_global(f_);
+  BL_GLOBAL T* __restrict__ fc = as_global(fc_);
+  const int g0 = (int)blockIdx.x * kRestrictPerWG;
+  const int end = g0 + kRestrictPerWG < total ? g0 + kRestrictPerWG : total;
+  const int b0 = ldc(wgbox + blockIdx.x);
+  const int g = g0 + (int)threadIdx.x;
+  if (ldc(cpre + b0 + 1) >= end) {  // the whole workgroup in box b0
+    if (g < end) restrict_cell<T>(ldc(fboxes + b0), ldc(cboxes + b0), g - ldc(cpre + b0), phi, f, fc, h2);
+  } else if (g < end) {
+    const int b = box_of_item(cpre, b0, nbox - 1, g);
+    restrict_cell<T>(fboxes[b], cboxes[b], g - cpre[b], phi, f, fc, h2);
+  }
+}
+
+// Prolongation, piecewise constant: an item is an x pair (2i', 2i'+1) of a fine
+// row (y, z); both cells add the value of their coarse cell (i', y/2, z/2).
+// Four items per lane (lanes, then lanes + blockDim, ...), all loads first.
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_prolong_add(const int32_t* __restrict__ ppre, int nbox, int total, const DevBox* __restrict__ fboxes,
-                  const DevBox* __restrict__ cboxes, T* phi_, const T* pc_) {
-  const int g = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (g >= total) return;
-  const int b = box_of_item(ppre, nbox, g);
-  const DevBox F = fboxes[b];
-  const DevBox C = cboxes[b];
-  int q = g - ppre[b];
-  const int npx = F.ex >> 1;
-  const int ip = q % npx;
-  q /= npx;
-  const int y = q % F.ey, z = q / F.ey;
-  const T v = as_global(pc_)[C.off + ip + (int64_t)(y >> 1) * C.sy + (int64_t)(z >> 1) * C.sz];
-  BL_GLOBAL T* p = as_global(phi_) + F.off + 2 * ip + (int64_t)y * F.sy + (int64_t)z * F.sz;
-  Vec<T, 2> w = ldv<T, 2>(p);
-  w.v[0] = w.v[0] + v;
-  w.v[1] = w.v[1] + v;
-  stv<T, 2>(p, w);
+    k_prolong_add(const int32_t* __restrict__ ppre, const int32_t* __restrict__ wgbox, int nbox, int total,
+                  const DevBox* __restrict__ fboxes, const DevBox* __restrict__ cboxes, T* phi_, const T* pc_) {
+  constexpr int K = kProlongPerWG / 256;
+  BL_GLOBAL T* __restrict__ phi = as_global(phi_);
+  const BL_GLOBAL T* __restrict__ pc = as_global(pc_);
+  const int g0 = (int)blockIdx.x * kProlongPerWG;
+  const int end = g0 + kProlongPerWG < total ? g0 + kProlongPerWG : total;
+  const int b0 = ldc(wgbox + blockIdx.x);
+  const bool one_box = ldc(ppre + b0 + 1) >= end;
+  int64_t at[K];
+  T v[K];
+  Vec<T, 2> w[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int g = g0 + k * 256 + (int)threadIdx.x;
+    at[k] = -1;
+    if (g >= end) continue;
+    int b = b0;
+    if (!one_box) b = box_of_item(ppre, b0, nbox - 1, g);
+    const DevBox F = one_box ? ldc(fboxes + b0) : fboxes[b];
+    const DevBox C = one_box ? ldc(cboxes + b0) : cboxes[b];
+    int q = g - (one_box ? ldc(ppre + b0) : ppre[b]);
+    const int npx = F.ex >> 1;
+    const int ip = q % npx;
+    q /= npx;
+    const int y = q % F.ey, z = q / F.ey;
+    v[k] = pc[C.off + ip + (int64_t)(y >> 1) * C.sy + (int64_t)(z >> 1) * C.sz];
+    at[k] = F.off + 2 * ip + (int64_t)y * F.sy + (int64_t)z * F.sz;
+    w[k] = ldv<T, 2>(phi + at[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (at[k] < 0) continue;
+    Vec<T, 2> o;
+    o.v[0] = w[k].v[0] + v[k];
+    o.v[1] = w[k].v[1] + v[k];
+    stv<T, 2>(phi + at[k], o);
+  }
 }
 
 __device__ double block_reduce(double v, int op);
@@ -1706,26 +1743,28 @@ hipError_t launch_restrict_residual(const Plan& fine, const Plan& coarse, const 
                                     double h2, hipStream_t s) {
   const int total = coarse.hcellpre.empty() ? 0 : coarse.hcellpre.back();
   if (total <= 0) return hipSuccess;
-  const int nb = (int)coarse.hboxes.size(), g = (total + 255) / 256;
+  const int nb = (int)coarse.hboxes.size(), g = (int)coarse.hcellwg.size();
   if (fine.dtype == BL_F64)
-    hipLaunchKernelGGL(k_restrict_residual<double>, dim3(g), dim3(256), 0, s, coarse.dcellpre, nb, total, fine.dboxes,
-                       coarse.dboxes, (const double*)phi, (const double*)f, (double*)fc, h2);
+    hipLaunchKernelGGL(k_restrict_residual<double>, dim3(g), dim3(kRestrictPerWG), 0, s, coarse.dcellpre,
+                       coarse.dcellwg, nb, total, fine.dboxes, coarse.dboxes, (const double*)phi, (const double*)f,
+                       (double*)fc, h2);
   else
-    hipLaunchKernelGGL(k_restrict_residual<float>, dim3(g), dim3(256), 0, s, coarse.dcellpre, nb, total, fine.dboxes,
-                       coarse.dboxes, (const float*)phi, (const float*)f, (float*)fc, h2);
+    hipLaunchKernelGGL(k_restrict_residual<float>, dim3(g), dim3(kRestrictPerWG), 0, s, coarse.dcellpre,
+                       coarse.dcellwg, nb, total, fine.dboxes, coarse.dboxes, (const float*)phi, (const float*)f,
+                       (float*)fc, h2);
   return hipGetLastError();
 }
 
 hipError_t launch_prolong_add(const Plan& fine, const Plan& coarse, void* phi, const void* pc, hipStream_t s) {
   const int total = fine.hpairpre.empty() ? 0 : fine.hpairpre.back();
   if (total <= 0) return hipSuccess;
-  const int nb = (int)fine.hboxes.size(), g = (total + 255) / 256;
+  const int nb = (int)fine.hboxes.size(), g = (int)fine.hpairwg.size();
   if (fine.dtype == BL_F64)
-    hipLaunchKernelGGL(k_prolong_add<double>, dim3(g), dim3(256), 0, s, fine.dpairpre, nb, total, fine.dboxes,
-                       coarse.dboxes, (double*)phi, (const double*)pc);
+    hipLaunchKernelGGL(k_prolong_add<double>, dim3(g), dim3(256), 0, s, fine.dpairpre, fine.dpairwg, nb, total,
+                       fine.dboxes, coarse.dboxes, (double*)phi, (const double*)pc);
   else
-    hipLaunchKernelGGL(k_prolong_add<float>, dim3(g), dim3(256), 0, s, fine.dpairpre, nb, total, fine.dboxes,
-                       coarse.dboxes, (float*)phi, (const float*)pc);
+    hipLaunchKernelGGL(k_prolong_add<float>, dim3(g), dim3(256), 0, s, fine.dpairpre, fine.dpairwg, nb, total,
+                       fine.dboxes, coarse.dboxes, (float*)phi, (const float*)pc);
   return hipGetLastError();
 }
 

@@ -769,6 +769,18 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
       p->hcellpre.push_back((int32_t)nc);
       p->hpairpre.push_back((int32_t)np2);
     }
+    // the box holding the first item of each workgroup
+    auto first_boxes = [](const std::vector<int32_t>& pre, int per, std::vector<int32_t>& out) {
+      out.clear();
+      if (pre.empty()) return;
+      size_t b = 0;
+      for (int64_t g = 0; g < pre.back(); g += per) {
+        while (pre[b + 1] <= g) ++b;
+        out.push_back((int32_t)b);
+      }
+    };
+    first_boxes(p->hcellpre, kRestrictPerWG, p->hcellwg);
+    first_boxes(p->hpairpre, kProlongPerWG, p->hpairwg);
   }
   // reduction chunks of about 32K values
   for (int b = 0; b < (int)p->hboxes.size(); ++b) {
