@@ -82,6 +82,8 @@ def _configure(L):
     L.orc_restrict_residual.restype = None
     L.orc_prolong_add.argtypes = [ctypes.c_int, _ip, _ip, ctypes.c_int, _dp, _i64p, _dp, _i64p]
     L.orc_prolong_add.restype = None
+    L.orc_heat8_step.argtypes = [ctypes.c_int, _ip, ctypes.c_int, ctypes.c_int, _dp, _dp, _i64p, ctypes.c_double]
+    L.orc_heat8_step.restype = None
     L.orc_heat_window.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_double]
     L.orc_heat_window.restype = ctypes.c_double
     return L
@@ -296,6 +298,49 @@ def heat_advance(u: OracleMultiFab, nsteps: int, c: float) -> OracleMultiFab:
         heat_step(a, b, c)
         a, b = b, a
     return a
+
+
+# -- the 8th-order heat step (9-cell span, ng >= 4) ------------------------------------
+H8_COEF = (-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0)  # centre, then m = 1..4
+
+
+def heat8_step(u_old: OracleMultiFab, u_new: OracleMultiFab, c: float) -> None:
+    """FillBoundary(u_old), then the 8th-order step on every valid cell (needs ng >= 4)."""
+    _same_layout(u_old, u_new)
+    if u_old.ng < 4:
+        raise ValueError("the 8th-order stencil needs 4 ghost layers")
+    u_old.fill_boundary()
+    lib().orc_heat8_step(u_old.nbox, _ptr(u_old.boxes, _ip), u_old.ng, u_old.ncomp, _ptr(u_old.data, _dp),
+                         _ptr(u_new.data, _dp), _ptr(u_old.fab_off, _i64p), c)
+
+
+def heat8_advance(u: OracleMultiFab, nsteps: int, c: float) -> OracleMultiFab:
+    a, b = u, u.copy()
+    for _ in range(nsteps):
+        heat8_step(a, b, c)
+        a, b = b, a
+    return a
+
+
+def heat8_window(u0_global: np.ndarray, center, nsteps: int, c: float) -> float:
+    """Value at global cell ``center`` after nsteps 8th-order steps of a fully periodic,
+    fully covered single component (Nz, Ny, Nx) array: the cube of half-width 4*nsteps
+    around the cell (periodic wrap) as the one box of a non-periodic domain whose 4 ghost
+    layers hold the wrapped neighbours and stay fixed.  A fixed ghost first changes a
+    result in step 2 and moves in 4 cells per step, so the centre is exact."""
+    i, j, k = center
+    n = int(nsteps)
+    Nz, Ny, Nx = u0_global.shape
+    h = 4 * n + 4
+    ix = np.arange(i - h, i + h + 1) % Nx
+    iy = np.arange(j - h, j + h + 1) % Ny
+    iz = np.arange(k - h, k + h + 1) % Nz
+    m = 8 * n + 1
+    box = np.array([[0, 0, 0, m - 1, m - 1, m - 1]], dtype=np.int64)
+    u = OracleMultiFab(box, box[0], (0, 0, 0), 1, 4)
+    u.fab(0)[0] = u0_global[np.ix_(iz, iy, ix)]
+    res = heat8_advance(u, n, c)
+    return float(res.fab(0)[0, h, h, h])
 
 
 def heat_window(u0_global: np.ndarray, center, nsteps: int, c: float) -> float:

@@ -604,6 +604,102 @@ def test_mg_vcycle_is_decomposition_invariant():
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+# ---------------------------------------------------------------------------------------------
+# The 8th-order heat step (9-cell span, 4 ghost layers)
+# ---------------------------------------------------------------------------------------------
+H8 = (-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0)
+
+
+def _h8_symbol(theta):
+    """Eigenvalue (times h^2) of the 8th-order second difference on exp(i theta x)."""
+    return H8[0] + 2.0 * sum(H8[m] * math.cos(m * theta) for m in range(1, 5))
+
+
+def _h8_sine_error(shape=(32, 24, 16), steps=12, boxes=None):
+    nx, ny, nz = shape
+    c = 0.09
+    modes = [(0.7, (1, 2, 3)), (0.3, (5, 1, 2))]
+    u0 = np.zeros((1, nz, ny, nx))
+    exact = np.zeros_like(u0)
+    for amp, k in modes:
+        phi = I.sine_product(shape, k)
+        g = 1.0 + c * sum(_h8_symbol(2 * math.pi * k[d] / shape[d]) for d in range(3))
+        u0[0] += amp * phi
+        exact[0] += amp * g ** steps * phi
+    if boxes is None:
+        boxes = I.random_chop(I.domain_box(shape), min_edge=4, max_edge=16, align=4, seed=3)
+    m = _mf(boxes, shape, ng=4)
+    m.load_global(u0)
+    out = O.heat8_advance(m, steps, c).to_global()
+    return np.abs(out - exact).max() / np.abs(exact).max()
+
+
+def test_heat8_sine_modes_decay_by_the_stencil_symbol():
+    assert _h8_sine_error() <= 1e-12
+    assert _h8_sine_error(boxes=I.regular_chop(I.domain_box((32, 24, 16)), 8)) <= 1e-12
+
+
+def test_heat8_is_eighth_order():
+    """One step of a smooth field recovers the exact Laplacian with an error that falls
+    by 2^8 when the grid is refined: the coefficients are those of the 8th-order formula."""
+    errs = []
+    for n in (16, 32):
+        x = (np.arange(n) + 0.5) / n
+        u = np.sin(2 * np.pi * x)[None, None, None, :] * np.ones((1, 8, 8, 1))
+        m = _mf(I.regular_chop(I.domain_box((n, 8, 8)), (n // 2, 8, 8)), (n, 8, 8), ng=4)
+        m.load_global(u)
+        c = 0.05
+        out = O.heat8_advance(m, 1, c).to_global()
+        lap = (out - u) / c * (n * n)  # (u_new - u) / (c h^2) = L_h u
+        exact = -(2 * np.pi) ** 2 * u
+        errs.append(np.abs(lap - exact).max())
+    assert 200 <= errs[0] / errs[1] <= 300, errs
+
+
+def _h8_roll(u, c):
+    D = []
+    for axis in (2, 1, 0):
+        p = [None] + [np.roll(u, mm, axis=axis) + np.roll(u, -mm, axis=axis) for mm in range(1, 5)]
+        D.append(((8.0 / 5.0 * p[1] + -1.0 / 5.0 * p[2]) + 8.0 / 315.0 * p[3]) + -1.0 / 560.0 * p[4])
+    return u + c * (((D[0] + D[1]) + D[2]) + (-205.0 / 24.0) * u)
+
+
+def test_heat8_single_periodic_box_equals_numpy_roll():
+    shape = (12, 10, 9)
+    u = I.uniform(shape, 1, seed=41)[0]
+    m = _mf(I.regular_chop(I.domain_box(shape), shape), shape, ng=4)
+    m.load_global(u[None])
+    ref = u
+    for _ in range(3):
+        ref = _h8_roll(ref, 0.09)
+    assert np.array_equal(O.heat8_advance(m, 3, 0.09).to_global()[0], ref)
+
+
+def test_heat8_many_boxes_equal_one_box_and_conserve_the_sum():
+    shape = (24, 20, 16)
+    u = I.uniform(shape, 2, seed=42)
+    outs = []
+    for boxes in (I.regular_chop(I.domain_box(shape), shape), I.random_chop(I.domain_box(shape), 4, 12, 4, seed=8)):
+        m = _mf(boxes, shape, ncomp=2, ng=4)
+        m.load_global(u)
+        outs.append(O.heat8_advance(m, 4, 0.09).to_global())
+    assert np.array_equal(outs[0], outs[1])
+    for comp in range(2):
+        assert abs(outs[0][comp].sum() - u[comp].sum()) <= 1e-12 * u[comp].sum()
+
+
+def test_heat8_window_equals_full_run():
+    n, steps = 24, 3
+    u0 = I.uniform(n, 1, seed=43)
+    m = _mf(I.random_chop(I.domain_box(n), 4, 12, 4, seed=1), n, ng=4)
+    m.load_global(u0)
+    full = O.heat8_advance(m, steps, 0.09).to_global()[0]
+    rng = np.random.default_rng(4)
+    for cell in [(0, 0, 0), (23, 11, 5)] + [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(4)]:
+        i, j, k = cell
+        assert O.heat8_window(u0[0], cell, steps, 0.09) == full[k, j, i]
+
+
 MUTATIONS = {
     "heat_drops_z_pair": ("double s = (sx + sy) + sz;\n            v[", "double s = (sx + sy);\n            v["),
     "heat_wrong_sign": ("uc + c * (s - 6.0 * uc)", "uc - c * (s - 6.0 * uc)"),
@@ -617,6 +713,10 @@ MUTATIONS = {
     "gsrb_drops_rhs": ("p[q] = (((sx + sy) + sz) + h2 * fb[q]) * inv6;", "p[q] = (((sx + sy) + sz)) * inv6;"),
     "varcoef_cell_coefficient": ("const double b = 0.5 * (bt[lo] + bt[hi]);", "const double b = bt[hi];"),
     "varcoef_flux_sign": ("return b * ((u[hi] - u[lo]) * inv_dx);", "return b * ((u[lo] - u[hi]) * inv_dx);"),
+    "heat8_swapped_coefficients": ("H8_A3 = 8.0 / 315.0, H8_A4 = -1.0 / 560.0;", "H8_A3 = -1.0 / 560.0, H8_A4 = 8.0 / 315.0;"),
+    "heat8_drops_far_y": ("u[fab_index(&g, comp, i, j - m, k)] + u[fab_index(&g, comp, i, j + m, k)]",
+                          "u[fab_index(&g, comp, i, j - m, k)] + u[fab_index(&g, comp, i, j + (m < 4 ? m : 0), k)]"),
+    "heat8_centre": ("static const double H8_A0X3 = -205.0 / 24.0;", "static const double H8_A0X3 = -205.0 / 36.0;"),
     "mg_restrict_weight": ("out[fab_index(&gc, 0, I, J, K)] = acc * 0.125;", "out[fab_index(&gc, 0, I, J, K)] = acc * 0.25;"),
     "mg_restrict_drops_children": ("residual_at(p, fb, &gf, 2 * I + a, 2 * J + bb, 2 * K + c, h2)",
                                    "residual_at(p, fb, &gf, 2 * I + a, 2 * J, 2 * K + c, h2)"),
@@ -637,6 +737,8 @@ def _pins_pass():
         test_gsrb_exact_discrete_solution_is_fixed_point()
         test_varcoef_single_periodic_box_equals_numpy_roll()
         test_mg_transfers_equal_dense_matrices((4, 4, 4))
+        checks.append(_h8_sine_error() <= 1e-12)
+        test_heat8_is_eighth_order()
         test_mg_converges_to_the_discrete_sine_solution("boxes_of_8")
     except (AssertionError, ValueError, IndexError):
         return False
