@@ -254,6 +254,20 @@ bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t
 bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream_t stream);
 
 /*
+ * nsteps forward-Euler heat steps with the 8th-order centred second difference
+ * (9 cells per axis: the stencil span of Sec. 4.2's application, applied to the
+ * heat equation), ping-ponging u[0] -> u[1] -> ...; result in u[nsteps % 2].
+ * With p_m = u[-m] + u[+m] along an axis (m = 1..4),
+ *   D = ((A1*p1 + A2*p2) + A3*p3) + A4*p4,   u_new = u + c*(((Dx + Dy) + Dz) + A0X3*u),
+ * A1 = 8/5, A2 = -1/5, A3 = 8/315, A4 = -1/560, A0X3 = 3*(-205/72), each rounded
+ * once (to the storage type for FP32); c = dt/dx^2.  Each step is
+ * FillBoundary(u_old) and one stencil launch over all boxes and components.
+ * nghost >= 4 (BL_EINVAL); shapes as bl_heat_step.  Forward Euler with this
+ * stencil is stable for c <= 0.1025.
+ */
+bl_status bl_heat8_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream_t stream);
+
+/*
  * nsteps forward-Euler steps of du/dt = div(beta grad u) in the flux form
  * (Sec. 4.1's face-flux loops, here with a coefficient per cell), ping-ponging
  * u[0] -> u[1] -> u[0] ...; the result is in u[nsteps % 2].  Per valid cell

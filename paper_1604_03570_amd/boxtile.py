@@ -69,6 +69,7 @@ _SIGS = {
     "bl_heat_step": [_vp, _vp, ctypes.c_double, _i32, _vp],
     "bl_heat_advance": [_vpp, _i32, ctypes.c_double, _vp],
     "bl_heat_varcoef_advance": [_vpp, _vp, _i32, ctypes.c_double, ctypes.c_double, _vp],
+    "bl_heat8_advance": [_vpp, _i32, ctypes.c_double, _vp],
     "bl_heat_step_unfused": [_vp, _vp, ctypes.c_double, _vp],
     "bl_gsrb_sweeps": [_vp, _vp, ctypes.c_double, _i32, _dp, _vp],
     "bl_residual_norm": [_vp, _vp, ctypes.c_double, _dp, _vp],
@@ -464,6 +465,14 @@ def heat_advance(u0: MultiFab, u1: MultiFab, nsteps: int, c: float, stream=None)
     """nsteps fused steps (one launch per step, captured in a HIP graph); returns the result holder."""
     arr = (ctypes.c_void_p * 2)(u0.handle.value, u1.handle.value)
     _check(_L.bl_heat_advance(arr, int(nsteps), float(c), _stream(stream)))
+    return u0 if nsteps % 2 == 0 else u1
+
+
+def heat8_advance(u0: MultiFab, u1: MultiFab, nsteps: int, c: float, stream=None) -> MultiFab:
+    """nsteps heat steps with the 8th-order second difference (nghost >= 4): FillBoundary and
+    one stencil launch per step; returns the result holder."""
+    arr = (ctypes.c_void_p * 2)(u0.handle.value, u1.handle.value)
+    _check(_L.bl_heat8_advance(arr, int(nsteps), float(c), _stream(stream)))
     return u0 if nsteps % 2 == 0 else u1
 
 

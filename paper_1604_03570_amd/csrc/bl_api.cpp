@@ -32,6 +32,7 @@ Plan::~Plan() {
   (void)hipFree(dvlin);
   (void)hipFree(dcellpre);
   (void)hipFree(dpairpre);
+  (void)hipFree(dh8);
   (void)hipFree(dcellwg);
   (void)hipFree(dpairwg);
 }
@@ -502,6 +503,36 @@ bl_status bl_heat_varcoef_advance(bl_multifab* u[2], bl_multifab* beta, int32_t 
     a.w = u[(s + 1) & 1]->data;
     if (!a.fused) BL_HIP(launch_fill(p, u[s & 1]->data, 0, p.ncomp, stream));
     BL_HIP(launch_heat_varcoef(p.dtype, p.vec, a, stream));
+  }
+  return BL_OK;
+}
+
+bl_status bl_heat8_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream_t stream) {
+  clear_error();
+  if (!u) return fail(BL_EINVAL, "NULL MultiFab array");
+  bl_status st = check_heat(u[0], u[1]);
+  if (st != BL_OK) return st;
+  Plan& p = *u[0]->plan;
+  if (p.ng < 4) return fail(BL_EINVAL, "the 8th-order stencil needs nghost >= 4, not %d", p.ng);
+  if (nsteps < 0) return fail(BL_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return BL_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_vc_mu);
+    if (!p.h8built) {
+      std::vector<DevTile> t;
+      int rm = 1, nv = 1;
+      build_h8_tiles(p, t, &rm, &nv);
+      if ((st = upload(&p.dh8, t, "hipMalloc/hipMemcpy(8th-order tiles)")) != BL_OK) return st;
+      p.hh8.swap(t);
+      p.h8rmax = rm;
+      p.h8nvtmax = nv;
+      p.h8built = true;
+    }
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    BL_HIP(launch_fill(p, u[s & 1]->data, 0, p.ncomp, stream));
+    BL_HIP(launch_heat8(p.dtype, p.vec, p.dh8, (int)p.hh8.size(), p.dboxes, u[s & 1]->data, u[(s + 1) & 1]->data, c,
+                        p.h8rmax, p.h8nvtmax, stream));
   }
   return BL_OK;
 }

@@ -319,6 +319,12 @@ struct Plan {
   DevLinTile* dvlin = nullptr;
   int vyhmax = 1, vxhmax = 1, vzchunk = 0;
 
+  // tiles of the 8th-order stencil (made on first use)
+  std::vector<DevTile> hh8;
+  DevTile* dh8 = nullptr;
+  int h8rmax = 1, h8nvtmax = 1;
+  bool h8built = false;
+
   ~Plan();
 };
 
@@ -337,6 +343,10 @@ void build_lin_tiles(const Plan& p, const TileConfig& cfg, int member, int box_b
                      std::vector<DevLinTile>& tiles, int* yhmax, int* xhmax);
 // LDS bytes of one workgroup of the linear-tile stencil forms.
 size_t lin_lds_bytes(const TileConfig& cfg, int esize, int vec, int yhmax, int xhmax);
+// Tiles of the 8th-order stencil: per box and component, x vectors in groups of
+// at most 16, rows in groups of at most min(32, 256 / group width), z in chunks
+// of 32 planes; memory order (z chunk, then y, then x).
+void build_h8_tiles(const Plan& p, std::vector<DevTile>& tiles, int* rmax, int* nvtmax);
 
 }  // namespace bl
 

@@ -998,6 +998,125 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ---------------------------------------------------------------- 8th-order heat step (9-cell span)
+// Workgroup barrier with acquire/release ordering of LDS only: loads from global
+// memory issued before it stay in flight.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Forward-Euler heat step with the 8th-order centred second difference (9
+// cells per axis; the span of Sec. 4.2's stencils).  With p_m = u[-m] + u[+m]
+// along an axis, D = ((A1*p1 + A2*p2) + A3*p3) + A4*p4 and
+// u_new = u + c*(((Dx + Dy) + Dz) + A0X3*u); each coefficient rounded once.
+constexpr double kH8A1 = 8.0 / 5.0, kH8A2 = -1.0 / 5.0, kH8A3 = 8.0 / 315.0, kH8A4 = -1.0 / 560.0;
+constexpr double kH8A0X3 = -205.0 / 24.0;
+
+// One workgroup per tile (x vectors xv0..xv0+nvt-1 of rows y0..y0+rows-1 over
+// planes z0..z1-1, at most 256 lanes, rows <= 32, nvt <= 32), marching up z.
+// Each lane keeps the 9 planes z-4..z+4 of its own vector column in registers.
+// Plane z goes into one of two LDS buffers of ldh x ldw values together with
+// its 4-wide x and y halo (the FAB's filled ghosts at box faces, from the x
+// ghost slab for x), so x and y neighbours come from LDS; the next plane's
+// column value and halo are loaded before the barrier and stay in flight
+// across it.  One barrier per plane.
+template <typename T, int V>
+__global__ void __launch_bounds__(256)
+    k_heat8(const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes, const T* u_, T* w_, T c, int ldw,
+            int ldh) {
+  using VT = Vec<T, V>;
+  extern __shared__ unsigned char smem_raw[];
+  T* const lds = reinterpret_cast<T*>(smem_raw);
+  const DevTile tl = ldc(tiles + logical_block());
+  const DevBox B = ldc(boxes + tl.box);
+  const BL_GLOBAL T* __restrict__ u = as_global(u_);
+  BL_GLOBAL T* __restrict__ w = as_global(w_);
+  const int l = (int)threadIdx.x;
+  const int nvt = tl.nvt, rows = tl.rows, W = nvt * V, x0 = tl.xv0 * V;
+  const int lx = l % nvt, ly = l / nvt;
+  const bool active = ly < rows;
+  const int lyc = active ? ly : 0;  // idle lanes shadow row 0, so every address stays valid
+  const int64_t sz = B.sz;
+  const int64_t comp0 = B.off + (int64_t)tl.comp * B.sc;
+  const int64_t col = comp0 + x0 + lx * V + (int64_t)(tl.y0 + lyc) * B.sy;
+  // y halo: 4 rows below and 4 above the tile, one vector per lane
+  const bool hy = l < 8 * nvt;
+  int64_t yh_at = col;
+  int yh_slot = 0;
+  if (hy) {
+    const int r = l / nvt, xv = l % nvt;
+    const int y = r < 4 ? tl.y0 - 4 + r : tl.y0 + rows + r - 4;
+    yh_at = comp0 + x0 + xv * V + (int64_t)y * B.sy;
+    yh_slot = (r < 4 ? r : rows + r) * ldw + 4 + xv * V;
+  }
+  // x halo: 4 values left and right of each row, one per lane; a value beyond
+  // the box's x range comes from the x ghost slab (layer = distance from the face - 1)
+  const bool hx = l < 8 * rows;
+  int64_t xh_at = col, xh_step = sz;
+  int xh_slot = 0;
+  if (hx) {
+    const int side = l / (4 * rows), rem = l - side * 4 * rows, m = rem / rows, yr = rem - m * rows;
+    const int y = tl.y0 + yr;
+    const int x = side ? x0 + W + m : x0 - 1 - m;
+    if (x < 0 || x >= B.ex) {
+      xh_at = B.xs + (int64_t)tl.comp * B.sc + (x < 0 ? 0 : B.xs_side) + (int64_t)y * B.ng + (x < 0 ? -1 - x : x - B.ex);
+      xh_step = B.xs_z;
+    } else {
+      xh_at = comp0 + x + (int64_t)y * B.sy;
+    }
+    xh_slot = (yr + 4) * ldw + (side ? 4 + W + m : 3 - m);
+  }
+  const T A1 = (T)kH8A1, A2 = (T)kH8A2, A3 = (T)kH8A3, A4 = (T)kH8A4, A0 = (T)kH8A0X3;
+
+  VT Q[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Q[k] = ldv<T, V>(u + col + (int64_t)(tl.z0 - 4 + k) * sz);
+  VT yh = hy ? ldv<T, V>(u + yh_at + (int64_t)tl.z0 * sz) : Q[0];
+  T xh = hx ? u[xh_at + (int64_t)tl.z0 * xh_step] : (T)0;
+  const int own = (ly + 4) * ldw + 4 + lx * V;
+  for (int z = tl.z0; z < tl.z1; ++z) {
+    T* buf = lds + ((z - tl.z0) & 1) * (ldw * ldh);
+    if (active) *reinterpret_cast<VT*>(buf + own) = Q[4];
+    if (hy) *reinterpret_cast<VT*>(buf + yh_slot) = yh;
+    if (hx) buf[xh_slot] = xh;
+    const bool more = z + 1 < tl.z1;
+    VT qn = Q[8], yhn = yh;
+    T xhn = xh;
+    if (more) {
+      qn = ldv<T, V>(u + col + (int64_t)(z + 5) * sz);
+      if (hy) yhn = ldv<T, V>(u + yh_at + (int64_t)(z + 1) * sz);
+      if (hx) xhn = u[xh_at + (int64_t)(z + 1) * xh_step];
+    }
+    lds_sync();
+    if (active) {
+      const T* row = buf + own;
+      VT o;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const T uc = Q[4].v[e];
+        const T px1 = row[e - 1] + row[e + 1], px2 = row[e - 2] + row[e + 2];
+        const T px3 = row[e - 3] + row[e + 3], px4 = row[e - 4] + row[e + 4];
+        const T py1 = row[e - ldw] + row[e + ldw], py2 = row[e - 2 * ldw] + row[e + 2 * ldw];
+        const T py3 = row[e - 3 * ldw] + row[e + 3 * ldw], py4 = row[e - 4 * ldw] + row[e + 4 * ldw];
+        const T pz1 = Q[3].v[e] + Q[5].v[e], pz2 = Q[2].v[e] + Q[6].v[e];
+        const T pz3 = Q[1].v[e] + Q[7].v[e], pz4 = Q[0].v[e] + Q[8].v[e];
+        const T Dx = ((A1 * px1 + A2 * px2) + A3 * px3) + A4 * px4;
+        const T Dy = ((A1 * py1 + A2 * py2) + A3 * py3) + A4 * py4;
+        const T Dz = ((A1 * pz1 + A2 * pz2) + A3 * pz3) + A4 * pz4;
+        o.v[e] = uc + c * (((Dx + Dy) + Dz) + A0 * uc);
+      }
+      stv_nt<T, V>(w + col + (int64_t)z * sz, o);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) Q[k] = Q[k + 1];
+    Q[8] = qn;
+    yh = yhn;
+    xh = xhn;
+  }
+}
+
 __device__ double block_reduce(double v, int op);
 
 // GSRB colour pass, fused with the ghost fill (neighbour boxes read through the
@@ -1765,6 +1884,30 @@ hipError_t launch_prolong_add(const Plan& fine, const Plan& coarse, void* phi, c
   else
     hipLaunchKernelGGL(k_prolong_add<float>, dim3(g), dim3(256), 0, s, fine.dpairpre, fine.dpairwg, nb, total,
                        fine.dboxes, coarse.dboxes, (float*)phi, (const float*)pc);
+  return hipGetLastError();
+}
+
+// 8th-order heat step over the tiles of k_heat8 (FillBoundary of u first).
+hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, int ntiles, const DevBox* boxes, const void* u,
+                        void* w, double c, int rmax, int nvtmax, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const int ldw = ((nvtmax * vec + 8) + 3) & ~3, ldh = rmax + 8;
+  const size_t lds = 2 * (size_t)ldw * ldh * (dtype == BL_F64 ? 8 : 4);
+  if (dtype == BL_F64) {
+    if (vec == 2)
+      hipLaunchKernelGGL((k_heat8<double, 2>), dim3(ntiles), dim3(256), lds, s, tiles, boxes, (const double*)u,
+                         (double*)w, c, ldw, ldh);
+    else
+      hipLaunchKernelGGL((k_heat8<double, 1>), dim3(ntiles), dim3(256), lds, s, tiles, boxes, (const double*)u,
+                         (double*)w, c, ldw, ldh);
+  } else {
+    if (vec == 4)
+      hipLaunchKernelGGL((k_heat8<float, 4>), dim3(ntiles), dim3(256), lds, s, tiles, boxes, (const float*)u,
+                         (float*)w, (float)c, ldw, ldh);
+    else
+      hipLaunchKernelGGL((k_heat8<float, 1>), dim3(ntiles), dim3(256), lds, s, tiles, boxes, (const float*)u,
+                         (float*)w, (float)c, ldw, ldh);
+  }
   return hipGetLastError();
 }
 

@@ -95,6 +95,11 @@ hipError_t launch_restrict_residual(const Plan& fine, const Plan& coarse, const 
                                     double h2, hipStream_t s);
 hipError_t launch_prolong_add(const Plan& fine, const Plan& coarse, void* phi, const void* pc, hipStream_t s);
 
+// 8th-order heat step (9-cell span) over tiles built for it: at most 256
+// lanes, rows <= rmax <= 32, nvt <= nvtmax <= 32; u's ghosts (>= 4 layers) filled.
+hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, int ntiles, const DevBox* boxes, const void* u,
+                        void* w, double c, int rmax, int nvtmax, hipStream_t s);
+
 int device_cu_count();
 
 }  // namespace bl

@@ -485,6 +485,34 @@ void build_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base,
   if (box_tile_start) box_tile_start->push_back((int)tiles.size());
 }
 
+void build_h8_tiles(const Plan& p, std::vector<DevTile>& tiles, int* rmax, int* nvtmax) {
+  tiles.clear();
+  for (int b = 0; b < (int)p.hboxes.size(); ++b) {
+    const DevBox& B = p.hboxes[b];
+    const int nvt_full = std::min(B.nvx, 16);
+    const int rows_full = std::max(1, std::min({B.ey, 32, 256 / nvt_full}));
+    for (int n = 0; n < p.ncomp; ++n)
+      for (int z0 = 0; z0 < B.ez; z0 += 32)
+        for (int y0 = 0; y0 < B.ey; y0 += rows_full)
+          for (int xv0 = 0; xv0 < B.nvx; xv0 += nvt_full) {
+            DevTile t;
+            std::memset(&t, 0, sizeof t);
+            t.box = b;
+            t.comp = n;
+            t.xv0 = xv0;
+            t.nvt = std::min(nvt_full, B.nvx - xv0);
+            t.y0 = y0;
+            t.rows = std::min(rows_full, B.ey - y0);
+            t.z0 = z0;
+            t.z1 = std::min(z0 + 32, B.ez);
+            for (int f = 0; f < 6; ++f) t.frec[f] = kFaceNone;
+            *rmax = std::max(*rmax, t.rows);
+            *nvtmax = std::max(*nvtmax, t.nvt);
+            tiles.push_back(t);
+          }
+  }
+}
+
 size_t lin_lds_bytes(const TileConfig& cfg, int esize, int vec, int yhmax, int xhmax) {
   const size_t zb = (size_t)cfg.zchunk, vb = (size_t)esize * vec;
   return zb * 64 * cfg.waves * vb + zb * 2 * yhmax * vb + zb * 2 * xhmax * esize;

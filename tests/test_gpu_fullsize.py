@@ -195,3 +195,29 @@ def test_256cube_vcycles_at_full_size(bt):
     more = mg.vcycles(phi, fm, h2, 4)
     say(f"256^3 vcycles: norms {n1[0]:.4e} then {[f'{x:.3e}' for x in more]}")
     assert more[-1] <= 1e-4 * n1[0]
+
+
+def test_256cube_heat8_at_full_size(bt):
+    """256^3 periodic, 64 boxes of 64^3, 4 ghost layers, FP64, 3 seeded sine modes, 20
+    steps of the 8th-order form: the closed form of the stencil's symbol to 1e-12 and
+    sampled cells equal the oracle's dependence-cone window bit for bit."""
+    n, steps, c = 256, 20, 0.09
+    dom = I.domain_box(n)
+    ba = bt.BoxArray.chop(dom, 64)
+    u0, modes = I.sine_modes(n, seed=4)
+    a, b = bt.MultiFab(ba, 1, 4, bt.F64), bt.MultiFab(ba, 1, 4, bt.F64)
+    a.from_global(u0)
+    got = bt.heat8_advance(a, b, steps, c).to_global()[0].cpu().numpy()
+    coef = (-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0)
+    exact = np.zeros_like(got)
+    for md in modes:
+        sym = sum(coef[0] + 2.0 * sum(coef[m] * math.cos(2 * math.pi * m * kd / n) for m in range(1, 5))
+                  for kd in md.k)
+        exact += md.amp * (1.0 + c * sym) ** steps * I.sine_product(n, md.k)
+    err = np.abs(got - exact).max() / np.abs(exact).max()
+    say(f"256^3 heat8: closed-form rel err {err:.3e}")
+    assert err <= 1e-12
+    rng = np.random.default_rng(3)
+    for cell in [(0, 0, 0), (255, 64, 130)] + [tuple(int(v) for v in rng.integers(0, n, 3))]:
+        i, j, k = cell
+        assert got[k, j, i] == O.heat8_window(u0[0], cell, steps, c), cell
