@@ -330,6 +330,40 @@ def mg_run(bt, I, torch, seed: int, cycles: int = 5) -> dict:
     return out
 
 
+def heat8_run(bt, I, torch, boxes, dom, u0, ncomp: int, steps: int = 10) -> dict:
+    """The 8th-order heat step (9-cell span, 4 ghost layers) on the same level and u0, FP64,
+    c = 0.09: FillBoundary of the 4 layers and the stencil, timed per step and apart."""
+    n = int(dom[3]) + 1
+    ba = bt.BoxArray.from_boxes(boxes, dom)
+    a, b = bt.MultiFab(ba, ncomp, 4, bt.F64), bt.MultiFab(ba, ncomp, 4, bt.F64)
+    for comp in range(ncomp):
+        a.from_global(u0[comp:comp + 1], scomp=comp)
+    cells = int(sum(int(np.prod(bx[3:] - bx[:3] + 1)) for bx in boxes)) * ncomp
+    bt.heat8_advance(a, b, 2, 0.09)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    bt.heat8_advance(a, b, steps, 0.09)
+    ev[1].record(stream)
+    for _ in range(steps):
+        a.fill_boundary()
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    fill = ev[1].elapsed_time(ev[2]) / steps
+    kern = ms - fill
+    gbs = 16 * cells / (kern / 1e3) / 1e9
+    out = {"workload": f"{n}^3 periodic, {len(boxes)} uneven boxes, {ncomp} comps, 4 ghost layers, FP64",
+           "ms_per_step": round(ms, 4), "fill_ms": round(fill, 4), "stencil_ms": round(kern, 4),
+           "gcell_s": round(cells / (ms / 1e3) / 1e9, 2), "stencil_gbs_at_16B": round(gbs, 1),
+           "stencil_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"heat8: {ms:.3f} ms/step (fill {fill:.3f}, stencil {kern:.3f} ms = {gbs:.0f} GB/s at 16 B/cell)")
+    del a, b, ba
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,6 +383,7 @@ def main() -> int:
     ap.add_argument("--no-gsrb", action="store_true", help="skip the GSRB smoother run")
     ap.add_argument("--no-varcoef", action="store_true", help="skip the variable-coefficient flux-form run")
     ap.add_argument("--no-mg", action="store_true", help="skip the multigrid V-cycle run")
+    ap.add_argument("--no-heat8", action="store_true", help="skip the 8th-order stencil run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three plain device copies of 2 GiB (reference for HBM byte counters)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -509,6 +544,8 @@ def main() -> int:
 
     if not args.no_extra and not args.no_varcoef and args.dtype == "f64":
         extra["varcoef"] = varcoef_run(bt, I, torch, boxes, dom, u0, ncomp, args.seed, 20)
+    if not args.no_extra and not args.no_heat8 and args.dtype == "f64":
+        extra["heat8"] = heat8_run(bt, I, torch, boxes, dom, u0, ncomp)
 
     if not args.no_extra and not args.no_gsrb:
         extra["gsrb"] = gsrb_run(bt, I, torch, args.seed)

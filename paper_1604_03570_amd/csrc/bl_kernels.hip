@@ -1076,6 +1076,12 @@ __global__ void __launch_bounds__(256)
   VT yh = hy ? ldv<T, V>(u + yh_at + (int64_t)tl.z0 * sz) : Q[0];
   T xh = hx ? u[xh_at + (int64_t)tl.z0 * xh_step] : (T)0;
   const int own = (ly + 4) * ldw + 4 + lx * V;
+  // running pointers, one plane further each step: the next column plane, the
+  // next plane's halo values, the output
+  const BL_GLOBAL T* pq = u + col + (int64_t)(tl.z0 + 5) * sz;
+  const BL_GLOBAL T* py = u + yh_at + (int64_t)(tl.z0 + 1) * sz;
+  const BL_GLOBAL T* px = u + xh_at + (int64_t)(tl.z0 + 1) * xh_step;
+  BL_GLOBAL T* pw = w + col + (int64_t)tl.z0 * sz;
   for (int z = tl.z0; z < tl.z1; ++z) {
     T* buf = lds + ((z - tl.z0) & 1) * (ldw * ldh);
     if (active) *reinterpret_cast<VT*>(buf + own) = Q[4];
@@ -1085,10 +1091,13 @@ __global__ void __launch_bounds__(256)
     VT qn = Q[8], yhn = yh;
     T xhn = xh;
     if (more) {
-      qn = ldv<T, V>(u + col + (int64_t)(z + 5) * sz);
-      if (hy) yhn = ldv<T, V>(u + yh_at + (int64_t)(z + 1) * sz);
-      if (hx) xhn = u[xh_at + (int64_t)(z + 1) * xh_step];
+      qn = ldv<T, V>(pq);
+      if (hy) yhn = ldv<T, V>(py);
+      if (hx) xhn = *px;
     }
+    pq += sz;
+    py += sz;
+    px += xh_step;
     lds_sync();
     if (active) {
       const T* row = buf + own;
@@ -1107,8 +1116,9 @@ __global__ void __launch_bounds__(256)
         const T Dz = ((A1 * pz1 + A2 * pz2) + A3 * pz3) + A4 * pz4;
         o.v[e] = uc + c * (((Dx + Dy) + Dz) + A0 * uc);
       }
-      stv_nt<T, V>(w + col + (int64_t)z * sz, o);
+      stv_nt<T, V>(pw, o);
     }
+    pw += sz;
 #pragma unroll
     for (int k = 0; k < 8; ++k) Q[k] = Q[k + 1];
     Q[8] = qn;
