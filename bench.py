@@ -200,6 +200,45 @@ def summarize_profiles(d: str) -> int:
     return 0
 
 
+EXTRAS_PROFILE_ARGS = "--steps 5 --warmup 1 --no-cpu-baseline --no-serve"
+
+
+def summarize_trace(d: str) -> int:
+    """Kernel trace statistics of one rocprofv3 run of this script with EXTRAS_PROFILE_ARGS
+    (every extra workload but serving): each kernel's calls and average duration, beside
+    the figures the run printed."""
+    import glob
+    import re
+    got = sorted(glob.glob(os.path.join(d, "trace/*kernel_stats.csv")))
+    if not got:
+        raise SystemExit(f"missing trace/*kernel_stats.csv under {d}")
+    stats = _read_csv(got[0])
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    log_text = open(os.path.join(d, "trace.log")).read()
+    hashes = set(re.findall(r"kernel source sha256/16: (\w+)", log_text))
+    if len(hashes) != 1:
+        raise SystemExit(f"no single kernel source hash in the run's log: {hashes}")
+    printed = [ln for ln in log_text.splitlines() if ln.startswith("[bench]")]
+    out = os.path.join(ROOT, "profiles", "kernels_every_workload.md")
+    with open(out, "w") as fh:
+        fh.write("# Every kernel of the benchmark's workloads (kernel trace)\n\n")
+        fh.write("Command (from the repository root, after `cd /tmp && export TMPDIR=/tmp` for the profiler's files):\n\n")
+        fh.write(f"    rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o run -- python3 bench.py {EXTRAS_PROFILE_ARGS}\n\n")
+        fh.write(f"Summarised with `python3 bench.py --summarize-trace <out>`.  Kernel source sha256/16: `{hashes.pop()}`.\n")
+        fh.write("The workloads: the 512^3 uneven level (fused heat FP64 and FP32, unfused, reductions, the "
+                 "variable-coefficient form, the 8th-order step with 4 ghost layers) and the 384^3 level of 64^3 "
+                 "boxes (GSRB, multigrid).  Averages mix every launch of a kernel, e.g. all multigrid levels.\n\n")
+        fh.write("| kernel | calls | average us | total % |\n|---|---|---|---|\n")
+        for r in stats[:40]:
+            fh.write(f"| `{_short_kernel(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f} |\n")
+        fh.write("\n## What the run printed\n\n")
+        for ln in printed:
+            fh.write(f"    {ln}\n")
+    print(f"wrote {out}")
+    return 0
+
+
 def gsrb_run(bt, I, torch, seed: int, sweeps: int = 20) -> dict:
     """Red-black Gauss-Seidel for -Lap(phi) = f: 384^3 periodic, 216 boxes of 64^3, f a seeded
     zero-mean N(0,1) field rounded to FP32, phi0 = 0, FP32 state, 20 sweeps with a FillBoundary
@@ -386,6 +425,9 @@ def main() -> int:
     ap.add_argument("--no-heat8", action="store_true", help="skip the 8th-order stencil run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three plain device copies of 2 GiB (reference for HBM byte counters)")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="no GPU: turn a kernel-trace run of this script with EXTRAS_PROFILE_ARGS (DIR/trace, "
+                         "DIR/trace.log) into profiles/kernels_every_workload.md")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="no GPU: turn rocprofv3 output of this script (DIR/trace, DIR/fetch, DIR/write) into "
                          "the summary and traffic files under profiles/")
@@ -393,6 +435,8 @@ def main() -> int:
 
     if args.summarize_profiles:
         return summarize_profiles(args.summarize_profiles)
+    if args.summarize_trace:
+        return summarize_trace(args.summarize_trace)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -94,8 +94,8 @@ TILE_SHAPES = [(2, 4, 0, 3), (8, 4, 0, 3), (4, 1, 0, 3), (4, 2, 0, 3), (8, 3, 0,
 
 @pytest.mark.parametrize("shape", TILE_SHAPES, ids=lambda s: "z%d_w%d_b%d" % (s[0], s[1], s[3]))
 def test_varcoef_every_tile_shape(bt, shape):
-    """The kernel runs on the plan's own tiles where twice their LDS fits, else on tiles
-    it builds with fewer planes per z block; every choice gives the oracle's bits."""
+    """The kernel runs on the plan's own tiles where they have 2 planes per z block, else
+    on tiles it builds; every plan shape gives the oracle's bits."""
     zchunk, waves, persist, block = shape
     say(f"varcoef tile shape zchunk={zchunk} waves={waves} block={block}")
     bt.set_tile_config(zchunk if block else 4, waves, persist, block)
@@ -108,9 +108,9 @@ def test_varcoef_every_tile_shape(bt, shape):
         bt.set_tile_config(4, 4, 0, 3)
 
 
-def test_varcoef_large_boxes_take_the_smaller_tiles(bt):
-    """128^3 boxes (planes wider than one workgroup) at 8 planes per z block: twice the
-    stencil's LDS would not fit, so the kernel runs on its own tiles; bits unchanged."""
+def test_varcoef_large_boxes(bt):
+    """Boxes of 128 x 128 x 16 (planes wider than one workgroup) under a plan of 8 planes
+    per z block: the kernel runs on its own tiles; bits unchanged."""
     n = 128
     rng = np.random.default_rng(3)
     dom = I.domain_box((n, n, 32))
