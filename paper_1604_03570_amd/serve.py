@@ -147,8 +147,9 @@ class Server:
 
     def prepare(self, requests) -> None:
         """Make every problem shape of the stream resident ahead of time, as in a
-        long-running server: its device tables, its kernels loaded and the allocator
-        holding blocks of its size, by one batched step of one problem per shape."""
+        long-running server: its device tables, its kernels loaded (those that build an
+        initial field too) and the allocator holding blocks of its size, by admitting one
+        problem per shape as a request would be and one batched step."""
         seen = set()
         batch = bt.Batch()
         keep = []
@@ -159,7 +160,7 @@ class Server:
             seen.add(key)
             ba = self.shapes.boxarray(r.n, r.box_edge)
             a, b = bt.MultiFab(ba, 1, 1, _DT[r.dtype]), bt.MultiFab(ba, 1, 1, _DT[r.dtype])
-            a.set_val(1.0)
+            a.from_global(initial_field(r, device=a.buffer.device))
             keep.append((a, b, batch.add(a, b, I.heat_c(r.n))))
         if keep:
             batch.step()
