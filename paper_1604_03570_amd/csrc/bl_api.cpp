@@ -33,7 +33,6 @@ Plan::~Plan() {
   (void)hipFree(dcellpre);
   (void)hipFree(dpairpre);
   (void)hipFree(dh8);
-  (void)hipFree(dg1);
   (void)hipFree(dcellwg);
   (void)hipFree(dpairwg);
 }
@@ -198,7 +197,6 @@ static void forget_graphs(const bl_multifab* mf) {
 using namespace bl;
 
 bl_multifab::~bl_multifab() {
-  (void)hipFree(dtwin);
   forget_graphs(this);
   (void)hipFree(dscratch);
   (void)hipHostFree(hres);
@@ -638,69 +636,14 @@ static hipError_t residual_norm_dev(const Plan& p, void* phi, const void* f, dou
   return launch_residual(p, phi, f, h2, partials, out, block_of(p), stream);
 }
 
-// The one-pass sweep needs 2 ghost layers, every ghost covered (periodic on
-// every axis, boxes covering the domain) and a second state buffer.
-static bool gsrb1_ok(const Plan& p) {
-  return p.ng >= 2 && p.covers && p.periodic[0] && p.periodic[1] && p.periodic[2];
-}
-
-// Sweeps in pairs, phi -> twin -> phi, each one FillBoundary(2 layers) and one
-// launch; an odd last sweep in place by the two-colour form.  Norms: each pass
-// takes the residual of its input, the state after the previous sweep; the
-// last one is taken after the sweeps.
-static bl_status gsrb_one_pass(Plan& p, bl_multifab* phi, const bl_multifab* f, double h2, int nsweeps,
-                               double* resnorm_host, hipStream_t stream) {
-  {
-    std::lock_guard<std::mutex> lk(g_vc_mu);
-    if (!p.g1built) {
-      std::vector<DevTile> t;
-      build_g1_tiles(p, t);
-      bl_status st = upload(&p.dg1, t, "hipMalloc/hipMemcpy(one-pass GSRB tiles)");
-      if (st != BL_OK) return st;
-      p.hg1.swap(t);
-      p.g1built = true;
-    }
-  }
-  if (!phi->dtwin) BL_HIP(hipMalloc(&phi->dtwin, phi->bytes));
-  const int nt = (int)p.hg1.size();
-  const size_t slots = std::max((size_t)nt, reduce_slots(p)) + 8;
-  bl_status st;
-  if (resnorm_host && (st = ensure_scratch(phi, slots + (size_t)nsweeps + 8, (size_t)nsweeps + 8)) != BL_OK)
-    return st;
-  double* partials = resnorm_host ? phi->dscratch : nullptr;
-  double* norms = resnorm_host ? phi->dscratch + slots : nullptr;
-  BL_HIP(launch_fill(p, f->data, 0, 1, stream));
-  void* buf[2] = {phi->data, phi->dtwin};
-  const int pairs = nsweeps / 2 * 2;
-  for (int s = 0; s < pairs; ++s) {
-    BL_HIP(launch_fill(p, buf[s & 1], 0, 1, stream));
-    double* part = (norms && s > 0) ? partials : nullptr;
-    BL_HIP(launch_gsrb_sweep1(p.dtype, p.dg1, nt, p.dboxes, buf[s & 1], buf[(s + 1) & 1], f->data, h2, part, stream));
-    if (part) BL_HIP(launch_reduce_partials(partials, nt, 1, norms + s - 1, stream));
-  }
-  if (norms) BL_HIP(residual_norm_dev(p, phi->data, f->data, h2, partials, norms + pairs - 1, stream));
-  if (pairs < nsweeps) {
-    BL_HIP(gsrb_smooth(p, phi->data, f->data, h2, 1, stream));
-    if (norms) BL_HIP(residual_norm_dev(p, phi->data, f->data, h2, partials, norms + nsweeps - 1, stream));
-  }
-  if (norms) {
-    BL_HIP(hipMemcpyAsync(phi->hres, norms, sizeof(double) * nsweeps, hipMemcpyDeviceToHost, stream));
-    BL_HIP(hipStreamSynchronize(stream));
-    std::memcpy(resnorm_host, phi->hres, sizeof(double) * nsweeps);
-  }
-  return BL_OK;
-}
-
 bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int32_t nsweeps, double* resnorm_host,
                          hipStream_t stream) {
   clear_error();
   bl_status st = check_gsrb(phi, f);
   if (st != BL_OK) return st;
   if (nsweeps < 0) return fail(BL_EINVAL, "nsweeps < 0");
-  Plan& pm = *phi->plan;
-  const Plan& p = pm;
+  const Plan& p = *phi->plan;
   const size_t nt = p.htiles.size();
-  if (gsrb1_ok(p) && nsweeps >= 2) return gsrb_one_pass(pm, phi, f, h2, nsweeps, resnorm_host, stream);
   if (gsrb_fused_ok(p, block_of(p))) {
     // fused form: no FillBoundary; each colour pass reads the neighbour boxes
     // through the face records.  The norm after sweep s is the black cells'

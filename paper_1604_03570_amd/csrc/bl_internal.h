@@ -325,13 +325,6 @@ struct Plan {
   int h8rmax = 1, h8nvtmax = 1;
   bool h8built = false;
 
-  // tiles of the one-pass GSRB sweep (made on first use); covers: the boxes
-  // cover the domain
-  std::vector<DevTile> hg1;
-  DevTile* dg1 = nullptr;
-  bool g1built = false;
-  bool covers = false;
-
   ~Plan();
 };
 
@@ -354,9 +347,6 @@ size_t lin_lds_bytes(const TileConfig& cfg, int esize, int vec, int yhmax, int x
 // at most 16, rows in groups of at most min(32, 256 / group width), z in chunks
 // of 32 planes; memory order (z chunk, then y, then x).
 void build_h8_tiles(const Plan& p, std::vector<DevTile>& tiles, int* rmax, int* nvtmax);
-// Tiles of the one-pass GSRB sweep, in cells: W = min(ex, 32) by H = min(ey, 32,
-// 256 / W), z in chunks of 64 planes; memory order.
-void build_g1_tiles(const Plan& p, std::vector<DevTile>& tiles);
 
 }  // namespace bl
 
@@ -364,7 +354,6 @@ struct bl_multifab {
   std::shared_ptr<bl::Plan> plan;
   void* data = nullptr;
   size_t bytes = 0;
-  void* dtwin = nullptr;        // second state buffer of the one-pass GSRB sweep, made on first use
   double* dscratch = nullptr;   // reduction partials + results (device), grown on demand
   size_t nscratch = 0;
   double* hres = nullptr;       // pinned host landing slots for scalar results

@@ -1129,127 +1129,6 @@ __global__ void __launch_bounds__(256)
 
 __device__ double block_reduce(double v, int op);
 
-// ---------------------------------------------------------------- GSRB sweep in one pass
-// Element offset (component 0) of box-local cell (x, y, z) of a FAB, x in
-// [-ng, ex+ng), y and z in the grown box: a row cell, or the x ghost slab.
-__device__ __forceinline__ int64_t fab_cell(const DevBox& B, int x, int y, int z) {
-  if (x < 0) return B.xs + (int64_t)z * B.xs_z + (int64_t)y * B.ng + (-1 - x);
-  if (x >= B.ex) return B.xs + B.xs_side + (int64_t)z * B.xs_z + (int64_t)y * B.ng + (x - B.ex);
-  return B.off + x + (int64_t)y * B.sy + (int64_t)z * B.sz;
-}
-
-// One whole red-black sweep (red first) in one pass, from phi (2 ghost layers
-// filled) into out, on a level whose ghost cells are all covered (periodic,
-// boxes covering the domain).  A workgroup takes a tile of W x H cells (W, H
-// <= 32, W*H <= 256) and marches up z.  For each plane k it holds in LDS the old
-// values of planes k-1..k+1 over the tile and a 2-cell ring, computes the new
-// red values of plane k over the tile and a 1-cell ring from them (the ring's
-// are exactly what the neighbouring boxes compute for those cells), then the
-// new black values of plane k-1 from the new red values of planes k-2..k, and
-// stores plane k-1.  Every cell update is the GSRB expression of the two-pass
-// form, on the same operands.  RES: also the residual of the old state (the
-// state after the previous sweep), r = f + (s - 6 phi) / h2 in FP64 from
-// promoted values, r^2 summed into partials[workgroup].
-template <typename T, bool RES>
-__global__ void __launch_bounds__(256)
-    k_gsrb_sweep1(const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes, const T* phi_, T* out_,
-                  const T* f_, T h2, T inv6, double inv_h2d, double* __restrict__ partials) {
-  constexpr int NOLD = 432, NRING = 340;  // (W+4)(H+4) and (W+2)(H+2) at most
-  __shared__ T sold[3][NOLD];
-  __shared__ T sred[3][NRING];
-  __shared__ T sf[3][NRING];
-  const DevTile tl = ldc(tiles + logical_block());
-  const DevBox B = ldc(boxes + tl.box);
-  const BL_GLOBAL T* __restrict__ phi = as_global(phi_);
-  const BL_GLOBAL T* __restrict__ f = as_global(f_);
-  BL_GLOBAL T* __restrict__ out = as_global(out_);
-  const int l = (int)threadIdx.x;
-  const int W = tl.nvt, H = tl.rows, x0 = tl.xv0, y0 = tl.y0, z0 = tl.z0, z1 = tl.z1;
-  const int ow = W + 4, rw = W + 2, nold = ow * (H + 4), nring = rw * (H + 2);
-  const int par0 = B.glo[0] + B.glo[1] + B.glo[2];
-  // this lane's two old-ring items and two f-ring items: offset at z = 0 and z stride
-  int64_t oa[2], ost[2], fa[2], fst[2];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int i = l + 256 * q;
-    const int ii = i < nold ? i : 0, jj = i < nring ? i : 0;
-    const int ox = x0 + ii % ow - 2, oy = y0 + ii / ow - 2;
-    oa[q] = fab_cell(B, ox, oy, 0);
-    ost[q] = (ox < 0 || ox >= B.ex) ? B.xs_z : B.sz;
-    const int fx = x0 + jj % rw - 1, fy = y0 + jj / rw - 1;
-    fa[q] = fab_cell(B, fx, fy, 0);
-    fst[q] = (fx < 0 || fx >= B.ex) ? B.xs_z : B.sz;
-  }
-  const bool has_o0 = l < nold, has_o1 = l + 256 < nold, has_f0 = l < nring, has_f1 = l + 256 < nring;
-  auto bz = [&](int z) { return (z - z0 + 3) % 3; };  // buffer of plane z (z >= z0 - 2)
-  // planes z0-2 and z0-1 of the old values into LDS; plane z0 and f of plane z0-1 in registers
-#pragma unroll
-  for (int z = -2; z < 0; ++z) {
-    if (has_o0) sold[bz(z0 + z)][l] = phi[oa[0] + (z0 + z) * ost[0]];
-    if (has_o1) sold[bz(z0 + z)][l + 256] = phi[oa[1] + (z0 + z) * ost[1]];
-  }
-  T po0 = has_o0 ? phi[oa[0] + z0 * ost[0]] : T(0), po1 = has_o1 ? phi[oa[1] + z0 * ost[1]] : T(0);
-  T pf0 = has_f0 ? f[fa[0] + (z0 - 1) * fst[0]] : T(0), pf1 = has_f1 ? f[fa[1] + (z0 - 1) * fst[1]] : T(0);
-  const bool cell = l < W * H;
-  const int cx = cell ? l % W : 0, cy = cell ? l / W : 0;
-  double acc = 0.0;
-  for (int k = z0 - 1; k <= z1; ++k) {
-    // old plane k+1 and f of plane k into LDS; the next ones into registers
-    if (has_o0) sold[bz(k + 1)][l] = po0;
-    if (has_o1) sold[bz(k + 1)][l + 256] = po1;
-    if (has_f0) sf[bz(k)][l] = pf0;
-    if (has_f1) sf[bz(k)][l + 256] = pf1;
-    if (k + 1 <= z1) {
-      if (has_o0) po0 = phi[oa[0] + (int64_t)(k + 2) * ost[0]];
-      if (has_o1) po1 = phi[oa[1] + (int64_t)(k + 2) * ost[1]];
-      if (has_f0) pf0 = f[fa[0] + (int64_t)(k + 1) * fst[0]];
-      if (has_f1) pf1 = f[fa[1] + (int64_t)(k + 1) * fst[1]];
-    }
-    lds_sync();
-    // new red values of plane k over the tile and its 1-cell ring
-    const T* om = sold[bz(k - 1)];
-    const T* oc = sold[bz(k)];
-    const T* op = sold[bz(k + 1)];
-    T* rk = sred[bz(k)];
-    const T* fk = sf[bz(k)];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int j = l + 256 * q;
-      if (j >= nring) continue;
-      const int rx = j % rw, ry = j / rw;
-      if (((par0 + x0 + rx - 1 + y0 + ry - 1 + k) & 1) != 0) continue;  // black cell
-      const int o = (ry + 1) * ow + rx + 1;
-      rk[j] = gsrb_cell(oc[o - 1], oc[o + 1], oc[o - ow], oc[o + ow], om[o], op[o], fk[j], h2, inv6);
-    }
-    if (RES && cell && k >= z0 && k < z1) {  // residual of the old state at the tile's cells
-      const int o = (cy + 2) * ow + cx + 2;
-      const double sv = (((double)oc[o - 1] + (double)oc[o + 1]) + ((double)oc[o - ow] + (double)oc[o + ow])) +
-                        ((double)om[o] + (double)op[o]);
-      const double r = (double)fk[(cy + 1) * rw + cx + 1] + (sv - 6.0 * (double)oc[o]) * inv_h2d;
-      acc += r * r;
-    }
-    lds_sync();
-    // plane k-1: red cells keep their new value, black cells solve from the new reds
-    if (cell && k - 1 >= z0) {
-      const int z = k - 1;
-      const int j = (cy + 1) * rw + cx + 1;
-      const T* rc = sred[bz(z)];
-      T v;
-      if (((par0 + x0 + cx + y0 + cy + z) & 1) == 0) {
-        v = rc[j];
-      } else {
-        v = gsrb_cell(rc[j - 1], rc[j + 1], rc[j - rw], rc[j + rw], sred[bz(z - 1)][j], sred[bz(z + 1)][j],
-                      sf[bz(z)][j], h2, inv6);
-      }
-      out[fab_cell(B, x0 + cx, y0 + cy, z)] = v;
-    }
-  }
-  if (RES) {
-    const double r = block_reduce(acc, R_SUM);
-    if (threadIdx.x == 0) partials[logical_block()] = r;
-  }
-}
-
 // GSRB colour pass, fused with the ghost fill (neighbour boxes read through the
 // face records), in place.  color 0 (red: even global i+j+k) or 1 (black)
 // updates that colour's cells; every lane stores its whole vector, the other
@@ -2038,28 +1917,6 @@ hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, int ntiles, co
     else
       hipLaunchKernelGGL((k_heat8<float, 1>), dim3(ntiles), dim3(256), lds, s, tiles, boxes, (const float*)u,
                          (float*)w, (float)c, ldw, ldh);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_gsrb_sweep1(int dtype, const DevTile* tiles, int ntiles, const DevBox* boxes, const void* phi,
-                              void* out, const void* f, double h2, double* partials, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  if (dtype == BL_F64) {
-    if (partials)
-      hipLaunchKernelGGL((k_gsrb_sweep1<double, true>), dim3(ntiles), dim3(256), 0, s, tiles, boxes,
-                         (const double*)phi, (double*)out, (const double*)f, h2, 1.0 / 6.0, 1.0 / h2, partials);
-    else
-      hipLaunchKernelGGL((k_gsrb_sweep1<double, false>), dim3(ntiles), dim3(256), 0, s, tiles, boxes,
-                         (const double*)phi, (double*)out, (const double*)f, h2, 1.0 / 6.0, 1.0 / h2, partials);
-  } else {
-    const float h2f = (float)h2, inv6f = (float)(1.0 / 6.0);
-    if (partials)
-      hipLaunchKernelGGL((k_gsrb_sweep1<float, true>), dim3(ntiles), dim3(256), 0, s, tiles, boxes,
-                         (const float*)phi, (float*)out, (const float*)f, h2f, inv6f, 1.0 / h2, partials);
-    else
-      hipLaunchKernelGGL((k_gsrb_sweep1<float, false>), dim3(ntiles), dim3(256), 0, s, tiles, boxes,
-                         (const float*)phi, (float*)out, (const float*)f, h2f, inv6f, 1.0 / h2, partials);
   }
   return hipGetLastError();
 }

@@ -100,12 +100,6 @@ hipError_t launch_prolong_add(const Plan& fine, const Plan& coarse, void* phi, c
 hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, int ntiles, const DevBox* boxes, const void* u,
                         void* w, double c, int rmax, int nvtmax, hipStream_t s);
 
-// One whole red-black sweep in one pass, phi -> out (phi's 2 ghost layers and
-// f's ghosts filled; every ghost covered); with partials, per-workgroup sums of
-// the squared residual of phi.  Tiles from build_g1_tiles.
-hipError_t launch_gsrb_sweep1(int dtype, const DevTile* tiles, int ntiles, const DevBox* boxes, const void* phi,
-                              void* out, const void* f, double h2, double* partials, hipStream_t s);
-
 int device_cu_count();
 
 }  // namespace bl

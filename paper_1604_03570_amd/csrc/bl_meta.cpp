@@ -513,32 +513,6 @@ void build_h8_tiles(const Plan& p, std::vector<DevTile>& tiles, int* rmax, int* 
   }
 }
 
-void build_g1_tiles(const Plan& p, std::vector<DevTile>& tiles) {
-  tiles.clear();
-  for (int b = 0; b < (int)p.hboxes.size(); ++b) {
-    const DevBox& B = p.hboxes[b];
-    const int W = std::min(B.ex, 32);
-    const int H = std::max(1, std::min({B.ey, 32, 256 / W}));
-    for (int n = 0; n < p.ncomp; ++n)
-      for (int z0 = 0; z0 < B.ez; z0 += 64)
-        for (int y0 = 0; y0 < B.ey; y0 += H)
-          for (int x0 = 0; x0 < B.ex; x0 += W) {
-            DevTile t;
-            std::memset(&t, 0, sizeof t);
-            t.box = b;
-            t.comp = n;
-            t.xv0 = x0;
-            t.nvt = std::min(W, B.ex - x0);
-            t.y0 = y0;
-            t.rows = std::min(H, B.ey - y0);
-            t.z0 = z0;
-            t.z1 = std::min(z0 + 64, B.ez);
-            for (int f = 0; f < 6; ++f) t.frec[f] = kFaceNone;
-            tiles.push_back(t);
-          }
-  }
-}
-
 size_t lin_lds_bytes(const TileConfig& cfg, int esize, int vec, int yhmax, int xhmax) {
   const size_t zb = (size_t)cfg.zchunk, vb = (size_t)esize * vec;
   return zb * 64 * cfg.waves * vb + zb * 2 * yhmax * vb + zb * 2 * xhmax * esize;
@@ -806,11 +780,6 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
   for (const DevTile& t : p->htiles) {
     p->rmax = std::max<int>(p->rmax, t.rows);
     p->nvtmax = std::max<int>(p->nvtmax, t.nvt);
-  }
-  {
-    int64_t vol = 0;
-    for (const Box& b : p->boxes) vol += b.volume();
-    p->covers = vol == p->domain.volume();  // the boxes are disjoint and inside the domain
   }
   // flattened cell and x-pair counts (grid transfers between multigrid levels)
   {
