@@ -178,3 +178,16 @@ def test_mg_degenerate_calls(bt):
         dom = I.domain_box(6)
         odd = bt.BoxArray.from_boxes(I.regular_chop(dom, 3), dom)
         bt.prolong_add(bt.MultiFab(odd, 1, 1, bt.F64), bt.MultiFab(bt.BoxArray.chop(I.domain_box(3), 3), 1, 1, bt.F64))
+
+
+def test_repeated_vcycle_calls_on_one_hierarchy(bt):
+    """Several calls on one hierarchy, with other sweep counts and another h2, continue
+    from the state left by the last one and give the oracle's bits."""
+    P = _problem(bt, "uneven64", bt.F64, seed=9)
+    mg = bt.Multigrid(P["ba"], bt.F64)
+    h2 = P["h2"]
+    plan = [(1, 2, 2, 8, h2), (2, 2, 2, 8, h2), (1, 1, 3, 5, h2), (1, 2, 2, 8, 2.0 * h2)]
+    for cycles, nu1, nu2, nub, hh in plan:
+        mg.vcycles(P["phi"], P["f"], hh, cycles, nu1, nu2, nub, with_norms=(cycles == 2))
+        O.mg_vcycles(P["ophi"], P["of"], hh, cycles, nu1, nu2, nub)
+        assert np.array_equal(gpu_global(P["phi"]), P["ophi"].to_global()), (cycles, nu1, nu2, nub)
