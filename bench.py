@@ -277,7 +277,8 @@ def gsrb_run(bt, I, torch, seed: int, sweeps: int = 20) -> dict:
         cs = n ** 3 * sweeps / (ms / 1e3)
         out[form] = {"ms_per_sweep": round(ms / sweeps, 4), "gcell_sweeps_s": round(cs / 1e9, 2),
                      "hbm_frac_at_12B": round(cs * 12 / (HBM_PEAK_GBS * 1e9), 4),
-                     "resnorm_first": norms[0], "resnorm_last": norms[-1]}
+                     "resnorm_first": norms[0], "resnorm_last": norms[-1],
+                     "resnorm_h32_first": norms[0] * (1.0 / n) ** 1.5, "resnorm_h32_last": norms[-1] * (1.0 / n) ** 1.5}
         log(f"gsrb {form}: {ms / sweeps:.3f} ms per sweep, {cs / 1e9:.1f} G cell-sweeps/s, "
             f"norm {norms[0]:.4e} -> {norms[-1]:.4e}")
         del phi, fm
@@ -403,6 +404,61 @@ def heat8_run(bt, I, torch, boxes, dom, u0, ncomp: int, steps: int = 10) -> dict
     return out
 
 
+def paper_shape_run(bt, I, torch, steps: int = 1000) -> dict:
+    """The paper's own workload as context: one 128^3 periodic box, FP64, 1000 fused
+    FillBoundary + heat steps (the paper times the kernel alone, on CPUs)."""
+    n = 128
+    dom = I.domain_box(n)
+    ba = bt.BoxArray.chop(dom, n)
+    a, b = bt.MultiFab(ba, 1, 1, bt.F64), bt.MultiFab(ba, 1, 1, bt.F64)
+    a.from_global(I.gaussian(n))
+    c = I.heat_c(n)
+    bt.heat_advance(a, b, steps, c)  # captures the graph; 1000 even: the state is back in a
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    bt.heat_advance(a, b, steps, c)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    g = n ** 3 * steps / (ms / 1e3) / 1e9
+    out = {"workload": f"{n}^3 periodic, one box, FP64, {steps} fused steps", "ms": round(ms, 3),
+           "gcell_s": round(g, 2),
+           "paper_cpu_context": {"one_core_tiled_gcell_s": 0.247, "twelve_threads_tiled_gcell_s": 2.2,
+                                 "note": "kernel time only, Ivy Bridge (Table 1 and the 12-thread speedup)"}}
+    log(f"paper's shape: 128^3 x {steps} steps in {ms:.1f} ms, {g:.1f} GCell/s")
+    del a, b, ba
+    torch.cuda.empty_cache()
+    return out
+
+
+def copy_line(bt, torch, nbytes: int = COPY_BYTES) -> dict:
+    """Device copies of nbytes timed with events, the attainable HBM line: the library's
+    plain streaming copy (16-byte lanes, 4 KB per workgroup) and torch's copy_."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    out = {"bytes": nbytes}
+    for name, fn in (("library", lambda: bt.device_copy(dst, src)), ("torch", lambda: dst.copy_(src))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        gbs = 2 * nbytes / (ms / 1e3) / 1e9
+        out[name] = {"ms": round(ms, 4), "gbs_read_plus_write": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"device copy ({name}): {gbs:.0f} GB/s read + write")
+    assert torch.equal(dst, src)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -520,9 +576,18 @@ def main() -> int:
         e3.record(stream)
         torch.cuda.synchronize()
         per_launch_ms = (e2.elapsed_time(e3) - ms) / steps
-        return ms, wall, drift, ba, a, b, per_launch_ms, tuned
+        # five more timings of the K-step graph from cur (the same work each time):
+        # their median and minimum
+        reps = []
+        for _ in range(5):
+            e2.record(stream)
+            bt.heat_advance(cur, oth, steps, c)
+            e3.record(stream)
+            torch.cuda.synchronize()
+            reps.append(e2.elapsed_time(e3) / steps)
+        return ms, wall, drift, ba, a, b, per_launch_ms, tuned, reps
 
-    ms, wall, drift, ba, a, b, per_launch_ms, tuned = run(args.dtype, args.steps, args.warmup)
+    ms, wall, drift, ba, a, b, per_launch_ms, tuned, reps = run(args.dtype, args.steps, args.warmup)
     esize = 8 if args.dtype == "f64" else 4
     sec = ms / 1e3
     value = cells * args.steps / sec / 1e9
@@ -534,7 +599,9 @@ def main() -> int:
 
     extra = {"sum_drift_rel": drift, "wall_ms_timed": round(wall * 1e3, 4),
              "tile_shape": tuned["best"] if tuned else list(cfg_tile), "autotune": tuned,
-             "nboxes": len(boxes), "fused_kernel_ms_per_launch": round(per_launch_ms, 5)}
+             "nboxes": len(boxes), "fused_kernel_ms_per_launch": round(per_launch_ms, 5),
+             "ms_per_step_repeats": {"n": len(reps), "median": round(float(np.median(reps)), 5),
+                                     "min": round(min(reps), 5)}}
     if not args.no_extra:
         # unfused form: fill kernel and stencil kernel timed apart (fill fraction)
         stream = torch.cuda.current_stream()
@@ -575,7 +642,7 @@ def main() -> int:
         del a, b, ba
         torch.cuda.empty_cache()
         if args.dtype == "f64":
-            ms32, _, drift32, ba32, a32, b32, _, tuned32 = run("f32", args.steps, args.warmup)
+            ms32, _, drift32, ba32, a32, b32, _, tuned32, _ = run("f32", args.steps, args.warmup)
             v32 = cells * args.steps / (ms32 / 1e3) / 1e9
             extra["f32_gcell_s"] = round(v32, 2)
             extra["f32_ms_per_step"] = round(ms32 / args.steps, 5)
@@ -585,6 +652,10 @@ def main() -> int:
             log(f"f32: {v32:.1f} GCell/s")
             del a32, b32, ba32
             torch.cuda.empty_cache()
+
+    if not args.no_extra and args.dtype == "f64":
+        extra["copy_line"] = copy_line(bt, torch)
+        extra["paper_shape"] = paper_shape_run(bt, I, torch)
 
     if not args.no_extra and not args.no_varcoef and args.dtype == "f64":
         extra["varcoef"] = varcoef_run(bt, I, torch, boxes, dom, u0, ncomp, args.seed, 20)

@@ -384,6 +384,16 @@ bl_status bl_reduce(const bl_multifab* mf, int32_t comp, bl_reduce_op op, double
 bl_status bl_reduce_async(const bl_multifab* mf, int32_t comp, bl_reduce_op op, double* out_dev,
                           hipStream_t stream);
 
+/* ------------------------------------------------------------ device copy */
+
+/*
+ * dst[0..bytes) = src[0..bytes) on the device, one 16-byte vector per lane and
+ * one 4 KB chunk per workgroup: the plain streaming copy that serves as the
+ * attainable-bandwidth line for the stencils.  dst, src and bytes must be
+ * multiples of 16 and the ranges must not overlap (BL_EINVAL).  Asynchronous.
+ */
+bl_status bl_device_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------ launch tuning */
 
 /*

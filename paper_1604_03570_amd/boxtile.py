@@ -70,6 +70,7 @@ _SIGS = {
     "bl_heat_advance": [_vpp, _i32, ctypes.c_double, _vp],
     "bl_heat_varcoef_advance": [_vpp, _vp, _i32, ctypes.c_double, ctypes.c_double, _vp],
     "bl_heat8_advance": [_vpp, _i32, ctypes.c_double, _vp],
+    "bl_device_copy": [_vp, _vp, ctypes.c_size_t, _vp],
     "bl_heat_step_unfused": [_vp, _vp, ctypes.c_double, _vp],
     "bl_gsrb_sweeps": [_vp, _vp, ctypes.c_double, _i32, _dp, _vp],
     "bl_residual_norm": [_vp, _vp, ctypes.c_double, _dp, _vp],
@@ -466,6 +467,14 @@ def heat_advance(u0: MultiFab, u1: MultiFab, nsteps: int, c: float, stream=None)
     arr = (ctypes.c_void_p * 2)(u0.handle.value, u1.handle.value)
     _check(_L.bl_heat_advance(arr, int(nsteps), float(c), _stream(stream)))
     return u0 if nsteps % 2 == 0 else u1
+
+
+def device_copy(dst: torch.Tensor, src: torch.Tensor, stream=None) -> None:
+    """dst = src (contiguous device tensors of the same byte size, 16-byte multiples)."""
+    if dst.nbytes != src.nbytes or not dst.is_contiguous() or not src.is_contiguous():
+        raise ValueError("device_copy needs contiguous tensors of one byte size")
+    _check(_L.bl_device_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), dst.nbytes,
+                             _stream(stream)))
 
 
 def heat8_advance(u0: MultiFab, u1: MultiFab, nsteps: int, c: float, stream=None) -> MultiFab:

@@ -905,6 +905,19 @@ bl_status bl_mg_vcycles(bl_mg* mg, bl_multifab* phi, const bl_multifab* f, doubl
   return BL_OK;
 }
 
+bl_status bl_device_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  clear_error();
+  if (bytes == 0) return BL_OK;
+  if (!dst || !src) return fail(BL_EINVAL, "NULL pointer");
+  if (((uintptr_t)dst | (uintptr_t)src | bytes) % 16 != 0)
+    return fail(BL_EINVAL, "pointers and size must be multiples of 16 bytes");
+  const uintptr_t d = (uintptr_t)dst, s0 = (uintptr_t)src;
+  if (d < s0 + bytes && s0 < d + bytes) return fail(BL_EINVAL, "source and destination overlap");
+  if (bytes / 16 / 256 >= (size_t)UINT32_MAX) return fail(BL_EINVAL, "copy too large for one launch");
+  BL_HIP(launch_copy16(dst, src, bytes, stream));
+  return BL_OK;
+}
+
 bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int32_t block) {
   clear_error();
   if (zchunk < 1 || zchunk > 16384 || waves < 1 || waves > kStencilMaxThreads / 64 || persist < 0 ||

@@ -1921,6 +1921,22 @@ hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, int ntiles, co
   return hipGetLastError();
 }
 
+// Plain device copy of nvec 16-byte vectors: one 4 KB chunk per workgroup, one
+// vector per lane (the shape that reached the highest copy bandwidth here).
+__global__ void __launch_bounds__(256) k_copy16(const Vec<double, 2>* src_, Vec<double, 2>* dst_, int64_t nvec) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < nvec) as_global(dst_)[i] = as_global(src_)[i];
+}
+
+hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const int64_t nvec = (int64_t)(bytes / 16);
+  if (nvec == 0) return hipSuccess;
+  const int64_t g = (nvec + 255) / 256;
+  hipLaunchKernelGGL(k_copy16, dim3((unsigned)g), dim3(256), 0, s, (const Vec<double, 2>*)src, (Vec<double, 2>*)dst,
+                     nvec);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_partials(const double* partials, int n, int take_sqrt, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, s, partials, n, (int)R_SUM, take_sqrt, out);
   return hipGetLastError();

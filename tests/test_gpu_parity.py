@@ -474,3 +474,12 @@ def test_degenerate_calls(bt):
             call()
         assert e.value.code == bt.BL_EINVAL
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 16, 64 << 20])
+def test_device_copy(bt, nbytes):
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros_like(src)
+    bt.device_copy(dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)

@@ -259,3 +259,15 @@ def test_multifab_bytes_cover_the_grown_boxes():
     for dtype, es in ((bt.F64, 8), (bt.F32, 4)):
         nb = ba.multifab_bytes(3, 1, dtype)
         assert 3 * grown * es <= nb <= 3 * grown * es * 1.35
+
+
+def test_device_copy_refuses_bad_arguments_before_any_launch():
+    """Argument errors return BL_EINVAL without touching a device (this runs on the CPU)."""
+    import ctypes
+    from paper_1604_03570_amd import boxtile as bt
+    L = bt.lib()
+    vp = ctypes.c_void_p
+    assert L.bl_device_copy(vp(0x1000), vp(0x9000), 0, None) == bt.BL_OK  # nothing to copy
+    for dst, src, n in [(0, 0x9000, 64), (0x1000, 0, 64), (0x1008, 0x9000, 64), (0x1000, 0x9000, 24),
+                        (0x1000, 0x1010, 64)]:
+        assert L.bl_device_copy(vp(dst), vp(src), n, None) != bt.BL_OK, (dst, src, n)
