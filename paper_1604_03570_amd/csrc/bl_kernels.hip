@@ -120,14 +120,30 @@ __device__ __forceinline__ T gsrb_cell(T xm, T xp, T ym, T yp, T zm, T zp, T fv,
   return ((((xm + xp) + (ym + yp)) + (zm + zp)) + h2 * fv) * inv6;
 }
 
-// Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each
-// XCD's workgroups take one contiguous eighth of the tile list (neighbouring
-// tiles then share that XCD's L2).  Bijective on [0, gridDim.x).
+// Workgroups are dealt round-robin to the 8 XCDs; renumber them so that the
+// tile list is cut into chunks of kXcdChunk consecutive tiles dealt to the XCDs
+// in turn.  A chunk's tiles share one XCD's L2, and all XCDs move through the
+// list together, so boxes next to each other in the list (and their shared
+// faces) are worked on at about the same time.  On the 512^3 uneven level this
+// ran at 70% of the HBM peak against 68% for one contiguous eighth per XCD and
+// 64% for plain round-robin.  A launch of fewer than kXcdChunkedFrom
+// workgroups (about two rounds of resident ones) runs nearly all at once, so
+// only L2 reuse between neighbouring tiles matters: it keeps one contiguous
+// eighth per XCD (one 128^3 box: 236 against 195 GCell/s chunked).  Past the
+// last whole round of chunks, workgroups keep their numbers.  Bijective on
+// [0, gridDim.x).
+constexpr int kXcdChunk = 16;
+constexpr int kXcdChunkedFrom = 4096;
 __device__ __forceinline__ int logical_block() {
   const int G = gridDim.x;
   const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
-  const int per = G >> 3, rem = G & 7;
-  return x * per + (x < rem ? x : rem) + q;
+  if (G < kXcdChunkedFrom) {
+    const int per = G >> 3, rem = G & 7;
+    return x * per + (x < rem ? x : rem) + q;
+  }
+  const int full = G / (8 * kXcdChunk) * (8 * kXcdChunk);
+  if ((int)blockIdx.x >= full) return (int)blockIdx.x;
+  return (q / kXcdChunk) * (8 * kXcdChunk) + x * kXcdChunk + q % kXcdChunk;
 }
 
 // Tiles of this workgroup: one tile, or (persistent grid) a contiguous range
