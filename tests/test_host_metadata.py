@@ -171,7 +171,7 @@ def test_tile_list_covers_every_cell_once(dtype, boxes_kind):
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
-@pytest.mark.parametrize("boxes_kind", ["regular", "uneven", "odd"])
+@pytest.mark.parametrize("boxes_kind", ["regular", "uneven", "odd", "cells"])
 @pytest.mark.parametrize("shape", [(4, 4), (2, 4), (8, 2), (4, 3)])
 def test_stencil_tiles_cover_every_cell_once(dtype, boxes_kind, shape):
     """Linear tiles (runs of consecutive vectors of a plane, whole planes stacked in z
@@ -182,9 +182,12 @@ def test_stencil_tiles_cover_every_cell_once(dtype, boxes_kind, shape):
     elif boxes_kind == "uneven":
         dom = I.domain_box(128)
         boxes = I.random_chop(dom, 16, 64, 8, seed=3)
-    else:
+    elif boxes_kind == "odd":
         dom = I.domain_box((21, 13, 9))
         boxes = I.random_chop(dom, 3, 8, 1, seed=5)
+    else:  # boxes of one and two cells, as on the coarse levels of a V-cycle
+        dom = I.domain_box((6, 4, 4))
+        boxes = I.random_chop(dom, 1, 2, 1, seed=7)
     ncomp = 2
     saved = bt.get_tile_config()
     bt.set_tile_config(shape[0], shape[1], 0, 3)
