@@ -1116,15 +1116,31 @@ __global__ void __launch_bounds__(256)
     px += xh_step;
     lds_sync();
     if (active) {
-      const T* row = buf + own;
+      // neighbours as whole aligned vectors (one 16-byte LDS read each: reading
+      // single elements of neighbouring vectors makes lanes 16 bytes apart and
+      // doubles the bank conflicts); x: the K vectors on each side, y: the
+      // vectors of the rows 1..4 below and above
+      const VT* rv = reinterpret_cast<const VT*>(buf + own);
+      constexpr int K = (4 + V - 1) / V;
+      const int lv = ldw / V;
+      VT X[2 * K + 1];
+#pragma unroll
+      for (int i = 0; i < 2 * K + 1; ++i) X[i] = i == K ? Q[4] : rv[i - K];
+      VT Ym[4], Yp[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        Ym[m] = rv[-(m + 1) * lv];
+        Yp[m] = rv[(m + 1) * lv];
+      }
+      auto xat = [&](int d) -> T { return X[(d + K * V) / V].v[(d + K * V) % V]; };  // cell d of the row
       VT o;
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         const T uc = Q[4].v[e];
-        const T px1 = row[e - 1] + row[e + 1], px2 = row[e - 2] + row[e + 2];
-        const T px3 = row[e - 3] + row[e + 3], px4 = row[e - 4] + row[e + 4];
-        const T py1 = row[e - ldw] + row[e + ldw], py2 = row[e - 2 * ldw] + row[e + 2 * ldw];
-        const T py3 = row[e - 3 * ldw] + row[e + 3 * ldw], py4 = row[e - 4 * ldw] + row[e + 4 * ldw];
+        const T px1 = xat(e - 1) + xat(e + 1), px2 = xat(e - 2) + xat(e + 2);
+        const T px3 = xat(e - 3) + xat(e + 3), px4 = xat(e - 4) + xat(e + 4);
+        const T py1 = Ym[0].v[e] + Yp[0].v[e], py2 = Ym[1].v[e] + Yp[1].v[e];
+        const T py3 = Ym[2].v[e] + Yp[2].v[e], py4 = Ym[3].v[e] + Yp[3].v[e];
         const T pz1 = Q[3].v[e] + Q[5].v[e], pz2 = Q[2].v[e] + Q[6].v[e];
         const T pz3 = Q[1].v[e] + Q[7].v[e], pz4 = Q[0].v[e] + Q[8].v[e];
         const T Dx = ((A1 * px1 + A2 * px2) + A3 * px3) + A4 * px4;
