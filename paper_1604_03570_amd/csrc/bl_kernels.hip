@@ -1107,13 +1107,15 @@ __global__ void __launch_bounds__(256)
     yh_at = comp0 + x0 + xv * V + (int64_t)y * B.sy;
     yh_slot = (r < 4 ? r : rows + r) * ldw + 4 + xv * V;
   }
-  // x halo: 4 values left and right of each row, one per lane; a value beyond
-  // the box's x range comes from the x ghost slab (layer = distance from the face - 1)
+  // x halo: 4 values left and right of each row, one per lane, the 4 values of
+  // a row side in 4 consecutive lanes (adjacent addresses, so a wave touches a
+  // quarter of the lines it would with one row per lane); a value beyond the
+  // box's x range comes from the x ghost slab (layer = distance from the face - 1)
   const bool hx = l < 8 * rows;
   int64_t xh_at = col, xh_step = sz;
   int xh_slot = 0;
   if (hx) {
-    const int side = l / (4 * rows), rem = l - side * 4 * rows, m = rem / rows, yr = rem - m * rows;
+    const int side = l / (4 * rows), rem = l - side * 4 * rows, m = rem & 3, yr = rem >> 2;
     const int y = tl.y0 + yr;
     const int x = side ? x0 + W + m : x0 - 1 - m;
     if (x < 0 || x >= B.ex) {
