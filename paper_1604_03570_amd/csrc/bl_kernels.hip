@@ -728,8 +728,9 @@ __device__ __forceinline__ T lane_shift(T v) { return v; }
 // from the adjacent lanes by DPP, so LDS is read only at run and row ends and
 // at the first and last lane of a wave (reading single elements of
 // neighbouring vectors from LDS puts lanes 16 bytes apart and doubles the bank
-// conflicts).  Measured: the GSRB pass 4% faster, the variable-coefficient
-// kernel 1%, the 7-point heat kernel 1% slower (it keeps the LDS reads).
+// conflicts).  Measured on one GPU against LDS reads: the GSRB pass 5-6%
+// faster (it takes DPP); the 7-point heat kernel 1% and the
+// variable-coefficient kernel 2% slower (they keep the LDS reads).
 template <typename T, int V, int ZB, bool DPP>
 __device__ __forceinline__ Nbr<T, V> tile_neighbours(const TileLds<T, V>& S, const LinLane& L, const DevLinTile& tl,
                                                      int nvx, int k, const Vec<T, V>& own) {
@@ -899,8 +900,8 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
     for (int e = 0; e < V; ++e) fz[e] = face_flux(P[0].v[e], P[1].v[e], Q[0].v[e], Q[1].v[e], inv_dx);
 #pragma unroll
     for (int k = 0; k < ZB; ++k) {
-      const Nbr<T, V> N = tile_neighbours<T, V, ZB, true>(S, L, tl, nvx, k, P[k + 1]);
-      const Nbr<T, V> NB = tile_neighbours<T, V, ZB, true>(Sb, L, tl, nvx, k, Q[k + 1]);
+      const Nbr<T, V> N = tile_neighbours<T, V, ZB, false>(S, L, tl, nvx, k, P[k + 1]);
+      const Nbr<T, V> NB = tile_neighbours<T, V, ZB, false>(Sb, L, tl, nvx, k, Q[k + 1]);
       const VT& c = P[k + 1];
       const VT& cbeta = Q[k + 1];
       T fx = face_flux(N.left, c.v[0], NB.left, cbeta.v[0], inv_dx);  // lower x face of element 0
