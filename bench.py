@@ -29,6 +29,7 @@ METRIC = "GCell-updates/s + % HBM roofline (heat_step+FillBoundary); p50/p99 ser
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 2 << 30
 CPU_SAMPLE_SECONDS = 10.0
+CPU_SAMPLE_SECONDS_1T = 5.0   # the one-thread sample of the oracle (at least one step)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat_fused_512cube_uneven_5comp_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1604_03570_amd", "csrc", "bl_kernels.hip")
 
@@ -75,15 +76,44 @@ def cpu_baseline(boxes, dom, u0, c, nthreads_note: str):
         if dt >= CPU_SAMPLE_SECONDS or nsteps >= 200:
             break
     cells = sum(int(np.prod(b[3:] - b[:3] + 1)) for b in boxes) * u0.shape[0]
-    log(f"cpu baseline: {nsteps} step(s) in {dt:.2f} s (setup {setup:.1f} s), {O.num_threads()} threads")
+    cores = O.num_threads()
+    log(f"cpu baseline: {nsteps} step(s) in {dt:.2f} s (setup {setup:.1f} s), {cores} threads")
+    # the same steps on one thread, a shorter sample
+    O.set_num_threads(1)
+    n1 = 0
+    t0 = time.perf_counter()
+    try:
+        while True:
+            O.heat_step(m, w, c)
+            m, w = w, m
+            n1 += 1
+            dt1 = time.perf_counter() - t0
+            if dt1 >= CPU_SAMPLE_SECONDS_1T or n1 >= 200:
+                break
+    finally:
+        O.set_num_threads(cores)
+    log(f"cpu baseline, one thread: {n1} step(s) in {dt1:.2f} s")
     return {
         "value": round(cells * nsteps / dt / 1e9, 5),
         "unit": "GCell-updates/s",
-        "cores": O.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"{nsteps} full steps (FillBoundary + 7-point update each) of the same workload, FP64, "
                   f"OpenMP over boxes ({nthreads_note})",
+        "single_thread": {"value": round(cells * n1 / dt1 / 1e9, 5), "steps": n1},
+        "host": {"cpu": host_cpu_model(), "nproc": os.cpu_count()},
     }
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 PROFILE_ARGS = "--steps 20 --warmup 2 --no-cpu-baseline --no-extra --calibrate-copy --zchunk 4 --waves 4 --block 3"

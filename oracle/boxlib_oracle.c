@@ -61,6 +61,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Thread count of the box loops from here on (n > 0); used to time the oracle
+ * on one thread beside its all-cores run. */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 typedef struct {
   int nx, ny, nz;      /* grown extents */
   int glo[3];          /* grown lower corner (global index) */

@@ -57,6 +57,8 @@ def build(force: bool = True) -> str:
 
 def _configure(L):
     L.orc_num_threads.restype = ctypes.c_int
+    L.orc_set_num_threads.argtypes = [ctypes.c_int]
+    L.orc_set_num_threads.restype = None
     L.orc_owner_map.argtypes = [ctypes.c_int, _ip, _ip, _i32p]
     L.orc_owner_map.restype = ctypes.c_int
     L.orc_fill_boundary.argtypes = [ctypes.c_int, _ip, _ip, _ip, ctypes.c_int, ctypes.c_int,
@@ -125,6 +127,11 @@ def source() -> str:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the box loops from here on (results do not depend on it)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def _ptr(a, t):
