@@ -6,7 +6,7 @@ import torch
 
 from oracle import oracle as O
 from paper_1604_03570_amd import inputs as I
-from tests.gpu_helpers import lib, say
+from tests.gpu_helpers import lib, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -66,3 +66,35 @@ def test_served_fp64_equals_oracle(bt):
         o.load_global(I.gaussian_separable(r.n, r.center))
         ref = O.heat_advance(o, r.steps, I.heat_c(r.n)).to_global()
         assert np.array_equal(got[r.rid], ref), r
+
+
+def test_serving_stream_sample_against_oracle(bt):
+    """The serving workload's own request stream (2000 requests, 200/s, seed 0, as the
+    bench serves it): the 10 largest requests by cell updates and 10 seeded others,
+    arrivals compressed so that they overlap on the device.  FP64 results equal the
+    oracle bit for bit; FP32 storage stays within 2e-5 relative per 100 steps (each
+    step adds a few FP32 roundings to a contractive update)."""
+    from paper_1604_03570_amd import serve as S
+    stream = I.request_stream(2000, 200.0, seed=0)
+    by_work = sorted(stream, key=lambda r: r.n ** 3 * r.steps, reverse=True)
+    largest = by_work[:10]
+    rest = [r for r in stream if r not in largest]
+    pick = np.random.default_rng(7).choice(len(rest), 10, replace=False)
+    sample = largest + [rest[int(i)] for i in sorted(pick)]
+    reqs = [I.Request(k, 0.002 * k, r.n, r.box_edge, r.steps, r.dtype, r.center) for k, r in enumerate(sample)]
+    got = {}
+    st = S.Server(64 << 30, max_slots=64,
+                  on_complete=lambda r, t: got.__setitem__(r.rid, t.double().cpu().numpy())).run(reqs)
+    say(f"served sample: {st.summary()}")
+    assert st.completed == len(reqs) and st.peak_active > 1
+    for r in reqs:
+        boxes = I.regular_chop(I.domain_box(r.n), min(r.box_edge, r.n))
+        o = O.OracleMultiFab(boxes, I.domain_box(r.n), (1, 1, 1), 1, 1)
+        o.load_global(I.gaussian_separable(r.n, r.center))
+        ref = O.heat_advance(o, r.steps, I.heat_c(r.n)).to_global()
+        if r.dtype == "f64":
+            assert np.array_equal(got[r.rid], ref), r
+        else:
+            err = rel_err(got[r.rid], ref)
+            say(f"request {r.rid}: n {r.n}, {r.steps} steps, f32 rel err {err:.2e}")
+            assert err <= 2e-5 * max(1.0, r.steps / 100.0), r
