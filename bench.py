@@ -402,33 +402,44 @@ def mg_run(bt, I, torch, seed: int, cycles: int = 5) -> dict:
 
 def heat8_run(bt, I, torch, boxes, dom, u0, ncomp: int, steps: int = 10) -> dict:
     """The 8th-order heat step (9-cell span, 4 ghost layers) on the same level and u0, FP64,
-    c = 0.09: FillBoundary of the 4 layers and the stencil, timed per step and apart."""
+    c = 0.09, in both forms: fused (neighbour boxes read directly, the default where the
+    layout allows it) and fill (FillBoundary of the 4 layers, then the stencil; the two
+    timed apart)."""
     n = int(dom[3]) + 1
     ba = bt.BoxArray.from_boxes(boxes, dom)
     a, b = bt.MultiFab(ba, ncomp, 4, bt.F64), bt.MultiFab(ba, ncomp, 4, bt.F64)
     for comp in range(ncomp):
         a.from_global(u0[comp:comp + 1], scomp=comp)
     cells = int(sum(int(np.prod(bx[3:] - bx[:3] + 1)) for bx in boxes)) * ncomp
-    bt.heat8_advance(a, b, 2, 0.09)
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    ev[0].record(stream)
-    bt.heat8_advance(a, b, steps, 0.09)
-    ev[1].record(stream)
-    for _ in range(steps):
-        a.fill_boundary()
-    ev[2].record(stream)
-    torch.cuda.synchronize()
-    ms = ev[0].elapsed_time(ev[1]) / steps
-    fill = ev[1].elapsed_time(ev[2]) / steps
-    kern = ms - fill
-    gbs = 16 * cells / (kern / 1e3) / 1e9
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def per_step(fn):
+        fn(2)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        fn(steps)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / steps
+
+    fill_form = per_step(lambda k: bt.heat8_advance(a, b, k, 0.09, form="fill"))
+    fill = per_step(lambda k: [a.fill_boundary() for _ in range(k)])
+    fused_ok = bt.heat8_fused_ok(a)
+    fused = per_step(lambda k: bt.heat8_advance(a, b, k, 0.09, form="fused")) if fused_ok else None
+    form = bt.heat8_auto_form(a)
+    ms = fused if form == "fused" else fill_form
+    kern = fill_form - fill
+    gbs = 16 * cells / (ms / 1e3) / 1e9
     out = {"workload": f"{n}^3 periodic, {len(boxes)} uneven boxes, {ncomp} comps, 4 ghost layers, FP64",
-           "ms_per_step": round(ms, 4), "fill_ms": round(fill, 4), "stencil_ms": round(kern, 4),
-           "gcell_s": round(cells / (ms / 1e3) / 1e9, 2), "stencil_gbs_at_16B": round(gbs, 1),
-           "stencil_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-    log(f"heat8: {ms:.3f} ms/step (fill {fill:.3f}, stencil {kern:.3f} ms = {gbs:.0f} GB/s at 16 B/cell)")
+           "form": form, "ms_per_step": round(ms, 4),
+           "fused_form_ms_per_step": round(fused, 4) if fused_ok else None,
+           "gcell_s": round(cells / (ms / 1e3) / 1e9, 2), "step_gbs_at_16B": round(gbs, 1),
+           "step_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "fill_form": {"ms_per_step": round(fill_form, 4), "fill_ms": round(fill, 4), "stencil_ms": round(kern, 4),
+                         "stencil_gbs_at_16B": round(16 * cells / (kern / 1e3) / 1e9, 1)}}
+    log(f"heat8: {ms:.3f} ms/step (default: {form} form, {gbs:.0f} GB/s at 16 B/cell); fill form {fill_form:.3f} ms "
+        f"(fill {fill:.3f}, stencil {kern:.3f}); fused form " + (f"{fused:.3f} ms" if fused_ok else "n/a"))
     del a, b, ba
     torch.cuda.empty_cache()
     return out

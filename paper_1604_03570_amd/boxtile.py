@@ -70,6 +70,10 @@ _SIGS = {
     "bl_heat_advance": [_vpp, _i32, ctypes.c_double, _vp],
     "bl_heat_varcoef_advance": [_vpp, _vp, _i32, ctypes.c_double, ctypes.c_double, _vp],
     "bl_heat8_advance": [_vpp, _i32, ctypes.c_double, _vp],
+    "bl_heat8_advance_form": [_vpp, _i32, ctypes.c_double, _i32, _vp],
+    "bl_heat8_fused_ok": [_vp, _i32p],
+    "bl_heat8_fused_layout": [_vp, _i32, _i32, _i32, _i32p, _i32p, _i64p, _i64p],
+    "bl_layout_index": [_vp, _i32, _i32, _i32, _i32, _i32p, _i32, _i64p],
     "bl_device_copy": [_vp, _vp, ctypes.c_size_t, _vp],
     "bl_heat_step_unfused": [_vp, _vp, ctypes.c_double, _vp],
     "bl_gsrb_sweeps": [_vp, _vp, ctypes.c_double, _i32, _dp, _vp],
@@ -253,6 +257,28 @@ class BoxArray:
         _check(_L.bl_tile_boxes(self._h, ts.ctypes.data_as(_i32p), k, int(arg), ctypes.byref(n),
                                 out.ctypes.data_as(_i32p)))
         return out
+
+    def heat8_fused_layout(self, ncomp: int, nghost: int, dtype: int = F64):
+        """Host-only: the fused 8th-order tiles of a MultiFab of this shape, as (tiles, strips,
+        total_elems): tiles rows {box, comp, x0, width, y0, rows, z0, z1, vec} (box-local
+        cells), strips (ntiles, 6, 4) rows {o, sx, sy, sz}.  BoxtileError where the fused form
+        does not apply."""
+        n = ctypes.c_int32()
+        total = ctypes.c_int64()
+        _check(_L.bl_heat8_fused_layout(self._h, ncomp, nghost, dtype, ctypes.byref(n), None, None,
+                                        ctypes.byref(total)))
+        tiles = np.zeros((n.value, 9), dtype=np.int32)
+        strips = np.zeros((n.value, 6, 4), dtype=np.int64)
+        _check(_L.bl_heat8_fused_layout(self._h, ncomp, nghost, dtype, ctypes.byref(n), tiles.ctypes.data_as(_i32p),
+                                        strips.ctypes.data_as(_i64p), ctypes.byref(total)))
+        return tiles, strips, total.value
+
+    def layout_index(self, ncomp: int, nghost: int, dtype: int, box: int, cell, comp: int) -> int:
+        """Host-only: element index of a cell (global indices, in the box's grown box)."""
+        c = (ctypes.c_int32 * 3)(*[int(v) for v in cell])
+        out = ctypes.c_int64()
+        _check(_L.bl_layout_index(self._h, ncomp, nghost, dtype, int(box), c, int(comp), ctypes.byref(out)))
+        return out.value
 
     def multifab_bytes(self, ncomp: int, nghost: int, dtype: int = F64) -> int:
         b = ctypes.c_size_t()
@@ -477,12 +503,31 @@ def device_copy(dst: torch.Tensor, src: torch.Tensor, stream=None) -> None:
                              _stream(stream)))
 
 
-def heat8_advance(u0: MultiFab, u1: MultiFab, nsteps: int, c: float, stream=None) -> MultiFab:
-    """nsteps heat steps with the 8th-order second difference (nghost >= 4): FillBoundary and
-    one stencil launch per step; returns the result holder."""
+H8_FORMS = {"auto": 0, "fill": 1, "fused": 2}
+
+
+def heat8_advance(u0: MultiFab, u1: MultiFab, nsteps: int, c: float, stream=None, form: str = "auto") -> MultiFab:
+    """nsteps heat steps with the 8th-order second difference (nghost >= 4), one stencil
+    launch per step: form "fill" (FillBoundary first), "fused" (neighbour boxes read
+    directly; BoxtileError where the layout does not allow it) or "auto" (heat8_auto_form);
+    returns the result holder."""
     arr = (ctypes.c_void_p * 2)(u0.handle.value, u1.handle.value)
-    _check(_L.bl_heat8_advance(arr, int(nsteps), float(c), _stream(stream)))
+    _check(_L.bl_heat8_advance_form(arr, int(nsteps), float(c), H8_FORMS[form], _stream(stream)))
     return u0 if nsteps % 2 == 0 else u1
+
+
+def heat8_fused_ok(mf: MultiFab) -> bool:
+    """True where the fused 8th-order form applies to mf's layout."""
+    ok = ctypes.c_int32(0)
+    _check(_L.bl_heat8_fused_ok(mf.handle, ctypes.byref(ok)))
+    return ok.value > 0
+
+
+def heat8_auto_form(mf: MultiFab) -> str:
+    """The form heat8_advance(form="auto") takes on mf's layout: "fused" or "fill"."""
+    ok = ctypes.c_int32(0)
+    _check(_L.bl_heat8_fused_ok(mf.handle, ctypes.byref(ok)))
+    return "fused" if ok.value == 2 else "fill"
 
 
 def heat_varcoef_advance(u0: MultiFab, u1: MultiFab, beta: MultiFab, nsteps: int, dt: float, dx: float,

@@ -33,6 +33,8 @@ Plan::~Plan() {
   (void)hipFree(dcellpre);
   (void)hipFree(dpairpre);
   (void)hipFree(dh8);
+  (void)hipFree(dh8f);
+  (void)hipFree(dh8s);
   (void)hipFree(dcellwg);
   (void)hipFree(dpairwg);
 }
@@ -504,7 +506,42 @@ bl_status bl_heat_varcoef_advance(bl_multifab* u[2], bl_multifab* beta, int32_t 
   return BL_OK;
 }
 
-bl_status bl_heat8_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream_t stream) {
+// The fused 8th-order tiles of p, made on first use; false (p.h8why) where
+// the layout does not allow them.  Caller holds g_vc_mu.
+static bl_status h8_fused_tiles(Plan& p, bool* ok, bool* prefer = nullptr) {
+  if (p.h8fused < 0) {
+    std::vector<DevTile> t;
+    std::vector<DevH8Strips> sv;
+    int rm = 1, nv = 1;
+    std::string why;
+    if (build_h8_fused_tiles(p, t, sv, &rm, &nv, &why)) {
+      bl_status st = upload(&p.dh8f, t, "hipMalloc/hipMemcpy(fused 8th-order tiles)");
+      if (st == BL_OK) st = upload(&p.dh8s, sv, "hipMalloc/hipMemcpy(8th-order strip sources)");
+      if (st != BL_OK) {
+        (void)hipFree(p.dh8f);
+        p.dh8f = nullptr;
+        return st;
+      }
+      std::vector<DevTile> fill_tiles;
+      int frm = 1, fnv = 1;
+      build_h8_tiles(p, fill_tiles, &frm, &fnv);
+      p.h8prefer = (double)t.size() <= kH8FusedTileRatio * (double)fill_tiles.size();
+      p.hh8f.swap(t);
+      p.hh8s.swap(sv);
+      p.h8frmax = rm;
+      p.h8fnvtmax = nv;
+      p.h8fused = 1;
+    } else {
+      p.h8why = why;
+      p.h8fused = 0;
+    }
+  }
+  *ok = p.h8fused == 1;
+  if (prefer) *prefer = *ok && p.h8prefer;
+  return BL_OK;
+}
+
+bl_status bl_heat8_advance_form(bl_multifab* u[2], int32_t nsteps, double c, int32_t form, hipStream_t stream) {
   clear_error();
   if (!u) return fail(BL_EINVAL, "NULL MultiFab array");
   bl_status st = check_heat(u[0], u[1]);
@@ -512,10 +549,18 @@ bl_status bl_heat8_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStrea
   Plan& p = *u[0]->plan;
   if (p.ng < 4) return fail(BL_EINVAL, "the 8th-order stencil needs nghost >= 4, not %d", p.ng);
   if (nsteps < 0) return fail(BL_EINVAL, "nsteps < 0");
-  if (nsteps == 0) return BL_OK;
+  if (form < BL_H8_AUTO || form > BL_H8_FUSED) return fail(BL_EINVAL, "unknown 8th-order form %d", (int)form);
+  bool fused = false;
   {
     std::lock_guard<std::mutex> lk(g_vc_mu);
-    if (!p.h8built) {
+    if (form != BL_H8_FILL) {
+      bool prefer = false;
+      if ((st = h8_fused_tiles(p, &fused, &prefer)) != BL_OK) return st;
+      if (!fused && form == BL_H8_FUSED)
+        return fail(BL_EINVAL, "the fused 8th-order form does not apply to this layout: %s", p.h8why.c_str());
+      if (form == BL_H8_AUTO) fused = prefer;
+    }
+    if (!fused && !p.h8built) {
       std::vector<DevTile> t;
       int rm = 1, nv = 1;
       build_h8_tiles(p, t, &rm, &nv);
@@ -527,10 +572,37 @@ bl_status bl_heat8_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStrea
     }
   }
   for (int s = 0; s < nsteps; ++s) {
-    BL_HIP(launch_fill(p, u[s & 1]->data, 0, p.ncomp, stream));
-    BL_HIP(launch_heat8(p.dtype, p.vec, p.dh8, (int)p.hh8.size(), p.dboxes, u[s & 1]->data, u[(s + 1) & 1]->data, c,
-                        p.h8rmax, p.h8nvtmax, stream));
+    void* src = u[s & 1]->data;
+    void* dst = u[(s + 1) & 1]->data;
+    if (fused) {
+      BL_HIP(launch_heat8(p.dtype, p.vec, p.dh8f, p.dh8s, (int)p.hh8f.size(), p.dboxes, src, dst, c, p.h8frmax,
+                          p.h8fnvtmax, stream));
+    } else {
+      BL_HIP(launch_fill(p, src, 0, p.ncomp, stream));
+      BL_HIP(launch_heat8(p.dtype, p.vec, p.dh8, nullptr, (int)p.hh8.size(), p.dboxes, src, dst, c, p.h8rmax,
+                          p.h8nvtmax, stream));
+    }
   }
+  return BL_OK;
+}
+
+bl_status bl_heat8_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream_t stream) {
+  return bl_heat8_advance_form(u, nsteps, c, BL_H8_AUTO, stream);
+}
+
+bl_status bl_heat8_fused_ok(const bl_multifab* mf, int32_t* ok) {
+  clear_error();
+  if (!mf || !ok) return fail(BL_EINVAL, "NULL argument");
+  Plan& p = *mf->plan;
+  if (p.ng < 4) {
+    *ok = 0;
+    return BL_OK;
+  }
+  std::lock_guard<std::mutex> lk(g_vc_mu);
+  bool f = false, prefer = false;
+  bl_status st = h8_fused_tiles(p, &f, &prefer);
+  if (st != BL_OK) return st;
+  *ok = prefer ? 2 : (f ? 1 : 0);
   return BL_OK;
 }
 

@@ -168,6 +168,22 @@ static_assert(sizeof(DevFaceRec) == 32, "DevFaceRec size");
 // one face record that covers the tile's part of that face, kFaceMany if
 // several records do (the kernel then searches), kFaceNone if the tile does
 // not touch face f.
+// Where the fused 8th-order stencil reads the cells next to one face of a tile
+// (strip 2*axis + side): cell (x, y, z) of component 0.. in box-local indices
+// of the tile's box is data[o + x*sx + y*sy + z*sz], o including the tile's
+// component.  The source is one neighbour box (through its FillBoundary
+// record, periodic shift included) or the box's own ghost cells where no box
+// covers the strip (x strips: the x ghost slab, sx = -1 on the low side).
+struct DevH8Src {
+  int64_t o;
+  int64_t sz;
+  int32_t sx, sy;
+};
+struct DevH8Strips {
+  DevH8Src s[6];
+};
+static_assert(sizeof(DevH8Strips) == 144, "DevH8Strips size");
+
 constexpr int32_t kFaceNone = -1;
 constexpr int32_t kFaceMany = -2;
 struct DevTile {    // 32-bit fields only: each one is a plain scalar load
@@ -237,6 +253,10 @@ constexpr int kStencilMaxThreads = 256;  // workgroup size limit of the stencil 
 constexpr int kRestrictPerWG = 256;     // coarse cells per workgroup of the restriction (one per lane)
 constexpr int kProlongPerWG = 1024;     // x pairs per workgroup of the prolongation (four per lane)
 constexpr size_t kDmaLdsMax = 65536;     // LDS of one workgroup of the halo-in-LDS stencil form, at most
+// The fused 8th-order form pays where a tile keeps the fill form's size: its
+// tiles re-read their halos and re-prime a 9-plane queue, so where neighbour
+// boundaries cut them into many more (uneven chops) the fill form is faster.
+constexpr double kH8FusedTileRatio = 1.25;
 
 // ---------------------------------------------------------------- layout + plans
 struct TileConfig {
@@ -324,6 +344,18 @@ struct Plan {
   DevTile* dh8 = nullptr;
   int h8rmax = 1, h8nvtmax = 1;
   bool h8built = false;
+  // the fused form's tiles (cut where the neighbour across a face changes) and
+  // their strip sources; h8fused: -1 not tried, 0 not possible (h8why), 1 built;
+  // h8prefer: the automatic choice takes the fused form (its tiles are not
+  // more than kH8FusedTileRatio times as many as the fill form's)
+  std::vector<DevTile> hh8f;
+  std::vector<DevH8Strips> hh8s;
+  DevTile* dh8f = nullptr;
+  DevH8Strips* dh8s = nullptr;
+  int h8frmax = 1, h8fnvtmax = 1;
+  int h8fused = -1;
+  bool h8prefer = false;
+  std::string h8why;
 
   ~Plan();
 };
@@ -347,6 +379,13 @@ size_t lin_lds_bytes(const TileConfig& cfg, int esize, int vec, int yhmax, int x
 // at most 16, rows in groups of at most min(32, 256 / group width), z in chunks
 // of 32 planes; memory order (z chunk, then y, then x).
 void build_h8_tiles(const Plan& p, std::vector<DevTile>& tiles, int* rmax, int* nvtmax);
+// Tiles of the fused 8th-order stencil (no FillBoundary): as build_h8_tiles,
+// also cut at every box-local coordinate where the neighbour across one of the
+// box's faces changes, so that each tile strip outside the box has one source.
+// False (reason in *why) where that is impossible: a cut inside an x vector, a
+// neighbour thinner than the strip, a y or z source row not vector-aligned.
+bool build_h8_fused_tiles(const Plan& p, std::vector<DevTile>& tiles, std::vector<DevH8Strips>& strips, int* rmax,
+                          int* nvtmax, std::string* why);
 
 }  // namespace bl
 

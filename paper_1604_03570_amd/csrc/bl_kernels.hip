@@ -1075,19 +1075,22 @@ constexpr double kH8A0X3 = -205.0 / 24.0;
 // planes z0..z1-1, at most 256 lanes, rows <= 32, nvt <= 32), marching up z.
 // Each lane keeps the 9 planes z-4..z+4 of its own vector column in registers.
 // Plane z goes into one of two LDS buffers of ldh x ldw values together with
-// its 4-wide x and y halo (the FAB's filled ghosts at box faces, from the x
-// ghost slab for x), so x and y neighbours come from LDS; the next plane's
-// column value and halo are loaded before the barrier and stay in flight
-// across it.  One barrier per plane.
-template <typename T, int V>
+// its 4-wide x and y halo, so x and y neighbours come from LDS; the next
+// plane's column value and halo are loaded before the barrier and stay in
+// flight across it.  One barrier per plane.  Cells outside the box come from
+// the FAB's filled ghosts (x: the x ghost slab), or, FUSED, straight from
+// their source through the tile's strip table (no FillBoundary).
+template <typename T, int V, bool FUSED>
 __global__ void __launch_bounds__(256)
-    k_heat8(const DevTile* __restrict__ tiles, const DevBox* __restrict__ boxes, const T* u_, T* w_, T c, int ldw,
-            int ldh) {
+    k_heat8(const DevTile* __restrict__ tiles, const DevH8Strips* __restrict__ strips,
+            const DevBox* __restrict__ boxes, const T* u_, T* w_, T c, int ldw, int ldh) {
   using VT = Vec<T, V>;
   extern __shared__ unsigned char smem_raw[];
   T* const lds = reinterpret_cast<T*>(smem_raw);
-  const DevTile tl = ldc(tiles + logical_block());
+  const int tid = logical_block();
+  const DevTile tl = ldc(tiles + tid);
   const DevBox B = ldc(boxes + tl.box);
+  const DevH8Strips SS = FUSED ? ldc(strips + tid) : DevH8Strips{};
   const BL_GLOBAL T* __restrict__ u = as_global(u_);
   BL_GLOBAL T* __restrict__ w = as_global(w_);
   const int l = (int)threadIdx.x;
@@ -1100,12 +1103,17 @@ __global__ void __launch_bounds__(256)
   const int64_t col = comp0 + x0 + lx * V + (int64_t)(tl.y0 + lyc) * B.sy;
   // y halo: 4 rows below and 4 above the tile, one vector per lane
   const bool hy = l < 8 * nvt;
-  int64_t yh_at = col;
+  int64_t yh_at = col, yh_step = sz;
   int yh_slot = 0;
   if (hy) {
     const int r = l / nvt, xv = l % nvt;
     const int y = r < 4 ? tl.y0 - 4 + r : tl.y0 + rows + r - 4;
     yh_at = comp0 + x0 + xv * V + (int64_t)y * B.sy;
+    if (FUSED && (y < 0 || y >= B.ey)) {
+      const DevH8Src& S = y < 0 ? SS.s[2] : SS.s[3];
+      yh_at = S.o + x0 + xv * V + (int64_t)y * S.sy;
+      yh_step = S.sz;
+    }
     yh_slot = (r < 4 ? r : rows + r) * ldw + 4 + xv * V;
   }
   // x halo: 4 values left and right of each row, one per lane, the 4 values of
@@ -1119,7 +1127,11 @@ __global__ void __launch_bounds__(256)
     const int side = l / (4 * rows), rem = l - side * 4 * rows, m = rem & 3, yr = rem >> 2;
     const int y = tl.y0 + yr;
     const int x = side ? x0 + W + m : x0 - 1 - m;
-    if (x < 0 || x >= B.ex) {
+    if (FUSED && (x < 0 || x >= B.ex)) {
+      const DevH8Src& S = x < 0 ? SS.s[0] : SS.s[1];
+      xh_at = S.o + (int64_t)x * S.sx + (int64_t)y * S.sy;
+      xh_step = S.sz;
+    } else if (x < 0 || x >= B.ex) {
       xh_at = B.xs + (int64_t)tl.comp * B.sc + (x < 0 ? 0 : B.xs_side) + (int64_t)y * B.ng + (x < 0 ? -1 - x : x - B.ex);
       xh_step = B.xs_z;
     } else {
@@ -1129,16 +1141,31 @@ __global__ void __launch_bounds__(256)
   }
   const T A1 = (T)kH8A1, A2 = (T)kH8A2, A3 = (T)kH8A3, A4 = (T)kH8A4, A0 = (T)kH8A0X3;
 
+  // the lane's column below and above the box (FUSED: planes z < 0 and z >= ez
+  // from the z strips' sources)
+  int64_t czlo = col, czhi = col, szlo = sz, szhi = sz;
+  if (FUSED) {
+    const int xc = x0 + lx * V, yc = tl.y0 + lyc;
+    czlo = SS.s[4].o + xc + (int64_t)yc * SS.s[4].sy;
+    szlo = SS.s[4].sz;
+    czhi = SS.s[5].o + xc + (int64_t)yc * SS.s[5].sy;
+    szhi = SS.s[5].sz;
+  }
+  auto column = [&](int zz) -> const BL_GLOBAL T* {
+    if (FUSED && zz < 0) return u + czlo + (int64_t)zz * szlo;
+    if (FUSED && zz >= B.ez) return u + czhi + (int64_t)zz * szhi;
+    return u + col + (int64_t)zz * sz;
+  };
   VT Q[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) Q[k] = ldv<T, V>(u + col + (int64_t)(tl.z0 - 4 + k) * sz);
-  VT yh = hy ? ldv<T, V>(u + yh_at + (int64_t)tl.z0 * sz) : Q[0];
+  for (int k = 0; k < 9; ++k) Q[k] = ldv<T, V>(column(tl.z0 - 4 + k));
+  VT yh = hy ? ldv<T, V>(u + yh_at + (int64_t)tl.z0 * yh_step) : Q[0];
   T xh = hx ? u[xh_at + (int64_t)tl.z0 * xh_step] : (T)0;
   const int own = (ly + 4) * ldw + 4 + lx * V;
   // running pointers, one plane further each step: the next column plane, the
   // next plane's halo values, the output
   const BL_GLOBAL T* pq = u + col + (int64_t)(tl.z0 + 5) * sz;
-  const BL_GLOBAL T* py = u + yh_at + (int64_t)(tl.z0 + 1) * sz;
+  const BL_GLOBAL T* py = u + yh_at + (int64_t)(tl.z0 + 1) * yh_step;
   const BL_GLOBAL T* px = u + xh_at + (int64_t)(tl.z0 + 1) * xh_step;
   BL_GLOBAL T* pw = w + col + (int64_t)tl.z0 * sz;
   for (int z = tl.z0; z < tl.z1; ++z) {
@@ -1150,12 +1177,12 @@ __global__ void __launch_bounds__(256)
     VT qn = Q[8], yhn = yh;
     T xhn = xh;
     if (more) {
-      qn = ldv<T, V>(pq);
+      qn = ldv<T, V>(FUSED ? column(z + 5) : pq);
       if (hy) yhn = ldv<T, V>(py);
       if (hx) xhn = *px;
     }
     pq += sz;
-    py += sz;
+    py += FUSED ? yh_step : sz;
     px += xh_step;
     lds_sync();
     if (active) {
@@ -1972,26 +1999,30 @@ hipError_t launch_prolong_add(const Plan& fine, const Plan& coarse, void* phi, c
   return hipGetLastError();
 }
 
-// 8th-order heat step over the tiles of k_heat8 (FillBoundary of u first).
-hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, int ntiles, const DevBox* boxes, const void* u,
-                        void* w, double c, int rmax, int nvtmax, hipStream_t s) {
+// 8th-order heat step over the tiles of k_heat8: with strips (one per tile),
+// the fused form; without, u's ghosts must have been filled.
+template <typename T, int V>
+static void heat8_t(const DevTile* tiles, const DevH8Strips* strips, int ntiles, const DevBox* boxes, const void* u,
+                    void* w, double c, int ldw, int ldh, size_t lds, hipStream_t s) {
+  if (strips)
+    hipLaunchKernelGGL((k_heat8<T, V, true>), dim3(ntiles), dim3(256), lds, s, tiles, strips, boxes, (const T*)u,
+                       (T*)w, (T)c, ldw, ldh);
+  else
+    hipLaunchKernelGGL((k_heat8<T, V, false>), dim3(ntiles), dim3(256), lds, s, tiles, strips, boxes, (const T*)u,
+                       (T*)w, (T)c, ldw, ldh);
+}
+
+hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, const DevH8Strips* strips, int ntiles,
+                        const DevBox* boxes, const void* u, void* w, double c, int rmax, int nvtmax, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const int ldw = ((nvtmax * vec + 8) + 3) & ~3, ldh = rmax + 8;
   const size_t lds = 2 * (size_t)ldw * ldh * (dtype == BL_F64 ? 8 : 4);
   if (dtype == BL_F64) {
-    if (vec == 2)
-      hipLaunchKernelGGL((k_heat8<double, 2>), dim3(ntiles), dim3(256), lds, s, tiles, boxes, (const double*)u,
-                         (double*)w, c, ldw, ldh);
-    else
-      hipLaunchKernelGGL((k_heat8<double, 1>), dim3(ntiles), dim3(256), lds, s, tiles, boxes, (const double*)u,
-                         (double*)w, c, ldw, ldh);
+    if (vec == 2) heat8_t<double, 2>(tiles, strips, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
+    else heat8_t<double, 1>(tiles, strips, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
   } else {
-    if (vec == 4)
-      hipLaunchKernelGGL((k_heat8<float, 4>), dim3(ntiles), dim3(256), lds, s, tiles, boxes, (const float*)u,
-                         (float*)w, (float)c, ldw, ldh);
-    else
-      hipLaunchKernelGGL((k_heat8<float, 1>), dim3(ntiles), dim3(256), lds, s, tiles, boxes, (const float*)u,
-                         (float*)w, (float)c, ldw, ldh);
+    if (vec == 4) heat8_t<float, 4>(tiles, strips, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
+    else heat8_t<float, 1>(tiles, strips, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
   }
   return hipGetLastError();
 }

@@ -1,6 +1,7 @@
 """Parity of the 8th-order heat step (9-cell span, HIP kernel through the C-ABI) with
 the oracle.  FP64 bit for bit (same operand order, coefficients rounded once, no FMA
-contraction); FP32 storage within 2e-5 of the FP64 oracle.  Layouts: uneven boxes, holes
+contraction); FP32 storage within 2e-5 of the FP64 oracle; the fill form and the fused
+form (neighbour boxes read directly) agree bit for bit.  Layouts: uneven boxes, holes
 next to a non-periodic side, odd extents (scalar lanes), boxes whose last x tile is one
 vector wide (its halo reaches past the row end into the x ghost slab), 5 ghost layers."""
 import math
@@ -41,10 +42,11 @@ def _layout(name, rng):
     return dom, periodic, boxes
 
 
+@pytest.mark.parametrize("form", ["fill", "fused"])
 @pytest.mark.parametrize("ng", [4, 5])
 @pytest.mark.parametrize("dtype_name", ["f64", "f32"])
 @pytest.mark.parametrize("layout", ["uneven_periodic", "holes_mixed", "odd_extents", "narrow_last_tile"])
-def test_heat8_equals_the_oracle(bt, layout, dtype_name, ng):
+def test_heat8_equals_the_oracle(bt, layout, dtype_name, ng, form):
     rng = np.random.default_rng(5)
     dom, periodic, boxes = _layout(layout, rng)
     dtype = bt.F64 if dtype_name == "f64" else bt.F32
@@ -55,7 +57,8 @@ def test_heat8_equals_the_oracle(bt, layout, dtype_name, ng):
     steps = 7
     say(f"heat8 layout={layout} dtype={dtype_name} ng={ng} nbox={len(boxes)}")
     _, a, b, o = make_pair(boxes, dom, periodic, 2, ng, dtype, g, ghost_value=0.5)
-    res = bt.heat8_advance(a, b, steps, C8)
+    assert bt.heat8_fused_ok(a)
+    res = bt.heat8_advance(a, b, steps, C8, form=form)
     ref = O.heat8_advance(o, steps, C8).to_global()
     got = gpu_global(res)
     if dtype == bt.F64:
@@ -64,6 +67,21 @@ def test_heat8_equals_the_oracle(bt, layout, dtype_name, ng):
         err = rel_err(got, ref)
         say(f"  fp32 rel err {err:.2e}")
         assert err <= 2e-5
+    if form == "fused":  # the two forms agree bit for bit, FP32 included
+        _, a2, b2, _ = make_pair(boxes, dom, periodic, 2, ng, dtype, g, ghost_value=0.5)
+        assert np.array_equal(gpu_global(bt.heat8_advance(a2, b2, steps, C8, form="fill")), got, equal_nan=True)
+
+
+def test_heat8_fused_form_refused_where_a_neighbour_is_thin(bt):
+    dom = I.domain_box(32)
+    boxes = np.array([[0, 0, 0, 1, 31, 31], [2, 0, 0, 31, 31, 31]])  # a neighbour 2 cells thick across x
+    g = np.random.default_rng(3).random((1, 32, 32, 32)) + 1.0
+    _, a, b, o = make_pair(boxes, dom, (1, 1, 1), 1, 4, bt.F64, g)
+    assert not bt.heat8_fused_ok(a)
+    with pytest.raises(bt.BoxtileError):
+        bt.heat8_advance(a, b, 1, C8, form="fused")
+    res = bt.heat8_advance(a, b, 3, C8)  # auto: the fill form
+    assert np.array_equal(gpu_global(res), O.heat8_advance(o, 3, C8).to_global())
 
 
 def test_heat8_degenerate_calls(bt):
