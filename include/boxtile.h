@@ -268,40 +268,39 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
  *   BL_H8_FUSED  no FillBoundary: cells outside a box are read from the
  *                neighbour box (periodic image included) that FillBoundary would
  *                copy them from, or from the box's own ghost cells where no box
- *                covers them.  Tiles are cut wherever the neighbour across a face
- *                changes.  Applies where every neighbour across a face is at
- *                least 4 cells thick and neighbour boundaries fall on x-vector
- *                edges (bl_heat8_fused_ok); else BL_EINVAL.
- *   BL_H8_AUTO   the fused form where it applies and those cuts leave at most
- *                1.25 times as many tiles as the fill form has (on uneven chops
- *                the smaller tiles cost more than the fill), else the fill form.
+ *                covers them; each lane finds its source among the face's
+ *                segments.  Applies where every neighbour across a face is at
+ *                least 4 cells thick and, with vectors of more than one cell,
+ *                neighbour boundaries fall on x-vector edges
+ *                (bl_heat8_fused_ok); else BL_EINVAL.
+ *   BL_H8_AUTO   the fused form where it applies, else the fill form.
  * The fill form writes u_old's ghost cells each step; the fused form writes no
  * ghost cell.  bl_heat8_advance is bl_heat8_advance_form with BL_H8_AUTO.
  */
 typedef enum { BL_H8_AUTO = 0, BL_H8_FILL = 1, BL_H8_FUSED = 2 } bl_h8_form;
 bl_status bl_heat8_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream_t stream);
 bl_status bl_heat8_advance_form(bl_multifab* u[2], int32_t nsteps, double c, int32_t form, hipStream_t stream);
-/* *ok = 0 where the fused form does not apply to mf's layout (also for
- * nghost < 4), 1 where it applies but BL_H8_AUTO takes the fill form, 2 where
- * BL_H8_AUTO takes it.  Builds and caches its tiles (host work and a device
+/* *ok = 1 where the fused form applies to mf's layout, else 0 (also for
+ * nghost < 4).  Builds and caches its face segments (host work and a device
  * upload, once per layout). */
 bl_status bl_heat8_fused_ok(const bl_multifab* mf, int32_t* ok);
 
 /*
  * Host-only views of the metadata above, for checking it without a GPU (no
- * device memory is touched).  bl_heat8_fused_layout: the fused 8th-order
- * tiles a MultiFab of this shape would use; *ntiles their count; with tiles
- * non-NULL, 9 int32 per tile {box, comp, x0, width, y0, rows, z0, z1, vec}
- * (box-local cells, x0 and width in cells); with strips non-NULL, 24 int64
- * per tile: for strips 0..5 (2*axis + side) {o, sx, sy, sz} as documented for
- * the fused form (cell (x, y, z) of the strip is element o + x*sx + y*sy +
- * z*sz); *total_elems (nullable) the MultiFab's element count.  BL_EINVAL
- * (reason in bl_last_error) where the fused form does not apply.
- * bl_layout_index: element index of cell (global indices, inside box's grown
- * box) of component comp in a MultiFab of this shape.
+ * device memory is touched).  bl_heat8_fused_layout: the face segments the
+ * fused 8th-order form would use for a MultiFab of this shape; *nsegs their
+ * count; with segs non-NULL, 12 int64 per segment {box, face (2*axis + side),
+ * t1lo, t1hi, t2lo, t2hi, o, sc, sx, sy, sz, vec}: the segment covers the 4 cell
+ * layers of that face over box-local tangential coordinates (t1, t2) in
+ * [t1lo, t1hi] x [t2lo, t2hi] ((y, z) for x faces, (x, z) for y faces, (x, y)
+ * for z faces), and cell (x, y, z) of component n there is element
+ * o + n*sc + x*sx + y*sy + z*sz; *total_elems (nullable) the MultiFab's
+ * element count.  BL_EINVAL (reason in bl_last_error) where the fused form
+ * does not apply.  bl_layout_index: element index of cell (global indices,
+ * inside box's grown box) of component comp in a MultiFab of this shape.
  */
-bl_status bl_heat8_fused_layout(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype, int32_t* ntiles,
-                                int32_t* tiles, int64_t* strips, int64_t* total_elems);
+bl_status bl_heat8_fused_layout(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype, int32_t* nsegs,
+                                int64_t* segs, int64_t* total_elems);
 bl_status bl_layout_index(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype, int32_t box,
                           const int32_t cell[3], int32_t comp, int64_t* index);
 

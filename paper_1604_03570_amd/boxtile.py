@@ -72,7 +72,7 @@ _SIGS = {
     "bl_heat8_advance": [_vpp, _i32, ctypes.c_double, _vp],
     "bl_heat8_advance_form": [_vpp, _i32, ctypes.c_double, _i32, _vp],
     "bl_heat8_fused_ok": [_vp, _i32p],
-    "bl_heat8_fused_layout": [_vp, _i32, _i32, _i32, _i32p, _i32p, _i64p, _i64p],
+    "bl_heat8_fused_layout": [_vp, _i32, _i32, _i32, _i32p, _i64p, _i64p],
     "bl_layout_index": [_vp, _i32, _i32, _i32, _i32, _i32p, _i32, _i64p],
     "bl_device_copy": [_vp, _vp, ctypes.c_size_t, _vp],
     "bl_heat_step_unfused": [_vp, _vp, ctypes.c_double, _vp],
@@ -259,19 +259,16 @@ class BoxArray:
         return out
 
     def heat8_fused_layout(self, ncomp: int, nghost: int, dtype: int = F64):
-        """Host-only: the fused 8th-order tiles of a MultiFab of this shape, as (tiles, strips,
-        total_elems): tiles rows {box, comp, x0, width, y0, rows, z0, z1, vec} (box-local
-        cells), strips (ntiles, 6, 4) rows {o, sx, sy, sz}.  BoxtileError where the fused form
-        does not apply."""
+        """Host-only: the face segments of the fused 8th-order form for a MultiFab of this
+        shape, as (segs, total_elems): segs rows {box, face, t1lo, t1hi, t2lo, t2hi, o, sc, sx,
+        sy, sz, vec}.  BoxtileError where the fused form does not apply."""
         n = ctypes.c_int32()
         total = ctypes.c_int64()
-        _check(_L.bl_heat8_fused_layout(self._h, ncomp, nghost, dtype, ctypes.byref(n), None, None,
+        _check(_L.bl_heat8_fused_layout(self._h, ncomp, nghost, dtype, ctypes.byref(n), None, ctypes.byref(total)))
+        segs = np.zeros((n.value, 12), dtype=np.int64)
+        _check(_L.bl_heat8_fused_layout(self._h, ncomp, nghost, dtype, ctypes.byref(n), segs.ctypes.data_as(_i64p),
                                         ctypes.byref(total)))
-        tiles = np.zeros((n.value, 9), dtype=np.int32)
-        strips = np.zeros((n.value, 6, 4), dtype=np.int64)
-        _check(_L.bl_heat8_fused_layout(self._h, ncomp, nghost, dtype, ctypes.byref(n), tiles.ctypes.data_as(_i32p),
-                                        strips.ctypes.data_as(_i64p), ctypes.byref(total)))
-        return tiles, strips, total.value
+        return segs, total.value
 
     def layout_index(self, ncomp: int, nghost: int, dtype: int, box: int, cell, comp: int) -> int:
         """Host-only: element index of a cell (global indices, in the box's grown box)."""
@@ -525,9 +522,7 @@ def heat8_fused_ok(mf: MultiFab) -> bool:
 
 def heat8_auto_form(mf: MultiFab) -> str:
     """The form heat8_advance(form="auto") takes on mf's layout: "fused" or "fill"."""
-    ok = ctypes.c_int32(0)
-    _check(_L.bl_heat8_fused_ok(mf.handle, ctypes.byref(ok)))
-    return "fused" if ok.value == 2 else "fill"
+    return "fused" if heat8_fused_ok(mf) else "fill"
 
 
 def heat_varcoef_advance(u0: MultiFab, u1: MultiFab, beta: MultiFab, nsteps: int, dt: float, dx: float,

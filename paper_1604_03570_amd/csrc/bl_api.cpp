@@ -33,8 +33,8 @@ Plan::~Plan() {
   (void)hipFree(dcellpre);
   (void)hipFree(dpairpre);
   (void)hipFree(dh8);
-  (void)hipFree(dh8f);
-  (void)hipFree(dh8s);
+  (void)hipFree(dh8seg);
+  (void)hipFree(dh8face);
   (void)hipFree(dcellwg);
   (void)hipFree(dpairwg);
 }
@@ -506,30 +506,24 @@ bl_status bl_heat_varcoef_advance(bl_multifab* u[2], bl_multifab* beta, int32_t 
   return BL_OK;
 }
 
-// The fused 8th-order tiles of p, made on first use; false (p.h8why) where
-// the layout does not allow them.  Caller holds g_vc_mu.
-static bl_status h8_fused_tiles(Plan& p, bool* ok, bool* prefer = nullptr) {
+// The fused 8th-order form's face segments of p, made on first use; *ok false
+// (reason in p.h8why) where the layout does not allow the form.  Caller holds
+// g_vc_mu.
+static bl_status h8_segments(Plan& p, bool* ok) {
   if (p.h8fused < 0) {
-    std::vector<DevTile> t;
-    std::vector<DevH8Strips> sv;
-    int rm = 1, nv = 1;
+    std::vector<DevH8Seg> sv;
+    std::vector<DevH8Face> fv;
     std::string why;
-    if (build_h8_fused_tiles(p, t, sv, &rm, &nv, &why)) {
-      bl_status st = upload(&p.dh8f, t, "hipMalloc/hipMemcpy(fused 8th-order tiles)");
-      if (st == BL_OK) st = upload(&p.dh8s, sv, "hipMalloc/hipMemcpy(8th-order strip sources)");
+    if (build_h8_segments(p, sv, fv, &why)) {
+      bl_status st = upload(&p.dh8seg, sv, "hipMalloc/hipMemcpy(8th-order face segments)");
+      if (st == BL_OK) st = upload(&p.dh8face, fv, "hipMalloc/hipMemcpy(8th-order faces)");
       if (st != BL_OK) {
-        (void)hipFree(p.dh8f);
-        p.dh8f = nullptr;
+        (void)hipFree(p.dh8seg);
+        p.dh8seg = nullptr;
         return st;
       }
-      std::vector<DevTile> fill_tiles;
-      int frm = 1, fnv = 1;
-      build_h8_tiles(p, fill_tiles, &frm, &fnv);
-      p.h8prefer = (double)t.size() <= kH8FusedTileRatio * (double)fill_tiles.size();
-      p.hh8f.swap(t);
-      p.hh8s.swap(sv);
-      p.h8frmax = rm;
-      p.h8fnvtmax = nv;
+      p.hh8seg.swap(sv);
+      p.hh8face.swap(fv);
       p.h8fused = 1;
     } else {
       p.h8why = why;
@@ -537,7 +531,6 @@ static bl_status h8_fused_tiles(Plan& p, bool* ok, bool* prefer = nullptr) {
     }
   }
   *ok = p.h8fused == 1;
-  if (prefer) *prefer = *ok && p.h8prefer;
   return BL_OK;
 }
 
@@ -554,13 +547,11 @@ bl_status bl_heat8_advance_form(bl_multifab* u[2], int32_t nsteps, double c, int
   {
     std::lock_guard<std::mutex> lk(g_vc_mu);
     if (form != BL_H8_FILL) {
-      bool prefer = false;
-      if ((st = h8_fused_tiles(p, &fused, &prefer)) != BL_OK) return st;
+      if ((st = h8_segments(p, &fused)) != BL_OK) return st;
       if (!fused && form == BL_H8_FUSED)
         return fail(BL_EINVAL, "the fused 8th-order form does not apply to this layout: %s", p.h8why.c_str());
-      if (form == BL_H8_AUTO) fused = prefer;
     }
-    if (!fused && !p.h8built) {
+    if (!p.h8built) {  // both forms run over the same tiles
       std::vector<DevTile> t;
       int rm = 1, nv = 1;
       build_h8_tiles(p, t, &rm, &nv);
@@ -574,14 +565,9 @@ bl_status bl_heat8_advance_form(bl_multifab* u[2], int32_t nsteps, double c, int
   for (int s = 0; s < nsteps; ++s) {
     void* src = u[s & 1]->data;
     void* dst = u[(s + 1) & 1]->data;
-    if (fused) {
-      BL_HIP(launch_heat8(p.dtype, p.vec, p.dh8f, p.dh8s, (int)p.hh8f.size(), p.dboxes, src, dst, c, p.h8frmax,
-                          p.h8fnvtmax, stream));
-    } else {
-      BL_HIP(launch_fill(p, src, 0, p.ncomp, stream));
-      BL_HIP(launch_heat8(p.dtype, p.vec, p.dh8, nullptr, (int)p.hh8.size(), p.dboxes, src, dst, c, p.h8rmax,
-                          p.h8nvtmax, stream));
-    }
+    if (!fused) BL_HIP(launch_fill(p, src, 0, p.ncomp, stream));
+    BL_HIP(launch_heat8(p.dtype, p.vec, p.dh8, fused ? p.dh8seg : nullptr, fused ? p.dh8face : nullptr,
+                        (int)p.hh8.size(), p.dboxes, src, dst, c, p.h8rmax, p.h8nvtmax, stream));
   }
   return BL_OK;
 }
@@ -599,10 +585,10 @@ bl_status bl_heat8_fused_ok(const bl_multifab* mf, int32_t* ok) {
     return BL_OK;
   }
   std::lock_guard<std::mutex> lk(g_vc_mu);
-  bool f = false, prefer = false;
-  bl_status st = h8_fused_tiles(p, &f, &prefer);
+  bool f = false;
+  bl_status st = h8_segments(p, &f);
   if (st != BL_OK) return st;
-  *ok = prefer ? 2 : (f ? 1 : 0);
+  *ok = f ? 1 : 0;
   return BL_OK;
 }
 

@@ -168,21 +168,25 @@ static_assert(sizeof(DevFaceRec) == 32, "DevFaceRec size");
 // one face record that covers the tile's part of that face, kFaceMany if
 // several records do (the kernel then searches), kFaceNone if the tile does
 // not touch face f.
-// Where the fused 8th-order stencil reads the cells next to one face of a tile
-// (strip 2*axis + side): cell (x, y, z) of component 0.. in box-local indices
-// of the tile's box is data[o + x*sx + y*sy + z*sz], o including the tile's
-// component.  The source is one neighbour box (through its FillBoundary
-// record, periodic shift included) or the box's own ghost cells where no box
-// covers the strip (x strips: the x ghost slab, sx = -1 on the low side).
-struct DevH8Src {
-  int64_t o;
-  int64_t sz;
+// Where the fused 8th-order stencil reads the cells next to one face of a box:
+// the face's 4 cell layers are tiled by segments, each a rectangle of the
+// face's tangential coordinates (t1, t2) = (y, z) for x faces, (x, z) for y
+// faces, (x, y) for z faces (box-local), over all 4 layers.  Cell (x, y, z) of
+// component n (box-local indices of the face's box) in a segment is
+// data[o + n*sc + x*sx + y*sy + z*sz].  The source is one neighbour box (through
+// its FillBoundary record, periodic shift included) or the box's own ghost
+// cells where no box covers that part of the face (x faces: the x ghost slab,
+// sx = -1 on the low side).
+struct DevH8Seg {
+  int64_t o, sc, sz;
   int32_t sx, sy;
+  int32_t t1lo, t1hi, t2lo, t2hi;
 };
-struct DevH8Strips {
-  DevH8Src s[6];
+static_assert(sizeof(DevH8Seg) == 48, "DevH8Seg size");
+struct DevH8Face {  // the segments of face f of a box: [start[f], start[f] + count[f])
+  int32_t start[6];
+  int32_t count[6];
 };
-static_assert(sizeof(DevH8Strips) == 144, "DevH8Strips size");
 
 constexpr int32_t kFaceNone = -1;
 constexpr int32_t kFaceMany = -2;
@@ -253,10 +257,6 @@ constexpr int kStencilMaxThreads = 256;  // workgroup size limit of the stencil 
 constexpr int kRestrictPerWG = 256;     // coarse cells per workgroup of the restriction (one per lane)
 constexpr int kProlongPerWG = 1024;     // x pairs per workgroup of the prolongation (four per lane)
 constexpr size_t kDmaLdsMax = 65536;     // LDS of one workgroup of the halo-in-LDS stencil form, at most
-// The fused 8th-order form pays where a tile keeps the fill form's size: its
-// tiles re-read their halos and re-prime a 9-plane queue, so where neighbour
-// boundaries cut them into many more (uneven chops) the fill form is faster.
-constexpr double kH8FusedTileRatio = 1.25;
 
 // ---------------------------------------------------------------- layout + plans
 struct TileConfig {
@@ -344,17 +344,13 @@ struct Plan {
   DevTile* dh8 = nullptr;
   int h8rmax = 1, h8nvtmax = 1;
   bool h8built = false;
-  // the fused form's tiles (cut where the neighbour across a face changes) and
-  // their strip sources; h8fused: -1 not tried, 0 not possible (h8why), 1 built;
-  // h8prefer: the automatic choice takes the fused form (its tiles are not
-  // more than kH8FusedTileRatio times as many as the fill form's)
-  std::vector<DevTile> hh8f;
-  std::vector<DevH8Strips> hh8s;
-  DevTile* dh8f = nullptr;
-  DevH8Strips* dh8s = nullptr;
-  int h8frmax = 1, h8fnvtmax = 1;
+  // the fused form's face segments (made on first use); h8fused: -1 not tried,
+  // 0 not possible (h8why), 1 built
+  std::vector<DevH8Seg> hh8seg;
+  std::vector<DevH8Face> hh8face;
+  DevH8Seg* dh8seg = nullptr;
+  DevH8Face* dh8face = nullptr;
   int h8fused = -1;
-  bool h8prefer = false;
   std::string h8why;
 
   ~Plan();
@@ -379,13 +375,11 @@ size_t lin_lds_bytes(const TileConfig& cfg, int esize, int vec, int yhmax, int x
 // at most 16, rows in groups of at most min(32, 256 / group width), z in chunks
 // of 32 planes; memory order (z chunk, then y, then x).
 void build_h8_tiles(const Plan& p, std::vector<DevTile>& tiles, int* rmax, int* nvtmax);
-// Tiles of the fused 8th-order stencil (no FillBoundary): as build_h8_tiles,
-// also cut at every box-local coordinate where the neighbour across one of the
-// box's faces changes, so that each tile strip outside the box has one source.
-// False (reason in *why) where that is impossible: a cut inside an x vector, a
-// neighbour thinner than the strip, a y or z source row not vector-aligned.
-bool build_h8_fused_tiles(const Plan& p, std::vector<DevTile>& tiles, std::vector<DevH8Strips>& strips, int* rmax,
-                          int* nvtmax, std::string* why);
+// Face segments of the fused 8th-order stencil (no FillBoundary) for every box.
+// False (reason in *why) where the form does not apply: a neighbour thinner
+// than the 4 layers across a face, or (vectors of more than one cell) a y- or
+// z-face segment edge inside an x vector or a source row not vector-aligned.
+bool build_h8_segments(const Plan& p, std::vector<DevH8Seg>& segs, std::vector<DevH8Face>& faces, std::string* why);
 
 }  // namespace bl
 

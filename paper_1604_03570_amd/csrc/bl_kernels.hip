@@ -1071,6 +1071,18 @@ __device__ __forceinline__ void lds_sync() {
 constexpr double kH8A1 = 8.0 / 5.0, kH8A2 = -1.0 / 5.0, kH8A3 = 8.0 / 315.0, kH8A4 = -1.0 / 560.0;
 constexpr double kH8A0X3 = -205.0 / 24.0;
 
+// The segment of a face (segments [start, start + count)) that covers
+// tangential coordinates (t1, t2).  The segments tile the face, so when none
+// of the first count - 1 does, the last one does.
+__device__ __forceinline__ DevH8Seg h8_find(const DevH8Seg* __restrict__ segs, int start, int count, int t1, int t2) {
+  int i = start;
+  for (; i < start + count - 1; ++i) {
+    const DevH8Seg g = segs[i];
+    if (t1 >= g.t1lo && t1 <= g.t1hi && t2 >= g.t2lo && t2 <= g.t2hi) break;
+  }
+  return segs[i];
+}
+
 // One workgroup per tile (x vectors xv0..xv0+nvt-1 of rows y0..y0+rows-1 over
 // planes z0..z1-1, at most 256 lanes, rows <= 32, nvt <= 32), marching up z.
 // Each lane keeps the 9 planes z-4..z+4 of its own vector column in registers.
@@ -1079,18 +1091,23 @@ constexpr double kH8A0X3 = -205.0 / 24.0;
 // plane's column value and halo are loaded before the barrier and stay in
 // flight across it.  One barrier per plane.  Cells outside the box come from
 // the FAB's filled ghosts (x: the x ghost slab), or, FUSED, straight from
-// their source through the tile's strip table (no FillBoundary).
+// their source: each lane finds the segment of its face that covers its cell
+// (h8_find) and finds the next one when its z leaves the segment.
 template <typename T, int V, bool FUSED>
 __global__ void __launch_bounds__(256)
-    k_heat8(const DevTile* __restrict__ tiles, const DevH8Strips* __restrict__ strips,
+    k_heat8(const DevTile* __restrict__ tiles, const DevH8Seg* __restrict__ segs, const DevH8Face* __restrict__ faces,
             const DevBox* __restrict__ boxes, const T* u_, T* w_, T c, int ldw, int ldh) {
   using VT = Vec<T, V>;
   extern __shared__ unsigned char smem_raw[];
   T* const lds = reinterpret_cast<T*>(smem_raw);
-  const int tid = logical_block();
-  const DevTile tl = ldc(tiles + tid);
+  const DevTile tl = ldc(tiles + logical_block());
   const DevBox B = ldc(boxes + tl.box);
-  const DevH8Strips SS = FUSED ? ldc(strips + tid) : DevH8Strips{};
+  const DevH8Face F = FUSED ? ldc(faces + tl.box) : DevH8Face{};
+  const int64_t n = tl.comp;
+  // address of cell (x, y, 0) of the tile's component through segment g
+  auto seg_at = [&](const DevH8Seg& g, int x, int y) -> int64_t {
+    return g.o + n * g.sc + (int64_t)x * g.sx + (int64_t)y * g.sy;
+  };
   const BL_GLOBAL T* __restrict__ u = as_global(u_);
   BL_GLOBAL T* __restrict__ w = as_global(w_);
   const int l = (int)threadIdx.x;
@@ -1103,16 +1120,20 @@ __global__ void __launch_bounds__(256)
   const int64_t col = comp0 + x0 + lx * V + (int64_t)(tl.y0 + lyc) * B.sy;
   // y halo: 4 rows below and 4 above the tile, one vector per lane
   const bool hy = l < 8 * nvt;
-  int64_t yh_at = col, yh_step = sz;
-  int yh_slot = 0;
+  int64_t yh_at = col;
+  int yh_step = B.sz;  // plane strides fit 32 bits (checked when the segments are made)
+  int yh_slot = 0, yh_x = 0, yh_y = 0, yh_f = -1, yh_t2hi = 0;  // yh_f >= 0: a y face's segment
   if (hy) {
     const int r = l / nvt, xv = l % nvt;
-    const int y = r < 4 ? tl.y0 - 4 + r : tl.y0 + rows + r - 4;
-    yh_at = comp0 + x0 + xv * V + (int64_t)y * B.sy;
-    if (FUSED && (y < 0 || y >= B.ey)) {
-      const DevH8Src& S = y < 0 ? SS.s[2] : SS.s[3];
-      yh_at = S.o + x0 + xv * V + (int64_t)y * S.sy;
-      yh_step = S.sz;
+    yh_y = r < 4 ? tl.y0 - 4 + r : tl.y0 + rows + r - 4;
+    yh_x = x0 + xv * V;
+    yh_at = comp0 + yh_x + (int64_t)yh_y * B.sy;
+    if (FUSED && (yh_y < 0 || yh_y >= B.ey)) {
+      yh_f = yh_y < 0 ? 2 : 3;
+      const DevH8Seg g = h8_find(segs, F.start[yh_f], F.count[yh_f], yh_x, tl.z0);
+      yh_at = seg_at(g, yh_x, yh_y);
+      yh_step = (int)g.sz;
+      yh_t2hi = g.t2hi;
     }
     yh_slot = (r < 4 ? r : rows + r) * ldw + 4 + xv * V;
   }
@@ -1121,16 +1142,21 @@ __global__ void __launch_bounds__(256)
   // quarter of the lines it would with one row per lane); a value beyond the
   // box's x range comes from the x ghost slab (layer = distance from the face - 1)
   const bool hx = l < 8 * rows;
-  int64_t xh_at = col, xh_step = sz;
-  int xh_slot = 0;
+  int64_t xh_at = col;
+  int xh_step = B.sz;
+  int xh_slot = 0, xh_x = 0, xh_y = 0, xh_f = -1, xh_t2hi = 0;  // xh_f >= 0: an x face's segment
   if (hx) {
     const int side = l / (4 * rows), rem = l - side * 4 * rows, m = rem & 3, yr = rem >> 2;
     const int y = tl.y0 + yr;
     const int x = side ? x0 + W + m : x0 - 1 - m;
+    xh_x = x;
+    xh_y = y;
     if (FUSED && (x < 0 || x >= B.ex)) {
-      const DevH8Src& S = x < 0 ? SS.s[0] : SS.s[1];
-      xh_at = S.o + (int64_t)x * S.sx + (int64_t)y * S.sy;
-      xh_step = S.sz;
+      xh_f = x < 0 ? 0 : 1;
+      const DevH8Seg g = h8_find(segs, F.start[xh_f], F.count[xh_f], y, tl.z0);
+      xh_at = seg_at(g, x, y);
+      xh_step = (int)g.sz;
+      xh_t2hi = g.t2hi;
     } else if (x < 0 || x >= B.ex) {
       xh_at = B.xs + (int64_t)tl.comp * B.sc + (x < 0 ? 0 : B.xs_side) + (int64_t)y * B.ng + (x < 0 ? -1 - x : x - B.ex);
       xh_step = B.xs_z;
@@ -1142,14 +1168,21 @@ __global__ void __launch_bounds__(256)
   const T A1 = (T)kH8A1, A2 = (T)kH8A2, A3 = (T)kH8A3, A4 = (T)kH8A4, A0 = (T)kH8A0X3;
 
   // the lane's column below and above the box (FUSED: planes z < 0 and z >= ez
-  // from the z strips' sources)
-  int64_t czlo = col, czhi = col, szlo = sz, szhi = sz;
+  // through the z faces' segments, one each for the whole tile)
+  int64_t czlo = col, czhi = col;
+  int szlo = B.sz, szhi = B.sz;
   if (FUSED) {
     const int xc = x0 + lx * V, yc = tl.y0 + lyc;
-    czlo = SS.s[4].o + xc + (int64_t)yc * SS.s[4].sy;
-    szlo = SS.s[4].sz;
-    czhi = SS.s[5].o + xc + (int64_t)yc * SS.s[5].sy;
-    szhi = SS.s[5].sz;
+    if (tl.z0 < 4) {
+      const DevH8Seg g = h8_find(segs, F.start[4], F.count[4], xc, yc);
+      czlo = seg_at(g, xc, yc);
+      szlo = (int)g.sz;
+    }
+    if (tl.z1 + 4 > B.ez) {
+      const DevH8Seg g = h8_find(segs, F.start[5], F.count[5], xc, yc);
+      czhi = seg_at(g, xc, yc);
+      szhi = (int)g.sz;
+    }
   }
   auto column = [&](int zz) -> const BL_GLOBAL T* {
     if (FUSED && zz < 0) return u + czlo + (int64_t)zz * szlo;
@@ -1177,9 +1210,28 @@ __global__ void __launch_bounds__(256)
     VT qn = Q[8], yhn = yh;
     T xhn = xh;
     if (more) {
-      qn = ldv<T, V>(FUSED ? column(z + 5) : pq);
-      if (hy) yhn = ldv<T, V>(py);
-      if (hx) xhn = *px;
+      // plane z + 5 > 0: only the box's planes and those above it
+      qn = ldv<T, V>(FUSED ? (z + 5 >= B.ez ? u + czhi + (int64_t)(z + 5) * szhi : pq) : pq);
+      if (hy) {
+        if (FUSED && yh_f >= 0 && z + 1 > yh_t2hi) {  // the next plane lies in the face's next segment
+          const DevH8Seg g = h8_find(segs, F.start[yh_f], F.count[yh_f], yh_x, z + 1);
+          yh_at = seg_at(g, yh_x, yh_y);
+          yh_step = (int)g.sz;
+          yh_t2hi = g.t2hi;
+          py = u + yh_at + (int64_t)(z + 1) * yh_step;
+        }
+        yhn = ldv<T, V>(py);
+      }
+      if (hx) {
+        if (FUSED && xh_f >= 0 && z + 1 > xh_t2hi) {
+          const DevH8Seg g = h8_find(segs, F.start[xh_f], F.count[xh_f], xh_y, z + 1);
+          xh_at = seg_at(g, xh_x, xh_y);
+          xh_step = (int)g.sz;
+          xh_t2hi = g.t2hi;
+          px = u + xh_at + (int64_t)(z + 1) * xh_step;
+        }
+        xhn = *px;
+      }
     }
     pq += sz;
     py += FUSED ? yh_step : sz;
@@ -1999,30 +2051,32 @@ hipError_t launch_prolong_add(const Plan& fine, const Plan& coarse, void* phi, c
   return hipGetLastError();
 }
 
-// 8th-order heat step over the tiles of k_heat8: with strips (one per tile),
-// the fused form; without, u's ghosts must have been filled.
+// 8th-order heat step over the tiles of k_heat8: with segs and faces, the
+// fused form; without, u's ghosts must have been filled.
 template <typename T, int V>
-static void heat8_t(const DevTile* tiles, const DevH8Strips* strips, int ntiles, const DevBox* boxes, const void* u,
-                    void* w, double c, int ldw, int ldh, size_t lds, hipStream_t s) {
-  if (strips)
-    hipLaunchKernelGGL((k_heat8<T, V, true>), dim3(ntiles), dim3(256), lds, s, tiles, strips, boxes, (const T*)u,
-                       (T*)w, (T)c, ldw, ldh);
+static void heat8_t(const DevTile* tiles, const DevH8Seg* segs, const DevH8Face* faces, int ntiles,
+                    const DevBox* boxes, const void* u, void* w, double c, int ldw, int ldh, size_t lds, hipStream_t s) {
+  if (segs)
+    hipLaunchKernelGGL((k_heat8<T, V, true>), dim3(ntiles), dim3(256), lds, s, tiles, segs, faces, boxes,
+                       (const T*)u, (T*)w, (T)c, ldw, ldh);
   else
-    hipLaunchKernelGGL((k_heat8<T, V, false>), dim3(ntiles), dim3(256), lds, s, tiles, strips, boxes, (const T*)u,
-                       (T*)w, (T)c, ldw, ldh);
+    hipLaunchKernelGGL((k_heat8<T, V, false>), dim3(ntiles), dim3(256), lds, s, tiles, segs, faces, boxes,
+                       (const T*)u, (T*)w, (T)c, ldw, ldh);
 }
 
-hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, const DevH8Strips* strips, int ntiles,
-                        const DevBox* boxes, const void* u, void* w, double c, int rmax, int nvtmax, hipStream_t s) {
+hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, const DevH8Seg* segs, const DevH8Face* faces,
+                        int ntiles, const DevBox* boxes, const void* u, void* w, double c, int rmax, int nvtmax,
+                        hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  if (segs && !faces) return hipErrorInvalidValue;
   const int ldw = ((nvtmax * vec + 8) + 3) & ~3, ldh = rmax + 8;
   const size_t lds = 2 * (size_t)ldw * ldh * (dtype == BL_F64 ? 8 : 4);
   if (dtype == BL_F64) {
-    if (vec == 2) heat8_t<double, 2>(tiles, strips, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
-    else heat8_t<double, 1>(tiles, strips, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
+    if (vec == 2) heat8_t<double, 2>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
+    else heat8_t<double, 1>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
   } else {
-    if (vec == 4) heat8_t<float, 4>(tiles, strips, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
-    else heat8_t<float, 1>(tiles, strips, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
+    if (vec == 4) heat8_t<float, 4>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
+    else heat8_t<float, 1>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
   }
   return hipGetLastError();
 }

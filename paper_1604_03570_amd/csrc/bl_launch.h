@@ -95,12 +95,13 @@ hipError_t launch_restrict_residual(const Plan& fine, const Plan& coarse, const 
                                     double h2, hipStream_t s);
 hipError_t launch_prolong_add(const Plan& fine, const Plan& coarse, void* phi, const void* pc, hipStream_t s);
 
-// 8th-order heat step (9-cell span) over tiles built for it: at most 256
-// lanes, rows <= rmax <= 32, nvt <= nvtmax <= 32.  strips == nullptr: u's
-// ghosts (>= 4 layers) filled; else one strip table per tile (fused form,
-// tiles from build_h8_fused_tiles), no fill needed.
-hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, const DevH8Strips* strips, int ntiles,
-                        const DevBox* boxes, const void* u, void* w, double c, int rmax, int nvtmax, hipStream_t s);
+// 8th-order heat step (9-cell span) over tiles built for it (build_h8_tiles):
+// at most 256 lanes, rows <= rmax <= 32, nvt <= nvtmax <= 32.  segs == nullptr:
+// u's ghosts (>= 4 layers) filled; else the fused form, cells outside a box
+// read through the face segments of build_h8_segments, no fill needed.
+hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, const DevH8Seg* segs, const DevH8Face* faces,
+                        int ntiles, const DevBox* boxes, const void* u, void* w, double c, int rmax, int nvtmax,
+                        hipStream_t s);
 
 // dst[0..bytes) = src[0..bytes): 16-byte aligned, bytes a multiple of 16.
 hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -513,103 +513,9 @@ void build_h8_tiles(const Plan& p, std::vector<DevTile>& tiles, int* rmax, int* 
   }
 }
 
-// Source of strip `s` of tile t of box b (see DevH8Src): the one FillBoundary
-// record of b whose region holds the strip's cells outside the box, or b's own
-// ghost cells where no record meets them.  False where records split the strip
-// or a vector load would be misaligned.  Every address the kernel can form for
-// the strip is checked to lie inside the MultiFab's storage.
-static bool h8_strip_source(const Plan& p, int b, const std::vector<int>& recs, const DevTile& t, int s,
-                            DevH8Src* out, std::string* why) {
-  const DevBox& B = p.hboxes[b];
-  const Box& bx = p.boxes[b];
-  const FabGeom& df = p.fabs[b];
-  const int V = p.vec, x0 = t.xv0 * V, W = t.nvt * V;
-  int lo[3] = {x0, t.y0, t.z0}, hi[3] = {x0 + W - 1, t.y0 + t.rows - 1, t.z1 - 1};
-  const int e[3] = {B.ex, B.ey, B.ez};
-  const int a = s / 2, side = s % 2;
-  if (side == 0) {
-    lo[a] = lo[a] - 4;
-    hi[a] = std::min(lo[a] + 3, -1);
-  } else {
-    const int top = hi[a];
-    lo[a] = std::max(top + 1, e[a]);
-    hi[a] = top + 4;
-  }
-  const int64_t n = t.comp;
-  DevH8Src src;
-  if (a == 0) {  // own x ghost slab: layer -1-x (low side) or x-ex (high side)
-    src.o = side ? df.xs + df.xs_side - B.ex : df.xs - 1;
-    src.o += n * df.sc;
-    src.sx = side ? 1 : -1;
-    src.sy = (int32_t)df.ng;
-    src.sz = df.xs_z;
-  } else {       // own rows of the grown box
-    src.o = df.off + n * df.sc;
-    src.sx = 1;
-    src.sy = (int32_t)df.sy;
-    src.sz = df.sz;
-  }
-  if (lo[a] > hi[a]) {  // the tile's cells next to this face all lie in the box
-    *out = src;
-    return true;
-  }
-  int glo[3], ghi[3];
-  for (int d = 0; d < 3; ++d) {
-    glo[d] = lo[d] + bx.lo[d];
-    ghi[d] = hi[d] + bx.lo[d];
-  }
-  int found = -1;
-  bool meets = false;
-  for (int ri : recs) {
-    const FillRecord& r = (*p.fill)[ri];
-    bool inside = true, overlap = true;
-    for (int d = 0; d < 3; ++d) {
-      if (glo[d] < r.region.lo[d] || ghi[d] > r.region.hi[d]) inside = false;
-      if (ghi[d] < r.region.lo[d] || glo[d] > r.region.hi[d]) overlap = false;
-    }
-    if (inside) {
-      found = ri;
-      break;
-    }
-    if (overlap) meets = true;
-  }
-  if (found < 0 && meets) {
-    *why = "a tile strip has several sources (a neighbour thinner than 4 cells across a face)";
-    return false;
-  }
-  if (found >= 0) {  // neighbour cell = destination cell + shift, inside the source's valid box
-    const FillRecord& r = (*p.fill)[found];
-    const FabGeom& sf = p.fabs[r.src];
-    src.o = sf.off + n * sf.sc + (int64_t)(bx.lo[0] + r.shift[0] - sf.valid.lo[0]) +
-            (int64_t)(bx.lo[1] + r.shift[1] - sf.valid.lo[1]) * sf.sy +
-            (int64_t)(bx.lo[2] + r.shift[2] - sf.valid.lo[2]) * sf.sz;
-    src.sx = 1;
-    src.sy = (int32_t)sf.sy;
-    src.sz = sf.sz;
-  }
-  if (a > 0 && V > 1 && (src.o % V != 0 || src.sy % V != 0 || src.sz % V != 0)) {
-    *why = "a y or z strip source is not vector-aligned";
-    return false;
-  }
-  // the affine address is extreme at the region's corners; y and z strips are
-  // read as whole vectors starting at x0, x0 + V, ..., x0 + W - V
-  const int len = a > 0 ? V : 1, xlast = a > 0 ? hi[0] - V + 1 : hi[0];
-  for (int c = 0; c < 8; ++c) {
-    const int x = c & 1 ? xlast : lo[0], y = c & 2 ? hi[1] : lo[1], z = c & 4 ? hi[2] : lo[2];
-    const int64_t at = src.o + (int64_t)x * src.sx + (int64_t)y * src.sy + (int64_t)z * src.sz;
-    if (at < 0 || at + len > (int64_t)p.total_elems) {
-      *why = "internal error: a strip address leaves the MultiFab";
-      return false;
-    }
-  }
-  *out = src;
-  return true;
-}
-
-bool build_h8_fused_tiles(const Plan& p, std::vector<DevTile>& tiles, std::vector<DevH8Strips>& strips, int* rmax,
-                          int* nvtmax, std::string* why) {
-  tiles.clear();
-  strips.clear();
+bool build_h8_segments(const Plan& p, std::vector<DevH8Seg>& segs, std::vector<DevH8Face>& faces, std::string* why) {
+  segs.clear();
+  faces.clear();
   if (p.ng < 4 || !p.fill) {
     *why = "nghost < 4";
     return false;
@@ -617,69 +523,114 @@ bool build_h8_fused_tiles(const Plan& p, std::vector<DevTile>& tiles, std::vecto
   const int V = p.vec, nb = (int)p.hboxes.size();
   std::vector<std::vector<int>> byd(nb);
   for (int i = 0; i < (int)p.fill->size(); ++i) byd[(*p.fill)[i].dst].push_back(i);
-  std::vector<int> cuts[3];
+  faces.resize(nb);
   for (int b = 0; b < nb; ++b) {
     const DevBox& B = p.hboxes[b];
     const Box& bx = p.boxes[b];
+    const FabGeom& df = p.fabs[b];
     const int e[3] = {B.ex, B.ey, B.ez};
-    for (int d = 0; d < 3; ++d) cuts[d].assign({0, e[d]});
-    // a record whose region lies outside the box along exactly one axis a (a
-    // face region) cuts the box along the two other axes at its edges
-    for (int ri : byd[b]) {
-      const Box& R = (*p.fill)[ri].region;
-      int lo[3], hi[3], nout = 0, a = -1;
-      for (int d = 0; d < 3; ++d) {
-        lo[d] = R.lo[d] - bx.lo[d];
-        hi[d] = R.hi[d] - bx.lo[d];
-        if (hi[d] < 0 || lo[d] >= e[d]) {
-          ++nout;
-          a = d;
+    for (int f = 0; f < 6; ++f) {
+      const int a = f / 2, side = f % 2;
+      const int u1 = a == 0 ? 1 : 0, u2 = a == 2 ? 1 : 2;  // tangential axes
+      const int nlo = side ? e[a] : -4, nhi = side ? e[a] + 3 : -1;  // the face's 4 layers
+      faces[b].start[f] = (int32_t)segs.size();
+      std::vector<int> c1{0, e[u1]}, c2{0, e[u2]};
+      std::vector<std::array<int, 4>> rects;  // covered (t1lo, t1hi, t2lo, t2hi)
+      auto add = [&](DevH8Seg g, int t1lo, int t1hi, int t2lo, int t2hi) -> bool {
+        g.t1lo = t1lo;
+        g.t1hi = t1hi;
+        g.t2lo = t2lo;
+        g.t2hi = t2hi;
+        if (g.sz > INT32_MAX || g.sy > INT32_MAX) {  // the kernel keeps plane strides in 32 bits
+          *why = "a plane stride exceeds 32 bits";
+          return false;
         }
+        if (V > 1 && a > 0) {  // y and z faces: a lane's vector of x cells lies in one segment
+          if (t1lo % V || (t1hi + 1) % V || g.o % V || g.sc % V || g.sy % V || g.sz % V) {
+            *why = "a y- or z-face segment is not vector-aligned";
+            return false;
+          }
+        }
+        for (int c = 0; c < 16; ++c) {  // the affine address is extreme at the corners
+          int q[3];
+          q[a] = c & 1 ? nhi : nlo;
+          q[u1] = c & 2 ? t1hi : t1lo;
+          q[u2] = c & 4 ? t2hi : t2lo;
+          const int64_t n = c & 8 ? p.ncomp - 1 : 0;
+          const int len = a > 0 ? V : 1;
+          if (a > 0 && (c & 2)) q[0] = t1hi - V + 1;  // vectors start at multiples of V
+          const int64_t at = g.o + n * g.sc + (int64_t)q[0] * g.sx + (int64_t)q[1] * g.sy + (int64_t)q[2] * g.sz;
+          if (at < 0 || at + len > (int64_t)p.total_elems) {
+            *why = "internal error: a segment address leaves the MultiFab";
+            return false;
+          }
+        }
+        segs.push_back(g);
+        return true;
+      };
+      for (int ri : byd[b]) {
+        const FillRecord& r = (*p.fill)[ri];
+        int lo[3], hi[3];
+        bool meets = true;
+        for (int d = 0; d < 3; ++d) {
+          lo[d] = r.region.lo[d] - bx.lo[d];
+          hi[d] = r.region.hi[d] - bx.lo[d];
+          const int slo = d == a ? nlo : 0, shi = d == a ? nhi : e[d] - 1;
+          lo[d] = std::max(lo[d], slo);
+          hi[d] = std::min(hi[d], shi);
+          if (lo[d] > hi[d]) meets = false;
+        }
+        if (!meets) continue;
+        if (lo[a] != nlo || hi[a] != nhi) {
+          *why = "a neighbour is thinner than the 4 ghost layers across a face";
+          return false;
+        }
+        const FabGeom& sf = p.fabs[r.src];
+        DevH8Seg g;
+        std::memset(&g, 0, sizeof g);
+        g.o = sf.off + (int64_t)(bx.lo[0] + r.shift[0] - sf.valid.lo[0]) +
+              (int64_t)(bx.lo[1] + r.shift[1] - sf.valid.lo[1]) * sf.sy +
+              (int64_t)(bx.lo[2] + r.shift[2] - sf.valid.lo[2]) * sf.sz;
+        g.sc = sf.sc;
+        g.sx = 1;
+        g.sy = (int32_t)sf.sy;
+        g.sz = sf.sz;
+        if (!add(g, lo[u1], hi[u1], lo[u2], hi[u2])) return false;
+        rects.push_back({lo[u1], hi[u1], lo[u2], hi[u2]});
+        c1.push_back(lo[u1]);
+        c1.push_back(hi[u1] + 1);
+        c2.push_back(lo[u2]);
+        c2.push_back(hi[u2] + 1);
       }
-      if (nout != 1) continue;
-      for (int d = 0; d < 3; ++d) {
-        if (d == a) continue;
-        cuts[d].push_back(std::max(0, std::min(lo[d], e[d])));
-        cuts[d].push_back(std::max(0, std::min(hi[d] + 1, e[d])));
+      // the parts of the face no box covers: the box's own ghost cells
+      std::sort(c1.begin(), c1.end());
+      c1.erase(std::unique(c1.begin(), c1.end()), c1.end());
+      std::sort(c2.begin(), c2.end());
+      c2.erase(std::unique(c2.begin(), c2.end()), c2.end());
+      DevH8Seg own;
+      std::memset(&own, 0, sizeof own);
+      own.sc = df.sc;
+      if (a == 0) {  // x ghost slab: layer -1-x (low side) or x-ex (high side)
+        own.o = side ? df.xs + df.xs_side - B.ex : df.xs - 1;
+        own.sx = side ? 1 : -1;
+        own.sy = (int32_t)df.ng;
+        own.sz = df.xs_z;
+      } else {       // rows of the grown box
+        own.o = df.off;
+        own.sx = 1;
+        own.sy = (int32_t)df.sy;
+        own.sz = df.sz;
       }
+      for (size_t i1 = 0; i1 + 1 < c1.size(); ++i1)
+        for (size_t i2 = 0; i2 + 1 < c2.size(); ++i2) {
+          const int t1 = c1[i1], t2 = c2[i2];
+          bool covered = false;
+          for (const auto& R : rects)
+            if (t1 >= R[0] && t1 <= R[1] && t2 >= R[2] && t2 <= R[3]) covered = true;
+          if (!covered && !add(own, c1[i1], c1[i1 + 1] - 1, c2[i2], c2[i2 + 1] - 1)) return false;
+        }
+      faces[b].count[f] = (int32_t)segs.size() - faces[b].start[f];
     }
-    for (int d = 0; d < 3; ++d) {
-      std::sort(cuts[d].begin(), cuts[d].end());
-      cuts[d].erase(std::unique(cuts[d].begin(), cuts[d].end()), cuts[d].end());
-    }
-    for (int x : cuts[0])
-      if (x % V) {
-        *why = "a neighbour's x boundary falls inside an x vector";
-        return false;
-      }
-    const int nvt_full = std::min(B.nvx, 16);
-    const int rows_full = std::max(1, std::min({B.ey, 32, 256 / nvt_full}));
-    for (int n = 0; n < p.ncomp; ++n)
-      for (size_t iz = 0; iz + 1 < cuts[2].size(); ++iz)
-        for (int z0 = cuts[2][iz]; z0 < cuts[2][iz + 1]; z0 += 32)
-          for (size_t iy = 0; iy + 1 < cuts[1].size(); ++iy)
-            for (int y0 = cuts[1][iy]; y0 < cuts[1][iy + 1]; y0 += rows_full)
-              for (size_t ix = 0; ix + 1 < cuts[0].size(); ++ix)
-                for (int xv0 = cuts[0][ix] / V; xv0 < cuts[0][ix + 1] / V; xv0 += nvt_full) {
-                  DevTile t;
-                  std::memset(&t, 0, sizeof t);
-                  t.box = b;
-                  t.comp = n;
-                  t.xv0 = xv0;
-                  t.nvt = std::min(nvt_full, cuts[0][ix + 1] / V - xv0);
-                  t.y0 = y0;
-                  t.rows = std::min(rows_full, cuts[1][iy + 1] - y0);
-                  t.z0 = z0;
-                  t.z1 = std::min(z0 + 32, cuts[2][iz + 1]);
-                  for (int f = 0; f < 6; ++f) t.frec[f] = kFaceNone;
-                  DevH8Strips S;
-                  for (int s = 0; s < 6; ++s)
-                    if (!h8_strip_source(p, b, byd[b], t, s, &S.s[s], why)) return false;
-                  *rmax = std::max(*rmax, t.rows);
-                  *nvtmax = std::max(*nvtmax, t.nvt);
-                  tiles.push_back(t);
-                  strips.push_back(S);
-                }
   }
   return true;
 }
@@ -1008,36 +959,27 @@ static bl_status host_plan(const bl_boxarray* ba, int32_t ncomp, int32_t nghost,
   return build_plan(ba, ncomp, nghost, dtype, tile_config(), out);
 }
 
-bl_status bl_heat8_fused_layout(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype, int32_t* ntiles,
-                                int32_t* tiles, int64_t* strips, int64_t* total_elems) {
+bl_status bl_heat8_fused_layout(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype, int32_t* nsegs,
+                                int64_t* segs, int64_t* total_elems) {
   clear_error();
-  if (!ntiles) return fail(BL_EINVAL, "NULL argument");
+  if (!nsegs) return fail(BL_EINVAL, "NULL argument");
   std::shared_ptr<Plan> p;
   bl_status st = host_plan(ba, ncomp, nghost, dtype, &p);
   if (st != BL_OK) return st;
-  std::vector<DevTile> t;
-  std::vector<DevH8Strips> sv;
-  int rm = 1, nv = 1;
+  std::vector<DevH8Seg> sv;
+  std::vector<DevH8Face> fv;
   std::string why;
-  if (!build_h8_fused_tiles(*p, t, sv, &rm, &nv, &why)) return fail(BL_EINVAL, "%s", why.c_str());
-  *ntiles = (int32_t)t.size();
+  if (!build_h8_segments(*p, sv, fv, &why)) return fail(BL_EINVAL, "%s", why.c_str());
+  *nsegs = (int32_t)sv.size();
   if (total_elems) *total_elems = (int64_t)p->total_elems;
-  for (size_t i = 0; i < t.size(); ++i) {
-    if (tiles) {
-      int32_t* r = tiles + 9 * i;
-      const int32_t v[9] = {t[i].box, t[i].comp, t[i].xv0 * p->vec, t[i].nvt * p->vec, t[i].y0, t[i].rows,
-                            t[i].z0, t[i].z1, p->vec};
-      std::memcpy(r, v, sizeof v);
-    }
-    if (strips)
-      for (int s = 0; s < 6; ++s) {
-        int64_t* r = strips + 24 * i + 4 * s;
-        r[0] = sv[i].s[s].o;
-        r[1] = sv[i].s[s].sx;
-        r[2] = sv[i].s[s].sy;
-        r[3] = sv[i].s[s].sz;
-      }
-  }
+  if (segs)
+    for (size_t b = 0; b < fv.size(); ++b)
+      for (int f = 0; f < 6; ++f)
+        for (int i = fv[b].start[f]; i < fv[b].start[f] + fv[b].count[f]; ++i) {
+          const DevH8Seg& g = sv[i];
+          const int64_t row[12] = {(int64_t)b, f, g.t1lo, g.t1hi, g.t2lo, g.t2hi, g.o, g.sc, g.sx, g.sy, g.sz, p->vec};
+          std::memcpy(segs + 12 * (int64_t)i, row, sizeof row);
+        }
   return BL_OK;
 }
 
