@@ -107,3 +107,27 @@ def test_fused_heat8_reports_layouts_it_cannot_take():
     boxes = np.array([[0, 0, 0, 31, 15, 31], [0, 16, 0, 5, 31, 31], [6, 16, 0, 31, 31, 31]])
     segs, _ = bt.BoxArray.from_boxes(boxes, dom).heat8_fused_layout(1, 4, bt.F32)
     assert (segs[:, 11] == 1).all()
+
+
+def test_layout_index_bounds_and_errors():
+    dom = I.domain_box(16)
+    boxes = I.regular_chop(dom, 8)
+    ba = bt.BoxArray.from_boxes(boxes, dom)
+    # cells of one box's grown box map to distinct elements inside the MultiFab
+    _, total = ba.heat8_fused_layout(2, 4, bt.F64)
+    seen = set()
+    for k in range(-4, 12):
+        for j in (-4, 0, 7, 11):
+            for i in range(-4, 12):
+                for comp in (0, 1):
+                    at = ba.layout_index(2, 4, bt.F64, 0, (i, j, k), comp)
+                    assert 0 <= at < total
+                    seen.add(at)
+    assert len(seen) == 16 * 4 * 16 * 2
+    for bad in (((12, 0, 0), 0, 0), ((0, 0, 0), 0, 2), ((0, -5, 0), 0, 0)):
+        cell, box, comp = bad
+        with pytest.raises(bt.BoxtileError) as e:
+            ba.layout_index(2, 4, bt.F64, box, cell, comp)
+        assert e.value.code == bt.BL_EINVAL
+    with pytest.raises(bt.BoxtileError):
+        ba.layout_index(2, 4, bt.F64, len(boxes), (0, 0, 0), 0)
