@@ -270,9 +270,9 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
  *                copy them from, or from the box's own ghost cells where no box
  *                covers them; each lane finds its source among the face's
  *                segments.  Applies where every neighbour across a face is at
- *                least 4 cells thick and, with vectors of more than one cell,
- *                neighbour boundaries fall on x-vector edges
- *                (bl_heat8_fused_ok); else BL_EINVAL.
+ *                least 4 cells thick, plane strides fit in 32 bits and, with
+ *                vectors of more than one cell, neighbour boundaries fall on
+ *                x-vector edges (bl_heat8_fused_ok); else BL_EINVAL.
  *   BL_H8_AUTO   the fused form where it applies, else the fill form.
  * The fill form writes u_old's ghost cells each step; the fused form writes no
  * ghost cell.  bl_heat8_advance is bl_heat8_advance_form with BL_H8_AUTO.
