@@ -246,7 +246,9 @@ bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t
  * read the neighbouring box's valid cells (or their periodic image) directly,
  * which is the value FillBoundary would have put in the ghost cell; x
  * neighbours come from the copy of each box's edge columns that every step
- * writes with the new state (a first kernel makes it for u[0]).  The launches
+ * writes with the new state (the first step reads them from the neighbours'
+ * rows in the default tile form; the other forms run a first kernel that makes
+ * the copy for u[0]).  The launches
  * are captured once in a HIP graph and replayed.  Ghost
  * cells are neither read where a box covers them nor written.  Results are
  * bit-identical to bl_heat_step with fill_first = 1.

@@ -24,6 +24,7 @@ bl_status hip_fail(int err, const char* what) {
 Plan::~Plan() {
   (void)hipFree(dboxes);
   (void)hipFree(dfacerecs);
+  (void)hipFree(dfacerecs_rows);
   (void)hipFree(dtiles);
   (void)hipFree(dlin);
   (void)hipFree(dred);
@@ -54,6 +55,8 @@ bl_status upload_plan(Plan& p) {
   bl_status st;
   if ((st = upload(&p.dboxes, p.hboxes, "hipMalloc/hipMemcpy(boxes)")) != BL_OK) return st;
   if ((st = upload(&p.dfacerecs, p.hfacerecs, "hipMalloc/hipMemcpy(face records)")) != BL_OK) return st;
+  if ((st = upload(&p.dfacerecs_rows, p.hfacerecs_rows, "hipMalloc/hipMemcpy(face records, rows)")) != BL_OK)
+    return st;
   if ((st = upload(&p.dtiles, p.htiles, "hipMalloc/hipMemcpy(tiles)")) != BL_OK) return st;
   if ((st = upload(&p.dlin, p.hlin, "hipMalloc/hipMemcpy(stencil tiles)")) != BL_OK) return st;
   if ((st = upload(&p.dred, p.hred, "hipMalloc/hipMemcpy(reduction chunks)")) != BL_OK) return st;
@@ -405,10 +408,15 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
                p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block, p.rmax, p.nvtmax,
                p.dlin, (int)p.hlin.size(), p.yhmax, p.xhmax};
     BL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    // the edge-column mirror of the starting state, then the fused steps
-    hipError_t le = launch_extract_mirror(p, u[0]->data, cs);
+    // The fused steps read x neighbours from the edge-column mirror that each
+    // step writes for its output.  The halo-in-LDS form reads the first step's
+    // from the neighbours' rows instead (no mirror of the starting state is
+    // needed); the other forms get one made first.
+    const bool rows_first = p.cfg.block == 3 && p.dlin && p.fvec && p.dfacerecs_rows;
+    hipError_t le = rows_first ? hipSuccess : launch_extract_mirror(p, u[0]->data, cs);
     for (int s = 0; s < nsteps && le == hipSuccess; ++s) {
       a.flip = s & 1;
+      a.recs = rows_first && s == 0 ? p.dfacerecs_rows : p.dfacerecs;
       le = launch_heat(p.dtype, p.vec, true, a, persistent_grid(persist), block_of(p), cs);
     }
     hipGraph_t graph = nullptr;

@@ -302,6 +302,10 @@ struct Plan {
   // host copies
   std::vector<DevBox> hboxes;
   std::vector<DevFaceRec> hfacerecs;
+  // the same records with every covered x face read from the source box's rows
+  // instead of its edge-column mirror: the first fused step of a run, whose
+  // input has no current mirror
+  std::vector<DevFaceRec> hfacerecs_rows;
   std::vector<DevTile> htiles;            // all components
   std::vector<int> box_tile_start;        // tiles of box b = [start[b], start[b+1])
   int rmax = 1;                           // most rows of any tile
@@ -321,6 +325,7 @@ struct Plan {
   // device copies (owned), made by upload_plan
   DevBox* dboxes = nullptr;
   DevFaceRec* dfacerecs = nullptr;
+  DevFaceRec* dfacerecs_rows = nullptr;
   DevTile* dtiles = nullptr;
   DevLinTile* dlin = nullptr;
   DevRedChunk* dred = nullptr;

@@ -796,6 +796,7 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
   const auto face_ptr = face_plan(ba, ng);
   const auto& faces = *face_ptr;
   p->hfacerecs.clear();
+  p->hfacerecs_rows.clear();
   size_t k = 0;
   for (size_t i = 0; i < ba->boxes.size(); ++i) {
     const Box& bx = ba->boxes[i];
@@ -850,6 +851,13 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
             (((R.base % p->vec) + p->vec) % p->vec != 0 || R.t1lo % p->vec != 0 || (R.t1hi + 1) % p->vec != 0))
           p->fvec = 0;
         p->hfacerecs.push_back(R);
+        if (a == 0 && !uncovered) {  // the source's edge column in its own rows
+          const int64_t ra = sf.index(q[0] + r.shift[0], q[1] + r.shift[1], q[2] + r.shift[2]);
+          R.base = ra - lo1 * sf.sy - lo2 * sf.sz;
+          R.s1 = (int32_t)sf.sy;
+          R.s2 = (int32_t)sf.sz;
+        }
+        p->hfacerecs_rows.push_back(R);
         ++cnt;
       }
       if (cnt > 32767) return fail(BL_EINVAL, "too many neighbours on one face of box %zu", i);
