@@ -652,8 +652,7 @@ bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, do
   double* dout = phi->dscratch + reduce_slots(p);
   const int grid = persistent_grid(tile_config().persist);
   if (gsrb_fused_ok(p, block_of(p))) {  // neighbour values straight from the neighbour boxes
-    BL_HIP(launch_extract_mirror(p, phi->data, stream));
-    BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, -1, 2, phi->dscratch, grid, block_of(p), stream));
+    BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, -1, 2, phi->dscratch, grid, block_of(p), stream, true));
     BL_HIP(launch_reduce_partials(phi->dscratch, gsrb_fused_grid(p, grid), 1, dout, stream));
   } else {
     BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
@@ -666,15 +665,15 @@ bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, do
 }
 
 // nsweeps red-black sweeps of phi in place, no norms: the fused passes where the
-// plan allows them (edge mirror extracted first), else a fill before each colour.
+// plan allows them (the first reads x-face neighbours from the neighbours' rows
+// and leaves the edge mirrors current), else a fill before each colour.
 static hipError_t gsrb_smooth(const Plan& p, void* phi, const void* f, double h2, int nsweeps, hipStream_t stream) {
   if (nsweeps <= 0) return hipSuccess;
   hipError_t e = hipSuccess;
   if (gsrb_fused_ok(p, block_of(p))) {
     const int grid = persistent_grid(tile_config().persist);
-    e = launch_extract_mirror(p, phi, stream);
     for (int s = 0; s < nsweeps && e == hipSuccess; ++s) {
-      e = launch_gsrb_fused(p, phi, f, h2, 0, 0, nullptr, grid, block_of(p), stream);
+      e = launch_gsrb_fused(p, phi, f, h2, 0, 0, nullptr, grid, block_of(p), stream, s == 0);
       if (e == hipSuccess) e = launch_gsrb_fused(p, phi, f, h2, 1, 1, nullptr, grid, block_of(p), stream);
     }
     return e;
@@ -694,8 +693,8 @@ static hipError_t residual_norm_dev(const Plan& p, void* phi, const void* f, dou
   hipError_t e;
   if (gsrb_fused_ok(p, block_of(p))) {
     const int grid = persistent_grid(tile_config().persist);
-    if ((e = launch_extract_mirror(p, phi, stream)) != hipSuccess) return e;
-    if ((e = launch_gsrb_fused(p, phi, f, h2, -1, 2, partials, grid, block_of(p), stream)) != hipSuccess) return e;
+    if ((e = launch_gsrb_fused(p, phi, f, h2, -1, 2, partials, grid, block_of(p), stream, true)) != hipSuccess)
+      return e;
     return launch_reduce_partials(partials, gsrb_fused_grid(p, grid), 1, out, stream);
   }
   if ((e = launch_fill(p, phi, 0, 1, stream)) != hipSuccess) return e;
@@ -722,6 +721,8 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
     double* red_part = resnorm_host ? phi->dscratch : nullptr;
     double* black_part = resnorm_host ? phi->dscratch + g : nullptr;
     double* norms = resnorm_host ? phi->dscratch + 2 * g : nullptr;
+    // the edge mirror of the starting state first: over many sweeps one
+    // extraction costs less than a first pass reading the neighbours' rows
     if (nsweeps > 0) BL_HIP(launch_extract_mirror(p, phi->data, stream));
     for (int s = 0; s < nsweeps; ++s) {
       BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, 0, 0, s > 0 ? red_part : nullptr, grid, block_of(p),

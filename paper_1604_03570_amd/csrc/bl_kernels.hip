@@ -1940,27 +1940,28 @@ hipError_t launch_residual(const Plan& p, const void* phi, const void* f, double
 // `partials` the per-workgroup sums of r^2 of the cells of colour rescolor.
 template <typename T, int V, int ZB>
 static hipError_t gsrb_dma_zb(const Plan& p, void* phi, const void* f, double h2, int color, int rescolor,
-                              double* partials, int g, int persist, int block, hipStream_t s) {
+                              double* partials, int g, int persist, int block, hipStream_t s, bool rows) {
+  const DevFaceRec* recs = rows ? p.dfacerecs_rows : p.dfacerecs;
   const size_t lds = dma_lds_bytes<T, V, ZB>(p.yhmax, p.xhmax, block);
   const T h2t = (T)h2, inv6 = (T)(1.0 / 6.0);
   if (partials)
     hipLaunchKernelGGL((k_gsrb_dma<T, V, ZB, true>), dim3(g), dim3(block), lds, s, p.dlin, (int)p.hlin.size(),
-                       p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor, 1.0 / h2, partials,
+                       p.dboxes, recs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor, 1.0 / h2, partials,
                        persist, p.yhmax);
   else
     hipLaunchKernelGGL((k_gsrb_dma<T, V, ZB, false>), dim3(g), dim3(block), lds, s, p.dlin, (int)p.hlin.size(),
-                       p.dboxes, p.dfacerecs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor, 1.0 / h2, partials,
+                       p.dboxes, recs, (T*)phi, (const T*)f, h2t, inv6, color, rescolor, 1.0 / h2, partials,
                        persist, p.yhmax);
   return hipGetLastError();
 }
 
 template <typename T, int V>
 static hipError_t gsrb_dma_v(const Plan& p, void* phi, const void* f, double h2, int color, int rescolor,
-                             double* partials, int g, int persist, int block, hipStream_t s) {
+                             double* partials, int g, int persist, int block, hipStream_t s, bool rows) {
   switch (p.cfg.zchunk) {
-    case 2: return gsrb_dma_zb<T, V, 2>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
-    case 8: return gsrb_dma_zb<T, V, 8>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
-    default: return gsrb_dma_zb<T, V, 4>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
+    case 2: return gsrb_dma_zb<T, V, 2>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s, rows);
+    case 8: return gsrb_dma_zb<T, V, 8>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s, rows);
+    default: return gsrb_dma_zb<T, V, 4>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s, rows);
   }
 }
 
@@ -1975,14 +1976,14 @@ int gsrb_fused_grid(const Plan& p, int grid) {
 }
 
 hipError_t launch_gsrb_fused(const Plan& p, void* phi, const void* f, double h2, int color, int rescolor,
-                             double* partials, int grid, int block, hipStream_t s) {
+                             double* partials, int grid, int block, hipStream_t s, bool rows) {
   if (p.hlin.empty()) return hipSuccess;
   const int g = gsrb_fused_grid(p, grid), persist = grid > 0 ? 1 : 0;
   if (p.dtype == BL_F64)
-    return p.vec == 2 ? gsrb_dma_v<double, 2>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s)
-                      : gsrb_dma_v<double, 1>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
-  return p.vec == 4 ? gsrb_dma_v<float, 4>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s)
-                    : gsrb_dma_v<float, 1>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s);
+    return p.vec == 2 ? gsrb_dma_v<double, 2>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s, rows)
+                      : gsrb_dma_v<double, 1>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s, rows);
+  return p.vec == 4 ? gsrb_dma_v<float, 4>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s, rows)
+                    : gsrb_dma_v<float, 1>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s, rows);
 }
 
 // Variable-coefficient heat step (k_heat_vc_dma) over the whole level, one

@@ -65,8 +65,10 @@ hipError_t launch_residual(const Plan& p, const void* phi, const void* f, double
 // into partials[0 .. gsrb_fused_grid).  Usable when gsrb_fused_ok.
 bool gsrb_fused_ok(const Plan& p, int block);
 int gsrb_fused_grid(const Plan& p, int grid);
+// rows: x-face neighbours from the neighbour boxes' rows, not their edge-column
+// mirrors (a first pass, when phi's mirror is not current; the pass leaves it so).
 hipError_t launch_gsrb_fused(const Plan& p, void* phi, const void* f, double h2, int color, int rescolor,
-                             double* partials, int grid, int block, hipStream_t s);
+                             double* partials, int grid, int block, hipStream_t s, bool rows = false);
 // *out = sum (sqrt of it if take_sqrt) of partials[0..n)
 hipError_t launch_reduce_partials(const double* partials, int n, int take_sqrt, double* out, hipStream_t s);
 
