@@ -43,6 +43,8 @@
  *   orc_heat_window    n heat steps on a cube window of a fully periodic global
  *                      array, returning the centre value (used to check single
  *                      outputs of very large runs one by one).
+ *   orc_fsum           exactly rounded sum of an array (the reductions' and the
+ *                      residual norm's sum).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -507,4 +509,111 @@ double orc_heat_window(double* w, double* tmp, int n, double c) {
     bb = t;
   }
   return a[((int64_t)n * e + n) * e + n];
+}
+
+/*
+ * Exactly rounded sum of n finite doubles: the reductions' definition (Sec. 3.1
+ * names the MultiFab sum; the oracle fixes it as the real sum of the values,
+ * rounded once to the nearest double, ties to even, so that it depends on
+ * neither order nor decomposition).  Method: Shewchuk's adaptive expansions
+ * ("Adaptive Precision Floating-Point Arithmetic and Fast Robust Geometric
+ * Predicates", 1997).  The running sum is held exactly as a list of
+ * non-overlapping partials of increasing magnitude; adding a value walks the
+ * list with an error-free two-sum (hi = x + y rounded, lo = the exact rounding
+ * error), keeping every non-zero error as a partial.  The result is the
+ * partials added from the largest down, stopping at the first inexact
+ * addition, with one correction so that a tie between two doubles, decided by
+ * the partials below, rounds the right way.
+ *
+ * Each thread sums a contiguous chunk into its own partials; the threads'
+ * partials are then added, exactly, into one list.  Since every step is exact
+ * the result does not depend on the thread count.  Partials are non-overlapping
+ * bit ranges inside the 2098-bit range of finite doubles, so there are never
+ * more than ORC_MAX_PARTIALS of them.  Returns NaN if a value or a partial is
+ * not finite (inputs here are residuals and states, far from overflow).
+ */
+#define ORC_MAX_PARTIALS 2112
+
+static int partials_add(double* p, int np, double x) {
+  int m = 0;
+  for (int j = 0; j < np; ++j) {
+    double y = p[j];
+    if ((x < 0 ? -x : x) < (y < 0 ? -y : y)) {
+      double t = x;
+      x = y;
+      y = t;
+    }
+    double hi = x + y;
+    double lo = y - (hi - x); /* exact: |x| >= |y| */
+    if (lo != 0.0) p[m++] = lo;
+    x = hi;
+  }
+  p[m++] = x;
+  return m;
+}
+
+static double partials_round(const double* p, int np) {
+  if (np == 0) return 0.0;
+  int n = np;
+  double hi = p[--n], lo = 0.0;
+  while (n > 0) {
+    double x = hi, y = p[--n];
+    hi = x + y;
+    lo = y - (hi - x);
+    if (lo != 0.0) break;
+  }
+  /* hi + lo is exact and lo is half an ulp of hi or less; if the partials still
+   * below point the same way as lo, a tie in hi + lo must round away from hi */
+  if (n > 0 && ((lo < 0 && p[n - 1] < 0) || (lo > 0 && p[n - 1] > 0))) {
+    double y = lo * 2.0, x = hi + y;
+    if (y == x - hi) hi = x;
+  }
+  return hi;
+}
+
+double orc_fsum(const double* v, int64_t n) {
+  int nt = orc_num_threads();
+  if (nt < 1) nt = 1;
+  if ((int64_t)nt > n / 65536 + 1) nt = (int)(n / 65536 + 1);
+  double* all = (double*)malloc(sizeof(double) * (size_t)nt * ORC_MAX_PARTIALS);
+  int* cnt = (int*)calloc((size_t)nt, sizeof(int));
+  int bad = 0;
+  if (!all || !cnt) {
+    free(all);
+    free(cnt);
+    return 0.0 / 0.0;
+  }
+#pragma omp parallel for schedule(static, 1) num_threads(nt) reduction(| : bad)
+  for (int t = 0; t < nt; ++t) {
+    int64_t a = n * t / nt, b = n * (t + 1) / nt;
+    double* p = all + (size_t)t * ORC_MAX_PARTIALS;
+    int np = 0;
+    for (int64_t i = a; i < b; ++i) {
+      double x = v[i];
+      if (x - x != 0.0) { /* inf or NaN */
+        bad = 1;
+        break;
+      }
+      np = partials_add(p, np, x);
+      if (p[np - 1] - p[np - 1] != 0.0) {
+        bad = 1;
+        break;
+      }
+    }
+    cnt[t] = np;
+  }
+  double res = 0.0 / 0.0;
+  if (!bad) {
+    double* q = (double*)malloc(sizeof(double) * ORC_MAX_PARTIALS);
+    if (q) {
+      int nq = 0;
+      for (int t = 0; t < nt; ++t)
+        for (int j = 0; j < cnt[t]; ++j) nq = partials_add(q, nq, all[(size_t)t * ORC_MAX_PARTIALS + j]);
+      res = partials_round(q, nq);
+      free(q);
+    }
+  }
+  free(all);
+  free(cnt);
+  return res;
 }

@@ -136,15 +136,17 @@ def test_vcycles_every_tile_shape(bt, shape):
         bt.set_tile_config(4, 4, 0, 3)
 
 
-def test_vcycles_f32_follow_f64(bt):
-    P64 = _problem(bt, "uneven64", bt.F64)
+def test_vcycles_f32_follow_the_oracle(bt):
+    """FP32 storage: 5 V-cycles against the oracle's 5 (FP64) on the same f: the field
+    within 1e-5, the first cycles' norms within 1e-5 (later ones reach the FP32
+    rounding floor), and the FP32 residual still falls 3x per cycle at first."""
     P32 = _problem(bt, "uneven64", bt.F32)
-    n64 = bt.Multigrid(P64["ba"], bt.F64).vcycles(P64["phi"], P64["f"], P64["h2"], 5)
     n32 = bt.Multigrid(P32["ba"], bt.F32).vcycles(P32["phi"], P32["f"], P32["h2"], 5)
-    a64, a32 = gpu_global(P64["phi"]), gpu_global(P32["phi"])
-    err = rel_err(a32, a64)
-    say(f"mg f32 vs f64: field rel err {err:.2e}, norms {n32} vs {n64}")
+    on = O.mg_vcycles(P32["ophi"], P32["of"], P32["h2"], 5)
+    err = rel_err(gpu_global(P32["phi"]), P32["ophi"].to_global())
+    say(f"mg f32 vs oracle: field rel err {err:.2e}, norms {n32} vs {on}")
     assert err <= 1e-5
+    assert all(abs(a - b) <= 1e-5 * b for a, b in zip(n32[:2], on[:2]))
     assert all(b < 0.3 * a for a, b in zip(n32[:3], n32[1:4]))
 
 

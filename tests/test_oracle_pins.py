@@ -21,6 +21,7 @@ the oracle and checks exactly that):
   * reductions against exactly known sums.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -607,6 +608,51 @@ def test_reductions_exact_cases():
     assert O.reduce(m, 1, "max") == 0.0 and O.reduce(m, 1, "min") == -15.5
 
 
+def _exact_sum(values) -> float:
+    """The real sum of the values (rational arithmetic, no rounding), rounded once to the
+    nearest double (Fraction -> float rounds correctly, ties to even)."""
+    from fractions import Fraction
+    return float(sum((Fraction(float(v)) for v in values), Fraction(0)))
+
+
+def _fsum_cases():
+    rng = np.random.default_rng(31)
+    tiny = 2.0 ** -1074
+    cases = [
+        [],
+        [3.5],
+        [1.0, 1e100, 1.0, -1e100],                      # the ones survive the cancellation
+        [1.0, 2.0 ** -53],                              # a tie: rounds to even (1.0)
+        [1.0, 2.0 ** -53, 2.0 ** -106],                 # just above the tie: rounds up
+        [1.0, -(2.0 ** -53), -(2.0 ** -106)],           # below 1 the spacing halves: no tie
+        [1.0 + 2.0 ** -52, 2.0 ** -53],                 # a tie from an odd last bit: rounds up
+        [1.0 + 2.0 ** -52, 2.0 ** -53, -(2.0 ** -110)],  # below that tie: stays
+        [tiny, tiny, -tiny, 2.0 ** 1000, -(2.0 ** 1000)],
+        list(rng.standard_normal(5000)),
+        list(rng.standard_normal(3000) * 10.0 ** rng.integers(-30, 30, 3000)),
+        list(np.concatenate([rng.random(2000) * 1e20, -rng.random(2000) * 1e20, rng.random(7) * 1e-20])),
+    ]
+    big = rng.standard_normal(400_000) ** 2  # long enough to be split over threads
+    return cases, big
+
+
+def test_fsum_is_the_exactly_rounded_sum():
+    """The oracle's sum (Shewchuk's expansions in C, split over threads) equals the real
+    sum rounded once, computed with rationals, on cancellation, ties, subnormals, wide
+    exponent ranges and a long array; and it equals math.fsum."""
+    cases, big = _fsum_cases()
+    for vals in cases:
+        assert O.fsum(np.array(vals, dtype=np.float64)) == _exact_sum(vals), vals[:4]
+        assert O.fsum(np.array(vals, dtype=np.float64)) == math.fsum(vals)
+    assert O.fsum(big) == math.fsum(big.tolist())
+    for nt in (1, 3, 8):
+        O.set_num_threads(nt)
+        try:
+            assert O.fsum(big) == math.fsum(big.tolist())
+        finally:
+            O.set_num_threads(os.cpu_count() or 1)
+
+
 # ---------------------------------------------------------------------------------------------
 # planted mistakes: each must make at least one pin fail
 # ---------------------------------------------------------------------------------------------
@@ -833,6 +879,8 @@ MUTATIONS = {
     "mg_residual_sign": ("return fb[q] + (((sx + sy) + sz) - 6.0 * p[q]) / h2;",
                          "return fb[q] - (((sx + sy) + sz) - 6.0 * p[q]) / h2;"),
     "mg_prolong_parent": ("floor_half(i), floor_half(j), floor_half(k))", "floor_half(i + 1), floor_half(j), floor_half(k))"),
+    "fsum_drops_errors": ("if (lo != 0.0) p[m++] = lo;", "(void)lo;"),
+    "fsum_no_tie_correction": ("if (y == x - hi) hi = x;", "(void)x;"),
 }
 
 
@@ -850,6 +898,7 @@ def _pins_pass():
         checks.append(_h8_sine_error() <= 1e-12)
         test_heat8_is_eighth_order()
         test_mg_converges_to_the_discrete_sine_solution("boxes_of_8")
+        test_fsum_is_the_exactly_rounded_sum()
     except (AssertionError, ValueError, IndexError):
         return False
     return all(checks)
