@@ -134,9 +134,11 @@ def _short_kernel(name: str) -> str:
 
 
 def summarize_profiles(d: str) -> int:
-    """Summaries of three rocprofv3 runs of this script with PROFILE_ARGS: kernel trace
-    statistics, FETCH_SIZE and WRITE_SIZE per dispatch.  The counters are scaled by
-    what they read for the plain 2 GiB device copy that the same runs end with."""
+    """Summaries of rocprofv3 runs of this script with PROFILE_ARGS: kernel trace
+    statistics (DIR/trace), FETCH_SIZE and WRITE_SIZE per dispatch (DIR/fetch,
+    DIR/write), and any further counter runs under DIR/pmc_*.  FETCH_SIZE and
+    WRITE_SIZE are scaled by what they read for the plain 2 GiB device copy that the
+    same runs end with."""
     import glob
     import statistics
     import re
@@ -175,6 +177,20 @@ def summarize_profiles(d: str) -> int:
                 vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         return vals
 
+    # steady state and first steps apart: a dispatch of the fused kernel that starts
+    # more than 20 us after the previous one ended opens a graph launch (the first
+    # step of an advance, which reads the x-face neighbours from their rows)
+    disp = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                  for r in _read_csv(one("trace/*kernel_trace.csv")) if r["Kernel_Name"] == hk)
+    firsts, steady, prev_end = [], [], None
+    for st, en in disp:
+        (firsts if prev_end is None or st - prev_end > 20000 else steady).append((en - st) / 1e3)
+        prev_end = en
+    steady_us = statistics.median(steady)
+    first_us = statistics.median(firsts)
+    ksteps = int(line["steps"])
+    graph_us = first_us + (ksteps - 1) * steady_us
+
     fetch = per_dispatch(one("fetch/*counter_collection.csv"), "FETCH_SIZE")
     write = per_dispatch(one("write/*counter_collection.csv"), "WRITE_SIZE")
     copy_name = next((k for k in fetch if "copyBuffer" in k), None)
@@ -212,6 +228,35 @@ def summarize_profiles(d: str) -> int:
                  f"measured / algorithmic = {(fetch_b + write_b) / alg:.4f}\n")
         fh.write(f"* achieved at the traced average: algorithmic {alg / (avg_us * 1e-6) / 1e9:.0f} GB/s, "
                  f"measured {(fetch_b + write_b) / (avg_us * 1e-6) / 1e9:.0f} GB/s\n")
+        fh.write("\n## Steady state and the first step of each advance\n\n")
+        fh.write(f"* {len(disp)} dispatches of the fused kernel: {len(firsts)} open a graph launch (the first step of "
+                 f"an advance reads the x-face neighbours from their rows), {len(steady)} follow one another\n")
+        fh.write(f"* median duration: steady state {steady_us:.1f} us ({alg / (steady_us * 1e-6) / 1e9:.0f} GB/s "
+                 f"algorithmic, {alg / (steady_us * 1e-6) / 1e9 / (HBM_PEAK_GBS):.4f} of 8 TB/s); first step "
+                 f"{first_us:.1f} us\n")
+        fh.write(f"* one {ksteps}-step advance from the trace: {graph_us / 1e3:.4f} ms of kernel time = "
+                 f"{ksteps * cells / (graph_us * 1e-6) / 1e9:.1f} GCell/s, roofline fraction "
+                 f"{ksteps * alg / (graph_us * 1e-6) / 1e9 / HBM_PEAK_GBS:.4f} (the bench line below, timed with "
+                 f"events around the graph launch: {line['roofline']['frac']})\n")
+        extra_dirs = sorted(x for x in os.listdir(d) if x.startswith("pmc_") and os.path.isdir(os.path.join(d, x)))
+        for xd in extra_dirs:
+            rows = _read_csv(one(f"{xd}/*counter_collection.csv"))
+            per = {}
+            for r in rows:
+                per.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+            names = sorted({cn for (kn, cn) in per if kn == hk})
+            fh.write(f"\n## Counters `{' '.join(names)}` (median per dispatch)\n\n")
+            fh.write(f"    rocprofv3 --pmc {' '.join(names)} --output-format csv -d <out>/{xd} -o run -- python3 bench.py {PROFILE_ARGS}\n\n")
+            fh.write("| kernel | " + " | ".join(names) + " |\n|---|" + "---|" * len(names) + "\n")
+            for kn in (hk, copy_name):
+                # the copy kernel: its largest dispatch (the 2 GiB copies, not torch's small ones)
+                vals = [(max(per[(kn, cn)]) if kn == copy_name else statistics.median(per[(kn, cn)]))
+                        if (kn, cn) in per else float("nan") for cn in names]
+                fh.write(f"| `{_short_kernel(kn)}` | " + " | ".join(f"{v:.0f}" for v in vals) + " |\n")
+            if "TCC_HIT_sum" in names and "TCC_MISS_sum" in names:
+                h = statistics.median(per[(hk, "TCC_HIT_sum")])
+                m = statistics.median(per[(hk, "TCC_MISS_sum")])
+                fh.write(f"\nL2 hit rate of the fused kernel: {h / (h + m):.4f}\n")
         fh.write(f"\nBench line of the trace run: `{json.dumps({k: line[k] for k in ('value', 'ms_per_step', 'roofline')})}`\n")
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -223,6 +268,7 @@ def summarize_profiles(d: str) -> int:
     t[dtype] = {"bytes_per_launch": round(fetch_b + write_b), "fetch_bytes": round(fetch_b),
                 "write_bytes": round(write_b), "fetch_scale": round(fetch_scale, 5),
                 "write_scale": round(write_scale, 5), "kernel": _short_kernel(hk), "avg_duration_us": round(avg_us, 2),
+                "steady_duration_us": round(steady_us, 2), "first_step_duration_us": round(first_us, 2),
                 "summary": os.path.relpath(out, ROOT)}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(t, fh, indent=1)
@@ -267,6 +313,69 @@ def summarize_trace(d: str) -> int:
             fh.write(f"    {ln}\n")
     print(f"wrote {out}")
     return 0
+
+
+def per_box_run(bt, I, torch) -> dict:
+    """The plain per-box form beside the batched one on the two small workloads:
+    CFG0, 64^3 periodic, 8 boxes of 32^3, Gaussian u0, 20 steps; and CFG1, 256^3
+    periodic, 64 boxes of 64^3, 3 seeded sine modes, 100 steps.  The per-box form is
+    FillBoundary followed by one stencil launch per box each step (the paper's
+    fill-then-kernel structure, one grid at a time); the batched form is the fused
+    kernel over the flattened tile list, one launch per step, the steps in one graph.
+    FP64 and FP32 storage, each timed with events over all its steps."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, n, edge, steps in (("cfg0_64cube_8x32", 64, 32, 20), ("cfg1_256cube_64x64", 256, 64, 100)):
+        dom = I.domain_box(n)
+        ba = bt.BoxArray.chop(dom, edge)
+        if n == 64:
+            u0 = I.gaussian(n)[None]
+        else:
+            u0, _ = I.sine_modes(n, seed=1)
+        c = I.heat_c(n)
+        cells = n ** 3
+        res = {"workload": f"{n}^3 periodic, {len(ba)} boxes of {edge}^3, 1 comp, 1 ghost, {steps} steps"}
+        for dname, dt, esize in (("f64", bt.F64, 8), ("f32", bt.F32, 4)):
+            g = u0 if dt == bt.F64 else I.round_f32(u0)
+            a, b = bt.MultiFab(ba, 1, 1, dt), bt.MultiFab(ba, 1, 1, dt)
+            a.from_global(g)
+
+            def per_box(x, y):
+                for _ in range(steps):
+                    bt.heat_step(x, y, c, fill_first=True)
+                    x, y = y, x
+                return x
+
+            def timed(fn):
+                fn()  # warm-up (captures the graph of the batched form)
+                a.from_global(g)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                r = fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / steps, r
+
+            ms_box, r_box = timed(lambda: per_box(a, b))
+            sum_box = r_box.sum(0)
+            g_box = r_box.to_global()
+            ms_bat, r_bat = timed(lambda: bt.heat_advance(a, b, steps, c))
+            same = bool(torch.equal(g_box, r_bat.to_global()))
+            gb, gt = cells / (ms_box / 1e3) / 1e9, cells / (ms_bat / 1e3) / 1e9
+            res[dname] = {"per_box": {"ms_per_step": round(ms_box, 5), "gcell_s": round(gb, 2),
+                                      "hbm_frac": round(gb * 2 * esize / HBM_PEAK_GBS, 4),
+                                      "launches_per_step": len(ba) + 1},
+                          "batched": {"ms_per_step": round(ms_bat, 5), "gcell_s": round(gt, 2),
+                                      "hbm_frac": round(gt * 2 * esize / HBM_PEAK_GBS, 4), "launches_per_step": 1},
+                          "batched_over_per_box": round(ms_box / ms_bat, 3),
+                          "same_result": same, "sum_after": sum_box}
+            log(f"{name} {dname}: per box {ms_box:.4f} ms/step ({gb:.1f} GCell/s), batched {ms_bat:.4f} "
+                f"ms/step ({gt:.1f} GCell/s), x{ms_box / ms_bat:.2f}, same result {same}")
+            del a, b, r_box, r_bat, g_box
+        out[name] = res
+    torch.cuda.empty_cache()
+    return out
 
 
 def gsrb_run(bt, I, torch, seed: int, sweeps: int = 20) -> dict:
@@ -604,9 +713,10 @@ def main() -> int:
         wall = time.perf_counter() - w0
         ms = e0.elapsed_time(e1)
         drift = abs(res.sum(0) - s0) / abs(s0)
-        # per-launch duration of the fused kernel: a 2K-step graph minus the K-step
-        # one (both measured with events on this stream), so the once-per-advance
-        # mirror extraction and the graph launch drop out
+        # marginal duration of one step: a 2K-step graph minus the K-step one (both
+        # measured with events on this stream); the first step of an advance (it
+        # reads the x-face neighbours from their rows, no edge mirror of the
+        # starting state exists yet) and the graph launch drop out of it
         cur = res
         oth = a if cur is b else b
         bt.heat_advance(cur, oth, 2 * steps, c)  # captures the 2K-step graph; 2K even: state back in cur
@@ -633,14 +743,21 @@ def main() -> int:
     sec = ms / 1e3
     value = cells * args.steps / sec / 1e9
     alg_bytes = 2 * esize * cells  # read u once, write u_new once
-    achieved = alg_bytes / (per_launch_ms / 1e3) / 1e9
+    # algorithmic bytes per launch over the average launch time of the timed region
+    # (one launch per step): the same figure as value x b_alg
+    achieved = alg_bytes / (sec / args.steps) / 1e9
+    marginal_gbs = alg_bytes / (per_launch_ms / 1e3) / 1e9
     traffic = measured_traffic(args.dtype)
     log(f"{args.dtype}: {ms:.3f} ms for {args.steps} steps (wall {wall * 1e3:.3f} ms), "
         f"{value:.1f} GCell/s, {achieved:.0f} GB/s, sum drift {drift:.2e}")
 
     extra = {"sum_drift_rel": drift, "wall_ms_timed": round(wall * 1e3, 4),
              "tile_shape": tuned["best"] if tuned else list(cfg_tile), "autotune": tuned,
-             "nboxes": len(boxes), "fused_kernel_ms_per_launch": round(per_launch_ms, 5),
+             "nboxes": len(boxes),
+             "marginal_per_launch": {"ms": round(per_launch_ms, 5), "gbs": round(marginal_gbs, 1),
+                                     "frac": round(marginal_gbs / HBM_PEAK_GBS, 4),
+                                     "note": "(T(2K-step graph) - T(K-step graph)) / K: one step of a long run, "
+                                             "without the first step of an advance and the graph launch"},
              "ms_per_step_repeats": {"n": len(reps), "median": round(float(np.median(reps)), 5),
                                      "min": round(min(reps), 5)}}
     if not args.no_extra:
@@ -697,6 +814,7 @@ def main() -> int:
     if not args.no_extra and args.dtype == "f64":
         extra["copy_line"] = copy_line(bt, torch)
         extra["paper_shape"] = paper_shape_run(bt, I, torch)
+        extra["per_box_baseline"] = per_box_run(bt, I, torch)
 
     if not args.no_extra and not args.no_varcoef and args.dtype == "f64":
         extra["varcoef"] = varcoef_run(bt, I, torch, boxes, dom, u0, ncomp, args.seed, 20)

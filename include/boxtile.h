@@ -444,7 +444,9 @@ bl_status bl_device_copy(void* dst, const void* src, size_t bytes, hipStream_t s
  * the tile's halo loaded from memory straight into LDS (zchunk 2, 4 or 8 for
  * the block forms), 0 for the z march.  Default: zchunk 4, waves 4, persist 0, block 3.
  * Applies to MultiFabs created afterwards and to
- * bl_batch objects at their next rebuild; results do not depend on it.
+ * bl_batch objects at their next rebuild; results do not depend on it.  The
+ * configuration is one setting of the whole process, shared by every thread:
+ * set it before creating MultiFabs, not while other threads create them.
  */
 bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int32_t block);
 bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist, int32_t* block);

@@ -95,6 +95,8 @@ static bl_status get_plan_cfg(const bl_boxarray* ba, int ncomp, int ng, int dtyp
   if (!p) {
     bl_status st = build_plan(ba, ncomp, ng, dtype, cfg, &p);
     if (st != BL_OK) return st;
+    // drop the entries of plans that no MultiFab holds any more
+    for (auto e = g_plans.begin(); e != g_plans.end();) e = e->second.expired() ? g_plans.erase(e) : std::next(e);
     g_plans[key] = p;
     // the most recent plans stay alive after their last MultiFab goes, so a
     // shape that comes back (a serving loop) reuses its tables

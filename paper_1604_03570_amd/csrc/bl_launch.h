@@ -66,7 +66,10 @@ hipError_t launch_residual(const Plan& p, const void* phi, const void* f, double
 bool gsrb_fused_ok(const Plan& p, int block);
 int gsrb_fused_grid(const Plan& p, int grid);
 // rows: x-face neighbours from the neighbour boxes' rows, not their edge-column
-// mirrors (a first pass, when phi's mirror is not current; the pass leaves it so).
+// mirrors (a first pass, when phi's mirror is not current).  Only colour passes
+// (color >= 0) rewrite the mirror; a norm-only pass (color -1) leaves it as it
+// was, so every caller that reads the mirror afterwards either refreshes it or
+// reads rows first.
 hipError_t launch_gsrb_fused(const Plan& p, void* phi, const void* f, double h2, int color, int rescolor,
                              double* partials, int grid, int block, hipStream_t s, bool rows = false);
 // *out = sum (sqrt of it if take_sqrt) of partials[0..n)

@@ -138,15 +138,18 @@ def test_vcycles_every_tile_shape(bt, shape):
 
 def test_vcycles_f32_follow_the_oracle(bt):
     """FP32 storage: 5 V-cycles against the oracle's 5 (FP64) on the same f: the field
-    within 1e-5, the first cycles' norms within 1e-5 (later ones reach the FP32
-    rounding floor), and the FP32 residual still falls 3x per cycle at first."""
+    within 1e-5; every norm within 1e-5 of the oracle's plus the FP32 floor (a norm from
+    FP32 state differs from the exact one by at most the norm of the residual of the
+    FP32 rounding error, which the cycles converge to; the last FP32 norm bounds it);
+    the FP32 residual still falls 3x per cycle at first."""
     P32 = _problem(bt, "uneven64", bt.F32)
     n32 = bt.Multigrid(P32["ba"], bt.F32).vcycles(P32["phi"], P32["f"], P32["h2"], 5)
     on = O.mg_vcycles(P32["ophi"], P32["of"], P32["h2"], 5)
     err = rel_err(gpu_global(P32["phi"]), P32["ophi"].to_global())
     say(f"mg f32 vs oracle: field rel err {err:.2e}, norms {n32} vs {on}")
     assert err <= 1e-5
-    assert all(abs(a - b) <= 1e-5 * b for a, b in zip(n32[:2], on[:2]))
+    assert all(abs(a - b) <= 1e-5 * b + n32[-1] for a, b in zip(n32, on)), (n32, on)
+    assert abs(n32[0] - on[0]) <= 1e-5 * on[0]
     assert all(b < 0.3 * a for a, b in zip(n32[:3], n32[1:4]))
 
 
