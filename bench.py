@@ -622,6 +622,7 @@ def main() -> int:
     ap.add_argument("--waves", type=int, default=None)
     ap.add_argument("--persist", type=int, default=None)
     ap.add_argument("--block", type=int, default=None)
+    ap.add_argument("--zsteps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and unfused measurements")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
@@ -656,11 +657,11 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    explicit = bool(args.zchunk or args.waves or args.persist is not None or args.block is not None)
+    explicit = bool(args.zchunk or args.waves or args.persist is not None or args.block is not None or args.zsteps)
     if explicit:
-        z, w, p, b = bt.get_tile_config()
+        z, w, p, b, zs = bt.get_tile_config()
         bt.set_tile_config(args.zchunk or z, args.waves or w, p if args.persist is None else args.persist,
-                           b if args.block is None else args.block)
+                           b if args.block is None else args.block, args.zsteps or zs)
     cfg_tile = bt.get_tile_config()
     log(f"kernel source sha256/16: {kernel_source_hash()}")
 

@@ -442,21 +442,25 @@ bl_status bl_device_copy(void* dst, const void* src, size_t bytes, hipStream_t s
  * form (each tile issues all of its loads before its updates), 2 for the
  * block form exchanging in-tile neighbours through LDS, 3 for that form with
  * the tile's halo loaded from memory straight into LDS (zchunk 2, 4 or 8 for
- * the block forms), 0 for the z march.  Default: zchunk 4, waves 4, persist 0, block 3.
- * Applies to MultiFabs created afterwards and to
+ * the block forms), 0 for the z march.  zsteps (1..64, form 3 only): z steps
+ * per tile; a workgroup takes its tile's planes zchunk at a time, bottom to
+ * top, and carries the two planes above a step into the next one, so the
+ * planes between steps are read once, not twice.  Default: zchunk 4, waves 4,
+ * persist 0, block 3, zsteps 1.  Applies to MultiFabs created afterwards and to
  * bl_batch objects at their next rebuild; results do not depend on it.  The
  * configuration is one setting of the whole process, shared by every thread:
  * set it before creating MultiFabs, not while other threads create them.
  */
-bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int32_t block);
-bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist, int32_t* block);
+bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int32_t block, int32_t zsteps);
+bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist, int32_t* block, int32_t* zsteps);
 
 /*
  * Autotuner of the tile shape (the paper tunes tile sizes per loop and
  * machine, Sec. 3.2 and Sec. 4.1; here the shape is picked by timing on the
  * device).  Times the fused heat step (bl_heat_advance's kernel) of u0/u1 on
  * `stream` for every candidate shape: block forms 3 and 2, zchunk 2, 4 and 8,
- * waves 2, 3 and 4 (persist as set by bl_set_tile_config), 2 warm-up steps
+ * waves 2, 3 and 4, zsteps 1, 2, 4 and 8 for form 3 (persist as set by
+ * bl_set_tile_config), 2 warm-up steps
  * then 2*trial_steps timed steps each (1 <= trial_steps <= 1000), and keeps
  * the fastest: MultiFabs of this (BoxArray, ncomp, nghost, dtype) created
  * afterwards use it, and u0 and u1 are switched to it now.  A later
@@ -465,14 +469,15 @@ bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist, 
  * The contents of u0 and u1 are overwritten (the trial steps advance them):
  * tune before loading initial data, or on scratch MultiFabs.  Synchronises
  * `stream`.  Optional outputs: the first max_results candidates' shapes
- * (configs[4*i .. 4*i+3] = zchunk, waves, persist, block) and their mean
- * milliseconds per step, their count in *nresults, the chosen shape in best[4].
+ * (configs[5*i .. 5*i+4] = zchunk, waves, persist, block, zsteps) and their
+ * mean milliseconds per step, their count in *nresults, the chosen shape in
+ * best[5].
  * Errors: ESHAPE/EDTYPE as bl_heat_step, ESHAPE if u0 is not on ba, EINVAL
  * for trial_steps or max_results out of range, EHIP.
  */
 bl_status bl_autotune(const bl_boxarray* ba, bl_multifab* u0, bl_multifab* u1, double c, int32_t trial_steps,
                       int32_t max_results, int32_t* nresults, int32_t* configs, float* ms_per_step,
-                      int32_t best[4], hipStream_t stream);
+                      int32_t best[5], hipStream_t stream);
 
 /* ------------------------------------------------------------------- batching */
 
@@ -551,10 +556,11 @@ bl_status bl_tile_list(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_
 /*
  * Tiles of the stencil forms with the halo in LDS (block form 3; empty under
  * other forms) for a MultiFab of this shape under the current tile
- * configuration: 10 int32 per tile {box, comp, q0, nq, nzs, z0, z1, zchunk,
- * vec, lanes}: the run of x vectors q0..q0+nq-1 of the box's plane (vector q
- * is row q / nvx, x vector q % nvx, nvx = x extent / vec) over planes z0..z1-1,
- * taken by nzs z blocks of zchunk planes; nzs*nq <= lanes.  Host metadata only.
+ * configuration: 11 int32 per tile {box, comp, q0, nq, nzs, z0, z1, zchunk,
+ * vec, lanes, zsteps}: the run of x vectors q0..q0+nq-1 of the box's plane
+ * (vector q is row q / nvx, x vector q % nvx, nvx = x extent / vec) over planes
+ * z0..z1-1, taken in z steps of nzs z blocks of zchunk planes each (at most
+ * zsteps steps); nzs*nq <= lanes.  Host metadata only.
  */
 bl_status bl_stencil_tiles(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_dtype dtype, int32_t* ntiles,
                            int32_t* tiles);

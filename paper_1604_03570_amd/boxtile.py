@@ -80,10 +80,10 @@ _SIGS = {
     "bl_residual_norm": [_vp, _vp, ctypes.c_double, _dp, _vp],
     "bl_reduce": [_vp, _i32, _i32, _dp, _vp],
     "bl_reduce_async": [_vp, _i32, _i32, _vp, _vp],
-    "bl_set_tile_config": [_i32, _i32, _i32, _i32],
+    "bl_set_tile_config": [_i32, _i32, _i32, _i32, _i32],
     "bl_autotune": [_vp, _vp, _vp, ctypes.c_double, _i32, _i32, _i32p, _i32p, ctypes.POINTER(ctypes.c_float), _i32p,
                     _vp],
-    "bl_get_tile_config": [_i32p, _i32p, _i32p, _i32p],
+    "bl_get_tile_config": [_i32p, _i32p, _i32p, _i32p, _i32p],
     "bl_batch_create": [_vpp],
     "bl_batch_add": [_vp, _vp, _vp, ctypes.c_double, _i32p],
     "bl_batch_remove": [_vp, _i32],
@@ -236,10 +236,11 @@ class BoxArray:
         return out
 
     def stencil_tiles(self, ncomp: int, nghost: int, dtype: int = F64) -> np.ndarray:
-        """Linear tiles of the stencil (block form 3): rows of {box, comp, q0, nq, nzs, z0, z1, zchunk, vec, lanes}."""
+        """Linear tiles of the stencil (block form 3): rows of
+        {box, comp, q0, nq, nzs, z0, z1, zchunk, vec, lanes, zsteps}."""
         n = ctypes.c_int32()
         _check(_L.bl_stencil_tiles(self._h, ncomp, nghost, dtype, ctypes.byref(n), None))
-        out = np.zeros((n.value, 10), dtype=np.int32)
+        out = np.zeros((n.value, 11), dtype=np.int32)
         _check(_L.bl_stencil_tiles(self._h, ncomp, nghost, dtype, ctypes.byref(n), out.ctypes.data_as(_i32p)))
         return out
 
@@ -324,28 +325,30 @@ def static_partition(ntiles: int, nworkers: int) -> list:
     return list(first)
 
 
-def set_tile_config(zchunk: int = 4, waves: int = 4, persist: int = 0, block: int = 3) -> None:
-    _check(_L.bl_set_tile_config(zchunk, waves, persist, block))
+def set_tile_config(zchunk: int = 4, waves: int = 4, persist: int = 0, block: int = 3, zsteps: int = 1) -> None:
+    _check(_L.bl_set_tile_config(zchunk, waves, persist, block, zsteps))
 
 
 def get_tile_config() -> tuple:
-    z, w, p, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(_L.bl_get_tile_config(ctypes.byref(z), ctypes.byref(w), ctypes.byref(p), ctypes.byref(b)))
-    return z.value, w.value, p.value, b.value
+    """(zchunk, waves, persist, block, zsteps)"""
+    v = [ctypes.c_int32() for _ in range(5)]
+    _check(_L.bl_get_tile_config(*(ctypes.byref(x) for x in v)))
+    return tuple(x.value for x in v)
 
 
 def autotune(ba: "BoxArray", u0: "MultiFab", u1: "MultiFab", c: float, trial_steps: int = 4, stream=None):
     """Time every candidate tile shape of the fused heat step on u0/u1 (their contents are
     overwritten) and keep the fastest for this (BoxArray, ncomp, nghost, dtype).
-    Returns (best (zchunk, waves, persist, block), [((zchunk, waves, persist, block), ms_per_step), ...])."""
+    Returns (best (zchunk, waves, persist, block, zsteps),
+    [((zchunk, waves, persist, block, zsteps), ms_per_step), ...])."""
     nmax = 64
-    cfgs = (ctypes.c_int32 * (4 * nmax))()
+    cfgs = (ctypes.c_int32 * (5 * nmax))()
     ms = (ctypes.c_float * nmax)()
     n = ctypes.c_int32()
-    best = (ctypes.c_int32 * 4)()
+    best = (ctypes.c_int32 * 5)()
     _check(_L.bl_autotune(ba.handle, u0.handle, u1.handle, float(c), int(trial_steps), nmax, ctypes.byref(n), cfgs, ms,
                           best, _stream(stream)))
-    table = [(tuple(cfgs[4 * i:4 * i + 4]), float(ms[i])) for i in range(n.value)]
+    table = [(tuple(cfgs[5 * i:5 * i + 5]), float(ms[i])) for i in range(n.value)]
     return tuple(best), table
 
 

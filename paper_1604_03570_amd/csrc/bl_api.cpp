@@ -72,7 +72,7 @@ bl_status upload_plan(Plan& p) {
 
 // Plans are shared by every MultiFab of one shape and tile configuration.
 static std::mutex g_plan_mu;
-static std::map<std::tuple<uint64_t, int, int, int, int, int, int>, std::weak_ptr<Plan>> g_plans;
+static std::map<std::tuple<uint64_t, int, int, int, int, int, int, int>, std::weak_ptr<Plan>> g_plans;
 static constexpr size_t kPlansKept = 64;
 static std::deque<std::shared_ptr<Plan>> g_plan_keep;
 
@@ -87,7 +87,7 @@ static TileConfig config_for(const bl_boxarray* ba, int ncomp, int ng, int dtype
 
 static bl_status get_plan_cfg(const bl_boxarray* ba, int ncomp, int ng, int dtype, const TileConfig& cfg,
                               bool to_device, std::shared_ptr<Plan>* out) {
-  auto key = std::make_tuple(ba->uid, ncomp, ng, dtype, cfg.zchunk, cfg.waves, cfg.block);
+  auto key = std::make_tuple(ba->uid, ncomp, ng, dtype, cfg.zchunk, cfg.waves, cfg.block, cfg.zsteps);
   std::lock_guard<std::mutex> lk(g_plan_mu);
   auto it = g_plans.find(key);
   std::shared_ptr<Plan> p;
@@ -446,7 +446,7 @@ static std::mutex g_vc_mu;
 
 static bl_status vc_tiles(Plan& p, VcArgs* a) {
   a->block = 64 * p.cfg.waves;
-  if (p.cfg.block == 3 && p.cfg.zchunk == 2 && !p.hlin.empty() &&
+  if (p.cfg.block == 3 && p.cfg.zchunk == 2 && p.cfg.zsteps == 1 && !p.hlin.empty() &&
       2 * vc_lds_half(p.dtype, p.vec, 2, p.yhmax, p.xhmax, a->block) <= kDmaLdsMax) {
     a->lin = p.dlin;
     a->nlin = (int)p.hlin.size();
@@ -461,6 +461,7 @@ static bl_status vc_tiles(Plan& p, VcArgs* a) {
     c.block = 3;
     c.zchunk = 2;
     c.persist = 0;
+    c.zsteps = 1;
     std::vector<DevLinTile> t;
     int yh = 1, xh = 1;
     build_lin_tiles(p, c, 0, 0, 0, t, &yh, &xh);
@@ -987,11 +988,13 @@ bl_status bl_device_copy(void* dst, const void* src, size_t bytes, hipStream_t s
   return BL_OK;
 }
 
-bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int32_t block) {
+bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int32_t block, int32_t zsteps) {
   clear_error();
   if (zchunk < 1 || zchunk > 16384 || waves < 1 || waves > kStencilMaxThreads / 64 || persist < 0 ||
-      persist > 64 || block < 0 || block > 3)
-    return fail(BL_EINVAL, "need 1 <= zchunk <= 16384, 1 <= waves <= %d, 0 <= persist <= 64, block in {0, 1, 2, 3}",
+      persist > 64 || block < 0 || block > 3 || zsteps < 1 || zsteps > 64)
+    return fail(BL_EINVAL,
+                "need 1 <= zchunk <= 16384, 1 <= waves <= %d, 0 <= persist <= 64, block in {0, 1, 2, 3}, "
+                "1 <= zsteps <= 64",
                 kStencilMaxThreads / 64);
   if (block && zchunk != 2 && zchunk != 4 && zchunk != 8)
     return fail(BL_EINVAL, "the block form needs zchunk 2, 4 or 8");
@@ -1000,6 +1003,7 @@ bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int
   c.waves = waves;
   c.persist = persist;
   c.block = block;
+  c.zsteps = zsteps;
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_tuned.clear();  // an explicit choice replaces earlier autotuned ones
   return BL_OK;
@@ -1007,7 +1011,7 @@ bl_status bl_set_tile_config(int32_t zchunk, int32_t waves, int32_t persist, int
 
 bl_status bl_autotune(const bl_boxarray* ba, bl_multifab* u0, bl_multifab* u1, double c, int32_t trial_steps,
                       int32_t max_results, int32_t* nresults, int32_t* configs, float* ms_per_step,
-                      int32_t best[4], hipStream_t stream) {
+                      int32_t best[5], hipStream_t stream) {
   clear_error();
   if (!ba) return fail(BL_EINVAL, "NULL BoxArray");
   bl_status st = check_heat(u0, u1);
@@ -1021,7 +1025,9 @@ bl_status bl_autotune(const bl_boxarray* ba, bl_multifab* u0, bl_multifab* u1, d
   std::vector<TileConfig> cands;
   for (int block : {3, 2})
     for (int z : {2, 4, 8})
-      for (int w : {2, 3, 4}) cands.push_back(TileConfig{z, w, persist, block});
+      for (int w : {2, 3, 4})
+        for (int zs : {1, 2, 4, 8})
+          if (block == 3 || zs == 1) cands.push_back(TileConfig{z, w, persist, block, zs});
   hipEvent_t e0 = nullptr, e1 = nullptr;
   BL_HIP(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1064,10 +1070,11 @@ bl_status bl_autotune(const bl_boxarray* ba, bl_multifab* u0, bl_multifab* u1, d
     ms /= (float)(2 * trial_steps);
     if (nres < max_results) {
       if (configs) {
-        configs[4 * nres + 0] = cfg.zchunk;
-        configs[4 * nres + 1] = cfg.waves;
-        configs[4 * nres + 2] = cfg.persist;
-        configs[4 * nres + 3] = cfg.block;
+        configs[5 * nres + 0] = cfg.zchunk;
+        configs[5 * nres + 1] = cfg.waves;
+        configs[5 * nres + 2] = cfg.persist;
+        configs[5 * nres + 3] = cfg.block;
+        configs[5 * nres + 4] = cfg.zsteps;
       }
       if (ms_per_step) ms_per_step[nres] = ms;
       ++nres;
@@ -1093,17 +1100,19 @@ bl_status bl_autotune(const bl_boxarray* ba, bl_multifab* u0, bl_multifab* u1, d
     best[1] = bc.waves;
     best[2] = bc.persist;
     best[3] = bc.block;
+    best[4] = bc.zsteps;
   }
   return BL_OK;
 }
 
-bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist, int32_t* block) {
+bl_status bl_get_tile_config(int32_t* zchunk, int32_t* waves, int32_t* persist, int32_t* block, int32_t* zsteps) {
   clear_error();
   const TileConfig& c = tile_config();
   if (zchunk) *zchunk = c.zchunk;
   if (waves) *waves = c.waves;
   if (persist) *persist = c.persist;
   if (block) *block = c.block;
+  if (zsteps) *zsteps = c.zsteps;
   return BL_OK;
 }
 
@@ -1189,7 +1198,7 @@ bl_status bl_stencil_tiles(const bl_boxarray* ba, int32_t ncomp, int32_t nghost,
   *ntiles = (int32_t)t.size();
   if (tiles)
     for (size_t i = 0; i < t.size(); ++i) {
-      int32_t* r = tiles + 10 * i;
+      int32_t* r = tiles + 11 * i;
       r[0] = t[i].box;
       r[1] = t[i].comp;
       r[2] = t[i].q0;
@@ -1200,6 +1209,7 @@ bl_status bl_stencil_tiles(const bl_boxarray* ba, int32_t ncomp, int32_t nghost,
       r[7] = plan->cfg.zchunk;
       r[8] = plan->vec;
       r[9] = 64 * plan->cfg.waves;
+      r[10] = plan->cfg.zsteps;
     }
   return BL_OK;
 }

@@ -675,20 +675,23 @@ __device__ __forceinline__ void stage_halo(const TileLds<T, V>& S, const DevLinT
   }
 }
 
-// The lane's planes zb0-1 .. zb0+ZB (clamped to zb1; z-face planes through the
-// face records when FUSED) into registers.
-template <typename T, int V, bool FUSED, int ZB>
+// The lane's planes zb0-1+K0 .. zb0+ZB (P[K0] .. P[ZB+1]; clamped to zb1; z-face
+// planes through the face records when FUSED) into registers.  K0 = 2 loads
+// what a z step of a tile needs beyond the two planes carried from the step
+// below it.
+template <typename T, int V, bool FUSED, int ZB, int K0 = 0>
 __device__ __forceinline__ void load_planes(Vec<T, V> (&P)[ZB + 2], const LinLane& L, const DevLinTile& tl,
                                             const DevBox& B, const DevFaceRec* __restrict__ recs,
                                             const BL_GLOBAL T* __restrict__ u, int64_t cb) {
   const int n = tl.comp, sz = B.sz;
   int64_t zlo = cb - sz, zhi = cb + (int64_t)B.ez * sz;
   if (FUSED) {
-    if (tl.z0 == 0) zlo = tile_face_index(recs, tl.frec[4], B.face_start[4], B.face_count[4], L.x0, L.y, n, zlo);
+    if (K0 == 0 && tl.z0 == 0)
+      zlo = tile_face_index(recs, tl.frec[4], B.face_start[4], B.face_count[4], L.x0, L.y, n, zlo);
     if (tl.z1 == B.ez) zhi = tile_face_index(recs, tl.frec[5], B.face_start[5], B.face_count[5], L.x0, L.y, n, zhi);
   }
 #pragma unroll
-  for (int k = 0; k < ZB + 2; ++k) {
+  for (int k = K0; k < ZB + 2; ++k) {
     const int z = L.zb0 - 1 + k < L.zb1 ? L.zb0 - 1 + k : L.zb1;
     int64_t a = cb + (int64_t)z * sz;
     if (FUSED) a = z < 0 ? zlo : (z >= B.ez ? zhi : a);
@@ -788,8 +791,25 @@ __device__ __forceinline__ void store_mirror(const TileLds<T, V>& S, const DevLi
   }
 }
 
-// Heat step, block form with the halo in LDS: one wait for all loads, the
-// lanes' planes into LDS, one barrier, the updates, full-vector stores.
+// z steps of a linear tile: a tile spans up to zsteps * ZB * nzs planes and is
+// worked on in steps of ZB * nzs planes (nzs z blocks side by side, each ZB
+// planes), bottom to top.  Step j is the tile cut to its planes.
+template <int ZB>
+__device__ __forceinline__ DevLinTile tile_zstep(const DevLinTile& tl, int j) {
+  DevLinTile ts = tl;
+  const int span = ZB * tl.nzs;
+  ts.z0 = tl.z0 + j * span;
+  ts.z1 = ts.z0 + span < tl.z1 ? ts.z0 + span : tl.z1;
+  const int nb = (ts.z1 - ts.z0 + ZB - 1) / ZB;
+  ts.nzs = nb < tl.nzs ? nb : tl.nzs;
+  return ts;
+}
+
+// Heat step, block form with the halo in LDS: per z step of the tile, one wait
+// for all loads, the lanes' planes into LDS, one barrier, the updates,
+// full-vector stores.  With one z block per step (planes of a workgroup's size
+// or more), the two planes above a step are carried in registers into the next
+// step, which loads only its ZB new planes.
 template <typename T, int V, bool FUSED, int ZB>
 __global__ void __launch_bounds__(kStencilMaxThreads)
     __attribute__((amdgpu_waves_per_eu(ZB == 8 ? 4 : 6)))
@@ -810,35 +830,46 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
     BL_GLOBAL T* __restrict__ w = as_global(static_cast<T*>(swap ? M.a : M.b));
     const T c = (T)M.c;
     const int nvx = B.nvx;
-    const LinLane L = lin_lane<V, ZB>(tl, nvx);
     const int64_t comp0 = B.off + (int64_t)tl.comp * B.sc;
-    const int64_t cb = comp0 + (int64_t)L.q * V;
+    const int span = ZB * tl.nzs, nsteps = (tl.z1 - tl.z0 + span - 1) / span;
+    const bool carry = tl.nzs == 1;
 
     VT P[ZB + 2];
-    load_planes<T, V, FUSED, ZB>(P, L, tl, B, recs, u, cb);
-    stage_halo<T, V, FUSED, ZB>(S, tl, B, recs, u, comp0);
-#pragma unroll
-    for (int k = 0; k < ZB; ++k) S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
-    __syncthreads();
-    BL_GLOBAL T* wp = w + cb;
-#pragma unroll
-    for (int k = 0; k < ZB; ++k) {
-      const Nbr<T, V> N = tile_neighbours<T, V, ZB, false>(S, L, tl, nvx, k, P[k + 1]);
-      VT o;
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        const T xm = e == 0 ? N.left : P[k + 1].v[e - 1];
-        const T xp = e == V - 1 ? N.right : P[k + 1].v[e + 1];
-        o.v[e] = heat_cell(P[k + 1].v[e], xm, xp, N.ym.v[e], N.yp.v[e], P[k].v[e], P[k + 2].v[e], c);
+    for (int j = 0; j < nsteps; ++j) {
+      const DevLinTile ts = tile_zstep<ZB>(tl, j);
+      const LinLane L = lin_lane<V, ZB>(ts, nvx);
+      const int64_t cb = comp0 + (int64_t)L.q * V;
+      if (j > 0 && carry) {
+        P[0] = P[ZB];
+        P[1] = P[ZB + 1];
+        load_planes<T, V, FUSED, ZB, 2>(P, L, ts, B, recs, u, cb);
+      } else {
+        load_planes<T, V, FUSED, ZB>(P, L, ts, B, recs, u, cb);
       }
-      const int z = L.zb0 + k;
-      if (z < L.zb1 && L.active) {
-        stv_nt<T, V>(wp + (int64_t)z * B.sz, o);
-        if (FUSED) stage_edges<T, V, ZB>(S, L, tl, nvx, k, o);
+      stage_halo<T, V, FUSED, ZB>(S, ts, B, recs, u, comp0);
+#pragma unroll
+      for (int k = 0; k < ZB; ++k) S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
+      __syncthreads();
+      BL_GLOBAL T* wp = w + cb;
+#pragma unroll
+      for (int k = 0; k < ZB; ++k) {
+        const Nbr<T, V> N = tile_neighbours<T, V, ZB, false>(S, L, ts, nvx, k, P[k + 1]);
+        VT o;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const T xm = e == 0 ? N.left : P[k + 1].v[e - 1];
+          const T xp = e == V - 1 ? N.right : P[k + 1].v[e + 1];
+          o.v[e] = heat_cell(P[k + 1].v[e], xm, xp, N.ym.v[e], N.yp.v[e], P[k].v[e], P[k + 2].v[e], c);
+        }
+        const int z = L.zb0 + k;
+        if (z < L.zb1 && L.active) {
+          stv_nt<T, V>(wp + (int64_t)z * B.sz, o);
+          if (FUSED) stage_edges<T, V, ZB>(S, L, ts, nvx, k, o);
+        }
       }
+      if (FUSED) store_mirror<T, V, ZB>(S, ts, B, w);
+      if (persist || j + 1 < nsteps) __syncthreads();  // the next step or tile reuses the LDS buffers
     }
-    if (FUSED) store_mirror<T, V, ZB>(S, tl, B, w);
-    if (persist) __syncthreads();  // the next tile reuses the LDS buffers
   }
 }
 
@@ -1316,60 +1347,75 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
     const DevLinTile tl = ldc(tiles + t);
     const DevBox B = ldc(boxes + tl.box);
     const int nvx = B.nvx;
-    const LinLane L = lin_lane<V, ZB>(tl, nvx);
     const int64_t comp0 = B.off + (int64_t)tl.comp * B.sc;
-    const int64_t cb = comp0 + (int64_t)L.q * V;
-    const int par0 = (B.glo[0] + L.x0 + B.glo[1] + L.y + B.glo[2]) & 1;  // parity of (x0, y, z = 0)
+    const int span = ZB * tl.nzs, nsteps = (tl.z1 - tl.z0 + span - 1) / span;
+    const bool carry = tl.nzs == 1;
 
+    // z steps as in k_heat_dma.  The two planes carried into a step hold the
+    // values from before this pass; the one below the step is also the pass's
+    // output there, but a cell of the colour this pass updates has z
+    // neighbours of the other colour, which the pass leaves unchanged.
     VT P[ZB + 2], F[ZB];
-    load_planes<T, V, true, ZB>(P, L, tl, B, recs, phi, cb);
+    for (int j = 0; j < nsteps; ++j) {
+      const DevLinTile ts = tile_zstep<ZB>(tl, j);
+      const LinLane L = lin_lane<V, ZB>(ts, nvx);
+      const int64_t cb = comp0 + (int64_t)L.q * V;
+      const int par0 = (B.glo[0] + L.x0 + B.glo[1] + L.y + B.glo[2]) & 1;  // parity of (x0, y, z = 0)
+      if (j > 0 && carry) {
+        P[0] = P[ZB];
+        P[1] = P[ZB + 1];
+        load_planes<T, V, true, ZB, 2>(P, L, ts, B, recs, phi, cb);
+      } else {
+        load_planes<T, V, true, ZB>(P, L, ts, B, recs, phi, cb);
+      }
 #pragma unroll
-    for (int k = 0; k < ZB; ++k) {
-      const int z = L.zb0 + k < L.zb1 ? L.zb0 + k : L.zb1 - 1;
-      F[k] = ldv<T, V>(fq + cb + (int64_t)z * B.sz);
-    }
-    stage_halo<T, V, true, ZB>(S, tl, B, recs, phi, comp0);
+      for (int k = 0; k < ZB; ++k) {
+        const int z = L.zb0 + k < L.zb1 ? L.zb0 + k : L.zb1 - 1;
+        F[k] = ldv<T, V>(fq + cb + (int64_t)z * B.sz);
+      }
+      stage_halo<T, V, true, ZB>(S, ts, B, recs, phi, comp0);
 #pragma unroll
-    for (int k = 0; k < ZB; ++k) S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
-    __syncthreads();
-    BL_GLOBAL T* wp = phi + cb;
+      for (int k = 0; k < ZB; ++k) S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
+      __syncthreads();
+      BL_GLOBAL T* wp = phi + cb;
 #pragma unroll
-    for (int k = 0; k < ZB; ++k) {
-      const Nbr<T, V> N = tile_neighbours<T, V, ZB, true>(S, L, tl, nvx, k, P[k + 1]);
-      const int z = L.zb0 + k;
-      const bool valid = z < L.zb1 && L.active;
-      VT o = P[k + 1];
-      if (color >= 0) {
+      for (int k = 0; k < ZB; ++k) {
+        const Nbr<T, V> N = tile_neighbours<T, V, ZB, true>(S, L, ts, nvx, k, P[k + 1]);
+        const int z = L.zb0 + k;
+        const bool valid = z < L.zb1 && L.active;
+        VT o = P[k + 1];
+        if (color >= 0) {
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-          const T xm = e == 0 ? N.left : P[k + 1].v[e - 1];
-          const T xp = e == V - 1 ? N.right : P[k + 1].v[e + 1];
-          const T nv = gsrb_cell(xm, xp, N.ym.v[e], N.yp.v[e], P[k].v[e], P[k + 2].v[e], F[k].v[e], h2, inv6);
-          if (((par0 + z + e) & 1) == color) o.v[e] = nv;
+          for (int e = 0; e < V; ++e) {
+            const T xm = e == 0 ? N.left : P[k + 1].v[e - 1];
+            const T xp = e == V - 1 ? N.right : P[k + 1].v[e + 1];
+            const T nv = gsrb_cell(xm, xp, N.ym.v[e], N.yp.v[e], P[k].v[e], P[k + 2].v[e], F[k].v[e], h2, inv6);
+            if (((par0 + z + e) & 1) == color) o.v[e] = nv;
+          }
+        }
+        if (RES && valid) {
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            if (rescolor != 2 && ((par0 + z + e) & 1) != rescolor) continue;
+            const double xm = e == 0 ? (double)N.left : (double)P[k + 1].v[e - 1];
+            const double xp = e == V - 1 ? (double)N.right : (double)P[k + 1].v[e + 1];
+            const double sv = ((xm + xp) + ((double)N.ym.v[e] + (double)N.yp.v[e])) +
+                              ((double)P[k].v[e] + (double)P[k + 2].v[e]);
+            // the cell's own value: after its update in the black pass, before it otherwise
+            const double cv = color == 1 ? (double)o.v[e] : (double)P[k + 1].v[e];
+            const double r = (double)F[k].v[e] + (sv - 6.0 * cv) * inv_h2d;
+            acc += r * r;
+          }
+        }
+        if (color < 0) continue;
+        if (valid) {
+          stv_nt<T, V>(wp + (int64_t)z * B.sz, o);
+          stage_edges<T, V, ZB>(S, L, ts, nvx, k, o);
         }
       }
-      if (RES && valid) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          if (rescolor != 2 && ((par0 + z + e) & 1) != rescolor) continue;
-          const double xm = e == 0 ? (double)N.left : (double)P[k + 1].v[e - 1];
-          const double xp = e == V - 1 ? (double)N.right : (double)P[k + 1].v[e + 1];
-          const double sv = ((xm + xp) + ((double)N.ym.v[e] + (double)N.yp.v[e])) +
-                            ((double)P[k].v[e] + (double)P[k + 2].v[e]);
-          // the cell's own value: after its update in the black pass, before it otherwise
-          const double cv = color == 1 ? (double)o.v[e] : (double)P[k + 1].v[e];
-          const double r = (double)F[k].v[e] + (sv - 6.0 * cv) * inv_h2d;
-          acc += r * r;
-        }
-      }
-      if (color < 0) continue;
-      if (valid) {
-        stv_nt<T, V>(wp + (int64_t)z * B.sz, o);
-        stage_edges<T, V, ZB>(S, L, tl, nvx, k, o);
-      }
+      if (color >= 0) store_mirror<T, V, ZB>(S, ts, B, phi);
+      if (persist || j + 1 < nsteps) __syncthreads();  // the next step or tile reuses the LDS buffers
     }
-    if (color >= 0) store_mirror<T, V, ZB>(S, tl, B, phi);
-    if (persist) __syncthreads();  // the next tile reuses the LDS buffers
   }
   if (RES) {
     const double r = block_reduce(acc, R_SUM);

@@ -658,7 +658,7 @@ void build_lin_tiles(const Plan& p, const TileConfig& cfg, int member, int box_b
       nq = P;
       nzs = std::max(1, std::min(lanes / P, (B.ez + zb - 1) / zb));
     }
-    const int zlen = zb * nzs;
+    const int zlen = zb * nzs * std::max(1, cfg.zsteps);
     // z cuts: multiples of zlen and every z boundary of the x- and y-face records
     zc.clear();
     for (int z = 0; z < B.ez; z += zlen) zc.push_back(z);

@@ -121,8 +121,8 @@ def test_vcycles_bit_exact_f64(bt, layout):
     assert norms[1] < 0.3 * norms[0]
 
 
-@pytest.mark.parametrize("shape", [(4, 4, 0, 3), (2, 2, 0, 3), (4, 4, 0, 2), (4, 4, 0, 0)],
-                         ids=["z4_w4_b3", "z2_w2_b3", "z4_w4_b2", "march"])
+@pytest.mark.parametrize("shape", [(4, 4, 0, 3), (2, 2, 0, 3), (4, 4, 0, 2), (4, 4, 0, 0), (4, 4, 0, 3, 4)],
+                         ids=["z4_w4_b3", "z2_w2_b3", "z4_w4_b2", "march", "z4_w4_b3_s4"])
 def test_vcycles_every_tile_shape(bt, shape):
     """The fused smoother (form 3) and the fill-then-pass smoother give the same bits."""
     bt.set_tile_config(*shape)

@@ -332,15 +332,17 @@ def test_batch_alone_equals_in_the_mix(bt):
 TILE_CONFIGS = [(1, 4, 0, 0), (2, 2, 0, 0), (3, 4, 0, 0), (8, 1, 0, 0), (1024, 4, 0, 0), (5, 3, 0, 0), (4, 4, 2, 0),
                 (1024, 2, 3, 0), (8, 4, 1, 0), (16, 1, 0, 0), (2, 4, 0, 1), (4, 4, 0, 1), (8, 2, 0, 1), (8, 4, 2, 1),
                 (2, 4, 0, 2), (4, 4, 0, 2), (8, 3, 0, 2), (4, 4, 2, 2), (4, 1, 0, 2),
-                (2, 4, 0, 3), (4, 4, 0, 3), (8, 3, 0, 3), (4, 4, 2, 3), (4, 1, 0, 3), (8, 2, 0, 3)]
+                (2, 4, 0, 3), (4, 4, 0, 3), (8, 3, 0, 3), (4, 4, 2, 3), (4, 1, 0, 3), (8, 2, 0, 3),
+                # z steps of form 3: a workgroup carries two planes from one step into the next
+                (4, 4, 0, 3, 2), (4, 4, 0, 3, 4), (2, 4, 0, 3, 8), (8, 3, 0, 3, 2), (4, 4, 2, 3, 4), (4, 1, 0, 3, 3)]
 
 
 @pytest.mark.parametrize("cfg", TILE_CONFIGS)
 @pytest.mark.parametrize("layout", ["uneven", "odd_noncovering"])
 def test_every_tile_configuration_bit_exact(bt, cfg, layout):
     """Every stencil kernel variant (z march, block forms of 2/4/8 planes with
-    registers, LDS neighbours or LDS halos, persistent grid) gives the oracle's
-    FP64 result, fused and per box, on ragged tiles."""
+    registers, LDS neighbours or LDS halos, z steps with carried planes, persistent
+    grid) gives the oracle's FP64 result, fused and per box, on ragged tiles."""
     rng = np.random.default_rng(31)
     if layout == "uneven":
         dom, periodic = I.domain_box((64, 48, 40)), (1, 1, 1)
@@ -391,7 +393,7 @@ def test_autotune_picks_the_fastest_and_stays_bit_exact(bt):
         s1.set_val(1.0)
         best, table = bt.autotune(ba, s0, s1, c, trial_steps=2)
         say(f"autotune best {best}, {len(table)} candidates")
-        assert len(table) == 18
+        assert len(table) == 45  # form 3: 3 zchunk x 3 waves x 4 zsteps; form 2: 3 x 3
         assert best == min(table, key=lambda t: t[1])[0]
         assert all(ms > 0 for _, ms in table)
         # the scratch pair, and a fresh pair of the same shape, now run the tuned shape
@@ -406,7 +408,8 @@ def test_autotune_picks_the_fastest_and_stays_bit_exact(bt):
 
 
 # ----------------------------------------------------------------------------- fused GSRB
-GSRB_CONFIGS = [(4, 4, 0, 3), (2, 4, 0, 3), (8, 2, 0, 3), (4, 3, 0, 3), (4, 4, 2, 3), (4, 4, 0, 2)]
+GSRB_CONFIGS = [(4, 4, 0, 3), (2, 4, 0, 3), (8, 2, 0, 3), (4, 3, 0, 3), (4, 4, 2, 3), (4, 4, 0, 2),
+                (4, 4, 0, 3, 4), (2, 4, 0, 3, 8), (8, 2, 0, 3, 2), (4, 4, 2, 3, 3)]
 
 
 @pytest.mark.parametrize("cfg", GSRB_CONFIGS)

@@ -89,16 +89,17 @@ def test_varcoef_equals_the_oracle(bt, layout, dtype_name):
     _check(bt, gpu_global(res), ref, dtype)
 
 
-TILE_SHAPES = [(2, 4, 0, 3), (8, 4, 0, 3), (4, 1, 0, 3), (4, 2, 0, 3), (8, 3, 0, 3), (4, 4, 0, 2), (0, 2, 0, 0)]
+TILE_SHAPES = [(2, 4, 0, 3, 1), (8, 4, 0, 3, 1), (4, 1, 0, 3, 1), (4, 2, 0, 3, 1), (8, 3, 0, 3, 1), (4, 4, 0, 2, 1),
+               (0, 2, 0, 0, 1), (2, 4, 0, 3, 4), (4, 4, 0, 3, 2)]
 
 
-@pytest.mark.parametrize("shape", TILE_SHAPES, ids=lambda s: "z%d_w%d_b%d" % (s[0], s[1], s[3]))
+@pytest.mark.parametrize("shape", TILE_SHAPES, ids=lambda s: "z%d_w%d_b%d_s%d" % (s[0], s[1], s[3], s[4]))
 def test_varcoef_every_tile_shape(bt, shape):
-    """The kernel runs on the plan's own tiles where they have 2 planes per z block, else
-    on tiles it builds; every plan shape gives the oracle's bits."""
-    zchunk, waves, persist, block = shape
-    say(f"varcoef tile shape zchunk={zchunk} waves={waves} block={block}")
-    bt.set_tile_config(zchunk if block else 4, waves, persist, block)
+    """The kernel runs on the plan's own tiles where they have 2 planes per z block and
+    one z step, else on tiles it builds; every plan shape gives the oracle's bits."""
+    zchunk, waves, persist, block, zsteps = shape
+    say(f"varcoef tile shape zchunk={zchunk} waves={waves} block={block} zsteps={zsteps}")
+    bt.set_tile_config(zchunk if block else 4, waves, persist, block, zsteps)
     try:
         P = _problem(bt, "uneven_periodic", bt.F64, 1, seed=5)
         res = bt.heat_varcoef_advance(P["a"], P["b"], P["beta"], 6, P["dt"], P["dx"])

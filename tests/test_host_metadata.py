@@ -172,7 +172,7 @@ def test_tile_list_covers_every_cell_once(dtype, boxes_kind):
 
 @pytest.mark.parametrize("dtype", [0, 1])
 @pytest.mark.parametrize("boxes_kind", ["regular", "uneven", "odd", "cells"])
-@pytest.mark.parametrize("shape", [(4, 4), (2, 4), (8, 2), (4, 3)])
+@pytest.mark.parametrize("shape", [(4, 4, 1), (2, 4, 2), (8, 2, 1), (4, 3, 4), (4, 4, 8)])
 def test_stencil_tiles_cover_every_cell_once(dtype, boxes_kind, shape):
     """Linear tiles (runs of consecutive vectors of a plane, whole planes stacked in z
     blocks for small planes) cover every valid cell of every component exactly once,
@@ -190,7 +190,7 @@ def test_stencil_tiles_cover_every_cell_once(dtype, boxes_kind, shape):
         boxes = I.random_chop(dom, 1, 2, 1, seed=7)
     ncomp = 2
     saved = bt.get_tile_config()
-    bt.set_tile_config(shape[0], shape[1], 0, 3)
+    bt.set_tile_config(shape[0], shape[1], 0, 3, shape[2])
     try:
         ba = bt.BoxArray.from_boxes(boxes, dom)
         tiles = ba.stencil_tiles(ncomp, 1, dtype)
@@ -206,9 +206,9 @@ def test_stencil_tiles_cover_every_cell_once(dtype, boxes_kind, shape):
             cuts.add(int(r[5] - bx[2]))
             cuts.add(int(r[8] - bx[2] + 1))
         for t in tiles[tiles[:, 0] == b]:
-            comp, q0, nq, nzs, z0, z1, zc, vec, lanes = t[1:]
+            comp, q0, nq, nzs, z0, z1, zc, vec, lanes, zsteps = t[1:]
             assert vec in (1, 2, 4) and ex % vec == 0 and nzs * nq <= lanes == 64 * shape[1]
-            assert z1 - z0 <= nzs * zc and nzs == -(-(z1 - z0) // zc)
+            assert zsteps == shape[2] and z1 - z0 <= nzs * zc * zsteps and nzs <= -(-(z1 - z0) // zc)
             assert not any(z0 < c < z1 for c in cuts)
             cover[comp, z0:z1, q0 * vec:(q0 + nq) * vec] += 1
         assert cover.min() == 1 and cover.max() == 1
