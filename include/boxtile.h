@@ -423,6 +423,24 @@ bl_status bl_reduce(const bl_multifab* mf, int32_t comp, bl_reduce_op op, double
 bl_status bl_reduce_async(const bl_multifab* mf, int32_t comp, bl_reduce_op op, double* out_dev,
                           hipStream_t stream);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): bl_reduce_async with the
+ * same kernels and the same result, bit for bit, but its partial results (one
+ * double per reduction chunk of about 32K values of the component) go to a
+ * fixed device array of the library's, 65536 doubles (512 KiB) per GPU, held
+ * from the first call on that GPU until the process ends.  It calls no
+ * hipMalloc, hipFree or allocating library routine.  BL_EINVAL if the
+ * MultiFab has more chunks than that (about 2^31 valid cells per component),
+ * or for a NULL argument, a component out of range or an unknown op.
+ * Asynchronous on `stream`; out_dev (one double, device memory) is written by
+ * the stream.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, or two threads) race and must be ordered
+ * by the caller.
+ */
+bl_status bl_reduce_async_noalloc(const bl_multifab* mf, int32_t comp, bl_reduce_op op, double* out_dev,
+                                  hipStream_t stream);
+
 /* ------------------------------------------------------------ device copy */
 
 /*

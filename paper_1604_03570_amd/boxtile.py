@@ -80,6 +80,7 @@ _SIGS = {
     "bl_residual_norm": [_vp, _vp, ctypes.c_double, _dp, _vp],
     "bl_reduce": [_vp, _i32, _i32, _dp, _vp],
     "bl_reduce_async": [_vp, _i32, _i32, _vp, _vp],
+    "bl_reduce_async_noalloc": [_vp, _i32, _i32, _vp, _vp],
     "bl_set_tile_config": [_i32, _i32, _i32, _i32, _i32],
     "bl_autotune": [_vp, _vp, _vp, ctypes.c_double, _i32, _i32, _i32p, _i32p, ctypes.POINTER(ctypes.c_float), _i32p,
                     _vp],
@@ -448,6 +449,13 @@ class MultiFab:
     def reduce_async(self, comp: int, op: str, out: torch.Tensor, stream=None) -> None:
         assert out.dtype == torch.float64 and out.is_cuda
         _check(_L.bl_reduce_async(self._h, comp, REDUCE_OPS[op], ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+
+    def reduce_async_noalloc(self, comp: int, op: str, out: torch.Tensor, stream=None) -> None:
+        """reduce_async whose partial results live in the library's fixed device array
+        (no allocation; calls that overlap on one GPU race)."""
+        assert out.dtype == torch.float64 and out.is_cuda
+        _check(_L.bl_reduce_async_noalloc(self._h, comp, REDUCE_OPS[op], ctypes.c_void_p(out.data_ptr()),
+                                          _stream(stream)))
 
     def sum(self, comp: int = 0) -> float:
         return self.reduce(comp, "sum")

@@ -616,6 +616,23 @@ bl_status bl_reduce_async(const bl_multifab* cmf, int32_t comp, bl_reduce_op op,
   return BL_OK;
 }
 
+bl_status bl_reduce_async_noalloc(const bl_multifab* mf, int32_t comp, bl_reduce_op op, double* out_dev,
+                                  hipStream_t stream) {
+  clear_error();
+  if (!mf || !out_dev) return fail(BL_EINVAL, "NULL argument");
+  const Plan& p = *mf->plan;
+  if (comp < 0 || comp >= p.ncomp) return fail(BL_EINVAL, "component %d out of range", comp);
+  if ((int)op < 0 || (int)op > 5) return fail(BL_EINVAL, "unknown reduction %d", (int)op);
+  if (!p.dred || p.hred.empty()) return fail(BL_EINVAL, "the MultiFab has no reduction chunks");
+  if (p.hred.size() > (size_t)kNoAllocPartials)
+    return fail(BL_EINVAL,
+                "the MultiFab has %zu reduction chunks (about 32K values each); the no-allocation form holds at "
+                "most %d partial results",
+                p.hred.size(), kNoAllocPartials);
+  BL_HIP(launch_reduce_noalloc(p, mf->data, comp, (int)op, out_dev, stream));
+  return BL_OK;
+}
+
 bl_status bl_reduce(const bl_multifab* cmf, int32_t comp, bl_reduce_op op, double* out_host, hipStream_t stream) {
   clear_error();
   bl_multifab* mf = const_cast<bl_multifab*>(cmf);

@@ -18,6 +18,7 @@
 
 #include <cmath>
 #include <limits>
+#include <mutex>
 
 #include "bl_internal.h"
 #include "bl_launch.h"
@@ -1934,6 +1935,42 @@ hipError_t launch_reduce(const Plan& p, const void* data, int comp, int op, doub
   }
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, s, partials, (int)nt, op, op == R_NORM2 ? 1 : 0, out);
   return hipGetLastError();
+}
+
+// ------------------------------------------------- reduction without allocation
+// The partial results of one reduction (one double per reduction chunk) in a
+// fixed device array instead of memory the library allocates.  Each GPU the
+// library runs on holds its own copy at its own address until the process ends;
+// host code uses only the address hipGetSymbolAddress returns for the current
+// device, never the array's name.  Nothing in it must start at zero: every
+// chunk writes its own slot before the final pass reads it.  Calls that overlap
+// on one GPU share the array and race.
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices];
+
+hipError_t noalloc_partials(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_reduce_noalloc(const Plan& p, const void* data, int comp, int op, double* out, hipStream_t s) {
+  double* partials = nullptr;
+  hipError_t e = noalloc_partials(&partials);
+  if (e != hipSuccess) return e;
+  return launch_reduce(p, data, comp, op, partials, out, 256, s);
 }
 
 hipError_t launch_gsrb(const Plan& p, void* phi, const void* f, double h2, int color, int block, hipStream_t s) {

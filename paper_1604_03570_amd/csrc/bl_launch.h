@@ -53,6 +53,13 @@ hipError_t launch_copy_fab(const Plan& p, void* data, void* dense, int box, int 
 hipError_t launch_reduce(const Plan& p, const void* data, int comp, int op, double* partials, double* out, int block,
                          hipStream_t s);
 
+// launch_reduce with the partials in the library's fixed device array of
+// kNoAllocPartials doubles (no allocation): needs p.dred and at most that many
+// chunks.  Calls that overlap on one GPU race on the array.
+constexpr int kNoAllocPartials = 65536;
+constexpr int kMaxDevices = 64;
+hipError_t launch_reduce_noalloc(const Plan& p, const void* data, int comp, int op, double* out, hipStream_t s);
+
 hipError_t launch_gsrb(const Plan& p, void* phi, const void* f, double h2, int color, int block, hipStream_t s);
 
 // ||f + L_h phi||_2 in FP64 into *out (device); reads phi's ghosts (fill first).
