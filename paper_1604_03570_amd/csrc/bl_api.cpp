@@ -440,13 +440,15 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
 
 // Tiles for the variable-coefficient kernel: 2 planes per z block (measured on
 // the 512^3 uneven level: 3.53 ms per step against 4.06 for 4 planes; twice the
-// stencil's LDS leaves room for fewer workgroups), the plan's own linear tiles
-// when they are of that shape, else tiles built once per plan.
+// stencil's LDS leaves room for fewer workgroups) in kVcZsteps z steps, the
+// plan's own linear tiles when they are of that shape, else tiles built once per
+// plan.
+static constexpr int kVcZsteps = 8;
 static std::mutex g_vc_mu;
 
 static bl_status vc_tiles(Plan& p, VcArgs* a) {
   a->block = 64 * p.cfg.waves;
-  if (p.cfg.block == 3 && p.cfg.zchunk == 2 && p.cfg.zsteps == 1 && !p.hlin.empty() &&
+  if (p.cfg.block == 3 && p.cfg.zchunk == 2 && p.cfg.zsteps == kVcZsteps && !p.hlin.empty() &&
       2 * vc_lds_half(p.dtype, p.vec, 2, p.yhmax, p.xhmax, a->block) <= kDmaLdsMax) {
     a->lin = p.dlin;
     a->nlin = (int)p.hlin.size();
@@ -461,7 +463,7 @@ static bl_status vc_tiles(Plan& p, VcArgs* a) {
     c.block = 3;
     c.zchunk = 2;
     c.persist = 0;
-    c.zsteps = 1;
+    c.zsteps = kVcZsteps;
     std::vector<DevLinTile> t;
     int yh = 1, xh = 1;
     build_lin_tiles(p, c, 0, 0, 0, t, &yh, &xh);

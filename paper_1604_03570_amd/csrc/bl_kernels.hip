@@ -911,53 +911,68 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
     const DevLinTile tl = ldc(tiles + t);
     const DevBox B = ldc(boxes + tl.box);
     const int nvx = B.nvx;
-    const LinLane L = lin_lane<V, ZB>(tl, nvx);
     const int64_t comp0 = B.off + (int64_t)tl.comp * B.sc;
-    const int64_t cb = comp0 + (int64_t)L.q * V;
+    const int span = ZB * tl.nzs, nsteps = (tl.z1 - tl.z0 + span - 1) / span;
+    const bool carry = tl.nzs == 1;
 
     VT P[ZB + 2], Q[ZB + 2];  // u, beta
-    load_planes<T, V, FUSED, ZB>(P, L, tl, B, recs, u, cb);
-    load_planes<T, V, FUSED, ZB>(Q, L, tl, B, recs, bt, cb);
-    stage_halo<T, V, FUSED, ZB>(S, tl, B, recs, u, comp0);
-    stage_halo<T, V, FUSED, ZB>(Sb, tl, B, recs, bt, comp0);
-#pragma unroll
-    for (int k = 0; k < ZB; ++k) {
-      S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
-      Sb.sh[k * Sb.nthr + threadIdx.x] = Q[k + 1];
-    }
-    __syncthreads();
-    BL_GLOBAL T* wp = w + cb;
-    T fz[V];  // flux through the lower z face of the current plane
-#pragma unroll
-    for (int e = 0; e < V; ++e) fz[e] = face_flux(P[0].v[e], P[1].v[e], Q[0].v[e], Q[1].v[e], inv_dx);
-#pragma unroll
-    for (int k = 0; k < ZB; ++k) {
-      const Nbr<T, V> N = tile_neighbours<T, V, ZB, false>(S, L, tl, nvx, k, P[k + 1]);
-      const Nbr<T, V> NB = tile_neighbours<T, V, ZB, false>(Sb, L, tl, nvx, k, Q[k + 1]);
-      const VT& c = P[k + 1];
-      const VT& cbeta = Q[k + 1];
-      T fx = face_flux(N.left, c.v[0], NB.left, cbeta.v[0], inv_dx);  // lower x face of element 0
-      VT o;
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        const T uxp = e == V - 1 ? N.right : c.v[e + 1];
-        const T bxp = e == V - 1 ? NB.right : cbeta.v[e + 1];
-        const T fxp = face_flux(c.v[e], uxp, cbeta.v[e], bxp, inv_dx);
-        const T fym = face_flux(N.ym.v[e], c.v[e], NB.ym.v[e], cbeta.v[e], inv_dx);
-        const T fyp = face_flux(c.v[e], N.yp.v[e], cbeta.v[e], NB.yp.v[e], inv_dx);
-        const T fzp = face_flux(c.v[e], P[k + 2].v[e], cbeta.v[e], Q[k + 2].v[e], inv_dx);
-        const T dfx = (fxp - fx) * inv_dx, dfy = (fyp - fym) * inv_dx, dfz = (fzp - fz[e]) * inv_dx;
-        o.v[e] = c.v[e] + dt * ((dfx + dfy) + dfz);
-        fx = fxp;
-        fz[e] = fzp;
+    for (int j = 0; j < nsteps; ++j) {  // z steps as in k_heat_dma, both fields carried
+      const DevLinTile ts = tile_zstep<ZB>(tl, j);
+      const LinLane L = lin_lane<V, ZB>(ts, nvx);
+      const int64_t cb = comp0 + (int64_t)L.q * V;
+      if (j > 0 && carry) {
+        P[0] = P[ZB];
+        P[1] = P[ZB + 1];
+        Q[0] = Q[ZB];
+        Q[1] = Q[ZB + 1];
+        load_planes<T, V, FUSED, ZB, 2>(P, L, ts, B, recs, u, cb);
+        load_planes<T, V, FUSED, ZB, 2>(Q, L, ts, B, recs, bt, cb);
+      } else {
+        load_planes<T, V, FUSED, ZB>(P, L, ts, B, recs, u, cb);
+        load_planes<T, V, FUSED, ZB>(Q, L, ts, B, recs, bt, cb);
       }
-      const int z = L.zb0 + k;
-      if (z < L.zb1 && L.active) {
-        stv_nt<T, V>(wp + (int64_t)z * B.sz, o);
-        if (FUSED) stage_edges<T, V, ZB>(S, L, tl, nvx, k, o);
+      stage_halo<T, V, FUSED, ZB>(S, ts, B, recs, u, comp0);
+      stage_halo<T, V, FUSED, ZB>(Sb, ts, B, recs, bt, comp0);
+#pragma unroll
+      for (int k = 0; k < ZB; ++k) {
+        S.sh[k * S.nthr + threadIdx.x] = P[k + 1];
+        Sb.sh[k * Sb.nthr + threadIdx.x] = Q[k + 1];
       }
+      __syncthreads();
+      BL_GLOBAL T* wp = w + cb;
+      T fz[V];  // flux through the lower z face of the current plane
+#pragma unroll
+      for (int e = 0; e < V; ++e) fz[e] = face_flux(P[0].v[e], P[1].v[e], Q[0].v[e], Q[1].v[e], inv_dx);
+#pragma unroll
+      for (int k = 0; k < ZB; ++k) {
+        const Nbr<T, V> N = tile_neighbours<T, V, ZB, false>(S, L, ts, nvx, k, P[k + 1]);
+        const Nbr<T, V> NB = tile_neighbours<T, V, ZB, false>(Sb, L, ts, nvx, k, Q[k + 1]);
+        const VT& c = P[k + 1];
+        const VT& cbeta = Q[k + 1];
+        T fx = face_flux(N.left, c.v[0], NB.left, cbeta.v[0], inv_dx);  // lower x face of element 0
+        VT o;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const T uxp = e == V - 1 ? N.right : c.v[e + 1];
+          const T bxp = e == V - 1 ? NB.right : cbeta.v[e + 1];
+          const T fxp = face_flux(c.v[e], uxp, cbeta.v[e], bxp, inv_dx);
+          const T fym = face_flux(N.ym.v[e], c.v[e], NB.ym.v[e], cbeta.v[e], inv_dx);
+          const T fyp = face_flux(c.v[e], N.yp.v[e], cbeta.v[e], NB.yp.v[e], inv_dx);
+          const T fzp = face_flux(c.v[e], P[k + 2].v[e], cbeta.v[e], Q[k + 2].v[e], inv_dx);
+          const T dfx = (fxp - fx) * inv_dx, dfy = (fyp - fym) * inv_dx, dfz = (fzp - fz[e]) * inv_dx;
+          o.v[e] = c.v[e] + dt * ((dfx + dfy) + dfz);
+          fx = fxp;
+          fz[e] = fzp;
+        }
+        const int z = L.zb0 + k;
+        if (z < L.zb1 && L.active) {
+          stv_nt<T, V>(wp + (int64_t)z * B.sz, o);
+          if (FUSED) stage_edges<T, V, ZB>(S, L, ts, nvx, k, o);
+        }
+      }
+      if (FUSED) store_mirror<T, V, ZB>(S, ts, B, w);
+      if (j + 1 < nsteps) __syncthreads();  // the next step reuses the LDS buffers
     }
-    if (FUSED) store_mirror<T, V, ZB>(S, tl, B, w);
   }
 }
 
