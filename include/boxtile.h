@@ -464,7 +464,7 @@ bl_status bl_device_copy(void* dst, const void* src, size_t bytes, hipStream_t s
  * per tile; a workgroup takes its tile's planes zchunk at a time, bottom to
  * top, and carries the two planes above a step into the next one, so the
  * planes between steps are read once, not twice.  Default: zchunk 4, waves 4,
- * persist 0, block 3, zsteps 1.  Applies to MultiFabs created afterwards and to
+ * persist 0, block 3, zsteps 2.  Applies to MultiFabs created afterwards and to
  * bl_batch objects at their next rebuild; results do not depend on it.  The
  * configuration is one setting of the whole process, shared by every thread:
  * set it before creating MultiFabs, not while other threads create them.
@@ -519,6 +519,13 @@ bl_status bl_batch_add(bl_batch* b, bl_multifab* u0, bl_multifab* u1, double c, 
 bl_status bl_batch_remove(bl_batch* b, int32_t member_id);
 bl_status bl_batch_parity(const bl_batch* b, int32_t member_id, int32_t* steps_done);
 bl_status bl_batch_step(bl_batch* b, hipStream_t stream);
+/*
+ * nsteps consecutive bl_batch_step calls in one (nsteps >= 0; EINVAL below):
+ * the same launches in the same order, issued from the library, so that a
+ * serving loop pays its own per-step host work once per call.  Members join and
+ * leave only between calls.
+ */
+bl_status bl_batch_steps(bl_batch* b, int32_t nsteps, hipStream_t stream);
 void bl_batch_destroy(bl_batch* b);
 
 /* ------------------------------------------------------- metadata inspection */

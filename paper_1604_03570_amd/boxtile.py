@@ -90,6 +90,7 @@ _SIGS = {
     "bl_batch_remove": [_vp, _i32],
     "bl_batch_parity": [_vp, _i32, _i32p],
     "bl_batch_step": [_vp, _vp],
+    "bl_batch_steps": [_vp, _i32, _vp],
     "bl_fill_plan": [_vp, _i32, _i32p, _i32p],
     "bl_face_plan": [_vp, _i32p, _i32p],
     "bl_tile_list": [_vp, _i32, _i32, _i32, _i32p, _i32p],
@@ -326,7 +327,7 @@ def static_partition(ntiles: int, nworkers: int) -> list:
     return list(first)
 
 
-def set_tile_config(zchunk: int = 4, waves: int = 4, persist: int = 0, block: int = 3, zsteps: int = 1) -> None:
+def set_tile_config(zchunk: int = 4, waves: int = 4, persist: int = 0, block: int = 3, zsteps: int = 2) -> None:
     _check(_L.bl_set_tile_config(zchunk, waves, persist, block, zsteps))
 
 
@@ -635,6 +636,10 @@ class Batch:
 
     def step(self, stream=None) -> None:
         _check(_L.bl_batch_step(self._h, _stream(stream)))
+
+    def steps(self, nsteps: int, stream=None) -> None:
+        """nsteps steps of every member in one call (no joins or leaves in between)."""
+        _check(_L.bl_batch_steps(self._h, int(nsteps), _stream(stream)))
 
     def __len__(self) -> int:
         return len(self._members)

@@ -1490,21 +1490,26 @@ bl_status bl_batch_parity(const bl_batch* b, int32_t member_id, int32_t* steps_d
   return fail(BL_EINVAL, "no member %d", member_id);
 }
 
-bl_status bl_batch_step(bl_batch* b, hipStream_t stream) {
+bl_status bl_batch_steps(bl_batch* b, int32_t nsteps, hipStream_t stream) {
   clear_error();
   if (!b) return fail(BL_EINVAL, "NULL batch");
+  if (nsteps < 0) return fail(BL_EINVAL, "nsteps < 0");
   bl_status st;
-  if (b->dirty && (st = batch_rebuild(b, stream)) != BL_OK) return st;
-  for (auto& g : b->groups) {
-    if (g.members.empty()) continue;
-    HeatArgs a{g.tiles.dev, (int)g.tiles.n, g.boxes.dev, g.recs.dev, DevMember{}, g.dmembers.dev,
-               (int)(b->tick & 1), g.fvec, b->cfg.block ? b->cfg.zchunk : 0, b->cfg.block, g.rmax, g.nvtmax,
-               g.lin.n ? g.lin.dev : nullptr, (int)g.lin.n, g.yhmax, g.xhmax};
-    BL_HIP(launch_heat(g.dtype, g.vec, true, a, persistent_grid(b->cfg.persist), 64 * b->cfg.waves, stream));
+  if (nsteps > 0 && b->dirty && (st = batch_rebuild(b, stream)) != BL_OK) return st;
+  for (int32_t s = 0; s < nsteps; ++s) {
+    for (auto& g : b->groups) {
+      if (g.members.empty()) continue;
+      HeatArgs a{g.tiles.dev, (int)g.tiles.n, g.boxes.dev, g.recs.dev, DevMember{}, g.dmembers.dev,
+                 (int)(b->tick & 1), g.fvec, b->cfg.block ? b->cfg.zchunk : 0, b->cfg.block, g.rmax, g.nvtmax,
+                 g.lin.n ? g.lin.dev : nullptr, (int)g.lin.n, g.yhmax, g.xhmax};
+      BL_HIP(launch_heat(g.dtype, g.vec, true, a, persistent_grid(b->cfg.persist), 64 * b->cfg.waves, stream));
+    }
+    b->tick++;
   }
-  b->tick++;
   return BL_OK;
 }
+
+bl_status bl_batch_step(bl_batch* b, hipStream_t stream) { return bl_batch_steps(b, 1, stream); }
 
 void bl_batch_destroy(bl_batch* b) { delete b; }
 

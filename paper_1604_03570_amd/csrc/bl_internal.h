@@ -265,7 +265,7 @@ struct TileConfig {
   int persist = 0;    // workgroups per CU for the persistent grid (0: one workgroup per tile)
   int block = 3;      // 0: z march; 1: block form; 2: block form with LDS neighbours; 3: as 2, halos
                       // loaded straight into LDS (block forms: zchunk 2, 4 or 8)
-  int zsteps = 1;     // form 3: z steps per linear tile (a tile spans up to zsteps * zchunk planes
+  int zsteps = 2;     // form 3: z steps per linear tile (a tile spans up to zsteps * zchunk planes
                       // per z block; a workgroup carries the planes between its steps)
 };
 TileConfig& tile_config();

@@ -11,6 +11,11 @@ The loop:
 * advances every member by one step per tick: one fused FillBoundary+stencil
   launch per dtype over all members' tiles, the paper's collapsed (grid, tile)
   loop of Sec. 3.3 spanning every problem;
+* issues several ticks per pass of the loop (Batch.steps), as many as no member
+  finishes before the last of them and at most max_steps, so the loop's host
+  work is paid once per pass, not once per step; the host runs at most
+  max_ahead_steps steps ahead of the GPU, which bounds how long a request that
+  arrives meanwhile waits to join;
 * retires a request, freeing its memory, when its step count is reached.
 
 Latency is completion minus arrival. Completion is the GPU time of the event
@@ -112,6 +117,10 @@ class ServeStats:
     completed: int = 0
     rejected: int = 0
     ticks: int = 0
+    launches: int = 0      # passes of the loop that issued steps (Batch.steps calls)
+    host_us: list = field(default_factory=list)    # host time of each such pass, admission to bookkeeping,
+                                                   # without the time spent waiting for the GPU
+    launch_us: list = field(default_factory=list)  # of which in Batch.steps (the launches themselves)
     latencies_ms: list = field(default_factory=list)
     queue_ms: list = field(default_factory=list)
     cell_updates: int = 0
@@ -131,6 +140,9 @@ class ServeStats:
             "throughput_gcell_s": round(self.cell_updates / max(self.makespan_s, 1e-9) / 1e9, 3),
             "makespan_s": round(self.makespan_s, 3), "peak_hbm_bytes": self.peak_bytes,
             "peak_active": self.peak_active, "mean_active": round(self.mean_active, 2),
+            "launches": self.launches, "steps_per_launch": round(self.ticks / max(self.launches, 1), 2),
+            "host_us_per_launch_p50": round(float(np.percentile(self.host_us, 50)), 1) if self.host_us else 0.0,
+            "launch_us_per_launch_p50": round(float(np.percentile(self.launch_us, 50)), 1) if self.launch_us else 0.0,
         }
 
 
@@ -139,9 +151,11 @@ class Server:
     on the host clock).  `on_complete(req, result_tensor)` receives each finished
     request's final field (dense (1, n, n, n) device tensor) when given."""
 
-    def __init__(self, hbm_budget: int, max_slots: int = 64, max_ahead: int = 3, on_complete=None):
+    def __init__(self, hbm_budget: int, max_slots: int = 64, max_steps: int = 16, max_ahead_steps: int = 16,
+                 on_complete=None):
         self.adm = Admission(int(hbm_budget), int(max_slots))
-        self.max_ahead = max_ahead
+        self.max_steps = max(1, int(max_steps))
+        self.max_ahead_steps = max(1, int(max_ahead_steps))
         self.on_complete = on_complete
         self.shapes = _Shapes()
 
@@ -180,8 +194,9 @@ class Server:
         live = {}
         batch = bt.Batch()
         st = ServeStats()
-        done_events = []       # (event, request, admit_host)
-        ahead = deque()        # events of recent ticks, to bound host run-ahead
+        done_events = []       # (event, request)
+        ahead = deque()        # (event, steps) of recent launches, to bound host run-ahead
+        ahead_steps = 0
         active_sum = 0
         tick = 0
         with torch.cuda.stream(stream):
@@ -190,7 +205,8 @@ class Server:
             t0_ev.record(stream)
             t0 = time.perf_counter()
             while pending or queue or live:
-                now = time.perf_counter() - t0
+                h0 = time.perf_counter()
+                now = h0 - t0
                 while pending and pending[0].arrival <= now:
                     queue.append(pending.popleft())
                 for r, need in self.adm.admit(queue, self.shapes.footprint):
@@ -210,14 +226,23 @@ class Server:
                     if pending:
                         time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.002)))
                     continue
-                batch.step(stream)
-                tick += 1
-                active_sum += len(live)
+                k = min(self.max_steps, min(L.req.steps - (tick - L.joined_tick) for L in live.values()))
+                l0 = time.perf_counter()
+                batch.steps(k, stream)
+                l1 = time.perf_counter()
+                tick += k
+                st.launches += 1
+                active_sum += len(live) * k
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(stream)
-                ahead.append(ev)
-                if len(ahead) > self.max_ahead:
-                    ahead.popleft().synchronize()
+                ahead.append((ev, k))
+                ahead_steps += k
+                w0 = time.perf_counter()
+                while ahead_steps - ahead[-1][1] >= self.max_ahead_steps:  # keep the newest launch in flight
+                    e_old, k_old = ahead.popleft()
+                    e_old.synchronize()
+                    ahead_steps -= k_old
+                waited = time.perf_counter() - w0
                 finished = [m for m, L in live.items() if tick - L.joined_tick == L.req.steps]
                 for m in finished:
                     L = live.pop(m)
@@ -228,6 +253,8 @@ class Server:
                     self.adm.release(L.nbytes)
                     done_events.append((ev, L.req))
                     st.cell_updates += L.req.n ** 3 * L.req.steps
+                st.launch_us.append((l1 - l0) * 1e6)
+                st.host_us.append((time.perf_counter() - h0 - waited) * 1e6)  # without waiting on the GPU
             torch.cuda.synchronize()
             last = 0.0
             for ev, r in done_events:
@@ -242,8 +269,8 @@ class Server:
         return st
 
 
-def serve_stream(requests, hbm_budget: int, max_slots: int = 64, on_complete=None) -> dict:
-    return Server(hbm_budget, max_slots, on_complete=on_complete).run(requests).summary()
+def serve_stream(requests, hbm_budget: int, max_slots: int = 64, on_complete=None, **kw) -> dict:
+    return Server(hbm_budget, max_slots, on_complete=on_complete, **kw).run(requests).summary()
 
 
 def offered_load(requests) -> float:

@@ -29,14 +29,20 @@ def _stream(seed, nreq, rate):
     return out
 
 
+@pytest.mark.parametrize("max_steps", [16, 1])
 @pytest.mark.parametrize("budget_mb", [4096, 2])
-def test_served_results_equal_alone_runs(bt, budget_mb):
+def test_served_results_equal_alone_runs(bt, budget_mb, max_steps):
+    """Each request's served result equals its run alone, bit for bit, whether the loop
+    issues one step per pass or several (members join and leave only between passes)."""
     from paper_1604_03570_amd import serve as S
     reqs = _stream(3, 24, 2000.0)
     got = {}
-    srv = S.Server(budget_mb << 20, max_slots=8, on_complete=lambda r, t: got.__setitem__(r.rid, t.double().cpu().numpy()))
+    srv = S.Server(budget_mb << 20, max_slots=8, max_steps=max_steps,
+                   on_complete=lambda r, t: got.__setitem__(r.rid, t.double().cpu().numpy()))
     st = srv.run(reqs)
-    say(f"budget {budget_mb} MB: {st.summary()}")
+    say(f"budget {budget_mb} MB, {max_steps} steps per pass at most: {st.summary()}")
+    if max_steps > 1:
+        assert st.ticks > st.launches  # several steps per pass happened
     assert st.completed + st.rejected == len(reqs)
     assert st.completed == len(got)
     if budget_mb > 100:
