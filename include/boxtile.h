@@ -202,6 +202,22 @@ bl_status bl_multifab_info(const bl_multifab* mf, int32_t* nboxes, int32_t* ncom
 void bl_multifab_destroy(bl_multifab* mf);
 
 /*
+ * Next to each box's valid cells the storage holds a copy of the box's first
+ * and last valid x column, contiguous along y (its edge mirror).  Reading a
+ * neighbour box's x face from that copy costs a few contiguous lines instead
+ * of one line per row.  The library remembers, per MultiFab, whether the copy
+ * is current: the calls that write it with the state they produce (the fused
+ * heat, GSRB and variable-coefficient steps, the unfused heat step's stencil)
+ * mark it so, every other write by the library marks it stale, and later calls
+ * read the copy only where it is current (the first step of an advance,
+ * FillBoundary, the first GSRB pass).  A caller who writes a MultiFab's
+ * storage without the library (through its own kernels or copies) must call
+ * bl_multifab_modified before the MultiFab's next use; otherwise a later call
+ * may read a stale copy.  BL_EINVAL for NULL.
+ */
+bl_status bl_multifab_modified(bl_multifab* mf);
+
+/*
  * Copy between the valid cells of components [scomp, scomp+ncomp) and a dense
  * device array `global_dev` of shape (ncomp, Nz, Ny, Nx) over the domain, x
  * fastest, of the MultiFab's dtype.  to_global != 0 copies MultiFab -> array

@@ -62,6 +62,7 @@ _SIGS = {
     "bl_multifab_layout": [_vp, _i32, _boxp, _szp, _i64p],
     "bl_multifab_xghost_layout": [_vp, _i32, _szp, _i64p],
     "bl_multifab_copy_fab": [_vp, _i32, _i32, _i32, _vp, _i32, _vp],
+    "bl_multifab_modified": [_vp],
     "bl_multifab_info": [_vp, _i32p, _i32p, _i32p, _i32p],
     "bl_multifab_copy_global": [_vp, _i32, _i32, _vp, _i32, _vp],
     "bl_multifab_set_val": [_vp, ctypes.c_double, _i32, _i32, _i32, _vp],
@@ -389,10 +390,16 @@ class MultiFab:
         return self._ptr
 
     def elements(self) -> torch.Tensor:
-        """The whole allocation viewed as elements of the MultiFab's dtype."""
+        """The whole allocation viewed as elements of the MultiFab's dtype.  After writing
+        through this view (or any other way around the library), call modified()."""
         esize = 8 if self.dtype == F64 else 4
         off = self._ptr - self.buffer.data_ptr()
         return self.buffer[off:off + self.nbytes].view(_TORCH[self.dtype])[: self.nbytes // esize]
+
+    def modified(self) -> None:
+        """Declare that the storage was written outside the library, so that no later
+        call trusts the boxes' edge mirrors before it has rewritten them."""
+        _check(_L.bl_multifab_modified(self._h))
 
     def layout(self, box: int):
         g = bl_box()

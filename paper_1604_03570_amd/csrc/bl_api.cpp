@@ -29,6 +29,7 @@ Plan::~Plan() {
   (void)hipFree(dlin);
   (void)hipFree(dred);
   (void)hipFree(dfillrecs);
+  (void)hipFree(dfillrecs_mir);
   (void)hipFree(dfillchunks);
   (void)hipFree(dvlin);
   (void)hipFree(dcellpre);
@@ -61,6 +62,8 @@ bl_status upload_plan(Plan& p) {
   if ((st = upload(&p.dlin, p.hlin, "hipMalloc/hipMemcpy(stencil tiles)")) != BL_OK) return st;
   if ((st = upload(&p.dred, p.hred, "hipMalloc/hipMemcpy(reduction chunks)")) != BL_OK) return st;
   if ((st = upload(&p.dfillrecs, p.hfillrecs, "hipMalloc/hipMemcpy(fill records)")) != BL_OK) return st;
+  if ((st = upload(&p.dfillrecs_mir, p.hfillrecs_mir, "hipMalloc/hipMemcpy(fill records, mirrors)")) != BL_OK)
+    return st;
   if ((st = upload(&p.dfillchunks, p.hfillchunks, "hipMalloc/hipMemcpy(fill chunks)")) != BL_OK) return st;
   if ((st = upload(&p.dcellpre, p.hcellpre, "hipMalloc/hipMemcpy(cell counts)")) != BL_OK) return st;
   if ((st = upload(&p.dpairpre, p.hpairpre, "hipMalloc/hipMemcpy(pair counts)")) != BL_OK) return st;
@@ -179,9 +182,10 @@ struct GraphKey {
   uint64_t cbits;
   int persist;
   int device;
+  bool start_mirror;
   bool operator==(const GraphKey& o) const {
     return u0 == o.u0 && u1 == o.u1 && d0 == o.d0 && d1 == o.d1 && nsteps == o.nsteps && cbits == o.cbits &&
-           persist == o.persist && device == o.device;
+           persist == o.persist && device == o.device && start_mirror == o.start_mirror;
   }
 };
 static std::mutex g_graph_mu;
@@ -282,7 +286,15 @@ bl_status bl_multifab_copy_fab(bl_multifab* mf, int32_t box, int32_t scomp, int3
   const Plan& p = *mf->plan;
   if (box < 0 || box >= (int)p.fabs.size()) return fail(BL_EINVAL, "box %d out of range", box);
   if (scomp < 0 || ncomp < 1 || scomp + ncomp > p.ncomp) return fail(BL_EINVAL, "component range out of bounds");
+  if (!to_dense) mf->mirror_current = false;
   BL_HIP(launch_copy_fab(p, mf->data, dense_dev, box, scomp, ncomp, to_dense, stream));
+  return BL_OK;
+}
+
+bl_status bl_multifab_modified(bl_multifab* mf) {
+  clear_error();
+  if (!mf) return fail(BL_EINVAL, "NULL MultiFab");
+  mf->mirror_current = false;
   return BL_OK;
 }
 
@@ -304,6 +316,7 @@ bl_status bl_multifab_copy_global(bl_multifab* mf, int32_t scomp, int32_t ncomp,
   if (!mf || !global_dev) return fail(BL_EINVAL, "NULL argument");
   const Plan& p = *mf->plan;
   if (scomp < 0 || ncomp < 1 || scomp + ncomp > p.ncomp) return fail(BL_EINVAL, "component range out of bounds");
+  if (!to_global) mf->mirror_current = false;
   BL_HIP(launch_copy_global(p, mf->data, global_dev, scomp, ncomp, to_global, block_of(p), stream));
   return BL_OK;
 }
@@ -314,6 +327,7 @@ bl_status bl_multifab_set_val(bl_multifab* mf, double val, int32_t scomp, int32_
   if (!mf) return fail(BL_EINVAL, "NULL MultiFab");
   const Plan& p = *mf->plan;
   if (scomp < 0 || ncomp < 1 || scomp + ncomp > p.ncomp) return fail(BL_EINVAL, "component range out of bounds");
+  mf->mirror_current = false;
   BL_HIP(launch_set_val(p, mf->data, val, scomp, ncomp, with_ghosts, block_of(p), stream));
   return BL_OK;
 }
@@ -323,7 +337,7 @@ bl_status bl_fill_boundary(bl_multifab* mf, int32_t scomp, int32_t ncomp, hipStr
   if (!mf) return fail(BL_EINVAL, "NULL MultiFab");
   const Plan& p = *mf->plan;
   if (scomp < 0 || ncomp < 1 || scomp + ncomp > p.ncomp) return fail(BL_EINVAL, "component range out of bounds");
-  BL_HIP(launch_fill(p, mf->data, scomp, ncomp, stream));
+  BL_HIP(launch_fill(p, mf->data, scomp, ncomp, stream, mf->mirror_current));
   return BL_OK;
 }
 
@@ -350,7 +364,8 @@ bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t
   bl_status st = check_heat(u_old, u_new);
   if (st != BL_OK) return st;
   const Plan& p = *u_old->plan;
-  if (fill_first) BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream));
+  if (fill_first) BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream, u_old->mirror_current));
+  u_new->mirror_current = false;  // the per-box kernels do not write the edge mirror
   HeatArgs a{};
   a.fvec = p.fvec;
   a.zblock = p.cfg.block ? p.cfg.zchunk : 0;
@@ -375,10 +390,12 @@ bl_status bl_heat_step_unfused(bl_multifab* u_old, bl_multifab* u_new, double c,
   bl_status st = check_heat(u_old, u_new);
   if (st != BL_OK) return st;
   const Plan& p = *u_old->plan;
-  BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream));
+  BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream, u_old->mirror_current));
   HeatArgs a{p.dtiles, (int)p.htiles.size(), p.dboxes, p.dfacerecs, member_of(u_old, u_new, c), nullptr, 0,
              p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block, p.rmax, p.nvtmax,
              p.dlin, (int)p.hlin.size(), p.yhmax, p.xhmax};
+  // the halo-in-LDS kernel over linear tiles writes the output's edge mirror, the others do not
+  u_new->mirror_current = p.cfg.block == 3 && p.dlin != nullptr;
   BL_HIP(launch_heat(p.dtype, p.vec, false, a, persistent_grid(tile_config().persist), block_of(p), stream));
   return BL_OK;
 }
@@ -396,7 +413,12 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
   BL_HIP(hipGetDevice(&dev));
   uint64_t cbits;
   std::memcpy(&cbits, &c, sizeof cbits);
-  GraphKey key{u[0], u[1], u[0]->data, u[1]->data, nsteps, cbits, persist, dev};
+  // the first step reads the starting state's x faces from its edge mirror when
+  // the library knows that mirror to be current, else from the neighbours' rows
+  // (form 3) or from a mirror extracted first (the other forms)
+  const bool start_mirror = u[0]->mirror_current;
+  const bool rows_first = !start_mirror && p.cfg.block == 3 && p.dlin && p.fvec && p.dfacerecs_rows;
+  GraphKey key{u[0], u[1], u[0]->data, u[1]->data, nsteps, cbits, persist, dev, start_mirror};
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -411,11 +433,10 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
                p.dlin, (int)p.hlin.size(), p.yhmax, p.xhmax};
     BL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     // The fused steps read x neighbours from the edge-column mirror that each
-    // step writes for its output.  The halo-in-LDS form reads the first step's
-    // from the neighbours' rows instead (no mirror of the starting state is
-    // needed); the other forms get one made first.
-    const bool rows_first = p.cfg.block == 3 && p.dlin && p.fvec && p.dfacerecs_rows;
-    hipError_t le = rows_first ? hipSuccess : launch_extract_mirror(p, u[0]->data, cs);
+    // step writes for its output.  Without a current mirror of the starting
+    // state, the halo-in-LDS form reads the first step's from the neighbours'
+    // rows instead; the other forms get one made first.
+    hipError_t le = rows_first || start_mirror ? hipSuccess : launch_extract_mirror(p, u[0]->data, cs);
     for (int s = 0; s < nsteps && le == hipSuccess; ++s) {
       a.flip = s & 1;
       a.recs = rows_first && s == 0 ? p.dfacerecs_rows : p.dfacerecs;
@@ -435,6 +456,8 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
     g_graphs.push_back({key, exec});
   }
   BL_HIP(hipGraphLaunch(exec, stream));
+  if (nsteps >= 2 || !rows_first) u[0]->mirror_current = true;  // written by step 1, extracted or kept
+  u[1]->mirror_current = true;                                    // written by step 0
   return BL_OK;
 }
 
@@ -505,17 +528,21 @@ bl_status bl_heat_varcoef_advance(bl_multifab* u[2], bl_multifab* beta, int32_t 
   a.dt = dt;
   a.inv_dx = inv_dx;
   if (a.fused) {  // neighbour values from the neighbour boxes' faces and edge mirrors
-    BL_HIP(launch_extract_mirror(p, beta->data, stream));
-    BL_HIP(launch_extract_mirror(p, u[0]->data, stream));
+    if (!beta->mirror_current) BL_HIP(launch_extract_mirror(p, beta->data, stream));
+    if (!u[0]->mirror_current) BL_HIP(launch_extract_mirror(p, u[0]->data, stream));
+    beta->mirror_current = true;
   } else {
-    BL_HIP(launch_fill(p, beta->data, 0, p.ncomp, stream));
+    BL_HIP(launch_fill(p, beta->data, 0, p.ncomp, stream, beta->mirror_current));
   }
   for (int s = 0; s < nsteps; ++s) {
     a.u = u[s & 1]->data;
     a.w = u[(s + 1) & 1]->data;
-    if (!a.fused) BL_HIP(launch_fill(p, u[s & 1]->data, 0, p.ncomp, stream));
+    if (!a.fused) BL_HIP(launch_fill(p, u[s & 1]->data, 0, p.ncomp, stream, s > 0 || u[0]->mirror_current));
     BL_HIP(launch_heat_varcoef(p.dtype, p.vec, a, stream));
   }
+  // the kernel writes its output's edge mirror (both forms)
+  u[0]->mirror_current = a.fused || nsteps >= 2 || u[0]->mirror_current;
+  u[1]->mirror_current = true;
   return BL_OK;
 }
 
@@ -575,6 +602,8 @@ bl_status bl_heat8_advance_form(bl_multifab* u[2], int32_t nsteps, double c, int
       p.h8built = true;
     }
   }
+  if (nsteps > 0) u[1]->mirror_current = false;  // the 8th-order kernels do not write the edge mirror
+  if (nsteps > 1) u[0]->mirror_current = false;
   for (int s = 0; s < nsteps; ++s) {
     void* src = u[s & 1]->data;
     void* dst = u[(s + 1) & 1]->data;
@@ -674,10 +703,11 @@ bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, do
   double* dout = phi->dscratch + reduce_slots(p);
   const int grid = persistent_grid(tile_config().persist);
   if (gsrb_fused_ok(p, block_of(p))) {  // neighbour values straight from the neighbour boxes
-    BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, -1, 2, phi->dscratch, grid, block_of(p), stream, true));
+    BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, -1, 2, phi->dscratch, grid, block_of(p), stream,
+                             !phi->mirror_current));
     BL_HIP(launch_reduce_partials(phi->dscratch, gsrb_fused_grid(p, grid), 1, dout, stream));
   } else {
-    BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
+    BL_HIP(launch_fill(p, phi->data, 0, 1, stream, phi->mirror_current));
     BL_HIP(launch_residual(p, phi->data, f->data, h2, phi->dscratch, dout, block_of(p), stream));
   }
   BL_HIP(hipMemcpyAsync(phi->hres, dout, sizeof(double), hipMemcpyDeviceToHost, stream));
@@ -743,9 +773,11 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
     double* red_part = resnorm_host ? phi->dscratch : nullptr;
     double* black_part = resnorm_host ? phi->dscratch + g : nullptr;
     double* norms = resnorm_host ? phi->dscratch + 2 * g : nullptr;
-    // the edge mirror of the starting state first: over many sweeps one
-    // extraction costs less than a first pass reading the neighbours' rows
-    if (nsweeps > 0) BL_HIP(launch_extract_mirror(p, phi->data, stream));
+    // the edge mirror of the starting state first, unless it is current: over
+    // many sweeps one extraction costs less than a first pass reading the
+    // neighbours' rows
+    if (nsweeps > 0 && !phi->mirror_current) BL_HIP(launch_extract_mirror(p, phi->data, stream));
+    if (nsweeps > 0) phi->mirror_current = true;  // every colour pass writes it
     for (int s = 0; s < nsweeps; ++s) {
       BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, 0, 0, s > 0 ? red_part : nullptr, grid, block_of(p),
                                stream));
@@ -762,6 +794,7 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
     return BL_OK;
   }
   if (resnorm_host && (st = ensure_scratch(phi, nt + (size_t)nsweeps + 8, (size_t)nsweeps + 8)) != BL_OK) return st;
+  if (nsweeps > 0) phi->mirror_current = false;  // the colour passes of this form do not write it
   for (int s = 0; s < nsweeps; ++s) {
     for (int color = 0; color < 2; ++color) {
       BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
@@ -809,7 +842,8 @@ bl_status bl_mg_restrict_residual(bl_multifab* phi, const bl_multifab* f, double
   if ((st = check_transfer(phi, fc)) != BL_OK) return st;
   if (phi->plan->ng < 1) return fail(BL_EINVAL, "the residual needs nghost >= 1");
   if (fc->data == phi->data || fc->data == f->data) return fail(BL_EINVAL, "fc shares storage with phi or f");
-  BL_HIP(launch_fill(*phi->plan, phi->data, 0, 1, stream));
+  BL_HIP(launch_fill(*phi->plan, phi->data, 0, 1, stream, phi->mirror_current));
+  fc->mirror_current = false;
   BL_HIP(launch_restrict_residual(*phi->plan, *fc->plan, phi->data, f->data, fc->data, h2, stream));
   return BL_OK;
 }
@@ -819,6 +853,7 @@ bl_status bl_mg_prolong_add(bl_multifab* phi, const bl_multifab* pc, hipStream_t
   bl_status st = check_transfer(phi, pc);
   if (st != BL_OK) return st;
   if (pc->data == phi->data) return fail(BL_EINVAL, "pc shares storage with phi");
+  phi->mirror_current = false;
   BL_HIP(launch_prolong_add(*phi->plan, *pc->plan, phi->data, pc->data, stream));
   return BL_OK;
 }
@@ -981,6 +1016,7 @@ bl_status bl_mg_vcycles(bl_mg* mg, bl_multifab* phi, const bl_multifab* f, doubl
   const Plan& p = *phi->plan;
   const size_t slots = reduce_slots(p) + 8;
   if (resnorm_host && (st = ensure_scratch(phi, slots + (size_t)ncycles, (size_t)ncycles + 8)) != BL_OK) return st;
+  if (ncycles > 0) phi->mirror_current = false;  // prolongation writes phi without its mirror
   for (int c = 0; c < ncycles; ++c) {
     if ((st = vcycle(mg, 0, phi, f, h2, nu1, nu2, nu_bottom, stream)) != BL_OK) return st;
     if (resnorm_host)
@@ -1112,6 +1148,8 @@ bl_status bl_autotune(const bl_boxarray* ba, bl_multifab* u0, bl_multifab* u1, d
   }
   forget_graphs(u0);
   forget_graphs(u1);
+  u0->mirror_current = false;  // the trial steps overwrote both
+  u1->mirror_current = false;
   u0->plan = best_plan;
   u1->plan = best_plan;
   if (best) {
@@ -1458,6 +1496,8 @@ bl_status bl_batch_add(bl_batch* b, bl_multifab* u0, bl_multifab* u1, double c, 
   bl_batch::Member m;
   m.u0 = u0;
   m.u1 = u1;
+  u0->mirror_current = false;  // the batch keeps its own record while the pair is a member
+  u1->mirror_current = false;
   m.c = c;
   m.joined = b->tick;
   m.id = b->next_id++;

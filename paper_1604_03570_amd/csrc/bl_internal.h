@@ -321,6 +321,9 @@ struct Plan {
   std::vector<int32_t> hcellwg;          // first box of each workgroup of kRestrictPerWG cells
   std::vector<int32_t> hpairwg;          // first box of each workgroup of kProlongPerWG pairs
   std::vector<DevFillRec> hfillrecs;
+  // the same records, except that a one-column source at a box's x face is read
+  // from the source box's edge mirror (contiguous along y) instead of its rows
+  std::vector<DevFillRec> hfillrecs_mir;
   std::vector<DevFillChunk> hfillchunks;
   std::shared_ptr<const std::vector<FillRecord>> fill;
 
@@ -332,6 +335,7 @@ struct Plan {
   DevLinTile* dlin = nullptr;
   DevRedChunk* dred = nullptr;
   DevFillRec* dfillrecs = nullptr;
+  DevFillRec* dfillrecs_mir = nullptr;
   DevFillChunk* dfillchunks = nullptr;
   int32_t* dcellpre = nullptr;
   int32_t* dpairpre = nullptr;
@@ -394,6 +398,11 @@ struct bl_multifab {
   std::shared_ptr<bl::Plan> plan;
   void* data = nullptr;
   size_t bytes = 0;
+  // every box's edge mirror holds its current first and last valid x column:
+  // set by the library's calls that write the mirror of the state they produce,
+  // cleared by every other write (and by bl_multifab_modified for writes made
+  // outside the library)
+  bool mirror_current = false;
   double* dscratch = nullptr;   // reduction partials + results (device), grown on demand
   size_t nscratch = 0;
   double* hres = nullptr;       // pinned host landing slots for scalar results

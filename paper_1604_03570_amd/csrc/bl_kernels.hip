@@ -810,7 +810,8 @@ __device__ __forceinline__ DevLinTile tile_zstep(const DevLinTile& tl, int j) {
 // for all loads, the lanes' planes into LDS, one barrier, the updates,
 // full-vector stores.  With one z block per step (planes of a workgroup's size
 // or more), the two planes above a step are carried in registers into the next
-// step, which loads only its ZB new planes.
+// step, which loads only its ZB new planes.  Both forms store the new edge
+// columns into the output's edge mirror.
 template <typename T, int V, bool FUSED, int ZB>
 __global__ void __launch_bounds__(kStencilMaxThreads)
     __attribute__((amdgpu_waves_per_eu(ZB == 8 ? 4 : 6)))
@@ -865,10 +866,10 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
         const int z = L.zb0 + k;
         if (z < L.zb1 && L.active) {
           stv_nt<T, V>(wp + (int64_t)z * B.sz, o);
-          if (FUSED) stage_edges<T, V, ZB>(S, L, ts, nvx, k, o);
+          stage_edges<T, V, ZB>(S, L, ts, nvx, k, o);
         }
       }
-      if (FUSED) store_mirror<T, V, ZB>(S, ts, B, w);
+      store_mirror<T, V, ZB>(S, ts, B, w);  // both forms leave the output's edge mirror current
       if (persist || j + 1 < nsteps) __syncthreads();  // the next step or tile reuses the LDS buffers
     }
   }
@@ -890,8 +891,8 @@ __device__ __forceinline__ T face_flux(T ulo, T uhi, T blo, T bhi, T inv_dx) {
 // computed once.  u and beta are staged alike, each with its own LDS region of
 // lds_half bytes: the lane's planes in registers and LDS, the tile's halo
 // straight into LDS.  FUSED: neighbour boxes through the face records (the
-// edge mirrors of u and beta current), the new u's edge columns into its
-// mirror; otherwise the FABs' own filled ghosts.
+// edge mirrors of u and beta current); otherwise the FABs' own filled ghosts.
+// Both forms store the new u's edge columns into its mirror.
 template <typename T, int V, bool FUSED, int ZB>
 __global__ void __launch_bounds__(kStencilMaxThreads)
     __attribute__((amdgpu_waves_per_eu(ZB == 8 ? 2 : (ZB == 4 ? 3 : 5))))
@@ -967,10 +968,10 @@ __global__ void __launch_bounds__(kStencilMaxThreads)
         const int z = L.zb0 + k;
         if (z < L.zb1 && L.active) {
           stv_nt<T, V>(wp + (int64_t)z * B.sz, o);
-          if (FUSED) stage_edges<T, V, ZB>(S, L, ts, nvx, k, o);
+          stage_edges<T, V, ZB>(S, L, ts, nvx, k, o);
         }
       }
-      if (FUSED) store_mirror<T, V, ZB>(S, ts, B, w);
+      store_mirror<T, V, ZB>(S, ts, B, w);  // both forms leave the output's edge mirror current
       if (j + 1 < nsteps) __syncthreads();  // the next step reuses the LDS buffers
     }
   }
@@ -1826,14 +1827,15 @@ hipError_t launch_heat(int dtype, int vec, bool fused, const HeatArgs& a, int gr
   return vec == 4 ? heat_dispatch<float, 4>(fused, a, grid, block, s) : heat_dispatch<float, 1>(fused, a, grid, block, s);
 }
 
-hipError_t launch_fill(const Plan& p, void* data, int scomp, int ncomp, hipStream_t s) {
+hipError_t launch_fill(const Plan& p, void* data, int scomp, int ncomp, hipStream_t s, bool from_mirror) {
   const int n = (int)p.hfillchunks.size();
   if (n == 0 || ncomp <= 0) return hipSuccess;
+  const DevFillRec* recs = from_mirror && p.dfillrecs_mir ? p.dfillrecs_mir : p.dfillrecs;
   if (p.esize == 8)
-    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(n), dim3(kFillChunk), 0, s, (unsigned long long*)data,
-                       p.dfillrecs, p.dfillchunks, scomp, ncomp);
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(n), dim3(kFillChunk), 0, s, (unsigned long long*)data, recs,
+                       p.dfillchunks, scomp, ncomp);
   else
-    hipLaunchKernelGGL(k_fill<unsigned int>, dim3(n), dim3(kFillChunk), 0, s, (unsigned int*)data, p.dfillrecs,
+    hipLaunchKernelGGL(k_fill<unsigned int>, dim3(n), dim3(kFillChunk), 0, s, (unsigned int*)data, recs,
                        p.dfillchunks, scomp, ncomp);
   return hipGetLastError();
 }

@@ -34,7 +34,9 @@ struct HeatArgs {
 // taking a contiguous range of tiles.
 hipError_t launch_heat(int dtype, int vec, bool fused, const HeatArgs& a, int grid, int block, hipStream_t s);
 
-hipError_t launch_fill(const Plan& p, void* data, int scomp, int ncomp, hipStream_t s);
+// FillBoundary of components [scomp, scomp+ncomp); from_mirror: one-column
+// sources at a box's x face are read from its edge mirror (which must be current)
+hipError_t launch_fill(const Plan& p, void* data, int scomp, int ncomp, hipStream_t s, bool from_mirror = false);
 
 hipError_t launch_copy_global(const Plan& p, void* data, void* global, int scomp, int ncomp, int to_global,
                               int block, hipStream_t s);

@@ -869,6 +869,7 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
   // storage class along x (low x slab, rows, high x slab), chunked.
   p->fill = fill_plan(ba, ng);
   p->hfillrecs.clear();
+  p->hfillrecs_mir.clear();
   p->hfillchunks.clear();
   for (const FillRecord& r : *p->fill) {
     const Box& db = ba->boxes[r.dst];
@@ -900,6 +901,18 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
       R.nz = R0.len(2);
       const int rid = (int)p->hfillrecs.size();
       p->hfillrecs.push_back(R);
+      // one source column at the source box's low or high x face: its edge mirror
+      const Box& sb = ba->boxes[r.src];
+      const int sx = lo[0] + sh[0];
+      if (R.nx == 1 && (sx == sb.lo[0] || sx == sb.hi[0])) {
+        const int side = sx == sb.lo[0] ? 0 : 1;  // a one-cell-wide source box: its low-side copy
+        R.src_base = sf.mir + (int64_t)side * sf.mir_side + (int64_t)(lo[2] + sh[2] - sb.lo[2]) * sb.len(1) +
+                     (lo[1] + sh[1] - sb.lo[1]);
+        R.ssx = 0;
+        R.ssy = 1;
+        R.ssz = sb.len(1);
+      }
+      p->hfillrecs_mir.push_back(R);
       const int64_t vol = R0.volume();
       for (int64_t c0 = 0; c0 < vol; c0 += kFillChunk) p->hfillchunks.push_back(DevFillChunk{rid, (int32_t)c0});
     }
