@@ -835,8 +835,9 @@ def main() -> int:
         from paper_1604_03570_amd import serve as S
         reqs = I.request_stream(2000, 200.0, seed=args.seed)
         sv = {"requests": len(reqs), "rate_per_s": 200.0, "offered_gcell_s": round(S.offered_load(reqs) / 1e9, 3)}
-        for name, budget in (("budget_64GiB", 64 << 30), ("budget_1GiB", 1 << 30)):
-            sv[name] = S.Server(budget, max_slots=64).run(reqs).summary()
+        for name, budget, steps in (("budget_64GiB", 64 << 30, 16), ("budget_1GiB", 1 << 30, 16),
+                                    ("budget_64GiB_one_step_per_launch", 64 << 30, 1)):
+            sv[name] = S.Server(budget, max_slots=64, max_steps=steps).run(reqs).summary()
             log(f"serve {name}: p50 {sv[name]['p50_ms']} ms, p99 {sv[name]['p99_ms']} ms, "
                 f"{sv[name]['throughput_gcell_s']} GCell/s")
         extra["serve"] = sv

@@ -1348,7 +1348,7 @@ __device__ double block_reduce(double v, int op);
 // pass.  color -1 stores nothing and may take any rescolor.
 template <typename T, int V, int ZB, bool RES>
 __global__ void __launch_bounds__(kStencilMaxThreads)
-    __attribute__((amdgpu_waves_per_eu(RES ? (ZB == 8 ? 2 : 4) : (ZB == 8 ? 3 : 6))))
+    __attribute__((amdgpu_waves_per_eu(RES ? (ZB == 8 ? 2 : 4) : (ZB == 8 ? 3 : 5))))
     k_gsrb_dma(const DevLinTile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
                const DevFaceRec* __restrict__ recs, T* phi_, const T* __restrict__ f_, T h2, T inv6, int color,
                int rescolor, double inv_h2d, double* __restrict__ partials, int persist, int yhmax) {
