@@ -472,39 +472,92 @@ def varcoef_run(bt, I, torch, boxes, dom, u0, ncomp: int, seed: int, steps: int)
     return out
 
 
+def _timed(torch, fn, reps: int) -> float:
+    """Milliseconds per call of fn over reps calls (events on the current stream), after one warm-up."""
+    fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def mg_levels_breakdown(bt, torch, ba, dt, h2: float, nlevels: int, bottom: int) -> list:
+    """Time of each level's part of a V(2,2) cycle, level by level: its 4 GSRB sweeps, the
+    restriction (with its FillBoundary) and the prolongation, on a MultiFab of that level's
+    boxes; from the fused bottom's first level on, one launch for all the coarser levels
+    (a hierarchy built on that level's boxes, whose bottom is its level 0)."""
+    rows, cur, h = [], ba, h2
+    for lev in range(nlevels):
+        cells = int(sum(int(np.prod(b[3:] - b[:3] + 1)) for b in cur.boxes()))
+        phi, fm = bt.MultiFab(cur, 1, 1, dt), bt.MultiFab(cur, 1, 1, dt)
+        phi.set_val(0.0, with_ghosts=True)
+        fm.set_val(1e-3, with_ghosts=True)
+        if lev == bottom:
+            mgb = bt.Multigrid(cur, dt)
+            ms = _timed(torch, lambda: mgb.vcycles(phi, fm, h, 1, with_norms=False), 20)
+            rows.append({"levels": f"{lev}-{nlevels - 1}", "cells": cells, "fused_bottom_ms": round(ms, 4)})
+            break
+        nxt = cur.coarsen(2) if lev + 1 < nlevels else None
+        row = {"level": lev, "cells": cells, "boxes": len(cur),
+               "sweeps_4_ms": round(_timed(torch, lambda: bt.gsrb_sweeps(phi, fm, h, 4, with_norms=False), 10), 4)}
+        if nxt is not None:
+            fc = bt.MultiFab(nxt, 1, 1, dt)
+            fc.set_val(0.0, with_ghosts=True)
+            row["restrict_ms"] = round(_timed(torch, lambda: bt.restrict_residual(phi, fm, h, fc), 10), 4)
+            row["prolong_ms"] = round(_timed(torch, lambda: bt.prolong_add(phi, fc), 10), 4)
+        rows.append(row)
+        if nxt is None:
+            break
+        cur, h = nxt, 4.0 * h
+    return rows
+
+
 def mg_run(bt, I, torch, seed: int, cycles: int = 5) -> dict:
-    """Multigrid V(2,2) cycles for -Lap(phi) = f on GSRB's level (384^3 periodic, 216 boxes
-    of 64^3, f as there): 7 levels down to 216 boxes of one cell, 8 bottom sweeps.  FP64 and
-    FP32 state; time per cycle and the residual's mean reduction per cycle."""
-    n = 384
-    dom = I.domain_box(n)
-    ba = bt.BoxArray.from_boxes(I.regular_chop(dom, 64), dom)
-    f = I.zero_mean_normal_f32(n, seed=seed)
-    h2 = (1.0 / n) ** 2
-    out = {"workload": f"{n}^3 periodic, 216 boxes of 64^3, V(2,2), 8 bottom sweeps, {cycles} cycles"}
-    for name, dt in (("f64", bt.F64), ("f32", bt.F32)):
-        phi, fm = bt.MultiFab(ba, 1, 1, dt), bt.MultiFab(ba, 1, 1, dt)
-        fm.set_val(0.0, with_ghosts=True)
-        fm.from_global(f)
-        mg = bt.Multigrid(ba, dt)
-        phi.set_val(0.0, with_ghosts=True)
-        r0 = bt.residual_norm(phi, fm, h2)
-        mg.vcycles(phi, fm, h2, 1, with_norms=False)  # warm-up
-        phi.set_val(0.0, with_ghosts=True)
-        torch.cuda.synchronize()
-        stream = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        mg.vcycles(phi, fm, h2, cycles, with_norms=False)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / cycles
-        rn = bt.residual_norm(phi, fm, h2)
-        out[name] = {"levels": mg.nlevels, "ms_per_vcycle": round(ms, 4), "resnorm_0": r0,
-                     f"resnorm_after_{cycles}": rn, "mean_reduction_per_cycle": (rn / r0) ** (1.0 / cycles)}
-        log(f"mg {name}: {mg.nlevels} levels, {ms:.3f} ms per V-cycle, residual {r0:.3e} -> {rn:.3e}")
-        del phi, fm, mg
-    del f
+    """Multigrid V(2,2) cycles for -Lap(phi) = f, 8 bottom sweeps, on GSRB's level (384^3
+    periodic, 216 boxes of 64^3: 7 levels down to 216 boxes of one cell) and on 256^3 (64
+    boxes of 64^3, 7 levels), f a seeded zero-mean N(0,1) field.  FP64 and FP32 state; time
+    per cycle, the residual's mean reduction per cycle, the level where the fused bottom
+    starts, and (FP64) each level's part of the cycle."""
+    out = {}
+    for n in (384, 256):
+        dom = I.domain_box(n)
+        ba = bt.BoxArray.from_boxes(I.regular_chop(dom, 64), dom)
+        f = I.zero_mean_normal_f32(n, seed=seed)
+        h2 = (1.0 / n) ** 2
+        res = {"workload": f"{n}^3 periodic, {len(ba)} boxes of 64^3, V(2,2), 8 bottom sweeps, {cycles} cycles"}
+        for name, dt in (("f64", bt.F64), ("f32", bt.F32)):
+            phi, fm = bt.MultiFab(ba, 1, 1, dt), bt.MultiFab(ba, 1, 1, dt)
+            fm.set_val(0.0, with_ghosts=True)
+            fm.from_global(f)
+            mg = bt.Multigrid(ba, dt)
+            phi.set_val(0.0, with_ghosts=True)
+            r0 = bt.residual_norm(phi, fm, h2)
+            mg.vcycles(phi, fm, h2, 1, with_norms=False)  # warm-up
+            phi.set_val(0.0, with_ghosts=True)
+            torch.cuda.synchronize()
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            mg.vcycles(phi, fm, h2, cycles, with_norms=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / cycles
+            rn = bt.residual_norm(phi, fm, h2)
+            res[name] = {"levels": mg.nlevels, "fused_bottom_from_level": mg.bottom_level,
+                         "ms_per_vcycle": round(ms, 4), "resnorm_0": r0,
+                         f"resnorm_after_{cycles}": rn, "mean_reduction_per_cycle": (rn / r0) ** (1.0 / cycles)}
+            log(f"mg {n}^3 {name}: {mg.nlevels} levels (fused from {mg.bottom_level}), {ms:.3f} ms per V-cycle, "
+                f"residual {r0:.3e} -> {rn:.3e}")
+            if name == "f64":
+                res[name]["per_level"] = mg_levels_breakdown(bt, torch, ba, dt, h2, mg.nlevels, mg.bottom_level)
+            del phi, fm, mg
+        del f
+        out[f"{n}cube"] = res
     torch.cuda.empty_cache()
     return out
 

@@ -413,6 +413,14 @@ bl_status bl_mg_workspace_bytes(const bl_boxarray* ba, bl_dtype dtype, int32_t m
 bl_status bl_mg_create(const bl_boxarray* ba, bl_dtype dtype, int32_t max_levels, void* work_dev, size_t bytes,
                        bl_mg** out);
 bl_status bl_mg_levels(const bl_mg* mg, int32_t* nlevels);
+/*
+ * First level of the hierarchy's fused bottom, or -1: from that level down,
+ * every level covers a fully periodic domain and all of them fit one
+ * workgroup's LDS (phi and f of each; 160 KiB on MI355X), and bl_mg_vcycles runs that part
+ * of each cycle as one launch (the same arithmetic as the level-by-level
+ * passes, so the same bits).
+ */
+bl_status bl_mg_bottom_level(const bl_mg* mg, int32_t* level);
 void bl_mg_destroy(bl_mg* mg);
 
 /*

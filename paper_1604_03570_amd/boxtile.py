@@ -103,6 +103,7 @@ _SIGS = {
     "bl_mg_workspace_bytes": [_vp, _i32, _i32, _szp, _i32p],
     "bl_mg_create": [_vp, _i32, _i32, _vp, ctypes.c_size_t, _vpp],
     "bl_mg_levels": [_vp, _i32p],
+    "bl_mg_bottom_level": [_vp, _i32p],
     "bl_mg_vcycles": [_vp, _vp, _vp, ctypes.c_double, _i32, _i32, _i32, _i32, _dp, _vp],
     "bl_static_partition": [_i32, _i32, _i32p],
 }
@@ -581,6 +582,9 @@ class Multigrid:
                                self.workspace.numel() - pad, ctypes.byref(h)))
         self._h = h
         self.nlevels = nl.value
+        bl_ = ctypes.c_int32()
+        _check(_L.bl_mg_bottom_level(h, ctypes.byref(bl_)))
+        self.bottom_level = bl_.value  # first level solved in one workgroup, -1: none
 
     def vcycles(self, phi: MultiFab, f: MultiFab, h2: float, ncycles: int, nu1: int = 2, nu2: int = 2,
                 nu_bottom: int = 8, with_norms: bool = True, stream=None):

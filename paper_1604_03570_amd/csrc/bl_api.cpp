@@ -863,6 +863,8 @@ bl_status bl_mg_prolong_add(bl_multifab* phi, const bl_multifab* pc, hipStream_t
 struct bl_mg {
   uint64_t ba_uid = 0;
   int dtype = 0;
+  int bottom = -1;     // first level of the fused bottom (levels bottom.. in one workgroup), -1: none
+  bl::MgBottom mb{};   // its levels' extents, corners and LDS offsets
   std::vector<bl_boxarray*> ba;     // levels 1..: owned coarse BoxArrays (ba[0] unused)
   std::vector<bl_multifab*> phi, f; // levels 1..: in the caller's workspace (index 0 unused)
   ~bl_mg() {
@@ -905,6 +907,17 @@ static bl_status mg_levels(const bl_boxarray* ba, int max_levels, std::vector<bl
 }
 
 static size_t mg_round(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// A level's boxes cover its whole domain, which is periodic on every axis: its
+// FillBoundary is then the periodic wrap of a dense array's index.
+static bool covers_periodic_domain(const bl_boxarray* ba) {
+  for (int d = 0; d < 3; ++d)
+    if (!ba->periodic[d]) return false;
+  int64_t v = 0;
+  for (const Box& b : ba->boxes) v += b.volume();
+  return v == ba->domain.volume();  // the boxes are disjoint and inside the domain
+}
+static void mg_plan_bottom(const bl_boxarray* ba0, bl_mg* mg);
 }  // namespace bl
 
 extern "C" {
@@ -963,7 +976,15 @@ bl_status bl_mg_create(const bl_boxarray* ba, bl_dtype dtype, int32_t max_levels
     mg->f.push_back(q);
     w += 2 * b;
   }
+  mg_plan_bottom(ba, mg.get());
   *out = mg.release();
+  return BL_OK;
+}
+
+bl_status bl_mg_bottom_level(const bl_mg* mg, int32_t* level) {
+  clear_error();
+  if (!mg || !level) return fail(BL_EINVAL, "NULL argument");
+  *level = mg->bottom;
   return BL_OK;
 }
 
@@ -979,10 +1000,45 @@ void bl_mg_destroy(bl_mg* mg) { delete mg; }
 }  // extern "C"
 
 namespace bl {
+// The fused bottom: the finest level L from which every level covers a fully
+// periodic domain and all of L.. fit one workgroup's LDS (phi and f of each).
+static void mg_plan_bottom(const bl_boxarray* ba0, bl_mg* mg) {
+  const int nl = (int)mg->ba.size();
+  const int esize = mg->dtype == BL_F64 ? 8 : 4;
+  const size_t limit = mg_bottom_lds_limit();
+  mg->bottom = -1;
+  size_t need = 0;
+  for (int l = nl - 1; l >= 0; --l) {
+    const bl_boxarray* ba = l == 0 ? ba0 : mg->ba[l];
+    if (!covers_periodic_domain(ba) || nl - l > kMgBottomMaxLevels) break;
+    need += 2 * (size_t)ba->domain.volume() * esize;
+    if (need > limit) break;
+    mg->bottom = l;
+  }
+  if (mg->bottom < 0) return;
+  MgBottom& m = mg->mb;
+  m.nlev = nl - mg->bottom;
+  int off = 0;
+  for (int i = 0; i < m.nlev; ++i) {
+    const int l = mg->bottom + i;
+    const bl_boxarray* ba = l == 0 ? ba0 : mg->ba[l];
+    for (int d = 0; d < 3; ++d) {
+      m.n[i][d] = ba->domain.len(d);
+      m.lo[i][d] = ba->domain.lo[d];
+    }
+    m.off[i] = off;
+    off += 2 * (int)ba->domain.volume();
+  }
+}
+
 // One V-cycle from level l (phi, f the level's MultiFabs, h2 its spacing squared).
 static bl_status vcycle(bl_mg* mg, size_t l, bl_multifab* phi, const bl_multifab* f, double h2, int nu1, int nu2,
                         int nu_bottom, hipStream_t stream) {
   const Plan& p = *phi->plan;
+  if ((int)l == mg->bottom && p.dcellpre) {  // this level and every coarser one in one workgroup
+    BL_HIP(launch_mg_bottom(p, phi->data, f->data, mg->mb, h2, l == 0 ? 1 : 0, nu1, nu2, nu_bottom, stream));
+    return BL_OK;
+  }
   if (l + 1 == mg->ba.size()) {
     BL_HIP(gsrb_smooth(p, phi->data, f->data, h2, nu_bottom, stream));
     return BL_OK;
@@ -992,7 +1048,8 @@ static bl_status vcycle(bl_mg* mg, size_t l, bl_multifab* phi, const bl_multifab
   bl_multifab* fc = mg->f[l + 1];
   BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
   BL_HIP(launch_restrict_residual(p, *fc->plan, phi->data, f->data, fc->data, h2, stream));
-  BL_HIP(launch_set_val(*pc->plan, pc->data, 0.0, 0, 1, 1, 256, stream));
+  // the coarse level starts from 0 (the fused bottom sets it itself)
+  if ((int)(l + 1) != mg->bottom) BL_HIP(launch_set_val(*pc->plan, pc->data, 0.0, 0, 1, 1, 256, stream));
   bl_status st = vcycle(mg, l + 1, pc, fc, 4.0 * h2, nu1, nu2, nu_bottom, stream);
   if (st != BL_OK) return st;
   BL_HIP(launch_prolong_add(p, *pc->plan, phi->data, pc->data, stream));

@@ -132,8 +132,10 @@ __device__ __forceinline__ T gsrb_cell(T xm, T xp, T ym, T yp, T zm, T zp, T fv,
 // only L2 reuse between neighbouring tiles matters: it keeps one contiguous
 // eighth per XCD (one 128^3 box: 236 against 195 GCell/s chunked).  Past the
 // last whole round of chunks, workgroups keep their numbers.  Bijective on
-// [0, gridDim.x).
-constexpr int kXcdChunk = 16;
+// [0, gridDim.x).  Chunks of 8 tiles since tiles take two z steps (16 tiles of
+// one step before: the same planes per chunk); 8, 16, 32 measured 2.010, 2.031,
+// 2.024 ms per step on the 512^3 uneven level.
+constexpr int kXcdChunk = 8;
 constexpr int kXcdChunkedFrom = 4096;
 __device__ __forceinline__ int logical_block() {
   const int G = gridDim.x;
@@ -1100,6 +1102,155 @@ __global__ void __launch_bounds__(256)
     o.v[0] = w[k].v[0] + v[k];
     o.v[1] = w[k].v[1] + v[k];
     stv<T, 2>(phi + at[k], o);
+  }
+}
+
+// ---------------------------------------------------------------- multigrid bottom in one workgroup
+// The coarse levels of a V-cycle where every level covers a fully periodic
+// domain: each level is a dense periodic array in LDS (phi, then f), so a
+// FillBoundary is the periodic wrap of the index and every pass is one
+// barrier, not a launch.  The arithmetic is the launched passes' own: the GSRB
+// cell update in T, the residual in FP64 from promoted values summed over the 8
+// children in the order z, y, x (lower first) and times 1/8, piecewise constant
+// prolongation in T.
+struct MgLevelView {
+  int nx, ny, nz, lo0, lo1, lo2;
+  int off;
+};
+
+__device__ __forceinline__ MgLevelView mg_level(const MgBottom& m, int l) {
+  MgLevelView v;
+  v.nx = m.n[l][0];
+  v.ny = m.n[l][1];
+  v.nz = m.n[l][2];
+  v.lo0 = m.lo[l][0];
+  v.lo1 = m.lo[l][1];
+  v.lo2 = m.lo[l][2];
+  v.off = m.off[l];
+  return v;
+}
+
+// nsweeps red-black sweeps (red = even global i+j+k first) of level v in LDS
+template <typename T>
+__device__ void mg_lds_smooth(T* lds, const MgLevelView& v, double h2, int nsweeps) {
+  const int N = v.nx * v.ny * v.nz;
+  T* phi = lds + v.off;
+  const T* f = phi + N;
+  const T h2t = (T)h2, inv6 = (T)(1.0 / 6.0);
+  for (int s = 0; s < nsweeps; ++s)
+    for (int color = 0; color < 2; ++color) {
+      for (int q = (int)threadIdx.x; q < N; q += (int)blockDim.x) {
+        const int i = q % v.nx, t = q / v.nx, j = t % v.ny, k = t / v.ny;
+        if (((v.lo0 + i + v.lo1 + j + v.lo2 + k) & 1) != color) continue;
+        const int im = i == 0 ? v.nx - 1 : i - 1, ip = i == v.nx - 1 ? 0 : i + 1;
+        const int jm = j == 0 ? v.ny - 1 : j - 1, jp = j == v.ny - 1 ? 0 : j + 1;
+        const int km = k == 0 ? v.nz - 1 : k - 1, kp = k == v.nz - 1 ? 0 : k + 1;
+        const int row = k * v.ny, pl = v.nx;
+        phi[q] = gsrb_cell(phi[(row + j) * pl + im], phi[(row + j) * pl + ip], phi[(row + jm) * pl + i],
+                           phi[(row + jp) * pl + i], phi[(km * v.ny + j) * pl + i], phi[(kp * v.ny + j) * pl + i],
+                           f[q], h2t, inv6);
+      }
+      __syncthreads();
+    }
+}
+
+// f of level c = the restriction of the residual f + L_h phi of level v
+template <typename T>
+__device__ void mg_lds_restrict(T* lds, const MgLevelView& v, const MgLevelView& c, double h2) {
+  const int N = v.nx * v.ny * v.nz, Nc = c.nx * c.ny * c.nz;
+  const T* phi = lds + v.off;
+  const T* f = phi + N;
+  T* fc = lds + c.off + Nc;
+  for (int q = (int)threadIdx.x; q < Nc; q += (int)blockDim.x) {
+    const int I = q % c.nx, t = q / c.nx, J = t % c.ny, K = t / c.ny;
+    double acc = 0.0;
+    for (int cz = 0; cz < 2; ++cz)
+      for (int by = 0; by < 2; ++by)
+        for (int ax = 0; ax < 2; ++ax) {
+          const int i = 2 * I + ax, j = 2 * J + by, k = 2 * K + cz;
+          const int im = i == 0 ? v.nx - 1 : i - 1, ip = i == v.nx - 1 ? 0 : i + 1;
+          const int jm = j == 0 ? v.ny - 1 : j - 1, jp = j == v.ny - 1 ? 0 : j + 1;
+          const int km = k == 0 ? v.nz - 1 : k - 1, kp = k == v.nz - 1 ? 0 : k + 1;
+          const int at = (k * v.ny + j) * v.nx + i;
+          const double xm = (double)phi[(k * v.ny + j) * v.nx + im], xp = (double)phi[(k * v.ny + j) * v.nx + ip];
+          const double ym = (double)phi[(k * v.ny + jm) * v.nx + i], yp = (double)phi[(k * v.ny + jp) * v.nx + i];
+          const double zm = (double)phi[(km * v.ny + j) * v.nx + i], zp = (double)phi[(kp * v.ny + j) * v.nx + i];
+          const double sv = ((xm + xp) + (ym + yp)) + (zm + zp);
+          const double r = (double)f[at] + (sv - 6.0 * (double)phi[at]) / h2;
+          acc = (cz == 0 && by == 0 && ax == 0) ? r : acc + r;
+        }
+    fc[q] = (T)(acc * 0.125);
+  }
+  T* pc = lds + c.off;
+  for (int q = (int)threadIdx.x; q < Nc; q += (int)blockDim.x) pc[q] = (T)0;
+  __syncthreads();
+}
+
+// phi of level v += phi of level c at each cell's parent
+template <typename T>
+__device__ void mg_lds_prolong(T* lds, const MgLevelView& v, const MgLevelView& c) {
+  const int N = v.nx * v.ny * v.nz;
+  T* phi = lds + v.off;
+  const T* pc = lds + c.off;
+  for (int q = (int)threadIdx.x; q < N; q += (int)blockDim.x) {
+    const int i = q % v.nx, t = q / v.nx, j = t % v.ny, k = t / v.ny;
+    phi[q] = phi[q] + pc[((k >> 1) * c.ny + (j >> 1)) * c.nx + (i >> 1)];
+  }
+  __syncthreads();
+}
+
+// Valid cell g of the level (its flattened index, boxes in order; cpre[b] = the
+// first cell of box b): its element in the MultiFab and its dense index.
+__device__ __forceinline__ void mg_cell(const DevBox* __restrict__ boxes, const int32_t* __restrict__ cpre, int nbox,
+                                        const MgLevelView& top, int g, int64_t& at, int& dense) {
+  const int b = box_of_item(cpre, 0, nbox - 1, g);
+  const DevBox& B = boxes[b];
+  const int q = g - cpre[b];
+  const int i = q % B.ex, t = q / B.ex, j = t % B.ey, k = t / B.ey;
+  dense = ((B.glo[2] + k - top.lo2) * top.ny + (B.glo[1] + j - top.lo1)) * top.nx + (B.glo[0] + i - top.lo0);
+  at = B.off + i + (int64_t)j * B.sy + (int64_t)k * B.sz;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_mg_bottom(const DevBox* __restrict__ boxes, const int32_t* __restrict__ cpre, int nbox, T* phi_, const T* f_,
+                MgBottom m, double h2, int load_phi, int nu1, int nu2, int nub) {
+  extern __shared__ unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  BL_GLOBAL T* phiL = as_global(phi_);
+  const BL_GLOBAL T* fL = as_global(f_);
+  const MgLevelView top = mg_level(m, 0);
+  const int N0 = top.nx * top.ny * top.nz;  // the boxes cover the domain: N0 valid cells
+  // level L's valid cells into the dense arrays, every lane its own cells of any box
+  for (int g = (int)threadIdx.x; g < N0; g += (int)blockDim.x) {
+    int64_t a;
+    int d;
+    mg_cell(boxes, cpre, nbox, top, g, a, d);
+    lds[top.off + N0 + d] = fL[a];
+    lds[top.off + d] = load_phi ? phiL[a] : (T)0;
+  }
+  __syncthreads();
+  // down: nu1 sweeps and restriction on every level but the coarsest
+  double h = h2;
+  for (int l = 0; l + 1 < m.nlev; ++l) {
+    const MgLevelView v = mg_level(m, l), c = mg_level(m, l + 1);
+    mg_lds_smooth<T>(lds, v, h, nu1);
+    mg_lds_restrict<T>(lds, v, c, h);
+    h *= 4.0;
+  }
+  mg_lds_smooth<T>(lds, mg_level(m, m.nlev - 1), h, nub);
+  // up: prolongation and nu2 sweeps
+  for (int l = m.nlev - 2; l >= 0; --l) {
+    h *= 0.25;
+    const MgLevelView v = mg_level(m, l), c = mg_level(m, l + 1);
+    mg_lds_prolong<T>(lds, v, c);
+    mg_lds_smooth<T>(lds, v, h, nu2);
+  }
+  for (int g = (int)threadIdx.x; g < N0; g += (int)blockDim.x) {
+    int64_t a;
+    int d;
+    mg_cell(boxes, cpre, nbox, top, g, a, d);
+    phiL[a] = lds[top.off + d];
   }
 }
 
@@ -2149,6 +2300,41 @@ hipError_t launch_prolong_add(const Plan& fine, const Plan& coarse, void* phi, c
   else
     hipLaunchKernelGGL(k_prolong_add<float>, dim3(g), dim3(256), 0, s, fine.dpairpre, fine.dpairwg, nb, total,
                        fine.dboxes, coarse.dboxes, (float*)phi, (const float*)pc);
+  return hipGetLastError();
+}
+
+size_t mg_bottom_lds(const MgBottom& m, int esize) {
+  size_t n = 0;
+  for (int l = 0; l < m.nlev; ++l) n += 2 * (size_t)m.n[l][0] * m.n[l][1] * m.n[l][2];
+  return n * (size_t)esize;
+}
+
+size_t mg_bottom_lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+    return 65536;
+  return (size_t)v < kMgBottomLds ? (size_t)v : kMgBottomLds;
+}
+
+hipError_t launch_mg_bottom(const Plan& pl, void* phi, const void* f, const MgBottom& m, double h2, int load_phi,
+                            int nu1, int nu2, int nu_bottom, hipStream_t s) {
+  const int nb = (int)pl.hboxes.size();
+  const size_t lds = mg_bottom_lds(m, pl.esize);
+  if (lds > 65536) {  // more than the default dynamic LDS of a launch
+    hipError_t e = pl.dtype == BL_F64
+                       ? hipFuncSetAttribute((const void*)k_mg_bottom<double>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                       : hipFuncSetAttribute((const void*)k_mg_bottom<float>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (pl.dtype == BL_F64)
+    hipLaunchKernelGGL(k_mg_bottom<double>, dim3(1), dim3(1024), lds, s, pl.dboxes, pl.dcellpre, nb, (double*)phi,
+                       (const double*)f, m, h2, load_phi, nu1, nu2, nu_bottom);
+  else
+    hipLaunchKernelGGL(k_mg_bottom<float>, dim3(1), dim3(1024), lds, s, pl.dboxes, pl.dcellpre, nb, (float*)phi,
+                       (const float*)f, m, h2, load_phi, nu1, nu2, nu_bottom);
   return hipGetLastError();
 }
 

@@ -64,6 +64,26 @@ hipError_t launch_reduce_noalloc(const Plan& p, const void* data, int comp, int 
 
 hipError_t launch_gsrb(const Plan& p, void* phi, const void* f, double h2, int color, int block, hipStream_t s);
 
+// The bottom of a V-cycle in one workgroup: levels L..L+nlev-1 of a hierarchy
+// whose levels from L down each cover a fully periodic domain, held as dense
+// periodic arrays in LDS (phi and f of every level).  Takes f of level L from
+// its MultiFab (and phi if load_phi, else phi = 0), runs the cycle's part from
+// level L down and back (nu1 sweeps, restriction, ..., nu_bottom sweeps on the
+// coarsest, ..., prolongation, nu2 sweeps) and stores phi's valid cells of
+// level L.  h2 is level L's spacing squared (times 4 per level below).
+constexpr int kMgBottomMaxLevels = 16;
+constexpr size_t kMgBottomLds = 163840;  // at most; the device's per-workgroup LDS if smaller
+size_t mg_bottom_lds_limit();
+struct MgBottom {
+  int nlev;
+  int n[kMgBottomMaxLevels][3];   // domain extents per level
+  int lo[kMgBottomMaxLevels][3];  // domain lower corners
+  int off[kMgBottomMaxLevels];    // LDS element offset of phi (f follows it)
+};
+size_t mg_bottom_lds(const MgBottom& m, int esize);
+hipError_t launch_mg_bottom(const Plan& pl, void* phi, const void* f, const MgBottom& m, double h2, int load_phi,
+                            int nu1, int nu2, int nu_bottom, hipStream_t s);
+
 // ||f + L_h phi||_2 in FP64 into *out (device); reads phi's ghosts (fill first).
 hipError_t launch_residual(const Plan& p, const void* phi, const void* f, double h2, double* partials, double* out,
                            int block, hipStream_t s);

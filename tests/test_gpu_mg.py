@@ -196,3 +196,31 @@ def test_repeated_vcycle_calls_on_one_hierarchy(bt):
         mg.vcycles(P["phi"], P["f"], hh, cycles, nu1, nu2, nub, with_norms=(cycles == 2))
         O.mg_vcycles(P["ophi"], P["of"], hh, cycles, nu1, nu2, nub)
         assert np.array_equal(gpu_global(P["phi"]), P["ophi"].to_global()), (cycles, nu1, nu2, nub)
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+@pytest.mark.parametrize("layout,expect", [("uneven64", "coarse"), ("cells32", "coarse"), ("tiny", 0),
+                                           ("holes_mixed", -1)])
+def test_fused_bottom_equals_the_oracle(bt, layout, dtype_name, expect):
+    """Where every level from some level down covers a fully periodic domain and fits one
+    workgroup's LDS, that bottom of the cycle runs as one launch (dense periodic arrays in
+    LDS); from level 0 itself on the tiny grid.  FP64: the oracle's bits and norms to
+    1e-13 over 3 cycles with other sweep counts too; FP32: within 1e-5.  Layouts with holes
+    or a non-periodic axis keep the level-by-level passes."""
+    dtype = bt.F64 if dtype_name == "f64" else bt.F32
+    P = _problem(bt, layout, dtype, seed=5)
+    mg = bt.Multigrid(P["ba"], dtype)
+    say(f"fused bottom layout={layout} {dtype_name}: levels {mg.nlevels}, bottom {mg.bottom_level}")
+    if expect == "coarse":
+        assert 0 < mg.bottom_level < mg.nlevels
+    else:
+        assert mg.bottom_level == expect
+    for ncyc, nu1, nu2, nub in ((2, 2, 2, 8), (1, 1, 3, 5)):
+        n = mg.vcycles(P["phi"], P["f"], P["h2"], ncyc, nu1, nu2, nub)
+        on = O.mg_vcycles(P["ophi"], P["of"], P["h2"], ncyc, nu1, nu2, nub)
+        got, ref = gpu_global(P["phi"]), P["ophi"].to_global()
+        if dtype == bt.F64:
+            assert np.array_equal(got, ref, equal_nan=True)
+            assert all(abs(a - b) <= 1e-13 * b for a, b in zip(n, on))
+        else:
+            assert rel_err(got, ref) <= 1e-5
