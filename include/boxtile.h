@@ -364,9 +364,40 @@ bl_status bl_heat_step_unfused(bl_multifab* u_old, bl_multifab* u_new, double c,
  * is synchronised once at the end).  phi and f share BoxArray, dtype and
  * nghost >= 1.  Every periodic axis needs an even extent (else BL_EINVAL:
  * the colouring would not match across the wrap).
+ *
+ * Where it applies (bl_gsrb_one_pass_applies), each sweep is one pass over
+ * the level: FillBoundary, then the new red values of the face ghost cells
+ * computed from the neighbouring boxes, then one launch that computes each
+ * box's red values a plane ahead of its black ones, into a second state
+ * buffer of phi's size (allocated on first use and kept with phi; phi holds
+ * the result when the call returns).  The cell values are those of the
+ * two-pass form to the bit; phi's ghost cells that a box covers are left
+ * with unspecified values (the two-pass form leaves them as they were), those
+ * no box covers keep theirs.  Writes f's edge mirror if it is not current.
  */
 bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int32_t nsweeps,
                          double* resnorm_host, hipStream_t stream);
+
+/*
+ * Configuration of bl_gsrb_sweeps (process-wide): one_pass = 1 (default)
+ * takes the one-pass sweep where it applies, 0 always the two colour passes;
+ * zchunk (>= 1, default 32): planes of one box per workgroup of the one-pass
+ * sweep; vectors_per_lane: 16-byte plane vectors per lane (1 or 2; 0, the
+ * default: 1 for planes of at most 512 vectors, else 2).  BL_EINVAL for
+ * other values.
+ */
+bl_status bl_set_gsrb_config(int32_t one_pass, int32_t zchunk, int32_t vectors_per_lane);
+bl_status bl_get_gsrb_config(int32_t* one_pass, int32_t* zchunk, int32_t* vectors_per_lane);
+
+/*
+ * *applies = 1 if bl_gsrb_sweeps on phi takes the one-pass sweep under the
+ * current configuration: every box's x extent a whole number of 16-byte
+ * vectors (vec = 4 FP32 or 2 FP64 values), planes of at most 1024 lanes'
+ * vectors, at least as many lanes as ghost items around a plane (2*ex/vec
+ * ghost-row vectors + 2*ey x ghost values), three plane buffers within one
+ * workgroup's LDS (160 KiB on MI355X).  Otherwise 0.
+ */
+bl_status bl_gsrb_one_pass_applies(const bl_multifab* phi, int32_t* applies);
 
 /* ||f + L_h phi||_2 over valid cells in FP64 (fills phi's ghosts first); synchronises. */
 bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, double* out_host,

@@ -83,6 +83,9 @@ _SIGS = {
     "bl_reduce_async": [_vp, _i32, _i32, _vp, _vp],
     "bl_reduce_async_noalloc": [_vp, _i32, _i32, _vp, _vp],
     "bl_set_tile_config": [_i32, _i32, _i32, _i32, _i32],
+    "bl_set_gsrb_config": [_i32, _i32, _i32],
+    "bl_get_gsrb_config": [_i32p, _i32p, _i32p],
+    "bl_gsrb_one_pass_applies": [_vp, _i32p],
     "bl_autotune": [_vp, _vp, _vp, ctypes.c_double, _i32, _i32, _i32p, _i32p, ctypes.POINTER(ctypes.c_float), _i32p,
                     _vp],
     "bl_get_tile_config": [_i32p, _i32p, _i32p, _i32p, _i32p],
@@ -609,6 +612,24 @@ def gsrb_sweeps(phi: MultiFab, f: MultiFab, h2: float, nsweeps: int, with_norms:
     norms = (ctypes.c_double * max(1, nsweeps))() if with_norms else None
     _check(_L.bl_gsrb_sweeps(phi.handle, f.handle, float(h2), int(nsweeps), norms, _stream(stream)))
     return list(norms)[:nsweeps] if with_norms else None
+
+
+def set_gsrb_config(one_pass: int = 1, zchunk: int = 32, vectors_per_lane: int = 0) -> None:
+    """Form of gsrb_sweeps: the one-pass sweep where it applies (one_pass=1) or the
+    two colour passes; planes per workgroup and vectors per lane of the one-pass sweep."""
+    _check(_L.bl_set_gsrb_config(int(one_pass), int(zchunk), int(vectors_per_lane)))
+
+
+def get_gsrb_config():
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_L.bl_get_gsrb_config(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def gsrb_one_pass_applies(phi: MultiFab) -> bool:
+    out = ctypes.c_int32()
+    _check(_L.bl_gsrb_one_pass_applies(phi.handle, ctypes.byref(out)))
+    return bool(out.value)
 
 
 def residual_norm(phi: MultiFab, f: MultiFab, h2: float, stream=None) -> float:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -39,6 +40,11 @@ Plan::~Plan() {
   (void)hipFree(dh8face);
   (void)hipFree(dcellwg);
   (void)hipFree(dpairwg);
+  (void)hipFree(dringrecs);
+  (void)hipFree(dpushrecs);
+  (void)hipFree(dpushface);
+  (void)hipFree(dmir2off);
+  (void)hipFree(dsweep);
 }
 
 template <typename T>
@@ -69,6 +75,10 @@ bl_status upload_plan(Plan& p) {
   if ((st = upload(&p.dpairpre, p.hpairpre, "hipMalloc/hipMemcpy(pair counts)")) != BL_OK) return st;
   if ((st = upload(&p.dcellwg, p.hcellwg, "hipMalloc/hipMemcpy(cell workgroups)")) != BL_OK) return st;
   if ((st = upload(&p.dpairwg, p.hpairwg, "hipMalloc/hipMemcpy(pair workgroups)")) != BL_OK) return st;
+  if ((st = upload(&p.dringrecs, p.hringrecs, "hipMalloc/hipMemcpy(ring records)")) != BL_OK) return st;
+  if ((st = upload(&p.dpushrecs, p.hpushrecs, "hipMalloc/hipMemcpy(push records)")) != BL_OK) return st;
+  if ((st = upload(&p.dpushface, p.hpushface, "hipMalloc/hipMemcpy(push faces)")) != BL_OK) return st;
+  if ((st = upload(&p.dmir2off, p.hmir2off, "hipMalloc/hipMemcpy(inner mirror offsets)")) != BL_OK) return st;
   p.uploaded = true;
   return BL_OK;
 }
@@ -209,6 +219,8 @@ using namespace bl;
 
 bl_multifab::~bl_multifab() {
   forget_graphs(this);
+  (void)hipFree(dtwin);
+  (void)hipFree(dmir2);
   (void)hipFree(dscratch);
   (void)hipHostFree(hres);
 }
@@ -693,6 +705,23 @@ static bl_status check_gsrb(bl_multifab* phi, const bl_multifab* f) {
   return BL_OK;
 }
 
+// ||f + L_h phi||_2 into dout (device): the fused read-only pass where the plan
+// allows it (neighbour values straight from the neighbour boxes), else
+// FillBoundary and the residual kernel.  partials: reduce_slots(p) doubles.
+static hipError_t residual_norm_dev(const Plan& p, bl_multifab* phi, const bl_multifab* f, double h2,
+                                    double* partials, double* dout, hipStream_t stream) {
+  hipError_t e;
+  const int grid = persistent_grid(tile_config().persist);
+  if (gsrb_fused_ok(p, block_of(p))) {
+    e = launch_gsrb_fused(p, phi->data, f->data, h2, -1, 2, partials, grid, block_of(p), stream, !phi->mirror_current);
+    if (e != hipSuccess) return e;
+    return launch_reduce_partials(partials, gsrb_fused_grid(p, grid), 1, dout, stream);
+  }
+  e = launch_fill(p, phi->data, 0, 1, stream, phi->mirror_current);
+  if (e != hipSuccess) return e;
+  return launch_residual(p, phi->data, f->data, h2, partials, dout, block_of(p), stream);
+}
+
 bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, double* out_host, hipStream_t stream) {
   clear_error();
   bl_status st = check_gsrb(phi, f);
@@ -701,15 +730,7 @@ bl_status bl_residual_norm(bl_multifab* phi, const bl_multifab* f, double h2, do
   const Plan& p = *phi->plan;
   if ((st = ensure_scratch(phi, reduce_slots(p) + 8, 8)) != BL_OK) return st;
   double* dout = phi->dscratch + reduce_slots(p);
-  const int grid = persistent_grid(tile_config().persist);
-  if (gsrb_fused_ok(p, block_of(p))) {  // neighbour values straight from the neighbour boxes
-    BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, -1, 2, phi->dscratch, grid, block_of(p), stream,
-                             !phi->mirror_current));
-    BL_HIP(launch_reduce_partials(phi->dscratch, gsrb_fused_grid(p, grid), 1, dout, stream));
-  } else {
-    BL_HIP(launch_fill(p, phi->data, 0, 1, stream, phi->mirror_current));
-    BL_HIP(launch_residual(p, phi->data, f->data, h2, phi->dscratch, dout, block_of(p), stream));
-  }
+  BL_HIP(residual_norm_dev(p, phi, f, h2, phi->dscratch, dout, stream));
   BL_HIP(hipMemcpyAsync(phi->hres, dout, sizeof(double), hipMemcpyDeviceToHost, stream));
   BL_HIP(hipStreamSynchronize(stream));
   *out_host = phi->hres[0];
@@ -753,12 +774,133 @@ static hipError_t residual_norm_dev(const Plan& p, void* phi, const void* f, dou
   return launch_residual(p, phi, f, h2, partials, out, block_of(p), stream);
 }
 
+// The red-black sweep's form: the one-pass sweep where it applies (default) or
+// always the two colour passes; planes per workgroup and vectors per lane (0:
+// chosen from the largest plane) of the one-pass sweep.
+static std::atomic<int> g_gsrb_one_pass{1}, g_gsrb_zchunk{32}, g_gsrb_vpl{0};
+
+// The one-pass sweep's work chunks for the current configuration; false if
+// some box does not fit it: an x extent that is not a whole number of 16-byte
+// vectors, planes of more than 1024 lanes' vectors, more ghost items per plane
+// (two ghost rows of vectors, two columns of values) than lanes, or three
+// plane buffers beyond one workgroup's LDS.
+static bool gsrb1_plan(Plan& p) {
+  std::lock_guard<std::mutex> lk(g_vc_mu);
+  const int zc = g_gsrb_zchunk.load(), want_k = g_gsrb_vpl.load();
+  if (p.sweep_req_zc == zc && p.sweep_req_k == want_k) return p.sweep_ok != 0;
+  p.sweep_req_zc = zc;
+  p.sweep_req_k = want_k;
+  p.sweep_ok = 0;
+  const int V = 16 / p.esize;
+  int pmax = 0;
+  for (const Box& b : p.boxes) {
+    if (b.len(0) % V) return false;
+    pmax = std::max(pmax, b.len(1) * (b.len(0) / V));
+  }
+  if (pmax == 0) return false;
+  const int k = want_k > 0 ? want_k : (pmax <= 512 ? 1 : 2);
+  if (k != 1 && k != 2) return false;
+  const int block = ((pmax + k - 1) / k + 63) / 64 * 64;
+  if (block > 1024) return false;
+  size_t lds = 0;
+  for (const Box& b : p.boxes) {
+    if (2 * (b.len(0) / V) + 2 * b.len(1) > block) return false;
+    lds = std::max(lds, gsrb_sweep_lds(b.len(0), b.len(1), V, p.esize));
+  }
+  if (lds > mg_bottom_lds_limit()) return false;
+  // chunks of zc planes; the chunks of 8 boxes at a time dealt out so that a
+  // box's chunks run on one XCD (workgroups go to the XCDs in turn) and share
+  // its L2 for the planes where they overlap
+  std::vector<DevRedChunk> w;
+  const int nb = (int)p.boxes.size();
+  for (int g0 = 0; g0 < nb; g0 += 8) {
+    const int g1 = std::min(nb, g0 + 8);
+    int maxc = 0;
+    for (int b = g0; b < g1; ++b) maxc = std::max(maxc, (p.boxes[b].len(2) + zc - 1) / zc);
+    for (int j = 0; j < maxc; ++j)
+      for (int b = g0; b < g1; ++b) {
+        const int ez = p.boxes[b].len(2);
+        if (j * zc < ez) w.push_back(DevRedChunk{b, j * zc, std::min(ez, (j + 1) * zc), 0});
+      }
+  }
+  (void)hipFree(p.dsweep);
+  p.dsweep = nullptr;
+  if (upload(&p.dsweep, w, "hipMalloc/hipMemcpy(sweep chunks)") != BL_OK) return false;
+  p.hsweep.swap(w);
+  p.sweep_zc = zc;
+  p.sweep_k = k;
+  p.sweep_block = block;
+  p.sweep_lds = lds;
+  p.sweep_ok = 1;
+  return true;
+}
+
+// nsweeps sweeps in one pass each, ping-ponging between phi and a second buffer
+// of its layout (copied back after an odd count).  FillBoundary of phi once;
+// per sweep the ring kernel (new red values into the face ghosts), then the
+// sweep into the other buffer, which also writes both its edge copies and fills
+// its face ghosts.  Norms: the black part of sweep s plus the red part of sweep
+// s+1; after the last sweep, the residual norm of the result.
+static bl_status gsrb_one_pass(Plan& p, bl_multifab* phi, const bl_multifab* f, double h2, int nsweeps,
+                               double* resnorm_host, hipStream_t stream) {
+  bool fresh = false;
+  if (!phi->dtwin) {
+    BL_HIP(hipMalloc(&phi->dtwin, phi->bytes));
+    fresh = true;
+  }
+  const size_t m2bytes = ((size_t)p.mir2_total * p.esize + 255) / 256 * 256;
+  if (!phi->dmir2) BL_HIP(hipMalloc(&phi->dmir2, 2 * m2bytes));
+  const int nw = (int)p.hsweep.size();
+  double* slots = nullptr;
+  double* norms = nullptr;
+  if (resnorm_host) {
+    bl_status st = ensure_scratch(phi, 3 * (size_t)nw + reduce_slots(p) + (size_t)nsweeps + 8, (size_t)nsweeps + 8);
+    if (st != BL_OK) return st;
+    slots = phi->dscratch;
+    norms = phi->dscratch + 3 * (size_t)nw + reduce_slots(p);
+  }
+  void* buf[2] = {phi->data, phi->dtwin};
+  void* m2[2] = {phi->dmir2, static_cast<char*>(phi->dmir2) + m2bytes};
+  BL_HIP(launch_extract_edges2(p, phi->data, m2[0], stream));
+  bl_multifab* fm = const_cast<bl_multifab*>(f);  // f's values are not changed: only its edge mirror is written
+  if (!fm->mirror_current) {
+    BL_HIP(launch_extract_mirror(p, fm->data, stream));
+    fm->mirror_current = true;
+  }
+  // ghost cells no box covers keep their values in both buffers (and a new
+  // second buffer starts as a copy, so that it holds no undefined values)
+  if (fresh || !p.faces_covered)
+    BL_HIP(hipMemcpyAsync(phi->dtwin, phi->data, phi->bytes, hipMemcpyDeviceToDevice, stream));
+  BL_HIP(launch_fill(p, phi->data, 0, 1, stream, true));
+  for (int s = 0; s < nsweeps; ++s) {
+    const int c = s & 1;
+    BL_HIP(launch_gsrb_ring(p, buf[c], f->data, m2[c], h2, stream));
+    double* red = slots && s > 0 ? slots + nw : nullptr;
+    double* black = slots ? slots + (s & 1 ? 2 * nw : 0) : nullptr;
+    BL_HIP(launch_gsrb_sweep(p, p.dsweep, nw, p.sweep_block, p.sweep_k, p.sweep_lds, buf[c], buf[c ^ 1], f->data,
+                             m2[c ^ 1], h2, red, black, stream));
+    if (slots && s > 0)
+      BL_HIP(launch_reduce_partials(slots + ((s - 1) & 1 ? nw : 0), 2 * nw, 1, norms + s - 1, stream));
+  }
+  if (nsweeps & 1) BL_HIP(hipMemcpyAsync(phi->data, phi->dtwin, phi->bytes, hipMemcpyDeviceToDevice, stream));
+  phi->mirror_current = true;
+  if (slots) {
+    BL_HIP(residual_norm_dev(p, phi, f, h2, slots + 3 * nw, norms + nsweeps - 1, stream));
+    BL_HIP(hipMemcpyAsync(phi->hres, norms, sizeof(double) * nsweeps, hipMemcpyDeviceToHost, stream));
+    BL_HIP(hipStreamSynchronize(stream));
+    std::memcpy(resnorm_host, phi->hres, sizeof(double) * nsweeps);
+  }
+  return BL_OK;
+}
+
 bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int32_t nsweeps, double* resnorm_host,
                          hipStream_t stream) {
   clear_error();
   bl_status st = check_gsrb(phi, f);
   if (st != BL_OK) return st;
   if (nsweeps < 0) return fail(BL_EINVAL, "nsweeps < 0");
+  if (nsweeps > 0 && g_gsrb_one_pass.load() && gsrb1_plan(*phi->plan))
+    return gsrb_one_pass(*phi->plan, phi, f, h2, nsweeps, resnorm_host, stream);
   const Plan& p = *phi->plan;
   const size_t nt = p.htiles.size();
   if (gsrb_fused_ok(p, block_of(p))) {
@@ -810,6 +952,32 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
     BL_HIP(hipStreamSynchronize(stream));
     std::memcpy(resnorm_host, phi->hres, sizeof(double) * nsweeps);
   }
+  return BL_OK;
+}
+
+bl_status bl_set_gsrb_config(int32_t one_pass, int32_t zchunk, int32_t vectors_per_lane) {
+  clear_error();
+  if (zchunk < 1) return fail(BL_EINVAL, "zchunk must be >= 1");
+  if (vectors_per_lane < 0 || vectors_per_lane > 2) return fail(BL_EINVAL, "vectors_per_lane must be 0, 1 or 2");
+  g_gsrb_one_pass = one_pass ? 1 : 0;
+  g_gsrb_zchunk = zchunk;
+  g_gsrb_vpl = vectors_per_lane;
+  return BL_OK;
+}
+
+bl_status bl_get_gsrb_config(int32_t* one_pass, int32_t* zchunk, int32_t* vectors_per_lane) {
+  clear_error();
+  if (!one_pass || !zchunk || !vectors_per_lane) return fail(BL_EINVAL, "NULL argument");
+  *one_pass = g_gsrb_one_pass.load();
+  *zchunk = g_gsrb_zchunk.load();
+  *vectors_per_lane = g_gsrb_vpl.load();
+  return BL_OK;
+}
+
+bl_status bl_gsrb_one_pass_applies(const bl_multifab* phi, int32_t* applies) {
+  clear_error();
+  if (!phi || !applies) return fail(BL_EINVAL, "NULL argument");
+  *applies = (g_gsrb_one_pass.load() && phi->plan->ncomp == 1 && phi->plan->ng >= 1 && gsrb1_plan(*phi->plan)) ? 1 : 0;
   return BL_OK;
 }
 

@@ -252,6 +252,34 @@ struct DevFillChunk {
   int32_t rec;
   int32_t start;     // first cell (linear x-fastest index inside the region)
 };
+// The one-pass red-black sweep: one covered part of one face ghost layer of a
+// box, whose new red values are computed from the source box's data.
+// Destination ghost cell (t1, t2) of the region (box-local coordinates of the
+// destination, the face coordinate fixed) is source box-local cell
+// (destination + d); t1 is the fastest of the face's tangential axes (y for
+// x faces, x for y and z faces).
+struct DevRingRec {
+  int32_t box, src, face;
+  int32_t lo[3];   // destination box-local cell at the region's low corner
+  int32_t n1, n2;  // region extents along t1 and t2
+  int32_t d[3];
+  int32_t pad_;
+};
+static_assert(sizeof(DevRingRec) == 48, "DevRingRec size");
+// Where the one-pass sweep writes a box's new face cells so that they land in
+// the neighbours' face ghost cells (the FillBoundary of its output, pushed by
+// the source): face cell (t1, t2) of the source box (box-local tangential
+// coordinates, t1lo..t1hi x t2lo..t2hi) goes to element base + t1*s1 + t2*s2.
+struct DevPushRec {
+  int64_t base;
+  int32_t s1, s2;
+  int32_t t1lo, t1hi, t2lo, t2hi;
+};
+static_assert(sizeof(DevPushRec) == 32, "DevPushRec size");
+struct DevPushFace {  // the push records of face f of a box: [start[f], start[f] + count[f])
+  int32_t start[6];
+  int32_t count[6];
+};
 constexpr int kFillChunk = 256;
 constexpr int kStencilMaxThreads = 256;  // workgroup size limit of the stencil kernels (waves <= 4)
 constexpr int kRestrictPerWG = 256;     // coarse cells per workgroup of the restriction (one per lane)
@@ -326,6 +354,22 @@ struct Plan {
   std::vector<DevFillRec> hfillrecs_mir;
   std::vector<DevFillChunk> hfillchunks;
   std::shared_ptr<const std::vector<FillRecord>> fill;
+  // one-pass red-black sweep: covered face parts, the same parts as push
+  // records grouped by source box and face, and each box's offset into the second edge-column copy (columns 1 and
+  // ex-2: 2*ey*ez values per box)
+  std::vector<DevRingRec> hringrecs;
+  std::vector<DevPushRec> hpushrecs;
+  std::vector<DevPushFace> hpushface;
+  std::vector<int64_t> hmir2off;
+  int64_t mir2_total = 0;
+  bool faces_covered = false;  // no box has a face ghost cell that no box covers
+  // the sweep's work chunks (box, planes), made on first use for one
+  // (planes per chunk, vectors per lane); block: lanes per workgroup
+  std::vector<DevRedChunk> hsweep;
+  DevRedChunk* dsweep = nullptr;
+  int sweep_zc = 0, sweep_k = 0, sweep_block = 0;
+  int sweep_req_zc = -1, sweep_req_k = -1, sweep_ok = 0;  // the configuration it was made for
+  size_t sweep_lds = 0;
 
   // device copies (owned), made by upload_plan
   DevBox* dboxes = nullptr;
@@ -341,6 +385,10 @@ struct Plan {
   int32_t* dpairpre = nullptr;
   int32_t* dcellwg = nullptr;
   int32_t* dpairwg = nullptr;
+  DevRingRec* dringrecs = nullptr;
+  DevPushRec* dpushrecs = nullptr;
+  DevPushFace* dpushface = nullptr;
+  int64_t* dmir2off = nullptr;
   bool uploaded = false;
   TileConfig cfg;
 
@@ -403,6 +451,10 @@ struct bl_multifab {
   // cleared by every other write (and by bl_multifab_modified for writes made
   // outside the library)
   bool mirror_current = false;
+  // the one-pass red-black sweep's second edge-column copy (columns 1 and ex-2
+  // of component 0), allocated on first use
+  void* dmir2 = nullptr;
+  void* dtwin = nullptr;  // the one-pass sweep's second state buffer (same layout)
   double* dscratch = nullptr;   // reduction partials + results (device), grown on demand
   size_t nscratch = 0;
   double* hres = nullptr;       // pinned host landing slots for scalar results

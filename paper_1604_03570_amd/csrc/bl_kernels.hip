@@ -1957,6 +1957,395 @@ hipError_t heat_dispatch(bool fused, const HeatArgs& a, int grid, int block, hip
   }
 }
 
+// ---------------------------------------------------------------- red-black sweep in one pass
+// A sweep is a red pass then a black pass; a black cell's neighbours are all
+// red and a red cell's all black, so one launch can do both if it has, for
+// every black cell, the new values of its six red neighbours.  Inside a box
+// they are computed one plane ahead; next to a face they are the neighbour
+// box's new red values at its own face cells, which the ring kernel computes
+// beforehand into the box's ghost layer, at the red positions only (the black
+// positions keep the old values that the red update of the box's own face
+// cells needs).  Both kernels evaluate every cell with gsrb_cell on the same
+// operands as the two-pass form, so FP64 results are the same bits.
+
+// Value of source box-local cell (i, j, k) of phi.  XF (the cell lies on the
+// box's low or high x column, the source of an x face): valid cells of columns
+// 0 and ex-1 from the edge mirror and of columns 1 and ex-2 from the second
+// edge-column copy m2 (2*ey*ez values: side 0 then side 1), so that a wave's
+// lanes, which run along y, read contiguous values; any other cell from the
+// FAB (rows or x ghost slab).
+template <typename T>
+__device__ __forceinline__ T ring_val(const BL_GLOBAL T* __restrict__ phi, const BL_GLOBAL T* __restrict__ m2,
+                                      const DevBox& S, int i, int j, int k, bool xf) {
+  if (xf && j >= 0 && j < S.ey && k >= 0 && k < S.ez) {
+    const int64_t yz = (int64_t)k * S.ey + j;
+    if (i == 0) return phi[S.mir + yz];
+    if (i == S.ex - 1) return phi[S.mir + S.mir_side + yz];
+    if (i == 1) return m2[yz];
+    if (i == S.ex - 2) return m2[(int64_t)S.ey * S.ez + yz];
+  }
+  return phi[cell_index(S, i, j, k)];
+}
+
+// The new red values of every covered face ghost cell, written into the ghost
+// layer at the red positions: the red update of the source box's cell, from its
+// six neighbours in the source FAB (whose face ghosts hold the old values) and
+// f.  One workgroup per record, a lane per red cell (h1 = red cells per row
+// at most, rows along t2).  Reads only black positions and writes only red
+// ones, through separate views.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_gsrb_ring(T* phi_, const T* __restrict__ f_, const DevBox* __restrict__ boxes,
+                const DevRingRec* __restrict__ recs, const T* __restrict__ mir2_,
+                const int64_t* __restrict__ mir2off, T h2, T inv6) {
+  const DevRingRec R = ldc(recs + blockIdx.x);
+  const int h1 = (R.n1 + 1) / 2, ncell = h1 * R.n2;
+  const DevBox D = ldc(boxes + R.box);
+  const DevBox S = ldc(boxes + R.src);
+  const BL_GLOBAL T* __restrict__ phi = as_global(static_cast<const T*>(phi_));
+  BL_GLOBAL T* __restrict__ out = as_global(phi_);
+  const BL_GLOBAL T* f = as_global(f_);
+  const BL_GLOBAL T* m2 = as_global(mir2_) + mir2off[R.src];
+  const int a = R.face >> 1;
+  const bool xf = a == 0;
+  const int par00 = (D.glo[0] + R.lo[0] + D.glo[1] + R.lo[1] + D.glo[2] + R.lo[2]) & 1;
+  for (int c = (int)threadIdx.x; c < ncell; c += (int)blockDim.x) {
+    const int u2 = c / h1;
+    const int u1 = 2 * (c - u2 * h1) + ((par00 + u2) & 1);  // the red cell: (par00 + u1 + u2) even
+    if (u1 >= R.n1) continue;
+    int q0 = R.lo[0], q1 = R.lo[1], q2 = R.lo[2];
+    if (a == 0) {
+      q1 += u1;
+      q2 += u2;
+    } else if (a == 1) {
+      q0 += u1;
+      q2 += u2;
+    } else {
+      q0 += u1;
+      q1 += u2;
+    }
+    const int i = q0 + R.d[0], j = q1 + R.d[1], k = q2 + R.d[2];
+    const T xm = ring_val(phi, m2, S, i - 1, j, k, xf), xp = ring_val(phi, m2, S, i + 1, j, k, xf);
+    const T ym = ring_val(phi, m2, S, i, j - 1, k, xf), yp = ring_val(phi, m2, S, i, j + 1, k, xf);
+    const T zm = ring_val(phi, m2, S, i, j, k - 1, xf), zp = ring_val(phi, m2, S, i, j, k + 1, xf);
+    const T fv =
+        xf ? f[S.mir + (i == 0 ? 0 : (int64_t)S.mir_side) + (int64_t)k * S.ey + j] : f[cell_index(S, i, j, k)];
+    out[cell_index(D, q0, q1, q2)] = gsrb_cell(xm, xp, ym, yp, zm, zp, fv, h2, inv6);
+  }
+}
+
+// Both edge-column copies of component 0: columns 0 and ex-1 into the edge
+// mirror, columns 1 and ex-2 into m2 (as read by ring_val).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_extract_edges2(T* __restrict__ data, const DevBox* __restrict__ boxes, T* __restrict__ mir2,
+                     const int64_t* __restrict__ mir2off) {
+  const DevBox B = ldc(boxes + blockIdx.x);
+  const int64_t cnt = (int64_t)B.ey * B.ez;
+  T* mir = data + B.mir;
+  T* m2 = mir2 + mir2off[blockIdx.x];
+  for (int64_t q = threadIdx.x; q < cnt; q += blockDim.x) {
+    const int y = (int)(q % B.ey), z = (int)(q / B.ey);
+    const T* r = data + B.off + (int64_t)y * B.sy + (int64_t)z * B.sz;
+    mir[q] = r[0];
+    mir[B.mir_side + q] = r[B.ex - 1];
+    m2[q] = r[1];
+    m2[cnt + q] = r[B.ex - 2];
+  }
+}
+
+// Value at x cell e of vector v, or the plane's neighbour values at the ends.
+template <typename T, int V>
+struct PlaneNbr {
+  T left, right;
+  Vec<T, V> ym, yp;
+};
+
+// In-plane neighbours of a lane's vector (row y, first cell x0) from an LDS
+// plane buffer: (ey + 2) rows of ex values (ghost row y = -1, the valid rows,
+// ghost row y = ey), then the ey low-x and ey high-x ghost values.
+template <typename T, int V>
+__device__ __forceinline__ PlaneNbr<T, V> plane_nbr(const T* pb, int ex, int ey, int nvx, int y, int xv) {
+  PlaneNbr<T, V> N;
+  const int x0 = xv * V, rowsz = (ey + 2) * ex;
+  const T* row = pb + (y + 1) * ex + x0;
+  N.ym = ldv<T, V>(row - ex);
+  N.yp = ldv<T, V>(row + ex);
+  N.left = xv > 0 ? row[-1] : pb[rowsz + y];
+  N.right = xv < nvx - 1 ? row[V] : pb[rowsz + ey + y];
+  return N;
+}
+
+// A box's new face cells into the face ghost cells of the boxes they border
+// (push records of one face of the box).  x faces: the value of cell (y, z);
+// y and z faces: the V values of x cells x0.. of row t2 (z, or y for z faces).
+template <typename T>
+__device__ __forceinline__ void push_x(BL_GLOBAL T* out, const DevPushRec* __restrict__ recs, int start, int count,
+                                       int y, int z, T v) {
+  for (int r = start; r < start + count; ++r) {
+    const DevPushRec Q = ldc(recs + r);
+    if (y >= Q.t1lo && y <= Q.t1hi && z >= Q.t2lo && z <= Q.t2hi)
+      out[Q.base + (int64_t)y * Q.s1 + (int64_t)z * Q.s2] = v;
+  }
+}
+template <typename T, int V>
+__device__ __forceinline__ void push_row(BL_GLOBAL T* out, const DevPushRec* __restrict__ recs, int start, int count,
+                                         int x0, int t2, const Vec<T, V>& o) {
+  for (int r = start; r < start + count; ++r) {
+    const DevPushRec Q = ldc(recs + r);
+    if (t2 < Q.t2lo || t2 > Q.t2hi) continue;
+    const int64_t b = Q.base + (int64_t)t2 * Q.s2;
+#pragma unroll
+    for (int e = 0; e < V; ++e)
+      if (x0 + e >= Q.t1lo && x0 + e <= Q.t1hi) out[b + x0 + e] = o.v[e];
+  }
+}
+
+// The cells of one colour in a lane's vector c (the colour of cell e is that of
+// e + q, q = 0 or 1 per lane): cells e = 2k + q, k < V/2, each solved from its
+// six neighbours (the values left and right of the vector, the vectors of the
+// rows and planes around it) and f, the other cells kept.  Operands picked by
+// selects, so a lane computes V/2 updates whatever its parity.  RES: r^2 with
+// r = f + (s - 6v)/h2 in FP64 from promoted values, v the cell's old value
+// (AFTER false) or new one (AFTER true), added to acc.
+// (The vectors come by value: a select between two elements of a vector behind
+// a reference becomes one load at a variable index, which puts the caller's
+// vectors in scratch memory.)
+template <typename T, int V, bool AFTER>
+__device__ __forceinline__ Vec<T, V> colour_update(Vec<T, V> c, T left, T right, Vec<T, V> ym, Vec<T, V> yp,
+                                                   Vec<T, V> zm, Vec<T, V> zp, Vec<T, V> fv, int q, T h2, T inv6,
+                                                   bool res, double inv_h2d, double& acc) {
+  Vec<T, V> o = c;
+  const bool s = q != 0;
+#pragma unroll
+  for (int k = 0; k < V / 2; ++k) {
+    const int e0 = 2 * k, e1 = 2 * k + 1;
+    const T own = s ? c.v[e1] : c.v[e0];
+    const T xm = s ? c.v[e0] : (e0 == 0 ? left : c.v[e0 - 1]);
+    const T xp = s ? (e1 == V - 1 ? right : c.v[e1 + 1]) : c.v[e1];
+    const T a = s ? ym.v[e1] : ym.v[e0], b = s ? yp.v[e1] : yp.v[e0];
+    const T cz = s ? zm.v[e1] : zm.v[e0], dz = s ? zp.v[e1] : zp.v[e0];
+    const T ff = s ? fv.v[e1] : fv.v[e0];
+    const T nv = gsrb_cell(xm, xp, a, b, cz, dz, ff, h2, inv6);
+    o.v[e0] = s ? c.v[e0] : nv;
+    o.v[e1] = s ? nv : c.v[e1];
+    if (res) {
+      const double sv = ((double)xm + (double)xp) + ((double)a + (double)b);
+      const double sum = sv + ((double)cz + (double)dz);
+      const double v = AFTER ? (double)nv : (double)own;
+      const double rr = (double)ff + (sum - 6.0 * v) * inv_h2d;
+      acc += rr * rr;
+    }
+  }
+  return o;
+}
+
+// One red-black sweep of the valid planes z0..z1-1 of one box per workgroup
+// (DevRedChunk), from phi into out (another buffer of the same layout).  phi's
+// face ghosts hold the old values at black positions and the new red values at
+// red positions (FillBoundary, then k_gsrb_ring).  The workgroup marches up z:
+// at plane i it computes the new red values of plane i from the old planes
+// i-1..i+1, then the new black values of plane i-1 from the red values of
+// planes i-2..i, and stores plane i-1: its cells, its four edge columns (the
+// edge mirror and the second copy) and its face cells into the face ghost
+// cells of out that they fill (push records), so that out needs no
+// FillBoundary before the next sweep.  It starts one plane below z0 and ends one
+// above z1 (red values only there); the planes outside the box are phi's
+// ghost planes as they stand.  Lane l takes plane vectors l + m*blockDim.x,
+// m < K; each plane passes through one of three LDS buffers (old values, then
+// the red values written over them in place: a cell's red update reads only
+// black cells, which keep their values), one barrier per plane; other lanes
+// read a buffer only while it holds plane i or i-1.  Plane i+2 and f of plane
+// i+1 are loaded during plane i.
+//
+// Norms (partials per workgroup, FP64 from promoted values, as the two-pass
+// form): red_part takes r^2 at the red cells of phi (the state before the
+// sweep), black_part at the black cells of the result; the sum of the black
+// part of one sweep and the red part of the next is the squared residual norm
+// of the state between them.
+template <typename T, int V, int K>
+__global__ void __launch_bounds__(1024)
+    k_gsrb_sweep(const DevBox* __restrict__ boxes, const DevRedChunk* __restrict__ work, const T* phi_, T* out_,
+                 const T* __restrict__ f_, T* omir2_, const int64_t* __restrict__ mir2off,
+                 const DevPushRec* __restrict__ push, const DevPushFace* __restrict__ pface, T h2, T inv6,
+                 double inv_h2d, double* __restrict__ red_part, double* __restrict__ black_part) {
+  using VT = Vec<T, V>;
+  extern __shared__ unsigned char smem_raw[];
+  const int wg = (int)blockIdx.x;
+  const DevRedChunk W = ldc(work + wg);
+  const DevBox B = ldc(boxes + W.box);
+  const BL_GLOBAL T* phi = as_global(phi_);
+  const BL_GLOBAL T* fq = as_global(f_);
+  BL_GLOBAL T* out = as_global(out_);
+  BL_GLOBAL T* omir2 = as_global(omir2_) + mir2off[W.box];
+  const int ex = B.ex, ey = B.ey, ez = B.ez, nvx = B.nvx, P = ey * nvx;
+  const int nthr = (int)blockDim.x, tid = (int)threadIdx.x;
+  const int z0 = W.z0, z1 = W.z1;
+  const int rowsz = (ey + 2) * ex, bufsz = (rowsz + 2 * ey + V - 1) / V * V;
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int64_t sz = B.sz;
+  const int gpar = B.glo[0] + B.glo[1] + B.glo[2];
+  const DevPushFace PF = ldc(pface + W.box);
+
+  // the lane's vectors: row, x vector, offset (plane 0) and parity of their first cell at z = 0
+  bool act[K];
+  int yv[K], xvv[K], par[K];
+  int64_t go[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    const int q = tid + m * nthr;
+    act[m] = q < P;
+    const int qq = act[m] ? q : P - 1;
+    yv[m] = qq / nvx;
+    xvv[m] = qq - yv[m] * nvx;
+    go[m] = B.off + (int64_t)yv[m] * B.sy + (int64_t)xvv[m] * V;
+    par[m] = (gpar + xvv[m] * V + yv[m]) & 1;
+  }
+  // the lane's ghost item of each plane: a vector of the ghost rows, or an x ghost value
+  const int nyr = 2 * nvx, nring = nyr + 2 * ey;
+  int64_t ra;
+  int64_t rstep;
+  int rl;  // LDS offset in a plane buffer
+  if (tid < nyr) {
+    const int side = tid / nvx, xv = tid - side * nvx;
+    ra = B.off + (int64_t)(side ? ey : -1) * B.sy + (int64_t)xv * V;
+    rstep = sz;
+    rl = (side ? ey + 1 : 0) * ex + xv * V;
+  } else {
+    const int t = tid < nring ? tid - nyr : 0, side = t / ey, yy = t - side * ey;
+    ra = B.xs + (int64_t)side * B.xs_side + (int64_t)yy * B.ng;
+    rstep = B.xs_z;
+    rl = rowsz + side * ey + yy;
+  }
+  auto ring_load = [&](int z, VT& h) {
+    if (tid < nyr)
+      h = ldv<T, V>(phi + ra + (int64_t)z * rstep);
+    else if (tid < nring)
+      h.v[0] = phi[ra + (int64_t)z * rstep];
+  };
+  auto ring_store = [&](T* pb, const VT& h) {
+    if (tid < nyr)
+      stv<T, V>(pb + rl, h);
+    else if (tid < nring)
+      pb[rl] = h.v[0];
+  };
+  auto plane_at = [&](int m, int z) -> VT {  // z in [-1, ez]
+    return ldv<T, V>(phi + go[m] + (int64_t)z * sz);
+  };
+  auto f_at = [&](int m, int z) -> VT { return ldv<T, V>(fq + go[m] + (int64_t)z * sz); };
+  auto clampz = [&](int z) { return z < -1 ? -1 : (z > ez ? ez : z); };
+  auto clampf = [&](int z) { return z < 0 ? 0 : (z > ez - 1 ? ez - 1 : z); };
+
+  // registers: plane i+1 (Gp) and i+2 (Gn, in flight) at the lane's vectors, f
+  // of planes i-1..i+1, the new red vector of plane i; planes i-2..i are read
+  // back from their LDS buffers at the lane's own position
+  VT Gp[K], Gn[K], Fm[K], Fc[K], Fn[K], Rc[K];
+  VT H, Hn;
+  const int i0 = z0 - 1;
+  auto own = [&](int m) { return (yv[m] + 1) * ex + xvv[m] * V; };
+  // planes i0-1 and i0 into buffers 2 and 0 (the ghost items of plane i0 when it
+  // is a valid plane), plane i0+1 into registers
+  ring_load(clampf(i0), H);
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    const VT a = plane_at(m, clampz(i0 - 1)), b = plane_at(m, clampz(i0));
+    Gp[m] = plane_at(m, clampz(i0 + 1));
+    Fc[m] = f_at(m, clampf(i0));
+    Fm[m] = Fc[m];
+    if (act[m]) {
+      stv<T, V>(lds + 2 * bufsz + own(m), a);
+      stv<T, V>(lds + own(m), b);
+    }
+  }
+  if (i0 >= 0 && i0 < ez) ring_store(lds, H);
+  double accr = 0.0, accb = 0.0;
+  for (int i = i0; i <= z1; ++i) {
+    const int r = i - i0, bc = r % 3, bm = (r + 2) % 3, bn = (r + 1) % 3;
+    T* pc = lds + bc * bufsz;  // plane i
+    T* pm = lds + bm * bufsz;  // plane i-1 (new red values)
+    T* pn = lds + bn * bufsz;  // plane i-2 (new red values), then plane i+1
+    lds_barrier();  // LDS only: the global stores need no wait, the loads are waited for where used
+    // loads for the next planes: the ghost item first, so that waiting for it
+    // at the end of this plane leaves the plane loads in flight
+    const bool next_in = i + 1 <= ez && i + 1 <= z1;
+    if (i + 1 < ez && i + 1 <= z1) ring_load(i + 1, Hn);
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      Gn[m] = plane_at(m, clampz(i + 2));
+      Fn[m] = f_at(m, clampf(i + 1));
+    }
+    // red values of plane i
+    if (i >= 0 && i < ez) {
+      const bool resr = red_part && i >= z0 && i < z1;
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        const PlaneNbr<T, V> N = plane_nbr<T, V>(pc, ex, ey, nvx, yv[m], xvv[m]);
+        const VT g = ldv<T, V>(pc + own(m));
+        const VT gm = ldv<T, V>(pm + own(m));  // plane i-1: old values at its black cells
+        const VT o = colour_update<T, V, false>(g, N.left, N.right, N.ym, N.yp, gm, Gp[m], Fc[m], (par[m] + i) & 1,
+                                                h2, inv6, resr && act[m], inv_h2d, accr);
+        Rc[m] = o;
+        if (act[m]) stv<T, V>(pc + own(m), o);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < K; ++m) Rc[m] = ldv<T, V>(pc + own(m));  // a ghost plane as it stands
+    }
+    // black values of plane i-1, stored: its cells, its edge columns, its face
+    // cells into the neighbours' face ghosts of out
+    if (i - 1 >= z0) {
+      const int z = i - 1;
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        const PlaneNbr<T, V> N = plane_nbr<T, V>(pm, ex, ey, nvx, yv[m], xvv[m]);
+        const VT rm1 = ldv<T, V>(pm + own(m));
+        const VT rm2 = ldv<T, V>(pn + own(m));
+        const VT o = colour_update<T, V, true>(rm1, N.left, N.right, N.ym, N.yp, rm2, Rc[m], Fm[m],
+                                               (par[m] + z + 1) & 1, h2, inv6, black_part && act[m], inv_h2d, accb);
+        if (!act[m]) continue;
+        stv<T, V>(out + go[m] + (int64_t)z * sz, o);
+        const int64_t yz = (int64_t)z * ey + yv[m];
+        if (xvv[m] == 0) {
+          out[B.mir + yz] = o.v[0];
+          omir2[yz] = o.v[1];
+          push_x(out, push, PF.start[0], PF.count[0], yv[m], z, o.v[0]);
+        }
+        if (xvv[m] == nvx - 1) {
+          out[B.mir + B.mir_side + yz] = o.v[V - 1];
+          omir2[(int64_t)ey * ez + yz] = o.v[V - 2];
+          push_x(out, push, PF.start[1], PF.count[1], yv[m], z, o.v[V - 1]);
+        }
+        if (yv[m] == 0) push_row<T, V>(out, push, PF.start[2], PF.count[2], xvv[m] * V, z, o);
+        if (yv[m] == ey - 1) push_row<T, V>(out, push, PF.start[3], PF.count[3], xvv[m] * V, z, o);
+        if (z == 0) push_row<T, V>(out, push, PF.start[4], PF.count[4], xvv[m] * V, yv[m], o);
+        if (z == ez - 1) push_row<T, V>(out, push, PF.start[5], PF.count[5], xvv[m] * V, yv[m], o);
+      }
+    }
+    // plane i+1 into the buffer that plane i-2 used (each lane reads and writes
+    // only its own slots there)
+    if (next_in) {
+#pragma unroll
+      for (int m = 0; m < K; ++m)
+        if (act[m]) stv<T, V>(pn + own(m), Gp[m]);
+      if (i + 1 < ez) ring_store(pn, Hn);
+    }
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      Gp[m] = Gn[m];
+      Fm[m] = Fc[m];
+      Fc[m] = Fn[m];
+    }
+  }
+  if (red_part) {
+    const double v = block_reduce(accr, R_SUM);
+    if (threadIdx.x == 0) red_part[wg] = v;
+  }
+  if (black_part) {
+    const double v = block_reduce(accb, R_SUM);
+    if (threadIdx.x == 0) black_part[wg] = v;
+  }
+}
+
 }  // namespace
 
 int device_cu_count() {
@@ -2235,6 +2624,62 @@ hipError_t launch_gsrb_fused(const Plan& p, void* phi, const void* f, double h2,
                       : gsrb_dma_v<double, 1>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s, rows);
   return p.vec == 4 ? gsrb_dma_v<float, 4>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s, rows)
                     : gsrb_dma_v<float, 1>(p, phi, f, h2, color, rescolor, partials, g, persist, block, s, rows);
+}
+
+// One-pass red-black sweep: the ring kernel, the edge-column copies, the sweep.
+hipError_t launch_gsrb_ring(const Plan& p, void* phi, const void* f, const void* mir2, double h2, hipStream_t s) {
+  const unsigned nr = (unsigned)p.hringrecs.size();
+  if (nr == 0) return hipSuccess;
+  if (p.dtype == BL_F64)
+    hipLaunchKernelGGL(k_gsrb_ring<double>, dim3(nr), dim3(256), 0, s, (double*)phi, (const double*)f, p.dboxes,
+                       p.dringrecs, (const double*)mir2, p.dmir2off, h2, 1.0 / 6.0);
+  else
+    hipLaunchKernelGGL(k_gsrb_ring<float>, dim3(nr), dim3(256), 0, s, (float*)phi, (const float*)f, p.dboxes,
+                       p.dringrecs, (const float*)mir2, p.dmir2off, (float)h2, (float)(1.0 / 6.0));
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_edges2(const Plan& p, void* data, void* mir2, hipStream_t s) {
+  const unsigned nb = (unsigned)p.hboxes.size();
+  if (nb == 0) return hipSuccess;
+  if (p.dtype == BL_F64)
+    hipLaunchKernelGGL(k_extract_edges2<double>, dim3(nb), dim3(256), 0, s, (double*)data, p.dboxes, (double*)mir2,
+                       p.dmir2off);
+  else
+    hipLaunchKernelGGL(k_extract_edges2<float>, dim3(nb), dim3(256), 0, s, (float*)data, p.dboxes, (float*)mir2,
+                       p.dmir2off);
+  return hipGetLastError();
+}
+
+size_t gsrb_sweep_lds(int ex, int ey, int vec, int esize) {
+  const size_t rowsz = (size_t)(ey + 2) * ex, bufsz = (rowsz + 2 * (size_t)ey + vec - 1) / vec * vec;
+  return 3 * bufsz * (size_t)esize;
+}
+
+template <typename T, int V, int K>
+static hipError_t gsrb_sweep_t(const Plan& p, const DevRedChunk* work, int nwork, int block, size_t lds,
+                               const void* phi, void* out, const void* f, void* omir2, double h2, double* red,
+                               double* black, hipStream_t s) {
+  if (lds > 65536) {  // more than the default dynamic LDS of a launch
+    hipError_t e = hipFuncSetAttribute((const void*)k_gsrb_sweep<T, V, K>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_gsrb_sweep<T, V, K>), dim3(nwork), dim3(block), lds, s, p.dboxes, work, (const T*)phi,
+                     (T*)out, (const T*)f, (T*)omir2, p.dmir2off, p.dpushrecs, p.dpushface, (T)h2, (T)(1.0 / 6.0),
+                     1.0 / h2, red, black);
+  return hipGetLastError();
+}
+
+hipError_t launch_gsrb_sweep(const Plan& p, const DevRedChunk* work, int nwork, int block, int k, size_t lds,
+                             const void* phi, void* out, const void* f, void* omir2, double h2, double* red,
+                             double* black, hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  if (p.dtype == BL_F64)
+    return k == 2 ? gsrb_sweep_t<double, 2, 2>(p, work, nwork, block, lds, phi, out, f, omir2, h2, red, black, s)
+                  : gsrb_sweep_t<double, 2, 1>(p, work, nwork, block, lds, phi, out, f, omir2, h2, red, black, s);
+  return k == 2 ? gsrb_sweep_t<float, 4, 2>(p, work, nwork, block, lds, phi, out, f, omir2, h2, red, black, s)
+                : gsrb_sweep_t<float, 4, 1>(p, work, nwork, block, lds, phi, out, f, omir2, h2, red, black, s);
 }
 
 // Variable-coefficient heat step (k_heat_vc_dma) over the whole level, one

@@ -103,6 +103,20 @@ hipError_t launch_gsrb_fused(const Plan& p, void* phi, const void* f, double h2,
                              double* partials, int grid, int block, hipStream_t s, bool rows = false);
 // *out = sum (sqrt of it if take_sqrt) of partials[0..n)
 hipError_t launch_reduce_partials(const double* partials, int n, int take_sqrt, double* out, hipStream_t s);
+// One-pass red-black sweep.  launch_gsrb_ring: the new red values of every
+// covered face ghost cell into phi's ghost layer (red positions); mir2: phi's
+// second edge-column copy.  launch_extract_edges2: both edge-column copies of
+// data (the mirror and mir2) from its rows.  launch_gsrb_sweep: the sweep of
+// the work chunks (box, planes) from phi into out, with out's edge columns;
+// red / black (may be NULL): per-workgroup partials of the squared residual at
+// phi's red cells and at out's black cells.  gsrb_sweep_lds: the LDS of a
+// workgroup for a box of ex x ey planes (3 plane buffers with their ghost items).
+hipError_t launch_gsrb_ring(const Plan& p, void* phi, const void* f, const void* mir2, double h2, hipStream_t s);
+hipError_t launch_extract_edges2(const Plan& p, void* data, void* mir2, hipStream_t s);
+size_t gsrb_sweep_lds(int ex, int ey, int vec, int esize);
+hipError_t launch_gsrb_sweep(const Plan& p, const DevRedChunk* work, int nwork, int block, int k, size_t lds,
+                             const void* phi, void* out, const void* f, void* omir2, double h2, double* red,
+                             double* black, hipStream_t s);
 
 // Variable-coefficient heat step in the flux form, u -> w with coefficient beta
 // (same layout), over linear tiles built for zchunk and block; LDS 2*vc_lds_half.

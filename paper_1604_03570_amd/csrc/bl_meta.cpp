@@ -865,6 +865,72 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
     }
   }
 
+  // One-pass red-black sweep: every covered part of a face ghost layer, with
+  // the offset from destination to source box-local cells, chunked; and the
+  // offsets of each box's second edge-column copy.
+  p->hringrecs.clear();
+  p->hpushrecs.clear();
+  p->hpushface.assign(ba->boxes.size(), DevPushFace{});
+  p->faces_covered = true;
+  // push records, per (source box, source face)
+  std::vector<std::vector<DevPushRec>> push(6 * ba->boxes.size());
+  for (const FaceRecord& r : faces) {
+    const bool uncovered = r.src == r.box && r.shift[0] == 0 && r.shift[1] == 0 && r.shift[2] == 0;
+    if (uncovered) {
+      p->faces_covered = false;
+      continue;
+    }
+    const Box& db = ba->boxes[r.box];
+    const Box& sb = ba->boxes[r.src];
+    const int a = r.face / 2;
+    const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+    DevRingRec R{};
+    R.box = r.box;
+    R.src = r.src;
+    R.face = r.face;
+    for (int d = 0; d < 3; ++d) {
+      R.lo[d] = r.region.lo[d] - db.lo[d];
+      R.d[d] = db.lo[d] + r.shift[d] - sb.lo[d];
+    }
+    R.n1 = r.region.len(t1);
+    R.n2 = r.region.len(t2);
+    p->hringrecs.push_back(R);
+    // the same part seen from the source: its face cells (the face opposite to
+    // the destination's) and the destination ghost cells they fill
+    const FabGeom& df = p->fabs[r.box];
+    DevPushRec Q{};
+    Q.t1lo = r.region.lo[t1] + r.shift[t1] - sb.lo[t1];
+    Q.t1hi = r.region.hi[t1] + r.shift[t1] - sb.lo[t1];
+    Q.t2lo = r.region.lo[t2] + r.shift[t2] - sb.lo[t2];
+    Q.t2hi = r.region.hi[t2] + r.shift[t2] - sb.lo[t2];
+    int64_t s1, s2;
+    if (a == 0) {
+      s1 = df.ng;
+      s2 = df.xs_z;
+    } else {
+      s1 = 1;
+      s2 = a == 1 ? df.sz : df.sy;
+    }
+    Q.s1 = (int32_t)s1;
+    Q.s2 = (int32_t)s2;
+    Q.base = df.index(r.region.lo[0], r.region.lo[1], r.region.lo[2]) - Q.t1lo * s1 - Q.t2lo * s2;
+    const int sface = 2 * a + (1 - r.face % 2);
+    push[6 * (size_t)r.src + sface].push_back(Q);
+  }
+  for (size_t i = 0; i < ba->boxes.size(); ++i)
+    for (int f = 0; f < 6; ++f) {
+      auto& v = push[6 * i + f];
+      p->hpushface[i].start[f] = (int32_t)p->hpushrecs.size();
+      p->hpushface[i].count[f] = (int32_t)v.size();
+      p->hpushrecs.insert(p->hpushrecs.end(), v.begin(), v.end());
+    }
+  p->hmir2off.assign(ba->boxes.size(), 0);
+  p->mir2_total = 0;
+  for (size_t i = 0; i < ba->boxes.size(); ++i) {
+    p->hmir2off[i] = p->mir2_total;
+    p->mir2_total += 2 * (int64_t)ba->boxes[i].len(1) * ba->boxes[i].len(2);
+  }
+
   // FillBoundary records: each plan region split by the destination's
   // storage class along x (low x slab, rows, high x slab), chunked.
   p->fill = fill_plan(ba, ng);

@@ -180,8 +180,9 @@ def test_512cube_uneven_heat8_fused_at_full_size(bt):
 def test_384cube_gsrb_at_full_size(bt):
     """384^3 periodic, 216 boxes of 64^3, zero-mean f, phi0 = 0, 20 sweeps with the FP64
     residual norm after each (the benchmark's GSRB workload) against the oracle's whole
-    run: the FP64 state bit for bit and all 20 norms to 1e-13; the FP32 state within 1e-5
-    of the oracle's field and all 20 FP32 norms within 1e-5; the norms fall every sweep."""
+    run: the FP64 state bit for bit and all 20 norms to 1e-13, in the one-pass and in the
+    two-pass form; the FP32 state of both forms the same bits, within 1e-5 of the
+    oracle's field, and all 20 FP32 norms within 1e-5; the norms fall every sweep."""
     n, sweeps = 384, 20
     dom = I.domain_box(n)
     boxes = I.regular_chop(dom, 64)
@@ -195,19 +196,28 @@ def test_384cube_gsrb_at_full_size(bt):
     ref = ophi.to_global()[0]
     del ophi, ofm
 
-    def run(dt):
+    def run(dt, one_pass):
         phi, fm = bt.MultiFab(ba, 1, 1, dt), bt.MultiFab(ba, 1, 1, dt)
         phi.set_val(0.0, with_ghosts=True)
         fm.set_val(0.0, with_ghosts=True)
         fm.from_global(f)
-        norms = bt.gsrb_sweeps(phi, fm, h2, sweeps)
+        bt.set_gsrb_config(one_pass, 32, 0)
+        try:
+            assert bt.gsrb_one_pass_applies(phi) == bool(one_pass)
+            norms = bt.gsrb_sweeps(phi, fm, h2, sweeps)
+        finally:
+            bt.set_gsrb_config(1, 32, 0)
         return phi.to_global()[0].double().cpu().numpy(), norms
 
-    g64, n64 = run(bt.F64)
-    assert np.array_equal(g64, ref), "FP64 GSRB field differs from the oracle's"
-    assert all(abs(g - r) <= 1e-13 * r for g, r in zip(n64, on)), (n64, on)
-    del g64
-    g32, n32 = run(bt.F32)
+    for one_pass in (1, 0):  # the one-pass sweep (the default here) and the two colour passes
+        g64, n64 = run(bt.F64, one_pass)
+        assert np.array_equal(g64, ref), f"FP64 GSRB field differs from the oracle's (one_pass={one_pass})"
+        assert all(abs(g - r) <= 1e-13 * r for g, r in zip(n64, on)), (one_pass, n64, on)
+        del g64
+    g32, n32 = run(bt.F32, 1)
+    g32b, _ = run(bt.F32, 0)
+    assert np.array_equal(g32, g32b), "FP32 one-pass and two-pass fields differ"
+    del g32b
     ferr = float(np.abs(g32 - ref).max() / np.abs(ref).max())
     nerr = max(abs(x - y) / y for x, y in zip(n32, on))
     say(f"384^3 gsrb: fp64 bit-exact; fp32 field rel err {ferr:.2e}, norm rel err {nerr:.2e}, "

@@ -138,9 +138,19 @@ def test_advances_in_sequence_continue_from_the_mirror(bt, layout):
     say(f"mirror continuation {layout}: {total} steps bit-exact")
 
 
-def test_gsrb_calls_in_sequence_skip_the_extraction(bt):
+@pytest.mark.parametrize("one_pass", [0, 1])
+def test_gsrb_calls_in_sequence_skip_the_extraction(bt, one_pass):
     """Two GSRB calls in a row (the second finds phi's mirror current and extracts
-    nothing) give the oracle's field and norms of one run of all the sweeps."""
+    nothing) give the oracle's field and norms of one run of all the sweeps, in the
+    two-pass form and in the one-pass form."""
+    bt.set_gsrb_config(one_pass, 32, 0)
+    try:
+        _gsrb_in_sequence(bt)
+    finally:
+        bt.set_gsrb_config(1, 32, 0)
+
+
+def _gsrb_in_sequence(bt):
     dom, periodic, boxes = _boxes("uneven")
     N = tuple(dom[3 + d] + 1 for d in range(3))
     rng = np.random.default_rng(4)

@@ -232,11 +232,17 @@ def _gsrb_problem(n, boxes_edge, dtype, seed=5):
     return phi, fm, ophi, ofm
 
 
-def test_gsrb_fp64_bit_exact_with_norms(bt):
+@pytest.mark.parametrize("one_pass", [0, 1])
+def test_gsrb_fp64_bit_exact_with_norms(bt, one_pass):
     n, sweeps = 32, 6
     h2 = (1.0 / n) ** 2
     phi, fm, ophi, ofm = _gsrb_problem(n, 16, bt.F64)
-    norms = bt.gsrb_sweeps(phi, fm, h2, sweeps)
+    bt.set_gsrb_config(one_pass, 32, 0)
+    try:
+        assert bt.gsrb_one_pass_applies(phi) == bool(one_pass)
+        norms = bt.gsrb_sweeps(phi, fm, h2, sweeps)
+    finally:
+        bt.set_gsrb_config(1, 32, 0)
     onorms = O.gsrb_sweeps(ophi, ofm, h2, sweeps)
     assert np.array_equal(gpu_global(phi), ophi.to_global())
     for g, r in zip(norms, onorms):
@@ -244,11 +250,16 @@ def test_gsrb_fp64_bit_exact_with_norms(bt):
     assert abs(bt.residual_norm(phi, fm, h2) - onorms[-1]) <= F64_SUM_TOL * onorms[-1]
 
 
-def test_gsrb_fp32_state_against_fp64_oracle(bt):
+@pytest.mark.parametrize("one_pass", [0, 1])
+def test_gsrb_fp32_state_against_fp64_oracle(bt, one_pass):
     n, sweeps = 64, 20
     h2 = (1.0 / n) ** 2
     phi, fm, ophi, ofm = _gsrb_problem(n, 32, bt.F32)
-    norms = bt.gsrb_sweeps(phi, fm, h2, sweeps)
+    bt.set_gsrb_config(one_pass, 32, 0)
+    try:
+        norms = bt.gsrb_sweeps(phi, fm, h2, sweeps)
+    finally:
+        bt.set_gsrb_config(1, 32, 0)
     onorms = O.gsrb_sweeps(ophi, ofm, h2, sweeps)
     err = rel_err(gpu_global(phi), ophi.to_global())
     nerr = max(abs(g - r) / r for g, r in zip(norms, onorms))
@@ -416,9 +427,10 @@ GSRB_CONFIGS = [(4, 4, 0, 3), (2, 4, 0, 3), (8, 2, 0, 3), (4, 3, 0, 3), (4, 4, 2
 @pytest.mark.parametrize("cfg", GSRB_CONFIGS)
 @pytest.mark.parametrize("layout", ["uneven", "odd_noncovering"])
 def test_gsrb_every_form_bit_exact_on_uneven_layouts(bt, cfg, layout):
-    """GSRB sweeps (fused colour passes with face records, or fill + colour passes)
-    give the oracle's FP64 field bit for bit and its norms to 1e-13, on uneven and on
-    non-covering, partly non-periodic layouts."""
+    """GSRB sweeps in the two-pass form (fused colour passes with face records, or
+    fill + colour passes) give the oracle's FP64 field bit for bit and its norms to
+    1e-13, on uneven and on non-covering, partly non-periodic layouts, under every
+    tile configuration."""
     rng = np.random.default_rng(41)
     if layout == "uneven":
         dom, periodic = I.domain_box((48, 40, 32)), (1, 1, 1)
@@ -433,6 +445,7 @@ def test_gsrb_every_form_bit_exact_on_uneven_layouts(bt, cfg, layout):
     h2, sweeps = 1.0 / 1024.0, 4
     saved = bt.get_tile_config()
     bt.set_tile_config(*cfg)
+    bt.set_gsrb_config(0, 32, 0)
     try:
         say(f"gsrb cfg {cfg} layout={layout}")
         _, phi, fm, ophi = make_pair(boxes, dom, periodic, 1, 1, bt.F64, g0, ghost_value=0.25)
@@ -443,6 +456,7 @@ def test_gsrb_every_form_bit_exact_on_uneven_layouts(bt, cfg, layout):
         got = gpu_global(phi)
     finally:
         bt.set_tile_config(*saved)
+        bt.set_gsrb_config(1, 32, 0)
     ofm = O.OracleMultiFab(boxes, dom, periodic, 1, 1)
     ofm.load_global(f)
     onorms = O.gsrb_sweeps(ophi, ofm, h2, sweeps)
