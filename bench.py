@@ -381,8 +381,10 @@ def per_box_run(bt, I, torch) -> dict:
 def gsrb_run(bt, I, torch, seed: int, sweeps: int = 20) -> dict:
     """Red-black Gauss-Seidel for -Lap(phi) = f: 384^3 periodic, 216 boxes of 64^3, f a seeded
     zero-mean N(0,1) field rounded to FP32, phi0 = 0, FP32 state, 20 sweeps with a FillBoundary
-    before each colour (the fused form reads neighbour boxes directly) and the FP64 residual
-    norm after every sweep.  Also the form with explicit fills, for comparison."""
+    before each colour (or its equivalent) and the FP64 residual norm after every sweep.  Forms:
+    one_pass (the default: one launch per sweep computes red a plane ahead of black, after the
+    ring kernel), two_pass (fused colour passes reading the neighbour boxes directly) and
+    fill_then_pass (explicit fills), each with the same result; one_pass also without norms."""
     n = 384
     dom = I.domain_box(n)
     ba = bt.BoxArray.from_boxes(I.regular_chop(dom, 64), dom)
@@ -392,34 +394,43 @@ def gsrb_run(bt, I, torch, seed: int, sweeps: int = 20) -> dict:
     h2 = (1.0 / n) ** 2
     out = {"workload": f"{n}^3 periodic, 216 boxes of 64^3, FP32 state, {sweeps} sweeps, FP64 norm each sweep"}
     saved = bt.get_tile_config()
-    for form, cfg in (("fused", None), ("fill_then_pass", (saved[0], saved[1], saved[2], 2))):
+    gsaved = bt.get_gsrb_config()
+    forms = (("one_pass", None, gsaved, True), ("one_pass_no_norms", None, gsaved, False),
+             ("two_pass", None, (0, gsaved[1], gsaved[2]), True),
+             ("fill_then_pass", (saved[0], saved[1], saved[2], 2), (0, gsaved[1], gsaved[2]), True))
+    for form, cfg, gcfg, with_norms in forms:
         if cfg:
             bt.set_tile_config(*cfg)
+        bt.set_gsrb_config(*gcfg)
         try:
             phi, fm = bt.MultiFab(ba, 1, 1, bt.F32), bt.MultiFab(ba, 1, 1, bt.F32)
             fm.set_val(0.0, with_ghosts=True)
             fm.from_global(f)
             phi.set_val(0.0, with_ghosts=True)
-            bt.gsrb_sweeps(phi, fm, h2, 2)  # warm-up
+            applies = bt.gsrb_one_pass_applies(phi)
+            bt.gsrb_sweeps(phi, fm, h2, 2, with_norms=with_norms)  # warm-up
             phi.set_val(0.0, with_ghosts=True)
             torch.cuda.synchronize()
             stream = torch.cuda.current_stream()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            norms = bt.gsrb_sweeps(phi, fm, h2, sweeps)
+            norms = bt.gsrb_sweeps(phi, fm, h2, sweeps, with_norms=with_norms)
             e1.record(stream)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1)
         finally:
             if cfg:
                 bt.set_tile_config(*saved)
+            bt.set_gsrb_config(*gsaved)
         cs = n ** 3 * sweeps / (ms / 1e3)
         out[form] = {"ms_per_sweep": round(ms / sweeps, 4), "gcell_sweeps_s": round(cs / 1e9, 2),
-                     "hbm_frac_at_12B": round(cs * 12 / (HBM_PEAK_GBS * 1e9), 4),
-                     "resnorm_first": norms[0], "resnorm_last": norms[-1],
-                     "resnorm_h32_first": norms[0] * (1.0 / n) ** 1.5, "resnorm_h32_last": norms[-1] * (1.0 / n) ** 1.5}
-        log(f"gsrb {form}: {ms / sweeps:.3f} ms per sweep, {cs / 1e9:.1f} G cell-sweeps/s, "
-            f"norm {norms[0]:.4e} -> {norms[-1]:.4e}")
+                     "hbm_frac_at_12B": round(cs * 12 / (HBM_PEAK_GBS * 1e9), 4), "one_pass": applies}
+        if norms:
+            out[form].update({"resnorm_first": norms[0], "resnorm_last": norms[-1],
+                              "resnorm_h32_first": norms[0] * (1.0 / n) ** 1.5,
+                              "resnorm_h32_last": norms[-1] * (1.0 / n) ** 1.5})
+        log(f"gsrb {form}: {ms / sweeps:.3f} ms per sweep, {cs / 1e9:.1f} G cell-sweeps/s"
+            + (f", norm {norms[0]:.4e} -> {norms[-1]:.4e}" if norms else ""))
         del phi, fm
     del f
     torch.cuda.empty_cache()

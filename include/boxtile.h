@@ -394,8 +394,8 @@ bl_status bl_get_gsrb_config(int32_t* one_pass, int32_t* zchunk, int32_t* vector
  * current configuration: every box's x extent a whole number of 16-byte
  * vectors (vec = 4 FP32 or 2 FP64 values), planes of at most 1024 lanes'
  * vectors, at least as many lanes as ghost items around a plane (2*ex/vec
- * ghost-row vectors + 2*ey x ghost values), three plane buffers within one
- * workgroup's LDS (160 KiB on MI355X).  Otherwise 0.
+ * ghost-row vectors + 2*ey x ghost values) and as 4*ey, three plane buffers
+ * within one workgroup's LDS (160 KiB on MI355X).  Otherwise 0.
  */
 bl_status bl_gsrb_one_pass_applies(const bl_multifab* phi, int32_t* applies);
 

@@ -782,8 +782,8 @@ static std::atomic<int> g_gsrb_one_pass{1}, g_gsrb_zchunk{32}, g_gsrb_vpl{0};
 // The one-pass sweep's work chunks for the current configuration; false if
 // some box does not fit it: an x extent that is not a whole number of 16-byte
 // vectors, planes of more than 1024 lanes' vectors, more ghost items per plane
-// (two ghost rows of vectors, two columns of values) than lanes, or three
-// plane buffers beyond one workgroup's LDS.
+// (two ghost rows of vectors, two columns of values) or edge-column values (4
+// per row) than lanes, or three plane buffers beyond one workgroup's LDS.
 static bool gsrb1_plan(Plan& p) {
   std::lock_guard<std::mutex> lk(g_vc_mu);
   const int zc = g_gsrb_zchunk.load(), want_k = g_gsrb_vpl.load();
@@ -804,7 +804,7 @@ static bool gsrb1_plan(Plan& p) {
   if (block > 1024) return false;
   size_t lds = 0;
   for (const Box& b : p.boxes) {
-    if (2 * (b.len(0) / V) + 2 * b.len(1) > block) return false;
+    if (2 * (b.len(0) / V) + 2 * b.len(1) > block || 4 * b.len(1) > block) return false;
     lds = std::max(lds, gsrb_sweep_lds(b.len(0), b.len(1), V, p.esize));
   }
   if (lds > mg_bottom_lds_limit()) return false;

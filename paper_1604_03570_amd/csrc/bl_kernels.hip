@@ -2094,10 +2094,14 @@ __device__ __forceinline__ void push_row(BL_GLOBAL T* out, const DevPushRec* __r
   for (int r = start; r < start + count; ++r) {
     const DevPushRec Q = ldc(recs + r);
     if (t2 < Q.t2lo || t2 > Q.t2hi) continue;
-    const int64_t b = Q.base + (int64_t)t2 * Q.s2;
+    const int64_t b = Q.base + (int64_t)t2 * Q.s2 + x0;
+    if (x0 >= Q.t1lo && x0 + V - 1 <= Q.t1hi && b % V == 0) {  // the whole vector, aligned
+      stv<T, V>(out + b, o);
+      continue;
+    }
 #pragma unroll
     for (int e = 0; e < V; ++e)
-      if (x0 + e >= Q.t1lo && x0 + e <= Q.t1hi) out[b + x0 + e] = o.v[e];
+      if (x0 + e >= Q.t1lo && x0 + e <= Q.t1hi) out[b + e] = o.v[e];
   }
 }
 
@@ -2111,12 +2115,12 @@ __device__ __forceinline__ void push_row(BL_GLOBAL T* out, const DevPushRec* __r
 // (The vectors come by value: a select between two elements of a vector behind
 // a reference becomes one load at a variable index, which puts the caller's
 // vectors in scratch memory.)
-template <typename T, int V, bool AFTER>
-__device__ __forceinline__ Vec<T, V> colour_update(Vec<T, V> c, T left, T right, Vec<T, V> ym, Vec<T, V> yp,
-                                                   Vec<T, V> zm, Vec<T, V> zp, Vec<T, V> fv, int q, T h2, T inv6,
-                                                   bool res, double inv_h2d, double& acc) {
+template <typename T, int V, bool AFTER, int QS>
+__device__ __forceinline__ Vec<T, V> colour_update_t(Vec<T, V> c, T left, T right, Vec<T, V> ym, Vec<T, V> yp,
+                                                     Vec<T, V> zm, Vec<T, V> zp, Vec<T, V> fv, int q, T h2, T inv6,
+                                                     bool res, double inv_h2d, double& acc) {
   Vec<T, V> o = c;
-  const bool s = q != 0;
+  const bool s = QS >= 0 ? QS != 0 : q != 0;
 #pragma unroll
   for (int k = 0; k < V / 2; ++k) {
     const int e0 = 2 * k, e1 = 2 * k + 1;
@@ -2140,6 +2144,17 @@ __device__ __forceinline__ Vec<T, V> colour_update(Vec<T, V> c, T left, T right,
   return o;
 }
 
+// The same with the parity taken as a branch into one of two select-free
+// bodies: where all lanes of a wave share q (the sweep lays out its lanes so
+// that they do), the wave runs one body only.
+template <typename T, int V, bool AFTER>
+__device__ __forceinline__ Vec<T, V> colour_update(Vec<T, V> c, T left, T right, Vec<T, V> ym, Vec<T, V> yp,
+                                                   Vec<T, V> zm, Vec<T, V> zp, Vec<T, V> fv, int q, T h2, T inv6,
+                                                   bool res, double inv_h2d, double& acc) {
+  if (q == 0) return colour_update_t<T, V, AFTER, 0>(c, left, right, ym, yp, zm, zp, fv, q, h2, inv6, res, inv_h2d, acc);
+  return colour_update_t<T, V, AFTER, 1>(c, left, right, ym, yp, zm, zp, fv, q, h2, inv6, res, inv_h2d, acc);
+}
+
 // One red-black sweep of the valid planes z0..z1-1 of one box per workgroup
 // (DevRedChunk), from phi into out (another buffer of the same layout).  phi's
 // face ghosts hold the old values at black positions and the new red values at
@@ -2147,9 +2162,9 @@ __device__ __forceinline__ Vec<T, V> colour_update(Vec<T, V> c, T left, T right,
 // at plane i it computes the new red values of plane i from the old planes
 // i-1..i+1, then the new black values of plane i-1 from the red values of
 // planes i-2..i, and stores plane i-1: its cells, its four edge columns (the
-// edge mirror and the second copy) and its face cells into the face ghost
-// cells of out that they fill (push records), so that out needs no
-// FillBoundary before the next sweep.  It starts one plane below z0 and ends one
+// edge mirror and the second copy; staged in LDS and stored by a few lanes one
+// plane later) and its face cells into the face ghost cells of out that they
+// fill (push records), so that out needs no FillBoundary before the next sweep.  It starts one plane below z0 and ends one
 // above z1 (red values only there); the planes outside the box are phi's
 // ghost planes as they stand.  Lane l takes plane vectors l + m*blockDim.x,
 // m < K; each plane passes through one of three LDS buffers (old values, then
@@ -2183,21 +2198,29 @@ __global__ void __launch_bounds__(1024)
   const int z0 = W.z0, z1 = W.z1;
   const int rowsz = (ey + 2) * ex, bufsz = (rowsz + 2 * ey + V - 1) / V * V;
   T* lds = reinterpret_cast<T*>(smem_raw);
+  // the four edge columns of a stored plane (x = 0, 1, ex-2, ex-1), staged for
+  // coalesced stores one plane later: two sets of 4*ey values
+  T* stg = lds + 3 * bufsz;
   const int64_t sz = B.sz;
   const int gpar = B.glo[0] + B.glo[1] + B.glo[2];
   const DevPushFace PF = ldc(pface + W.box);
 
-  // the lane's vectors: row, x vector, offset (plane 0) and parity of their first cell at z = 0
+  // the lane's vectors: row, x vector, offset (plane 0) and parity of their
+  // first cell at z = 0.  Vector index q runs over the even rows first, then the
+  // odd rows, so that the lanes of a wave share their colour pattern (x
+  // vectors start at even x).
   bool act[K];
   int yv[K], xvv[K], par[K];
   int64_t go[K];
+  const int neven = (ey + 1) / 2 * nvx;
 #pragma unroll
   for (int m = 0; m < K; ++m) {
     const int q = tid + m * nthr;
     act[m] = q < P;
     const int qq = act[m] ? q : P - 1;
-    yv[m] = qq / nvx;
-    xvv[m] = qq - yv[m] * nvx;
+    const int odd = qq >= neven ? 1 : 0, qr = qq - odd * neven, rr = qr / nvx;
+    yv[m] = 2 * rr + odd;
+    xvv[m] = qr - rr * nvx;
     go[m] = B.off + (int64_t)yv[m] * B.sy + (int64_t)xvv[m] * V;
     par[m] = (gpar + xvv[m] * V + yv[m]) & 1;
   }
@@ -2258,6 +2281,27 @@ __global__ void __launch_bounds__(1024)
     }
   }
   if (i0 >= 0 && i0 < ez) ring_store(lds, H);
+  // the staged edge columns of plane zz (set sidx) into out's edge mirror, the
+  // second copy and the x-face ghosts of the neighbours: lane t < 4*ey takes
+  // column t / ey, row t % ey
+  auto flush_edges = [&](int sidx, int zz) {
+    if (tid < 4 * ey) {
+      const int c = tid / ey, y = tid - c * ey;
+      const T v = stg[sidx * 4 * ey + tid];
+      const int64_t yz = (int64_t)zz * ey + y;
+      if (c == 0) {
+        out[B.mir + yz] = v;
+        push_x(out, push, PF.start[0], PF.count[0], y, zz, v);
+      } else if (c == 1) {
+        omir2[yz] = v;
+      } else if (c == 2) {
+        omir2[(int64_t)ey * ez + yz] = v;
+      } else {
+        out[B.mir + B.mir_side + yz] = v;
+        push_x(out, push, PF.start[1], PF.count[1], y, zz, v);
+      }
+    }
+  };
   double accr = 0.0, accb = 0.0;
   for (int i = i0; i <= z1; ++i) {
     const int r = i - i0, bc = r % 3, bm = (r + 2) % 3, bn = (r + 1) % 3;
@@ -2274,6 +2318,7 @@ __global__ void __launch_bounds__(1024)
       Gn[m] = plane_at(m, clampz(i + 2));
       Fn[m] = f_at(m, clampf(i + 1));
     }
+    if (i - 2 >= z0) flush_edges((i - 1) & 1, i - 2);  // the plane stored one step ago
     // red values of plane i
     if (i >= 0 && i < ez) {
       const bool resr = red_part && i >= z0 && i < z1;
@@ -2304,16 +2349,14 @@ __global__ void __launch_bounds__(1024)
                                                (par[m] + z + 1) & 1, h2, inv6, black_part && act[m], inv_h2d, accb);
         if (!act[m]) continue;
         stv<T, V>(out + go[m] + (int64_t)z * sz, o);
-        const int64_t yz = (int64_t)z * ey + yv[m];
+        T* sg = stg + (i & 1) * 4 * ey;
         if (xvv[m] == 0) {
-          out[B.mir + yz] = o.v[0];
-          omir2[yz] = o.v[1];
-          push_x(out, push, PF.start[0], PF.count[0], yv[m], z, o.v[0]);
+          sg[yv[m]] = o.v[0];
+          sg[ey + yv[m]] = o.v[1];
         }
         if (xvv[m] == nvx - 1) {
-          out[B.mir + B.mir_side + yz] = o.v[V - 1];
-          omir2[(int64_t)ey * ez + yz] = o.v[V - 2];
-          push_x(out, push, PF.start[1], PF.count[1], yv[m], z, o.v[V - 1]);
+          sg[2 * ey + yv[m]] = o.v[V - 2];
+          sg[3 * ey + yv[m]] = o.v[V - 1];
         }
         if (yv[m] == 0) push_row<T, V>(out, push, PF.start[2], PF.count[2], xvv[m] * V, z, o);
         if (yv[m] == ey - 1) push_row<T, V>(out, push, PF.start[3], PF.count[3], xvv[m] * V, z, o);
@@ -2336,6 +2379,8 @@ __global__ void __launch_bounds__(1024)
       Fc[m] = Fn[m];
     }
   }
+  lds_barrier();
+  flush_edges(z1 & 1, z1 - 1);  // the last plane
   if (red_part) {
     const double v = block_reduce(accr, R_SUM);
     if (threadIdx.x == 0) red_part[wg] = v;
@@ -2653,7 +2698,7 @@ hipError_t launch_extract_edges2(const Plan& p, void* data, void* mir2, hipStrea
 
 size_t gsrb_sweep_lds(int ex, int ey, int vec, int esize) {
   const size_t rowsz = (size_t)(ey + 2) * ex, bufsz = (rowsz + 2 * (size_t)ey + vec - 1) / vec * vec;
-  return 3 * bufsz * (size_t)esize;
+  return (3 * bufsz + 8 * (size_t)ey) * (size_t)esize;
 }
 
 template <typename T, int V, int K>
