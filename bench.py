@@ -207,13 +207,13 @@ def summarize_profiles(d: str) -> int:
     cells = line["config"]["cell_updates_per_step"]
     esize = 8 if dtype == "f64" else 4
     alg = 2 * esize * cells
-    cmd = f"rocprofv3 {{--kernel-trace --stats | --pmc FETCH_SIZE | --pmc WRITE_SIZE}} --output-format csv -- python3 bench.py {PROFILE_ARGS}"
+    args = f"{PROFILE_ARGS} --dtype {dtype}"
     out = os.path.join(ROOT, "profiles", f"heat_fused_512cube_uneven_5comp_{dtype}.md")
     with open(out, "w") as fh:
         fh.write(f"# Fused heat step + FillBoundary, 512^3 random chop, 5 comps, {dtype}\n\n")
         fh.write("Commands (three runs, from the repository root, after `cd /tmp && export TMPDIR=/tmp` for the profiler's files):\n\n")
         for opt in ("--kernel-trace --stats", "--pmc FETCH_SIZE", "--pmc WRITE_SIZE"):
-            fh.write(f"    rocprofv3 {opt} --output-format csv -d <out> -o run -- python3 bench.py {PROFILE_ARGS}\n")
+            fh.write(f"    rocprofv3 {opt} --output-format csv -d <out> -o run -- python3 bench.py {args}\n")
         fh.write(f"\nSummarised with `python3 bench.py --summarize-profiles <out>`.  Kernel source sha256/16: `{src_hash}`.\n\n")
         fh.write("## Kernel trace statistics\n\n| kernel | calls | average us | total % |\n|---|---|---|---|\n")
         for r in stats[:10]:
@@ -230,7 +230,8 @@ def summarize_profiles(d: str) -> int:
                  f"measured {(fetch_b + write_b) / (avg_us * 1e-6) / 1e9:.0f} GB/s\n")
         fh.write("\n## Steady state and the first step of each advance\n\n")
         fh.write(f"* {len(disp)} dispatches of the fused kernel: {len(firsts)} open a graph launch (the first step of "
-                 f"an advance reads the x-face neighbours from their rows), {len(steady)} follow one another\n")
+                 f"an advance; it reads the x-face neighbours from their rows unless the input's edge mirror is "
+                 f"current), {len(steady)} follow one another\n")
         fh.write(f"* median duration: steady state {steady_us:.1f} us ({alg / (steady_us * 1e-6) / 1e9:.0f} GB/s "
                  f"algorithmic, {alg / (steady_us * 1e-6) / 1e9 / (HBM_PEAK_GBS):.4f} of 8 TB/s); first step "
                  f"{first_us:.1f} us\n")
@@ -246,7 +247,7 @@ def summarize_profiles(d: str) -> int:
                 per.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(float(r["Counter_Value"]))
             names = sorted({cn for (kn, cn) in per if kn == hk})
             fh.write(f"\n## Counters `{' '.join(names)}` (median per dispatch)\n\n")
-            fh.write(f"    rocprofv3 --pmc {' '.join(names)} --output-format csv -d <out>/{xd} -o run -- python3 bench.py {PROFILE_ARGS}\n\n")
+            fh.write(f"    rocprofv3 --pmc {' '.join(names)} --output-format csv -d <out>/{xd} -o run -- python3 bench.py {args}\n\n")
             fh.write("| kernel | " + " | ".join(names) + " |\n|---|" + "---|" * len(names) + "\n")
             for kn in (hk, copy_name):
                 # the copy kernel: its largest dispatch (the 2 GiB copies, not torch's small ones)
