@@ -277,7 +277,7 @@ def summarize_profiles(d: str) -> int:
     return 0
 
 
-EXTRAS_PROFILE_ARGS = "--steps 5 --warmup 1 --no-cpu-baseline --no-serve"
+EXTRAS_PROFILE_ARGS = "--steps 5 --warmup 1 --no-cpu-baseline --no-serve --calibrate-copy"
 
 
 def summarize_trace(d: str) -> int:
