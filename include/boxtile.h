@@ -381,8 +381,9 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
 /*
  * Configuration of bl_gsrb_sweeps (process-wide): one_pass = 1 (default)
  * takes the one-pass sweep where it applies, 0 always the two colour passes;
- * zchunk (>= 1, default 32): planes of one box per workgroup of the one-pass
- * sweep; vectors_per_lane: 16-byte plane vectors per lane (1 or 2; 0, the
+ * zchunk (>= 0): planes of one box per workgroup of the one-pass sweep (0,
+ * the default: 32, halved down to 8 while the level would have fewer than 256
+ * workgroups); vectors_per_lane: 16-byte plane vectors per lane (1 or 2; 0, the
  * default: 1 for planes of at most 512 vectors, else 2).  BL_EINVAL for
  * other values.
  */

@@ -614,7 +614,7 @@ def gsrb_sweeps(phi: MultiFab, f: MultiFab, h2: float, nsweeps: int, with_norms:
     return list(norms)[:nsweeps] if with_norms else None
 
 
-def set_gsrb_config(one_pass: int = 1, zchunk: int = 32, vectors_per_lane: int = 0) -> None:
+def set_gsrb_config(one_pass: int = 1, zchunk: int = 0, vectors_per_lane: int = 0) -> None:
     """Form of gsrb_sweeps: the one-pass sweep where it applies (one_pass=1) or the
     two colour passes; planes per workgroup and vectors per lane of the one-pass sweep."""
     _check(_L.bl_set_gsrb_config(int(one_pass), int(zchunk), int(vectors_per_lane)))

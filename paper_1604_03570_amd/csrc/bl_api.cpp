@@ -775,9 +775,10 @@ static hipError_t residual_norm_dev(const Plan& p, void* phi, const void* f, dou
 }
 
 // The red-black sweep's form: the one-pass sweep where it applies (default) or
-// always the two colour passes; planes per workgroup and vectors per lane (0:
-// chosen from the largest plane) of the one-pass sweep.
-static std::atomic<int> g_gsrb_one_pass{1}, g_gsrb_zchunk{32}, g_gsrb_vpl{0};
+// always the two colour passes; planes per workgroup (0: 32, halved down to 8
+// while the level has fewer than 256 chunks) and vectors per lane (0: chosen
+// from the largest plane) of the one-pass sweep.
+static std::atomic<int> g_gsrb_one_pass{1}, g_gsrb_zchunk{0}, g_gsrb_vpl{0};
 
 // The one-pass sweep's work chunks for the current configuration; false if
 // some box does not fit it: an x extent that is not a whole number of 16-byte
@@ -786,9 +787,9 @@ static std::atomic<int> g_gsrb_one_pass{1}, g_gsrb_zchunk{32}, g_gsrb_vpl{0};
 // per row) than lanes, or three plane buffers beyond one workgroup's LDS.
 static bool gsrb1_plan(Plan& p) {
   std::lock_guard<std::mutex> lk(g_vc_mu);
-  const int zc = g_gsrb_zchunk.load(), want_k = g_gsrb_vpl.load();
-  if (p.sweep_req_zc == zc && p.sweep_req_k == want_k) return p.sweep_ok != 0;
-  p.sweep_req_zc = zc;
+  const int zreq = g_gsrb_zchunk.load(), want_k = g_gsrb_vpl.load();
+  if (p.sweep_req_zc == zreq && p.sweep_req_k == want_k) return p.sweep_ok != 0;
+  p.sweep_req_zc = zreq;
   p.sweep_req_k = want_k;
   p.sweep_ok = 0;
   const int V = 16 / p.esize;
@@ -798,6 +799,16 @@ static bool gsrb1_plan(Plan& p) {
     pmax = std::max(pmax, b.len(1) * (b.len(0) / V));
   }
   if (pmax == 0) return false;
+  int zc = zreq;
+  if (zc == 0) {
+    auto chunks = [&](int z) {
+      int64_t n = 0;
+      for (const Box& b : p.boxes) n += (b.len(2) + z - 1) / z;
+      return n;
+    };
+    zc = 32;
+    while (zc > 8 && chunks(zc) < 256) zc /= 2;
+  }
   const int k = want_k > 0 ? want_k : (pmax <= 512 ? 1 : 2);
   if (k != 1 && k != 2) return false;
   const int block = ((pmax + k - 1) / k + 63) / 64 * 64;
@@ -842,7 +853,7 @@ static bool gsrb1_plan(Plan& p) {
 // its face ghosts.  Norms: the black part of sweep s plus the red part of sweep
 // s+1; after the last sweep, the residual norm of the result.
 static bl_status gsrb_one_pass(Plan& p, bl_multifab* phi, const bl_multifab* f, double h2, int nsweeps,
-                               double* resnorm_host, hipStream_t stream) {
+                               double* resnorm_host, hipStream_t stream, bool edges_current = false) {
   bool fresh = false;
   if (!phi->dtwin) {
     BL_HIP(hipMalloc(&phi->dtwin, phi->bytes));
@@ -861,7 +872,9 @@ static bl_status gsrb_one_pass(Plan& p, bl_multifab* phi, const bl_multifab* f, 
   }
   void* buf[2] = {phi->data, phi->dtwin};
   void* m2[2] = {phi->dmir2, static_cast<char*>(phi->dmir2) + m2bytes};
-  BL_HIP(launch_extract_edges2(p, phi->data, m2[0], stream));
+  // both edge-column copies of the starting state, unless the caller knows them
+  // current (the previous call on this state was a one-pass call of an even count)
+  if (!edges_current) BL_HIP(launch_extract_edges2(p, phi->data, m2[0], stream));
   bl_multifab* fm = const_cast<bl_multifab*>(f);  // f's values are not changed: only its edge mirror is written
   if (!fm->mirror_current) {
     BL_HIP(launch_extract_mirror(p, fm->data, stream));
@@ -957,7 +970,7 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
 
 bl_status bl_set_gsrb_config(int32_t one_pass, int32_t zchunk, int32_t vectors_per_lane) {
   clear_error();
-  if (zchunk < 1) return fail(BL_EINVAL, "zchunk must be >= 1");
+  if (zchunk < 0) return fail(BL_EINVAL, "zchunk must be >= 0 (0: chosen per level)");
   if (vectors_per_lane < 0 || vectors_per_lane > 2) return fail(BL_EINVAL, "vectors_per_lane must be 0, 1 or 2");
   g_gsrb_one_pass = one_pass ? 1 : 0;
   g_gsrb_zchunk = zchunk;
@@ -1035,6 +1048,9 @@ struct bl_mg {
   bl::MgBottom mb{};   // its levels' extents, corners and LDS offsets
   std::vector<bl_boxarray*> ba;     // levels 1..: owned coarse BoxArrays (ba[0] unused)
   std::vector<bl_multifab*> phi, f; // levels 1..: in the caller's workspace (index 0 unused)
+  // per level, during bl_mg_vcycles: phi's edge-column copies hold its current
+  // state (its last write was a one-pass smoothing call of an even count)
+  std::vector<char> edges;
   ~bl_mg() {
     for (bl_multifab* m : phi) bl_multifab_destroy(m);
     for (bl_multifab* m : f) bl_multifab_destroy(m);
@@ -1199,6 +1215,25 @@ static void mg_plan_bottom(const bl_boxarray* ba0, bl_mg* mg) {
   }
 }
 
+// nu smoothing sweeps on level l: the one-pass form where it applies on levels
+// of at least kMgOnePassCells cells and nu is even (the result then lands in phi
+// itself and its edge copies stay current), else the two colour passes.
+constexpr int64_t kMgOnePassCells = 4 << 20;
+static bl_status mg_smooth(bl_mg* mg, size_t l, bl_multifab* phi, const bl_multifab* f, double h2, int nu,
+                           hipStream_t stream) {
+  Plan& p = *phi->plan;
+  int64_t cells = 0;
+  for (const Box& b : p.boxes) cells += b.volume();
+  if (nu > 0 && nu % 2 == 0 && cells >= kMgOnePassCells && g_gsrb_one_pass.load() && gsrb1_plan(p)) {
+    bl_status st = gsrb_one_pass(p, phi, f, h2, nu, nullptr, stream, mg->edges[l] != 0);
+    mg->edges[l] = st == BL_OK;
+    return st;
+  }
+  mg->edges[l] = 0;
+  BL_HIP(gsrb_smooth(p, phi->data, f->data, h2, nu, stream));
+  return BL_OK;
+}
+
 // One V-cycle from level l (phi, f the level's MultiFabs, h2 its spacing squared).
 static bl_status vcycle(bl_mg* mg, size_t l, bl_multifab* phi, const bl_multifab* f, double h2, int nu1, int nu2,
                         int nu_bottom, hipStream_t stream) {
@@ -1211,18 +1246,21 @@ static bl_status vcycle(bl_mg* mg, size_t l, bl_multifab* phi, const bl_multifab
     BL_HIP(gsrb_smooth(p, phi->data, f->data, h2, nu_bottom, stream));
     return BL_OK;
   }
-  BL_HIP(gsrb_smooth(p, phi->data, f->data, h2, nu1, stream));
+  bl_status st = mg_smooth(mg, l, phi, f, h2, nu1, stream);
+  if (st != BL_OK) return st;
   bl_multifab* pc = mg->phi[l + 1];
   bl_multifab* fc = mg->f[l + 1];
   BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
   BL_HIP(launch_restrict_residual(p, *fc->plan, phi->data, f->data, fc->data, h2, stream));
+  fc->mirror_current = false;
   // the coarse level starts from 0 (the fused bottom sets it itself)
   if ((int)(l + 1) != mg->bottom) BL_HIP(launch_set_val(*pc->plan, pc->data, 0.0, 0, 1, 1, 256, stream));
-  bl_status st = vcycle(mg, l + 1, pc, fc, 4.0 * h2, nu1, nu2, nu_bottom, stream);
+  mg->edges[l + 1] = 0;
+  st = vcycle(mg, l + 1, pc, fc, 4.0 * h2, nu1, nu2, nu_bottom, stream);
   if (st != BL_OK) return st;
   BL_HIP(launch_prolong_add(p, *pc->plan, phi->data, pc->data, stream));
-  BL_HIP(gsrb_smooth(p, phi->data, f->data, h2, nu2, stream));
-  return BL_OK;
+  mg->edges[l] = 0;
+  return mg_smooth(mg, l, phi, f, h2, nu2, stream);
 }
 }  // namespace bl
 
@@ -1241,12 +1279,13 @@ bl_status bl_mg_vcycles(bl_mg* mg, bl_multifab* phi, const bl_multifab* f, doubl
   const Plan& p = *phi->plan;
   const size_t slots = reduce_slots(p) + 8;
   if (resnorm_host && (st = ensure_scratch(phi, slots + (size_t)ncycles, (size_t)ncycles + 8)) != BL_OK) return st;
-  if (ncycles > 0) phi->mirror_current = false;  // prolongation writes phi without its mirror
+  mg->edges.assign(mg->phi.size(), 0);  // nothing known of the levels' edge copies at the start
   for (int c = 0; c < ncycles; ++c) {
     if ((st = vcycle(mg, 0, phi, f, h2, nu1, nu2, nu_bottom, stream)) != BL_OK) return st;
     if (resnorm_host)
       BL_HIP(residual_norm_dev(p, phi->data, f->data, h2, phi->dscratch, phi->dscratch + slots + c, stream));
   }
+  if (ncycles > 0) phi->mirror_current = false;  // conservatively: prolongation writes phi without its mirror
   if (resnorm_host && ncycles > 0) {
     BL_HIP(hipMemcpyAsync(phi->hres, phi->dscratch + slots, sizeof(double) * ncycles, hipMemcpyDeviceToHost, stream));
     BL_HIP(hipStreamSynchronize(stream));

@@ -201,12 +201,12 @@ def test_384cube_gsrb_at_full_size(bt):
         phi.set_val(0.0, with_ghosts=True)
         fm.set_val(0.0, with_ghosts=True)
         fm.from_global(f)
-        bt.set_gsrb_config(one_pass, 32, 0)
+        bt.set_gsrb_config(one_pass, 0, 0)
         try:
             assert bt.gsrb_one_pass_applies(phi) == bool(one_pass)
             norms = bt.gsrb_sweeps(phi, fm, h2, sweeps)
         finally:
-            bt.set_gsrb_config(1, 32, 0)
+            bt.set_gsrb_config(1, 0, 0)
         return phi.to_global()[0].double().cpu().numpy(), norms
 
     for one_pass in (1, 0):  # the one-pass sweep (the default here) and the two colour passes

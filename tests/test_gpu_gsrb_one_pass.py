@@ -29,7 +29,7 @@ def bt():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     b = lib()
     yield b
-    b.set_gsrb_config(1, 32, 0)
+    b.set_gsrb_config(1, 0, 0)
 
 
 def _layout(name, rng):
@@ -76,7 +76,7 @@ def _run(bt, P, h2, sweeps, cfg):
         norms = bt.gsrb_sweeps(P["phi"], P["fm"], h2, sweeps)
         return applies, norms, gpu_global(P["phi"])
     finally:
-        bt.set_gsrb_config(1, 32, 0)
+        bt.set_gsrb_config(1, 0, 0)
 
 
 def _same_norms(got, ref):
@@ -91,7 +91,7 @@ def test_one_pass_fp64_equals_the_oracle(bt, layout, sweeps):
     say(f"gsrb one-pass fp64 layout={layout} sweeps={sweeps}")
     h2 = 1.0 / 1024.0
     P = _problem(bt, layout, bt.F64)
-    applies, norms, got = _run(bt, P, h2, sweeps, (1, 32, 0))
+    applies, norms, got = _run(bt, P, h2, sweeps, (1, 0, 0))
     assert applies
     onorms = O.gsrb_sweeps(P["ophi"], P["ofm"], h2, sweeps)
     ref = P["ophi"].to_global()
@@ -129,8 +129,8 @@ def test_one_pass_equals_the_two_pass_form(bt, layout):
         say(f"gsrb one-pass vs two-pass layout={layout} dtype={dtype}")
         A = _problem(bt, layout, dtype, seed=11)
         B = _problem(bt, layout, dtype, seed=11)
-        a1, n1, g1 = _run(bt, A, h2, 6, (1, 32, 0))
-        a2, n2, g2 = _run(bt, B, h2, 6, (0, 32, 0))
+        a1, n1, g1 = _run(bt, A, h2, 6, (1, 0, 0))
+        a2, n2, g2 = _run(bt, B, h2, 6, (0, 0, 0))
         assert a1 and not a2
         assert np.array_equal(g1, g2)
         _same_norms(n1, n2)
@@ -193,7 +193,7 @@ def test_fallback_where_the_one_pass_sweep_does_not_apply(bt):
     """Odd x extents: the two-pass form runs; the oracle's bits."""
     h2 = 1.0 / 1024.0
     P = _problem(bt, "odd_x", bt.F64)
-    applies, norms, got = _run(bt, P, h2, 3, (1, 32, 0))
+    applies, norms, got = _run(bt, P, h2, 3, (1, 0, 0))
     assert not applies
     onorms = O.gsrb_sweeps(P["ophi"], P["ofm"], h2, 3)
     ref = P["ophi"].to_global()
@@ -206,7 +206,7 @@ def test_configuration_calls(bt):
     try:
         bt.set_gsrb_config(0, 8, 1)
         assert bt.get_gsrb_config() == (0, 8, 1)
-        for bad in ((1, 0, 0), (1, 16, 3), (1, 16, -1)):
+        for bad in ((1, -1, 0), (1, 16, 3), (1, 16, -1)):
             with pytest.raises(bt.BoxtileError) as e:
                 bt.set_gsrb_config(*bad)
             assert e.value.code == bt.BL_EINVAL

@@ -185,6 +185,36 @@ def test_mg_degenerate_calls(bt):
         bt.prolong_add(bt.MultiFab(odd, 1, 1, bt.F64), bt.MultiFab(bt.BoxArray.chop(I.domain_box(3), 3), 1, 1, bt.F64))
 
 
+def test_vcycles_with_one_pass_smoothing(bt):
+    """A finest level of 4M cells (128 x 128 x 256, periodic, 32 boxes of 64^3), which the
+    V-cycle smooths with the one-pass sweep where the sweep count is even: two V(2,2)
+    cycles, a V(1,3) cycle (odd counts: the two colour passes there) and a V(2,2) cycle
+    again give the oracle's FP64 bits and norms; so does the two-pass form."""
+    dom, periodic = I.domain_box((128, 128, 256)), (1, 1, 1)
+    boxes = I.regular_chop(dom, 64)
+    N = (128, 128, 256)
+    f = I.zero_mean_normal_f32(N, seed=3)
+    h2 = (1.0 / 256) ** 2
+    for one_pass in (1, 0):
+        say(f"mg one-pass smoothing on 4M cells, one_pass={one_pass}")
+        ba = bt.BoxArray.from_boxes(boxes, dom, periodic)
+        phi, ophi = _pair(bt, ba, boxes, dom, periodic, bt.F64, np.zeros_like(f))
+        fm, ofm = _pair(bt, ba, boxes, dom, periodic, bt.F64, f)
+        assert bt.gsrb_one_pass_applies(phi)
+        mg = bt.Multigrid(ba, bt.F64)
+        bt.set_gsrb_config(one_pass, 0, 0)
+        try:
+            for cycles, nu1, nu2 in ((2, 2, 2), (1, 1, 3), (1, 2, 2)):
+                norms = mg.vcycles(phi, fm, h2, cycles, nu1, nu2, 8)
+                onorms = O.mg_vcycles(ophi, ofm, h2, cycles, nu1, nu2, 8)
+                assert np.array_equal(gpu_global(phi), ophi.to_global()), (one_pass, cycles, nu1, nu2)
+                for a, b in zip(norms, onorms):
+                    assert abs(a - b) <= 1e-13 * b
+        finally:
+            bt.set_gsrb_config(1, 0, 0)
+        del mg, phi, fm
+
+
 def test_repeated_vcycle_calls_on_one_hierarchy(bt):
     """Several calls on one hierarchy, with other sweep counts and another h2, continue
     from the state left by the last one and give the oracle's bits."""

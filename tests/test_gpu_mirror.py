@@ -143,11 +143,11 @@ def test_gsrb_calls_in_sequence_skip_the_extraction(bt, one_pass):
     """Two GSRB calls in a row (the second finds phi's mirror current and extracts
     nothing) give the oracle's field and norms of one run of all the sweeps, in the
     two-pass form and in the one-pass form."""
-    bt.set_gsrb_config(one_pass, 32, 0)
+    bt.set_gsrb_config(one_pass, 0, 0)
     try:
         _gsrb_in_sequence(bt)
     finally:
-        bt.set_gsrb_config(1, 32, 0)
+        bt.set_gsrb_config(1, 0, 0)
 
 
 def _gsrb_in_sequence(bt):

@@ -237,12 +237,12 @@ def test_gsrb_fp64_bit_exact_with_norms(bt, one_pass):
     n, sweeps = 32, 6
     h2 = (1.0 / n) ** 2
     phi, fm, ophi, ofm = _gsrb_problem(n, 16, bt.F64)
-    bt.set_gsrb_config(one_pass, 32, 0)
+    bt.set_gsrb_config(one_pass, 0, 0)
     try:
         assert bt.gsrb_one_pass_applies(phi) == bool(one_pass)
         norms = bt.gsrb_sweeps(phi, fm, h2, sweeps)
     finally:
-        bt.set_gsrb_config(1, 32, 0)
+        bt.set_gsrb_config(1, 0, 0)
     onorms = O.gsrb_sweeps(ophi, ofm, h2, sweeps)
     assert np.array_equal(gpu_global(phi), ophi.to_global())
     for g, r in zip(norms, onorms):
@@ -255,11 +255,11 @@ def test_gsrb_fp32_state_against_fp64_oracle(bt, one_pass):
     n, sweeps = 64, 20
     h2 = (1.0 / n) ** 2
     phi, fm, ophi, ofm = _gsrb_problem(n, 32, bt.F32)
-    bt.set_gsrb_config(one_pass, 32, 0)
+    bt.set_gsrb_config(one_pass, 0, 0)
     try:
         norms = bt.gsrb_sweeps(phi, fm, h2, sweeps)
     finally:
-        bt.set_gsrb_config(1, 32, 0)
+        bt.set_gsrb_config(1, 0, 0)
     onorms = O.gsrb_sweeps(ophi, ofm, h2, sweeps)
     err = rel_err(gpu_global(phi), ophi.to_global())
     nerr = max(abs(g - r) / r for g, r in zip(norms, onorms))
@@ -445,7 +445,7 @@ def test_gsrb_every_form_bit_exact_on_uneven_layouts(bt, cfg, layout):
     h2, sweeps = 1.0 / 1024.0, 4
     saved = bt.get_tile_config()
     bt.set_tile_config(*cfg)
-    bt.set_gsrb_config(0, 32, 0)
+    bt.set_gsrb_config(0, 0, 0)
     try:
         say(f"gsrb cfg {cfg} layout={layout}")
         _, phi, fm, ophi = make_pair(boxes, dom, periodic, 1, 1, bt.F64, g0, ghost_value=0.25)
@@ -456,7 +456,7 @@ def test_gsrb_every_form_bit_exact_on_uneven_layouts(bt, cfg, layout):
         got = gpu_global(phi)
     finally:
         bt.set_tile_config(*saved)
-        bt.set_gsrb_config(1, 32, 0)
+        bt.set_gsrb_config(1, 0, 0)
     ofm = O.OracleMultiFab(boxes, dom, periodic, 1, 1)
     ofm.load_global(f)
     onorms = O.gsrb_sweeps(ophi, ofm, h2, sweeps)
