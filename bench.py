@@ -576,9 +576,9 @@ def mg_run(bt, I, torch, seed: int, cycles: int = 5) -> dict:
 
 def heat8_run(bt, I, torch, boxes, dom, u0, ncomp: int, steps: int = 10) -> dict:
     """The 8th-order heat step (9-cell span, 4 ghost layers) on the same level and u0, FP64,
-    c = 0.09, in both forms: fused (neighbour boxes read directly, the default where the
-    layout allows it) and fill (FillBoundary of the 4 layers, then the stencil; the two
-    timed apart)."""
+    c = 0.09, in each form: fused (neighbour boxes read directly, the default where the
+    layout allows it), fused with the 4-layer edge mirrors, and fill (FillBoundary of the
+    4 layers, then the stencil; the two timed apart)."""
     n = int(dom[3]) + 1
     ba = bt.BoxArray.from_boxes(boxes, dom)
     a, b = bt.MultiFab(ba, ncomp, 4, bt.F64), bt.MultiFab(ba, ncomp, 4, bt.F64)
@@ -601,6 +601,10 @@ def heat8_run(bt, I, torch, boxes, dom, u0, ncomp: int, steps: int = 10) -> dict
     fill = per_step(lambda k: [a.fill_boundary() for _ in range(k)])
     fused_ok = bt.heat8_fused_ok(a)
     fused = per_step(lambda k: bt.heat8_advance(a, b, k, 0.09, form="fused")) if fused_ok else None
+    try:
+        mirror = per_step(lambda k: bt.heat8_advance(a, b, k, 0.09, form="fused_mirror"))
+    except bt.BoxtileError:  # a box narrower than 8 cells in x
+        mirror = None
     form = bt.heat8_auto_form(a)
     ms = fused if form == "fused" else fill_form
     kern = fill_form - fill
@@ -608,12 +612,14 @@ def heat8_run(bt, I, torch, boxes, dom, u0, ncomp: int, steps: int = 10) -> dict
     out = {"workload": f"{n}^3 periodic, {len(boxes)} uneven boxes, {ncomp} comps, 4 ghost layers, FP64",
            "form": form, "ms_per_step": round(ms, 4),
            "fused_form_ms_per_step": round(fused, 4) if fused_ok else None,
+           "fused_mirror_form_ms_per_step": round(mirror, 4) if mirror is not None else None,
            "gcell_s": round(cells / (ms / 1e3) / 1e9, 2), "step_gbs_at_16B": round(gbs, 1),
            "step_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
            "fill_form": {"ms_per_step": round(fill_form, 4), "fill_ms": round(fill, 4), "stencil_ms": round(kern, 4),
                          "stencil_gbs_at_16B": round(16 * cells / (kern / 1e3) / 1e9, 1)}}
     log(f"heat8: {ms:.3f} ms/step (default: {form} form, {gbs:.0f} GB/s at 16 B/cell); fill form {fill_form:.3f} ms "
-        f"(fill {fill:.3f}, stencil {kern:.3f}); fused form " + (f"{fused:.3f} ms" if fused_ok else "n/a"))
+        f"(fill {fill:.3f}, stencil {kern:.3f}); fused form " + (f"{fused:.3f} ms" if fused_ok else "n/a") +
+        "; with the 4-layer mirrors " + (f"{mirror:.3f} ms" if mirror is not None else "n/a"))
     del a, b, ba
     torch.cuda.empty_cache()
     return out

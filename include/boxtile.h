@@ -203,17 +203,18 @@ void bl_multifab_destroy(bl_multifab* mf);
 
 /*
  * Next to each box's valid cells the storage holds a copy of the box's first
- * and last valid x column, contiguous along y (its edge mirror).  Reading a
- * neighbour box's x face from that copy costs a few contiguous lines instead
- * of one line per row.  The library remembers, per MultiFab, whether the copy
- * is current: the calls that write it with the state they produce (the fused
- * heat, GSRB and variable-coefficient steps, the unfused heat step's stencil)
- * mark it so, every other write by the library marks it stale, and later calls
- * read the copy only where it is current (the first step of an advance,
- * FillBoundary, the first GSRB pass).  A caller who writes a MultiFab's
- * storage without the library (through its own kernels or copies) must call
- * bl_multifab_modified before the MultiFab's next use; otherwise a later call
- * may read a stale copy.  BL_EINVAL for NULL.
+ * and last valid x column, contiguous along y (its edge mirror; with nghost
+ * >= 4, of its first and last 4 columns).  Reading a neighbour box's x face
+ * from that copy costs a few contiguous lines instead of one line per row.
+ * The library remembers, per MultiFab, whether the copy is current: the calls
+ * that write it with the state they produce (the fused heat, GSRB and
+ * variable-coefficient steps, the 8th-order mirror form, the unfused heat
+ * step's stencil) mark it so, every other write by the library marks it
+ * stale, and later calls read the copy only where it is current (the first
+ * step of an advance, FillBoundary, the first GSRB pass).  A caller who writes
+ * a MultiFab's storage without the library (through its own kernels or
+ * copies) must call bl_multifab_modified before the MultiFab's next use;
+ * otherwise a later call may read a stale copy.  BL_EINVAL for NULL.
  */
 bl_status bl_multifab_modified(bl_multifab* mf);
 
@@ -292,10 +293,20 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
  *                vectors of more than one cell, neighbour boundaries fall on
  *                x-vector edges (bl_heat8_fused_ok); else BL_EINVAL.
  *   BL_H8_AUTO   the fused form where it applies, else the fill form.
- * The fill form writes u_old's ghost cells each step; the fused form writes no
+ *   BL_H8_FUSED_MIRROR  the fused form that also writes u_new's 4-layer edge
+ *                mirror (copies of the first and last 4 valid x columns,
+ *                contiguous along y; see bl_multifab_modified) and, where its
+ *                input's mirror is current, reads the x-face cells a neighbour
+ *                covers from that neighbour's mirror instead of its rows (a few
+ *                contiguous lines per face plane instead of one line per row).
+ *                The first step of a call reads the rows unless the previous
+ *                call left u[0]'s mirror current.  Needs every box at least 8
+ *                cells wide in x (BL_EINVAL).  Fewer bytes fetched, more
+ *                written; BL_H8_AUTO does not pick it.
+ * The fill form writes u_old's ghost cells each step; the fused forms write no
  * ghost cell.  bl_heat8_advance is bl_heat8_advance_form with BL_H8_AUTO.
  */
-typedef enum { BL_H8_AUTO = 0, BL_H8_FILL = 1, BL_H8_FUSED = 2 } bl_h8_form;
+typedef enum { BL_H8_AUTO = 0, BL_H8_FILL = 1, BL_H8_FUSED = 2, BL_H8_FUSED_MIRROR = 3 } bl_h8_form;
 bl_status bl_heat8_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream_t stream);
 bl_status bl_heat8_advance_form(bl_multifab* u[2], int32_t nsteps, double c, int32_t form, hipStream_t stream);
 /* *ok = 1 where the fused form applies to mf's layout, else 0 (also for
@@ -306,8 +317,10 @@ bl_status bl_heat8_fused_ok(const bl_multifab* mf, int32_t* ok);
 /*
  * Host-only views of the metadata above, for checking it without a GPU (no
  * device memory is touched).  bl_heat8_fused_layout: the face segments the
- * fused 8th-order form would use for a MultiFab of this shape; *nsegs their
- * count; with segs non-NULL, 12 int64 per segment {box, face (2*axis + side),
+ * fused 8th-order form would use for a MultiFab of this shape (from_mirror = 0:
+ * those of a step that reads neighbour rows; 1: those of a step whose input's
+ * 4-layer mirror is current, BL_EINVAL where a box is narrower than 8 cells in
+ * x); *nsegs their count; with segs non-NULL, 12 int64 per segment {box, face (2*axis + side),
  * t1lo, t1hi, t2lo, t2hi, o, sc, sx, sy, sz, vec}: the segment covers the 4 cell
  * layers of that face over box-local tangential coordinates (t1, t2) in
  * [t1lo, t1hi] x [t2lo, t2hi] ((y, z) for x faces, (x, z) for y faces, (x, y)
@@ -316,11 +329,17 @@ bl_status bl_heat8_fused_ok(const bl_multifab* mf, int32_t* ok);
  * element count.  BL_EINVAL (reason in bl_last_error) where the fused form
  * does not apply.  bl_layout_index: element index of cell (global indices,
  * inside box's grown box) of component comp in a MultiFab of this shape.
+ * bl_layout_mirror_index: element index of row j, plane k (global indices,
+ * inside box's valid box) of layer `layer` of side `side` (0 low x, 1 high x)
+ * of box's edge mirror, the copy of valid column `layer` (side 0) or
+ * ex-1-layer (side 1); 4 layers with nghost >= 4, else 1 (BL_EINVAL beyond).
  */
-bl_status bl_heat8_fused_layout(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype, int32_t* nsegs,
-                                int64_t* segs, int64_t* total_elems);
+bl_status bl_heat8_fused_layout(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype,
+                                int32_t from_mirror, int32_t* nsegs, int64_t* segs, int64_t* total_elems);
 bl_status bl_layout_index(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype, int32_t box,
                           const int32_t cell[3], int32_t comp, int64_t* index);
+bl_status bl_layout_mirror_index(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype, int32_t box,
+                                 int32_t side, int32_t layer, int32_t j, int32_t k, int32_t comp, int64_t* index);
 
 /*
  * nsteps forward-Euler steps of du/dt = div(beta grad u) in the flux form

@@ -73,8 +73,9 @@ _SIGS = {
     "bl_heat8_advance": [_vpp, _i32, ctypes.c_double, _vp],
     "bl_heat8_advance_form": [_vpp, _i32, ctypes.c_double, _i32, _vp],
     "bl_heat8_fused_ok": [_vp, _i32p],
-    "bl_heat8_fused_layout": [_vp, _i32, _i32, _i32, _i32p, _i64p, _i64p],
+    "bl_heat8_fused_layout": [_vp, _i32, _i32, _i32, _i32, _i32p, _i64p, _i64p],
     "bl_layout_index": [_vp, _i32, _i32, _i32, _i32, _i32p, _i32, _i64p],
+    "bl_layout_mirror_index": [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i64p],
     "bl_device_copy": [_vp, _vp, ctypes.c_size_t, _vp],
     "bl_heat_step_unfused": [_vp, _vp, ctypes.c_double, _vp],
     "bl_gsrb_sweeps": [_vp, _vp, ctypes.c_double, _i32, _dp, _vp],
@@ -266,17 +267,30 @@ class BoxArray:
                                 out.ctypes.data_as(_i32p)))
         return out
 
-    def heat8_fused_layout(self, ncomp: int, nghost: int, dtype: int = F64):
+    def heat8_fused_layout(self, ncomp: int, nghost: int, dtype: int = F64, from_mirror: bool = False):
         """Host-only: the face segments of the fused 8th-order form for a MultiFab of this
         shape, as (segs, total_elems): segs rows {box, face, t1lo, t1hi, t2lo, t2hi, o, sc, sx,
-        sy, sz, vec}.  BoxtileError where the fused form does not apply."""
+        sy, sz, vec}.  from_mirror: the segments of a step whose input's 4-layer edge mirror is
+        current (covered x faces read the neighbours' mirrors).  BoxtileError where the form
+        does not apply."""
         n = ctypes.c_int32()
         total = ctypes.c_int64()
-        _check(_L.bl_heat8_fused_layout(self._h, ncomp, nghost, dtype, ctypes.byref(n), None, ctypes.byref(total)))
-        segs = np.zeros((n.value, 12), dtype=np.int64)
-        _check(_L.bl_heat8_fused_layout(self._h, ncomp, nghost, dtype, ctypes.byref(n), segs.ctypes.data_as(_i64p),
+        fm = 1 if from_mirror else 0
+        _check(_L.bl_heat8_fused_layout(self._h, ncomp, nghost, dtype, fm, ctypes.byref(n), None,
                                         ctypes.byref(total)))
+        segs = np.zeros((n.value, 12), dtype=np.int64)
+        _check(_L.bl_heat8_fused_layout(self._h, ncomp, nghost, dtype, fm, ctypes.byref(n),
+                                        segs.ctypes.data_as(_i64p), ctypes.byref(total)))
         return segs, total.value
+
+    def layout_mirror_index(self, ncomp: int, nghost: int, dtype: int, box: int, side: int, layer: int, j: int,
+                            k: int, comp: int) -> int:
+        """Host-only: element index of row j, plane k (global) of layer `layer` of side `side` of
+        a box's edge mirror (the copy of valid column `layer`, or ex-1-layer on side 1)."""
+        out = ctypes.c_int64()
+        _check(_L.bl_layout_mirror_index(self._h, ncomp, nghost, dtype, int(box), int(side), int(layer), int(j),
+                                         int(k), int(comp), ctypes.byref(out)))
+        return out.value
 
     def layout_index(self, ncomp: int, nghost: int, dtype: int, box: int, cell, comp: int) -> int:
         """Host-only: element index of a cell (global indices, in the box's grown box)."""
@@ -523,14 +537,15 @@ def device_copy(dst: torch.Tensor, src: torch.Tensor, stream=None) -> None:
                              _stream(stream)))
 
 
-H8_FORMS = {"auto": 0, "fill": 1, "fused": 2}
+H8_FORMS = {"auto": 0, "fill": 1, "fused": 2, "fused_mirror": 3}
 
 
 def heat8_advance(u0: MultiFab, u1: MultiFab, nsteps: int, c: float, stream=None, form: str = "auto") -> MultiFab:
     """nsteps heat steps with the 8th-order second difference (nghost >= 4), one stencil
     launch per step: form "fill" (FillBoundary first), "fused" (neighbour boxes read
-    directly; BoxtileError where the layout does not allow it) or "auto" (heat8_auto_form);
-    returns the result holder."""
+    directly; BoxtileError where the layout does not allow it), "fused_mirror" (the fused
+    form writing and reading the 4-layer edge mirrors; boxes at least 8 cells wide in x)
+    or "auto" (heat8_auto_form); returns the result holder."""
     arr = (ctypes.c_void_p * 2)(u0.handle.value, u1.handle.value)
     _check(_L.bl_heat8_advance_form(arr, int(nsteps), float(c), H8_FORMS[form], _stream(stream)))
     return u0 if nsteps % 2 == 0 else u1

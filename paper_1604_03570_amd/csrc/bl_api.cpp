@@ -37,6 +37,7 @@ Plan::~Plan() {
   (void)hipFree(dpairpre);
   (void)hipFree(dh8);
   (void)hipFree(dh8seg);
+  (void)hipFree(dh8segm);
   (void)hipFree(dh8face);
   (void)hipFree(dcellwg);
   (void)hipFree(dpairwg);
@@ -298,7 +299,7 @@ bl_status bl_multifab_copy_fab(bl_multifab* mf, int32_t box, int32_t scomp, int3
   const Plan& p = *mf->plan;
   if (box < 0 || box >= (int)p.fabs.size()) return fail(BL_EINVAL, "box %d out of range", box);
   if (scomp < 0 || ncomp < 1 || scomp + ncomp > p.ncomp) return fail(BL_EINVAL, "component range out of bounds");
-  if (!to_dense) mf->mirror_current = false;
+  if (!to_dense) mf->mark_mirror(false);
   BL_HIP(launch_copy_fab(p, mf->data, dense_dev, box, scomp, ncomp, to_dense, stream));
   return BL_OK;
 }
@@ -306,7 +307,7 @@ bl_status bl_multifab_copy_fab(bl_multifab* mf, int32_t box, int32_t scomp, int3
 bl_status bl_multifab_modified(bl_multifab* mf) {
   clear_error();
   if (!mf) return fail(BL_EINVAL, "NULL MultiFab");
-  mf->mirror_current = false;
+  mf->mark_mirror(false);
   return BL_OK;
 }
 
@@ -328,7 +329,7 @@ bl_status bl_multifab_copy_global(bl_multifab* mf, int32_t scomp, int32_t ncomp,
   if (!mf || !global_dev) return fail(BL_EINVAL, "NULL argument");
   const Plan& p = *mf->plan;
   if (scomp < 0 || ncomp < 1 || scomp + ncomp > p.ncomp) return fail(BL_EINVAL, "component range out of bounds");
-  if (!to_global) mf->mirror_current = false;
+  if (!to_global) mf->mark_mirror(false);
   BL_HIP(launch_copy_global(p, mf->data, global_dev, scomp, ncomp, to_global, block_of(p), stream));
   return BL_OK;
 }
@@ -339,7 +340,7 @@ bl_status bl_multifab_set_val(bl_multifab* mf, double val, int32_t scomp, int32_
   if (!mf) return fail(BL_EINVAL, "NULL MultiFab");
   const Plan& p = *mf->plan;
   if (scomp < 0 || ncomp < 1 || scomp + ncomp > p.ncomp) return fail(BL_EINVAL, "component range out of bounds");
-  mf->mirror_current = false;
+  mf->mark_mirror(false);
   BL_HIP(launch_set_val(p, mf->data, val, scomp, ncomp, with_ghosts, block_of(p), stream));
   return BL_OK;
 }
@@ -377,7 +378,7 @@ bl_status bl_heat_step(bl_multifab* u_old, bl_multifab* u_new, double c, int32_t
   if (st != BL_OK) return st;
   const Plan& p = *u_old->plan;
   if (fill_first) BL_HIP(launch_fill(p, u_old->data, 0, p.ncomp, stream, u_old->mirror_current));
-  u_new->mirror_current = false;  // the per-box kernels do not write the edge mirror
+  u_new->mark_mirror(false);  // the per-box kernels do not write the edge mirror
   HeatArgs a{};
   a.fvec = p.fvec;
   a.zblock = p.cfg.block ? p.cfg.zchunk : 0;
@@ -407,7 +408,7 @@ bl_status bl_heat_step_unfused(bl_multifab* u_old, bl_multifab* u_new, double c,
              p.fvec, p.cfg.block ? p.cfg.zchunk : 0, p.cfg.block, p.rmax, p.nvtmax,
              p.dlin, (int)p.hlin.size(), p.yhmax, p.xhmax};
   // the halo-in-LDS kernel over linear tiles writes the output's edge mirror, the others do not
-  u_new->mirror_current = p.cfg.block == 3 && p.dlin != nullptr;
+  u_new->mark_mirror(p.cfg.block == 3 && p.dlin != nullptr);
   BL_HIP(launch_heat(p.dtype, p.vec, false, a, persistent_grid(tile_config().persist), block_of(p), stream));
   return BL_OK;
 }
@@ -468,8 +469,8 @@ bl_status bl_heat_advance(bl_multifab* u[2], int32_t nsteps, double c, hipStream
     g_graphs.push_back({key, exec});
   }
   BL_HIP(hipGraphLaunch(exec, stream));
-  if (nsteps >= 2 || !rows_first) u[0]->mirror_current = true;  // written by step 1, extracted or kept
-  u[1]->mirror_current = true;                                    // written by step 0
+  if (nsteps >= 2 || !rows_first) u[0]->mark_mirror(true);  // written by step 1, extracted or kept
+  u[1]->mark_mirror(true);                                    // written by step 0
   return BL_OK;
 }
 
@@ -542,7 +543,7 @@ bl_status bl_heat_varcoef_advance(bl_multifab* u[2], bl_multifab* beta, int32_t 
   if (a.fused) {  // neighbour values from the neighbour boxes' faces and edge mirrors
     if (!beta->mirror_current) BL_HIP(launch_extract_mirror(p, beta->data, stream));
     if (!u[0]->mirror_current) BL_HIP(launch_extract_mirror(p, u[0]->data, stream));
-    beta->mirror_current = true;
+    beta->mark_mirror(true);
   } else {
     BL_HIP(launch_fill(p, beta->data, 0, p.ncomp, stream, beta->mirror_current));
   }
@@ -553,8 +554,8 @@ bl_status bl_heat_varcoef_advance(bl_multifab* u[2], bl_multifab* beta, int32_t 
     BL_HIP(launch_heat_varcoef(p.dtype, p.vec, a, stream));
   }
   // the kernel writes its output's edge mirror (both forms)
-  u[0]->mirror_current = a.fused || nsteps >= 2 || u[0]->mirror_current;
-  u[1]->mirror_current = true;
+  u[0]->mark_mirror(a.fused || nsteps >= 2 || u[0]->mirror_current);
+  u[1]->mark_mirror(true);
   return BL_OK;
 }
 
@@ -563,19 +564,26 @@ bl_status bl_heat_varcoef_advance(bl_multifab* u[2], bl_multifab* beta, int32_t 
 // g_vc_mu.
 static bl_status h8_segments(Plan& p, bool* ok) {
   if (p.h8fused < 0) {
-    std::vector<DevH8Seg> sv;
+    std::vector<DevH8Seg> sv, mv;
     std::vector<DevH8Face> fv;
     std::string why;
-    if (build_h8_segments(p, sv, fv, &why)) {
+    if (build_h8_segments(p, sv, fv, &why, &mv)) {
       bl_status st = upload(&p.dh8seg, sv, "hipMalloc/hipMemcpy(8th-order face segments)");
       if (st == BL_OK) st = upload(&p.dh8face, fv, "hipMalloc/hipMemcpy(8th-order faces)");
+      if (st == BL_OK && !mv.empty()) st = upload(&p.dh8segm, mv, "hipMalloc/hipMemcpy(8th-order mirror segments)");
       if (st != BL_OK) {
         (void)hipFree(p.dh8seg);
+        (void)hipFree(p.dh8face);
+        (void)hipFree(p.dh8segm);
         p.dh8seg = nullptr;
+        p.dh8face = nullptr;
+        p.dh8segm = nullptr;
         return st;
       }
       p.hh8seg.swap(sv);
       p.hh8face.swap(fv);
+      p.h8mirror = !mv.empty();
+      p.hh8segm.swap(mv);
       p.h8fused = 1;
     } else {
       p.h8why = why;
@@ -594,14 +602,17 @@ bl_status bl_heat8_advance_form(bl_multifab* u[2], int32_t nsteps, double c, int
   Plan& p = *u[0]->plan;
   if (p.ng < 4) return fail(BL_EINVAL, "the 8th-order stencil needs nghost >= 4, not %d", p.ng);
   if (nsteps < 0) return fail(BL_EINVAL, "nsteps < 0");
-  if (form < BL_H8_AUTO || form > BL_H8_FUSED) return fail(BL_EINVAL, "unknown 8th-order form %d", (int)form);
+  if (form < BL_H8_AUTO || form > BL_H8_FUSED_MIRROR)
+    return fail(BL_EINVAL, "unknown 8th-order form %d", (int)form);
   bool fused = false;
   {
     std::lock_guard<std::mutex> lk(g_vc_mu);
     if (form != BL_H8_FILL) {
       if ((st = h8_segments(p, &fused)) != BL_OK) return st;
-      if (!fused && form == BL_H8_FUSED)
+      if (!fused && (form == BL_H8_FUSED || form == BL_H8_FUSED_MIRROR))
         return fail(BL_EINVAL, "the fused 8th-order form does not apply to this layout: %s", p.h8why.c_str());
+      if (form == BL_H8_FUSED_MIRROR && !p.h8mirror)
+        return fail(BL_EINVAL, "the 4-layer mirror form needs every box at least 8 cells wide in x");
     }
     if (!p.h8built) {  // both forms run over the same tiles
       std::vector<DevTile> t;
@@ -614,14 +625,23 @@ bl_status bl_heat8_advance_form(bl_multifab* u[2], int32_t nsteps, double c, int
       p.h8built = true;
     }
   }
-  if (nsteps > 0) u[1]->mirror_current = false;  // the 8th-order kernels do not write the edge mirror
-  if (nsteps > 1) u[0]->mirror_current = false;
+  // the mirror form writes every output's 4-layer mirror, and reads its
+  // input's where that is current: from step 1 on, and at step 0 where the
+  // last write to u[0] was such a step
+  const bool mir = form == BL_H8_FUSED_MIRROR;
+  const bool start_mirror = u[0]->mirror4_current;
   for (int s = 0; s < nsteps; ++s) {
     void* src = u[s & 1]->data;
     void* dst = u[(s + 1) & 1]->data;
     if (!fused) BL_HIP(launch_fill(p, src, 0, p.ncomp, stream));
-    BL_HIP(launch_heat8(p.dtype, p.vec, p.dh8, fused ? p.dh8seg : nullptr, fused ? p.dh8face : nullptr,
-                        (int)p.hh8.size(), p.dboxes, src, dst, c, p.h8rmax, p.h8nvtmax, stream));
+    const DevH8Seg* segs = !fused ? nullptr : (mir && (s > 0 || start_mirror)) ? p.dh8segm : p.dh8seg;
+    BL_HIP(launch_heat8(p.dtype, p.vec, p.dh8, segs, fused ? p.dh8face : nullptr, (int)p.hh8.size(), p.dboxes, src,
+                        dst, c, p.h8rmax, p.h8nvtmax, mir, stream));
+  }
+  for (int s = 0; s < nsteps && s < 2; ++s) {  // the MultiFabs steps s and s+2, ... wrote
+    bl_multifab* out = u[(s + 1) & 1];
+    out->mark_mirror(mir);
+    out->mirror4_current = mir;
   }
   return BL_OK;
 }
@@ -878,7 +898,7 @@ static bl_status gsrb_one_pass(Plan& p, bl_multifab* phi, const bl_multifab* f, 
   bl_multifab* fm = const_cast<bl_multifab*>(f);  // f's values are not changed: only its edge mirror is written
   if (!fm->mirror_current) {
     BL_HIP(launch_extract_mirror(p, fm->data, stream));
-    fm->mirror_current = true;
+    fm->mark_mirror(true);
   }
   // ghost cells no box covers keep their values in both buffers (and a new
   // second buffer starts as a copy, so that it holds no undefined values)
@@ -896,7 +916,7 @@ static bl_status gsrb_one_pass(Plan& p, bl_multifab* phi, const bl_multifab* f, 
       BL_HIP(launch_reduce_partials(slots + ((s - 1) & 1 ? nw : 0), 2 * nw, 1, norms + s - 1, stream));
   }
   if (nsweeps & 1) BL_HIP(hipMemcpyAsync(phi->data, phi->dtwin, phi->bytes, hipMemcpyDeviceToDevice, stream));
-  phi->mirror_current = true;
+  phi->mark_mirror(true);
   if (slots) {
     BL_HIP(residual_norm_dev(p, phi, f, h2, slots + 3 * nw, norms + nsweeps - 1, stream));
     BL_HIP(hipMemcpyAsync(phi->hres, norms, sizeof(double) * nsweeps, hipMemcpyDeviceToHost, stream));
@@ -932,7 +952,7 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
     // many sweeps one extraction costs less than a first pass reading the
     // neighbours' rows
     if (nsweeps > 0 && !phi->mirror_current) BL_HIP(launch_extract_mirror(p, phi->data, stream));
-    if (nsweeps > 0) phi->mirror_current = true;  // every colour pass writes it
+    if (nsweeps > 0) phi->mark_mirror(true);  // every colour pass writes it
     for (int s = 0; s < nsweeps; ++s) {
       BL_HIP(launch_gsrb_fused(p, phi->data, f->data, h2, 0, 0, s > 0 ? red_part : nullptr, grid, block_of(p),
                                stream));
@@ -949,7 +969,7 @@ bl_status bl_gsrb_sweeps(bl_multifab* phi, const bl_multifab* f, double h2, int3
     return BL_OK;
   }
   if (resnorm_host && (st = ensure_scratch(phi, nt + (size_t)nsweeps + 8, (size_t)nsweeps + 8)) != BL_OK) return st;
-  if (nsweeps > 0) phi->mirror_current = false;  // the colour passes of this form do not write it
+  if (nsweeps > 0) phi->mark_mirror(false);  // the colour passes of this form do not write it
   for (int s = 0; s < nsweeps; ++s) {
     for (int color = 0; color < 2; ++color) {
       BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
@@ -1024,7 +1044,7 @@ bl_status bl_mg_restrict_residual(bl_multifab* phi, const bl_multifab* f, double
   if (phi->plan->ng < 1) return fail(BL_EINVAL, "the residual needs nghost >= 1");
   if (fc->data == phi->data || fc->data == f->data) return fail(BL_EINVAL, "fc shares storage with phi or f");
   BL_HIP(launch_fill(*phi->plan, phi->data, 0, 1, stream, phi->mirror_current));
-  fc->mirror_current = false;
+  fc->mark_mirror(false);
   BL_HIP(launch_restrict_residual(*phi->plan, *fc->plan, phi->data, f->data, fc->data, h2, stream));
   return BL_OK;
 }
@@ -1034,7 +1054,7 @@ bl_status bl_mg_prolong_add(bl_multifab* phi, const bl_multifab* pc, hipStream_t
   bl_status st = check_transfer(phi, pc);
   if (st != BL_OK) return st;
   if (pc->data == phi->data) return fail(BL_EINVAL, "pc shares storage with phi");
-  phi->mirror_current = false;
+  phi->mark_mirror(false);
   BL_HIP(launch_prolong_add(*phi->plan, *pc->plan, phi->data, pc->data, stream));
   return BL_OK;
 }
@@ -1252,7 +1272,7 @@ static bl_status vcycle(bl_mg* mg, size_t l, bl_multifab* phi, const bl_multifab
   bl_multifab* fc = mg->f[l + 1];
   BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
   BL_HIP(launch_restrict_residual(p, *fc->plan, phi->data, f->data, fc->data, h2, stream));
-  fc->mirror_current = false;
+  fc->mark_mirror(false);
   // the coarse level starts from 0 (the fused bottom sets it itself)
   if ((int)(l + 1) != mg->bottom) BL_HIP(launch_set_val(*pc->plan, pc->data, 0.0, 0, 1, 1, 256, stream));
   mg->edges[l + 1] = 0;
@@ -1285,7 +1305,7 @@ bl_status bl_mg_vcycles(bl_mg* mg, bl_multifab* phi, const bl_multifab* f, doubl
     if (resnorm_host)
       BL_HIP(residual_norm_dev(p, phi->data, f->data, h2, phi->dscratch, phi->dscratch + slots + c, stream));
   }
-  if (ncycles > 0) phi->mirror_current = false;  // conservatively: prolongation writes phi without its mirror
+  if (ncycles > 0) phi->mark_mirror(false);  // conservatively: prolongation writes phi without its mirror
   if (resnorm_host && ncycles > 0) {
     BL_HIP(hipMemcpyAsync(phi->hres, phi->dscratch + slots, sizeof(double) * ncycles, hipMemcpyDeviceToHost, stream));
     BL_HIP(hipStreamSynchronize(stream));
@@ -1412,8 +1432,8 @@ bl_status bl_autotune(const bl_boxarray* ba, bl_multifab* u0, bl_multifab* u1, d
   }
   forget_graphs(u0);
   forget_graphs(u1);
-  u0->mirror_current = false;  // the trial steps overwrote both
-  u1->mirror_current = false;
+  u0->mark_mirror(false);  // the trial steps overwrote both
+  u1->mark_mirror(false);
   u0->plan = best_plan;
   u1->plan = best_plan;
   if (best) {
@@ -1760,8 +1780,8 @@ bl_status bl_batch_add(bl_batch* b, bl_multifab* u0, bl_multifab* u1, double c, 
   bl_batch::Member m;
   m.u0 = u0;
   m.u1 = u1;
-  u0->mirror_current = false;  // the batch keeps its own record while the pair is a member
-  u1->mirror_current = false;
+  u0->mark_mirror(false);  // the batch keeps its own record while the pair is a member
+  u1->mark_mirror(false);
   m.c = c;
   m.joined = b->tick;
   m.id = b->next_id++;

@@ -129,7 +129,10 @@ namespace bl {
 //   mirror: a copy of the box's own first (s = 0) and last (s = 1) valid x
 //           column, contiguous along y: mir + s*mir_side + k*ey + j.  The fused
 //           stencil writes it with each new state; neighbours read their x
-//           face values from it.
+//           face values from it.  With nghost >= 4 it holds 4 layers per side,
+//           layer m (m = 0..3: column m, or column ex-1-m on side 1) at
+//           mir + s*mir_side + m*ey*ez + k*ey + j, so layer 0 is where the
+//           1-layer copy is; the fused 8th-order step writes all 4.
 struct DevBox {
   int64_t off;       // row cell (0,0,0), component 0
   int64_t sc;        // component stride
@@ -305,6 +308,7 @@ struct FabGeom {
   int64_t sy, sz, sc;
   int64_t xs, xs_side, xs_z;
   int64_t mir, mir_side;
+  int mir_layers;     // 4 with nghost >= 4, else 1 (layer stride ey*ez)
   int ng;
   // element index (component 0) of any cell of the grown box, global indices
   int64_t index(int i, int j, int k) const {
@@ -411,6 +415,13 @@ struct Plan {
   DevH8Face* dh8face = nullptr;
   int h8fused = -1;
   std::string h8why;
+  // the same segments with every x-face segment a neighbour covers reading
+  // that neighbour's 4-layer edge mirror instead of its rows; h8mirror: the
+  // fused form writes its output's 4-layer mirror and may read them (every
+  // box at least 8 cells wide in x)
+  std::vector<DevH8Seg> hh8segm;
+  DevH8Seg* dh8segm = nullptr;
+  bool h8mirror = false;
 
   ~Plan();
 };
@@ -438,7 +449,11 @@ void build_h8_tiles(const Plan& p, std::vector<DevTile>& tiles, int* rmax, int* 
 // False (reason in *why) where the form does not apply: a neighbour thinner
 // than the 4 layers across a face, or (vectors of more than one cell) a y- or
 // z-face segment edge inside an x vector or a source row not vector-aligned.
-bool build_h8_segments(const Plan& p, std::vector<DevH8Seg>& segs, std::vector<DevH8Face>& faces, std::string* why);
+// With msegs: also the segments that read x faces from the neighbours' 4-layer
+// edge mirrors (same order and tangential ranges; left empty where some box is
+// narrower than 8 cells in x, whose two mirror sides would share columns).
+bool build_h8_segments(const Plan& p, std::vector<DevH8Seg>& segs, std::vector<DevH8Face>& faces, std::string* why,
+                       std::vector<DevH8Seg>* msegs = nullptr);
 
 }  // namespace bl
 
@@ -451,6 +466,15 @@ struct bl_multifab {
   // cleared by every other write (and by bl_multifab_modified for writes made
   // outside the library)
   bool mirror_current = false;
+  // layers 1..3 of the 4-layer mirror (nghost >= 4) are current too: set only
+  // by the fused 8th-order step, which writes all 4
+  bool mirror4_current = false;
+  // every write by the library but that step: layer 0 current or not, and the
+  // other layers stale
+  void mark_mirror(bool layer0_current) {
+    mirror_current = layer0_current;
+    mirror4_current = false;
+  }
   // the one-pass red-black sweep's second edge-column copy (columns 1 and ex-2
   // of component 0), allocated on first use
   void* dmir2 = nullptr;

@@ -1291,17 +1291,24 @@ __device__ __forceinline__ DevH8Seg h8_find(const DevH8Seg* __restrict__ segs, i
 // flight across it.  One barrier per plane.  Cells outside the box come from
 // the FAB's filled ghosts (x: the x ghost slab), or, FUSED, straight from
 // their source: each lane finds the segment of its face that covers its cell
-// (h8_find) and finds the next one when its z leaves the segment.
+// (h8_find) and finds the next one when its z leaves the segment.  FUSED with
+// wmir: the lanes of the first and last 4 x columns (boxes at least 8 cells
+// wide, 4 a multiple of V) also store their new values into w's 4-layer edge
+// mirror, layer m of side s at mir + s*mir_side + m*ey*ez + z*ey + y, where
+// the next step's neighbours read their x-face cells.
 template <typename T, int V, bool FUSED>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     k_heat8(const DevTile* __restrict__ tiles, const DevH8Seg* __restrict__ segs, const DevH8Face* __restrict__ faces,
-            const DevBox* __restrict__ boxes, const T* u_, T* w_, T c, int ldw, int ldh) {
+            const DevBox* __restrict__ boxes, const T* u_, T* w_, T c, int ldw, int ldh, int wmir) {
   using VT = Vec<T, V>;
   extern __shared__ unsigned char smem_raw[];
   T* const lds = reinterpret_cast<T*>(smem_raw);
   const DevTile tl = ldc(tiles + logical_block());
   const DevBox B = ldc(boxes + tl.box);
   const DevH8Face F = FUSED ? ldc(faces + tl.box) : DevH8Face{};
+  // the same record through memory, for faces chosen per lane (indexing F with
+  // a lane's value would place it in scratch)
+  const DevH8Face* __restrict__ Fp = faces + tl.box;
   const int64_t n = tl.comp;
   // address of cell (x, y, 0) of the tile's component through segment g
   auto seg_at = [&](const DevH8Seg& g, int x, int y) -> int64_t {
@@ -1329,7 +1336,7 @@ __global__ void __launch_bounds__(256)
     yh_at = comp0 + yh_x + (int64_t)yh_y * B.sy;
     if (FUSED && (yh_y < 0 || yh_y >= B.ey)) {
       yh_f = yh_y < 0 ? 2 : 3;
-      const DevH8Seg g = h8_find(segs, F.start[yh_f], F.count[yh_f], yh_x, tl.z0);
+      const DevH8Seg g = h8_find(segs, Fp->start[yh_f], Fp->count[yh_f], yh_x, tl.z0);
       yh_at = seg_at(g, yh_x, yh_y);
       yh_step = (int)g.sz;
       yh_t2hi = g.t2hi;
@@ -1352,7 +1359,7 @@ __global__ void __launch_bounds__(256)
     xh_y = y;
     if (FUSED && (x < 0 || x >= B.ex)) {
       xh_f = x < 0 ? 0 : 1;
-      const DevH8Seg g = h8_find(segs, F.start[xh_f], F.count[xh_f], y, tl.z0);
+      const DevH8Seg g = h8_find(segs, Fp->start[xh_f], Fp->count[xh_f], y, tl.z0);
       xh_at = seg_at(g, x, y);
       xh_step = (int)g.sz;
       xh_t2hi = g.t2hi;
@@ -1365,6 +1372,15 @@ __global__ void __launch_bounds__(256)
     xh_slot = (yr + 4) * ldw + (side ? 4 + W + m : 3 - m);
   }
   const T A1 = (T)kH8A1, A2 = (T)kH8A2, A3 = (T)kH8A3, A4 = (T)kH8A4, A0 = (T)kH8A0X3;
+  // the mirror element of the lane's first cell at z = 0 (relative to the
+  // component's mirror), or -1: side 0 layer = column, side 1 layer = ex-1-column
+  const int mlay = B.ey * B.ez;
+  int moff = -1;
+  if (FUSED && wmir && active) {
+    const int xc = x0 + lx * V;
+    if (xc < 4) moff = xc * mlay + tl.y0 + ly;
+    else if (xc >= B.ex - 4) moff = B.mir_side + (B.ex - 1 - xc) * mlay + tl.y0 + ly;
+  }
 
   // the lane's column below and above the box (FUSED: planes z < 0 and z >= ez
   // through the z faces' segments, one each for the whole tile)
@@ -1394,13 +1410,16 @@ __global__ void __launch_bounds__(256)
   VT yh = hy ? ldv<T, V>(u + yh_at + (int64_t)tl.z0 * yh_step) : Q[0];
   T xh = hx ? u[xh_at + (int64_t)tl.z0 * xh_step] : (T)0;
   const int own = (ly + 4) * ldw + 4 + lx * V;
-  // running pointers, one plane further each step: the next column plane, the
-  // next plane's halo values, the output
-  const BL_GLOBAL T* pq = u + col + (int64_t)(tl.z0 + 5) * sz;
+  // running pointers, one plane further each step: the next plane's halo
+  // values; the column's next plane and the output are formed from col each
+  // step (col is made opaque, so they are not kept as two more 64-bit pointers)
   const BL_GLOBAL T* py = u + yh_at + (int64_t)(tl.z0 + 1) * yh_step;
   const BL_GLOBAL T* px = u + xh_at + (int64_t)(tl.z0 + 1) * xh_step;
-  BL_GLOBAL T* pw = w + col + (int64_t)tl.z0 * sz;
   for (int z = tl.z0; z < tl.z1; ++z) {
+    int64_t cz = col;
+    asm volatile("" : "+v"(cz));
+    const BL_GLOBAL T* pq = u + cz + (int64_t)(z + 5) * sz;
+    BL_GLOBAL T* pw = w + cz + (int64_t)z * sz;
     T* buf = lds + ((z - tl.z0) & 1) * (ldw * ldh);
     if (active) *reinterpret_cast<VT*>(buf + own) = Q[4];
     if (hy) *reinterpret_cast<VT*>(buf + yh_slot) = yh;
@@ -1413,7 +1432,7 @@ __global__ void __launch_bounds__(256)
       qn = ldv<T, V>(FUSED ? (z + 5 >= B.ez ? u + czhi + (int64_t)(z + 5) * szhi : pq) : pq);
       if (hy) {
         if (FUSED && yh_f >= 0 && z + 1 > yh_t2hi) {  // the next plane lies in the face's next segment
-          const DevH8Seg g = h8_find(segs, F.start[yh_f], F.count[yh_f], yh_x, z + 1);
+          const DevH8Seg g = h8_find(segs, Fp->start[yh_f], Fp->count[yh_f], yh_x, z + 1);
           yh_at = seg_at(g, yh_x, yh_y);
           yh_step = (int)g.sz;
           yh_t2hi = g.t2hi;
@@ -1423,7 +1442,7 @@ __global__ void __launch_bounds__(256)
       }
       if (hx) {
         if (FUSED && xh_f >= 0 && z + 1 > xh_t2hi) {
-          const DevH8Seg g = h8_find(segs, F.start[xh_f], F.count[xh_f], xh_y, z + 1);
+          const DevH8Seg g = h8_find(segs, Fp->start[xh_f], Fp->count[xh_f], xh_y, z + 1);
           xh_at = seg_at(g, xh_x, xh_y);
           xh_step = (int)g.sz;
           xh_t2hi = g.t2hi;
@@ -1432,7 +1451,6 @@ __global__ void __launch_bounds__(256)
         xhn = *px;
       }
     }
-    pq += sz;
     py += FUSED ? yh_step : sz;
     px += xh_step;
     lds_sync();
@@ -1444,15 +1462,36 @@ __global__ void __launch_bounds__(256)
       const VT* rv = reinterpret_cast<const VT*>(buf + own);
       constexpr int K = (4 + V - 1) / V;
       const int lv = ldw / V;
+      // the y neighbours' 8 reads first; FUSED: the x neighbours' 4 reads once
+      // the rows 1 and 2 away are summed, into the registers those freed, so
+      // that 4 waves per SIMD fit in the registers (mirror stores included)
+      T py1[V], py2[V], py3[V], py4[V];
+      {
+        VT Ym[4], Yp[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          Ym[m] = rv[-(m + 1) * lv];
+          Yp[m] = rv[(m + 1) * lv];
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          py1[e] = Ym[0].v[e] + Yp[0].v[e];
+          py2[e] = Ym[1].v[e] + Yp[1].v[e];
+        }
+        if (FUSED) {
+#pragma unroll
+          for (int e = 0; e < V; ++e) asm volatile("" ::"v"(py1[e]), "v"(py2[e]));
+          asm volatile("" ::: "memory");
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          py3[e] = Ym[2].v[e] + Yp[2].v[e];
+          py4[e] = Ym[3].v[e] + Yp[3].v[e];
+        }
+      }
       VT X[2 * K + 1];
 #pragma unroll
       for (int i = 0; i < 2 * K + 1; ++i) X[i] = i == K ? Q[4] : rv[i - K];
-      VT Ym[4], Yp[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        Ym[m] = rv[-(m + 1) * lv];
-        Yp[m] = rv[(m + 1) * lv];
-      }
       auto xat = [&](int d) -> T { return X[(d + K * V) / V].v[(d + K * V) % V]; };  // cell d of the row
       VT o;
 #pragma unroll
@@ -1460,18 +1499,25 @@ __global__ void __launch_bounds__(256)
         const T uc = Q[4].v[e];
         const T px1 = xat(e - 1) + xat(e + 1), px2 = xat(e - 2) + xat(e + 2);
         const T px3 = xat(e - 3) + xat(e + 3), px4 = xat(e - 4) + xat(e + 4);
-        const T py1 = Ym[0].v[e] + Yp[0].v[e], py2 = Ym[1].v[e] + Yp[1].v[e];
-        const T py3 = Ym[2].v[e] + Yp[2].v[e], py4 = Ym[3].v[e] + Yp[3].v[e];
         const T pz1 = Q[3].v[e] + Q[5].v[e], pz2 = Q[2].v[e] + Q[6].v[e];
         const T pz3 = Q[1].v[e] + Q[7].v[e], pz4 = Q[0].v[e] + Q[8].v[e];
         const T Dx = ((A1 * px1 + A2 * px2) + A3 * px3) + A4 * px4;
-        const T Dy = ((A1 * py1 + A2 * py2) + A3 * py3) + A4 * py4;
+        const T Dy = ((A1 * py1[e] + A2 * py2[e]) + A3 * py3[e]) + A4 * py4[e];
         const T Dz = ((A1 * pz1 + A2 * pz2) + A3 * pz3) + A4 * pz4;
         o.v[e] = uc + c * (((Dx + Dy) + Dz) + A0 * uc);
       }
       stv_nt<T, V>(pw, o);
+      if (FUSED && moff >= 0) {  // the cells of one vector: consecutive layers, forward on side 0
+        // (mo is opaque to the compiler, so the addresses below are formed here
+        // from one register rather than hoisted out of the loop as 64-bit values)
+        int mo = moff;
+        asm volatile("" : "+v"(mo));
+        BL_GLOBAL T* pm = w + (B.mir + n * B.sc + (int64_t)z * B.ey);
+        const int step = mo >= B.mir_side ? -mlay : mlay;
+#pragma unroll
+        for (int e = 0; e < V; ++e) pm[mo + e * step] = o.v[e];
+      }
     }
-    pw += sz;
 #pragma unroll
     for (int k = 0; k < 8; ++k) Q[k] = Q[k + 1];
     Q[8] = qn;
@@ -2829,31 +2875,36 @@ hipError_t launch_mg_bottom(const Plan& pl, void* phi, const void* f, const MgBo
 }
 
 // 8th-order heat step over the tiles of k_heat8: with segs and faces, the
-// fused form; without, u's ghosts must have been filled.
+// fused form (write_mirror: which also writes w's 4-layer edge mirror);
+// without, u's ghosts must have been filled.
 template <typename T, int V>
 static void heat8_t(const DevTile* tiles, const DevH8Seg* segs, const DevH8Face* faces, int ntiles,
-                    const DevBox* boxes, const void* u, void* w, double c, int ldw, int ldh, size_t lds, hipStream_t s) {
+                    const DevBox* boxes, const void* u, void* w, double c, int ldw, int ldh, int wmir, size_t lds,
+                    hipStream_t s) {
   if (segs)
     hipLaunchKernelGGL((k_heat8<T, V, true>), dim3(ntiles), dim3(256), lds, s, tiles, segs, faces, boxes,
-                       (const T*)u, (T*)w, (T)c, ldw, ldh);
+                       (const T*)u, (T*)w, (T)c, ldw, ldh, wmir);
   else
     hipLaunchKernelGGL((k_heat8<T, V, false>), dim3(ntiles), dim3(256), lds, s, tiles, segs, faces, boxes,
-                       (const T*)u, (T*)w, (T)c, ldw, ldh);
+                       (const T*)u, (T*)w, (T)c, ldw, ldh, 0);
 }
 
 hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, const DevH8Seg* segs, const DevH8Face* faces,
                         int ntiles, const DevBox* boxes, const void* u, void* w, double c, int rmax, int nvtmax,
-                        hipStream_t s) {
+                        bool write_mirror, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (segs && !faces) return hipErrorInvalidValue;
+  if (write_mirror && !segs) return hipErrorInvalidValue;
+  if (write_mirror && 4 % vec) return hipErrorInvalidValue;  // a vector lies in one side's 4 columns
   const int ldw = ((nvtmax * vec + 8) + 3) & ~3, ldh = rmax + 8;
   const size_t lds = 2 * (size_t)ldw * ldh * (dtype == BL_F64 ? 8 : 4);
+  const int wm = write_mirror ? 1 : 0;
   if (dtype == BL_F64) {
-    if (vec == 2) heat8_t<double, 2>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
-    else heat8_t<double, 1>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
+    if (vec == 2) heat8_t<double, 2>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, wm, lds, s);
+    else heat8_t<double, 1>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, wm, lds, s);
   } else {
-    if (vec == 4) heat8_t<float, 4>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
-    else heat8_t<float, 1>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, lds, s);
+    if (vec == 4) heat8_t<float, 4>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, wm, lds, s);
+    else heat8_t<float, 1>(tiles, segs, faces, ntiles, boxes, u, w, c, ldw, ldh, wm, lds, s);
   }
   return hipGetLastError();
 }

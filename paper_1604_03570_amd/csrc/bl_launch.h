@@ -149,7 +149,7 @@ hipError_t launch_prolong_add(const Plan& fine, const Plan& coarse, void* phi, c
 // read through the face segments of build_h8_segments, no fill needed.
 hipError_t launch_heat8(int dtype, int vec, const DevTile* tiles, const DevH8Seg* segs, const DevH8Face* faces,
                         int ntiles, const DevBox* boxes, const void* u, void* w, double c, int rmax, int nvtmax,
-                        hipStream_t s);
+                        bool write_mirror, hipStream_t s);
 
 // dst[0..bytes) = src[0..bytes): 16-byte aligned, bytes a multiple of 16.
 hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -513,14 +513,19 @@ void build_h8_tiles(const Plan& p, std::vector<DevTile>& tiles, int* rmax, int* 
   }
 }
 
-bool build_h8_segments(const Plan& p, std::vector<DevH8Seg>& segs, std::vector<DevH8Face>& faces, std::string* why) {
+bool build_h8_segments(const Plan& p, std::vector<DevH8Seg>& segs, std::vector<DevH8Face>& faces, std::string* why,
+                       std::vector<DevH8Seg>* msegs) {
   segs.clear();
   faces.clear();
+  if (msegs) msegs->clear();
   if (p.ng < 4 || !p.fill) {
     *why = "nghost < 4";
     return false;
   }
   const int V = p.vec, nb = (int)p.hboxes.size();
+  bool mir = msegs != nullptr;  // the mirror form: every box at least 8 cells wide in x
+  for (const Box& b : p.boxes)
+    if (b.len(0) < 8) mir = false;
   std::vector<std::vector<int>> byd(nb);
   for (int i = 0; i < (int)p.fill->size(); ++i) byd[(*p.fill)[i].dst].push_back(i);
   faces.resize(nb);
@@ -536,7 +541,9 @@ bool build_h8_segments(const Plan& p, std::vector<DevH8Seg>& segs, std::vector<D
       faces[b].start[f] = (int32_t)segs.size();
       std::vector<int> c1{0, e[u1]}, c2{0, e[u2]};
       std::vector<std::array<int, 4>> rects;  // covered (t1lo, t1hi, t2lo, t2hi)
-      auto add = [&](DevH8Seg g, int t1lo, int t1hi, int t2lo, int t2hi) -> bool {
+      // checks segment g over (t1, t2) and appends it (with gm, the mirror
+      // form's segment over the same cells, to the mirror form's list)
+      auto check = [&](DevH8Seg& g, int t1lo, int t1hi, int t2lo, int t2hi) -> bool {
         g.t1lo = t1lo;
         g.t1hi = t1hi;
         g.t2lo = t2lo;
@@ -565,7 +572,15 @@ bool build_h8_segments(const Plan& p, std::vector<DevH8Seg>& segs, std::vector<D
             return false;
           }
         }
+        return true;
+      };
+      auto add = [&](DevH8Seg g, DevH8Seg gm, int t1lo, int t1hi, int t2lo, int t2hi) -> bool {
+        if (!check(g, t1lo, t1hi, t2lo, t2hi)) return false;
         segs.push_back(g);
+        if (mir) {
+          if (!check(gm, t1lo, t1hi, t2lo, t2hi)) return false;
+          msegs->push_back(gm);
+        }
         return true;
       };
       for (int ri : byd[b]) {
@@ -595,7 +610,32 @@ bool build_h8_segments(const Plan& p, std::vector<DevH8Seg>& segs, std::vector<D
         g.sx = 1;
         g.sy = (int32_t)sf.sy;
         g.sz = sf.sz;
-        if (!add(g, lo[u1], hi[u1], lo[u2], hi[u2])) return false;
+        DevH8Seg gm = g;
+        if (mir && a == 0) {
+          // source column cx = X0 + x of the neighbour (ex_s wide), a copy of
+          // which is mirror layer cx on its side 0 (high face: cx = 0..3) or
+          // ex_s-1-cx on its side 1 (low face); rows j = Y0 + y, planes k = Z0 + z
+          const Box& sb = p.boxes[r.src];
+          const int64_t exs = sb.len(0), eys = sb.len(1), L = eys * sb.len(2);
+          const int64_t X0 = bx.lo[0] + r.shift[0] - sf.valid.lo[0];
+          const int64_t Y0 = bx.lo[1] + r.shift[1] - sf.valid.lo[1], Z0 = bx.lo[2] + r.shift[2] - sf.valid.lo[2];
+          const int64_t c0 = X0 + nlo, c1 = X0 + nhi;  // the source columns of the face's layers
+          const bool ok = side ? (c0 == 0 && c1 == 3) : (c0 == exs - 4 && c1 == exs - 1);
+          if (!ok || sf.mir_layers != 4 || L > INT32_MAX) {
+            *why = "internal error: an x face's neighbour columns are not its mirror layers";
+            return false;
+          }
+          gm.sy = 1;
+          gm.sz = eys;
+          if (side) {  // layer = X0 + x on side 0
+            gm.o = sf.mir + X0 * L + Y0 + Z0 * eys;
+            gm.sx = (int32_t)L;
+          } else {     // layer = exs - 1 - X0 - x on side 1
+            gm.o = sf.mir + sf.mir_side + (exs - 1 - X0) * L + Y0 + Z0 * eys;
+            gm.sx = (int32_t)-L;
+          }
+        }
+        if (!add(g, gm, lo[u1], hi[u1], lo[u2], hi[u2])) return false;
         rects.push_back({lo[u1], hi[u1], lo[u2], hi[u2]});
         c1.push_back(lo[u1]);
         c1.push_back(hi[u1] + 1);
@@ -627,7 +667,7 @@ bool build_h8_segments(const Plan& p, std::vector<DevH8Seg>& segs, std::vector<D
           bool covered = false;
           for (const auto& R : rects)
             if (t1 >= R[0] && t1 <= R[1] && t2 >= R[2] && t2 <= R[3]) covered = true;
-          if (!covered && !add(own, c1[i1], c1[i1 + 1] - 1, c2[i2], c2[i2 + 1] - 1)) return false;
+          if (!covered && !add(own, own, c1[i1], c1[i1 + 1] - 1, c2[i2], c2[i2 + 1] - 1)) return false;
         }
       faces[b].count[f] = (int32_t)segs.size() - faces[b].start[f];
     }
@@ -714,7 +754,8 @@ static int64_t layout_fab(const Box& b, int ng, int ncomp, int64_t A, int64_t fa
   const int64_t plane = round_up(nyg * px, A);
   const int64_t rows = nzg * plane;
   const int64_t slab = round_up(2 * nzg * nyg * ng, A);
-  const int64_t mirror = round_up(2 * ez * ey, A);
+  const int64_t layers = ng >= 4 ? 4 : 1;
+  const int64_t mirror = round_up(2 * layers * ez * ey, A);
   f.valid = b;
   f.grown = b.grow(ng);
   f.ng = ng;
@@ -726,7 +767,8 @@ static int64_t layout_fab(const Box& b, int ng, int ncomp, int64_t A, int64_t fa
   f.xs_side = nzg * nyg * ng;
   f.xs_z = nyg * ng;
   f.xs = fab + rows + ng * f.xs_z + (int64_t)ng * ng;
-  f.mir_side = ez * ey;
+  f.mir_side = layers * ez * ey;
+  f.mir_layers = (int)layers;
   f.mir = fab + rows + slab;
   return f.sc * ncomp;
 }
@@ -1046,17 +1088,19 @@ static bl_status host_plan(const bl_boxarray* ba, int32_t ncomp, int32_t nghost,
   return build_plan(ba, ncomp, nghost, dtype, tile_config(), out);
 }
 
-bl_status bl_heat8_fused_layout(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype, int32_t* nsegs,
-                                int64_t* segs, int64_t* total_elems) {
+bl_status bl_heat8_fused_layout(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype,
+                                int32_t from_mirror, int32_t* nsegs, int64_t* segs, int64_t* total_elems) {
   clear_error();
   if (!nsegs) return fail(BL_EINVAL, "NULL argument");
   std::shared_ptr<Plan> p;
   bl_status st = host_plan(ba, ncomp, nghost, dtype, &p);
   if (st != BL_OK) return st;
-  std::vector<DevH8Seg> sv;
+  std::vector<DevH8Seg> rv, mv;
   std::vector<DevH8Face> fv;
   std::string why;
-  if (!build_h8_segments(*p, sv, fv, &why)) return fail(BL_EINVAL, "%s", why.c_str());
+  if (!build_h8_segments(*p, rv, fv, &why, &mv)) return fail(BL_EINVAL, "%s", why.c_str());
+  if (from_mirror && mv.empty()) return fail(BL_EINVAL, "a box is narrower than 8 cells in x: no 4-layer mirror form");
+  const std::vector<DevH8Seg>& sv = from_mirror ? mv : rv;
   *nsegs = (int32_t)sv.size();
   if (total_elems) *total_elems = (int64_t)p->total_elems;
   if (segs)
@@ -1084,6 +1128,26 @@ bl_status bl_layout_index(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, 
     if (cell[d] < g.grown.lo[d] || cell[d] > g.grown.hi[d])
       return fail(BL_EINVAL, "cell outside box %d's grown box", (int)box);
   *index = g.index(cell[0], cell[1], cell[2]) + (int64_t)comp * g.sc;
+  return BL_OK;
+}
+
+bl_status bl_layout_mirror_index(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, int32_t dtype, int32_t box,
+                                 int32_t side, int32_t layer, int32_t j, int32_t k, int32_t comp, int64_t* index) {
+  clear_error();
+  if (!index) return fail(BL_EINVAL, "NULL argument");
+  std::shared_ptr<Plan> p;
+  bl_status st = host_plan(ba, ncomp, nghost, dtype, &p);
+  if (st != BL_OK) return st;
+  if (box < 0 || box >= (int32_t)p->fabs.size()) return fail(BL_EINVAL, "box %d out of range", (int)box);
+  if (comp < 0 || comp >= ncomp) return fail(BL_EINVAL, "component %d out of range", (int)comp);
+  const FabGeom& g = p->fabs[box];
+  if (side < 0 || side > 1 || layer < 0 || layer >= g.mir_layers)
+    return fail(BL_EINVAL, "side %d layer %d: the mirror has 2 sides of %d layers", (int)side, (int)layer, g.mir_layers);
+  const Box& b = g.valid;
+  if (j < b.lo[1] || j > b.hi[1] || k < b.lo[2] || k > b.hi[2]) return fail(BL_EINVAL, "row outside box %d", (int)box);
+  const int64_t ey = b.len(1), ez = b.len(2);
+  *index = g.mir + side * g.mir_side + layer * ey * ez + (int64_t)(k - b.lo[2]) * ey + (j - b.lo[1]) +
+           (int64_t)comp * g.sc;
   return BL_OK;
 }
 

@@ -149,11 +149,13 @@ def test_512cube_uneven_varcoef_at_full_size(bt):
     say("512^3 uneven varcoef: sampled cells bit-exact, sums conserved")
 
 
-def test_512cube_uneven_heat8_fused_at_full_size(bt):
+@pytest.mark.parametrize("form", ["auto", "fused_mirror"])
+def test_512cube_uneven_heat8_fused_at_full_size(bt, form):
     """512^3 periodic, the seeded uneven chop, 5 comps, 4 ghost layers, FP64: 10 steps of
     the 8th-order form in the benchmark's configuration (the default, fused form, which
-    reads neighbour boxes directly); sampled cells equal the oracle's dependence-cone
-    window bit for bit and every component's sum is conserved."""
+    reads neighbour boxes directly, and the fused form with the 4-layer edge mirrors);
+    sampled cells equal the oracle's dependence-cone window bit for bit and every
+    component's sum is conserved."""
     n, ncomp, steps, c = 512, 5, 10, 0.09
     dom = I.domain_box(n)
     boxes = I.random_chop(dom, 16, 128, 8, seed=0)
@@ -164,7 +166,7 @@ def test_512cube_uneven_heat8_fused_at_full_size(bt):
         a.from_global(u0[comp:comp + 1], scomp=comp)
     assert bt.heat8_auto_form(a) == "fused"
     s0 = [a.sum(comp) for comp in range(ncomp)]
-    res = bt.heat8_advance(a, b, steps, c)
+    res = bt.heat8_advance(a, b, steps, c, form=form)
     torch.cuda.synchronize()
     for comp in range(ncomp):
         drift = abs(res.sum(comp) - s0[comp]) / abs(s0[comp])
@@ -174,7 +176,7 @@ def test_512cube_uneven_heat8_fused_at_full_size(bt):
         for _ in range(3):
             cell = tuple(int(v) for v in rng.integers(0, n, 3))
             assert _cell(res, boxes, comp, cell) == O.heat8_window(u0[comp], cell, steps, c), (comp, cell)
-    say("512^3 uneven heat8 (fused): sampled cells bit-exact, sums conserved")
+    say(f"512^3 uneven heat8 ({form}): sampled cells bit-exact, sums conserved")
 
 
 def test_384cube_gsrb_at_full_size(bt):

@@ -1,7 +1,8 @@
 """Parity of the 8th-order heat step (9-cell span, HIP kernel through the C-ABI) with
 the oracle.  FP64 bit for bit (same operand order, coefficients rounded once, no FMA
-contraction); FP32 storage within 2e-5 of the FP64 oracle; the fill form and the fused
-form (neighbour boxes read directly) agree bit for bit.  Layouts: uneven boxes, holes
+contraction); FP32 storage within 2e-5 of the FP64 oracle; the fill form, the fused form
+(neighbour boxes read directly) and the fused form with the 4-layer edge mirrors agree bit
+for bit.  Layouts: uneven boxes, holes
 next to a non-periodic side, odd extents (scalar lanes), boxes whose last x tile is one
 vector wide (its halo reaches past the row end into the x ghost slab), 5 ghost layers."""
 import math
@@ -42,7 +43,7 @@ def _layout(name, rng):
     return dom, periodic, boxes
 
 
-@pytest.mark.parametrize("form", ["fill", "fused"])
+@pytest.mark.parametrize("form", ["fill", "fused", "fused_mirror"])
 @pytest.mark.parametrize("ng", [4, 5])
 @pytest.mark.parametrize("dtype_name", ["f64", "f32"])
 @pytest.mark.parametrize("layout", ["uneven_periodic", "holes_mixed", "odd_extents", "narrow_last_tile"])
@@ -55,9 +56,14 @@ def test_heat8_equals_the_oracle(bt, layout, dtype_name, ng, form):
     if dtype == bt.F32:
         g = I.round_f32(g)
     steps = 7
-    say(f"heat8 layout={layout} dtype={dtype_name} ng={ng} nbox={len(boxes)}")
+    say(f"heat8 layout={layout} dtype={dtype_name} ng={ng} form={form} nbox={len(boxes)}")
     _, a, b, o = make_pair(boxes, dom, periodic, 2, ng, dtype, g, ghost_value=0.5)
     assert bt.heat8_fused_ok(a)
+    if form == "fused_mirror" and layout == "odd_extents":  # boxes 5 cells wide: no 4-layer mirror form
+        with pytest.raises(bt.BoxtileError) as e:
+            bt.heat8_advance(a, b, steps, C8, form=form)
+        assert e.value.code == bt.BL_EINVAL and "8 cells" in str(e.value)
+        return
     res = bt.heat8_advance(a, b, steps, C8, form=form)
     ref = O.heat8_advance(o, steps, C8).to_global()
     got = gpu_global(res)
@@ -67,7 +73,7 @@ def test_heat8_equals_the_oracle(bt, layout, dtype_name, ng, form):
         err = rel_err(got, ref)
         say(f"  fp32 rel err {err:.2e}")
         assert err <= 2e-5
-    if form == "fused":  # the two forms agree bit for bit, FP32 included
+    if form != "fill":  # the forms agree bit for bit, FP32 included
         _, a2, b2, _ = make_pair(boxes, dom, periodic, 2, ng, dtype, g, ghost_value=0.5)
         assert np.array_equal(gpu_global(bt.heat8_advance(a2, b2, steps, C8, form="fill")), got, equal_nan=True)
 

@@ -194,3 +194,104 @@ def test_varcoef_calls_in_sequence_skip_the_extraction(bt):
     r = bt.heat_varcoef_advance(r, other, bm, 3, dt, dx)
     ref = O.heat_varcoef_advance(o, ob, 5, dt, dx).to_global()
     assert np.array_equal(gpu_global(r), ref)
+
+
+C8 = 0.09
+
+
+def _check_4_layer_mirror(bt, mf, boxes, ncomp, rng, nsample=200):
+    """The 4-layer mirror of mf holds its first and last 4 valid x columns: every
+    corner of every box's mirror and a random sample of its other elements."""
+    el = mf.elements()
+    ba, ng, dt = mf.ba, mf.nghost, mf.dtype
+    pts = []
+    for b, bx in enumerate(boxes):
+        for side in (0, 1):
+            for layer in range(4):
+                for j in (bx[1], bx[4]):
+                    for k in (bx[2], bx[5]):
+                        pts.append((b, side, layer, int(j), int(k), ncomp - 1))
+    for _ in range(nsample):
+        b = int(rng.integers(len(boxes)))
+        bx = boxes[b]
+        pts.append((b, int(rng.integers(2)), int(rng.integers(4)), int(rng.integers(bx[1], bx[4] + 1)),
+                    int(rng.integers(bx[2], bx[5] + 1)), int(rng.integers(ncomp))))
+    mi, ci = [], []
+    for b, side, layer, j, k, comp in pts:
+        bx = boxes[b]
+        i = bx[0] + layer if side == 0 else bx[3] - layer
+        mi.append(ba.layout_mirror_index(ncomp, ng, dt, b, side, layer, j, k, comp))
+        ci.append(ba.layout_index(ncomp, ng, dt, b, (int(i), j, k), comp))
+    mi = torch.as_tensor(mi, device=el.device)
+    ci = torch.as_tensor(ci, device=el.device)
+    assert torch.equal(el[mi], el[ci])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_heat8_calls_in_sequence_continue_from_the_4_layer_mirror(bt, dtype):
+    """8th-order advances in the mirror form of 1, 2, 3, 1, 2, 1 and 2 steps alternating
+    the pair's roles, with a 7-point advance (which writes the first mirror layer only), a
+    fill-form call (which writes none) and an outside write declared modified between
+    them: every call reads a neighbour's 4-layer mirror only where the last write left all
+    4 layers current.
+    FP64 states equal the oracle's bit for bit; FP32 states equal those of the same
+    calls in the fill form throughout (the forms agree bit for bit).  After each
+    8th-order call the result's mirror holds its edge columns; FillBoundary then reads
+    the first mirror layer, and every ghost equals the oracle's fill."""
+    dom, periodic, boxes = _boxes("uneven")
+    N = tuple(dom[3 + d] + 1 for d in range(3))
+    dt = bt.F64 if dtype == "f64" else bt.F32
+    rng = np.random.default_rng(12)
+    g = rng.random((2,) + N[::-1]) + 1.0
+    if dt == bt.F32:
+        g = I.round_f32(g)
+    ba, a, b, o = make_pair(boxes, dom, periodic, 2, 4, dt, g, ghost_value=0.25)
+    _, a2, b2, _ = make_pair(boxes, dom, periodic, 2, 4, dt, g, ghost_value=0.25)
+    assert bt.heat8_fused_ok(a)
+    ba.heat8_fused_layout(2, 4, dt, from_mirror=True)  # the mirror form applies
+    ox, oy = o, o.copy()
+    pairs = [[a, b], [a2, b2]]  # the default form, the fill form
+    idx = torch.as_tensor(_valid_indices(a, boxes), device=a.elements().device)
+    seq = (("h8", 1), ("h8", 2), ("h8", 3), ("heat", 1), ("h8", 1), ("fill", 2), ("h8", 2), ("modified", 0),
+           ("h8", 1), ("h8", 2))
+    for kind, n in seq:
+        say(f"heat8 mirror sequence {dtype}: {kind} {n}")
+        for p, pair in enumerate(pairs):
+            x, y = pair
+            if kind == "h8":
+                r = bt.heat8_advance(x, y, n, C8, form="fused_mirror" if p == 0 else "fill")
+            elif kind == "fill":
+                r = bt.heat8_advance(x, y, n, C8, form="fill")
+            elif kind == "heat":
+                r = bt.heat_advance(x, y, n, 0.15)
+            else:  # valid cells scaled around the library, the write declared
+                el = x.elements()  # (every MultiFab of one shape has one layout)
+                el[idx] *= 0.5
+                x.modified()
+                r = x
+            if r is not x:
+                pair.reverse()
+        if dt == bt.F64:
+            for _ in range(n):
+                if kind == "heat":
+                    O.heat_step(ox, oy, 0.15)
+                elif kind == "modified":
+                    break
+                else:
+                    O.heat8_step(ox, oy, C8)
+                ox, oy = oy, ox
+            if kind == "modified":
+                ox.load_global(gpu_global(pairs[0][0]))
+            ref = ox.to_global()
+            m = np.isfinite(ref)
+            assert np.array_equal(gpu_global(pairs[0][0])[m], ref[m]), (kind, n)
+        assert np.array_equal(gpu_global(pairs[0][0]), gpu_global(pairs[1][0]), equal_nan=True), (kind, n)
+        if kind == "h8":
+            _check_4_layer_mirror(bt, pairs[0][0], boxes, 2, rng)
+    res = pairs[0][0]
+    res.fill_boundary()
+    om = O.OracleMultiFab(boxes, dom, periodic, 2, 4)
+    om.data[...] = np.nan
+    om.load_global(gpu_global(res))
+    om.fill_boundary()
+    _ghosts_equal(bt, res, om, boxes)

@@ -131,3 +131,112 @@ def test_layout_index_bounds_and_errors():
         assert e.value.code == bt.BL_EINVAL
     with pytest.raises(bt.BoxtileError):
         ba.layout_index(2, 4, bt.F64, len(boxes), (0, 0, 0), 0)
+
+
+def _mirror_element(ba, ncomp, ng, dtype, boxes, b2, gs, comp):
+    """Element of box b2's 4-layer edge mirror that holds its valid cell gs."""
+    bx = boxes[b2]
+    ex = int(bx[3] - bx[0] + 1)
+    cx = int(gs[0] - bx[0])
+    side, layer = (0, cx) if cx < 4 else (1, ex - 1 - cx)
+    assert 0 <= layer < 4, (b2, gs)
+    return ba.layout_mirror_index(ncomp, ng, dtype, b2, side, layer, gs[1], gs[2], comp)
+
+
+@pytest.mark.parametrize("name", ["uneven", "regular", "one_box", "nonperiodic_x", "slab_hole"])
+@pytest.mark.parametrize("dtype", [bt.F64, bt.F32])
+def test_fused_heat8_mirror_segments_read_the_neighbours_mirror(name, dtype):
+    """The segments of a step whose input's 4-layer mirror is current: y and z faces
+    and uncovered x faces as in the rows form; an x-face cell a box covers is the
+    element of that box's mirror holding FillBoundary's source cell (a sample of 300
+    cells per layout, found the way the kernel searches, plus every segment corner)."""
+    boxes, dom, periodic = _layouts()[name]
+    ncomp, ng = 2, 4
+    ba = bt.BoxArray.from_boxes(boxes, dom, periodic)
+    rows, total = ba.heat8_fused_layout(ncomp, ng, dtype)
+    mir, total2 = ba.heat8_fused_layout(ncomp, ng, dtype, from_mirror=True)
+    assert total2 == total and mir.shape == rows.shape
+    assert np.array_equal(mir[:, :6], rows[:, :6])  # the same segments, in the same order
+    xf = mir[:, 1] < 2
+    assert np.array_equal(mir[~xf], rows[~xf])      # y and z faces: unchanged
+    idx = lambda b, cell, comp: ba.layout_index(ncomp, ng, dtype, b, cell, comp)
+    rng = np.random.default_rng(8)
+    cases = []
+    for g in mir[xf]:
+        b, f = int(g[0]), int(g[1])
+        for t1 in (g[2], g[3]):
+            for t2 in (g[4], g[5]):
+                cases.append((b, f, int(t1), int(t2), None))
+    for _ in range(300):
+        b = int(rng.integers(len(boxes)))
+        bx = boxes[b]
+        cases.append((b, int(rng.integers(2)), int(rng.integers(bx[4] - bx[1] + 1)),
+                      int(rng.integers(bx[5] - bx[2] + 1)), None))
+    moved = 0
+    for b, f, t1, t2, _ in cases:
+        bx = boxes[b]
+        e0 = int(bx[3] - bx[0] + 1)
+        face = mir[(mir[:, 0] == b) & (mir[:, 1] == f)]
+        hit = [g for g in face[:-1] if g[2] <= t1 <= g[3] and g[4] <= t2 <= g[5]]
+        g = hit[0] if hit else face[-1]
+        o, sc, sx, sy, sz = (int(v) for v in g[6:11])
+        for depth in (range(e0, e0 + 4) if f else range(-4, 0)):
+            glob = (bx[0] + depth, bx[1] + t1, bx[2] + t2)
+            b2, gs = _source(boxes, dom, periodic, b, glob)
+            covered = all(boxes[b2][d] <= gs[d] <= boxes[b2][3 + d] for d in range(3))
+            for comp in (0, ncomp - 1):
+                got = o + comp * sc + depth * sx + t1 * sy + t2 * sz
+                if covered:
+                    assert got == _mirror_element(ba, ncomp, ng, dtype, boxes, b2, gs, comp), (name, b, f, depth)
+                    moved += 1
+                else:
+                    assert got == idx(b2, gs, comp)
+                assert 0 <= got < total
+    if name != "slab_hole" or periodic[0]:
+        assert moved > 0
+
+
+def test_fused_heat8_mirror_form_needs_boxes_8_wide():
+    for name in ("odd_extents", "holes_mixed"):  # boxes 5 and 4 cells wide in x
+        boxes, dom, periodic = _layouts()[name]
+        ba = bt.BoxArray.from_boxes(boxes, dom, periodic)
+        ba.heat8_fused_layout(1, 4, bt.F64)  # the rows form applies
+        with pytest.raises(bt.BoxtileError) as e:
+            ba.heat8_fused_layout(1, 4, bt.F64, from_mirror=True)
+        assert e.value.code == bt.BL_EINVAL and "8 cells" in str(e.value)
+
+
+def test_mirror_layout_holds_4_layers_apart_from_the_cells():
+    """With 4 ghost layers every box's mirror has 2 sides x 4 layers of ey*ez
+    elements per component, all distinct, inside the MultiFab and apart from every
+    cell of the grown boxes; with 1 ghost layer one layer per side (BL_EINVAL for
+    layer 1)."""
+    dom = I.domain_box(16)
+    boxes = I.regular_chop(dom, (8, 16, 8))
+    ba = bt.BoxArray.from_boxes(boxes, dom)
+    ncomp = 2
+    _, total = ba.heat8_fused_layout(ncomp, 4, bt.F64)
+    cells = set()
+    for b, bx in enumerate(boxes):
+        for k in range(bx[2] - 4, bx[5] + 5):
+            for j in range(bx[1] - 4, bx[4] + 5):
+                for i in range(bx[0] - 4, bx[3] + 5):
+                    for comp in range(ncomp):
+                        cells.add(ba.layout_index(ncomp, 4, bt.F64, b, (i, j, k), comp))
+    mir = set()
+    for b, bx in enumerate(boxes):
+        for side in (0, 1):
+            for layer in range(4):
+                for k in range(bx[2], bx[5] + 1):
+                    for j in range(bx[1], bx[4] + 1):
+                        for comp in range(ncomp):
+                            mir.add(ba.layout_mirror_index(ncomp, 4, bt.F64, b, side, layer, j, k, comp))
+    n = sum(2 * 4 * (bx[4] - bx[1] + 1) * (bx[5] - bx[2] + 1) * ncomp for bx in boxes)
+    assert len(mir) == n and not (mir & cells)
+    assert min(mir) >= 0 and max(mir) < total
+    bx = boxes[0]
+    ba.layout_mirror_index(1, 1, bt.F64, 0, 1, 0, bx[1], bx[2], 0)
+    for bad in ((0, 1), (2, 0), (0, 4)):
+        with pytest.raises(bt.BoxtileError) as e:
+            ba.layout_mirror_index(1, 1 if bad == (0, 1) else 4, bt.F64, 0, bad[0], bad[1], bx[1], bx[2], 0)
+        assert e.value.code == bt.BL_EINVAL
