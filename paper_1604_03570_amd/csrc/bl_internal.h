@@ -284,6 +284,7 @@ struct DevPushFace {  // the push records of face f of a box: [start[f], start[f
   int32_t count[6];
 };
 constexpr int kFillChunk = 256;
+constexpr size_t kLatencyTiles = 1024;  // below this many linear tiles, shorter tiles (build_lin_tiles)
 constexpr int kStencilMaxThreads = 256;  // workgroup size limit of the stencil kernels (waves <= 4)
 constexpr int kRestrictPerWG = 256;     // coarse cells per workgroup of the restriction (one per lane)
 constexpr int kProlongPerWG = 1024;     // x pairs per workgroup of the prolongation (four per lane)

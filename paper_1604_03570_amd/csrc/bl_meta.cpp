@@ -680,8 +680,9 @@ size_t lin_lds_bytes(const TileConfig& cfg, int esize, int vec, int yhmax, int x
   return zb * 64 * cfg.waves * vb + zb * 2 * yhmax * vb + zb * 2 * xhmax * esize;
 }
 
-void build_lin_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base, int rec_base,
-                     std::vector<DevLinTile>& tiles, int* yhmax, int* xhmax) {
+// The linear tiles of p with at most zsteps z steps of at most nzs_cap z blocks each.
+static void lin_tiles_pass(const Plan& p, const TileConfig& cfg, int zsteps, int nzs_cap, int member, int box_base,
+                           int rec_base, std::vector<DevLinTile>& tiles, int* yhmax, int* xhmax) {
   const int lanes = 64 * cfg.waves;
   const int zb = std::max(1, cfg.zchunk);
   std::vector<int> zc;
@@ -696,9 +697,9 @@ void build_lin_tiles(const Plan& p, const TileConfig& cfg, int member, int box_b
     } else {           // whole planes, as many z blocks as fill the workgroup
       ntq = 1;
       nq = P;
-      nzs = std::max(1, std::min(lanes / P, (B.ez + zb - 1) / zb));
+      nzs = std::max(1, std::min({lanes / P, (B.ez + zb - 1) / zb, nzs_cap}));
     }
-    const int zlen = zb * nzs * std::max(1, cfg.zsteps);
+    const int zlen = zb * nzs * std::max(1, zsteps);
     // z cuts: multiples of zlen and every z boundary of the x- and y-face records
     zc.clear();
     for (int z = 0; z < B.ez; z += zlen) zc.push_back(z);
@@ -740,6 +741,25 @@ void build_lin_tiles(const Plan& p, const TileConfig& cfg, int member, int box_b
           if (xhmax) *xhmax = std::max(*xhmax, t.nzs * t.nrows);
           tiles.push_back(t);
         }
+  }
+}
+
+void build_lin_tiles(const Plan& p, const TileConfig& cfg, int member, int box_base, int rec_base,
+                     std::vector<DevLinTile>& tiles, int* yhmax, int* xhmax) {
+  // A small level (few cells per box or few boxes) is latency-bound: a launch
+  // takes about as long as its workgroups' chains of z steps.  Where the
+  // configured shape gives fewer than kLatencyTiles tiles, one z step per tile,
+  // then one z block per step, give more and shorter workgroups.
+  const size_t first = tiles.size();
+  const int yh0 = yhmax ? *yhmax : 0, xh0 = xhmax ? *xhmax : 0;
+  const int zs[3] = {std::max(1, cfg.zsteps), 1, 1}, cap[3] = {1 << 30, 1 << 30, 1};
+  for (int k = 0; k < 3; ++k) {
+    if (k > 0 && zs[k] == zs[k - 1] && cap[k] == cap[k - 1]) continue;
+    tiles.resize(first);
+    if (yhmax) *yhmax = yh0;
+    if (xhmax) *xhmax = xh0;
+    lin_tiles_pass(p, cfg, zs[k], cap[k], member, box_base, rec_base, tiles, yhmax, xhmax);
+    if (tiles.size() - first >= kLatencyTiles) break;
   }
 }
 
