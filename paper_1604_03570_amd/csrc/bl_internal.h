@@ -285,6 +285,7 @@ struct DevPushFace {  // the push records of face f of a box: [start[f], start[f
 };
 constexpr int kFillChunk = 256;
 constexpr size_t kLatencyTiles = 1024;  // below this many linear tiles, shorter tiles (build_lin_tiles)
+constexpr size_t kRingRecs = 2048;      // below this many one-pass ring records, records split along t2
 constexpr int kStencilMaxThreads = 256;  // workgroup size limit of the stencil kernels (waves <= 4)
 constexpr int kRestrictPerWG = 256;     // coarse cells per workgroup of the restriction (one per lane)
 constexpr int kProlongPerWG = 1024;     // x pairs per workgroup of the prolongation (four per lane)

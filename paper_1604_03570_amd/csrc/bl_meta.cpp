@@ -979,6 +979,25 @@ bl_status build_plan(const bl_boxarray* cba, int ncomp, int ng, int dtype, const
     const int sface = 2 * a + (1 - r.face % 2);
     push[6 * (size_t)r.src + sface].push_back(Q);
   }
+  // few faces (a level of few boxes): each ring record split along t2 into
+  // near-equal parts of at least 4 rows, so the ring launch has about
+  // kRingRecs workgroups instead of one per face
+  if (!p->hringrecs.empty() && p->hringrecs.size() < kRingRecs) {
+    const int parts = (int)((kRingRecs + p->hringrecs.size() - 1) / p->hringrecs.size());
+    std::vector<DevRingRec> split;
+    for (const DevRingRec& R : p->hringrecs) {
+      const int t2 = R.face / 2 == 2 ? 1 : 2;
+      const int k = std::max(1, std::min(parts, R.n2 / 4));
+      for (int q = 0; q < k; ++q) {
+        const int a0 = (int)((int64_t)R.n2 * q / k), a1 = (int)((int64_t)R.n2 * (q + 1) / k);
+        DevRingRec P = R;
+        P.lo[t2] = R.lo[t2] + a0;
+        P.n2 = a1 - a0;
+        split.push_back(P);
+      }
+    }
+    p->hringrecs.swap(split);
+  }
   for (size_t i = 0; i < ba->boxes.size(); ++i)
     for (int f = 0; f < 6; ++f) {
       auto& v = push[6 * i + f];
