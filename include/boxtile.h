@@ -660,7 +660,9 @@ bl_status bl_tile_list(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_
  * vec, lanes, zsteps}: the run of x vectors q0..q0+nq-1 of the box's plane
  * (vector q is row q / nvx, x vector q % nvx, nvx = x extent / vec) over planes
  * z0..z1-1, taken in z steps of nzs z blocks of zchunk planes each (at most
- * zsteps steps); nzs*nq <= lanes.  Host metadata only.
+ * zsteps steps); nzs*nq <= lanes.  Where the configured shape gives fewer than
+ * 1024 tiles, every tile takes one z step, and if still fewer, one z block per
+ * step (more, shorter workgroups for a small level).  Host metadata only.
  */
 bl_status bl_stencil_tiles(const bl_boxarray* ba, int32_t ncomp, int32_t nghost, bl_dtype dtype, int32_t* ntiles,
                            int32_t* tiles);

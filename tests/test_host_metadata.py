@@ -171,6 +171,31 @@ def test_tile_list_covers_every_cell_once(dtype, boxes_kind):
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
+def test_small_levels_take_shorter_tiles(dtype):
+    """Where the configured shape (4 planes, 4 waves, 2 z steps) gives fewer than 1024
+    tiles, every tile takes one z step, and if that is still fewer than 1024, one z block
+    per step: more and shorter workgroups for latency-bound launches.  A level with
+    enough tiles keeps two z steps."""
+    saved = bt.get_tile_config()
+    bt.set_tile_config(4, 4, 0, 3, 2)
+    try:
+        def tiles(n, edge):
+            dom = I.domain_box(n)
+            return bt.BoxArray.from_boxes(I.regular_chop(dom, edge), dom).stencil_tiles(1, 1, dtype)
+        large = tiles(256, 64)   # 64 boxes of 64^3: thousands of tiles
+        mid = tiles(64, 32)      # 8 boxes of 32^3: under 1024 even with one z step
+        tiny = tiles(32, 8)      # 64 boxes of 8^3: whole planes stacked in z blocks
+    finally:
+        bt.set_tile_config(*saved)
+    planes = lambda t: t[:, 6] - t[:, 5]
+    assert len(large) >= 1024 and (planes(large) == 2 * 4 * large[:, 4]).any()
+    for t in (mid, tiny):
+        assert len(t) < 1024
+        assert (t[:, 4] == 1).all() and (planes(t) <= 4).all()
+    assert len(tiny) == 64 * 2  # 8 planes per box in z blocks of 4: two tiles each
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
 @pytest.mark.parametrize("boxes_kind", ["regular", "uneven", "odd", "cells"])
 @pytest.mark.parametrize("shape", [(4, 4, 1), (2, 4, 2), (8, 2, 1), (4, 3, 4), (4, 4, 8)])
 def test_stencil_tiles_cover_every_cell_once(dtype, boxes_kind, shape):
