@@ -8,7 +8,9 @@ FP64 fields are the oracle's bits; norms are held to 1e-13 (FP64 sums in another
 order); FP32 state to 1e-5 of the FP64 oracle.  Layouts: regular and uneven
 periodic levels, a level with holes and non-periodic sides (ghost cells that no
 box covers keep the caller's value), boxes that are their own periodic neighbours,
-and one the one-pass sweep does not take (odd x extents: it falls back).  Every
+boxes of odd y and z extents (the face ghost work split into uneven parts that start
+on either colour), and one the one-pass sweep does not take (odd x extents: it falls
+back).  Every
 work split (planes per workgroup, vectors per lane) and odd and even sweep counts.
 """
 import numpy as np
@@ -46,6 +48,9 @@ def _layout(name, rng):
     elif name == "self_periodic":  # each box spans y and z: its own neighbour across those faces
         dom, periodic = I.domain_box((32, 16, 12)), (1, 1, 1)
         boxes = I.regular_chop(dom, (8, 16, 12))
+    elif name == "odd_yz":  # odd y and z extents: face records split unevenly, odd first planes
+        dom, periodic = I.domain_box((32, 26, 22)), (1, 1, 1)
+        boxes = I.regular_chop(dom, (16, 13, 11))
     else:  # odd x extents: not a whole number of 16-byte vectors
         dom, periodic = I.domain_box((30, 20, 26)), (1, 1, 1)
         boxes = I.regular_chop(dom, (15, 10, 13))
@@ -86,7 +91,7 @@ def _same_norms(got, ref):
 
 
 @pytest.mark.parametrize("sweeps", [3, 4])
-@pytest.mark.parametrize("layout", ["regular", "uneven", "holes_mixed", "self_periodic"])
+@pytest.mark.parametrize("layout", ["regular", "uneven", "holes_mixed", "self_periodic", "odd_yz"])
 def test_one_pass_fp64_equals_the_oracle(bt, layout, sweeps):
     say(f"gsrb one-pass fp64 layout={layout} sweeps={sweeps}")
     h2 = 1.0 / 1024.0
