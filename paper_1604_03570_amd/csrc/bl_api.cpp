@@ -630,6 +630,9 @@ bl_status bl_heat8_advance_form(bl_multifab* u[2], int32_t nsteps, double c, int
   // last write to u[0] was such a step
   const bool mir = form == BL_H8_FUSED_MIRROR;
   const bool start_mirror = u[0]->mirror4_current;
+  // the MultiFabs the steps write are stale until the last step is launched
+  // (an error in between leaves them so)
+  for (int s = 0; s < nsteps && s < 2; ++s) u[(s + 1) & 1]->mark_mirror(false);
   for (int s = 0; s < nsteps; ++s) {
     void* src = u[s & 1]->data;
     void* dst = u[(s + 1) & 1]->data;
