@@ -876,7 +876,8 @@ static bool gsrb1_plan(Plan& p) {
 // its face ghosts.  Norms: the black part of sweep s plus the red part of sweep
 // s+1; after the last sweep, the residual norm of the result.
 static bl_status gsrb_one_pass(Plan& p, bl_multifab* phi, const bl_multifab* f, double h2, int nsweeps,
-                               double* resnorm_host, hipStream_t stream, bool edges_current = false) {
+                               double* resnorm_host, hipStream_t stream, bool edges_current = false,
+                               bool ghosts_current = false) {
   bool fresh = false;
   if (!phi->dtwin) {
     BL_HIP(hipMalloc(&phi->dtwin, phi->bytes));
@@ -907,7 +908,10 @@ static bl_status gsrb_one_pass(Plan& p, bl_multifab* phi, const bl_multifab* f, 
   // second buffer starts as a copy, so that it holds no undefined values)
   if (fresh || !p.faces_covered)
     BL_HIP(hipMemcpyAsync(phi->dtwin, phi->data, phi->bytes, hipMemcpyDeviceToDevice, stream));
-  BL_HIP(launch_fill(p, phi->data, 0, 1, stream, true));
+  // the face ghosts of the starting state, unless the caller knows them current
+  // (the previous call on this state was a one-pass call: its last sweep pushed
+  // them; the sweeps read no edge or corner ghost)
+  if (!ghosts_current) BL_HIP(launch_fill(p, phi->data, 0, 1, stream, true));
   for (int s = 0; s < nsweeps; ++s) {
     const int c = s & 1;
     BL_HIP(launch_gsrb_ring(p, buf[c], f->data, m2[c], h2, stream));
@@ -1074,6 +1078,10 @@ struct bl_mg {
   // per level, during bl_mg_vcycles: phi's edge-column copies hold its current
   // state (its last write was a one-pass smoothing call of an even count)
   std::vector<char> edges;
+  // per level, during bl_mg_vcycles: phi's covered face ghosts hold its current
+  // state (its last write was a one-pass smoothing call, whose last sweep
+  // pushed them)
+  std::vector<char> ghosts;
   ~bl_mg() {
     for (bl_multifab* m : phi) bl_multifab_destroy(m);
     for (bl_multifab* m : f) bl_multifab_destroy(m);
@@ -1248,11 +1256,11 @@ static bl_status mg_smooth(bl_mg* mg, size_t l, bl_multifab* phi, const bl_multi
   int64_t cells = 0;
   for (const Box& b : p.boxes) cells += b.volume();
   if (nu > 0 && nu % 2 == 0 && cells >= kMgOnePassCells && g_gsrb_one_pass.load() && gsrb1_plan(p)) {
-    bl_status st = gsrb_one_pass(p, phi, f, h2, nu, nullptr, stream, mg->edges[l] != 0);
-    mg->edges[l] = st == BL_OK;
+    bl_status st = gsrb_one_pass(p, phi, f, h2, nu, nullptr, stream, mg->edges[l] != 0, mg->ghosts[l] != 0);
+    mg->edges[l] = mg->ghosts[l] = st == BL_OK;
     return st;
   }
-  mg->edges[l] = 0;
+  mg->edges[l] = mg->ghosts[l] = 0;
   BL_HIP(gsrb_smooth(p, phi->data, f->data, h2, nu, stream));
   return BL_OK;
 }
@@ -1273,16 +1281,17 @@ static bl_status vcycle(bl_mg* mg, size_t l, bl_multifab* phi, const bl_multifab
   if (st != BL_OK) return st;
   bl_multifab* pc = mg->phi[l + 1];
   bl_multifab* fc = mg->f[l + 1];
-  BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
+  // the residual reads face ghosts only: current after a one-pass smoothing
+  if (!mg->ghosts[l]) BL_HIP(launch_fill(p, phi->data, 0, 1, stream));
   BL_HIP(launch_restrict_residual(p, *fc->plan, phi->data, f->data, fc->data, h2, stream));
   fc->mark_mirror(false);
   // the coarse level starts from 0 (the fused bottom sets it itself)
   if ((int)(l + 1) != mg->bottom) BL_HIP(launch_set_val(*pc->plan, pc->data, 0.0, 0, 1, 1, 256, stream));
-  mg->edges[l + 1] = 0;
+  mg->edges[l + 1] = mg->ghosts[l + 1] = 0;
   st = vcycle(mg, l + 1, pc, fc, 4.0 * h2, nu1, nu2, nu_bottom, stream);
   if (st != BL_OK) return st;
   BL_HIP(launch_prolong_add(p, *pc->plan, phi->data, pc->data, stream));
-  mg->edges[l] = 0;
+  mg->edges[l] = mg->ghosts[l] = 0;
   return mg_smooth(mg, l, phi, f, h2, nu2, stream);
 }
 }  // namespace bl
@@ -1302,7 +1311,8 @@ bl_status bl_mg_vcycles(bl_mg* mg, bl_multifab* phi, const bl_multifab* f, doubl
   const Plan& p = *phi->plan;
   const size_t slots = reduce_slots(p) + 8;
   if (resnorm_host && (st = ensure_scratch(phi, slots + (size_t)ncycles, (size_t)ncycles + 8)) != BL_OK) return st;
-  mg->edges.assign(mg->phi.size(), 0);  // nothing known of the levels' edge copies at the start
+  mg->edges.assign(mg->phi.size(), 0);  // nothing known of the levels' edge copies and ghosts at the start
+  mg->ghosts.assign(mg->phi.size(), 0);
   for (int c = 0; c < ncycles; ++c) {
     if ((st = vcycle(mg, 0, phi, f, h2, nu1, nu2, nu_bottom, stream)) != BL_OK) return st;
     if (resnorm_host)
