@@ -103,3 +103,15 @@ def test_heat8_degenerate_calls(bt):
         bt.heat8_advance(a1, b1, 1, C8)
     with pytest.raises(bt.BoxtileError):
         bt.heat8_advance(a, b, -1, C8)
+    # an unknown form: refused before any launch, the state untouched
+    import ctypes
+    arr = (ctypes.c_void_p * 2)(a.handle.value, b.handle.value)
+    for form in (-1, 4):
+        assert bt._L.bl_heat8_advance_form(arr, 1, ctypes.c_double(C8), form, None) == bt.BL_EINVAL
+    assert np.array_equal(gpu_global(a), before)
+    # the mirror form needs boxes at least 8 cells wide in x: 16 boxes of 4 x 16 x 16
+    boxes4 = I.regular_chop(dom, (4, 16, 16))
+    _, a4, b4, _ = make_pair(boxes4, dom, (1, 1, 1), 1, 4, bt.F64, g)
+    with pytest.raises(bt.BoxtileError) as e:
+        bt.heat8_advance(a4, b4, 1, C8, form="fused_mirror")
+    assert e.value.code == bt.BL_EINVAL and "8 cells" in str(e.value)
