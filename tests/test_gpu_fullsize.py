@@ -179,6 +179,29 @@ def test_512cube_uneven_heat8_fused_at_full_size(bt, form):
     say(f"512^3 uneven heat8 ({form}): sampled cells bit-exact, sums conserved")
 
 
+def test_512cube_uneven_heat8_fp32_forms_agree(bt):
+    """512^3 periodic, the seeded uneven chop, 5 comps, 4 ghost layers, FP32 storage: 4
+    steps of the 8th-order step in the fill form, the fused form and the fused form with
+    the 4-layer edge mirrors give the same bits on every valid cell (the same operations
+    on the same operands; the forms differ only in where a face cell is read from)."""
+    n, ncomp, steps, c = 512, 5, 4, 0.09
+    dom = I.domain_box(n)
+    boxes = I.random_chop(dom, 16, 128, 8, seed=0)
+    ba = bt.BoxArray.from_boxes(boxes, dom)
+    u0 = I.round_f32(I.uniform(n, ncomp, seed=2))
+    got = {}
+    for form in ("fill", "fused", "fused_mirror"):
+        a, b = bt.MultiFab(ba, ncomp, 4, bt.F32), bt.MultiFab(ba, ncomp, 4, bt.F32)
+        a.set_val(0.0, with_ghosts=True)
+        for comp in range(ncomp):
+            a.from_global(u0[comp:comp + 1], scomp=comp)
+        got[form] = bt.heat8_advance(a, b, steps, c, form=form).to_global()
+        del a, b
+        torch.cuda.synchronize()
+    assert torch.equal(got["fused"], got["fill"]) and torch.equal(got["fused_mirror"], got["fill"])
+    say("512^3 uneven heat8 FP32: fill, fused and mirror forms bit-identical")
+
+
 def test_384cube_gsrb_at_full_size(bt):
     """384^3 periodic, 216 boxes of 64^3, zero-mean f, phi0 = 0, 20 sweeps with the FP64
     residual norm after each (the benchmark's GSRB workload) against the oracle's whole
